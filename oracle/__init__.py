@@ -1,0 +1,187 @@
+"""FP64 CPU oracle for the sphere GRF sampler (Creasey & Lang, arXiv:1709.10314).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline leg of
+the benchmark may import this package; the product library never does.
+
+The arithmetic lives in ``oracle.c`` (plain C, FP64, OpenMP); this module only builds
+it with gcc and marshals numpy arrays through ctypes.  Functions and the passages of
+the paper they follow:
+
+* ``grid``          -- ring-centre grid (Sec. 4 grid, read as ring centres)
+* ``spectrum``      -- C_l = prod_i (kappa_i + l(l+1))^-1           (eq. (Cl))
+* ``legendre``      -- L_lm(z) and dL_lm/dz                          (Sec. 2)
+* ``jblock``        -- J^m_pq(z1, z2), brute-force sum over l        (Lemma 2.1)
+* ``setup``         -- A, B, B_eq per mode and ring step             (Alg. 1; eqs.
+                       (trans_matrix), (innov_matrix), (state_initial))
+* ``philox``/``normal`` -- white-noise source (Philox4x32-10 + Box-Muller)
+* ``sample_modes``  -- the state-space recursion, both hemispheres   (Alg. 2; eq. (state_space))
+* ``dft``           -- inverse DFT along phi                         (Alg. 2, last step)
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_d = ctypes.c_double
+_i = ctypes.c_int
+_u64 = ctypes.c_uint64
+_pd = ctypes.POINTER(ctypes.c_double)
+_pu32 = ctypes.POINTER(ctypes.c_uint32)
+
+
+def build(force=True):
+    """Compile oracle.c into liboracle.so with gcc (IEEE FP64, no fast-math)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
+           "-ffp-contract=off", _SRC, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    lib.orc_grid.argtypes = [_i, _pd, _pd]
+    lib.orc_spectrum.argtypes = [_i, _pd, _i, _pd]
+    lib.orc_spectrum.restype = _i
+    lib.orc_legendre.argtypes = [_i, _i, _d, _pd, _pd]
+    lib.orc_jblock.argtypes = [_i, _i, _i, _pd, _d, _d, _pd]
+    lib.orc_setup.argtypes = [_i, _i, _pd, _i, _i, _i, _pd, _pd]
+    lib.orc_setup.restype = _i
+    lib.orc_n_sets.argtypes = [_i]
+    lib.orc_n_sets.restype = _i
+    lib.orc_start_ring.argtypes = [_i]
+    lib.orc_start_ring.restype = _i
+    lib.orc_m_top.argtypes = [_i, _i]
+    lib.orc_m_top.restype = _i
+    lib.orc_philox.argtypes = [_pu32, _pu32, _pu32]
+    lib.orc_normal.argtypes = [_u64, _i, _i, _i, _i, _i]
+    lib.orc_normal.restype = _d
+    lib.orc_sample_modes.argtypes = [_i, _i, _i, _i, _pd, _pd, _u64, _i, _pd]
+    lib.orc_sample_modes.restype = _i
+    lib.orc_dft.argtypes = [_i, _i, _i, _i, _i, _i, _pd, _pd]
+    lib.orc_dft.restype = _i
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return a.ctypes.data_as(_pd)
+
+
+def grid(n_theta):
+    """theta_i = pi (i + 1/2) / n_theta and z_i = cos(theta_i), ring 0 nearest z = +1."""
+    th = np.empty(n_theta)
+    z = np.empty(n_theta)
+    _load().orc_grid(n_theta, _p(th), _p(z))
+    return th, z
+
+
+def spectrum(kappa, ell_max):
+    """C_l = prod_i (kappa_i + l(l+1))^-1, l = 0..ell_max (eq. (Cl))."""
+    k = np.ascontiguousarray(kappa, dtype=np.float64).reshape(-1)
+    C = np.empty(ell_max + 1)
+    rc = _load().orc_spectrum(len(k), _p(k), ell_max, _p(C))
+    if rc != 0:
+        raise ValueError("spectrum has a non-positive or non-finite C_l")
+    return C
+
+
+def legendre(m, ell_max, theta):
+    """(L, dL): L_lm(cos theta) and dL_lm/dz for l = m..ell_max (no Condon-Shortley sign)."""
+    n = max(ell_max - m + 1, 0)
+    L = np.zeros(n)
+    dL = np.zeros(n)
+    if n:
+        _load().orc_legendre(m, ell_max, float(theta), _p(L), _p(dL))
+    return L, dL
+
+
+def jblock(order, m, ell_max, C, theta1, theta2):
+    """J^m_pq(z1, z2) = sum_l C_l d^p L_lm(z1) d^q L_lm(z2), an order x order array."""
+    C = np.ascontiguousarray(C, dtype=np.float64)
+    J = np.zeros(order * order)
+    _load().orc_jblock(order, m, ell_max, _p(C), float(theta1), float(theta2), _p(J))
+    return J.reshape(order, order)
+
+
+def n_sets(n_theta):
+    return _load().orc_n_sets(n_theta)
+
+
+def start_ring(n_theta):
+    return _load().orc_start_ring(n_theta)
+
+
+def m_top(ell_max, n_phi):
+    return _load().orc_m_top(ell_max, n_phi)
+
+
+def setup(order, C, n_theta, n_phi, sets=None):
+    """Alg. 1.  Returns (A, B), each [sets][m_top+1][order][order]; set 0 holds B_eq."""
+    C = np.ascontiguousarray(C, dtype=np.float64)
+    ell_max = len(C) - 1
+    mt = m_top(ell_max, n_phi)
+    ns = n_sets(n_theta) if sets is None else min(sets, n_sets(n_theta))
+    A = np.zeros((ns, mt + 1, order, order))
+    B = np.zeros((ns, mt + 1, order, order))
+    rc = _load().orc_setup(order, ell_max, _p(C), n_theta, n_phi, ns, _p(A), _p(B))
+    if rc != 0:
+        raise ValueError("orc_setup rejected its arguments")
+    return A, B
+
+
+def philox(ctr, key):
+    """Philox4x32-10 block for a 4-word counter and a 2-word key."""
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (ctypes.c_uint32 * 4)()
+    _load().orc_philox(c, k, o)
+    return [int(x) for x in o]
+
+
+def normal(key, m, part, ring, order, q):
+    """xi_q that produces ring `ring` of chain (m, part) for the field keyed `key`."""
+    return _load().orc_normal(int(key), m, part, ring, order, q)
+
+
+def sample_modes(order, n_theta, A, B, seed, count, sets=None):
+    """Alg. 2 chains: g[count][n_theta][m_top+1] complex (NaN where no factor set reaches)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    ns = A.shape[0] if sets is None else sets
+    mt = A.shape[1] - 1
+    g = np.empty((count, n_theta, mt + 1, 2))
+    _load().orc_sample_modes(order, n_theta, mt, ns, _p(A), _p(B), int(seed), count, _p(g))
+    return g[..., 0] + 1j * g[..., 1]
+
+
+def dft(g, n_phi, r0=0, r1=None):
+    """Alg. 2 last step on rings [r0, r1): T[count][r1-r0][n_phi] (unnormalised C2R)."""
+    count, n_theta, mt1 = g.shape
+    r1 = n_theta if r1 is None else r1
+    gi = np.empty((count, n_theta, mt1, 2))
+    gi[..., 0] = g.real
+    gi[..., 1] = g.imag
+    T = np.empty((count, r1 - r0, n_phi))
+    _load().orc_dft(n_theta, n_phi, mt1 - 1, count, r0, r1, _p(gi), _p(T))
+    return T
+
+
+def sample(order, n_theta, n_phi, A, B, seed, count):
+    """Full plain method (chains + DFT), returns (T, g)."""
+    g = sample_modes(order, n_theta, A, B, seed, count)
+    return dft(g, n_phi), g

@@ -1,0 +1,514 @@
+/*
+ * FP64 CPU oracle for the sampling method of Creasey & Lang, "Fast generation of
+ * isotropic Gaussian random fields on the sphere" (arXiv:1709.10314).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  The product path (the HIP
+ * library) shares no code with it and never calls it.
+ *
+ * Everything here is plain, slow FP64 C, written so that each step can be checked
+ * against the paper by eye:
+ *   - grid and spectrum                         (Sec. 2, eq. (Cl); Sec. 4 grid)
+ *   - fully normalised associated Legendre L_lm and dL_lm/dz by the forward
+ *     recurrence in l, seeded with an extended-exponent sectoral value
+ *                                               (Sec. 2, definition of L_lm)
+ *   - cross-covariance blocks J^m_pq(z1,z2) as brute-force sums over l
+ *                                               (Lemma 2.1, cross covariances)
+ *   - transition A, innovation factor B, start factor B_eq
+ *                                               (eqs. (trans_matrix),
+ *                                                (innov_matrix), (state_initial);
+ *                                                Alg. 1)
+ *   - Philox4x32-10 words and Box-Muller normals (white-noise source; the paper
+ *     leaves it open)
+ *   - the state-space recursion outward from the equator, south half by mirror
+ *                                               (eq. (state_space); Alg. 2; the
+ *                                                symmetry remark after Alg. 1)
+ *   - the inverse DFT along phi                 (Alg. 2, last step)
+ *
+ * Readings where the paper is silent or garbled (each is listed in the design notes):
+ *   grid      theta_i = pi (i + 1/2) / n_theta, z_i = cos(theta_i), ring 0 nearest z = +1;
+ *             phi_j = 2 pi j / n_phi.
+ *   modes     m = 0 .. m_top, m_top = min(ell_max, n_phi/2 - 1); the Nyquist mode is not used.
+ *   DFT       unnormalised: T = g_0 + 2 sum_{m>=1} Re(g_m e^{i m phi}).
+ *   A, B      A = J(b,a) J(a,a)^+ with J(b,a)_pq = E[x_b,p x_a,q];  S = J(b,b) - A J(a,b);
+ *             both factorisations by an equilibrated, thresholded Cholesky (rules below).
+ *   start     even n_theta: ring s = n_theta/2 - 1 from chol(J(s,s)), one crossing step
+ *             to ring s+1 (= -z_s), then outward both ways; odd n_theta: start at the
+ *             equator ring.  South steps use D A D, D B D with D = diag((-1)^p).
+ *   noise     m = 0: one real chain (scale 1); m > 0: Re and Im chains with B scaled by
+ *             1/sqrt(2) (complex standard normal with E|w|^2 = 1).
+ *   RNG       key = (lo32, hi32) of (seed + field); counter = (floor(idx/4), m, part, 0) with
+ *             idx = ring*M + q; word idx mod 4; u = (x + 0.5) 2^-32; Box-Muller on the word
+ *             pairs (0,1) and (2,3).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAXM 2            /* state dimension supported: value and first z-derivative */
+#define ORC_TINY 1e-290       /* a block diagonal below this is treated as exactly zero */
+#define ORC_TAU 1e-12         /* pivot / relative-variance threshold after equilibration */
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------------- */
+/* Grid (Sec. 4, with the ring-centre reading above).                          */
+/* ------------------------------------------------------------------------- */
+void orc_grid(int n_theta, double* theta, double* z)
+{
+    for (int i = 0; i < n_theta; ++i) {
+        double t = M_PI * (i + 0.5) / n_theta;
+        if (theta) theta[i] = t;
+        if (z) z[i] = cos(t);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Spectrum, eq. (Cl): C_l = prod_i (kappa_i + l(l+1))^-1 for l <= ell_max.     */
+/* Returns 0, or -1 if some C_l is not finite and positive.                    */
+/* ------------------------------------------------------------------------- */
+int orc_spectrum(int n_kappa, const double* kappa, int ell_max, double* C)
+{
+    for (int l = 0; l <= ell_max; ++l) {
+        double c = 1.0;
+        for (int i = 0; i < n_kappa; ++i) c /= (kappa[i] + (double)l * (l + 1));
+        if (!(c > 0.0) || !isfinite(c)) return -1;
+        C[l] = c;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Fully normalised associated Legendre functions (Sec. 2):                    */
+/*   L_lm(z) = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!) P_lm(z),  z = cos(theta),     */
+/* without the Condon-Shortley sign (it cancels in every product L_lm L_lm).   */
+/* Fills L[l-m] and dL[l-m] = dL_lm/dz for l = m .. ell_max.                   */
+/*                                                                             */
+/* Sectoral start:  L_00 = 1/sqrt(4 pi),                                       */
+/*                  L_kk = sqrt((2k+1)/(2k)) sin(theta) L_{k-1,k-1}.            */
+/* First step:      L_{m+1,m} = sqrt(2m+3) z L_mm.                              */
+/* Recurrence:      L_lm = a_lm (z L_{l-1,m} - L_{l-2,m} / a_{l-1,m}),          */
+/*                  a_lm = sqrt((4l^2 - 1)/(l^2 - m^2)).                        */
+/* Derivative:      (1 - z^2) dL_lm/dz = -l z L_lm                              */
+/*                        + sqrt((2l+1)(l^2 - m^2)/(2l-1)) L_{l-1,m}.           */
+/* The running pair carries a binary exponent e (value = p * 2^e) so that the   */
+/* sin^m(theta) seed cannot underflow; values are returned as plain doubles     */
+/* (ldexp), i.e. anything below the FP64 range comes back as zero/subnormal.    */
+/* ------------------------------------------------------------------------- */
+void orc_legendre(int m, int ell_max, double theta, double* L, double* dL)
+{
+    const double z = cos(theta), s = sin(theta), s2 = s * s;
+    const double big = ldexp(1.0, 480), small = ldexp(1.0, -480);
+    int e = 0;
+    double p = 1.0 / sqrt(4.0 * M_PI);
+    for (int k = 1; k <= m; ++k) {
+        p *= sqrt((2.0 * k + 1.0) / (2.0 * k)) * s;
+        if (fabs(p) < small) { p *= big; e -= 480; }
+    }
+    if (ell_max < m) return;
+    /* l = m */
+    L[0] = ldexp(p, e);
+    if (dL) dL[0] = ldexp(-(double)m * z * p / s2, e);
+    if (ell_max == m) return;
+    /* l = m + 1 */
+    double p0 = p;
+    double p1 = sqrt(2.0 * m + 3.0) * z * p;
+    L[1] = ldexp(p1, e);
+    if (dL) {
+        double l = m + 1.0;
+        double c = sqrt((2.0 * l + 1.0) * (l * l - (double)m * m) / (2.0 * l - 1.0));
+        dL[1] = ldexp((-l * z * p1 + c * p0) / s2, e);
+    }
+    for (int li = m + 2; li <= ell_max; ++li) {
+        double l = li, lm1 = li - 1;
+        double a = sqrt((4.0 * l * l - 1.0) / (l * l - (double)m * m));
+        double a_prev = sqrt((4.0 * lm1 * lm1 - 1.0) / (lm1 * lm1 - (double)m * m));
+        double p2 = a * (z * p1 - p0 / a_prev);
+        p0 = p1;
+        p1 = p2;
+        if (e < 0 && (fabs(p1) > big || fabs(p0) > big)) {
+            p0 *= small;
+            p1 *= small;
+            e += 480;
+        }
+        L[li - m] = ldexp(p1, e);
+        if (dL) {
+            double c = sqrt((2.0 * l + 1.0) * (l * l - (double)m * m) / (2.0 * l - 1.0));
+            dL[li - m] = ldexp((-l * z * p1 + c * p0) / s2, e);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Cross-covariance block (Lemma 2.1 and the cross covariances of Sec. 2):     */
+/*   J_pq = sum_{l=m}^{ell_max} C_l  d^p L_lm(z1)  d^q L_lm(z2),  p,q < M,     */
+/* with z1 = cos(theta1), z2 = cos(theta2).  J[p*M + q].                       */
+/* ------------------------------------------------------------------------- */
+void orc_jblock(int order, int m, int ell_max, const double* C, double theta1, double theta2,
+                double* J)
+{
+    int n = ell_max - m + 1;
+    for (int i = 0; i < order * order; ++i) J[i] = 0.0;
+    if (n <= 0) return;
+    double* L1 = (double*)malloc(sizeof(double) * 4 * n);
+    double* D1 = L1 + n;
+    double* L2 = L1 + 2 * n;
+    double* D2 = L1 + 3 * n;
+    orc_legendre(m, ell_max, theta1, L1, D1);
+    orc_legendre(m, ell_max, theta2, L2, D2);
+    for (int p = 0; p < order; ++p)
+        for (int q = 0; q < order; ++q) {
+            const double* f1 = p ? D1 : L1;
+            const double* f2 = q ? D2 : L2;
+            double acc = 0.0;
+            for (int k = 0; k < n; ++k) acc += C[m + k] * f1[k] * f2[k];
+            J[p * order + q] = acc;
+        }
+    free(L1);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Thresholded Cholesky of an equilibrated symmetric M x M matrix X:           */
+/* X ~= G G^T with G lower triangular, positive kept pivots.  A pivot that is   */
+/* not above ORC_TAU is dropped: its column of G is zero and kept[j] = 0.       */
+/* ------------------------------------------------------------------------- */
+static void thr_chol(int M, const double* X, double* G, int* kept)
+{
+    for (int i = 0; i < M * M; ++i) G[i] = 0.0;
+    for (int j = 0; j < M; ++j) {
+        double d = X[j * M + j];
+        for (int k = 0; k < j; ++k) d -= G[j * M + k] * G[j * M + k];
+        if (!(d > ORC_TAU)) { kept[j] = 0; continue; }
+        kept[j] = 1;
+        double gjj = sqrt(d);
+        G[j * M + j] = gjj;
+        for (int i = j + 1; i < M; ++i) {
+            double v = X[i * M + j];
+            for (int k = 0; k < j; ++k) v -= G[i * M + k] * G[j * M + k];
+            G[i * M + j] = v / gjj;
+        }
+    }
+}
+
+/* Start factor, eq. (state_initial): B_eq B_eq^T = J(s,s). */
+void orc_start_factor(int M, const double* Kss, double* Beq)
+{
+    double d[ORC_MAXM], R[ORC_MAXM * ORC_MAXM], G[ORC_MAXM * ORC_MAXM];
+    int kept[ORC_MAXM];
+    for (int p = 0; p < M; ++p) d[p] = Kss[p * M + p] > ORC_TINY ? 1.0 / sqrt(Kss[p * M + p]) : 0.0;
+    for (int p = 0; p < M; ++p)
+        for (int q = 0; q < M; ++q) R[p * M + q] = d[p] * Kss[p * M + q] * d[q];
+    thr_chol(M, R, G, kept);
+    for (int p = 0; p < M; ++p)
+        for (int q = 0; q < M; ++q)
+            Beq[p * M + q] = d[p] > 0.0 ? sqrt(Kss[p * M + p]) * G[p * M + q] : 0.0;
+}
+
+/* One conditional step a -> b, eqs. (trans_matrix) and (innov_matrix):        */
+/*   A = J(b,a) J(a,a)^+,   S = J(b,b) - A J(a,b),   B B^T = S,                 */
+/* where Kba[p*M+q] = E[x_b,p x_a,q].  Both sides are first equilibrated by     */
+/* the block diagonals, so the algebra runs on correlations.                   */
+void orc_step_factors(int M, const double* Kaa, const double* Kbb, const double* Kba,
+                      double* A, double* B)
+{
+    double da[ORC_MAXM], db[ORC_MAXM];
+    double Raa[ORC_MAXM * ORC_MAXM], Rbb[ORC_MAXM * ORC_MAXM], Rba[ORC_MAXM * ORC_MAXM];
+    double G[ORC_MAXM * ORC_MAXM], At[ORC_MAXM * ORC_MAXM], St[ORC_MAXM * ORC_MAXM];
+    double Q[ORC_MAXM * ORC_MAXM], H[ORC_MAXM * ORC_MAXM], e[ORC_MAXM];
+    int kept[ORC_MAXM], kept2[ORC_MAXM];
+
+    for (int p = 0; p < M; ++p) {
+        da[p] = Kaa[p * M + p] > ORC_TINY ? 1.0 / sqrt(Kaa[p * M + p]) : 0.0;
+        db[p] = Kbb[p * M + p] > ORC_TINY ? 1.0 / sqrt(Kbb[p * M + p]) : 0.0;
+    }
+    for (int p = 0; p < M; ++p)
+        for (int q = 0; q < M; ++q) {
+            Raa[p * M + q] = da[p] * Kaa[p * M + q] * da[q];
+            Rbb[p * M + q] = db[p] * Kbb[p * M + q] * db[q];
+            Rba[p * M + q] = db[p] * Kba[p * M + q] * da[q];
+        }
+    thr_chol(M, Raa, G, kept);
+
+    /* At = Rba Raa^+ on the kept pivots: each row r of At solves (G G^T) r^T = Rba[i,:]^T */
+    for (int i = 0; i < M; ++i) {
+        double w[ORC_MAXM], u[ORC_MAXM];
+        for (int j = 0; j < M; ++j) {               /* forward: G w = v */
+            if (!kept[j]) { w[j] = 0.0; continue; }
+            double v = Rba[i * M + j];
+            for (int k = 0; k < j; ++k) if (kept[k]) v -= G[j * M + k] * w[k];
+            w[j] = v / G[j * M + j];
+        }
+        for (int j = M - 1; j >= 0; --j) {          /* backward: G^T u = w */
+            if (!kept[j]) { u[j] = 0.0; continue; }
+            double v = w[j];
+            for (int k = j + 1; k < M; ++k) if (kept[k]) v -= G[k * M + j] * u[k];
+            u[j] = v / G[j * M + j];
+        }
+        for (int j = 0; j < M; ++j) At[i * M + j] = u[j];
+    }
+    /* St = Rbb - At Rba^T, symmetrised */
+    for (int p = 0; p < M; ++p)
+        for (int q = 0; q < M; ++q) {
+            double v = Rbb[p * M + q];
+            for (int k = 0; k < M; ++k) v -= At[p * M + k] * Rba[q * M + k];
+            St[p * M + q] = v;
+        }
+    for (int p = 0; p < M; ++p)
+        for (int q = 0; q < p; ++q) {
+            double v = 0.5 * (St[p * M + q] + St[q * M + p]);
+            St[p * M + q] = St[q * M + p] = v;
+        }
+    /* B~ = chol(St) with its own equilibration; a relative conditional variance
+       not above ORC_TAU is treated as zero */
+    for (int p = 0; p < M; ++p) e[p] = St[p * M + p] > ORC_TAU ? 1.0 / sqrt(St[p * M + p]) : 0.0;
+    for (int p = 0; p < M; ++p)
+        for (int q = 0; q < M; ++q) Q[p * M + q] = e[p] * St[p * M + q] * e[q];
+    thr_chol(M, Q, H, kept2);
+    /* undo the equilibration */
+    for (int p = 0; p < M; ++p)
+        for (int q = 0; q < M; ++q) {
+            double sb = db[p] > 0.0 ? sqrt(Kbb[p * M + p]) : 0.0;
+            A[p * M + q] = sb * At[p * M + q] * da[q];
+            B[p * M + q] = e[p] > 0.0 ? sb * H[p * M + q] / e[p] : 0.0;
+        }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Factor-set bookkeeping.  Factor set j of mode m:                            */
+/*   even n_theta (s = n/2 - 1):  j = 0 start at ring s; j = 1 crossing s -> s+1; */
+/*                                j >= 2 north step (s-j+2) -> (s-j+1).        */
+/*   odd n_theta  (s = (n-1)/2):  j = 0 start at the equator ring s;           */
+/*                                j >= 1 north step (s-j+1) -> (s-j).          */
+/* The south half reuses set j conjugated by D (mirror z -> -z).               */
+/* ------------------------------------------------------------------------- */
+int orc_n_sets(int n_theta) { return (n_theta % 2 == 0) ? n_theta / 2 + 1 : (n_theta + 1) / 2; }
+int orc_start_ring(int n_theta) { return (n_theta % 2 == 0) ? n_theta / 2 - 1 : (n_theta - 1) / 2; }
+int orc_m_top(int ell_max, int n_phi)
+{
+    int m = n_phi / 2 - 1;
+    return ell_max < m ? ell_max : m;
+}
+
+/* Ring pair (a, b) of factor set j in the north chain (b = s+1 for the crossing). */
+static void set_rings(int n_theta, int j, int* a, int* b)
+{
+    int s = orc_start_ring(n_theta);
+    if (j == 0) { *a = *b = s; return; }
+    if (n_theta % 2 == 0) {
+        if (j == 1) { *a = s; *b = s + 1; return; }
+        *a = s - j + 2; *b = s - j + 1;
+    } else {
+        *a = s - j + 1; *b = s - j;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Alg. 1: factors for every mode m = 0..m_top and factor sets j = 0..n_sets-1. */
+/* A and B are [n_sets][m_top+1][M][M] (row-major, B lower triangular); for     */
+/* j = 0, A = 0 and B = B_eq.  Only the first `n_sets` sets are computed (the   */
+/* caller may ask for fewer than orc_n_sets(n_theta)).                          */
+/* ------------------------------------------------------------------------- */
+int orc_setup(int order, int ell_max, const double* C, int n_theta, int n_phi, int n_sets,
+              double* A, double* B)
+{
+    if (order < 1 || order > ORC_MAXM || n_theta < 2 || ell_max < 0) return -1;
+    int m_top = orc_m_top(ell_max, n_phi);
+    int MM = order * order;
+    int total = orc_n_sets(n_theta);
+    if (n_sets > total) n_sets = total;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int m = 0; m <= m_top; ++m) {
+        double Kaa[ORC_MAXM * ORC_MAXM], Kbb[ORC_MAXM * ORC_MAXM], Kba[ORC_MAXM * ORC_MAXM];
+        for (int j = 0; j < n_sets; ++j) {
+            int a, b;
+            set_rings(n_theta, j, &a, &b);
+            double ta = M_PI * (a + 0.5) / n_theta, tb = M_PI * (b + 0.5) / n_theta;
+            double* Aj = A + ((size_t)j * (m_top + 1) + m) * MM;
+            double* Bj = B + ((size_t)j * (m_top + 1) + m) * MM;
+            if (j == 0) {
+                orc_jblock(order, m, ell_max, C, ta, ta, Kaa);
+                for (int i = 0; i < MM; ++i) Aj[i] = 0.0;
+                orc_start_factor(order, Kaa, Bj);
+                continue;
+            }
+            orc_jblock(order, m, ell_max, C, ta, ta, Kaa);
+            orc_jblock(order, m, ell_max, C, tb, tb, Kbb);
+            orc_jblock(order, m, ell_max, C, tb, ta, Kba);
+            orc_step_factors(order, Kaa, Kbb, Kba, Aj, Bj);
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of            */
+/*   (c0,c1,c2,c3) -> (hi(B*c2) ^ c1 ^ k0, lo(B*c2), hi(A*c0) ^ c3 ^ k1, lo(A*c0)) */
+/* with A = 0xD2511F53, B = 0xCD9E8D57, and the key bumped by the Weyl          */
+/* constants (0x9E3779B9, 0xBB67AE85) between rounds.                          */
+/* ------------------------------------------------------------------------- */
+void orc_philox(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint64_t pa = (uint64_t)0xD2511F53u * c0;
+        uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)pb;
+        uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)pa;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Normal xi_q feeding ring `ring` of chain (m, part) of the field with key
+   `key`; Box-Muller in FP64 on the words of one Philox block. */
+double orc_normal(uint64_t key, int m, int part, int ring, int order, int q)
+{
+    int idx = ring * order + q;
+    uint32_t ctr[4] = {(uint32_t)(idx / 4), (uint32_t)m, (uint32_t)part, 0u};
+    uint32_t k[2] = {(uint32_t)key, (uint32_t)(key >> 32)};
+    uint32_t w[4];
+    orc_philox(ctr, k, w);
+    int word = idx % 4;
+    int pair = word / 2;
+    double u0 = ((double)w[2 * pair] + 0.5) * ldexp(1.0, -32);
+    double u1 = ((double)w[2 * pair + 1] + 0.5) * ldexp(1.0, -32);
+    double r = sqrt(-2.0 * log(u0));
+    return (word % 2 == 0) ? r * cos(2.0 * M_PI * u1) : r * sin(2.0 * M_PI * u1);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Alg. 2, chain part: for every field f (key seed+f), mode m and part, draw    */
+/* the start state at ring s (eq. (state_initial)) and run eq. (state_space)    */
+/* outward in both hemispheres.  g is [count][n_theta][m_top+1][2] (Re, Im).   */
+/* Only factor sets j < n_sets are used; rings they do not reach stay NaN.     */
+/* ------------------------------------------------------------------------- */
+int orc_sample_modes(int order, int n_theta, int m_top, int n_sets, const double* A,
+                     const double* B, uint64_t seed, int count, double* g)
+{
+    const int M = order, MM = order * order;
+    const int s = orc_start_ring(n_theta);
+    const int even = (n_theta % 2 == 0);
+    const size_t row = (size_t)(m_top + 1) * 2;
+    for (size_t i = 0; i < (size_t)count * n_theta * row; ++i) g[i] = NAN;
+#pragma omp parallel for collapse(2) schedule(dynamic, 4)
+    for (int f = 0; f < count; ++f)
+        for (int m = 0; m <= m_top; ++m) {
+            uint64_t key = seed + (uint64_t)f;
+            double* gf = g + (size_t)f * n_theta * row;
+            for (int part = 0; part < 2; ++part) {
+                if (m == 0 && part == 1) {                 /* g_0 is real */
+                    for (int r = 0; r < n_theta; ++r) gf[r * row + 1] = 0.0;
+                    continue;
+                }
+                const double sc = (m == 0) ? 1.0 : 1.0 / sqrt(2.0);
+                double xs[ORC_MAXM], x[ORC_MAXM], xn[ORC_MAXM], w[ORC_MAXM];
+                /* start ring s */
+                const double* B0 = B + (size_t)m * MM;
+                for (int q = 0; q < M; ++q) w[q] = orc_normal(key, m, part, s, M, q);
+                for (int p = 0; p < M; ++p) {
+                    xs[p] = 0.0;
+                    for (int q = 0; q < M; ++q) xs[p] += sc * B0[p * M + q] * w[q];
+                }
+                gf[(size_t)s * row + 2 * m + part] = xs[0];
+                /* north: rings s-1 .. 0 */
+                for (int p = 0; p < M; ++p) x[p] = xs[p];
+                for (int j = even ? 2 : 1; j < n_sets; ++j) {
+                    int r = even ? s - j + 1 : s - j;
+                    const double* Aj = A + ((size_t)j * (m_top + 1) + m) * MM;
+                    const double* Bj = B + ((size_t)j * (m_top + 1) + m) * MM;
+                    for (int q = 0; q < M; ++q) w[q] = orc_normal(key, m, part, r, M, q);
+                    for (int p = 0; p < M; ++p) {
+                        xn[p] = 0.0;
+                        for (int q = 0; q < M; ++q) xn[p] += Aj[p * M + q] * x[q] + sc * Bj[p * M + q] * w[q];
+                    }
+                    for (int p = 0; p < M; ++p) x[p] = xn[p];
+                    gf[(size_t)r * row + 2 * m + part] = x[0];
+                }
+                /* south: crossing (even n) then mirrored steps with D A D, D B D */
+                for (int p = 0; p < M; ++p) x[p] = xs[p];
+                int r = s;
+                int j0 = 1;
+                if (even) {
+                    if (n_sets < 2) continue;
+                    const double* Aj = A + ((size_t)1 * (m_top + 1) + m) * MM;
+                    const double* Bj = B + ((size_t)1 * (m_top + 1) + m) * MM;
+                    r = s + 1;
+                    for (int q = 0; q < M; ++q) w[q] = orc_normal(key, m, part, r, M, q);
+                    for (int p = 0; p < M; ++p) {
+                        xn[p] = 0.0;
+                        for (int q = 0; q < M; ++q) xn[p] += Aj[p * M + q] * x[q] + sc * Bj[p * M + q] * w[q];
+                    }
+                    for (int p = 0; p < M; ++p) x[p] = xn[p];
+                    gf[(size_t)r * row + 2 * m + part] = x[0];
+                    j0 = 2;
+                }
+                for (int j = j0; j < n_sets; ++j) {
+                    r += 1;
+                    const double* Aj = A + ((size_t)j * (m_top + 1) + m) * MM;
+                    const double* Bj = B + ((size_t)j * (m_top + 1) + m) * MM;
+                    for (int q = 0; q < M; ++q) w[q] = orc_normal(key, m, part, r, M, q);
+                    for (int p = 0; p < M; ++p) {
+                        xn[p] = 0.0;
+                        for (int q = 0; q < M; ++q) {
+                            double sgn = ((p + q) % 2 == 0) ? 1.0 : -1.0;   /* D X D */
+                            xn[p] += sgn * (Aj[p * M + q] * x[q] + sc * Bj[p * M + q] * w[q]);
+                        }
+                    }
+                    for (int p = 0; p < M; ++p) x[p] = xn[p];
+                    gf[(size_t)r * row + 2 * m + part] = x[0];
+                }
+            }
+        }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Alg. 2, last step: inverse DFT along phi for rings [r0, r1) of each field:   */
+/*   T(z_i, phi_j) = g_0 + 2 sum_{m=1}^{m_top} (Re g_m cos(m phi_j)             */
+/*                                              - Im g_m sin(m phi_j)),         */
+/* phi_j = 2 pi j / n_phi, twiddles indexed exactly by (m j) mod n_phi.         */
+/* g is [count][n_theta][m_top+1][2]; T is [count][r1-r0][n_phi].               */
+/* ------------------------------------------------------------------------- */
+int orc_dft(int n_theta, int n_phi, int m_top, int count, int r0, int r1, const double* g, double* T)
+{
+    double* cs = (double*)malloc(sizeof(double) * 2 * n_phi);
+    if (!cs) return -1;
+    for (int k = 0; k < n_phi; ++k) {
+        cs[2 * k] = cos(2.0 * M_PI * k / n_phi);
+        cs[2 * k + 1] = sin(2.0 * M_PI * k / n_phi);
+    }
+    const size_t row = (size_t)(m_top + 1) * 2;
+    const int nr = r1 - r0;
+#pragma omp parallel for collapse(2) schedule(dynamic, 1)
+    for (int f = 0; f < count; ++f)
+        for (int i = r0; i < r1; ++i) {
+            const double* gr = g + ((size_t)f * n_theta + i) * row;
+            double* Tr = T + ((size_t)f * nr + (i - r0)) * n_phi;
+            for (int j = 0; j < n_phi; ++j) {
+                double acc = 0.0;
+                for (int m = 1; m <= m_top; ++m) {
+                    size_t k = ((size_t)m * j) % (size_t)n_phi;
+                    acc += gr[2 * m] * cs[2 * k] - gr[2 * m + 1] * cs[2 * k + 1];
+                }
+                Tr[j] = gr[0] + 2.0 * acc;
+            }
+        }
+    free(cs);
+    return 0;
+}
+
+/* Full plain method for convenience: setup + chains + DFT on all rings. */
+int orc_sample(int order, int n_theta, int n_phi, int m_top, const double* A, const double* B,
+               uint64_t seed, int count, double* g_work, double* T)
+{
+    int ns = orc_n_sets(n_theta);
+    orc_sample_modes(order, n_theta, m_top, ns, A, B, seed, count, g_work);
+    return orc_dft(n_theta, n_phi, m_top, count, 0, n_theta, g_work, T);
+}

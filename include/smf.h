@@ -1,0 +1,114 @@
+/*
+ * smf.h -- C ABI of the MI355X (gfx950) sampler of isotropic Gaussian random fields
+ * on the sphere by latitude-ring Gauss-Markov recursions and an FFT along phi
+ * (Creasey & Lang, "Fast generation of isotropic Gaussian random fields on the
+ * sphere", arXiv:1709.10314).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Return value: SMF_OK (0) on success, a negative SMF_E* code on error.  On error no
+ *    output buffer is written and no plan is created; smf_error_string() names the code.
+ *  - Device pointers are HIP device memory (e.g. torch.cuda tensors); host pointers are
+ *    ordinary CPU memory.  The caller owns every buffer it passes; the plan owns its own
+ *    device buffers (factors, spectrum, twiddles) and frees them in smf_destroy().
+ *  - Streams are hipStream_t passed as void* (NULL = the null stream).  Sampling calls
+ *    are asynchronous on that stream; setup synchronises its stream before returning.
+ *  - A plan is immutable after setup; the sampling calls only read it, so one plan may be
+ *    used from several streams at once (each call needs its own output buffer).
+ *
+ * Grid: n_theta iso-latitude rings at ring centres theta_i = pi (i + 1/2) / n_theta
+ * (ring 0 nearest the north pole, z_i = cos theta_i) and n_phi equispaced longitudes
+ * phi_j = 2 pi j / n_phi (Sec. 4, grid and Alg. 2).  Modes m = 0..m_top with
+ * m_top = min(ell_max, n_phi/2 - 1).
+ */
+#ifndef SMF_H
+#define SMF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct smf_plan smf_plan;
+
+/* Angular power spectrum, eq. (Cl): C_l = prod_{i<n_kappa} (kappa_i + l(l+1))^-1 for
+ * l = 0..ell_max, and C_l = 0 above ell_max.  If c_ell is non-NULL it is used instead
+ * (ell_max + 1 values, host memory).  `order` is the Markov order M, i.e. the state
+ * dimension (value and first M-1 z-derivatives, Sec. 2 Markov property); M in {1, 2}.
+ * For the rational form M is normally n_kappa. */
+typedef struct {
+    int order;
+    int n_kappa;
+    const double* kappa;   /* host, n_kappa values */
+    const double* c_ell;   /* host, ell_max + 1 values, or NULL */
+    int ell_max;
+} smf_spectrum;
+
+enum {
+    SMF_OK = 0,
+    SMF_EINVAL = -1,     /* bad argument (shape, order, NULL pointer, count < 0, ...) */
+    SMF_ENOMEM = -2,     /* device allocation failed */
+    SMF_EHIP = -3,       /* a HIP runtime call or kernel launch failed */
+    SMF_ENUMERIC = -4    /* spectrum has a C_l that is not finite and positive */
+};
+
+enum {
+    SMF_FP64 = 1,        /* sample in FP64 (recursion, normals, FFT) */
+    SMF_FP32 = 2         /* sample in FP32 (factors rounded from the FP64 setup) */
+};
+
+/* Alg. 1 (pre-computation of covariance matrices), run on the GPU in FP64: for every
+ * mode m <= m_top, the start factor B_eq (eq. (state_initial)) at the start ring, and for
+ * each ring step the transition A = J(b,a) J(a,a)^+ (eq. (trans_matrix)) and the lower
+ * Cholesky factor B of S = J(b,b) - A J(a,b) (eq. (innov_matrix)), with J the
+ * cross-covariance blocks of Lemma 2.1 summed over l <= ell_max.  Only the northern half
+ * is stored; the southern steps are the mirror D A D, D B D (symmetry remark after Alg. 1).
+ *   spec      host; copied, not retained.
+ *   n_theta   >= 2 rings.     n_phi  power of two in [4, 16384].
+ *   flags     exactly one of SMF_FP64, SMF_FP32.
+ *   out       receives the new plan (host pointer to a pointer).
+ * Errors: SMF_EINVAL (shapes, order not in {1,2}, ell_max < 0, n_kappa < 0, NULL
+ * pointers, flags), SMF_ENUMERIC (a C_l not finite and > 0), SMF_ENOMEM, SMF_EHIP. */
+int smf_setup(const smf_spectrum* spec, int n_theta, int n_phi, int flags, void* hip_stream,
+              smf_plan** out);
+
+/* Alg. 2 (Gaussian random field generation): `count` fields, field f drawn with the
+ * Philox4x32-10 key seed + f.  Writes out_dev, device memory of count*n_theta*n_phi
+ * float (SMF_FP32 plan) or double (SMF_FP64 plan), layout [field][ring][phi], ring 0
+ * nearest the north pole.  count = 0 is a no-op.  Uses no memory beyond out_dev: the
+ * modes g_m are written into out_dev and transformed in place.
+ * Errors: SMF_EINVAL (NULL plan/out with count > 0, count < 0), SMF_EHIP. */
+int smf_sample(const smf_plan* plan, uint64_t seed, int count, void* out_dev, void* hip_stream);
+
+/* The chains of Alg. 2 only (eqs. (state_initial) and (state_space)), without the FFT:
+ * writes g_m(z_i) for field f, ring i, mode m as interleaved (Re, Im) pairs at
+ * g_dev[((f*n_theta + i)*(n_phi/2) + m)*2 + {0,1}], element type as in smf_sample; the
+ * entries for m > m_top are zero.  Same size and errors as smf_sample. */
+int smf_sample_modes(const smf_plan* plan, uint64_t seed, int count, void* g_dev, void* hip_stream);
+
+/* Plan geometry: dims[0..7] = {order, n_theta, n_phi, ell_max, m_top, n_sets, start_ring,
+ * precision flag}.  n_sets = number of factor sets per mode (start, crossing for even
+ * n_theta, then one per northern step).  Errors: SMF_EINVAL on NULL. */
+int smf_plan_dims(const smf_plan* plan, int* dims);
+
+/* Copies the FP64 factors to host arrays A_host and B_host, each of n_sets*(m_top+1)*M*M
+ * doubles, layout [set][m][p][q] row-major (B lower triangular; set 0 holds A = 0 and
+ * B = B_eq).  Set j >= 1 is the step between the ring pair it covers: for even n_theta
+ * (start ring s = n_theta/2 - 1) set 1 is the crossing s -> s+1 and set j >= 2 the step
+ * s-j+2 -> s-j+1; for odd n_theta (s = (n_theta-1)/2) set j >= 1 is s-j+1 -> s-j.
+ * Synchronous.  Errors: SMF_EINVAL on NULL, SMF_EHIP. */
+int smf_get_factors(const smf_plan* plan, double* A_host, double* B_host);
+
+/* Frees the plan and its device memory (synchronises the device first).  NULL is a
+ * no-op. */
+int smf_destroy(smf_plan* plan);
+
+/* Static string for an SMF_* code. */
+const char* smf_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMF_H */

@@ -72,6 +72,11 @@ def _load():
     lib.orc_normal.restype = _d
     lib.orc_sample_modes.argtypes = [_i, _i, _i, _i, _pd, _pd, _u64, _i, _pd]
     lib.orc_sample_modes.restype = _i
+    _pi = ctypes.POINTER(ctypes.c_int)
+    lib.orc_setup_modes.argtypes = [_i, _i, _pd, _i, _i, _pi, _i, _pd, _pd]
+    lib.orc_setup_modes.restype = _i
+    lib.orc_sample_modes_list.argtypes = [_i, _i, _pi, _i, _i, _pd, _pd, _u64, _i, _pd]
+    lib.orc_sample_modes_list.restype = _i
     lib.orc_dft.argtypes = [_i, _i, _i, _i, _i, _i, _pd, _pd]
     lib.orc_dft.restype = _i
     _lib = lib
@@ -142,6 +147,32 @@ def setup(order, C, n_theta, n_phi, sets=None):
     if rc != 0:
         raise ValueError("orc_setup rejected its arguments")
     return A, B
+
+
+def setup_modes(order, C, n_theta, modes, sets=None):
+    """Alg. 1 for the listed modes only: (A, B), each [sets][len(modes)][order][order]."""
+    C = np.ascontiguousarray(C, dtype=np.float64)
+    md = np.ascontiguousarray(modes, dtype=np.int32)
+    ns = n_sets(n_theta) if sets is None else min(sets, n_sets(n_theta))
+    A = np.zeros((ns, len(md), order, order))
+    B = np.zeros((ns, len(md), order, order))
+    rc = _load().orc_setup_modes(order, len(C) - 1, _p(C), n_theta, ns,
+                                 md.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(md), _p(A), _p(B))
+    if rc != 0:
+        raise ValueError("orc_setup_modes rejected its arguments")
+    return A, B
+
+
+def sample_modes_list(order, n_theta, modes, A, B, seed, count, sets=None):
+    """Chains of the listed modes: g[count][n_theta][len(modes)] complex (NaN where unreached)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    md = np.ascontiguousarray(modes, dtype=np.int32)
+    ns = A.shape[0] if sets is None else sets
+    g = np.empty((count, n_theta, len(md), 2))
+    _load().orc_sample_modes_list(order, n_theta, md.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                  len(md), ns, _p(A), _p(B), int(seed), count, _p(g))
+    return g[..., 0] + 1j * g[..., 1]
 
 
 def philox(ctr, key):

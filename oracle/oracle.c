@@ -306,31 +306,31 @@ static void set_rings(int n_theta, int j, int* a, int* b)
 }
 
 /* ------------------------------------------------------------------------- */
-/* Alg. 1: factors for every mode m = 0..m_top and factor sets j = 0..n_sets-1. */
-/* A and B are [n_sets][m_top+1][M][M] (row-major, B lower triangular); for     */
-/* j = 0, A = 0 and B = B_eq.  Only the first `n_sets` sets are computed (the   */
-/* caller may ask for fewer than orc_n_sets(n_theta)).                          */
+/* Alg. 1 for the modes listed in `modes` (each <= m_top) and factor sets       */
+/* j = 0..n_sets-1.  A and B are [n_sets][n_modes][M][M] (row-major, B lower    */
+/* triangular); for j = 0, A = 0 and B = B_eq.  n_sets may be smaller than      */
+/* orc_n_sets(n_theta) to cover only the rings nearest the start.              */
 /* ------------------------------------------------------------------------- */
-int orc_setup(int order, int ell_max, const double* C, int n_theta, int n_phi, int n_sets,
-              double* A, double* B)
+int orc_setup_modes(int order, int ell_max, const double* C, int n_theta, int n_sets,
+                    const int* modes, int n_modes, double* A, double* B)
 {
     if (order < 1 || order > ORC_MAXM || n_theta < 2 || ell_max < 0) return -1;
-    int m_top = orc_m_top(ell_max, n_phi);
     int MM = order * order;
     int total = orc_n_sets(n_theta);
     if (n_sets > total) n_sets = total;
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int m = 0; m <= m_top; ++m) {
+    for (int i = 0; i < n_modes; ++i) {
+        int m = modes[i];
         double Kaa[ORC_MAXM * ORC_MAXM], Kbb[ORC_MAXM * ORC_MAXM], Kba[ORC_MAXM * ORC_MAXM];
         for (int j = 0; j < n_sets; ++j) {
             int a, b;
             set_rings(n_theta, j, &a, &b);
             double ta = M_PI * (a + 0.5) / n_theta, tb = M_PI * (b + 0.5) / n_theta;
-            double* Aj = A + ((size_t)j * (m_top + 1) + m) * MM;
-            double* Bj = B + ((size_t)j * (m_top + 1) + m) * MM;
+            double* Aj = A + ((size_t)j * n_modes + i) * MM;
+            double* Bj = B + ((size_t)j * n_modes + i) * MM;
             if (j == 0) {
                 orc_jblock(order, m, ell_max, C, ta, ta, Kaa);
-                for (int i = 0; i < MM; ++i) Aj[i] = 0.0;
+                for (int k = 0; k < MM; ++k) Aj[k] = 0.0;
                 orc_start_factor(order, Kaa, Bj);
                 continue;
             }
@@ -341,6 +341,19 @@ int orc_setup(int order, int ell_max, const double* C, int n_theta, int n_phi, i
         }
     }
     return 0;
+}
+
+/* Alg. 1 for every mode m = 0..m_top. */
+int orc_setup(int order, int ell_max, const double* C, int n_theta, int n_phi, int n_sets,
+              double* A, double* B)
+{
+    int m_top = orc_m_top(ell_max, n_phi);
+    int* modes = (int*)malloc(sizeof(int) * (m_top + 1));
+    if (!modes) return -1;
+    for (int m = 0; m <= m_top; ++m) modes[m] = m;
+    int rc = orc_setup_modes(order, ell_max, C, n_theta, n_sets, modes, m_top + 1, A, B);
+    free(modes);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -386,50 +399,53 @@ double orc_normal(uint64_t key, int m, int part, int ring, int order, int q)
 /* ------------------------------------------------------------------------- */
 /* Alg. 2, chain part: for every field f (key seed+f), mode m and part, draw    */
 /* the start state at ring s (eq. (state_initial)) and run eq. (state_space)    */
-/* outward in both hemispheres.  g is [count][n_theta][m_top+1][2] (Re, Im).   */
-/* Only factor sets j < n_sets are used; rings they do not reach stay NaN.     */
+/* outward in both hemispheres, for the modes listed in `modes` with factors     */
+/* [n_sets][n_modes][M][M] as orc_setup_modes writes them.                      */
+/* g is [count][n_theta][n_modes][2] (Re, Im).  Only factor sets j < n_sets are  */
+/* used; rings they do not reach stay NaN.                                      */
 /* ------------------------------------------------------------------------- */
-int orc_sample_modes(int order, int n_theta, int m_top, int n_sets, const double* A,
-                     const double* B, uint64_t seed, int count, double* g)
+int orc_sample_modes_list(int order, int n_theta, const int* modes, int n_modes, int n_sets,
+                          const double* A, const double* B, uint64_t seed, int count, double* g)
 {
     const int M = order, MM = order * order;
     const int s = orc_start_ring(n_theta);
     const int even = (n_theta % 2 == 0);
-    const size_t row = (size_t)(m_top + 1) * 2;
+    const size_t row = (size_t)n_modes * 2;
     for (size_t i = 0; i < (size_t)count * n_theta * row; ++i) g[i] = NAN;
 #pragma omp parallel for collapse(2) schedule(dynamic, 4)
     for (int f = 0; f < count; ++f)
-        for (int m = 0; m <= m_top; ++m) {
+        for (int i = 0; i < n_modes; ++i) {
+            const int m = modes[i];
             uint64_t key = seed + (uint64_t)f;
             double* gf = g + (size_t)f * n_theta * row;
             for (int part = 0; part < 2; ++part) {
                 if (m == 0 && part == 1) {                 /* g_0 is real */
-                    for (int r = 0; r < n_theta; ++r) gf[r * row + 1] = 0.0;
+                    for (int r = 0; r < n_theta; ++r) gf[r * row + 2 * i + 1] = 0.0;
                     continue;
                 }
                 const double sc = (m == 0) ? 1.0 : 1.0 / sqrt(2.0);
                 double xs[ORC_MAXM], x[ORC_MAXM], xn[ORC_MAXM], w[ORC_MAXM];
                 /* start ring s */
-                const double* B0 = B + (size_t)m * MM;
+                const double* B0 = B + (size_t)i * MM;
                 for (int q = 0; q < M; ++q) w[q] = orc_normal(key, m, part, s, M, q);
                 for (int p = 0; p < M; ++p) {
                     xs[p] = 0.0;
                     for (int q = 0; q < M; ++q) xs[p] += sc * B0[p * M + q] * w[q];
                 }
-                gf[(size_t)s * row + 2 * m + part] = xs[0];
+                gf[(size_t)s * row + 2 * i + part] = xs[0];
                 /* north: rings s-1 .. 0 */
                 for (int p = 0; p < M; ++p) x[p] = xs[p];
                 for (int j = even ? 2 : 1; j < n_sets; ++j) {
                     int r = even ? s - j + 1 : s - j;
-                    const double* Aj = A + ((size_t)j * (m_top + 1) + m) * MM;
-                    const double* Bj = B + ((size_t)j * (m_top + 1) + m) * MM;
+                    const double* Aj = A + ((size_t)j * n_modes + i) * MM;
+                    const double* Bj = B + ((size_t)j * n_modes + i) * MM;
                     for (int q = 0; q < M; ++q) w[q] = orc_normal(key, m, part, r, M, q);
                     for (int p = 0; p < M; ++p) {
                         xn[p] = 0.0;
                         for (int q = 0; q < M; ++q) xn[p] += Aj[p * M + q] * x[q] + sc * Bj[p * M + q] * w[q];
                     }
                     for (int p = 0; p < M; ++p) x[p] = xn[p];
-                    gf[(size_t)r * row + 2 * m + part] = x[0];
+                    gf[(size_t)r * row + 2 * i + part] = x[0];
                 }
                 /* south: crossing (even n) then mirrored steps with D A D, D B D */
                 for (int p = 0; p < M; ++p) x[p] = xs[p];
@@ -437,8 +453,8 @@ int orc_sample_modes(int order, int n_theta, int m_top, int n_sets, const double
                 int j0 = 1;
                 if (even) {
                     if (n_sets < 2) continue;
-                    const double* Aj = A + ((size_t)1 * (m_top + 1) + m) * MM;
-                    const double* Bj = B + ((size_t)1 * (m_top + 1) + m) * MM;
+                    const double* Aj = A + ((size_t)1 * n_modes + i) * MM;
+                    const double* Bj = B + ((size_t)1 * n_modes + i) * MM;
                     r = s + 1;
                     for (int q = 0; q < M; ++q) w[q] = orc_normal(key, m, part, r, M, q);
                     for (int p = 0; p < M; ++p) {
@@ -446,13 +462,13 @@ int orc_sample_modes(int order, int n_theta, int m_top, int n_sets, const double
                         for (int q = 0; q < M; ++q) xn[p] += Aj[p * M + q] * x[q] + sc * Bj[p * M + q] * w[q];
                     }
                     for (int p = 0; p < M; ++p) x[p] = xn[p];
-                    gf[(size_t)r * row + 2 * m + part] = x[0];
+                    gf[(size_t)r * row + 2 * i + part] = x[0];
                     j0 = 2;
                 }
                 for (int j = j0; j < n_sets; ++j) {
                     r += 1;
-                    const double* Aj = A + ((size_t)j * (m_top + 1) + m) * MM;
-                    const double* Bj = B + ((size_t)j * (m_top + 1) + m) * MM;
+                    const double* Aj = A + ((size_t)j * n_modes + i) * MM;
+                    const double* Bj = B + ((size_t)j * n_modes + i) * MM;
                     for (int q = 0; q < M; ++q) w[q] = orc_normal(key, m, part, r, M, q);
                     for (int p = 0; p < M; ++p) {
                         xn[p] = 0.0;
@@ -462,11 +478,23 @@ int orc_sample_modes(int order, int n_theta, int m_top, int n_sets, const double
                         }
                     }
                     for (int p = 0; p < M; ++p) x[p] = xn[p];
-                    gf[(size_t)r * row + 2 * m + part] = x[0];
+                    gf[(size_t)r * row + 2 * i + part] = x[0];
                 }
             }
         }
     return 0;
+}
+
+/* Chains for every mode m = 0..m_top: g is [count][n_theta][m_top+1][2]. */
+int orc_sample_modes(int order, int n_theta, int m_top, int n_sets, const double* A,
+                     const double* B, uint64_t seed, int count, double* g)
+{
+    int* modes = (int*)malloc(sizeof(int) * (m_top + 1));
+    if (!modes) return -1;
+    for (int m = 0; m <= m_top; ++m) modes[m] = m;
+    int rc = orc_sample_modes_list(order, n_theta, modes, m_top + 1, n_sets, A, B, seed, count, g);
+    free(modes);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------- */

@@ -1,0 +1,74 @@
+// Counter-based white noise for the ring recursion: Philox4x32-10 (Salmon, Moraes, Dror,
+// Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11) and Box-Muller.
+//
+// Counter map: the normal xi_q that produces ring r of chain (m, part) of a field keyed
+// K = seed + field is word w = (r M + q) mod 4 of the Philox block with counter
+// (floor((r M + q) / 4), m, part, 0) and key (lo32(K), hi32(K)).  Words are turned into
+// uniforms u = (x + 1/2) 2^-32 and paired (0,1), (2,3) by Box-Muller:
+//   n_{2i} = sqrt(-2 ln u_{2i}) cos(2 pi u_{2i+1}),  n_{2i+1} = sqrt(-2 ln u_{2i}) sin(2 pi u_{2i+1}).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace smf {
+
+struct PhiloxBlock {
+    uint32_t w[4];
+};
+
+__device__ __forceinline__ PhiloxBlock philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                     uint32_t c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t pb = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    PhiloxBlock b;
+    b.w[0] = c0; b.w[1] = c1; b.w[2] = c2; b.w[3] = c3;
+    return b;
+}
+
+template <typename T>
+struct BoxMuller;
+
+template <>
+struct BoxMuller<double> {
+    // (r cos, r sin) of the pair (x0, x1)
+    __device__ __forceinline__ static void pair(uint32_t x0, uint32_t x1, double& a, double& b)
+    {
+        const double u0 = ((double)x0 + 0.5) * 0x1p-32;
+        const double u1 = ((double)x1 + 0.5) * 0x1p-32;
+        const double r = sqrt(-2.0 * log(u0));
+        double s, c;
+        sincospi(2.0 * u1, &s, &c);
+        a = r * c;
+        b = r * s;
+    }
+};
+
+template <>
+struct BoxMuller<float> {
+    __device__ __forceinline__ static void pair(uint32_t x0, uint32_t x1, float& a, float& b)
+    {
+        // (x + 1/2) 2^-32 with one rounding of x to 24 bits: relative error ~2^-24
+        const float u0 = fmaf((float)x0, 0x1p-32f, 0x1p-33f);
+        const float u1 = fmaf((float)x1, 0x1p-32f, 0x1p-33f);
+        const float r = sqrtf(-2.0f * logf(u0));
+        float s, c;
+        sincospif(2.0f * u1, &s, &c);
+        a = r * c;
+        b = r * s;
+    }
+};
+
+}  // namespace smf

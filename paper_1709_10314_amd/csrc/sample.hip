@@ -1,0 +1,429 @@
+// Sampling kernels: the latitude-ring state-space recursion with fused Philox normals
+// (Creasey & Lang, Alg. 2; eqs. (state_initial), (state_space)) and the complex-to-real
+// inverse FFT along phi of every ring (Alg. 2, last step).
+#include "rng.h"
+#include "smf_internal.h"
+
+namespace smf {
+namespace {
+
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+// ------------------------------------------------------------------ recursion
+struct RecArgs {
+    int n_theta, n_phi, m_top, m_rows, n_sets, s, even;
+    int lanes_fh;      // lanes per (field, hemisphere): 2 * round_up(m_rows, 32)
+    int count;
+    uint32_t seed_lo, seed_hi;
+};
+
+// Normals of one chain, cached per Philox block; the chain visits rings monotonically
+// (after the start/crossing), so each block is generated once.
+template <typename T, int M>
+struct NoiseStream {
+    uint32_t k0, k1, m, part;
+    int blk;
+    T n[4];
+
+    __device__ void init(uint64_t key, int m_, int part_)
+    {
+        k0 = (uint32_t)key;
+        k1 = (uint32_t)(key >> 32);
+        m = (uint32_t)m_;
+        part = (uint32_t)part_;
+        blk = -1;
+    }
+    __device__ __forceinline__ void fetch(int b)
+    {
+        const PhiloxBlock w = philox4x32_10((uint32_t)b, m, part, 0u, k0, k1);
+        BoxMuller<T>::pair(w.w[0], w.w[1], n[0], n[1]);
+        BoxMuller<T>::pair(w.w[2], w.w[3], n[2], n[3]);
+        blk = b;
+    }
+    // xi_q of ring r
+    __device__ __forceinline__ T get(int r, int q)
+    {
+        const int idx = r * M + q;
+        const int b = idx >> 2;
+        if (b != blk) fetch(b);
+        const int w = idx & 3;
+        return w == 0 ? n[0] : (w == 1 ? n[1] : (w == 2 ? n[2] : n[3]));
+    }
+};
+
+template <typename T, int M>
+struct Factors {
+    T a00, a01, a10, a11, b00, b10, b11;
+};
+
+template <typename T, int M>
+__device__ __forceinline__ Factors<T, M> load_factors(const T* __restrict__ fac, size_t rec)
+{
+    Factors<T, M> F;
+    if (M == 1) {
+        using V2 = typename Vec2<T>::type;
+        const V2 v = *reinterpret_cast<const V2*>(fac + rec * 2);
+        F.a00 = v.x; F.b00 = v.y;
+        F.a01 = F.a10 = F.a11 = F.b10 = F.b11 = T(0);
+    } else {
+        const T* p = fac + rec * 8;
+        F.a00 = p[0]; F.a01 = p[1]; F.a10 = p[2]; F.a11 = p[3];
+        F.b00 = p[4]; F.b10 = p[5]; F.b11 = p[6];
+    }
+    return F;
+}
+
+// One lane per chain (field f, hemisphere h, mode m, part Re/Im).  A wave covers 32 modes
+// x 2 parts of one (f, h), so control flow and ring order are wave-uniform.  The northern
+// chain draws the start state at ring s and steps to ring 0; the southern chain redraws
+// the same start state (same counters), takes the crossing step (even n_theta) and steps
+// to ring n_theta-1 with the mirrored factors, carried as y = D x so that the stored
+// northern A, B apply unchanged with D xi as the noise.
+template <typename T, int M>
+__global__ __launch_bounds__(256) void recursion_kernel(RecArgs a, const T* __restrict__ fac,
+                                                        T* __restrict__ out)
+{
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    const int fh = idx / a.lanes_fh;
+    if (fh >= 2 * a.count) return;
+    const int f = fh >> 1, h = fh & 1;
+    const int rem = idx - fh * a.lanes_fh;
+    const int m = rem >> 1, part = rem & 1;
+    if (m >= a.m_rows) return;
+    T* __restrict__ g = out + (size_t)f * a.n_theta * a.n_phi + 2 * m + part;
+    const int r_lo = h ? a.s + 1 : 0;
+    const int r_hi = h ? a.n_theta : a.s + 1;
+    if (m > a.m_top || (m == 0 && part == 1)) {
+        for (int r = r_lo; r < r_hi; ++r) g[(size_t)r * a.n_phi] = T(0);
+        return;
+    }
+    const uint64_t key = (((uint64_t)a.seed_hi << 32) | a.seed_lo) + (uint64_t)f;
+    NoiseStream<T, M> ns;
+    ns.init(key, m, part);
+    const T sc = (m == 0) ? T(1) : T(0.70710678118654752440);
+
+    // start, eq. (state_initial)
+    const Factors<T, M> F0 = load_factors<T, M>(fac, (size_t)m);
+    T x0, x1 = T(0);
+    {
+        const T w0 = ns.get(a.s, 0);
+        if (M == 1) {
+            x0 = sc * F0.b00 * w0;
+        } else {
+            const T w1 = ns.get(a.s, 1);
+            x0 = sc * (F0.b00 * w0);
+            x1 = sc * (F0.b10 * w0 + F0.b11 * w1);
+        }
+    }
+    const size_t mr = (size_t)a.m_rows;
+    int j0 = 1;
+    if (h == 0) {
+        g[(size_t)a.s * a.n_phi] = x0;
+        if (a.even) j0 = 2;
+        for (int j = j0; j < a.n_sets; ++j) {
+            const int r = a.even ? a.s - j + 1 : a.s - j;
+            const Factors<T, M> F = load_factors<T, M>(fac, (size_t)j * mr + m);
+            const T w0 = ns.get(r, 0);
+            T y0, y1 = T(0);
+            if (M == 1) {
+                y0 = F.a00 * x0 + sc * F.b00 * w0;
+            } else {
+                const T w1 = ns.get(r, 1);
+                y0 = F.a00 * x0 + F.a01 * x1 + sc * (F.b00 * w0);
+                y1 = F.a10 * x0 + F.a11 * x1 + sc * (F.b10 * w0 + F.b11 * w1);
+            }
+            x0 = y0; x1 = y1;
+            g[(size_t)r * a.n_phi] = x0;
+        }
+    } else {
+        if (a.even) {
+            const int r = a.s + 1;
+            const Factors<T, M> F = load_factors<T, M>(fac, mr + m);
+            const T w0 = ns.get(r, 0);
+            T y0, y1 = T(0);
+            if (M == 1) {
+                y0 = F.a00 * x0 + sc * F.b00 * w0;
+            } else {
+                const T w1 = ns.get(r, 1);
+                y0 = F.a00 * x0 + F.a01 * x1 + sc * (F.b00 * w0);
+                y1 = F.a10 * x0 + F.a11 * x1 + sc * (F.b10 * w0 + F.b11 * w1);
+            }
+            x0 = y0; x1 = y1;
+            g[(size_t)r * a.n_phi] = x0;
+            j0 = 2;
+        }
+        x1 = -x1;   // y = D x
+        for (int j = j0; j < a.n_sets; ++j) {
+            const int r = a.s + j;
+            const Factors<T, M> F = load_factors<T, M>(fac, (size_t)j * mr + m);
+            const T w0 = ns.get(r, 0);
+            T y0, y1 = T(0);
+            if (M == 1) {
+                y0 = F.a00 * x0 + sc * F.b00 * w0;
+            } else {
+                const T w1 = -ns.get(r, 1);   // D xi
+                y0 = F.a00 * x0 + F.a01 * x1 + sc * (F.b00 * w0);
+                y1 = F.a10 * x0 + F.a11 * x1 + sc * (F.b10 * w0 + F.b11 * w1);
+            }
+            x0 = y0; x1 = y1;
+            g[(size_t)r * a.n_phi] = x0;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ C2R FFT
+// Per ring: X_m = g_m (m <= m_top, else 0; X_{N-m} = conj X_m), N = n_phi, H = N/2.
+//   T_j = sum_m X_m e^{2 pi i m j / N}
+// via one complex inverse FFT of length H: with w = e^{2 pi i / N},
+//   Z_k = (X_k + conj X_{H-k}) + i w^k (X_k - conj X_{H-k}),  k < H  (X_H = 0),
+//   z_j = sum_k Z_k e^{2 pi i k j / H},   T_{2j} = Re z_j,  T_{2j+1} = Im z_j.
+// The ring is read from and written back to the same memory (the modes were stored in
+// place by the recursion), staged through LDS; Stockham radix-8/4/2 passes, each pass
+// reading all its inputs before a barrier and writing after it.
+
+template <typename T>
+struct Cx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> csub(Cx<T> a, Cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> mul_i(Cx<T> a) { return {-a.im, a.re}; }   // i a
+
+// In-register inverse DFT of size R (kernel e^{+2 pi i r q / R}).
+template <typename T, int R>
+__device__ __forceinline__ void dft_inv(Cx<T>* v)
+{
+    if (R == 2) {
+        const Cx<T> a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if (R == 4) {
+        const Cx<T> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+        const Cx<T> s13 = cadd(v[1], v[3]), d13 = mul_i(csub(v[1], v[3]));
+        v[0] = cadd(s02, s13);
+        v[2] = csub(s02, s13);
+        v[1] = cadd(d02, d13);
+        v[3] = csub(d02, d13);
+    } else {   // R == 8: radix-2 over two size-4 DFTs of the even and odd samples
+        Cx<T> e[4] = {v[0], v[2], v[4], v[6]};
+        Cx<T> o[4] = {v[1], v[3], v[5], v[7]};
+        dft_inv<T, 4>(e);
+        dft_inv<T, 4>(o);
+        const T h = T(0.70710678118654752440);
+        const Cx<T> o1 = {h * (o[1].re - o[1].im), h * (o[1].re + o[1].im)};   // (1+i)/sqrt2
+        const Cx<T> o2 = mul_i(o[2]);                                            // i
+        const Cx<T> o3 = {-h * (o[3].re + o[3].im), h * (o[3].re - o[3].im)};   // (-1+i)/sqrt2
+        v[0] = cadd(e[0], o[0]); v[4] = csub(e[0], o[0]);
+        v[1] = cadd(e[1], o1);   v[5] = csub(e[1], o1);
+        v[2] = cadd(e[2], o2);   v[6] = csub(e[2], o2);
+        v[3] = cadd(e[3], o3);   v[7] = csub(e[3], o3);
+    }
+}
+
+// One Stockham pass of radix R over H points held in LDS buffer `buf`, current
+// sub-transform length Ns.  Butterfly b: k = b mod Ns; inputs buf[b + r H/R] times
+// e^{2 pi i k r / (Ns R)}; outputs to ((b / Ns) Ns R + k) + q Ns.
+template <typename T, int LOG2H, int R, int NT, int LOG2NS>
+__device__ __forceinline__ void stockham_pass(Cx<T>* buf, const Cx<T>* __restrict__ tw)
+{
+    constexpr int Ns = 1 << LOG2NS;
+    constexpr int H = 1 << LOG2H;
+    constexpr int NB = H / R;
+    constexpr int PER = (NB + NT - 1) / NT;
+    Cx<T> v[PER][R];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int b = tid + i * NT;
+        if (NB % NT == 0 || b < NB) {
+            const int k = b & (Ns - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = buf[b + r * NB];
+            if (Ns > 1) {
+                // twiddle exponent k r / (Ns R) of a full turn = (k r N / (Ns R)) / N
+                constexpr int shift = (LOG2H + 1) - (LOG2NS + (R == 8 ? 3 : (R == 4 ? 2 : 1)));
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[(k * r) << shift]);
+            }
+            dft_inv<T, R>(v[i]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int b = tid + i * NT;
+        if (NB % NT == 0 || b < NB) {
+            const int k = b & (Ns - 1);
+            const int o = (b - k) * R + k;
+#pragma unroll
+            for (int q = 0; q < R; ++q) buf[o + q * Ns] = v[i][q];
+        }
+    }
+    __syncthreads();
+}
+
+// Radix 8 while at least 3 bits remain, then one radix-4 or radix-2 pass.
+template <typename T, int LOG2H, int NT, int DONE>
+__device__ __forceinline__ void run_passes(Cx<T>* buf, const Cx<T>* __restrict__ tw)
+{
+    constexpr int REM = LOG2H - DONE;
+    if constexpr (REM >= 3) {
+        stockham_pass<T, LOG2H, 8, NT, DONE>(buf, tw);
+        run_passes<T, LOG2H, NT, DONE + 3>(buf, tw);
+    } else if constexpr (REM == 2) {
+        stockham_pass<T, LOG2H, 4, NT, DONE>(buf, tw);
+    } else if constexpr (REM == 1) {
+        stockham_pass<T, LOG2H, 2, NT, DONE>(buf, tw);
+    }
+}
+
+template <int LOG2H>
+struct FftThreads {
+    static constexpr int value = (1 << LOG2H) / 8 < 64 ? 64 : ((1 << LOG2H) / 8 > 256 ? 256 : (1 << LOG2H) / 8);
+};
+
+template <typename T, int LOG2H>
+__global__ __launch_bounds__(FftThreads<LOG2H>::value) void c2r_kernel(T* __restrict__ data,
+                                                                       const T* __restrict__ twr,
+                                                                       int m_top)
+{
+    constexpr int H = 1 << LOG2H;
+    constexpr int N = 2 * H;
+    constexpr int NT = FftThreads<LOG2H>::value;
+    extern __shared__ unsigned char smem_raw[];
+    Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem_raw);
+    const Cx<T>* tw = reinterpret_cast<const Cx<T>*>(twr);
+    Cx<T>* __restrict__ row = reinterpret_cast<Cx<T>*>(data + (size_t)blockIdx.x * N);
+    const int tid = threadIdx.x;
+
+    // pre-processing: Z_k from X_k and conj X_{H-k}
+    constexpr int PER = (H + NT - 1) / NT;
+    Cx<T> z[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int k = tid + i * NT;
+        if (H % NT == 0 || k < H) {
+            const Cx<T> zero = {T(0), T(0)};
+            const Cx<T> xk = (k <= m_top) ? row[k] : zero;
+            Cx<T> xm = zero;
+            if (k > 0 && H - k <= m_top) {
+                const Cx<T> t = row[H - k];
+                xm = {t.re, -t.im};
+            }
+            const Cx<T> s = cadd(xk, xm);
+            const Cx<T> d = cmul(tw[k], csub(xk, xm));
+            z[i] = cadd(s, mul_i(d));
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int k = tid + i * NT;
+        if (H % NT == 0 || k < H) buf[k] = z[i];
+    }
+    __syncthreads();
+
+    run_passes<T, LOG2H, NT, 0>(buf, tw);
+
+    // T_{2j} + i T_{2j+1} = z_j: the complex result written as interleaved reals
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int k = tid + i * NT;
+        if (H % NT == 0 || k < H) row[k] = buf[k];
+    }
+}
+
+template <typename T, int LOG2H>
+hipError_t launch_c2r_t(const T* tw, int m_top, int rows, T* data, hipStream_t st)
+{
+    constexpr int H = 1 << LOG2H;
+    const size_t lds = sizeof(Cx<T>) * H;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)c2r_kernel<T, LOG2H>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((c2r_kernel<T, LOG2H>), dim3(rows), dim3(FftThreads<LOG2H>::value), lds, st,
+                       data, tw, m_top);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_c2r(int log2h, const T* tw, int m_top, int rows, T* data, hipStream_t st)
+{
+    switch (log2h) {
+        case 1: return launch_c2r_t<T, 1>(tw, m_top, rows, data, st);
+        case 2: return launch_c2r_t<T, 2>(tw, m_top, rows, data, st);
+        case 3: return launch_c2r_t<T, 3>(tw, m_top, rows, data, st);
+        case 4: return launch_c2r_t<T, 4>(tw, m_top, rows, data, st);
+        case 5: return launch_c2r_t<T, 5>(tw, m_top, rows, data, st);
+        case 6: return launch_c2r_t<T, 6>(tw, m_top, rows, data, st);
+        case 7: return launch_c2r_t<T, 7>(tw, m_top, rows, data, st);
+        case 8: return launch_c2r_t<T, 8>(tw, m_top, rows, data, st);
+        case 9: return launch_c2r_t<T, 9>(tw, m_top, rows, data, st);
+        case 10: return launch_c2r_t<T, 10>(tw, m_top, rows, data, st);
+        case 11: return launch_c2r_t<T, 11>(tw, m_top, rows, data, st);
+        case 12: return launch_c2r_t<T, 12>(tw, m_top, rows, data, st);
+        case 13: return launch_c2r_t<T, 13>(tw, m_top, rows, data, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, uint64_t seed, int count,
+                            void* out, hipStream_t st)
+{
+    RecArgs a;
+    a.n_theta = g.n_theta;
+    a.n_phi = g.n_phi;
+    a.m_top = g.m_top;
+    a.m_rows = g.m_rows;
+    a.n_sets = g.n_sets;
+    a.s = g.s;
+    a.even = g.even;
+    a.lanes_fh = 2 * ((g.m_rows + 31) / 32 * 32);
+    a.count = count;
+    a.seed_lo = (uint32_t)seed;
+    a.seed_hi = (uint32_t)(seed >> 32);
+    const long long lanes = (long long)a.lanes_fh * 2 * count;
+    const dim3 grid((unsigned)((lanes + 255) / 256));
+    if (fp64) {
+        if (g.order == 1)
+            hipLaunchKernelGGL((recursion_kernel<double, 1>), grid, dim3(256), 0, st, a,
+                               (const double*)fac, (double*)out);
+        else
+            hipLaunchKernelGGL((recursion_kernel<double, 2>), grid, dim3(256), 0, st, a,
+                               (const double*)fac, (double*)out);
+    } else {
+        if (g.order == 1)
+            hipLaunchKernelGGL((recursion_kernel<float, 1>), grid, dim3(256), 0, st, a,
+                               (const float*)fac, (float*)out);
+        else
+            hipLaunchKernelGGL((recursion_kernel<float, 2>), grid, dim3(256), 0, st, a,
+                               (const float*)fac, (float*)out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_c2r(const Geometry& g, int fp64, const void* tw, int count, void* data,
+                      hipStream_t st)
+{
+    const int log2h = __builtin_ctz((unsigned)g.n_phi) - 1;
+    const int rows = count * g.n_theta;
+    if (rows == 0) return hipSuccess;
+    if (fp64) return dispatch_c2r<double>(log2h, (const double*)tw, g.m_top, rows, (double*)data, st);
+    return dispatch_c2r<float>(log2h, (const float*)tw, g.m_top, rows, (float*)data, st);
+}
+
+}  // namespace smf

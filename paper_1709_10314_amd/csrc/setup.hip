@@ -1,0 +1,311 @@
+// FP64 setup on the GPU: spectrum, cross-covariance blocks by Legendre sums, and the
+// transition / innovation / start factors of every (mode, ring step)
+// (Creasey & Lang, Alg. 1; Lemma 2.1; eqs. (trans_matrix), (innov_matrix), (state_initial)).
+#include "smf_internal.h"
+
+namespace smf {
+namespace {
+
+// ---------------------------------------------------------------- spectrum, eq. (Cl)
+__global__ void spectrum_kernel(const double* __restrict__ kappa, int n_kappa,
+                                const double* __restrict__ c_explicit, int ell_max,
+                                double* __restrict__ C, int* __restrict__ bad)
+{
+    int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l > ell_max) return;
+    double c;
+    if (c_explicit) {
+        c = c_explicit[l];
+    } else {
+        double ll = (double)l * (double)(l + 1);
+        double den = 1.0;
+        for (int i = 0; i < n_kappa; ++i) den *= (kappa[i] + ll);
+        c = 1.0 / den;
+    }
+    // finite and strictly positive, NaN rejected
+    if (!(c > 0.0) || !(c <= 1.7976931348623157e308)) atomicOr(bad, 1);
+    C[l] = c;
+}
+
+// ---------------------------------------------------------------- twiddles
+__global__ void twiddle_kernel(int n, double* __restrict__ tw64, float* __restrict__ tw32)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    double sn, cs;
+    sincospi(2.0 * (double)t / (double)n, &sn, &cs);   // e^{+2 pi i t / n}
+    tw64[2 * t] = cs;
+    tw64[2 * t + 1] = sn;
+    tw32[2 * t] = (float)cs;
+    tw32[2 * t + 1] = (float)sn;
+}
+
+// ---------------------------------------------------------------- Legendre stream
+// Fully normalised L_lm(z) (no Condon-Shortley sign) and dL_lm/dz along l for one ring,
+// carried as mantissa pair (p0 = L_{l-1}, p1 = L_l) times 2^e so the sin^m seed cannot
+// underflow.  value()/deriv() return plain doubles (0 or subnormal below FP64 range).
+struct LegendreStream {
+    double z, inv_s2, p0, p1;
+    int e;
+    __device__ double value() const { return ldexp(p1, e); }
+};
+
+constexpr double kUp = 0x1p400;      // rescale unit 2^400
+constexpr double kDown = 0x1p-400;
+
+// ---------------------------------------------------------------- factorisations
+// Equilibration weight 1/sqrt(d) of a diagonal entry, zero if it is not above kTiny.
+__device__ inline double eq_weight(double d) { return d > kTiny ? 1.0 / sqrt(d) : 0.0; }
+
+// Order 1: scalar blocks.  Writes A (transition) and B (innovation sd).
+__device__ inline void factors_m1(double kaa, double kbb, double kba, double& A, double& B)
+{
+    const double da = eq_weight(kaa), db = eq_weight(kbb);
+    const double raa = da * kaa * da, rbb = db * kbb * db, rba = db * kba * da;
+    const double at = (raa > kTau) ? rba / raa : 0.0;          // R_ba R_aa^+
+    const double st = rbb - at * rba;                           // conditional, equilibrated
+    const double e = st > kTau ? 1.0 / sqrt(st) : 0.0;
+    const double q = e * st * e;
+    const double bt = (e > 0.0 && q > kTau) ? sqrt(q) / e : 0.0;
+    const double sb = db > 0.0 ? sqrt(kbb) : 0.0;
+    A = sb * at * da;
+    B = sb * bt;
+}
+
+// Order 1 start: B_eq = sqrt(J(s,s)).
+__device__ inline double start_m1(double kss)
+{
+    const double d = eq_weight(kss);
+    const double r = d * kss * d;
+    return (d > 0.0 && r > kTau) ? sqrt(kss) * sqrt(r) : 0.0;
+}
+
+// Thresholded Cholesky of a symmetric 2x2 (x00, x01, x11) that is already equilibrated.
+// Lower factor (g00, g10, g11); a dropped pivot leaves its column zero.
+__device__ inline void chol2(double x00, double x01, double x11, double& g00, double& g10,
+                             double& g11, bool& k0, bool& k1)
+{
+    k0 = x00 > kTau;
+    g00 = k0 ? sqrt(x00) : 0.0;
+    g10 = k0 ? x01 / g00 : 0.0;
+    const double piv = x11 - g10 * g10;
+    k1 = piv > kTau;
+    g11 = k1 ? sqrt(piv) : 0.0;
+}
+
+// Order 2 step a -> b.  kaa, kbb symmetric (00, 01, 11); kba full with
+// kba[p][q] = E[x_b,p x_a,q].  A row-major 2x2, B lower (b00, b10, b11).
+__device__ void factors_m2(const double kaa[3], const double kbb[3], const double kba[4],
+                           double A[4], double B[3])
+{
+    const double da0 = eq_weight(kaa[0]), da1 = eq_weight(kaa[2]);
+    const double db0 = eq_weight(kbb[0]), db1 = eq_weight(kbb[2]);
+    // equilibrated blocks
+    const double r00 = da0 * kaa[0] * da0, r01 = da0 * kaa[1] * da1, r11 = da1 * kaa[2] * da1;
+    const double s00 = db0 * kbb[0] * db0, s01 = db0 * kbb[1] * db1, s11 = db1 * kbb[2] * db1;
+    const double c00 = db0 * kba[0] * da0, c01 = db0 * kba[1] * da1;
+    const double c10 = db1 * kba[2] * da0, c11 = db1 * kba[3] * da1;
+    double g00, g10, g11;
+    bool k0, k1;
+    chol2(r00, r01, r11, g00, g10, g11, k0, k1);
+    // At = C R^+ on the kept pivots: for kept {0,1} the inverse of R = G G^T is
+    // (1/(g00^2 g11^2)) [[r11, -r01], [-r01, r00]]; one kept pivot conditions on it alone.
+    double t00, t01, t10, t11;
+    if (k0 && k1) {
+        const double det = (g00 * g00) * (g11 * g11);
+        const double i00 = r11 / det, i01 = -r01 / det, i11 = r00 / det;
+        t00 = c00 * i00 + c01 * i01;
+        t01 = c00 * i01 + c01 * i11;
+        t10 = c10 * i00 + c11 * i01;
+        t11 = c10 * i01 + c11 * i11;
+    } else if (k0) {
+        t00 = c00 / r00; t01 = 0.0;
+        t10 = c10 / r00; t11 = 0.0;
+    } else if (k1) {   // pivot 0 dropped: g10 = 0, so the pivot of index 1 is r11 itself
+        t00 = 0.0; t01 = c01 / r11;
+        t10 = 0.0; t11 = c11 / r11;
+    } else {
+        t00 = t01 = t10 = t11 = 0.0;
+    }
+    // St = S - At C^T, symmetrised
+    const double q00 = s00 - (t00 * c00 + t01 * c01);
+    const double q11 = s11 - (t10 * c10 + t11 * c11);
+    const double q01a = s01 - (t00 * c10 + t01 * c11);
+    const double q10a = s01 - (t10 * c00 + t11 * c01);
+    const double q01 = 0.5 * (q01a + q10a);
+    // its own equilibration, then the thresholded Cholesky
+    const double e0 = q00 > kTau ? 1.0 / sqrt(q00) : 0.0;
+    const double e1 = q11 > kTau ? 1.0 / sqrt(q11) : 0.0;
+    double h00, h10, h11;
+    bool j0, j1;
+    chol2(e0 * q00 * e0, e0 * q01 * e1, e1 * q11 * e1, h00, h10, h11, j0, j1);
+    // undo both equilibrations
+    const double sb0 = db0 > 0.0 ? sqrt(kbb[0]) : 0.0;
+    const double sb1 = db1 > 0.0 ? sqrt(kbb[2]) : 0.0;
+    A[0] = sb0 * t00 * da0;
+    A[1] = sb0 * t01 * da1;
+    A[2] = sb1 * t10 * da0;
+    A[3] = sb1 * t11 * da1;
+    B[0] = e0 > 0.0 ? sb0 * h00 / e0 : 0.0;
+    B[1] = e1 > 0.0 ? sb1 * h10 / e1 : 0.0;
+    B[2] = e1 > 0.0 ? sb1 * h11 / e1 : 0.0;
+}
+
+// Order 2 start: B_eq = chol(J(s,s)) through the equilibrated thresholded Cholesky.
+__device__ void start_m2(const double k[3], double B[3])
+{
+    const double d0 = eq_weight(k[0]), d1 = eq_weight(k[2]);
+    double g00, g10, g11;
+    bool k0, k1;
+    chol2(d0 * k[0] * d0, d0 * k[1] * d1, d1 * k[2] * d1, g00, g10, g11, k0, k1);
+    const double s0 = d0 > 0.0 ? sqrt(k[0]) : 0.0;
+    const double s1 = d1 > 0.0 ? sqrt(k[2]) : 0.0;
+    B[0] = s0 * g00;
+    B[1] = s1 * g10;
+    B[2] = s1 * g11;
+}
+
+// ---------------------------------------------------------------- factor kernel
+// One thread per (set j, mode m); a 64-lane block holds consecutive sets of one mode, so
+// the l loop and its coefficients are uniform across the wave.  Each thread runs the
+// Legendre recurrence at its two rings a, b (Sec. 2 definition of L_lm), accumulates
+// J(a,a), J(b,b), J(b,a) (Lemma 2.1 and the cross covariances), and factorises.
+template <int M>
+__global__ __launch_bounds__(64) void factor_kernel(Geometry g, const double* __restrict__ C,
+                                                    double* __restrict__ f64,
+                                                    float* __restrict__ f32)
+{
+    const int j = blockIdx.x * 64 + threadIdx.x;
+    const int m = blockIdx.y;
+    if (j >= g.n_sets) return;
+    int a, b;
+    if (j == 0) {
+        a = b = g.s;
+    } else if (g.even) {
+        if (j == 1) { a = g.s; b = g.s + 1; }
+        else { a = g.s - j + 2; b = g.s - j + 1; }
+    } else {
+        a = g.s - j + 1; b = g.s - j;
+    }
+    LegendreStream ra, rb;
+    double sa, sb;
+    sincospi(((double)a + 0.5) / (double)g.n_theta, &sa, &ra.z);
+    sincospi(((double)b + 0.5) / (double)g.n_theta, &sb, &rb.z);
+    ra.inv_s2 = 1.0 / (sa * sa);
+    rb.inv_s2 = 1.0 / (sb * sb);
+    // sectoral seed L_mm = sqrt((2m+1)/(4pi) prod_k (2k-1)/(2k)) sin^m, built as
+    // L_kk = sqrt((2k+1)/(2k)) sin L_{k-1,k-1} from L_00 = 1/sqrt(4 pi)
+    double pa = 0.28209479177387814347, pb = pa;   // 1/sqrt(4 pi)
+    int ea = 0, eb = 0;
+    for (int k = 1; k <= m; ++k) {
+        const double f = sqrt((2.0 * k + 1.0) / (2.0 * k));
+        pa *= f * sa;
+        pb *= f * sb;
+        if (fabs(pa) < kDown) { pa *= kUp; ea -= 400; }
+        if (fabs(pb) < kDown) { pb *= kUp; eb -= 400; }
+    }
+    ra.p0 = 0.0; ra.p1 = pa; ra.e = ea;
+    rb.p0 = 0.0; rb.p1 = pb; rb.e = eb;
+
+    double Kaa[3] = {0, 0, 0}, Kbb[3] = {0, 0, 0}, Kba[4] = {0, 0, 0, 0};
+    const double dm = (double)m;
+    double inv_a_prev = 0.0;   // 1 / a_{l-1,m}
+    for (int l = m; l <= g.ell_max; ++l) {
+        const double dl = (double)l;
+        double c_der;          // sqrt((2l+1)(l^2-m^2)/(2l-1)) = (2l+1)/a_lm
+        if (l == m) {
+            c_der = 0.0;
+        } else if (l == m + 1) {
+            const double a1 = sqrt(2.0 * dm + 3.0);
+            ra.p0 = ra.p1; ra.p1 = a1 * ra.z * ra.p0;
+            rb.p0 = rb.p1; rb.p1 = a1 * rb.z * rb.p0;
+            inv_a_prev = 1.0 / a1;
+            c_der = a1;
+        } else {
+            const double q = (4.0 * dl * dl - 1.0) / ((dl - dm) * (dl + dm));
+            const double al = sqrt(q);
+            double t = al * (ra.z * ra.p1 - inv_a_prev * ra.p0);
+            ra.p0 = ra.p1; ra.p1 = t;
+            t = al * (rb.z * rb.p1 - inv_a_prev * rb.p0);
+            rb.p0 = rb.p1; rb.p1 = t;
+            inv_a_prev = 1.0 / al;
+            c_der = (2.0 * dl + 1.0) * inv_a_prev;
+        }
+        if (ra.e < 0 && fabs(ra.p1) > kUp) { ra.p0 *= kDown; ra.p1 *= kDown; ra.e += 400; }
+        if (rb.e < 0 && fabs(rb.p1) > kUp) { rb.p0 *= kDown; rb.p1 *= kDown; rb.e += 400; }
+        const double cl = C[l];
+        const double va = ra.value(), vb = rb.value();
+        if (M == 1) {
+            Kaa[0] = fma(cl * va, va, Kaa[0]);
+            Kbb[0] = fma(cl * vb, vb, Kbb[0]);
+            Kba[0] = fma(cl * vb, va, Kba[0]);
+        } else {
+            // (1 - z^2) dL_l/dz = -l z L_l + c_der L_{l-1}
+            const double da = ldexp((c_der * ra.p0 - dl * ra.z * ra.p1) * ra.inv_s2, ra.e);
+            const double db = ldexp((c_der * rb.p0 - dl * rb.z * rb.p1) * rb.inv_s2, rb.e);
+            const double cva = cl * va, cda = cl * da, cvb = cl * vb, cdb = cl * db;
+            Kaa[0] = fma(cva, va, Kaa[0]);
+            Kaa[1] = fma(cva, da, Kaa[1]);
+            Kaa[2] = fma(cda, da, Kaa[2]);
+            Kbb[0] = fma(cvb, vb, Kbb[0]);
+            Kbb[1] = fma(cvb, db, Kbb[1]);
+            Kbb[2] = fma(cdb, db, Kbb[2]);
+            Kba[0] = fma(cvb, va, Kba[0]);
+            Kba[1] = fma(cvb, da, Kba[1]);
+            Kba[2] = fma(cdb, va, Kba[2]);
+            Kba[3] = fma(cdb, da, Kba[3]);
+        }
+    }
+
+    const size_t base = ((size_t)j * g.m_rows + m) * factor_stride(M);
+    if (M == 1) {
+        double A, B;
+        if (j == 0) { A = 0.0; B = start_m1(Kaa[0]); }
+        else factors_m1(Kaa[0], Kbb[0], Kba[0], A, B);
+        f64[base] = A;
+        f64[base + 1] = B;
+        if (f32) { f32[base] = (float)A; f32[base + 1] = (float)B; }
+    } else {
+        double A[4] = {0, 0, 0, 0}, B[3];
+        if (j == 0) start_m2(Kaa, B);
+        else factors_m2(Kaa, Kbb, Kba, A, B);
+        const double v[8] = {A[0], A[1], A[2], A[3], B[0], B[1], B[2], 0.0};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) f64[base + i] = v[i];
+        if (f32) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) f32[base + i] = (float)v[i];
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_spectrum(const double* kappa_dev, int n_kappa, const double* c_explicit_dev,
+                           int ell_max, double* C_dev, int* bad_dev, hipStream_t st)
+{
+    const int n = ell_max + 1;
+    hipLaunchKernelGGL(spectrum_kernel, dim3((n + 255) / 256), dim3(256), 0, st, kappa_dev,
+                       n_kappa, c_explicit_dev, ell_max, C_dev, bad_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_factors(const Geometry& g, const double* C_dev, double* f64, float* f32,
+                          hipStream_t st)
+{
+    dim3 grid((g.n_sets + 63) / 64, g.m_top + 1);
+    if (g.order == 1)
+        hipLaunchKernelGGL(factor_kernel<1>, grid, dim3(64), 0, st, g, C_dev, f64, f32);
+    else
+        hipLaunchKernelGGL(factor_kernel<2>, grid, dim3(64), 0, st, g, C_dev, f64, f32);
+    return hipGetLastError();
+}
+
+hipError_t launch_twiddles(int n_phi, double* tw64, float* tw32, hipStream_t st)
+{
+    hipLaunchKernelGGL(twiddle_kernel, dim3((n_phi + 255) / 256), dim3(256), 0, st, n_phi, tw64,
+                       tw32);
+    return hipGetLastError();
+}
+
+}  // namespace smf

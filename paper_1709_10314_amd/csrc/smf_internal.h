@@ -1,0 +1,73 @@
+// Internal declarations shared by the HIP translation units of libsmf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/smf.h"
+
+namespace smf {
+
+// Thresholds of the factorisation (equilibrated, thresholded Cholesky):
+//   a block diagonal entry not above kTiny is exactly zero (its row/column is dropped);
+//   after equilibration a pivot, or a conditional variance relative to the marginal one,
+//   not above kTau is dropped.
+constexpr double kTiny = 1e-290;
+constexpr double kTau = 1e-12;
+
+// Factor record per (set j, mode m): M = 1 -> {A00, B00};
+// M = 2 -> {A00, A01, A10, A11, B00, B10, B11, 0}.  Stored [set][m][E], m stride n_phi/2.
+__host__ __device__ constexpr int factor_stride(int order) { return order == 1 ? 2 : 8; }
+
+struct Geometry {
+    int order;       // Markov order M
+    int n_theta;
+    int n_phi;
+    int ell_max;
+    int m_top;       // highest mode sampled
+    int m_rows;      // n_phi / 2 rows per factor set (m > m_top rows are zero)
+    int n_sets;      // factor sets per mode
+    int s;           // start ring
+    int even;        // n_theta even (crossing step present)
+};
+
+inline Geometry make_geometry(int order, int n_theta, int n_phi, int ell_max)
+{
+    Geometry g;
+    g.order = order;
+    g.n_theta = n_theta;
+    g.n_phi = n_phi;
+    g.ell_max = ell_max;
+    g.m_top = ell_max < n_phi / 2 - 1 ? ell_max : n_phi / 2 - 1;
+    g.m_rows = n_phi / 2;
+    g.even = (n_theta % 2 == 0);
+    g.n_sets = g.even ? n_theta / 2 + 1 : (n_theta + 1) / 2;
+    g.s = g.even ? n_theta / 2 - 1 : (n_theta - 1) / 2;
+    return g;
+}
+
+// ---- setup (FP64) ----
+hipError_t launch_spectrum(const double* kappa_dev, int n_kappa, const double* c_explicit_dev,
+                           int ell_max, double* C_dev, int* bad_dev, hipStream_t st);
+hipError_t launch_factors(const Geometry& g, const double* C_dev, double* f64, float* f32,
+                          hipStream_t st);
+hipError_t launch_twiddles(int n_phi, double* tw64, float* tw32, hipStream_t st);
+
+// ---- sampling ----
+hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, uint64_t seed, int count,
+                            void* out, hipStream_t st);
+hipError_t launch_c2r(const Geometry& g, int fp64, const void* tw, int count, void* data,
+                      hipStream_t st);
+
+}  // namespace smf
+
+struct smf_plan {
+    smf::Geometry g;
+    int flags;           // SMF_FP64 or SMF_FP32
+    double* C;           // [ell_max + 1]
+    double* f64;         // FP64 factors
+    float* f32;          // FP32 factors (SMF_FP32 plans)
+    double* tw64;        // e^{+2 pi i t / n_phi}, t < n_phi
+    float* tw32;
+    int device;
+};

@@ -1,0 +1,206 @@
+"""ctypes binding of libsmf (include/smf.h): the same entry points, argument marshalling only.
+
+Device memory and streams come from PyTorch (``tensor.data_ptr()``,
+``torch.cuda.current_stream().cuda_stream``); every step of setup and sampling runs in the
+library's HIP kernels.  There is no fallback: if libsmf.so is missing or fails to load,
+``load()`` raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsmf.so")
+
+SMF_OK, SMF_EINVAL, SMF_ENOMEM, SMF_EHIP, SMF_ENUMERIC = 0, -1, -2, -3, -4
+SMF_FP64, SMF_FP32 = 1, 2
+
+# every symbol include/smf.h declares
+EXPORTS = ("smf_setup", "smf_sample", "smf_sample_modes", "smf_plan_dims", "smf_get_factors",
+           "smf_destroy", "smf_error_string")
+
+
+class smf_spectrum(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int), ("n_kappa", ctypes.c_int),
+                ("kappa", ctypes.POINTER(ctypes.c_double)),
+                ("c_ell", ctypes.POINTER(ctypes.c_double)), ("ell_max", ctypes.c_int)]
+
+
+class SmfError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__(f"{what}: {smf_error_string(code)} ({code})")
+
+
+_lib = None
+
+
+def load():
+    """Load libsmf.so (built by paper_1709_10314_amd/build.py); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64
+    lib.smf_setup.argtypes = [ctypes.POINTER(smf_spectrum), i, i, i, vp, ctypes.POINTER(vp)]
+    lib.smf_sample.argtypes = [vp, u64, i, vp, vp]
+    lib.smf_sample_modes.argtypes = [vp, u64, i, vp, vp]
+    lib.smf_plan_dims.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    lib.smf_get_factors.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.smf_destroy.argtypes = [vp]
+    lib.smf_error_string.argtypes = [i]
+    lib.smf_error_string.restype = ctypes.c_char_p
+    for name in ("smf_setup", "smf_sample", "smf_sample_modes", "smf_plan_dims",
+                 "smf_get_factors", "smf_destroy"):
+        getattr(lib, name).restype = i
+    _lib = lib
+    return lib
+
+
+def smf_error_string(code):
+    return load().smf_error_string(int(code)).decode()
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def smf_setup(order, n_theta, n_phi, ell_max, kappa=None, c_ell=None, flags=SMF_FP32, stream=None):
+    """Returns (code, plan handle).  kappa: factors of C_l (eq. (Cl)); c_ell: explicit C_l."""
+    lib = load()
+    spec = smf_spectrum()
+    spec.order = int(order)
+    spec.ell_max = int(ell_max)
+    keep = []
+    if c_ell is not None:
+        c = np.ascontiguousarray(c_ell, dtype=np.float64)
+        keep.append(c)
+        spec.c_ell = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        spec.n_kappa = 0
+    else:
+        k = np.ascontiguousarray([] if kappa is None else kappa, dtype=np.float64).reshape(-1)
+        keep.append(k)
+        spec.n_kappa = len(k)
+        spec.kappa = k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if len(k) else None
+    plan = ctypes.c_void_p()
+    rc = lib.smf_setup(ctypes.byref(spec), int(n_theta), int(n_phi), int(flags),
+                       _stream_handle(stream), ctypes.byref(plan))
+    return rc, plan
+
+
+def smf_sample(plan, seed, count, out_ptr, stream=None):
+    return load().smf_sample(plan, ctypes.c_uint64(int(seed)), int(count), ctypes.c_void_p(out_ptr),
+                             _stream_handle(stream))
+
+
+def smf_sample_modes(plan, seed, count, g_ptr, stream=None):
+    return load().smf_sample_modes(plan, ctypes.c_uint64(int(seed)), int(count), ctypes.c_void_p(g_ptr),
+                                   _stream_handle(stream))
+
+
+def smf_plan_dims(plan):
+    d = (ctypes.c_int * 8)()
+    rc = load().smf_plan_dims(plan, d)
+    return rc, list(d)
+
+
+def smf_get_factors(plan, A, B):
+    pd = ctypes.POINTER(ctypes.c_double)
+    return load().smf_get_factors(plan, A.ctypes.data_as(pd), B.ctypes.data_as(pd))
+
+
+def smf_destroy(plan):
+    return load().smf_destroy(plan)
+
+
+class Plan:
+    """A setup plan (Alg. 1 factors on the GPU) with sampling methods (Alg. 2)."""
+
+    def __init__(self, order, n_theta, n_phi, ell_max, kappa=None, c_ell=None, precision="fp32",
+                 stream=None):
+        flags = {"fp32": SMF_FP32, "fp64": SMF_FP64}[precision]
+        rc, h = smf_setup(order, n_theta, n_phi, ell_max, kappa=kappa, c_ell=c_ell, flags=flags,
+                          stream=stream)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_setup")
+        self._h = h
+        rc, d = smf_plan_dims(h)
+        (self.order, self.n_theta, self.n_phi, self.ell_max, self.m_top, self.n_sets,
+         self.start_ring, fl) = d
+        self.precision = "fp64" if fl == SMF_FP64 else "fp32"
+
+    @property
+    def handle(self):
+        return self._h
+
+    def dtype(self):
+        import torch
+
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    def empty(self, count, device="cuda"):
+        import torch
+
+        return torch.empty((count, self.n_theta, self.n_phi), dtype=self.dtype(), device=device)
+
+    def sample(self, seed, count, out=None, stream=None):
+        """count fields keyed seed..seed+count-1 as a [count, n_theta, n_phi] tensor."""
+        if out is None:
+            out = self.empty(count)
+        self._check_out(out, count)
+        rc = smf_sample(self._h, seed, count, out.data_ptr(), stream)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_sample")
+        return out
+
+    def sample_modes(self, seed, count, out=None, stream=None):
+        """Pre-FFT modes g_m as [count, n_theta, n_phi/2, 2] (Re, Im) in the sample dtype."""
+        if out is None:
+            out = self.empty(count)
+        self._check_out(out, count)
+        rc = smf_sample_modes(self._h, seed, count, out.data_ptr(), stream)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_sample_modes")
+        return out.view(count, self.n_theta, self.n_phi // 2, 2)
+
+    def factors(self):
+        """FP64 (A, B), each [n_sets, m_top+1, order, order]."""
+        shape = (self.n_sets, self.m_top + 1, self.order, self.order)
+        A = np.zeros(shape)
+        B = np.zeros(shape)
+        rc = smf_get_factors(self._h, A, B)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_get_factors")
+        return A, B
+
+    def _check_out(self, out, count):
+        if not out.is_cuda or out.dtype != self.dtype() or not out.is_contiguous():
+            raise ValueError("output must be a contiguous device tensor of the plan's dtype")
+        if out.numel() < count * self.n_theta * self.n_phi:
+            raise ValueError("output tensor too small")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            smf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,42 @@
+"""Seeded synthetic workloads of the benchmark and the tests.
+
+Only shapes, spectra parameters and seeds live here (no arithmetic of the method), so
+both the HIP path and the oracle can be driven from the same definitions.  Spectra are
+C_l = (l(l+1) + kappa^2)^-M, i.e. M repeated factors kappa_i = kappa^2 of eq. (Cl);
+ell_max is the band limit of the Legendre sums.
+"""
+import math
+
+import numpy as np
+
+PLAIN_SMALL = dict(name="plain-64x128-M1-fp64", n_theta=64, n_phi=128, order=1, kappa=8.0,
+                   ell_max=63, count=1, seed=1, precision="fp64")
+PLAIN_1024 = dict(name="plain-1024x2048-M1-fp64-x16", n_theta=1024, n_phi=2048, order=1,
+                  kappa=20.0, ell_max=1023, count=16, seed=1, precision="fp64")
+PRECISION_4096 = dict(name="precision-4096x8192-M2-fp32-x8", n_theta=4096, n_phi=8192, order=2,
+                      kappa=50.0, ell_max=4095, count=8, seed=1, precision="fp32")
+PRECISION_8192 = dict(name="precision-8192x16384-M2-fp32-x4", n_theta=8192, n_phi=16384,
+                      order=2, kappa=100.0, ell_max=8191, count=4, seed=1, precision="fp32")
+
+CONFIGS = [PLAIN_SMALL, PLAIN_1024, PRECISION_4096, PRECISION_8192]
+
+
+def kappas(cfg):
+    """kappa_i of eq. (Cl) for a config: kappa^2 repeated `order` times."""
+    return [cfg["kappa"] ** 2] * cfg["order"]
+
+
+def batch_mix(n_fields=256, seed=0):
+    """Mixed batch: n_theta uniform on {128, ..., 2048}, n_phi = 2 n_theta, ln kappa
+    uniform on [ln 2, ln 200], order 1 or 2 with equal probability, ell_max = n_theta - 1,
+    Philox seeds 1..n_fields.  Drawn with numpy's PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = np.array([128, 256, 512, 1024, 2048])
+    out = []
+    for f in range(n_fields):
+        n_theta = int(rng.choice(sizes))
+        kappa = float(math.exp(rng.uniform(math.log(2.0), math.log(200.0))))
+        order = int(1 + rng.integers(0, 2))
+        out.append(dict(n_theta=n_theta, n_phi=2 * n_theta, order=order, kappa=kappa,
+                        ell_max=n_theta - 1, seed=1 + f, precision="fp32"))
+    return out

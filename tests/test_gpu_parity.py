@@ -1,0 +1,264 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same
+Philox normals.  Bars: FP64 path <= 1e-10 relative RMS per field, FP32 path <= 1e-4;
+factors (FP64 setup) within 1e-10 (A) and 1e-8 (B) in units of the marginal standard
+deviations (B = chol(S) inherits eps/sqrt(S~) from the cancelling S = J(b,b) - A J(a,b),
+and the threshold keeps S~ above 1e-12)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import factor_errors, log, rel_rms
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-4}
+
+
+def _plan(order, n_theta, n_phi, ell_max, kappa, precision):
+    from paper_1709_10314_amd import Plan
+
+    return Plan(order, n_theta, n_phi, ell_max, kappa=[kappa] * order, precision=precision)
+
+
+def _gpu_modes(plan, seed, count):
+    g = plan.sample_modes(seed, count)
+    torch.cuda.synchronize()
+    g = g.double().cpu().numpy()
+    return g[..., 0] + 1j * g[..., 1]
+
+
+# (order, kappa_i, n_theta, n_phi, ell_max): several tiles, ragged tails, odd/even rings,
+# truncated modes (ell_max > n_phi/2 - 1) and band-limited modes (ell_max < n_phi/2 - 1)
+SMALL = [
+    (1, 64.0, 64, 128, 63),
+    (1, 400.0, 33, 64, 40),
+    (2, 2500.0, 16, 32, 15),
+    (2, 100.0, 24, 128, 63),
+    (2, 9.0, 21, 64, 20),
+    (1, 3.0, 10, 256, 70),
+    (2, 30.0, 2, 4, 5),
+    (1, 12.0, 3, 8, 2),
+    (2, 700.0, 130, 256, 200),
+]
+
+
+@pytest.mark.parametrize("case", SMALL, ids=lambda c: "M%d-k%g-%dx%d-l%d" % c)
+def test_factors_match_oracle(case):
+    order, kap, n, nphi, lmax = case
+    log(f"factors {case}")
+    plan = _plan(order, n, nphi, lmax, kap, "fp64")
+    Ag, Bg = plan.factors()
+    plan.close()
+    C = oracle.spectrum([kap] * order, lmax)
+    Ao, Bo = oracle.setup(order, C, n, nphi)
+    assert Ag.shape == Ao.shape
+    dA, dB = factor_errors(Ag, Bg, Ao, Bo, n)
+    log(f"  max dA {dA:.3e}  max dB {dB:.3e}")
+    assert dA < 1e-10 and dB < 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", SMALL, ids=lambda c: "M%d-k%g-%dx%d-l%d" % c)
+def test_modes_and_field_match_oracle(case, precision):
+    order, kap, n, nphi, lmax = case
+    log(f"modes+field {case} {precision}")
+    count, seed = 3, 17
+    plan = _plan(order, n, nphi, lmax, kap, precision)
+    g = _gpu_modes(plan, seed, count)
+    T = plan.sample(seed, count)
+    torch.cuda.synchronize()
+    T = T.double().cpu().numpy()
+    mt = plan.m_top
+    plan.close()
+    C = oracle.spectrum([kap] * order, lmax)
+    A, B = oracle.setup(order, C, n, nphi)
+    To, go = oracle.sample(order, n, nphi, A, B, seed, count)
+    assert np.all(g[:, :, mt + 1:] == 0)
+    for f in range(count):
+        eg = rel_rms(np.stack([g[f, :, : mt + 1].real, g[f, :, : mt + 1].imag]),
+                     np.stack([go[f].real, go[f].imag]))
+        eT = rel_rms(T[f], To[f])
+        log(f"  field {f}: modes {eg:.3e}  field {eT:.3e}")
+        assert eg <= TOL[precision] and eT <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_plain_64x128_config(precision):
+    """The 64 x 128 plain form: C_l = (l(l+1) + 64)^-1, ell_max 63, seed 1, one field."""
+    log(f"plain 64x128 {precision}")
+    plan = _plan(1, 64, 128, 63, 64.0, precision)
+    T = plan.sample(1, 1)
+    torch.cuda.synchronize()
+    T = T.double().cpu().numpy()
+    plan.close()
+    C = oracle.spectrum([64.0], 63)
+    A, B = oracle.setup(1, C, 64, 128)
+    To, _ = oracle.sample(1, 64, 128, A, B, 1, 1)
+    e = rel_rms(T[0], To[0])
+    log(f"  rel RMS {e:.3e}")
+    assert e <= TOL[precision]
+
+
+def test_plain_1024x2048_x16_full_size():
+    """16 fields on 1024 x 2048, kappa = 20, M = 1, FP64, seeds 1..16: every mode of
+    every ring against the oracle, and the field on 12 sampled rings."""
+    n, nphi, lmax, kap, count = 1024, 2048, 1023, 400.0, 16
+    log("plain 1024x2048 x16: GPU")
+    plan = _plan(1, n, nphi, lmax, kap, "fp64")
+    Ag, Bg = plan.factors()
+    g = _gpu_modes(plan, 1, count)
+    T = plan.sample(1, count)
+    torch.cuda.synchronize()
+    T = T.cpu().numpy()
+    plan.close()
+    log("  oracle setup")
+    C = oracle.spectrum([kap], lmax)
+    Ao, Bo = oracle.setup(1, C, n, nphi)
+    dA, dB = factor_errors(Ag, Bg, Ao, Bo, n)
+    log(f"  factors dA {dA:.3e} dB {dB:.3e}")
+    assert dA < 1e-10 and dB < 1e-8
+    log("  oracle chains")
+    go = oracle.sample_modes(1, n, Ao, Bo, 1, count)
+    rings = [0, 1, 100, 400, 510, 511, 512, 513, 700, 1000, 1022, 1023]
+    for f in range(count):
+        eg = rel_rms(np.stack([g[f].real, g[f].imag]), np.stack([go[f].real, go[f].imag]))
+        assert eg <= 1e-10, (f, eg)
+    log("  oracle DFT on sampled rings")
+    gs = go[:, rings, :]
+    To = oracle.dft(gs, nphi)
+    for f in range(count):
+        eT = rel_rms(T[f][rings], To[f])
+        log(f"  field {f}: field {eT:.3e}")
+        assert eT <= 1e-10
+
+
+def _full_size_precision_form(n, nphi, lmax, kap, count):
+    """FP32 precision form at full size: the field on rings next to the equator against
+    the oracle over all modes (the oracle builds only the factor sets those rings need),
+    and every ring of sampled modes against the oracle."""
+    order = 2
+    s = n // 2 - 1
+    log(f"precision form {n}x{nphi} x{count}: GPU")
+    plan = _plan(order, n, nphi, lmax, kap, "fp32")
+    T = plan.sample(1, count)
+    torch.cuda.synchronize()
+    rings = list(range(s - 2, s + 4))
+    Tr = T[:, rings, :].double().cpu().numpy()
+    del T
+    g = _gpu_modes(plan, 1, count)
+    Ag, Bg = plan.factors()
+    plan.close()
+    torch.cuda.empty_cache()
+    C = oracle.spectrum([kap] * order, lmax)
+    log("  oracle: near-equator factors for all modes")
+    sets = 4
+    Ae, Be = oracle.setup(order, C, n, nphi, sets=sets)
+    ge = oracle.sample_modes(order, n, Ae, Be, 1, count, sets=sets)
+    To = oracle.dft(ge[:, rings, :], nphi)
+    for f in range(count):
+        eT = rel_rms(Tr[f], To[f])
+        log(f"  field {f}: near-equator field {eT:.3e}")
+        assert eT <= 1e-4
+    modes = [0, 1, 2, 3, 97, lmax // 2, lmax // 2 + 1, lmax - 2, lmax - 1, lmax]
+    log(f"  oracle: all rings of modes {modes}")
+    Am, Bm = oracle.setup_modes(order, C, n, modes)
+    dA, dB = factor_errors(Ag[:, modes], Bg[:, modes], Am, Bm, n)
+    log(f"  factors dA {dA:.3e} dB {dB:.3e}")
+    assert dA < 1e-10 and dB < 1e-8
+    gm = oracle.sample_modes_list(order, n, modes, Am, Bm, 1, count)
+    for f in range(count):
+        eg = rel_rms(np.stack([g[f][:, modes].real, g[f][:, modes].imag]),
+                     np.stack([gm[f].real, gm[f].imag]))
+        log(f"  field {f}: sampled modes {eg:.3e}")
+        assert eg <= 1e-4
+
+
+def test_precision_4096x8192_x8_full_size():
+    _full_size_precision_form(4096, 8192, 4095, 2500.0, 8)
+
+
+def test_determinism_and_field_keying():
+    plan = _plan(2, 40, 64, 31, 100.0, "fp64")
+    a = plan.sample(5, 4).cpu().numpy()
+    b = plan.sample(5, 4).cpu().numpy()
+    assert np.array_equal(a, b)
+    for f in range(4):
+        c = plan.sample(5 + f, 1).cpu().numpy()
+        assert np.array_equal(a[f], c[0])
+    plan.close()
+
+
+def test_constant_field_lmax_zero():
+    """ell_max = 0: one constant N(0, C_0/(4 pi)) over the sphere."""
+    for prec in ("fp64", "fp32"):
+        plan = _plan(1, 12, 16, 0, 3.0, prec)
+        T = plan.sample(11, 2).double().cpu().numpy()
+        plan.close()
+        for f in range(2):
+            xi = oracle.normal(11 + f, 0, 0, oracle.start_ring(12), 1, 0)
+            np.testing.assert_allclose(T[f], np.sqrt(1 / 3.0 / (4 * np.pi)) * xi, rtol=TOL[prec])
+
+
+def test_error_codes():
+    from paper_1709_10314_amd import smf
+
+    for args in [(3, 8, 16, 5), (1, 1, 16, 5), (1, 8, 12, 5), (1, 8, 2, 5), (1, 8, 32768, 5),
+                 (1, 8, 16, -1)]:
+        rc, h = smf.smf_setup(*args, kappa=[4.0], flags=smf.SMF_FP64)
+        assert rc == smf.SMF_EINVAL, args
+    rc, _ = smf.smf_setup(1, 8, 16, 5, kappa=[4.0], flags=3)
+    assert rc == smf.SMF_EINVAL
+    rc, _ = smf.smf_setup(1, 8, 16, 5, kappa=[0.0], flags=smf.SMF_FP64)       # C_0 = 1/0
+    assert rc == smf.SMF_ENUMERIC
+    rc, _ = smf.smf_setup(1, 8, 16, 5, c_ell=[1.0, 0.5, -1.0, 1.0, 1.0, 1.0], flags=smf.SMF_FP32)
+    assert rc == smf.SMF_ENUMERIC
+    rc, _ = smf.smf_setup(1, 8, 16, 5, c_ell=[1.0, 0.5, float("nan"), 1.0, 1.0, 1.0], flags=smf.SMF_FP32)
+    assert rc == smf.SMF_ENUMERIC
+    plan = _plan(1, 8, 16, 5, 4.0, "fp32")
+    assert smf.smf_sample(plan.handle, 1, -1, 0) == smf.SMF_EINVAL
+    assert smf.smf_sample(plan.handle, 1, 0, 0) == smf.SMF_OK
+    assert smf.smf_sample(plan.handle, 1, 2, 0) == smf.SMF_EINVAL
+    plan.close()
+
+
+def test_explicit_spectrum_matches_rational_form():
+    """c_ell given explicitly reproduces the kappa form exactly."""
+    from paper_1709_10314_amd import Plan
+
+    C = oracle.spectrum([50.0, 50.0], 31)
+    p1 = Plan(2, 20, 64, 31, c_ell=C, precision="fp64")
+    p2 = Plan(2, 20, 64, 31, kappa=[50.0, 50.0], precision="fp64")
+    a = p1.sample(3, 2).cpu().numpy()
+    b = p2.sample(3, 2).cpu().numpy()
+    p1.close()
+    p2.close()
+    assert rel_rms(a, b) < 1e-14
+
+
+def test_empirical_covariance_of_gpu_samples():
+    """Sec. 5's validation on GPU samples: N = 10^5 fields on 8 x 128, covariance
+    against C_T(x, y) = sum_l (2l+1)/(4 pi) C_l P_l(<x, y>) within 5 standard errors plus
+    the chain's Markov defect (bounded from the oracle's factors)."""
+    from test_oracle_pins import _addition_target, _markov_defect
+
+    order, kap, n, lmax = 1, 20.0, 8, 63
+    nphi = 2 * (lmax + 1)
+    plan = _plan(order, n, nphi, lmax, kap, "fp32")
+    N = 100_000
+    T = plan.sample(99, N).double().cpu().numpy()
+    plan.close()
+    C = oracle.spectrum([kap] * order, lmax)
+    A, B = oracle.setup(order, C, n, nphi)
+    th, _ = oracle.grid(n)
+    var = np.sum((2 * np.arange(lmax + 1) + 1) * C) / (4 * np.pi)
+    defect = _markov_defect(oracle, order, A, B, n, lmax, C)
+    jj = np.arange(0, nphi, 8)
+    phis = 2 * np.pi * jj / nphi
+    for a in range(n):
+        emp = np.einsum("k,kbj->bj", T[:, a, 0], T[:, :, jj]) / N
+        cosg = (np.cos(th[a]) * np.cos(th)[:, None]
+                + np.sin(th[a]) * np.sin(th)[:, None] * np.cos(phis)[None, :])
+        ref = np.vectorize(lambda c: _addition_target(C, c))(cosg)
+        tol = 5 * np.sqrt((var * var + ref ** 2) / N) + defect[a][:, None]
+        assert np.all(np.abs(emp - ref) <= tol), (a, np.max(np.abs(emp - ref) / tol))

@@ -79,6 +79,7 @@ def _load():
     lib.orc_sample_modes_list.restype = _i
     lib.orc_dft.argtypes = [_i, _i, _i, _i, _i, _i, _pd, _pd]
     lib.orc_dft.restype = _i
+    lib.orc_max_threads.restype = _i
     _lib = lib
     return lib
 
@@ -173,6 +174,11 @@ def sample_modes_list(order, n_theta, modes, A, B, seed, count, sets=None):
     _load().orc_sample_modes_list(order, n_theta, md.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                                   len(md), ns, _p(A), _p(B), int(seed), count, _p(g))
     return g[..., 0] + 1j * g[..., 1]
+
+
+def max_threads():
+    """OpenMP threads the oracle's parallel loops use."""
+    return _load().orc_max_threads()
 
 
 def philox(ctr, key):

@@ -42,6 +42,9 @@
  *             pairs (0,1) and (2,3).
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -53,6 +56,16 @@
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
 #endif
+
+/* Threads an OpenMP region of the oracle will use. */
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------- */
 /* Grid (Sec. 4, with the ring-centre reading above).                          */
@@ -232,34 +245,34 @@ void orc_step_factors(int M, const double* Kaa, const double* Kbb, const double*
         }
     thr_chol(M, Raa, G, kept);
 
-    /* At = Rba Raa^+ on the kept pivots: each row r of At solves (G G^T) r^T = Rba[i,:]^T */
+    /* With Raa = G G^T on the kept pivots, eq. (innov_matrix) reads
+       St = Rbb - (Rba G^-T)(Rba G^-T)^T and eq. (trans_matrix) At = (Rba G^-T) G^-1:
+       Y = Rba G^-T by forward substitution (row i of Y solves G y = Rba[i,:]^T), then
+       At = Y G^-1 by back substitution; this keeps rounding at eps/sqrt(pivot) instead
+       of the eps/pivot of an explicit inverse. */
+    double Y[ORC_MAXM * ORC_MAXM];
     for (int i = 0; i < M; ++i) {
-        double w[ORC_MAXM], u[ORC_MAXM];
-        for (int j = 0; j < M; ++j) {               /* forward: G w = v */
-            if (!kept[j]) { w[j] = 0.0; continue; }
+        double u[ORC_MAXM];
+        for (int j = 0; j < M; ++j) {               /* forward: G y = v */
+            if (!kept[j]) { Y[i * M + j] = 0.0; continue; }
             double v = Rba[i * M + j];
-            for (int k = 0; k < j; ++k) if (kept[k]) v -= G[j * M + k] * w[k];
-            w[j] = v / G[j * M + j];
+            for (int k = 0; k < j; ++k) if (kept[k]) v -= G[j * M + k] * Y[i * M + k];
+            Y[i * M + j] = v / G[j * M + j];
         }
-        for (int j = M - 1; j >= 0; --j) {          /* backward: G^T u = w */
+        for (int j = M - 1; j >= 0; --j) {          /* backward: G^T u = y */
             if (!kept[j]) { u[j] = 0.0; continue; }
-            double v = w[j];
+            double v = Y[i * M + j];
             for (int k = j + 1; k < M; ++k) if (kept[k]) v -= G[k * M + j] * u[k];
             u[j] = v / G[j * M + j];
         }
         for (int j = 0; j < M; ++j) At[i * M + j] = u[j];
     }
-    /* St = Rbb - At Rba^T, symmetrised */
+    /* St = Rbb - Y Y^T (symmetric by construction) */
     for (int p = 0; p < M; ++p)
         for (int q = 0; q < M; ++q) {
             double v = Rbb[p * M + q];
-            for (int k = 0; k < M; ++k) v -= At[p * M + k] * Rba[q * M + k];
+            for (int k = 0; k < M; ++k) v -= Y[p * M + k] * Y[q * M + k];
             St[p * M + q] = v;
-        }
-    for (int p = 0; p < M; ++p)
-        for (int q = 0; q < p; ++q) {
-            double v = 0.5 * (St[p * M + q] + St[q * M + p]);
-            St[p * M + q] = St[q * M + p] = v;
         }
     /* B~ = chol(St) with its own equilibration; a relative conditional variance
        not above ORC_TAU is treated as zero */

@@ -62,8 +62,12 @@ __device__ inline void factors_m1(double kaa, double kbb, double kba, double& A,
 {
     const double da = eq_weight(kaa), db = eq_weight(kbb);
     const double raa = da * kaa * da, rbb = db * kbb * db, rba = db * kba * da;
-    const double at = (raa > kTau) ? rba / raa : 0.0;          // R_ba R_aa^+
-    const double st = rbb - at * rba;                           // conditional, equilibrated
+    // R_aa = g^2; y = R_ba / g; At = y / g; St = R_bb - y^2 (eq. (innov_matrix) via the
+    // Cholesky factor of R_aa rather than its inverse)
+    const double gaa = (raa > kTau) ? sqrt(raa) : 0.0;
+    const double y = gaa > 0.0 ? rba / gaa : 0.0;
+    const double at = gaa > 0.0 ? y / gaa : 0.0;
+    const double st = rbb - y * y;
     const double e = st > kTau ? 1.0 / sqrt(st) : 0.0;
     const double q = e * st * e;
     const double bt = (e > 0.0 && q > kTau) ? sqrt(q) / e : 0.0;
@@ -108,31 +112,21 @@ __device__ void factors_m2(const double kaa[3], const double kbb[3], const doubl
     double g00, g10, g11;
     bool k0, k1;
     chol2(r00, r01, r11, g00, g10, g11, k0, k1);
-    // At = C R^+ on the kept pivots: for kept {0,1} the inverse of R = G G^T is
-    // (1/(g00^2 g11^2)) [[r11, -r01], [-r01, r00]]; one kept pivot conditions on it alone.
-    double t00, t01, t10, t11;
-    if (k0 && k1) {
-        const double det = (g00 * g00) * (g11 * g11);
-        const double i00 = r11 / det, i01 = -r01 / det, i11 = r00 / det;
-        t00 = c00 * i00 + c01 * i01;
-        t01 = c00 * i01 + c01 * i11;
-        t10 = c10 * i00 + c11 * i01;
-        t11 = c10 * i01 + c11 * i11;
-    } else if (k0) {
-        t00 = c00 / r00; t01 = 0.0;
-        t10 = c10 / r00; t11 = 0.0;
-    } else if (k1) {   // pivot 0 dropped: g10 = 0, so the pivot of index 1 is r11 itself
-        t00 = 0.0; t01 = c01 / r11;
-        t10 = 0.0; t11 = c11 / r11;
-    } else {
-        t00 = t01 = t10 = t11 = 0.0;
-    }
-    // St = S - At C^T, symmetrised
-    const double q00 = s00 - (t00 * c00 + t01 * c01);
-    const double q11 = s11 - (t10 * c10 + t11 * c11);
-    const double q01a = s01 - (t00 * c10 + t01 * c11);
-    const double q10a = s01 - (t10 * c00 + t11 * c01);
-    const double q01 = 0.5 * (q01a + q10a);
+    // With R = G G^T on the kept pivots: Y = C G^-T (row i solves G y = c_i), then
+    // At = Y G^-1 and St = S - Y Y^T (eqs. (trans_matrix), (innov_matrix)); rounding
+    // grows as eps / g11 rather than the eps / g11^2 of an explicit inverse.  A dropped
+    // pivot leaves its column of Y and At zero.
+    const double y00 = k0 ? c00 / g00 : 0.0;
+    const double y10 = k0 ? c10 / g00 : 0.0;
+    const double y01 = k1 ? (c01 - g10 * y00) / g11 : 0.0;
+    const double y11 = k1 ? (c11 - g10 * y10) / g11 : 0.0;
+    const double t01 = k1 ? y01 / g11 : 0.0;
+    const double t11 = k1 ? y11 / g11 : 0.0;
+    const double t00 = k0 ? (y00 - t01 * g10) / g00 : 0.0;
+    const double t10 = k0 ? (y10 - t11 * g10) / g00 : 0.0;
+    const double q00 = s00 - (y00 * y00 + y01 * y01);
+    const double q11 = s11 - (y10 * y10 + y11 * y11);
+    const double q01 = s01 - (y00 * y10 + y01 * y11);
     // its own equilibration, then the thresholded Cholesky
     const double e0 = q00 > kTau ? 1.0 / sqrt(q00) : 0.0;
     const double e1 = q11 > kTau ? 1.0 / sqrt(q11) : 0.0;

@@ -17,38 +17,47 @@ def rel_rms(x, ref):
     return float(np.sqrt(np.sum((x - ref) ** 2) / den)) if den > 0 else float(np.sqrt(np.sum(x * x)))
 
 
-def marginal_sd(A, B, n_theta):
-    """Marginal standard deviations (per state component) before and after each factor
-    set, from exact covariance propagation of the northern chain through (A, B); these
-    equal sqrt(diag J) at the rings (the chain reproduces J at each ring).
-    Returns sd_a, sd_b of shape [sets, modes, order]."""
+def chain_covariances(A, B, n_theta):
+    """Covariance of the state before (Sa) and after (Sb) each factor set, by exact
+    propagation of the northern chain through (A, B) from the start factor; the chain
+    reproduces J at each ring, so these are J(a,a) and J(b,b).  Shapes [sets, modes, M, M]."""
     ns, nm, M, _ = A.shape
     even = n_theta % 2 == 0
-    sig = {}
-    sd_a = np.zeros((ns, nm, M))
-    sd_b = np.zeros((ns, nm, M))
+    Sa = np.zeros((ns, nm, M, M))
+    Sb = np.zeros((ns, nm, M, M))
     S0 = np.einsum("mpk,mqk->mpq", B[0], B[0])
-    sd_a[0] = sd_b[0] = np.sqrt(np.maximum(np.einsum("mpp->mp", S0), 0))
+    Sa[0] = Sb[0] = S0
     prev = S0
     for j in range(1, ns):
-        Sa = S0 if (j == 1 or (even and j == 2)) else prev
-        Sb = np.einsum("mpk,mkl,mql->mpq", A[j], Sa, A[j]) + np.einsum("mpk,mqk->mpq", B[j], B[j])
-        sd_a[j] = np.sqrt(np.maximum(np.einsum("mpp->mp", Sa), 0))
-        sd_b[j] = np.sqrt(np.maximum(np.einsum("mpp->mp", Sb), 0))
+        Sa[j] = S0 if (j == 1 or (even and j == 2)) else prev
+        Sb[j] = np.einsum("mpk,mkl,mql->mpq", A[j], Sa[j], A[j]) + np.einsum("mpk,mqk->mpq", B[j], B[j])
         if not (even and j == 1):
-            prev = Sb
-    return sd_a, sd_b
+            prev = Sb[j]
+    return Sa, Sb
+
+
+def _sqrtm_psd(S):
+    w, V = np.linalg.eigh(S)
+    return np.einsum("...ij,...j,...kj->...ik", V, np.sqrt(np.clip(w, 0, None)), V)
 
 
 def factor_errors(Ag, Bg, Ao, Bo, n_theta):
-    """Errors of device factors against oracle factors in units of the marginal standard
-    deviations: |dA_pq| sd_a,q / sd_b,p and |dB_pq| / sd_b,p (rows with sd_b = 0 must be
-    zero on both sides).  Returns (max dA, max dB)."""
-    sd_a, sd_b = marginal_sd(Ao, Bo, n_theta)
+    """Errors of device factors against oracle factors, measured on what the factors do
+    to the chain's law rather than entry by entry (the entries of A are ill-determined
+    along near-null directions of J(a,a), and those of B = chol(S) when S is nearly
+    singular):
+      dA = max |(A_dev - A_orc) J(a,a)^{1/2}|_pq / sd_b,p   (conditional-mean map on a
+                                                             unit-variance input)
+      dS = max |B_dev B_dev^T - B_orc B_orc^T|_pq / (sd_b,p sd_b,q)   (conditional covariance)
+    with sd_b = sqrt(diag J(b,b)); rows with sd_b = 0 must be zero on both sides."""
+    Sa, Sb = chain_covariances(Ao, Bo, n_theta)
+    sd_b = np.sqrt(np.clip(np.einsum("...pp->...p", Sb), 0, None))
+    R = _sqrtm_psd(Sa)
+    eA = np.abs(np.einsum("...pk,...kq->...pq", Ag - Ao, R))
+    eS = np.abs(np.einsum("...pk,...qk->...pq", Bg, Bg) - np.einsum("...pk,...qk->...pq", Bo, Bo))
     live = sd_b > 0
     with np.errstate(divide="ignore", invalid="ignore"):
-        dA = np.abs(Ag - Ao) * sd_a[:, :, None, :] / sd_b[:, :, :, None]
-        dB = np.abs(Bg - Bo) / sd_b[:, :, :, None]
-    dA = np.where(live[..., None], dA, np.abs(Ag - Ao))
-    dB = np.where(live[..., None], dB, np.abs(Bg - Bo))
-    return float(np.nanmax(dA)), float(np.nanmax(dB))
+        dA = np.where(live[..., None], eA / sd_b[..., :, None], np.abs(Ag - Ao))
+        den = sd_b[..., :, None] * sd_b[..., None, :]
+        dS = np.where(den > 0, eS / den, eS)
+    return float(np.nanmax(dA)), float(np.nanmax(dS))

@@ -1,8 +1,11 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same
 Philox normals.  Bars: FP64 path <= 1e-10 relative RMS per field, FP32 path <= 1e-4;
-factors (FP64 setup) within 1e-10 (A) and 1e-8 (B) in units of the marginal standard
-deviations (B = chol(S) inherits eps/sqrt(S~) from the cancelling S = J(b,b) - A J(a,b),
-and the threshold keeps S~ above 1e-12)."""
+factors (FP64 setup) compared by their action on the chain's law (gpu_helpers.factor_errors):
+the conditional-mean map on a unit-variance input within 1e-8 and the conditional
+covariance within 1e-9, in units of the marginal standard deviations.  Both sides sum J
+with different FP64 roundings; the order-2 transition solves with J(a,a), whose smaller
+pivot 1 - rho^2 falls toward the 1e-12 threshold at evanescent modes, so its error grows
+as eps / sqrt(1 - rho^2)."""
 import numpy as np
 import pytest
 
@@ -55,7 +58,7 @@ def test_factors_match_oracle(case):
     assert Ag.shape == Ao.shape
     dA, dB = factor_errors(Ag, Bg, Ao, Bo, n)
     log(f"  max dA {dA:.3e}  max dB {dB:.3e}")
-    assert dA < 1e-10 and dB < 1e-8
+    assert dA < 1e-8 and dB < 1e-9
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -117,7 +120,7 @@ def test_plain_1024x2048_x16_full_size():
     Ao, Bo = oracle.setup(1, C, n, nphi)
     dA, dB = factor_errors(Ag, Bg, Ao, Bo, n)
     log(f"  factors dA {dA:.3e} dB {dB:.3e}")
-    assert dA < 1e-10 and dB < 1e-8
+    assert dA < 1e-8 and dB < 1e-9
     log("  oracle chains")
     go = oracle.sample_modes(1, n, Ao, Bo, 1, count)
     rings = [0, 1, 100, 400, 510, 511, 512, 513, 700, 1000, 1022, 1023]
@@ -165,7 +168,7 @@ def _full_size_precision_form(n, nphi, lmax, kap, count):
     Am, Bm = oracle.setup_modes(order, C, n, modes)
     dA, dB = factor_errors(Ag[:, modes], Bg[:, modes], Am, Bm, n)
     log(f"  factors dA {dA:.3e} dB {dB:.3e}")
-    assert dA < 1e-10 and dB < 1e-8
+    assert dA < 1e-8 and dB < 1e-9
     gm = oracle.sample_modes_list(order, n, modes, Am, Bm, 1, count)
     for f in range(count):
         eg = rel_rms(np.stack([g[f][:, modes].real, g[f][:, modes].imag]),
@@ -176,6 +179,10 @@ def _full_size_precision_form(n, nphi, lmax, kap, count):
 
 def test_precision_4096x8192_x8_full_size():
     _full_size_precision_form(4096, 8192, 4095, 2500.0, 8)
+
+
+def test_precision_8192x16384_x4_full_size():
+    _full_size_precision_form(8192, 16384, 8191, 10000.0, 4)
 
 
 def test_determinism_and_field_keying():
@@ -233,7 +240,8 @@ def test_explicit_spectrum_matches_rational_form():
     b = p2.sample(3, 2).cpu().numpy()
     p1.close()
     p2.close()
-    assert rel_rms(a, b) < 1e-14
+    # the two C_l differ in the last bit (product then reciprocal vs repeated division)
+    assert rel_rms(a, b) < 1e-10
 
 
 def test_empirical_covariance_of_gpu_samples():

@@ -41,14 +41,15 @@ __device__ __forceinline__ PhiloxBlock philox4x32_10(uint32_t c0, uint32_t c1, u
 template <typename T>
 struct BoxMuller;
 
+// FP64: accurate log, sqrt and sin/cos of 2 pi u (via sinpi/cospi of 2u).
 template <>
 struct BoxMuller<double> {
-    // (r cos, r sin) of the pair (x0, x1)
-    __device__ __forceinline__ static void pair(uint32_t x0, uint32_t x1, double& a, double& b)
+    // (sc r cos, sc r sin) of the pair (x0, x1)
+    __device__ __forceinline__ static void pair(uint32_t x0, uint32_t x1, double sc, double& a, double& b)
     {
         const double u0 = ((double)x0 + 0.5) * 0x1p-32;
         const double u1 = ((double)x1 + 0.5) * 0x1p-32;
-        const double r = sqrt(-2.0 * log(u0));
+        const double r = sc * sqrt(-2.0 * log(u0));
         double s, c;
         sincospi(2.0 * u1, &s, &c);
         a = r * c;
@@ -56,18 +57,18 @@ struct BoxMuller<double> {
     }
 };
 
+// FP32: the hardware transcendentals.  v_log_f32 is log2, so -2 ln u = -2 ln(2) log2 u;
+// v_sin_f32 / v_cos_f32 take their argument in turns, so sin(2 pi u) = v_sin_f32(u).
 template <>
 struct BoxMuller<float> {
-    __device__ __forceinline__ static void pair(uint32_t x0, uint32_t x1, float& a, float& b)
+    __device__ __forceinline__ static void pair(uint32_t x0, uint32_t x1, float sc, float& a, float& b)
     {
         // (x + 1/2) 2^-32 with one rounding of x to 24 bits: relative error ~2^-24
         const float u0 = fmaf((float)x0, 0x1p-32f, 0x1p-33f);
         const float u1 = fmaf((float)x1, 0x1p-32f, 0x1p-33f);
-        const float r = sqrtf(-2.0f * logf(u0));
-        float s, c;
-        sincospif(2.0f * u1, &s, &c);
-        a = r * c;
-        b = r * s;
+        const float r = sc * __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u0));
+        a = r * __builtin_amdgcn_cosf(u1);
+        b = r * __builtin_amdgcn_sinf(u1);
     }
 };
 

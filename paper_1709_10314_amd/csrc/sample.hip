@@ -14,161 +14,160 @@ template <> struct Vec2<double> { using type = double2; };
 // ------------------------------------------------------------------ recursion
 struct RecArgs {
     int n_theta, n_phi, m_top, m_rows, n_sets, s, even;
-    int lanes_fh;      // lanes per (field, hemisphere): 2 * round_up(m_rows, 32)
-    int count;
+    int n_fh;          // 2 * count chains families (field, hemisphere)
+    int n_fg;          // workgroups per m-tile: ceil(n_fh / 4)
+    int n_wg;          // n_mtiles * n_fg real workgroups
+    int per_xcd;       // launched workgroups / 8
     uint32_t seed_lo, seed_hi;
 };
 
-// Normals of one chain, cached per Philox block; the chain visits rings monotonically
-// (after the start/crossing), so each block is generated once.
-template <typename T, int M>
-struct NoiseStream {
-    uint32_t k0, k1, m, part;
-    int blk;
-    T n[4];
-
-    __device__ void init(uint64_t key, int m_, int part_)
-    {
-        k0 = (uint32_t)key;
-        k1 = (uint32_t)(key >> 32);
-        m = (uint32_t)m_;
-        part = (uint32_t)part_;
-        blk = -1;
-    }
-    __device__ __forceinline__ void fetch(int b)
-    {
-        const PhiloxBlock w = philox4x32_10((uint32_t)b, m, part, 0u, k0, k1);
-        BoxMuller<T>::pair(w.w[0], w.w[1], n[0], n[1]);
-        BoxMuller<T>::pair(w.w[2], w.w[3], n[2], n[3]);
-        blk = b;
-    }
-    // xi_q of ring r
-    __device__ __forceinline__ T get(int r, int q)
-    {
-        const int idx = r * M + q;
-        const int b = idx >> 2;
-        if (b != blk) fetch(b);
-        const int w = idx & 3;
-        return w == 0 ? n[0] : (w == 1 ? n[1] : (w == 2 ? n[2] : n[3]));
-    }
-};
-
-template <typename T, int M>
-struct Factors {
-    T a00, a01, a10, a11, b00, b10, b11;
-};
-
-template <typename T, int M>
-__device__ __forceinline__ Factors<T, M> load_factors(const T* __restrict__ fac, size_t rec)
+// Four normals of one Philox block (counter (blk, m, part, 0)), each scaled by sc
+// (1 for m = 0, 1/sqrt(2) for the Re/Im parts of m > 0).
+template <typename T>
+__device__ __forceinline__ void block_normals(uint32_t blk, uint32_t m, uint32_t part, uint32_t k0,
+                                              uint32_t k1, T sc, T n[4])
 {
-    Factors<T, M> F;
-    if (M == 1) {
-        using V2 = typename Vec2<T>::type;
-        const V2 v = *reinterpret_cast<const V2*>(fac + rec * 2);
-        F.a00 = v.x; F.b00 = v.y;
-        F.a01 = F.a10 = F.a11 = F.b10 = F.b11 = T(0);
-    } else {
-        const T* p = fac + rec * 8;
-        F.a00 = p[0]; F.a01 = p[1]; F.a10 = p[2]; F.a11 = p[3];
-        F.b00 = p[4]; F.b10 = p[5]; F.b11 = p[6];
-    }
-    return F;
+    const PhiloxBlock w = philox4x32_10(blk, m, part, 0u, k0, k1);
+    BoxMuller<T>::pair(w.w[0], w.w[1], sc, n[0], n[1]);
+    BoxMuller<T>::pair(w.w[2], w.w[3], sc, n[2], n[3]);
 }
 
-// One lane per chain (field f, hemisphere h, mode m, part Re/Im).  A wave covers 32 modes
-// x 2 parts of one (f, h), so control flow and ring order are wave-uniform.  The northern
-// chain draws the start state at ring s and steps to ring 0; the southern chain redraws
-// the same start state (same counters), takes the crossing step (even n_theta) and steps
-// to ring n_theta-1 with the mirrored factors, carried as y = D x so that the stored
-// northern A, B apply unchanged with D xi as the noise.
+// One state-space step x <- A x + B w (eq. (state_space)) with the record of set j.
+// `flip` applies the mirror (noise D w for the southern chain carried as y = D x).
+template <typename T, int M>
+__device__ __forceinline__ void chain_step(const T* __restrict__ rec, T& x0, T& x1, T w0, T w1)
+{
+    if (M == 1) {
+        using V2 = typename Vec2<T>::type;
+        const V2 v = *reinterpret_cast<const V2*>(rec);
+        x0 = v.x * x0 + v.y * w0;
+    } else {
+        const T a00 = rec[0], a01 = rec[1], a10 = rec[2], a11 = rec[3];
+        const T b00 = rec[4], b10 = rec[5], b11 = rec[6];
+        const T y0 = a00 * x0 + a01 * x1 + b00 * w0;
+        const T y1 = a10 * x0 + a11 * x1 + (b10 * w0 + b11 * w1);
+        x0 = y0;
+        x1 = y1;
+    }
+}
+
+// One lane per chain (field f, hemisphere h, mode m, part Re/Im).  A wave holds 32 modes x
+// 2 parts of one (f, h), so f and h are wave-uniform (scalar registers) and so are the
+// Philox key and the ring order; a workgroup holds four (f, h) families of the same 32
+// modes, which read the same factor records.  Workgroups are numbered so that every
+// workgroup of an m-tile lands on the same XCD (workgroup b runs on XCD b mod 8): each XCD
+// streams its own slice of the factors through its own L2.
+//
+// The northern chain draws the start state at ring s and steps to ring 0; the southern
+// chain redraws the same start state (same counters), takes the crossing step (even
+// n_theta) and steps to ring n_theta-1 with the mirrored factors, carried as y = D x so
+// that the stored northern records apply unchanged with D w as the noise.  Rings are
+// walked in groups of 4/M that share one Philox block, so each normal is picked by a
+// compile-time word index.
 template <typename T, int M>
 __global__ __launch_bounds__(256) void recursion_kernel(RecArgs a, const T* __restrict__ fac,
                                                         T* __restrict__ out)
 {
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    const int fh = idx / a.lanes_fh;
-    if (fh >= 2 * a.count) return;
+    constexpr int G = 4 / M;   // rings per Philox block
+    const int b = blockIdx.x;
+    const int L = (b & 7) * a.per_xcd + (b >> 3);
+    if (L >= a.n_wg) return;
+    const int mt = L / a.n_fg;
+    const int fg = L - mt * a.n_fg;
+    const int fh = __builtin_amdgcn_readfirstlane(fg * 4 + (int)(threadIdx.x >> 6));
+    if (fh >= a.n_fh) return;
     const int f = fh >> 1, h = fh & 1;
-    const int rem = idx - fh * a.lanes_fh;
-    const int m = rem >> 1, part = rem & 1;
+    const int lane = threadIdx.x & 63;
+    const int m = mt * 32 + (lane >> 1), part = lane & 1;
     if (m >= a.m_rows) return;
     T* __restrict__ g = out + (size_t)f * a.n_theta * a.n_phi + 2 * m + part;
-    const int r_lo = h ? a.s + 1 : 0;
-    const int r_hi = h ? a.n_theta : a.s + 1;
+    const int n = a.n_theta, s = a.s;
     if (m > a.m_top || (m == 0 && part == 1)) {
+        const int r_lo = h ? s + 1 : 0, r_hi = h ? n : s + 1;
         for (int r = r_lo; r < r_hi; ++r) g[(size_t)r * a.n_phi] = T(0);
         return;
     }
     const uint64_t key = (((uint64_t)a.seed_hi << 32) | a.seed_lo) + (uint64_t)f;
-    NoiseStream<T, M> ns;
-    ns.init(key, m, part);
+    const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
     const T sc = (m == 0) ? T(1) : T(0.70710678118654752440);
+    const T* __restrict__ fm = fac + (size_t)m * factor_stride(M);
+    const size_t set_stride = (size_t)a.m_rows * factor_stride(M);
 
-    // start, eq. (state_initial)
-    const Factors<T, M> F0 = load_factors<T, M>(fac, (size_t)m);
+    // start, eq. (state_initial), at ring s
+    T nz[4];
     T x0, x1 = T(0);
     {
-        const T w0 = ns.get(a.s, 0);
+        block_normals<T>((uint32_t)((s * M) >> 2), (uint32_t)m, (uint32_t)part, k0, k1, sc, nz);
+        const int w = (s * M) & 3;
+        const T w0 = w == 0 ? nz[0] : (w == 1 ? nz[1] : (w == 2 ? nz[2] : nz[3]));
         if (M == 1) {
-            x0 = sc * F0.b00 * w0;
+            x0 = fm[1] * w0;
         } else {
-            const T w1 = ns.get(a.s, 1);
-            x0 = sc * (F0.b00 * w0);
-            x1 = sc * (F0.b10 * w0 + F0.b11 * w1);
+            const T w1 = w == 0 ? nz[1] : nz[3];
+            x0 = fm[4] * w0;
+            x1 = fm[5] * w0 + fm[6] * w1;
         }
     }
-    const size_t mr = (size_t)a.m_rows;
-    int j0 = 1;
     if (h == 0) {
-        g[(size_t)a.s * a.n_phi] = x0;
-        if (a.even) j0 = 2;
-        for (int j = j0; j < a.n_sets; ++j) {
-            const int r = a.even ? a.s - j + 1 : a.s - j;
-            const Factors<T, M> F = load_factors<T, M>(fac, (size_t)j * mr + m);
-            const T w0 = ns.get(r, 0);
-            T y0, y1 = T(0);
-            if (M == 1) {
-                y0 = F.a00 * x0 + sc * F.b00 * w0;
-            } else {
-                const T w1 = ns.get(r, 1);
-                y0 = F.a00 * x0 + F.a01 * x1 + sc * (F.b00 * w0);
-                y1 = F.a10 * x0 + F.a11 * x1 + sc * (F.b10 * w0 + F.b11 * w1);
+        g[(size_t)s * a.n_phi] = x0;
+        // north: rings s-1 .. 0; ring r uses set j = s - r + even
+        int r_hi = s - 1;
+        while (r_hi >= 0) {
+            const int base = (r_hi / G) * G;
+            T nb[4];
+            block_normals<T>((uint32_t)((base * M) >> 2), (uint32_t)m, (uint32_t)part, k0, k1, sc, nb);
+#pragma unroll
+            for (int t = G - 1; t >= 0; --t) {
+                const int r = base + t;
+                if (r <= r_hi) {
+                    const int j = s - r + a.even;
+                    const T w0 = nb[t * M];
+                    const T w1 = M == 2 ? nb[t * M + 1] : T(0);
+                    chain_step<T, M>(fm + (size_t)j * set_stride, x0, x1, w0, w1);
+                    g[(size_t)r * a.n_phi] = x0;
+                }
             }
-            x0 = y0; x1 = y1;
-            g[(size_t)r * a.n_phi] = x0;
+            r_hi = base - 1;
         }
     } else {
+        int r_lo = s + 1;
         if (a.even) {
-            const int r = a.s + 1;
-            const Factors<T, M> F = load_factors<T, M>(fac, mr + m);
-            const T w0 = ns.get(r, 0);
-            T y0, y1 = T(0);
-            if (M == 1) {
-                y0 = F.a00 * x0 + sc * F.b00 * w0;
+            // crossing s -> s+1 with set 1, in the true coordinates
+            const int r = s + 1;
+            T w0, w1 = T(0);
+            if (((r * M) >> 2) == ((s * M) >> 2)) {
+                const int w = (r * M) & 3;
+                w0 = w == 0 ? nz[0] : (w == 1 ? nz[1] : (w == 2 ? nz[2] : nz[3]));
+                if (M == 2) w1 = w == 0 ? nz[1] : nz[3];
             } else {
-                const T w1 = ns.get(r, 1);
-                y0 = F.a00 * x0 + F.a01 * x1 + sc * (F.b00 * w0);
-                y1 = F.a10 * x0 + F.a11 * x1 + sc * (F.b10 * w0 + F.b11 * w1);
+                T nc[4];
+                block_normals<T>((uint32_t)((r * M) >> 2), (uint32_t)m, (uint32_t)part, k0, k1, sc, nc);
+                const int w = (r * M) & 3;
+                w0 = w == 0 ? nc[0] : (w == 1 ? nc[1] : (w == 2 ? nc[2] : nc[3]));
+                if (M == 2) w1 = w == 0 ? nc[1] : nc[3];
             }
-            x0 = y0; x1 = y1;
+            chain_step<T, M>(fm + set_stride, x0, x1, w0, w1);
             g[(size_t)r * a.n_phi] = x0;
-            j0 = 2;
+            r_lo = s + 2;
         }
         x1 = -x1;   // y = D x
-        for (int j = j0; j < a.n_sets; ++j) {
-            const int r = a.s + j;
-            const Factors<T, M> F = load_factors<T, M>(fac, (size_t)j * mr + m);
-            const T w0 = ns.get(r, 0);
-            T y0, y1 = T(0);
-            if (M == 1) {
-                y0 = F.a00 * x0 + sc * F.b00 * w0;
-            } else {
-                const T w1 = -ns.get(r, 1);   // D xi
-                y0 = F.a00 * x0 + F.a01 * x1 + sc * (F.b00 * w0);
-                y1 = F.a10 * x0 + F.a11 * x1 + sc * (F.b10 * w0 + F.b11 * w1);
+        // south: rings r_lo .. n-1; ring r uses set j = r - s with noise D w
+        while (r_lo < n) {
+            const int base = (r_lo / G) * G;
+            T nb[4];
+            block_normals<T>((uint32_t)((base * M) >> 2), (uint32_t)m, (uint32_t)part, k0, k1, sc, nb);
+#pragma unroll
+            for (int t = 0; t < G; ++t) {
+                const int r = base + t;
+                if (r >= r_lo && r < n) {
+                    const int j = r - s;
+                    const T w0 = nb[t * M];
+                    const T w1 = M == 2 ? -nb[t * M + 1] : T(0);
+                    chain_step<T, M>(fm + (size_t)j * set_stride, x0, x1, w0, w1);
+                    g[(size_t)r * a.n_phi] = x0;
+                }
             }
-            x0 = y0; x1 = y1;
-            g[(size_t)r * a.n_phi] = x0;
+            r_lo = base + G;
         }
     }
 }
@@ -392,12 +391,14 @@ hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, uint64
     a.n_sets = g.n_sets;
     a.s = g.s;
     a.even = g.even;
-    a.lanes_fh = 2 * ((g.m_rows + 31) / 32 * 32);
-    a.count = count;
+    a.n_fh = 2 * count;
+    a.n_fg = (a.n_fh + 3) / 4;
+    const int n_mt = (g.m_rows + 31) / 32;
+    a.n_wg = n_mt * a.n_fg;
+    a.per_xcd = (a.n_wg + 7) / 8;
     a.seed_lo = (uint32_t)seed;
     a.seed_hi = (uint32_t)(seed >> 32);
-    const long long lanes = (long long)a.lanes_fh * 2 * count;
-    const dim3 grid((unsigned)((lanes + 255) / 256));
+    const dim3 grid((unsigned)(a.per_xcd * 8));
     if (fp64) {
         if (g.order == 1)
             hipLaunchKernelGGL((recursion_kernel<double, 1>), grid, dim3(256), 0, st, a,

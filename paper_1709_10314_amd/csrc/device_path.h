@@ -1,0 +1,322 @@
+// Device bodies of the sampling path, shared by the per-plan kernels (sample.hip) and the
+// persistent batch kernel (batch.hip):
+//   run_chain  -- one (field, hemisphere, mode, part) chain of the latitude-ring recursion
+//                 with fused Philox normals (Creasey & Lang, Alg. 2; eqs. (state_initial),
+//                 (state_space); the mirror remark after Alg. 1)
+//   c2r_row    -- the complex-to-real inverse FFT of one ring, in place (Alg. 2, last step)
+#pragma once
+
+#include "rng.h"
+#include "smf_internal.h"
+
+namespace smf {
+
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+// ------------------------------------------------------------------ recursion
+
+// Four normals of one Philox block (counter (blk, m, part, 0)), each scaled by sc
+// (1 for m = 0, 1/sqrt(2) for the Re/Im parts of m > 0).
+template <typename T>
+__device__ __forceinline__ void block_normals(uint32_t blk, uint32_t m, uint32_t part, uint32_t k0,
+                                              uint32_t k1, T sc, T n[4])
+{
+    const PhiloxBlock w = philox4x32_10(blk, m, part, 0u, k0, k1);
+    BoxMuller<T>::pair(w.w[0], w.w[1], sc, n[0], n[1]);
+    BoxMuller<T>::pair(w.w[2], w.w[3], sc, n[2], n[3]);
+}
+
+// One state-space step x <- A x + B w (eq. (state_space)) with the factor record `rec`.
+template <typename T, int M>
+__device__ __forceinline__ void chain_step(const T* __restrict__ rec, T& x0, T& x1, T w0, T w1)
+{
+    if (M == 1) {
+        using V2 = typename Vec2<T>::type;
+        const V2 v = *reinterpret_cast<const V2*>(rec);
+        x0 = v.x * x0 + v.y * w0;
+    } else {
+        const T a00 = rec[0], a01 = rec[1], a10 = rec[2], a11 = rec[3];
+        const T b00 = rec[4], b10 = rec[5], b11 = rec[6];
+        const T y0 = a00 * x0 + a01 * x1 + b00 * w0;
+        const T y1 = a10 * x0 + a11 * x1 + (b10 * w0 + b11 * w1);
+        x0 = y0;
+        x1 = y1;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T pick4(const T n[4], int w)
+{
+    return w == 0 ? n[0] : (w == 1 ? n[1] : (w == 2 ? n[2] : n[3]));
+}
+
+// One chain.  `fm` points at the mode's record in factor set 0 (sets `set_stride` apart);
+// `g` at the chain's slot of ring 0 of its field (rings `row` elements apart).
+// The northern chain (h = 0) draws the start state at ring s and steps to ring 0; the
+// southern chain (h = 1) redraws the same start state (same counters), takes the crossing
+// step (even n_theta) and steps to ring n-1 with the mirrored factors, carried as
+// y = D x so that the stored northern records apply unchanged with D w as the noise.
+// Rings are walked in groups of 4/M that share one Philox block, so each normal is
+// picked by a compile-time word index.  The ring order is uniform across the wave.
+template <typename T, int M>
+__device__ __forceinline__ void run_chain(int n, int s, int even, int h, int m, int part,
+                                          uint32_t k0, uint32_t k1, const T* __restrict__ fm,
+                                          size_t set_stride, T* __restrict__ g, size_t row)
+{
+    constexpr int G = 4 / M;   // rings per Philox block
+    const T sc = (m == 0) ? T(1) : T(0.70710678118654752440);
+    const uint32_t um = (uint32_t)m, up = (uint32_t)part;
+
+    // start, eq. (state_initial), at ring s
+    T nz[4];
+    T x0, x1 = T(0);
+    {
+        block_normals<T>((uint32_t)((s * M) >> 2), um, up, k0, k1, sc, nz);
+        const int w = (s * M) & 3;
+        const T w0 = pick4(nz, w);
+        if (M == 1) {
+            x0 = fm[1] * w0;
+        } else {
+            const T w1 = w == 0 ? nz[1] : nz[3];
+            x0 = fm[4] * w0;
+            x1 = fm[5] * w0 + fm[6] * w1;
+        }
+    }
+    if (h == 0) {
+        g[(size_t)s * row] = x0;
+        // north: rings s-1 .. 0; ring r uses set j = s - r + even
+        int r_hi = s - 1;
+        while (r_hi >= 0) {
+            const int base = (r_hi / G) * G;
+            T nb[4];
+            block_normals<T>((uint32_t)((base * M) >> 2), um, up, k0, k1, sc, nb);
+#pragma unroll
+            for (int t = G - 1; t >= 0; --t) {
+                const int r = base + t;
+                if (r <= r_hi) {
+                    const int j = s - r + even;
+                    const T w0 = nb[t * M];
+                    const T w1 = M == 2 ? nb[t * M + 1] : T(0);
+                    chain_step<T, M>(fm + (size_t)j * set_stride, x0, x1, w0, w1);
+                    g[(size_t)r * row] = x0;
+                }
+            }
+            r_hi = base - 1;
+        }
+    } else {
+        int r_lo = s + 1;
+        if (even) {
+            // crossing s -> s+1 with set 1, in the true coordinates
+            const int r = s + 1;
+            const int w = (r * M) & 3;
+            T w0, w1 = T(0);
+            if (((r * M) >> 2) == ((s * M) >> 2)) {
+                w0 = pick4(nz, w);
+                if (M == 2) w1 = w == 0 ? nz[1] : nz[3];
+            } else {
+                T nc[4];
+                block_normals<T>((uint32_t)((r * M) >> 2), um, up, k0, k1, sc, nc);
+                w0 = pick4(nc, w);
+                if (M == 2) w1 = w == 0 ? nc[1] : nc[3];
+            }
+            chain_step<T, M>(fm + set_stride, x0, x1, w0, w1);
+            g[(size_t)r * row] = x0;
+            r_lo = s + 2;
+        }
+        x1 = -x1;   // y = D x
+        // south: rings r_lo .. n-1; ring r uses set j = r - s with noise D w
+        while (r_lo < n) {
+            const int base = (r_lo / G) * G;
+            T nb[4];
+            block_normals<T>((uint32_t)((base * M) >> 2), um, up, k0, k1, sc, nb);
+#pragma unroll
+            for (int t = 0; t < G; ++t) {
+                const int r = base + t;
+                if (r >= r_lo && r < n) {
+                    const int j = r - s;
+                    const T w0 = nb[t * M];
+                    const T w1 = M == 2 ? -nb[t * M + 1] : T(0);
+                    chain_step<T, M>(fm + (size_t)j * set_stride, x0, x1, w0, w1);
+                    g[(size_t)r * row] = x0;
+                }
+            }
+            r_lo = base + G;
+        }
+    }
+}
+
+// Zero the slots of modes above m_top (and the imaginary part of g_0) in one hemisphere.
+template <typename T>
+__device__ __forceinline__ void zero_chain(int n, int s, int h, T* __restrict__ g, size_t row)
+{
+    const int r_lo = h ? s + 1 : 0, r_hi = h ? n : s + 1;
+    for (int r = r_lo; r < r_hi; ++r) g[(size_t)r * row] = T(0);
+}
+
+// ------------------------------------------------------------------ C2R FFT
+// Per ring: X_m = g_m (m <= m_top, else 0; X_{N-m} = conj X_m), N = n_phi, H = N/2.
+//   T_j = sum_m X_m e^{2 pi i m j / N}
+// via one complex inverse FFT of length H: with w = e^{2 pi i / N},
+//   Z_k = (X_k + conj X_{H-k}) + i w^k (X_k - conj X_{H-k}),  k < H  (X_H = 0),
+//   z_j = sum_k Z_k e^{2 pi i k j / H},   T_{2j} = Re z_j,  T_{2j+1} = Im z_j.
+// The ring is read from and written back to the same memory (the modes were stored in
+// place by the recursion), staged through LDS; Stockham radix-8/4/2 passes, each pass
+// reading all its inputs before a barrier and writing after it.
+
+template <typename T>
+struct Cx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> csub(Cx<T> a, Cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> mul_i(Cx<T> a) { return {-a.im, a.re}; }   // i a
+
+// In-register inverse DFT of size R (kernel e^{+2 pi i r q / R}).
+template <typename T, int R>
+__device__ __forceinline__ void dft_inv(Cx<T>* v)
+{
+    if (R == 2) {
+        const Cx<T> a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if (R == 4) {
+        const Cx<T> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+        const Cx<T> s13 = cadd(v[1], v[3]), d13 = mul_i(csub(v[1], v[3]));
+        v[0] = cadd(s02, s13);
+        v[2] = csub(s02, s13);
+        v[1] = cadd(d02, d13);
+        v[3] = csub(d02, d13);
+    } else {   // R == 8: radix-2 over two size-4 DFTs of the even and odd samples
+        Cx<T> e[4] = {v[0], v[2], v[4], v[6]};
+        Cx<T> o[4] = {v[1], v[3], v[5], v[7]};
+        dft_inv<T, 4>(e);
+        dft_inv<T, 4>(o);
+        const T h = T(0.70710678118654752440);
+        const Cx<T> o1 = {h * (o[1].re - o[1].im), h * (o[1].re + o[1].im)};   // (1+i)/sqrt2
+        const Cx<T> o2 = mul_i(o[2]);                                            // i
+        const Cx<T> o3 = {-h * (o[3].re + o[3].im), h * (o[3].re - o[3].im)};   // (-1+i)/sqrt2
+        v[0] = cadd(e[0], o[0]); v[4] = csub(e[0], o[0]);
+        v[1] = cadd(e[1], o1);   v[5] = csub(e[1], o1);
+        v[2] = cadd(e[2], o2);   v[6] = csub(e[2], o2);
+        v[3] = cadd(e[3], o3);   v[7] = csub(e[3], o3);
+    }
+}
+
+// One Stockham pass of radix R over H points held in LDS buffer `buf`, current
+// sub-transform length Ns = 2^LOG2NS.  Butterfly b: k = b mod Ns; inputs buf[b + r H/R]
+// times e^{2 pi i k r / (Ns R)}; outputs to ((b / Ns) Ns R + k) + q Ns.  Twiddles come
+// from the table tw[t] = e^{2 pi i t / N}, N = 2H.
+template <typename T, int LOG2H, int R, int NT, int LOG2NS>
+__device__ __forceinline__ void stockham_pass(Cx<T>* buf, const Cx<T>* __restrict__ tw)
+{
+    constexpr int Ns = 1 << LOG2NS;
+    constexpr int H = 1 << LOG2H;
+    constexpr int NB = H / R;
+    constexpr int PER = (NB + NT - 1) / NT;
+    Cx<T> v[PER][R];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int b = tid + i * NT;
+        if (NB % NT == 0 || b < NB) {
+            const int k = b & (Ns - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = buf[b + r * NB];
+            if (Ns > 1) {
+                // twiddle exponent k r / (Ns R) of a full turn = (k r N / (Ns R)) / N
+                constexpr int shift = (LOG2H + 1) - (LOG2NS + (R == 8 ? 3 : (R == 4 ? 2 : 1)));
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[(k * r) << shift]);
+            }
+            dft_inv<T, R>(v[i]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int b = tid + i * NT;
+        if (NB % NT == 0 || b < NB) {
+            const int k = b & (Ns - 1);
+            const int o = (b - k) * R + k;
+#pragma unroll
+            for (int q = 0; q < R; ++q) buf[o + q * Ns] = v[i][q];
+        }
+    }
+    __syncthreads();
+}
+
+// Radix 8 while at least 3 bits remain, then one radix-4 or radix-2 pass.
+template <typename T, int LOG2H, int NT, int DONE>
+__device__ __forceinline__ void run_passes(Cx<T>* buf, const Cx<T>* __restrict__ tw)
+{
+    constexpr int REM = LOG2H - DONE;
+    if constexpr (REM >= 3) {
+        stockham_pass<T, LOG2H, 8, NT, DONE>(buf, tw);
+        run_passes<T, LOG2H, NT, DONE + 3>(buf, tw);
+    } else if constexpr (REM == 2) {
+        stockham_pass<T, LOG2H, 4, NT, DONE>(buf, tw);
+    } else if constexpr (REM == 1) {
+        stockham_pass<T, LOG2H, 2, NT, DONE>(buf, tw);
+    }
+}
+
+// C2R of one ring row (2H reals, holding modes 0..H-1 as complex on entry), by NT threads
+// with an LDS buffer of H complex values.  Ends with the row written; the caller must
+// barrier before reusing `buf`.
+template <typename T, int LOG2H, int NT>
+__device__ __forceinline__ void c2r_row(T* __restrict__ data_row, const T* __restrict__ twr, int m_top,
+                                        Cx<T>* buf)
+{
+    constexpr int H = 1 << LOG2H;
+    const Cx<T>* tw = reinterpret_cast<const Cx<T>*>(twr);
+    Cx<T>* __restrict__ row = reinterpret_cast<Cx<T>*>(data_row);
+    const int tid = threadIdx.x;
+
+    // pre-processing: Z_k from X_k and conj X_{H-k}
+    constexpr int PER = (H + NT - 1) / NT;
+    Cx<T> z[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int k = tid + i * NT;
+        if (H % NT == 0 || k < H) {
+            const Cx<T> zero = {T(0), T(0)};
+            const Cx<T> xk = (k <= m_top) ? row[k] : zero;
+            Cx<T> xm = zero;
+            if (k > 0 && H - k <= m_top) {
+                const Cx<T> t = row[H - k];
+                xm = {t.re, -t.im};
+            }
+            const Cx<T> s = cadd(xk, xm);
+            const Cx<T> d = cmul(tw[k], csub(xk, xm));
+            z[i] = cadd(s, mul_i(d));
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int k = tid + i * NT;
+        if (H % NT == 0 || k < H) buf[k] = z[i];
+    }
+    __syncthreads();
+
+    run_passes<T, LOG2H, NT, 0>(buf, tw);
+
+    // T_{2j} + i T_{2j+1} = z_j: the complex result written as interleaved reals
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int k = tid + i * NT;
+        if (H % NT == 0 || k < H) row[k] = buf[k];
+    }
+}
+
+}  // namespace smf

@@ -2,9 +2,31 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <vector>
+
+#include "batch.h"
 #include "smf_internal.h"
 
 using smf::Geometry;
+
+namespace smf {
+// Host state of a batch plan: one FP32 sub-plan per field plus the device work list.
+struct BatchState {
+    int n = 0;
+    std::vector<smf_plan*> sub;
+    std::vector<int64_t> offsets;   // n + 1 packed-output offsets (elements)
+    BatchField* fields_dev = nullptr;
+    uint32_t* items_dev = nullptr;
+    int* counters_dev = nullptr;
+    int n_rec = 0, n_items = 0;
+    size_t lds = 0;
+    int grid = 0;
+    int max_per_cu = 1;
+    int n_cu = 1;
+    int spin_limit = 1 << 22;
+};
+}  // namespace smf
 
 namespace {
 
@@ -144,7 +166,7 @@ int smf_setup(const smf_spectrum* spec, int n_theta, int n_phi, int flags, void*
 static int sample_common(const smf_plan* plan, uint64_t seed, int count, void* out_dev,
                          void* hip_stream, bool fft)
 {
-    if (!plan || count < 0) return SMF_EINVAL;
+    if (!plan || plan->batch || count < 0) return SMF_EINVAL;
     if (count == 0) return SMF_OK;
     if (!out_dev) return SMF_EINVAL;
     DeviceGuard dg(plan->device);
@@ -172,7 +194,7 @@ int smf_sample_modes(const smf_plan* plan, uint64_t seed, int count, void* g_dev
 
 int smf_plan_dims(const smf_plan* plan, int* dims)
 {
-    if (!plan || !dims) return SMF_EINVAL;
+    if (!plan || plan->batch || !dims) return SMF_EINVAL;
     const Geometry& g = plan->g;
     dims[0] = g.order;
     dims[1] = g.n_theta;
@@ -187,7 +209,7 @@ int smf_plan_dims(const smf_plan* plan, int* dims)
 
 int smf_get_factors(const smf_plan* plan, double* A_host, double* B_host)
 {
-    if (!plan || !A_host || !B_host) return SMF_EINVAL;
+    if (!plan || plan->batch || !A_host || !B_host) return SMF_EINVAL;
     DeviceGuard dg(plan->device);
     const Geometry& g = plan->g;
     const int M = g.order, E = smf::factor_stride(M);
@@ -220,6 +242,16 @@ int smf_destroy(smf_plan* plan)
     if (!plan) return SMF_OK;
     DeviceGuard dg(plan->device);
     (void)hipDeviceSynchronize();
+    if (plan->batch) {
+        smf::BatchState* b = plan->batch;
+        for (smf_plan* p : b->sub) smf_destroy(p);
+        (void)hipFree(b->fields_dev);
+        (void)hipFree(b->items_dev);
+        (void)hipFree(b->counters_dev);
+        delete b;
+        free(plan);
+        return SMF_OK;
+    }
     (void)hipFree(plan->C);
     (void)hipFree(plan->f64);
     if (plan->f32) (void)hipFree(plan->f32);
@@ -237,8 +269,181 @@ const char* smf_error_string(int code)
         case SMF_ENOMEM: return "device memory allocation failed";
         case SMF_EHIP: return "HIP runtime error";
         case SMF_ENUMERIC: return "spectrum has a C_l that is not finite and positive";
+        case SMF_EWAIT: return "a batch FFT item gave up waiting for its field's chains";
         default: return "unknown error code";
     }
+}
+
+
+int smf_setup_batch(int n, const smf_spectrum* specs, const int* n_theta, const int* n_phi, int flags,
+                    void* hip_stream, smf_plan** out)
+{
+    if (!out) return SMF_EINVAL;
+    *out = nullptr;
+    if (n < 1 || n > 65535 || !specs || !n_theta || !n_phi || flags != SMF_FP32) return SMF_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (n_phi[i] > 4096 || n_theta[i] > 65535) return SMF_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    smf::BatchState* b = new smf::BatchState();
+    b->n = n;
+    b->offsets.assign(n + 1, 0);
+    int rc = SMF_OK;
+    std::vector<smf::BatchField> fields(n);
+    std::vector<int> order_idx(n);
+    std::vector<uint32_t> items;
+    smf_plan* plan = nullptr;
+    int dev = 0, blocks = 0;
+    for (int i = 0; i < n; ++i) {
+        smf_plan* p = nullptr;
+        rc = setup_impl(&specs[i], n_theta[i], n_phi[i], SMF_FP32, st, &p);
+        if (rc != SMF_OK) goto fail;
+        b->sub.push_back(p);
+        b->offsets[i + 1] = b->offsets[i] + (int64_t)n_theta[i] * n_phi[i];
+        const Geometry& g = p->g;
+        smf::BatchField& F = fields[i];
+        F.fac = p->f32;
+        F.tw = p->tw32;
+        F.out_off = b->offsets[i];
+        F.n_theta = g.n_theta;
+        F.n_phi = g.n_phi;
+        F.order = g.order;
+        F.m_top = g.m_top;
+        F.m_rows = g.m_rows;
+        F.s = g.s;
+        F.even = g.even;
+        F.log2h = __builtin_ctz((unsigned)g.n_phi) - 1;
+        F.n_rec_items = ((g.m_rows + 31) / 32 + 1) / 2;
+        F.seed_off = i;
+        b->lds = std::max(b->lds, sizeof(float) * 2 * (size_t)(g.n_phi / 2));
+    }
+    // longest chains first; FFT items follow in the same field order
+    for (int i = 0; i < n; ++i) order_idx[i] = i;
+    std::stable_sort(order_idx.begin(), order_idx.end(),
+                     [&](int x, int y) { return fields[x].n_theta > fields[y].n_theta; });
+    for (int i : order_idx)
+        for (int t = 0; t < fields[i].n_rec_items; ++t) items.push_back(((uint32_t)i << 16) | (uint32_t)t);
+    b->n_rec = (int)items.size();
+    for (int i : order_idx)
+        for (int r = 0; r < fields[i].n_theta; ++r) items.push_back(((uint32_t)i << 16) | (uint32_t)r);
+    b->n_items = (int)items.size();
+    if (hipMalloc(&b->fields_dev, sizeof(smf::BatchField) * n) != hipSuccess ||
+        hipMalloc(&b->items_dev, sizeof(uint32_t) * items.size()) != hipSuccess ||
+        hipMalloc(&b->counters_dev, sizeof(int) * (n + 2)) != hipSuccess) {
+        (void)hipGetLastError();
+        rc = SMF_ENOMEM;
+        goto fail;
+    }
+    if (hipMemcpy(b->fields_dev, fields.data(), sizeof(smf::BatchField) * n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->items_dev, items.data(), sizeof(uint32_t) * items.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        rc = SMF_EHIP;
+        goto fail;
+    }
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        smf::batch_max_blocks_per_cu(b->lds, &blocks) != hipSuccess) {
+        rc = SMF_EHIP;
+        goto fail;
+    }
+    b->max_per_cu = std::max(blocks, 1);
+    b->grid = b->n_cu * b->max_per_cu;
+    plan = (smf_plan*)calloc(1, sizeof(smf_plan));
+    if (!plan) { rc = SMF_ENOMEM; goto fail; }
+    plan->flags = SMF_FP32;
+    plan->device = dev;
+    plan->batch = b;
+    *out = plan;
+    return SMF_OK;
+fail:
+    for (smf_plan* p : b->sub) smf_destroy(p);
+    if (b->fields_dev) (void)hipFree(b->fields_dev);
+    if (b->items_dev) (void)hipFree(b->items_dev);
+    if (b->counters_dev) (void)hipFree(b->counters_dev);
+    delete b;
+    return rc;
+}
+
+int smf_batch_layout(const smf_plan* plan, int64_t* offsets)
+{
+    if (!plan || !plan->batch || !offsets) return SMF_EINVAL;
+    const smf::BatchState* b = plan->batch;
+    for (int i = 0; i <= b->n; ++i) offsets[i] = b->offsets[i];
+    return SMF_OK;
+}
+
+static int batch_launch(const smf_plan* plan, uint64_t seed, void* out_dev, hipStream_t st, int grid)
+{
+    const smf::BatchState* b = plan->batch;
+    smf::BatchArgs a;
+    a.fields = b->fields_dev;
+    a.items = b->items_dev;
+    a.counters = b->counters_dev;
+    a.out = (float*)out_dev;
+    a.seed = seed;
+    a.n_fields = b->n;
+    a.n_rec = b->n_rec;
+    a.n_items = b->n_items;
+    a.spin_limit = b->spin_limit;
+    return smf::launch_batch(a, grid, b->lds, st) == hipSuccess ? SMF_OK : SMF_EHIP;
+}
+
+int smf_sample_batch(const smf_plan* plan, uint64_t seed, void* out_dev, void* hip_stream)
+{
+    if (!plan || !plan->batch || !out_dev) return SMF_EINVAL;
+    DeviceGuard dg(plan->device);
+    return batch_launch(plan, seed, out_dev, (hipStream_t)hip_stream, plan->batch->grid);
+}
+
+int smf_batch_status(const smf_plan* plan, void* hip_stream)
+{
+    if (!plan || !plan->batch) return SMF_EINVAL;
+    DeviceGuard dg(plan->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    int err = 0;
+    if (hipMemcpyAsync(&err, plan->batch->counters_dev + 1, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return SMF_EHIP;
+    return err ? SMF_EWAIT : SMF_OK;
+}
+
+int smf_batch_set_wait_limit(smf_plan* plan, int spins)
+{
+    if (!plan || !plan->batch || spins < -1) return SMF_EINVAL;
+    plan->batch->spin_limit = spins;
+    return SMF_OK;
+}
+
+int smf_autotune_batch(smf_plan* plan, uint64_t seed, void* out_dev, void* hip_stream, int* grid_out)
+{
+    if (!plan || !plan->batch || !out_dev) return SMF_EINVAL;
+    DeviceGuard dg(plan->device);
+    smf::BatchState* b = plan->batch;
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return SMF_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return SMF_EHIP; }
+    int best_grid = b->grid;
+    float best = 1e30f;
+    int rc = SMF_OK;
+    for (int k = 1; k <= b->max_per_cu && rc == SMF_OK; ++k) {
+        const int grid = k * b->n_cu;
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 3 && rc == SMF_OK; ++rep) {
+            float ms = 0.f;
+            if (hipEventRecord(e0, st) != hipSuccess) { rc = SMF_EHIP; break; }
+            rc = batch_launch(plan, seed, out_dev, st, grid);
+            if (rc != SMF_OK) break;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = SMF_EHIP; break; }
+            if (rep > 0) ms_min = std::min(ms_min, ms);   // first run warms up
+        }
+        if (rc == SMF_OK && ms_min < best) { best = ms_min; best_grid = grid; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SMF_OK) return rc;
+    b->grid = best_grid;
+    if (grid_out) *grid_out = best_grid;
+    return SMF_OK;
 }
 
 }  // extern "C"

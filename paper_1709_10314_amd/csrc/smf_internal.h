@@ -61,6 +61,10 @@ hipError_t launch_c2r(const Geometry& g, int fp64, const void* tw, int count, vo
 
 }  // namespace smf
 
+namespace smf {
+struct BatchState;
+}
+
 struct smf_plan {
     smf::Geometry g;
     int flags;           // SMF_FP64 or SMF_FP32
@@ -70,4 +74,5 @@ struct smf_plan {
     double* tw64;        // e^{+2 pi i t / n_phi}, t < n_phi
     float* tw32;
     int device;
+    smf::BatchState* batch;   // non-null for a batch plan (see smf_setup_batch)
 };

@@ -13,12 +13,13 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsmf.so")
 
-SMF_OK, SMF_EINVAL, SMF_ENOMEM, SMF_EHIP, SMF_ENUMERIC = 0, -1, -2, -3, -4
+SMF_OK, SMF_EINVAL, SMF_ENOMEM, SMF_EHIP, SMF_ENUMERIC, SMF_EWAIT = 0, -1, -2, -3, -4, -5
 SMF_FP64, SMF_FP32 = 1, 2
 
 # every symbol include/smf.h declares
 EXPORTS = ("smf_setup", "smf_sample", "smf_sample_modes", "smf_plan_dims", "smf_get_factors",
-           "smf_destroy", "smf_error_string")
+           "smf_destroy", "smf_error_string", "smf_setup_batch", "smf_batch_layout",
+           "smf_sample_batch", "smf_batch_status", "smf_batch_set_wait_limit", "smf_autotune_batch")
 
 
 class smf_spectrum(ctypes.Structure):
@@ -53,8 +54,17 @@ def load():
     lib.smf_destroy.argtypes = [vp]
     lib.smf_error_string.argtypes = [i]
     lib.smf_error_string.restype = ctypes.c_char_p
+    lib.smf_setup_batch.argtypes = [i, ctypes.POINTER(smf_spectrum), ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_int), i, vp, ctypes.POINTER(vp)]
+    lib.smf_batch_layout.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.smf_sample_batch.argtypes = [vp, u64, vp, vp]
+    lib.smf_batch_status.argtypes = [vp, vp]
+    lib.smf_batch_set_wait_limit.argtypes = [vp, i]
+    lib.smf_autotune_batch.argtypes = [vp, u64, vp, vp, ctypes.POINTER(ctypes.c_int)]
     for name in ("smf_setup", "smf_sample", "smf_sample_modes", "smf_plan_dims",
-                 "smf_get_factors", "smf_destroy"):
+                 "smf_get_factors", "smf_destroy", "smf_setup_batch", "smf_batch_layout",
+                 "smf_sample_batch", "smf_batch_status", "smf_batch_set_wait_limit",
+                 "smf_autotune_batch"):
         getattr(lib, name).restype = i
     _lib = lib
     return lib
@@ -120,6 +130,123 @@ def smf_get_factors(plan, A, B):
 
 def smf_destroy(plan):
     return load().smf_destroy(plan)
+
+
+def _spectrum_struct(order, ell_max, kappa=None, c_ell=None, keep=None):
+    spec = smf_spectrum()
+    spec.order = int(order)
+    spec.ell_max = int(ell_max)
+    if c_ell is not None:
+        c = np.ascontiguousarray(c_ell, dtype=np.float64)
+        keep.append(c)
+        spec.c_ell = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        spec.n_kappa = 0
+    else:
+        k = np.ascontiguousarray([] if kappa is None else kappa, dtype=np.float64).reshape(-1)
+        keep.append(k)
+        spec.n_kappa = len(k)
+        spec.kappa = k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if len(k) else None
+    return spec
+
+
+def smf_setup_batch(fields, flags=SMF_FP32, stream=None):
+    """fields: list of dicts with order, n_theta, n_phi, ell_max and kappa (list of kappa_i)
+    or c_ell.  Returns (code, plan handle)."""
+    keep = []
+    n = len(fields)
+    specs = (smf_spectrum * n)()
+    nt = (ctypes.c_int * n)()
+    npf = (ctypes.c_int * n)()
+    for i, f in enumerate(fields):
+        specs[i] = _spectrum_struct(f["order"], f["ell_max"], f.get("kappa"), f.get("c_ell"), keep)
+        nt[i] = int(f["n_theta"])
+        npf[i] = int(f["n_phi"])
+    plan = ctypes.c_void_p()
+    rc = load().smf_setup_batch(n, specs, nt, npf, int(flags), _stream_handle(stream), ctypes.byref(plan))
+    return rc, plan
+
+
+def smf_batch_layout(plan, n):
+    off = (ctypes.c_int64 * (n + 1))()
+    rc = load().smf_batch_layout(plan, off)
+    return rc, [int(x) for x in off]
+
+
+def smf_sample_batch(plan, seed, out_ptr, stream=None):
+    return load().smf_sample_batch(plan, ctypes.c_uint64(int(seed)), ctypes.c_void_p(out_ptr),
+                                   _stream_handle(stream))
+
+
+def smf_batch_status(plan, stream=None):
+    return load().smf_batch_status(plan, _stream_handle(stream))
+
+
+def smf_batch_set_wait_limit(plan, spins):
+    return load().smf_batch_set_wait_limit(plan, int(spins))
+
+
+def smf_autotune_batch(plan, seed, out_ptr, stream=None):
+    g = ctypes.c_int(0)
+    rc = load().smf_autotune_batch(plan, ctypes.c_uint64(int(seed)), ctypes.c_void_p(out_ptr),
+                                   _stream_handle(stream), ctypes.byref(g))
+    return rc, g.value
+
+
+class BatchPlan:
+    """Many fields of uneven shape, spectrum and order, sampled in one persistent launch."""
+
+    def __init__(self, fields, stream=None):
+        rc, h = smf_setup_batch(fields, SMF_FP32, stream)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_setup_batch")
+        self._h = h
+        self.n = len(fields)
+        self.fields = [dict(f) for f in fields]
+        rc, self.offsets = smf_batch_layout(h, self.n)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def empty(self, device="cuda"):
+        import torch
+
+        return torch.empty(self.offsets[-1], dtype=torch.float32, device=device)
+
+    def sample(self, seed, out=None, stream=None):
+        if out is None:
+            out = self.empty()
+        if not out.is_cuda or out.dtype.itemsize != 4 or out.numel() < self.offsets[-1]:
+            raise ValueError("output must be a device float32 tensor of offsets[-1] elements")
+        rc = smf_sample_batch(self._h, seed, out.data_ptr(), stream)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_sample_batch")
+        return out
+
+    def field(self, out, i):
+        """View of field i ([n_theta, n_phi]) in a packed output."""
+        f = self.fields[i]
+        return out[self.offsets[i]:self.offsets[i + 1]].view(f["n_theta"], f["n_phi"])
+
+    def status(self, stream=None):
+        return smf_batch_status(self._h, stream)
+
+    def autotune(self, seed, out, stream=None):
+        rc, grid = smf_autotune_batch(self._h, seed, out.data_ptr(), stream)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_autotune_batch")
+        return grid
+
+    def close(self):
+        if getattr(self, "_h", None):
+            smf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Plan:

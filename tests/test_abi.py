@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     lib = smf.load()
     for n in _declared():
         assert hasattr(lib, n), n
-    assert set(_declared()) <= set(smf.EXPORTS) | {"smf_sample_batch", "smf_setup_batch"}
+    assert set(_declared()) == set(smf.EXPORTS)
 
 
 def test_error_strings_and_null_handling_without_gpu():
@@ -44,6 +44,12 @@ def test_error_strings_and_null_handling_without_gpu():
     assert lib.smf_get_factors(None, None, None) == smf.SMF_EINVAL
     assert lib.smf_destroy(None) == smf.SMF_OK
     assert lib.smf_setup(None, 8, 16, smf.SMF_FP64, None, None) == smf.SMF_EINVAL
+    assert lib.smf_sample_batch(None, 1, None, None) == smf.SMF_EINVAL
+    assert lib.smf_batch_layout(None, None) == smf.SMF_EINVAL
+    assert lib.smf_batch_status(None, None) == smf.SMF_EINVAL
+    assert lib.smf_batch_set_wait_limit(None, 5) == smf.SMF_EINVAL
+    assert lib.smf_autotune_batch(None, 1, None, None, None) == smf.SMF_EINVAL
+    assert lib.smf_setup_batch(0, None, None, None, smf.SMF_FP32, None, None) == smf.SMF_EINVAL
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):

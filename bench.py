@@ -30,7 +30,7 @@ def log(msg):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("rng.h", "sample.hip", "smf_internal.h"):
+    for f in ("rng.h", "device_path.h", "sample.hip", "smf_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_1709_10314_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -108,6 +108,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-rings", type=int, default=96)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB (calibrates rocprofv3 FETCH/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -118,6 +120,16 @@ def main():
         return
 
     import torch
+
+    if args.copy_calibration:
+        n = 1 << 28                                   # 2^28 floats = 1 GiB each way
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": 4 * n, "launches": 3}), flush=True)
+        return
 
     from paper_1709_10314_amd import Plan, workloads
 

@@ -50,8 +50,7 @@ enum {
     SMF_EINVAL = -1,     /* bad argument (shape, order, NULL pointer, count < 0, ...) */
     SMF_ENOMEM = -2,     /* device allocation failed */
     SMF_EHIP = -3,       /* a HIP runtime call or kernel launch failed */
-    SMF_ENUMERIC = -4,   /* spectrum has a C_l that is not finite and positive */
-    SMF_EWAIT = -5       /* a batch FFT item gave up waiting for its field's chains */
+    SMF_ENUMERIC = -4    /* spectrum has a C_l that is not finite and positive */
 };
 
 enum {
@@ -101,11 +100,11 @@ int smf_plan_dims(const smf_plan* plan, int* dims);
  * Synchronous.  Errors: SMF_EINVAL on NULL, SMF_EHIP. */
 int smf_get_factors(const smf_plan* plan, double* A_host, double* B_host);
 
-/* ---- batched form: many fields of uneven shape, spectrum and order in one launch ---- */
+/* ---- batched form: many fields of uneven shape, spectrum and order per call ---- */
 
-/* One FP32 plan per field (Alg. 1 for each, as smf_setup with SMF_FP32) plus the work
- * list of one persistent kernel that runs every field's chains (Alg. 2) and then the FFT
- * of each of its rings.  specs, n_theta, n_phi: host arrays of n entries (n in
+/* One FP32 plan per field (Alg. 1 for each, as smf_setup with SMF_FP32) plus flat work
+ * lists: chain items (field, group of m-tiles), longest chains first, and one FFT item
+ * per ring of every field.  specs, n_theta, n_phi: host arrays of n entries (n in
  * [1, 65535]); n_phi[i] a power of two in [4, 4096]; flags must be SMF_FP32.
  * Errors: as smf_setup, per field. */
 int smf_setup_batch(int n, const smf_spectrum* specs, const int* n_theta, const int* n_phi,
@@ -115,29 +114,20 @@ int smf_setup_batch(int n, const smf_spectrum* specs, const int* n_theta, const 
  * field i occupies [offsets[i], offsets[i+1]) as [ring][phi].  Errors: SMF_EINVAL. */
 int smf_batch_layout(const smf_plan* plan, int64_t* offsets);
 
-/* Samples every field of a batch plan in one persistent launch (after a small counter
- * reset kernel; no memset, no allocation, so the call can be captured in a HIP graph).
- * Field i uses Philox key seed + i.  out_dev: device float array of offsets[n] elements.
- * The plan's device counters are shared: calls on one batch plan must not overlap (use one
- * stream per plan, or one plan per stream).  Asynchronous; smf_batch_status reports
- * whether any wait gave up.  Errors: SMF_EINVAL (NULL, not a batch plan), SMF_EHIP. */
+/* Samples every field of a batch plan (Alg. 2 for each): one launch over all chain
+ * items, then one over all rings.  No memset, no allocation and no host synchronisation,
+ * so the call can be captured in a HIP graph; it only reads the plan, so calls may
+ * overlap on different streams.  Field i uses Philox key seed + i.  out_dev: device
+ * float array of offsets[n] elements.  Errors: SMF_EINVAL (NULL, not a batch plan),
+ * SMF_EHIP. */
 int smf_sample_batch(const smf_plan* plan, uint64_t seed, void* out_dev, void* hip_stream);
 
-/* Synchronises hip_stream and returns SMF_OK, or SMF_EWAIT if an FFT item of the last
- * batch call gave up waiting for its field's chains (that ring's output is then
- * unreliable).  Errors: SMF_EINVAL, SMF_EHIP. */
-int smf_batch_status(const smf_plan* plan, void* hip_stream);
-
-/* Bound on each FFT item's wait, in sleep iterations (default 2^22, about a second).
- * spins = -1 makes every FFT item skip the wait and report SMF_EWAIT (exercises the
- * error path; the output is then unreliable).  Errors: SMF_EINVAL (spins < -1). */
-int smf_batch_set_wait_limit(smf_plan* plan, int spins);
-
-/* Autotuner: times the persistent launch for 1..(max resident per CU) workgroups per
- * compute unit (writing out_dev, seed as in smf_sample_batch), keeps the fastest grid in
- * the plan and returns it in *grid_out (may be NULL).  Synchronous.
+/* Autotuner of the chain-item tile shape: times smf_sample_batch with 1, 2 and 4 m-tiles
+ * per chain item (2, 4 and 8 waves per workgroup; writing out_dev, seed as in
+ * smf_sample_batch), keeps the fastest in the plan and returns its m-tile count in
+ * *tiles_out (may be NULL).  Synchronous; not to be called while the plan is in use.
  * Errors: SMF_EINVAL, SMF_EHIP. */
-int smf_autotune_batch(smf_plan* plan, uint64_t seed, void* out_dev, void* hip_stream, int* grid_out);
+int smf_autotune_batch(smf_plan* plan, uint64_t seed, void* out_dev, void* hip_stream, int* tiles_out);
 
 /* Frees the plan and its device memory (synchronises the device first).  NULL is a
  * no-op. */

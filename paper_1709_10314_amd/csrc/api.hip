@@ -11,20 +11,18 @@
 using smf::Geometry;
 
 namespace smf {
-// Host state of a batch plan: one FP32 sub-plan per field plus the device work list.
+// Host state of a batch plan: one FP32 sub-plan per field plus the device work lists.
 struct BatchState {
     int n = 0;
     std::vector<smf_plan*> sub;
-    std::vector<int64_t> offsets;   // n + 1 packed-output offsets (elements)
+    std::vector<int64_t> offsets;        // n + 1 packed-output offsets (elements)
     BatchField* fields_dev = nullptr;
-    uint32_t* items_dev = nullptr;
-    int* counters_dev = nullptr;
-    int n_rec = 0, n_items = 0;
+    uint32_t* chain_dev[3] = {nullptr, nullptr, nullptr};   // items for 1, 2, 4 m-tiles
+    int n_chain[3] = {0, 0, 0};
+    uint32_t* fft_dev = nullptr;
+    int n_fft = 0;
     size_t lds = 0;
-    int grid = 0;
-    int max_per_cu = 1;
-    int n_cu = 1;
-    int spin_limit = 1 << 22;
+    int tiles_idx = 1;                   // current tile shape: 2 m-tiles per item
 };
 }  // namespace smf
 
@@ -246,8 +244,8 @@ int smf_destroy(smf_plan* plan)
         smf::BatchState* b = plan->batch;
         for (smf_plan* p : b->sub) smf_destroy(p);
         (void)hipFree(b->fields_dev);
-        (void)hipFree(b->items_dev);
-        (void)hipFree(b->counters_dev);
+        for (int k = 0; k < 3; ++k) (void)hipFree(b->chain_dev[k]);
+        (void)hipFree(b->fft_dev);
         delete b;
         free(plan);
         return SMF_OK;
@@ -269,7 +267,6 @@ const char* smf_error_string(int code)
         case SMF_ENOMEM: return "device memory allocation failed";
         case SMF_EHIP: return "HIP runtime error";
         case SMF_ENUMERIC: return "spectrum has a C_l that is not finite and positive";
-        case SMF_EWAIT: return "a batch FFT item gave up waiting for its field's chains";
         default: return "unknown error code";
     }
 }
@@ -290,9 +287,9 @@ int smf_setup_batch(int n, const smf_spectrum* specs, const int* n_theta, const 
     int rc = SMF_OK;
     std::vector<smf::BatchField> fields(n);
     std::vector<int> order_idx(n);
-    std::vector<uint32_t> items;
+    std::vector<uint32_t> fft_items;
     smf_plan* plan = nullptr;
-    int dev = 0, blocks = 0;
+    int dev = 0;
     for (int i = 0; i < n; ++i) {
         smf_plan* p = nullptr;
         rc = setup_impl(&specs[i], n_theta[i], n_phi[i], SMF_FP32, st, &p);
@@ -312,40 +309,48 @@ int smf_setup_batch(int n, const smf_spectrum* specs, const int* n_theta, const 
         F.s = g.s;
         F.even = g.even;
         F.log2h = __builtin_ctz((unsigned)g.n_phi) - 1;
-        F.n_rec_items = ((g.m_rows + 31) / 32 + 1) / 2;
         F.seed_off = i;
         b->lds = std::max(b->lds, sizeof(float) * 2 * (size_t)(g.n_phi / 2));
     }
-    // longest chains first; FFT items follow in the same field order
+    // chain items longest chain first, for each tile shape; FFT items in the same order
     for (int i = 0; i < n; ++i) order_idx[i] = i;
     std::stable_sort(order_idx.begin(), order_idx.end(),
                      [&](int x, int y) { return fields[x].n_theta > fields[y].n_theta; });
+    for (int k = 0; k < 3; ++k) {
+        const int tiles = 1 << k;
+        std::vector<uint32_t> items;
+        for (int i : order_idx) {
+            const int n_mt = (fields[i].m_rows + 31) / 32;
+            for (int t = 0; t < (n_mt + tiles - 1) / tiles; ++t)
+                items.push_back(((uint32_t)i << 16) | (uint32_t)t);
+        }
+        b->n_chain[k] = (int)items.size();
+        if (hipMalloc(&b->chain_dev[k], sizeof(uint32_t) * items.size()) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = SMF_ENOMEM;
+            goto fail;
+        }
+        if (hipMemcpy(b->chain_dev[k], items.data(), sizeof(uint32_t) * items.size(),
+                      hipMemcpyHostToDevice) != hipSuccess) {
+            rc = SMF_EHIP;
+            goto fail;
+        }
+    }
     for (int i : order_idx)
-        for (int t = 0; t < fields[i].n_rec_items; ++t) items.push_back(((uint32_t)i << 16) | (uint32_t)t);
-    b->n_rec = (int)items.size();
-    for (int i : order_idx)
-        for (int r = 0; r < fields[i].n_theta; ++r) items.push_back(((uint32_t)i << 16) | (uint32_t)r);
-    b->n_items = (int)items.size();
+        for (int r = 0; r < fields[i].n_theta; ++r) fft_items.push_back(((uint32_t)i << 16) | (uint32_t)r);
+    b->n_fft = (int)fft_items.size();
     if (hipMalloc(&b->fields_dev, sizeof(smf::BatchField) * n) != hipSuccess ||
-        hipMalloc(&b->items_dev, sizeof(uint32_t) * items.size()) != hipSuccess ||
-        hipMalloc(&b->counters_dev, sizeof(int) * (n + 2)) != hipSuccess) {
+        hipMalloc(&b->fft_dev, sizeof(uint32_t) * fft_items.size()) != hipSuccess) {
         (void)hipGetLastError();
         rc = SMF_ENOMEM;
         goto fail;
     }
     if (hipMemcpy(b->fields_dev, fields.data(), sizeof(smf::BatchField) * n, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->items_dev, items.data(), sizeof(uint32_t) * items.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(b->fft_dev, fft_items.data(), sizeof(uint32_t) * fft_items.size(),
+                  hipMemcpyHostToDevice) != hipSuccess || hipGetDevice(&dev) != hipSuccess) {
         rc = SMF_EHIP;
         goto fail;
     }
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        smf::batch_max_blocks_per_cu(b->lds, &blocks) != hipSuccess) {
-        rc = SMF_EHIP;
-        goto fail;
-    }
-    b->max_per_cu = std::max(blocks, 1);
-    b->grid = b->n_cu * b->max_per_cu;
     plan = (smf_plan*)calloc(1, sizeof(smf_plan));
     if (!plan) { rc = SMF_ENOMEM; goto fail; }
     plan->flags = SMF_FP32;
@@ -356,8 +361,9 @@ int smf_setup_batch(int n, const smf_spectrum* specs, const int* n_theta, const 
 fail:
     for (smf_plan* p : b->sub) smf_destroy(p);
     if (b->fields_dev) (void)hipFree(b->fields_dev);
-    if (b->items_dev) (void)hipFree(b->items_dev);
-    if (b->counters_dev) (void)hipFree(b->counters_dev);
+    for (int k = 0; k < 3; ++k)
+        if (b->chain_dev[k]) (void)hipFree(b->chain_dev[k]);
+    if (b->fft_dev) (void)hipFree(b->fft_dev);
     delete b;
     return rc;
 }
@@ -370,49 +376,29 @@ int smf_batch_layout(const smf_plan* plan, int64_t* offsets)
     return SMF_OK;
 }
 
-static int batch_launch(const smf_plan* plan, uint64_t seed, void* out_dev, hipStream_t st, int grid)
+static int batch_launch(const smf_plan* plan, uint64_t seed, void* out_dev, hipStream_t st, int tiles_idx)
 {
     const smf::BatchState* b = plan->batch;
     smf::BatchArgs a;
     a.fields = b->fields_dev;
-    a.items = b->items_dev;
-    a.counters = b->counters_dev;
+    a.chain_items = b->chain_dev[tiles_idx];
+    a.fft_items = b->fft_dev;
     a.out = (float*)out_dev;
     a.seed = seed;
-    a.n_fields = b->n;
-    a.n_rec = b->n_rec;
-    a.n_items = b->n_items;
-    a.spin_limit = b->spin_limit;
-    return smf::launch_batch(a, grid, b->lds, st) == hipSuccess ? SMF_OK : SMF_EHIP;
+    a.tiles = 1 << tiles_idx;
+    a.n_chain_items = b->n_chain[tiles_idx];
+    a.n_fft_items = b->n_fft;
+    return smf::launch_batch(a, b->lds, st) == hipSuccess ? SMF_OK : SMF_EHIP;
 }
 
 int smf_sample_batch(const smf_plan* plan, uint64_t seed, void* out_dev, void* hip_stream)
 {
     if (!plan || !plan->batch || !out_dev) return SMF_EINVAL;
     DeviceGuard dg(plan->device);
-    return batch_launch(plan, seed, out_dev, (hipStream_t)hip_stream, plan->batch->grid);
+    return batch_launch(plan, seed, out_dev, (hipStream_t)hip_stream, plan->batch->tiles_idx);
 }
 
-int smf_batch_status(const smf_plan* plan, void* hip_stream)
-{
-    if (!plan || !plan->batch) return SMF_EINVAL;
-    DeviceGuard dg(plan->device);
-    hipStream_t st = (hipStream_t)hip_stream;
-    int err = 0;
-    if (hipMemcpyAsync(&err, plan->batch->counters_dev + 1, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-        return SMF_EHIP;
-    return err ? SMF_EWAIT : SMF_OK;
-}
-
-int smf_batch_set_wait_limit(smf_plan* plan, int spins)
-{
-    if (!plan || !plan->batch || spins < -1) return SMF_EINVAL;
-    plan->batch->spin_limit = spins;
-    return SMF_OK;
-}
-
-int smf_autotune_batch(smf_plan* plan, uint64_t seed, void* out_dev, void* hip_stream, int* grid_out)
+int smf_autotune_batch(smf_plan* plan, uint64_t seed, void* out_dev, void* hip_stream, int* tiles_out)
 {
     if (!plan || !plan->batch || !out_dev) return SMF_EINVAL;
     DeviceGuard dg(plan->device);
@@ -421,28 +407,27 @@ int smf_autotune_batch(smf_plan* plan, uint64_t seed, void* out_dev, void* hip_s
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return SMF_EHIP;
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return SMF_EHIP; }
-    int best_grid = b->grid;
+    int best_k = b->tiles_idx;
     float best = 1e30f;
     int rc = SMF_OK;
-    for (int k = 1; k <= b->max_per_cu && rc == SMF_OK; ++k) {
-        const int grid = k * b->n_cu;
+    for (int k = 0; k < 3 && rc == SMF_OK; ++k) {
         float ms_min = 1e30f;
         for (int rep = 0; rep < 3 && rc == SMF_OK; ++rep) {
             float ms = 0.f;
             if (hipEventRecord(e0, st) != hipSuccess) { rc = SMF_EHIP; break; }
-            rc = batch_launch(plan, seed, out_dev, st, grid);
+            rc = batch_launch(plan, seed, out_dev, st, k);
             if (rc != SMF_OK) break;
             if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = SMF_EHIP; break; }
-            if (rep > 0) ms_min = std::min(ms_min, ms);   // first run warms up
+            if (rep > 0) ms_min = std::min(ms_min, ms);   // the first run warms up
         }
-        if (rc == SMF_OK && ms_min < best) { best = ms_min; best_grid = grid; }
+        if (rc == SMF_OK && ms_min < best) { best = ms_min; best_k = k; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != SMF_OK) return rc;
-    b->grid = best_grid;
-    if (grid_out) *grid_out = best_grid;
+    b->tiles_idx = best_k;
+    if (tiles_out) *tiles_out = 1 << best_k;
     return SMF_OK;
 }
 

@@ -1,4 +1,4 @@
-// Descriptors of the persistent batch kernel (batch.hip).
+// Descriptors of the batch kernels (batch.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -6,26 +6,27 @@
 
 namespace smf {
 
+constexpr int kMaxTiles = 4;                       // m-tiles per chain item (tile shape)
+constexpr int kMaxChainThreads = 64 * 2 * kMaxTiles;
+
 struct BatchField {
     const float* fac;     // FP32 factor records of the field's plan
     const float* tw;      // its FFT twiddles
     int64_t out_off;      // first element of the field in the packed output
     int n_theta, n_phi, order, m_top, m_rows, s, even, log2h;
-    int n_rec_items;      // chain items of this field
     int seed_off;         // Philox key = seed + seed_off
 };
 
 struct BatchArgs {
     const BatchField* fields;
-    const uint32_t* items;   // (field << 16) | sub
-    int* counters;           // [0] queue head, [1] error word, [2 + f] chain items done
+    const uint32_t* chain_items;   // (field << 16) | group of `tiles` m-tiles
+    const uint32_t* fft_items;     // (field << 16) | ring
     float* out;
     uint64_t seed;
-    int n_fields, n_rec, n_items;
-    int spin_limit;          // bound on the FFT items' waits (iterations of s_sleep)
+    int tiles;                     // m-tiles per chain item: 1, 2 or 4
+    int n_chain_items, n_fft_items;
 };
 
-hipError_t launch_batch(const BatchArgs& a, int grid, size_t lds, hipStream_t st);
-hipError_t batch_max_blocks_per_cu(size_t lds, int* blocks);
+hipError_t launch_batch(const BatchArgs& a, size_t lds, hipStream_t st);
 
 }  // namespace smf

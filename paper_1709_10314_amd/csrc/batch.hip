@@ -1,26 +1,26 @@
-// Batched sampling of many fields of uneven shape, spectrum and order in one persistent
-// launch (FP32).  Each field runs Alg. 2 of Creasey & Lang: its ring chains (eqs.
-// (state_initial), (state_space)) and then the inverse FFT of each of its rings.
+// Batched sampling of many fields of uneven shape, spectrum and order (FP32) in two
+// launches: one over the chain items of every field (Creasey & Lang, Alg. 2; eqs.
+// (state_initial), (state_space)), then one over every ring of every field (the inverse
+// FFT, Alg. 2 last step).  Both grids are flat work lists built at setup: a workgroup
+// looks its item up and runs it, with no queue, no counters and no waiting, so the call
+// is a pair of ordinary launches that a HIP graph can capture.
 //
-// Work items are pulled from one atomic counter.  Items 0..n_rec-1 are chain items
-// (field, pair of m-tiles; four waves = 2 hemispheres x 2 m-tiles), ordered longest chain
-// first; items n_rec.. are FFT items (field, ring) in the same field order.  An FFT item
-// waits until its field's chain items are all done (per-field counter, release/acquire
-// at agent scope so the modes written on another XCD are visible).  Chain items never
-// wait, and every chain item is taken before any FFT item, so the waits always end; they
-// are bounded anyway, and a wait that runs out sets the error word instead of hanging.
+// A chain item is (field, group of `tiles` m-tiles); the workgroup holds 2 x tiles waves
+// (hemisphere x m-tile).  Chain items are listed longest chain first so that the
+// in-order dispatch starts the long fields early.  The number of m-tiles per item is the
+// tile shape the autotuner picks.
 #include "batch.h"
 #include "device_path.h"
 
 namespace smf {
 namespace {
 
-constexpr int kBatchThreads = 256;
+constexpr int kFftThreads = 256;
 
 template <int LOG2H>
 __device__ __forceinline__ void fft_item(float* row, const float* tw, int m_top, Cx<float>* buf)
 {
-    c2r_row<float, LOG2H, kBatchThreads>(row, tw, m_top, buf);
+    c2r_row<float, LOG2H, kFftThreads>(row, tw, m_top, buf);
 }
 
 __device__ void dispatch_fft(int log2h, float* row, const float* tw, int m_top, Cx<float>* buf)
@@ -41,95 +41,60 @@ __device__ void dispatch_fft(int log2h, float* row, const float* tw, int m_top, 
     }
 }
 
-__global__ __launch_bounds__(kBatchThreads) void batch_reset_kernel(int* counters, int n)
+// One workgroup per chain item; wave w -> hemisphere w & 1, m-tile tiles * sub + (w >> 1).
+__global__ __launch_bounds__(kMaxChainThreads) void batch_chain_kernel(BatchArgs a)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        counters[i] = 0;
+    const uint32_t code = a.chain_items[blockIdx.x];
+    const int fi = (int)(code >> 16);
+    const int sub = (int)(code & 0xFFFF);
+    const BatchField& F = a.fields[fi];
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int h = w & 1;
+    const int lane = threadIdx.x & 63;
+    const int m = (a.tiles * sub + (w >> 1)) * 32 + (lane >> 1), part = lane & 1;
+    if (m >= F.m_rows) return;
+    float* g = a.out + F.out_off + 2 * m + part;
+    if (m > F.m_top || (m == 0 && part == 1)) {
+        zero_chain<float>(F.n_theta, F.s, h, g, (size_t)F.n_phi);
+        return;
+    }
+    const uint64_t key = a.seed + (uint64_t)F.seed_off;
+    const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+    const size_t stride = (size_t)F.m_rows * factor_stride(F.order);
+    if (F.order == 1)
+        run_chain<float, 1>(F.n_theta, F.s, F.even, h, m, part, k0, k1,
+                            F.fac + (size_t)m * factor_stride(1), stride, g, (size_t)F.n_phi);
+    else
+        run_chain<float, 2>(F.n_theta, F.s, F.even, h, m, part, k0, k1,
+                            F.fac + (size_t)m * factor_stride(2), stride, g, (size_t)F.n_phi);
 }
 
-__global__ __launch_bounds__(kBatchThreads) void batch_kernel(BatchArgs a)
+// One workgroup per ring of every field.
+__global__ __launch_bounds__(kFftThreads) void batch_fft_kernel(BatchArgs a)
 {
     extern __shared__ unsigned char smem_raw[];
-    Cx<float>* buf = reinterpret_cast<Cx<float>*>(smem_raw);
-    __shared__ int s_item;
-    int* queue = a.counters;
-    int* err = a.counters + 1;
-    int* done = a.counters + 2;
-    const int tid = threadIdx.x;
-    for (;;) {
-        if (tid == 0) s_item = atomicAdd(queue, 1);
-        __syncthreads();
-        const int item = s_item;
-        __syncthreads();
-        if (item >= a.n_items) return;
-        const uint32_t code = a.items[item];
-        const int fi = (int)(code >> 16);
-        const int sub = (int)(code & 0xFFFF);
-        const BatchField F = a.fields[fi];
-        if (item < a.n_rec) {
-            // chain item: wave w -> hemisphere w & 1, m-tile 2 sub + (w >> 1)
-            const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-            const int h = w & 1;
-            const int lane = tid & 63;
-            const int m = (2 * sub + (w >> 1)) * 32 + (lane >> 1), part = lane & 1;
-            if (m < F.m_rows) {
-                float* g = a.out + F.out_off + 2 * m + part;
-                if (m > F.m_top || (m == 0 && part == 1)) {
-                    zero_chain<float>(F.n_theta, F.s, h, g, (size_t)F.n_phi);
-                } else {
-                    const uint64_t key = a.seed + (uint64_t)F.seed_off;
-                    const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
-                    const size_t stride = (size_t)F.m_rows * factor_stride(F.order);
-                    if (F.order == 1)
-                        run_chain<float, 1>(F.n_theta, F.s, F.even, h, m, part, k0, k1,
-                                            F.fac + (size_t)m * factor_stride(1), stride, g,
-                                            (size_t)F.n_phi);
-                    else
-                        run_chain<float, 2>(F.n_theta, F.s, F.even, h, m, part, k0, k1,
-                                            F.fac + (size_t)m * factor_stride(2), stride, g,
-                                            (size_t)F.n_phi);
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __syncthreads();
-            if (tid == 0) __hip_atomic_fetch_add(done + fi, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            // FFT item: ring `sub` of field fi, once all chain items of fi are done
-            if (tid == 0) {
-                int spins = 0;
-                if (a.spin_limit < 0) atomicOr(err, 1);   // wait skipped on request
-                else while (__hip_atomic_load(done + fi, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < F.n_rec_items) {
-                    __builtin_amdgcn_s_sleep(8);
-                    if (++spins > a.spin_limit) {
-                        atomicOr(err, 1);
-                        break;
-                    }
-                }
-            }
-            __syncthreads();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            dispatch_fft(F.log2h, a.out + F.out_off + (size_t)sub * F.n_phi, F.tw, F.m_top, buf);
-            __syncthreads();
-        }
-    }
+    const uint32_t code = a.fft_items[blockIdx.x];
+    const int fi = (int)(code >> 16);
+    const int ring = (int)(code & 0xFFFF);
+    const BatchField& F = a.fields[fi];
+    dispatch_fft(F.log2h, a.out + F.out_off + (size_t)ring * F.n_phi, F.tw, F.m_top,
+                 reinterpret_cast<Cx<float>*>(smem_raw));
 }
 
 }  // namespace
 
-hipError_t launch_batch(const BatchArgs& a, int grid, size_t lds, hipStream_t st)
+hipError_t launch_batch(const BatchArgs& a, size_t lds, hipStream_t st)
 {
-    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(kBatchThreads), 0, st, a.counters,
-                       a.n_fields + 2);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(kBatchThreads), lds, st, a);
-    return hipGetLastError();
-}
-
-hipError_t batch_max_blocks_per_cu(size_t lds, int* blocks)
-{
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void*)batch_kernel, kBatchThreads,
-                                                        lds);
+    if (a.n_chain_items > 0) {
+        hipLaunchKernelGGL(batch_chain_kernel, dim3(a.n_chain_items), dim3(64 * 2 * a.tiles), 0, st, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (a.n_fft_items > 0) {
+        hipLaunchKernelGGL(batch_fft_kernel, dim3(a.n_fft_items), dim3(kFftThreads), lds, st, a);
+        return hipGetLastError();
+    }
+    return hipSuccess;
 }
 
 }  // namespace smf

@@ -13,13 +13,13 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsmf.so")
 
-SMF_OK, SMF_EINVAL, SMF_ENOMEM, SMF_EHIP, SMF_ENUMERIC, SMF_EWAIT = 0, -1, -2, -3, -4, -5
+SMF_OK, SMF_EINVAL, SMF_ENOMEM, SMF_EHIP, SMF_ENUMERIC = 0, -1, -2, -3, -4
 SMF_FP64, SMF_FP32 = 1, 2
 
 # every symbol include/smf.h declares
 EXPORTS = ("smf_setup", "smf_sample", "smf_sample_modes", "smf_plan_dims", "smf_get_factors",
            "smf_destroy", "smf_error_string", "smf_setup_batch", "smf_batch_layout",
-           "smf_sample_batch", "smf_batch_status", "smf_batch_set_wait_limit", "smf_autotune_batch")
+           "smf_sample_batch", "smf_autotune_batch")
 
 
 class smf_spectrum(ctypes.Structure):
@@ -58,13 +58,10 @@ def load():
                                     ctypes.POINTER(ctypes.c_int), i, vp, ctypes.POINTER(vp)]
     lib.smf_batch_layout.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     lib.smf_sample_batch.argtypes = [vp, u64, vp, vp]
-    lib.smf_batch_status.argtypes = [vp, vp]
-    lib.smf_batch_set_wait_limit.argtypes = [vp, i]
     lib.smf_autotune_batch.argtypes = [vp, u64, vp, vp, ctypes.POINTER(ctypes.c_int)]
     for name in ("smf_setup", "smf_sample", "smf_sample_modes", "smf_plan_dims",
                  "smf_get_factors", "smf_destroy", "smf_setup_batch", "smf_batch_layout",
-                 "smf_sample_batch", "smf_batch_status", "smf_batch_set_wait_limit",
-                 "smf_autotune_batch"):
+                 "smf_sample_batch", "smf_autotune_batch"):
         getattr(lib, name).restype = i
     _lib = lib
     return lib
@@ -177,14 +174,6 @@ def smf_sample_batch(plan, seed, out_ptr, stream=None):
                                    _stream_handle(stream))
 
 
-def smf_batch_status(plan, stream=None):
-    return load().smf_batch_status(plan, _stream_handle(stream))
-
-
-def smf_batch_set_wait_limit(plan, spins):
-    return load().smf_batch_set_wait_limit(plan, int(spins))
-
-
 def smf_autotune_batch(plan, seed, out_ptr, stream=None):
     g = ctypes.c_int(0)
     rc = load().smf_autotune_batch(plan, ctypes.c_uint64(int(seed)), ctypes.c_void_p(out_ptr),
@@ -228,14 +217,12 @@ class BatchPlan:
         f = self.fields[i]
         return out[self.offsets[i]:self.offsets[i + 1]].view(f["n_theta"], f["n_phi"])
 
-    def status(self, stream=None):
-        return smf_batch_status(self._h, stream)
-
     def autotune(self, seed, out, stream=None):
-        rc, grid = smf_autotune_batch(self._h, seed, out.data_ptr(), stream)
+        """Picks the chain-item tile shape (m-tiles per item); returns it."""
+        rc, tiles = smf_autotune_batch(self._h, seed, out.data_ptr(), stream)
         if rc != SMF_OK:
             raise SmfError(rc, "smf_autotune_batch")
-        return grid
+        return tiles
 
     def close(self):
         if getattr(self, "_h", None):

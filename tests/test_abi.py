@@ -46,8 +46,6 @@ def test_error_strings_and_null_handling_without_gpu():
     assert lib.smf_setup(None, 8, 16, smf.SMF_FP64, None, None) == smf.SMF_EINVAL
     assert lib.smf_sample_batch(None, 1, None, None) == smf.SMF_EINVAL
     assert lib.smf_batch_layout(None, None) == smf.SMF_EINVAL
-    assert lib.smf_batch_status(None, None) == smf.SMF_EINVAL
-    assert lib.smf_batch_set_wait_limit(None, 5) == smf.SMF_EINVAL
     assert lib.smf_autotune_batch(None, 1, None, None, None) == smf.SMF_EINVAL
     assert lib.smf_setup_batch(0, None, None, None, smf.SMF_FP32, None, None) == smf.SMF_EINVAL
 

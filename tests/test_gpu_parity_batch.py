@@ -1,7 +1,6 @@
-"""GPU tests of the batched persistent launch: every field of a mixed batch against the
-same field sampled alone (same kernels' arithmetic, so equal to FP32 rounding) and against
-the FP64 oracle (1e-4), HIP-graph capture and replay, the autotuner, and the wait error
-path forced from the host."""
+"""GPU tests of the batched form: every field of a mixed batch against the same field
+sampled alone (same device arithmetic, so equal to FP32 rounding) and against the FP64
+oracle (1e-4), HIP-graph capture and replay, and the tile-shape autotuner."""
 import numpy as np
 import pytest
 
@@ -40,7 +39,6 @@ def test_batch_matches_single_plans_and_oracle():
     fields = _mixed_fields()
     bp = BatchPlan(fields)
     out = bp.sample(40)
-    assert bp.status() == 0
     for i, f in enumerate(fields):
         Tb = bp.field(out, i).double().cpu().numpy()
         Ts = _single(f, 40 + i)
@@ -55,8 +53,8 @@ def test_batch_matches_single_plans_and_oracle():
 
 
 def test_batch_graph_capture_replays():
-    """One graph holds the counter reset and the persistent launch; every replay, with
-    eager work and synchronisations between replays, equals the eager result."""
+    """One graph holds both launches; every replay, with eager work and synchronisations
+    between replays, equals the eager result."""
     from paper_1709_10314_amd import BatchPlan
 
     fields = _mixed_fields()[:6]
@@ -77,8 +75,7 @@ def test_batch_graph_capture_replays():
         junk = torch.randn(1 << 20, device="cuda").sum()   # eager work between replays
         g.replay()
         torch.cuda.synchronize()
-        assert bp.status() == 0
-        assert torch.equal(out, eager), rep
+            assert torch.equal(out, eager), rep
         del junk
     bp.close()
 
@@ -90,31 +87,12 @@ def test_batch_autotune_keeps_results():
     bp = BatchPlan(fields)
     ref = bp.sample(3).clone()
     out = bp.empty()
-    grid = bp.autotune(3, out)
-    log(f"autotuned grid {grid}")
-    assert grid > 0
+    tiles = bp.autotune(3, out)
+    log(f"autotuned m-tiles per chain item: {tiles}")
+    assert tiles in (1, 2, 4)
     out2 = bp.sample(3)
     torch.cuda.synchronize()
     assert torch.equal(out2, ref)
-    bp.close()
-
-
-def test_batch_wait_error_path_forced_from_host():
-    """A wait limit of -1 makes every FFT item skip its wait and flag SMF_EWAIT; the kernel
-    still exits normally, and the default limit restores correct output."""
-    from paper_1709_10314_amd import BatchPlan, smf
-
-    fields = _mixed_fields()[:4]
-    bp = BatchPlan(fields)
-    ref = bp.sample(5).clone()
-    assert smf.smf_batch_set_wait_limit(bp.handle, -1) == smf.SMF_OK
-    bp.sample(5)
-    assert bp.status() == smf.SMF_EWAIT
-    assert smf.smf_batch_set_wait_limit(bp.handle, 1 << 22) == smf.SMF_OK
-    out = bp.sample(5)
-    assert bp.status() == smf.SMF_OK
-    assert torch.equal(out, ref)
-    assert smf.smf_batch_set_wait_limit(bp.handle, -2) == smf.SMF_EINVAL
     bp.close()
 
 
@@ -147,7 +125,6 @@ def test_mixed_256_field_workload_sampled():
     log("setup 256 fields")
     bp = BatchPlan(fields)
     out = bp.sample(1)
-    assert bp.status() == 0
     pts = bp.offsets[-1]
     log(f"{pts} points")
     for i in (0, 1, 17, 64, 128, 200, 254, 255):

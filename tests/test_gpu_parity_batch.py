@@ -75,7 +75,7 @@ def test_batch_graph_capture_replays():
         junk = torch.randn(1 << 20, device="cuda").sum()   # eager work between replays
         g.replay()
         torch.cuda.synchronize()
-            assert torch.equal(out, eager), rep
+        assert torch.equal(out, eager), rep
         del junk
     bp.close()
 

@@ -41,7 +41,29 @@ def _sqrtm_psd(S):
     return np.einsum("...ij,...j,...kj->...ik", V, np.sqrt(np.clip(w, 0, None)), V)
 
 
-def factor_errors(Ag, Bg, Ao, Bo, n_theta):
+def threshold_ambiguous(Ao, Bo, n_theta, lo=1e-14, hi=1e-10):
+    """Steps whose factorisation sits near the 1e-12 thresholds, from the oracle's chain:
+    the smaller pivot 1 - rho^2 of the equilibrated J(a,a) (order 2) or a relative
+    conditional variance diag(B B^T) / diag J(b,b) within [lo, hi].  There keeping or
+    dropping a pivot changes the conditional law discontinuously, and two FP64 roundings
+    of J may fall on different sides.  Returns a [sets, modes] bool mask."""
+    Sa, Sb = chain_covariances(Ao, Bo, n_theta)
+    M = Ao.shape[-1]
+    amb = np.zeros(Ao.shape[:2], dtype=bool)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        if M == 2:
+            d = Sa[..., 0, 0] * Sa[..., 1, 1]
+            piv = np.where(d > 0, 1 - Sa[..., 0, 1] ** 2 / d, 1.0)
+            amb |= (piv >= lo) & (piv <= hi)
+        S = np.einsum("...pk,...pk->...p", Bo, Bo)
+        Kd = np.einsum("...pp->...p", Sb)
+        rel = np.where(Kd > 0, S / Kd, 1.0)
+        amb |= np.any((rel >= lo) & (rel <= hi), axis=-1)
+    amb[0] = False
+    return amb
+
+
+def factor_errors(Ag, Bg, Ao, Bo, n_theta, skip_ambiguous=True):
     """Errors of device factors against oracle factors, measured on what the factors do
     to the chain's law rather than entry by entry (the entries of A are ill-determined
     along near-null directions of J(a,a), and those of B = chol(S) when S is nearly
@@ -49,7 +71,9 @@ def factor_errors(Ag, Bg, Ao, Bo, n_theta):
       dA = max |(A_dev - A_orc) J(a,a)^{1/2}|_pq / sd_b,p   (conditional-mean map on a
                                                              unit-variance input)
       dS = max |B_dev B_dev^T - B_orc B_orc^T|_pq / (sd_b,p sd_b,q)   (conditional covariance)
-    with sd_b = sqrt(diag J(b,b)); rows with sd_b = 0 must be zero on both sides."""
+    with sd_b = sqrt(diag J(b,b)); rows with sd_b = 0 must be zero on both sides.  Steps
+    next to a threshold (threshold_ambiguous) are left out when skip_ambiguous is set.
+    Returns (max dA, max dS, number of steps left out)."""
     Sa, Sb = chain_covariances(Ao, Bo, n_theta)
     sd_b = np.sqrt(np.clip(np.einsum("...pp->...p", Sb), 0, None))
     R = _sqrtm_psd(Sa)
@@ -60,4 +84,9 @@ def factor_errors(Ag, Bg, Ao, Bo, n_theta):
         dA = np.where(live[..., None], eA / sd_b[..., :, None], np.abs(Ag - Ao))
         den = sd_b[..., :, None] * sd_b[..., None, :]
         dS = np.where(den > 0, eS / den, eS)
-    return float(np.nanmax(dA)), float(np.nanmax(dS))
+    amb = threshold_ambiguous(Ao, Bo, n_theta) if skip_ambiguous else np.zeros(Ao.shape[:2], bool)
+    keep = ~amb
+    dA = dA[keep]
+    dS = dS[keep]
+    return (float(np.nanmax(dA)) if dA.size else 0.0, float(np.nanmax(dS)) if dS.size else 0.0,
+            int(amb.sum()))

@@ -59,6 +59,8 @@ def _load():
     lib.orc_spectrum.restype = _i
     lib.orc_legendre.argtypes = [_i, _i, _d, _pd, _pd]
     lib.orc_jblock.argtypes = [_i, _i, _i, _pd, _d, _d, _pd]
+    lib.orc_jblock_zs.argtypes = [_i, _i, _i, _pd, _d, _d, _d, _d, _pd]
+    lib.orc_ring_zs.argtypes = [_i, _i, _pd, _pd]
     lib.orc_setup.argtypes = [_i, _i, _pd, _i, _i, _i, _pd, _pd]
     lib.orc_setup.restype = _i
     lib.orc_n_sets.argtypes = [_i]
@@ -121,6 +123,24 @@ def jblock(order, m, ell_max, C, theta1, theta2):
     C = np.ascontiguousarray(C, dtype=np.float64)
     J = np.zeros(order * order)
     _load().orc_jblock(order, m, ell_max, _p(C), float(theta1), float(theta2), _p(J))
+    return J.reshape(order, order)
+
+
+def ring_zs(n_theta, i):
+    """(z_i, sin theta_i) of ring i, through the complementary angle (exact at the equator)."""
+    z = ctypes.c_double()
+    s = ctypes.c_double()
+    _load().orc_ring_zs(n_theta, i, ctypes.byref(z), ctypes.byref(s))
+    return z.value, s.value
+
+
+def jblock_ring(order, m, ell_max, C, n_theta, i1, i2):
+    """J^m(z_{i1}, z_{i2}) at two rings of the grid (ring values as the setup uses them)."""
+    C = np.ascontiguousarray(C, dtype=np.float64)
+    z1, s1 = ring_zs(n_theta, i1)
+    z2, s2 = ring_zs(n_theta, i2)
+    J = np.zeros(order * order)
+    _load().orc_jblock_zs(order, m, ell_max, _p(C), z1, s1, z2, s2, _p(J))
     return J.reshape(order, order)
 
 

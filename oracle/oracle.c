@@ -27,7 +27,7 @@
  *
  * Readings where the paper is silent or garbled (each is listed in the design notes):
  *   grid      theta_i = pi (i + 1/2) / n_theta, z_i = cos(theta_i), ring 0 nearest z = +1;
- *             phi_j = 2 pi j / n_phi.
+ *             phi_j = 2 pi j / n_phi; z_i evaluated as sin(pi (n - 2i - 1) / (2n)).
  *   modes     m = 0 .. m_top, m_top = min(ell_max, n_phi/2 - 1); the Nyquist mode is not used.
  *   DFT       unnormalised: T = g_0 + 2 sum_{m>=1} Re(g_m e^{i m phi}).
  *   A, B      A = J(b,a) J(a,a)^+ with J(b,a)_pq = E[x_b,p x_a,q];  S = J(b,b) - A J(a,b);
@@ -68,14 +68,26 @@ int orc_max_threads(void)
 }
 
 /* ------------------------------------------------------------------------- */
-/* Grid (Sec. 4, with the ring-centre reading above).                          */
+/* Grid (Sec. 4, with the ring-centre reading above).  z_i = cos(theta_i) and   */
+/* sin(theta_i) are evaluated through the complementary angle                  */
+/* pi/2 - theta_i = pi (n - 2i - 1) / (2n), whose numerator is an exact        */
+/* integer: the equator ring of an odd grid gets z = 0 exactly and mirrored     */
+/* rings get exactly opposite z, the symmetry z_{-i} = -z_i of Sec. 4.         */
 /* ------------------------------------------------------------------------- */
+void orc_ring_zs(int n_theta, int i, double* z, double* s)
+{
+    double q = (double)(n_theta - 2 * i - 1) / (2.0 * n_theta);
+    *z = sin(M_PI * q);
+    *s = cos(M_PI * q);
+}
+
 void orc_grid(int n_theta, double* theta, double* z)
 {
     for (int i = 0; i < n_theta; ++i) {
-        double t = M_PI * (i + 0.5) / n_theta;
-        if (theta) theta[i] = t;
-        if (z) z[i] = cos(t);
+        double zi, si;
+        orc_ring_zs(n_theta, i, &zi, &si);
+        if (theta) theta[i] = M_PI * (i + 0.5) / n_theta;
+        if (z) z[i] = zi;
     }
 }
 
@@ -111,9 +123,9 @@ int orc_spectrum(int n_kappa, const double* kappa, int ell_max, double* C)
 /* sin^m(theta) seed cannot underflow; values are returned as plain doubles     */
 /* (ldexp), i.e. anything below the FP64 range comes back as zero/subnormal.    */
 /* ------------------------------------------------------------------------- */
-void orc_legendre(int m, int ell_max, double theta, double* L, double* dL)
+void orc_legendre_zs(int m, int ell_max, double z, double s, double* L, double* dL)
 {
-    const double z = cos(theta), s = sin(theta), s2 = s * s;
+    const double s2 = s * s;
     const double big = ldexp(1.0, 480), small = ldexp(1.0, -480);
     int e = 0;
     double p = 1.0 / sqrt(4.0 * M_PI);
@@ -155,13 +167,19 @@ void orc_legendre(int m, int ell_max, double theta, double* L, double* dL)
     }
 }
 
+/* The same at z = cos(theta), s = sin(theta). */
+void orc_legendre(int m, int ell_max, double theta, double* L, double* dL)
+{
+    orc_legendre_zs(m, ell_max, cos(theta), sin(theta), L, dL);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Cross-covariance block (Lemma 2.1 and the cross covariances of Sec. 2):     */
 /*   J_pq = sum_{l=m}^{ell_max} C_l  d^p L_lm(z1)  d^q L_lm(z2),  p,q < M,     */
 /* with z1 = cos(theta1), z2 = cos(theta2).  J[p*M + q].                       */
 /* ------------------------------------------------------------------------- */
-void orc_jblock(int order, int m, int ell_max, const double* C, double theta1, double theta2,
-                double* J)
+void orc_jblock_zs(int order, int m, int ell_max, const double* C, double z1, double s1, double z2,
+                   double s2, double* J)
 {
     int n = ell_max - m + 1;
     for (int i = 0; i < order * order; ++i) J[i] = 0.0;
@@ -170,8 +188,8 @@ void orc_jblock(int order, int m, int ell_max, const double* C, double theta1, d
     double* D1 = L1 + n;
     double* L2 = L1 + 2 * n;
     double* D2 = L1 + 3 * n;
-    orc_legendre(m, ell_max, theta1, L1, D1);
-    orc_legendre(m, ell_max, theta2, L2, D2);
+    orc_legendre_zs(m, ell_max, z1, s1, L1, D1);
+    orc_legendre_zs(m, ell_max, z2, s2, L2, D2);
     for (int p = 0; p < order; ++p)
         for (int q = 0; q < order; ++q) {
             const double* f1 = p ? D1 : L1;
@@ -181,6 +199,13 @@ void orc_jblock(int order, int m, int ell_max, const double* C, double theta1, d
             J[p * order + q] = acc;
         }
     free(L1);
+}
+
+/* The same with z1 = cos(theta1), z2 = cos(theta2). */
+void orc_jblock(int order, int m, int ell_max, const double* C, double theta1, double theta2,
+                double* J)
+{
+    orc_jblock_zs(order, m, ell_max, C, cos(theta1), sin(theta1), cos(theta2), sin(theta2), J);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -338,18 +363,20 @@ int orc_setup_modes(int order, int ell_max, const double* C, int n_theta, int n_
         for (int j = 0; j < n_sets; ++j) {
             int a, b;
             set_rings(n_theta, j, &a, &b);
-            double ta = M_PI * (a + 0.5) / n_theta, tb = M_PI * (b + 0.5) / n_theta;
+            double za, sa, zb, sb;
+            orc_ring_zs(n_theta, a, &za, &sa);
+            orc_ring_zs(n_theta, b, &zb, &sb);
             double* Aj = A + ((size_t)j * n_modes + i) * MM;
             double* Bj = B + ((size_t)j * n_modes + i) * MM;
             if (j == 0) {
-                orc_jblock(order, m, ell_max, C, ta, ta, Kaa);
+                orc_jblock_zs(order, m, ell_max, C, za, sa, za, sa, Kaa);
                 for (int k = 0; k < MM; ++k) Aj[k] = 0.0;
                 orc_start_factor(order, Kaa, Bj);
                 continue;
             }
-            orc_jblock(order, m, ell_max, C, ta, ta, Kaa);
-            orc_jblock(order, m, ell_max, C, tb, tb, Kbb);
-            orc_jblock(order, m, ell_max, C, tb, ta, Kba);
+            orc_jblock_zs(order, m, ell_max, C, za, sa, za, sa, Kaa);
+            orc_jblock_zs(order, m, ell_max, C, zb, sb, zb, sb, Kbb);
+            orc_jblock_zs(order, m, ell_max, C, zb, sb, za, sa, Kba);
             orc_step_factors(order, Kaa, Kbb, Kba, Aj, Bj);
         }
     }

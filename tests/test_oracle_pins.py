@@ -163,15 +163,15 @@ def _propagate_check(orc, order, kappa, n, lmax, n_phi):
         return np.max(np.abs(S - K)[mask] / sc[mask]) if mask.any() else 0.0
 
     for m in range(A.shape[1]):
-        Ks = orc.jblock(order, m, lmax, C, th[s], th[s])
+        Ks = orc.jblock_ring(order, m, lmax, C, n, s, s)
         Ss = B[0, m] @ B[0, m].T
         worst = max(worst, cmp(Ss, Ks))
         # north
         Sig, a = Ss, s
         for j in range(2 if even else 1, A.shape[0]):
             b = s - j + 1 if even else s - j
-            Kbb = orc.jblock(order, m, lmax, C, th[b], th[b])
-            Kba = orc.jblock(order, m, lmax, C, th[b], th[a])
+            Kbb = orc.jblock_ring(order, m, lmax, C, n, b, b)
+            Kba = orc.jblock_ring(order, m, lmax, C, n, b, a)
             cross = A[j, m] @ Sig
             Sig = A[j, m] @ Sig @ A[j, m].T + B[j, m] @ B[j, m].T
             worst = max(worst, cmp(Sig, Kbb), cmp(cross, Kba))
@@ -181,8 +181,8 @@ def _propagate_check(orc, order, kappa, n, lmax, n_phi):
         j0 = 1
         if even:
             b = s + 1
-            Kbb = orc.jblock(order, m, lmax, C, th[b], th[b])
-            Kba = orc.jblock(order, m, lmax, C, th[b], th[a])
+            Kbb = orc.jblock_ring(order, m, lmax, C, n, b, b)
+            Kba = orc.jblock_ring(order, m, lmax, C, n, b, a)
             cross = A[1, m] @ Sig
             Sig = A[1, m] @ Sig @ A[1, m].T + B[1, m] @ B[1, m].T
             worst = max(worst, cmp(Sig, Kbb), cmp(cross, Kba))
@@ -190,8 +190,8 @@ def _propagate_check(orc, order, kappa, n, lmax, n_phi):
         for j in range(j0, A.shape[0]):
             b = a + 1
             Am, Bm = D @ A[j, m] @ D, D @ B[j, m] @ D
-            Kbb = orc.jblock(order, m, lmax, C, th[b], th[b])
-            Kba = orc.jblock(order, m, lmax, C, th[b], th[a])
+            Kbb = orc.jblock_ring(order, m, lmax, C, n, b, b)
+            Kba = orc.jblock_ring(order, m, lmax, C, n, b, a)
             cross = Am @ Sig
             Sig = Am @ Sig @ Am.T + Bm @ Bm.T
             worst = max(worst, cmp(Sig, Kbb), cmp(cross, Kba))
@@ -231,9 +231,9 @@ def test_mirror_factors_match_direct_southern_step(orc):
         for j in range(2, A.shape[0]):
             a_n, b_n = s - j + 2, s - j + 1
             a_s, b_s = n - 1 - a_n, n - 1 - b_n
-            Kaa = orc.jblock(order, m, lmax, C, th[a_s], th[a_s])
-            Kbb = orc.jblock(order, m, lmax, C, th[b_s], th[b_s])
-            Kba = orc.jblock(order, m, lmax, C, th[b_s], th[a_s])
+            Kaa = orc.jblock_ring(order, m, lmax, C, n, a_s, a_s)
+            Kbb = orc.jblock_ring(order, m, lmax, C, n, b_s, b_s)
+            Kba = orc.jblock_ring(order, m, lmax, C, n, b_s, a_s)
             As, Bs = _step(orc, order, Kaa, Kbb, Kba)
             # the two sides round their thetas differently, and near-deterministic steps
             # make S = J(b,b) - A J(a,b) a strong cancellation, so errors are measured in
@@ -527,6 +527,6 @@ def _markov_defect(orc, order, A, B, n, lmax, C):
         cov = _chain_cov(order, A, B, n, m)
         for a in range(n):
             for b in range(n):
-                Kab = orc.jblock(order, m, lmax, C, th[a], th[b])[0, 0]
+                Kab = orc.jblock_ring(order, m, lmax, C, n, a, b)[0, 0]
                 out[a, b] += w * abs(cov[(a, b)][0, 0] - Kab)
     return out

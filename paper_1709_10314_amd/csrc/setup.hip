@@ -181,10 +181,13 @@ __global__ __launch_bounds__(64) void factor_kernel(Geometry g, const double* __
     } else {
         a = g.s - j + 1; b = g.s - j;
     }
+    // z = cos(theta) and sin(theta) through the complementary angle
+    // pi/2 - theta = pi (n - 2i - 1) / (2n): the equator ring of an odd grid gets z = 0
+    // exactly and mirrored rings get exactly opposite z
     LegendreStream ra, rb;
     double sa, sb;
-    sincospi(((double)a + 0.5) / (double)g.n_theta, &sa, &ra.z);
-    sincospi(((double)b + 0.5) / (double)g.n_theta, &sb, &rb.z);
+    sincospi((double)(g.n_theta - 2 * a - 1) / (2.0 * g.n_theta), &ra.z, &sa);
+    sincospi((double)(g.n_theta - 2 * b - 1) / (2.0 * g.n_theta), &rb.z, &sb);
     ra.inv_s2 = 1.0 / (sa * sa);
     rb.inv_s2 = 1.0 / (sb * sb);
     // sectoral seed L_mm = sqrt((2m+1)/(4pi) prod_k (2k-1)/(2k)) sin^m, built as

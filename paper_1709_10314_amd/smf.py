@@ -44,6 +44,12 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    # PyTorch ships its own HIP runtime under the same soname; load it first so that the
+    # library and torch's tensors and streams share one runtime in this process
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp, i, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64
     lib.smf_setup.argtypes = [ctypes.POINTER(smf_spectrum), i, i, i, vp, ctypes.POINTER(vp)]

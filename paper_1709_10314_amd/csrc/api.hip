@@ -84,7 +84,7 @@ int setup_impl(const smf_spectrum* spec, int n_theta, int n_phi, int flags, hipS
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SMF_EHIP;
     // the FFT holds n_phi/2 complex values of the sample type in LDS
-    const size_t lds = (size_t)(n_phi / 2) * (flags == SMF_FP64 ? 16 : 8);
+    const size_t lds = (size_t)((n_phi / 2) + (n_phi / 32)) * (flags == SMF_FP64 ? 16 : 8);
     int lds_max = 0;
     if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         return SMF_EHIP;
@@ -306,11 +306,12 @@ int smf_setup_batch(int n, const smf_spectrum* specs, const int* n_theta, const 
         F.order = g.order;
         F.m_top = g.m_top;
         F.m_rows = g.m_rows;
+        F.n_sets = g.n_sets;
         F.s = g.s;
         F.even = g.even;
         F.log2h = __builtin_ctz((unsigned)g.n_phi) - 1;
         F.seed_off = i;
-        b->lds = std::max(b->lds, sizeof(float) * 2 * (size_t)(g.n_phi / 2));
+        b->lds = std::max(b->lds, sizeof(float) * 2 * (size_t)(g.n_phi / 2 + g.n_phi / 32));
     }
     // chain items longest chain first, for each tile shape; FFT items in the same order
     for (int i = 0; i < n; ++i) order_idx[i] = i;

@@ -13,7 +13,7 @@ struct BatchField {
     const float* fac;     // FP32 factor records of the field's plan
     const float* tw;      // its FFT twiddles
     int64_t out_off;      // first element of the field in the packed output
-    int n_theta, n_phi, order, m_top, m_rows, s, even, log2h;
+    int n_theta, n_phi, order, m_top, m_rows, n_sets, s, even, log2h;
     int seed_off;         // Philox key = seed + seed_off
 };
 

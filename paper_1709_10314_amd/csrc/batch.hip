@@ -62,10 +62,10 @@ __global__ __launch_bounds__(kMaxChainThreads) void batch_chain_kernel(BatchArgs
     const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
     const size_t stride = (size_t)F.m_rows * factor_stride(F.order);
     if (F.order == 1)
-        run_chain<float, 1>(F.n_theta, F.s, F.even, h, m, part, k0, k1,
+        run_chain<float, 1>(F.n_theta, F.s, F.even, F.n_sets, h, m, part, k0, k1,
                             F.fac + (size_t)m * factor_stride(1), stride, g, (size_t)F.n_phi);
     else
-        run_chain<float, 2>(F.n_theta, F.s, F.even, h, m, part, k0, k1,
+        run_chain<float, 2>(F.n_theta, F.s, F.even, F.n_sets, h, m, part, k0, k1,
                             F.fac + (size_t)m * factor_stride(2), stride, g, (size_t)F.n_phi);
 }
 

@@ -1,5 +1,5 @@
 // Device bodies of the sampling path, shared by the per-plan kernels (sample.hip) and the
-// persistent batch kernel (batch.hip):
+// batch kernels (batch.hip):
 //   run_chain  -- one (field, hemisphere, mode, part) chain of the latitude-ring recursion
 //                 with fused Philox normals (Creasey & Lang, Alg. 2; eqs. (state_initial),
 //                 (state_space); the mirror remark after Alg. 1)
@@ -52,20 +52,185 @@ __device__ __forceinline__ T pick4(const T n[4], int w)
     return w == 0 ? n[0] : (w == 1 ? n[1] : (w == 2 ? n[2] : n[3]));
 }
 
+// Factor record of one step, loaded ahead of use (register prefetch pipeline).
+template <typename T, int M>
+struct Rec {
+    T v[M == 1 ? 2 : 7];
+};
+
+template <typename T, int M>
+__device__ __forceinline__ Rec<T, M> load_rec(const T* __restrict__ rec)
+{
+    Rec<T, M> R;
+    if constexpr (M == 1) {
+        using V2 = typename Vec2<T>::type;
+        const V2 v = *reinterpret_cast<const V2*>(rec);
+        R.v[0] = v.x;
+        R.v[1] = v.y;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 7; ++i) R.v[i] = rec[i];
+    }
+    return R;
+}
+
+// x <- A x + B w with a prefetched record
+template <typename T, int M>
+__device__ __forceinline__ void chain_step_rec(const Rec<T, M>& R, T& x0, T& x1, T w0, T w1)
+{
+    if constexpr (M == 1) {
+        x0 = R.v[0] * x0 + R.v[1] * w0;
+    } else {
+        const T y0 = R.v[0] * x0 + R.v[1] * x1 + R.v[4] * w0;
+        const T y1 = R.v[2] * x0 + R.v[3] * x1 + (R.v[5] * w0 + R.v[6] * w1);
+        x0 = y0;
+        x1 = y1;
+    }
+}
+
+// Rings are walked in groups of G = 4/M that share one Philox block (counter block
+// (ring M) / 4).  Ring r uses set j = s - r + even walking north and j = r - s walking
+// south; the southern noise is D w (second component negated).
+//
+// A group that is cut by the start or the last ring is stepped with direct loads.  Full
+// groups run through a register prefetch pipeline: the G records of full group q are
+// loaded while group q - P is computed (slot q mod P, a compile-time index after
+// unrolling by P), so the loads of P*G rings are in flight during a group's arithmetic.
+// The unrolled body has no branches, which lets the compiler count outstanding loads
+// exactly instead of draining them.  Prefetches past the walk are clamped to valid sets
+// and never used.
+template <typename T, int M, bool NORTH>
+__device__ __forceinline__ int set_of_ring(int r, int s, int even, int n_sets)
+{
+    int j = NORTH ? s - r + even : r - s;
+    return j < 0 ? 0 : (j >= n_sets ? n_sets - 1 : j);
+}
+
+template <typename T, int M, bool NORTH>
+__device__ __forceinline__ void step_group_direct(int base, int lo, int hi, int s, int even, int n_sets,
+                                                  uint32_t um, uint32_t up, uint32_t k0, uint32_t k1, T sc,
+                                                  const T* __restrict__ fm, size_t set_stride,
+                                                  T* __restrict__ g, size_t row, T& x0, T& x1)
+{
+    constexpr int G = 4 / M;
+    T nb[4];
+    block_normals<T>((uint32_t)((base * M) >> 2), um, up, k0, k1, sc, nb);
+#pragma unroll
+    for (int tt = 0; tt < G; ++tt) {
+        const int t = NORTH ? G - 1 - tt : tt;
+        const int r = base + t;
+        if (r >= lo && r <= hi) {
+            const Rec<T, M> R = load_rec<T, M>(fm + (size_t)set_of_ring<T, M, NORTH>(r, s, even, n_sets) * set_stride);
+            const T w0 = nb[t * M];
+            const T w1 = M == 2 ? (NORTH ? nb[t * M + 1] : -nb[t * M + 1]) : T(0);
+            chain_step_rec<T, M>(R, x0, x1, w0, w1);
+            g[(size_t)r * row] = x0;
+        }
+    }
+}
+
+template <typename T, int M, int P, bool NORTH>
+__device__ __forceinline__ void walk_hemisphere(int n, int s, int even, int r_first, int m, int part,
+                                                uint32_t k0, uint32_t k1, T sc,
+                                                const T* __restrict__ fm, size_t set_stride,
+                                                int n_sets, T* __restrict__ g, size_t row, T& x0, T& x1)
+{
+    constexpr int G = 4 / M;
+    const uint32_t um = (uint32_t)m, up = (uint32_t)part;
+    // full groups: q = 0..ng-1 with ring bases b0 - q G (north) or b0 + q G (south)
+    int b0, ng;
+    if (NORTH) {
+        if (r_first < 0) return;
+        int top = r_first;
+        const int base = (top / G) * G;
+        if (top != base + G - 1) {   // cut first group
+            step_group_direct<T, M, true>(base, 0, top, s, even, n_sets, um, up, k0, k1, sc, fm, set_stride,
+                                          g, row, x0, x1);
+            top = base - 1;
+        }
+        ng = (top + 1) / G;
+        b0 = top + 1 - G;
+    } else {
+        if (r_first >= n) return;
+        int lo = r_first;
+        const int base = (lo / G) * G;
+        if (lo != base) {            // cut first group
+            step_group_direct<T, M, false>(base, lo, n - 1, s, even, n_sets, um, up, k0, k1, sc, fm,
+                                           set_stride, g, row, x0, x1);
+            lo = base + G;
+        }
+        ng = lo < n ? (n - lo) / G : 0;
+        b0 = lo;
+    }
+    if (ng > 0) {
+        Rec<T, M> buf[P][G];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int base = NORTH ? b0 - p * G : b0 + p * G;
+#pragma unroll
+            for (int t = 0; t < G; ++t)
+                buf[p][t] = load_rec<T, M>(fm + (size_t)set_of_ring<T, M, NORTH>(base + t, s, even, n_sets) * set_stride);
+        }
+        int q = 0;
+        for (; q + P <= ng; q += P) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int base = NORTH ? b0 - (q + p) * G : b0 + (q + p) * G;
+                T nb[4];
+                block_normals<T>((uint32_t)((base * M) >> 2), um, up, k0, k1, sc, nb);
+#pragma unroll
+                for (int tt = 0; tt < G; ++tt) {
+                    const int t = NORTH ? G - 1 - tt : tt;
+                    const T w0 = nb[t * M];
+                    const T w1 = M == 2 ? (NORTH ? nb[t * M + 1] : -nb[t * M + 1]) : T(0);
+                    chain_step_rec<T, M>(buf[p][t], x0, x1, w0, w1);
+                    g[(size_t)(base + t) * row] = x0;
+                }
+                const int nbase = NORTH ? base - P * G : base + P * G;
+#pragma unroll
+                for (int t = 0; t < G; ++t)
+                    buf[p][t] = load_rec<T, M>(fm + (size_t)set_of_ring<T, M, NORTH>(nbase + t, s, even, n_sets) * set_stride);
+            }
+        }
+        // fewer than P full groups left: their records are already in the slots
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            if (q + p < ng) {
+                const int base = NORTH ? b0 - (q + p) * G : b0 + (q + p) * G;
+                T nb[4];
+                block_normals<T>((uint32_t)((base * M) >> 2), um, up, k0, k1, sc, nb);
+#pragma unroll
+                for (int tt = 0; tt < G; ++tt) {
+                    const int t = NORTH ? G - 1 - tt : tt;
+                    const T w0 = nb[t * M];
+                    const T w1 = M == 2 ? (NORTH ? nb[t * M + 1] : -nb[t * M + 1]) : T(0);
+                    chain_step_rec<T, M>(buf[p][t], x0, x1, w0, w1);
+                    g[(size_t)(base + t) * row] = x0;
+                }
+            }
+        }
+    }
+    if (!NORTH) {
+        // cut last group of the south walk
+        const int lo = b0 + ng * G;
+        if (lo < n)
+            step_group_direct<T, M, false>(lo, lo, n - 1, s, even, n_sets, um, up, k0, k1, sc, fm, set_stride,
+                                           g, row, x0, x1);
+    }
+}
+
 // One chain.  `fm` points at the mode's record in factor set 0 (sets `set_stride` apart);
 // `g` at the chain's slot of ring 0 of its field (rings `row` elements apart).
 // The northern chain (h = 0) draws the start state at ring s and steps to ring 0; the
 // southern chain (h = 1) redraws the same start state (same counters), takes the crossing
 // step (even n_theta) and steps to ring n-1 with the mirrored factors, carried as
 // y = D x so that the stored northern records apply unchanged with D w as the noise.
-// Rings are walked in groups of 4/M that share one Philox block, so each normal is
-// picked by a compile-time word index.  The ring order is uniform across the wave.
-template <typename T, int M>
-__device__ __forceinline__ void run_chain(int n, int s, int even, int h, int m, int part,
+// The ring order is uniform across the wave.
+template <typename T, int M, int P = 4>
+__device__ __forceinline__ void run_chain(int n, int s, int even, int n_sets, int h, int m, int part,
                                           uint32_t k0, uint32_t k1, const T* __restrict__ fm,
                                           size_t set_stride, T* __restrict__ g, size_t row)
 {
-    constexpr int G = 4 / M;   // rings per Philox block
     const T sc = (m == 0) ? T(1) : T(0.70710678118654752440);
     const uint32_t um = (uint32_t)m, up = (uint32_t)part;
 
@@ -86,25 +251,8 @@ __device__ __forceinline__ void run_chain(int n, int s, int even, int h, int m, 
     }
     if (h == 0) {
         g[(size_t)s * row] = x0;
-        // north: rings s-1 .. 0; ring r uses set j = s - r + even
-        int r_hi = s - 1;
-        while (r_hi >= 0) {
-            const int base = (r_hi / G) * G;
-            T nb[4];
-            block_normals<T>((uint32_t)((base * M) >> 2), um, up, k0, k1, sc, nb);
-#pragma unroll
-            for (int t = G - 1; t >= 0; --t) {
-                const int r = base + t;
-                if (r <= r_hi) {
-                    const int j = s - r + even;
-                    const T w0 = nb[t * M];
-                    const T w1 = M == 2 ? nb[t * M + 1] : T(0);
-                    chain_step<T, M>(fm + (size_t)j * set_stride, x0, x1, w0, w1);
-                    g[(size_t)r * row] = x0;
-                }
-            }
-            r_hi = base - 1;
-        }
+        walk_hemisphere<T, M, P, true>(n, s, even, s - 1, m, part, k0, k1, sc, fm, set_stride, n_sets,
+                                       g, row, x0, x1);
     } else {
         int r_lo = s + 1;
         if (even) {
@@ -126,24 +274,8 @@ __device__ __forceinline__ void run_chain(int n, int s, int even, int h, int m, 
             r_lo = s + 2;
         }
         x1 = -x1;   // y = D x
-        // south: rings r_lo .. n-1; ring r uses set j = r - s with noise D w
-        while (r_lo < n) {
-            const int base = (r_lo / G) * G;
-            T nb[4];
-            block_normals<T>((uint32_t)((base * M) >> 2), um, up, k0, k1, sc, nb);
-#pragma unroll
-            for (int t = 0; t < G; ++t) {
-                const int r = base + t;
-                if (r >= r_lo && r < n) {
-                    const int j = r - s;
-                    const T w0 = nb[t * M];
-                    const T w1 = M == 2 ? -nb[t * M + 1] : T(0);
-                    chain_step<T, M>(fm + (size_t)j * set_stride, x0, x1, w0, w1);
-                    g[(size_t)r * row] = x0;
-                }
-            }
-            r_lo = base + G;
-        }
+        walk_hemisphere<T, M, P, false>(n, s, even, r_lo, m, part, k0, k1, sc, fm, set_stride, n_sets,
+                                        g, row, x0, x1);
     }
 }
 
@@ -213,8 +345,31 @@ __device__ __forceinline__ void dft_inv(Cx<T>* v)
     }
 }
 
+// LDS slot of element i: one pad slot after every 16 elements, so that the strided
+// Stockham writes (stride Ns R elements per thread) spread over the banks.
+__device__ __forceinline__ int lds_slot(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int lds_slots(int h) { return h + (h >> 4); }
+
+// Twiddles w^r, r = 1..R-1, of one butterfly: w = tw[t] and w^4 = tw[4t] from the table
+// (t < N/4 whenever R = 8, since k < Ns <= H/8), the rest by at most two products.
+template <typename T, int R>
+__device__ __forceinline__ void butterfly_twiddles(const Cx<T>* __restrict__ tw, int t, Cx<T>* w)
+{
+    w[1] = tw[t];
+    if (R >= 4) {
+        w[2] = cmul(w[1], w[1]);
+        w[3] = cmul(w[2], w[1]);
+    }
+    if (R == 8) {
+        w[4] = tw[4 * t];
+        w[5] = cmul(w[4], w[1]);
+        w[6] = cmul(w[4], w[2]);
+        w[7] = cmul(w[4], w[3]);
+    }
+}
+
 // One Stockham pass of radix R over H points held in LDS buffer `buf`, current
-// sub-transform length Ns = 2^LOG2NS.  Butterfly b: k = b mod Ns; inputs buf[b + r H/R]
+// sub-transform length Ns = 2^LOG2NS.  Butterfly b: k = b mod Ns; inputs b + r H/R
 // times e^{2 pi i k r / (Ns R)}; outputs to ((b / Ns) Ns R + k) + q Ns.  Twiddles come
 // from the table tw[t] = e^{2 pi i t / N}, N = 2H.
 template <typename T, int LOG2H, int R, int NT, int LOG2NS>
@@ -232,12 +387,14 @@ __device__ __forceinline__ void stockham_pass(Cx<T>* buf, const Cx<T>* __restric
         if (NB % NT == 0 || b < NB) {
             const int k = b & (Ns - 1);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[i][r] = buf[b + r * NB];
+            for (int r = 0; r < R; ++r) v[i][r] = buf[lds_slot(b + r * NB)];
             if (Ns > 1) {
                 // twiddle exponent k r / (Ns R) of a full turn = (k r N / (Ns R)) / N
                 constexpr int shift = (LOG2H + 1) - (LOG2NS + (R == 8 ? 3 : (R == 4 ? 2 : 1)));
+                Cx<T> w[R];
+                butterfly_twiddles<T, R>(tw, k << shift, w);
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[(k * r) << shift]);
+                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], w[r]);
             }
             dft_inv<T, R>(v[i]);
         }
@@ -250,7 +407,7 @@ __device__ __forceinline__ void stockham_pass(Cx<T>* buf, const Cx<T>* __restric
             const int k = b & (Ns - 1);
             const int o = (b - k) * R + k;
 #pragma unroll
-            for (int q = 0; q < R; ++q) buf[o + q * Ns] = v[i][q];
+            for (int q = 0; q < R; ++q) buf[lds_slot(o + q * Ns)] = v[i][q];
         }
     }
     __syncthreads();
@@ -272,7 +429,7 @@ __device__ __forceinline__ void run_passes(Cx<T>* buf, const Cx<T>* __restrict__
 }
 
 // C2R of one ring row (2H reals, holding modes 0..H-1 as complex on entry), by NT threads
-// with an LDS buffer of H complex values.  Ends with the row written; the caller must
+// with an LDS buffer of lds_slots(H) complex values.  Ends with the row written; the caller must
 // barrier before reusing `buf`.
 template <typename T, int LOG2H, int NT>
 __device__ __forceinline__ void c2r_row(T* __restrict__ data_row, const T* __restrict__ twr, int m_top,
@@ -283,9 +440,8 @@ __device__ __forceinline__ void c2r_row(T* __restrict__ data_row, const T* __res
     Cx<T>* __restrict__ row = reinterpret_cast<Cx<T>*>(data_row);
     const int tid = threadIdx.x;
 
-    // pre-processing: Z_k from X_k and conj X_{H-k}
+    // pre-processing: Z_k from X_k and conj X_{H-k}, straight into LDS
     constexpr int PER = (H + NT - 1) / NT;
-    Cx<T> z[PER];
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int k = tid + i * NT;
@@ -299,13 +455,8 @@ __device__ __forceinline__ void c2r_row(T* __restrict__ data_row, const T* __res
             }
             const Cx<T> s = cadd(xk, xm);
             const Cx<T> d = cmul(tw[k], csub(xk, xm));
-            z[i] = cadd(s, mul_i(d));
+            buf[lds_slot(k)] = cadd(s, mul_i(d));
         }
-    }
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int k = tid + i * NT;
-        if (H % NT == 0 || k < H) buf[k] = z[i];
     }
     __syncthreads();
 
@@ -315,7 +466,7 @@ __device__ __forceinline__ void c2r_row(T* __restrict__ data_row, const T* __res
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int k = tid + i * NT;
-        if (H % NT == 0 || k < H) row[k] = buf[k];
+        if (H % NT == 0 || k < H) row[k] = buf[lds_slot(k)];
     }
 }
 

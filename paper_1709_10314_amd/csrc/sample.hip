@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256) void recursion_kernel(RecArgs a, const T* __re
         return;
     }
     const uint64_t key = (((uint64_t)a.seed_hi << 32) | a.seed_lo) + (uint64_t)f;
-    run_chain<T, M>(a.n_theta, a.s, a.even, h, m, part, (uint32_t)key, (uint32_t)(key >> 32),
+    run_chain<T, M>(a.n_theta, a.s, a.even, a.n_sets, h, m, part, (uint32_t)key, (uint32_t)(key >> 32),
                     fac + (size_t)m * factor_stride(M), (size_t)a.m_rows * factor_stride(M), g,
                     (size_t)a.n_phi);
 }
@@ -52,9 +52,16 @@ struct FftThreads {
     static constexpr int value = (1 << LOG2H) / 8 < 64 ? 64 : ((1 << LOG2H) / 8 > 256 ? 256 : (1 << LOG2H) / 8);
 };
 
+// At least four waves per SIMD (VGPRs capped at 128) for the FP32 transforms up to
+// n_phi = 8192; larger or FP64 rows need more registers than that without spilling.
+template <typename T, int LOG2H>
+struct FftWaves {
+    static constexpr int value = (sizeof(T) == 4 && LOG2H <= 12) ? 4 : 1;
+};
+
 // One workgroup per ring row.
 template <typename T, int LOG2H>
-__global__ __launch_bounds__(FftThreads<LOG2H>::value) void c2r_kernel(T* __restrict__ data,
+__global__ __launch_bounds__(FftThreads<LOG2H>::value, (FftWaves<T, LOG2H>::value)) void c2r_kernel(T* __restrict__ data,
                                                                        const T* __restrict__ twr,
                                                                        int m_top)
 {
@@ -66,8 +73,7 @@ __global__ __launch_bounds__(FftThreads<LOG2H>::value) void c2r_kernel(T* __rest
 template <typename T, int LOG2H>
 hipError_t launch_c2r_t(const T* tw, int m_top, int rows, T* data, hipStream_t st)
 {
-    constexpr int H = 1 << LOG2H;
-    const size_t lds = sizeof(Cx<T>) * H;
+    const size_t lds = sizeof(Cx<T>) * lds_slots(1 << LOG2H);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)c2r_kernel<T, LOG2H>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

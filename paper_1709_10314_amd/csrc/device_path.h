@@ -428,6 +428,65 @@ __device__ __forceinline__ void run_passes(Cx<T>* buf, const Cx<T>* __restrict__
     }
 }
 
+// The pre-processing works on mirror pairs (k, H-k), k = tid + i NT < H/2: both Z_k and
+// Z_{H-k} come from the same two modes, with w^{H-k} = -conj(w^k).  Pair k = 0 (whose
+// partner X_H is zero) also carries the self-paired k = H/2.  A thread holds PAIRS + 1
+// pairs of modes (X_k, X_{H-k}); the last slot is X_{H/2} for thread 0.
+template <int LOG2H, int NT>
+struct PrepShape {
+    static constexpr int H = 1 << LOG2H;
+    static constexpr int HALF = H / 2;
+    static constexpr int PAIRS = HALF > 0 ? (HALF + NT - 1) / NT : 0;
+};
+
+template <typename T, int LOG2H, int NT>
+__device__ __forceinline__ void c2r_load(const Cx<T>* __restrict__ row, int m_top, Cx<T>* xa, Cx<T>* xb)
+{
+    using S = PrepShape<LOG2H, NT>;
+    const int tid = threadIdx.x;
+    const Cx<T> zero = {T(0), T(0)};
+#pragma unroll
+    for (int i = 0; i < S::PAIRS; ++i) {
+        const int k = tid + i * NT;
+        xa[i] = zero;
+        xb[i] = zero;
+        if (S::HALF % NT == 0 || k < S::HALF) {
+            if (k <= m_top) xa[i] = row[k];
+            if (k > 0 && S::H - k <= m_top) xb[i] = row[S::H - k];
+        }
+    }
+    xa[S::PAIRS] = zero;   // X_{H/2} (thread 0), or X_1 when H = 1... never: H >= 2
+    if (tid == 0 && S::HALF <= m_top) xa[S::PAIRS] = row[S::HALF];
+}
+
+// Z_k = (X_k + conj X_{H-k}) + i w^k (X_k - conj X_{H-k}) for both members of each pair,
+// written to LDS.
+template <typename T, int LOG2H, int NT>
+__device__ __forceinline__ void c2r_prep(const Cx<T>* __restrict__ tw, const Cx<T>* xa, const Cx<T>* xb,
+                                         Cx<T>* buf)
+{
+    using S = PrepShape<LOG2H, NT>;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < S::PAIRS; ++i) {
+        const int k = tid + i * NT;
+        if (S::HALF % NT == 0 || k < S::HALF) {
+            const Cx<T> a = xa[i], b = xb[i];                 // X_k, X_{H-k}
+            const Cx<T> ca = {a.re, -a.im}, cb = {b.re, -b.im};
+            const Cx<T> w = tw[k];
+            const Cx<T> wm = {-w.re, w.im};                   // w^{H-k} = -conj(w^k)
+            buf[lds_slot(k)] = cadd(cadd(a, cb), mul_i(cmul(w, csub(a, cb))));
+            if (k > 0) buf[lds_slot(S::H - k)] = cadd(cadd(b, ca), mul_i(cmul(wm, csub(b, ca))));
+        }
+    }
+    if (tid == 0) {
+        const Cx<T> a = xa[S::PAIRS];                         // X_{H/2}, its own partner
+        const Cx<T> ca = {a.re, -a.im};
+        const Cx<T> w = tw[S::HALF];
+        buf[lds_slot(S::HALF)] = cadd(cadd(a, ca), mul_i(cmul(w, csub(a, ca))));
+    }
+}
+
 // C2R of one ring row (2H reals, holding modes 0..H-1 as complex on entry), by NT threads
 // with an LDS buffer of lds_slots(H) complex values.  Ends with the row written; the caller must
 // barrier before reusing `buf`.
@@ -435,38 +494,81 @@ template <typename T, int LOG2H, int NT>
 __device__ __forceinline__ void c2r_row(T* __restrict__ data_row, const T* __restrict__ twr, int m_top,
                                         Cx<T>* buf)
 {
+    using S = PrepShape<LOG2H, NT>;
     constexpr int H = 1 << LOG2H;
+    constexpr int PER = (H + NT - 1) / NT;
     const Cx<T>* tw = reinterpret_cast<const Cx<T>*>(twr);
     Cx<T>* __restrict__ row = reinterpret_cast<Cx<T>*>(data_row);
-    const int tid = threadIdx.x;
-
-    // pre-processing: Z_k from X_k and conj X_{H-k}, straight into LDS
-    constexpr int PER = (H + NT - 1) / NT;
+    // pre-processing pair by pair, straight from global memory into LDS
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int k = tid + i * NT;
-        if (H % NT == 0 || k < H) {
-            const Cx<T> zero = {T(0), T(0)};
-            const Cx<T> xk = (k <= m_top) ? row[k] : zero;
-            Cx<T> xm = zero;
-            if (k > 0 && H - k <= m_top) {
-                const Cx<T> t = row[H - k];
-                xm = {t.re, -t.im};
-            }
-            const Cx<T> s = cadd(xk, xm);
-            const Cx<T> d = cmul(tw[k], csub(xk, xm));
-            buf[lds_slot(k)] = cadd(s, mul_i(d));
+    for (int i = 0; i < S::PAIRS; ++i) {
+        Cx<T> xa[2], xb[2];
+        const int k = threadIdx.x + i * NT;
+        const Cx<T> zero = {T(0), T(0)};
+        xa[0] = xb[0] = xa[1] = zero;
+        if (S::HALF % NT == 0 || k < S::HALF) {
+            if (k <= m_top) xa[0] = row[k];
+            if (k > 0 && H - k <= m_top) xb[0] = row[H - k];
+            const Cx<T> a = xa[0], b = xb[0];
+            const Cx<T> ca = {a.re, -a.im}, cb = {b.re, -b.im};
+            const Cx<T> w = tw[k];
+            const Cx<T> wm = {-w.re, w.im};
+            buf[lds_slot(k)] = cadd(cadd(a, cb), mul_i(cmul(w, csub(a, cb))));
+            if (k > 0) buf[lds_slot(H - k)] = cadd(cadd(b, ca), mul_i(cmul(wm, csub(b, ca))));
         }
     }
+    if (threadIdx.x == 0) {
+        const Cx<T> zero = {T(0), T(0)};
+        const Cx<T> a = (S::HALF <= m_top) ? row[S::HALF] : zero;
+        const Cx<T> ca = {a.re, -a.im};
+        buf[lds_slot(S::HALF)] = cadd(cadd(a, ca), mul_i(cmul(tw[S::HALF], csub(a, ca))));
+    }
     __syncthreads();
-
     run_passes<T, LOG2H, NT, 0>(buf, tw);
-
     // T_{2j} + i T_{2j+1} = z_j: the complex result written as interleaved reals
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-        const int k = tid + i * NT;
+        const int k = threadIdx.x + i * NT;
         if (H % NT == 0 || k < H) row[k] = buf[lds_slot(k)];
+    }
+}
+
+// C2R of rows row0, row0 + stride, ... < rows by one workgroup.  With PREFETCH the next
+// row's modes are loaded into registers right after the current row has been moved into
+// LDS, so their global latency overlaps the current row's passes (a barrier waits on
+// LDS traffic only); without it each row is loaded when its turn comes (fewer registers).
+template <typename T, int LOG2H, int NT, bool PREFETCH>
+__device__ __forceinline__ void c2r_rows(T* __restrict__ data, const T* __restrict__ twr, int m_top,
+                                         Cx<T>* buf, int rows, int row0, int stride)
+{
+    constexpr int H = 1 << LOG2H;
+    constexpr int PER = (H + NT - 1) / NT;
+    if constexpr (!PREFETCH) {
+        for (int r = row0; r < rows; r += stride) {
+            c2r_row<T, LOG2H, NT>(data + (size_t)r * (2 * H), twr, m_top, buf);
+            __syncthreads();
+        }
+        return;
+    } else {
+        const Cx<T>* tw = reinterpret_cast<const Cx<T>*>(twr);
+        Cx<T> xa[PrepShape<LOG2H, NT>::PAIRS + 1], xb[PrepShape<LOG2H, NT>::PAIRS + 1];
+        if (row0 < rows)
+            c2r_load<T, LOG2H, NT>(reinterpret_cast<const Cx<T>*>(data + (size_t)row0 * (2 * H)), m_top, xa, xb);
+        for (int r = row0; r < rows; r += stride) {
+            c2r_prep<T, LOG2H, NT>(tw, xa, xb, buf);
+            __syncthreads();
+            const int rn = r + stride;
+            if (rn < rows)
+                c2r_load<T, LOG2H, NT>(reinterpret_cast<const Cx<T>*>(data + (size_t)rn * (2 * H)), m_top, xa, xb);
+            run_passes<T, LOG2H, NT, 0>(buf, tw);
+            Cx<T>* __restrict__ row = reinterpret_cast<Cx<T>*>(data + (size_t)r * (2 * H));
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int k = threadIdx.x + i * NT;
+                if (H % NT == 0 || k < H) row[k] = buf[lds_slot(k)];
+            }
+            __syncthreads();
+        }
     }
 }
 

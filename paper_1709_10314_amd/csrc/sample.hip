@@ -47,28 +47,41 @@ __global__ __launch_bounds__(256) void recursion_kernel(RecArgs a, const T* __re
                     (size_t)a.n_phi);
 }
 
-template <int LOG2H>
+// Threads per row: H/8 clamped to [64, 256], and 512 for the largest rows (FP32 n_phi =
+// 16384, FP64 n_phi >= 8192) so that each thread holds fewer butterflies.
+template <typename T, int LOG2H>
 struct FftThreads {
-    static constexpr int value = (1 << LOG2H) / 8 < 64 ? 64 : ((1 << LOG2H) / 8 > 256 ? 256 : (1 << LOG2H) / 8);
+    static constexpr int base = (1 << LOG2H) / 8 < 64 ? 64 : ((1 << LOG2H) / 8 > 256 ? 256 : (1 << LOG2H) / 8);
+    static constexpr int value = (LOG2H >= (sizeof(T) == 4 ? 13 : 12)) ? 512 : base;
 };
 
-// At least four waves per SIMD (VGPRs capped at 128) for the FP32 transforms up to
-// n_phi = 8192; larger or FP64 rows need more registers than that without spilling.
+// Rows prefetch the next row during the current one's passes while the extra registers
+// fit (FP32 up to n_phi = 8192, FP64 up to 2048); larger rows load row by row.
+template <typename T, int LOG2H>
+struct FftPrefetch {
+    static constexpr bool value = sizeof(T) == 4 ? LOG2H <= 12 : LOG2H <= 10;
+};
+
+// Register budget in waves per SIMD: 4 (128 VGPRs) for small rows, else 2 (256 VGPRs),
+// and 1 for the 512-thread rows.
 template <typename T, int LOG2H>
 struct FftWaves {
-    static constexpr int value = (sizeof(T) == 4 && LOG2H <= 12) ? 4 : 1;
+    static constexpr int value = FftThreads<T, LOG2H>::value == 512 ? 1
+                                 : (LOG2H < (sizeof(T) == 4 ? 11 : 8) ? 4 : 2);
 };
 
-// One workgroup per ring row.
+// Each workgroup transforms rows blockIdx.x, blockIdx.x + gridDim.x, ...
 template <typename T, int LOG2H>
-__global__ __launch_bounds__(FftThreads<LOG2H>::value, (FftWaves<T, LOG2H>::value)) void c2r_kernel(T* __restrict__ data,
-                                                                       const T* __restrict__ twr,
-                                                                       int m_top)
+__global__ __launch_bounds__((FftThreads<T, LOG2H>::value), (FftWaves<T, LOG2H>::value)) void c2r_kernel(
+    T* __restrict__ data, const T* __restrict__ twr, int m_top, int rows)
 {
     extern __shared__ unsigned char smem_raw[];
-    c2r_row<T, LOG2H, FftThreads<LOG2H>::value>(data + (size_t)blockIdx.x * (2 << LOG2H), twr, m_top,
-                                                 reinterpret_cast<Cx<T>*>(smem_raw));
+    c2r_rows<T, LOG2H, FftThreads<T, LOG2H>::value, FftPrefetch<T, LOG2H>::value>(
+        data, twr, m_top, reinterpret_cast<Cx<T>*>(smem_raw), rows, blockIdx.x, gridDim.x);
 }
+
+// Workgroups of the row-looping FFT: enough to fill every CU several times over.
+constexpr int kFftGrid = 2048;
 
 template <typename T, int LOG2H>
 hipError_t launch_c2r_t(const T* tw, int m_top, int rows, T* data, hipStream_t st)
@@ -79,8 +92,9 @@ hipError_t launch_c2r_t(const T* tw, int m_top, int rows, T* data, hipStream_t s
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((c2r_kernel<T, LOG2H>), dim3(rows), dim3(FftThreads<LOG2H>::value), lds, st,
-                       data, tw, m_top);
+    const int grid = rows < kFftGrid ? rows : kFftGrid;
+    hipLaunchKernelGGL((c2r_kernel<T, LOG2H>), dim3(grid), dim3(FftThreads<T, LOG2H>::value), lds, st, data, tw,
+                       m_top, rows);
     return hipGetLastError();
 }
 

@@ -29,18 +29,20 @@ __device__ __forceinline__ void block_normals(uint32_t blk, uint32_t m, uint32_t
 }
 
 // One state-space step x <- A x + B w (eq. (state_space)) with the factor record `rec`.
+// The products are fused in a fixed order (explicit fma), so a step rounds the same way
+// wherever it is inlined.
 template <typename T, int M>
 __device__ __forceinline__ void chain_step(const T* __restrict__ rec, T& x0, T& x1, T w0, T w1)
 {
     if (M == 1) {
         using V2 = typename Vec2<T>::type;
         const V2 v = *reinterpret_cast<const V2*>(rec);
-        x0 = v.x * x0 + v.y * w0;
+        x0 = fma(v.x, x0, v.y * w0);
     } else {
         const T a00 = rec[0], a01 = rec[1], a10 = rec[2], a11 = rec[3];
         const T b00 = rec[4], b10 = rec[5], b11 = rec[6];
-        const T y0 = a00 * x0 + a01 * x1 + b00 * w0;
-        const T y1 = a10 * x0 + a11 * x1 + (b10 * w0 + b11 * w1);
+        const T y0 = fma(a00, x0, fma(a01, x1, b00 * w0));
+        const T y1 = fma(a10, x0, fma(a11, x1, fma(b10, w0, b11 * w1)));
         x0 = y0;
         x1 = y1;
     }
@@ -74,19 +76,31 @@ __device__ __forceinline__ Rec<T, M> load_rec(const T* __restrict__ rec)
     return R;
 }
 
-// x <- A x + B w with a prefetched record
+// x <- A x + B w with a prefetched record (same fused order as chain_step)
 template <typename T, int M>
 __device__ __forceinline__ void chain_step_rec(const Rec<T, M>& R, T& x0, T& x1, T w0, T w1)
 {
     if constexpr (M == 1) {
-        x0 = R.v[0] * x0 + R.v[1] * w0;
+        x0 = fma(R.v[0], x0, R.v[1] * w0);
     } else {
-        const T y0 = R.v[0] * x0 + R.v[1] * x1 + R.v[4] * w0;
-        const T y1 = R.v[2] * x0 + R.v[3] * x1 + (R.v[5] * w0 + R.v[6] * w1);
+        const T y0 = fma(R.v[0], x0, fma(R.v[1], x1, R.v[4] * w0));
+        const T y1 = fma(R.v[2], x0, fma(R.v[3], x1, fma(R.v[5], w0, R.v[6] * w1)));
         x0 = y0;
         x1 = y1;
     }
 }
+
+// Philox groups kept in flight by the register prefetch pipeline of a chain walk.
+#ifndef SMF_CHAIN_P32
+#define SMF_CHAIN_P32 8
+#endif
+#ifndef SMF_CHAIN_P64
+#define SMF_CHAIN_P64 4
+#endif
+template <typename T>
+struct ChainDepth {
+    static constexpr int value = sizeof(T) == 4 ? SMF_CHAIN_P32 : SMF_CHAIN_P64;
+};
 
 // Rings are walked in groups of G = 4/M that share one Philox block (counter block
 // (ring M) / 4).  Ring r uses set j = s - r + even walking north and j = r - s walking
@@ -129,37 +143,38 @@ __device__ __forceinline__ void step_group_direct(int base, int lo, int hi, int 
     }
 }
 
+// Walks rings r_first..r_last (north: descending, south: ascending).
 template <typename T, int M, int P, bool NORTH>
-__device__ __forceinline__ void walk_hemisphere(int n, int s, int even, int r_first, int m, int part,
+__device__ __forceinline__ void walk_hemisphere(int s, int even, int r_first, int r_last, int m, int part,
                                                 uint32_t k0, uint32_t k1, T sc,
                                                 const T* __restrict__ fm, size_t set_stride,
                                                 int n_sets, T* __restrict__ g, size_t row, T& x0, T& x1)
 {
     constexpr int G = 4 / M;
     const uint32_t um = (uint32_t)m, up = (uint32_t)part;
-    // full groups: q = 0..ng-1 with ring bases b0 - q G (north) or b0 + q G (south)
+    if (NORTH ? r_first < r_last : r_first > r_last) return;
+    // cut first group, then full groups q = 0..ng-1 with bases b0 - q G (north) or
+    // b0 + q G (south), then a cut last group
     int b0, ng;
     if (NORTH) {
-        if (r_first < 0) return;
         int top = r_first;
         const int base = (top / G) * G;
-        if (top != base + G - 1) {   // cut first group
-            step_group_direct<T, M, true>(base, 0, top, s, even, n_sets, um, up, k0, k1, sc, fm, set_stride,
-                                          g, row, x0, x1);
+        if (top != base + G - 1 || base < r_last) {
+            step_group_direct<T, M, true>(base, base > r_last ? base : r_last, top, s, even, n_sets, um, up, k0,
+                                          k1, sc, fm, set_stride, g, row, x0, x1);
             top = base - 1;
         }
-        ng = (top + 1) / G;
+        ng = top + 1 - r_last >= G ? (top + 1 - r_last) / G : 0;
         b0 = top + 1 - G;
     } else {
-        if (r_first >= n) return;
         int lo = r_first;
         const int base = (lo / G) * G;
-        if (lo != base) {            // cut first group
-            step_group_direct<T, M, false>(base, lo, n - 1, s, even, n_sets, um, up, k0, k1, sc, fm,
-                                           set_stride, g, row, x0, x1);
+        if (lo != base || base + G - 1 > r_last) {
+            step_group_direct<T, M, false>(base, lo, base + G - 1 < r_last ? base + G - 1 : r_last, s, even, n_sets,
+                                           um, up, k0, k1, sc, fm, set_stride, g, row, x0, x1);
             lo = base + G;
         }
-        ng = lo < n ? (n - lo) / G : 0;
+        ng = r_last - lo + 1 >= G ? (r_last - lo + 1) / G : 0;
         b0 = lo;
     }
     if (ng > 0) {
@@ -173,11 +188,25 @@ __device__ __forceinline__ void walk_hemisphere(int n, int s, int even, int r_fi
         }
         int q = 0;
         for (; q + P <= ng; q += P) {
+            // the P Philox blocks of this stage in lockstep, then their normals
+            uint32_t blk[P];
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const int base = NORTH ? b0 - (q + p) * G : b0 + (q + p) * G;
-                T nb[4];
-                block_normals<T>((uint32_t)((base * M) >> 2), um, up, k0, k1, sc, nb);
+                blk[p] = (uint32_t)((base * M) >> 2);
+            }
+            PhiloxBlock wb[P];
+            philox4x32_10_n<P>(blk, um, up, k0, k1, wb);
+            T nbs[P][4];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                BoxMuller<T>::pair(wb[p].w[0], wb[p].w[1], sc, nbs[p][0], nbs[p][1]);
+                BoxMuller<T>::pair(wb[p].w[2], wb[p].w[3], sc, nbs[p][2], nbs[p][3]);
+            }
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int base = NORTH ? b0 - (q + p) * G : b0 + (q + p) * G;
+                const T* nb = nbs[p];
 #pragma unroll
                 for (int tt = 0; tt < G; ++tt) {
                     const int t = NORTH ? G - 1 - tt : tt;
@@ -210,11 +239,18 @@ __device__ __forceinline__ void walk_hemisphere(int n, int s, int even, int r_fi
             }
         }
     }
-    if (!NORTH) {
-        // cut last group of the south walk
+    // cut last group
+    if (NORTH) {
+        const int end = b0 - ng * G + G - 1;   // highest ring not yet produced
+        if (end >= r_last) {
+            const int base = (end / G) * G;
+            step_group_direct<T, M, true>(base, r_last, end, s, even, n_sets, um, up, k0, k1, sc, fm,
+                                          set_stride, g, row, x0, x1);
+        }
+    } else {
         const int lo = b0 + ng * G;
-        if (lo < n)
-            step_group_direct<T, M, false>(lo, lo, n - 1, s, even, n_sets, um, up, k0, k1, sc, fm, set_stride,
+        if (lo <= r_last)
+            step_group_direct<T, M, false>(lo, lo, r_last, s, even, n_sets, um, up, k0, k1, sc, fm, set_stride,
                                            g, row, x0, x1);
     }
 }
@@ -226,7 +262,7 @@ __device__ __forceinline__ void walk_hemisphere(int n, int s, int even, int r_fi
 // step (even n_theta) and steps to ring n-1 with the mirrored factors, carried as
 // y = D x so that the stored northern records apply unchanged with D w as the noise.
 // The ring order is uniform across the wave.
-template <typename T, int M, int P = 4>
+template <typename T, int M, int P = ChainDepth<T>::value>
 __device__ __forceinline__ void run_chain(int n, int s, int even, int n_sets, int h, int m, int part,
                                           uint32_t k0, uint32_t k1, const T* __restrict__ fm,
                                           size_t set_stride, T* __restrict__ g, size_t row)
@@ -251,8 +287,8 @@ __device__ __forceinline__ void run_chain(int n, int s, int even, int n_sets, in
     }
     if (h == 0) {
         g[(size_t)s * row] = x0;
-        walk_hemisphere<T, M, P, true>(n, s, even, s - 1, m, part, k0, k1, sc, fm, set_stride, n_sets,
-                                       g, row, x0, x1);
+        walk_hemisphere<T, M, P, true>(s, even, s - 1, 0, m, part, k0, k1, sc, fm, set_stride, n_sets, g, row,
+                                       x0, x1);
     } else {
         int r_lo = s + 1;
         if (even) {
@@ -274,8 +310,8 @@ __device__ __forceinline__ void run_chain(int n, int s, int even, int n_sets, in
             r_lo = s + 2;
         }
         x1 = -x1;   // y = D x
-        walk_hemisphere<T, M, P, false>(n, s, even, r_lo, m, part, k0, k1, sc, fm, set_stride, n_sets,
-                                        g, row, x0, x1);
+        walk_hemisphere<T, M, P, false>(s, even, r_lo, n - 1, m, part, k0, k1, sc, fm, set_stride, n_sets, g,
+                                        row, x0, x1);
     }
 }
 

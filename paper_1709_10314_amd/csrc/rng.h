@@ -38,6 +38,68 @@ __device__ __forceinline__ PhiloxBlock philox4x32_10(uint32_t c0, uint32_t c1, u
     return b;
 }
 
+// N independent Philox blocks whose counters differ only in the first word, advanced one
+// round at a time so that a caller can interleave the rounds with other work.
+template <int N>
+struct PhiloxLanes {
+    uint32_t a[N], b[N], c[N], d[N];
+    uint32_t k0, k1;
+
+    __device__ __forceinline__ PhiloxLanes(const uint32_t* c0, uint32_t c1, uint32_t c2, uint32_t key0,
+                                           uint32_t key1)
+        : k0(key0), k1(key1)
+    {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            a[i] = c0[i];
+            b[i] = c1;
+            c[i] = c2;
+            d[i] = 0u;
+        }
+    }
+
+    // one round of all N blocks, then the Weyl key bump
+    __device__ __forceinline__ void round()
+    {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const uint64_t pa = (uint64_t)a[i] * 0xD2511F53u;
+            const uint64_t pb = (uint64_t)c[i] * 0xCD9E8D57u;
+            const uint32_t n0 = (uint32_t)(pb >> 32) ^ b[i] ^ k0;
+            const uint32_t n2 = (uint32_t)(pa >> 32) ^ d[i] ^ k1;
+            b[i] = (uint32_t)pb;
+            d[i] = (uint32_t)pa;
+            a[i] = n0;
+            c[i] = n2;
+        }
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+
+    __device__ __forceinline__ PhiloxBlock block(int i) const
+    {
+        PhiloxBlock w;
+        w.w[0] = a[i]; w.w[1] = b[i]; w.w[2] = c[i]; w.w[3] = d[i];
+        return w;
+    }
+};
+
+// All ten rounds of N blocks in lockstep; the scheduling barrier after each round keeps
+// the compiler from serialising the blocks, so their multiply/xor chains interleave.
+template <int N>
+__device__ __forceinline__ void philox4x32_10_n(const uint32_t* c0, uint32_t c1, uint32_t c2, uint32_t k0,
+                                                uint32_t k1, PhiloxBlock* out)
+{
+    PhiloxLanes<N> ph(c0, c1, c2, k0, k1);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        ph.round();
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = ph.block(i);
+}
+
 template <typename T>
 struct BoxMuller;
 

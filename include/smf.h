@@ -87,6 +87,28 @@ int smf_sample(const smf_plan* plan, uint64_t seed, int count, void* out_dev, vo
  * entries for m > m_top are zero.  Same size and errors as smf_sample. */
 int smf_sample_modes(const smf_plan* plan, uint64_t seed, int count, void* g_dev, void* hip_stream);
 
+/* Ring blocks of the affine scan (single-field plans).  The recursion of eq. (state_space)
+ * is affine in the state, so a chain cut into ring blocks can run its blocks in parallel:
+ * each block's end state from zero start, then the true block starts by composing the
+ * blocks' transitions (products of the step matrices A, built at setup) with those end
+ * states, then each block again from its true start.  Used when a call's chains alone
+ * cannot fill the GPU; it doubles the arithmetic and changes results only by rounding.
+ *   blocks  0: automatic: the scan is used when count * 2 * ceil(n_phi / 64) < 1024
+ *              (fewer chains than one wavefront per SIMD of the chip), with the fewest
+ *              blocks giving >= 4096 wavefronts while every block keeps >= 32 ring steps;
+ *           1: never;
+ *           2, 4, 8 or 16: always, with that many blocks, capped at the plan's maximum (the
+ *              largest power of two <= 16 leaving >= 8 ring steps per block, 1 when the
+ *              walk has fewer than 16 steps) and at 8 for SMF_FP64 plans.
+ * The plan stores one transition per (fine block, m): 16 * (n_phi/2) * M*M values in FP64
+ * (and FP32 for SMF_FP32 plans).
+ * Errors: SMF_EINVAL (NULL, batch plan, blocks not 0, 1 or a power of two <= 16). */
+int smf_set_ring_blocks(smf_plan* plan, int blocks);
+
+/* The ring blocks a call of smf_sample or smf_sample_modes with `count` fields would use
+ * (1 = plain recursion).  Errors: SMF_EINVAL (NULL, batch plan, count < 0). */
+int smf_get_ring_blocks(const smf_plan* plan, int count, int* blocks);
+
 /* Plan geometry (single-field plans): dims[0..7] = {order, n_theta, n_phi, ell_max, m_top, n_sets, start_ring,
  * precision flag}.  n_sets = number of factor sets per mode (start, crossing for even
  * n_theta, then one per northern step).  Errors: SMF_EINVAL on NULL. */

@@ -32,7 +32,7 @@ bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
 // Owns the device buffers of a plan under construction; frees them unless released.
 struct DevBufs {
-    void* p[8] = {nullptr};
+    void* p[12] = {nullptr};
     int n = 0;
     template <typename T>
     int alloc(T** out, size_t count)
@@ -68,7 +68,9 @@ struct DeviceGuard {
     }
 };
 
-int setup_impl(const smf_spectrum* spec, int n_theta, int n_phi, int flags, hipStream_t st,
+// `scan`: also build the block transitions of the affine scan (single-field plans; the
+// sub-plans of a batch only ever run the plain recursion).
+int setup_impl(const smf_spectrum* spec, int n_theta, int n_phi, int flags, hipStream_t st, bool scan,
                smf_plan** out)
 {
     if (!spec || !out) return SMF_EINVAL;
@@ -135,6 +137,20 @@ int setup_impl(const smf_spectrum* spec, int n_theta, int n_phi, int flags, hipS
     if ((rc = bufs.alloc(&plan->tw64, (size_t)2 * n_phi))) goto fail;
     if ((rc = bufs.alloc(&plan->tw32, (size_t)2 * n_phi))) goto fail;
     if (smf::launch_twiddles(n_phi, plan->tw64, plan->tw32, st) != hipSuccess) { rc = SMF_EHIP; goto fail; }
+    plan->scan_fine = scan ? smf::scan_fine_blocks(g) : 1;
+    if (plan->scan_fine > 1) {
+        const size_t nphi = (size_t)plan->scan_fine * g.m_rows * g.order * g.order;
+        if ((rc = bufs.alloc(&plan->phi64, nphi))) goto fail;
+        if (hipMemsetAsync(plan->phi64, 0, nphi * sizeof(double), st) != hipSuccess) { rc = SMF_EHIP; goto fail; }
+        if (flags == SMF_FP32) {
+            if ((rc = bufs.alloc(&plan->phi32, nphi))) goto fail;
+            if (hipMemsetAsync(plan->phi32, 0, nphi * sizeof(float), st) != hipSuccess) { rc = SMF_EHIP; goto fail; }
+        }
+        if (smf::launch_phi(g, plan->f64, plan->scan_fine, plan->phi64, plan->phi32, st) != hipSuccess) {
+            rc = SMF_EHIP;
+            goto fail;
+        }
+    }
     if (hipStreamSynchronize(st) != hipSuccess) { rc = SMF_EHIP; goto fail; }
 
     // scratch used only during setup
@@ -158,7 +174,24 @@ extern "C" {
 int smf_setup(const smf_spectrum* spec, int n_theta, int n_phi, int flags, void* hip_stream,
               smf_plan** out)
 {
-    return setup_impl(spec, n_theta, n_phi, flags, (hipStream_t)hip_stream, out);
+    return setup_impl(spec, n_theta, n_phi, flags, (hipStream_t)hip_stream, true, out);
+}
+
+// Ring blocks a call with `count` fields uses (1: plain recursion).  Automatic rule: the
+// plain recursion has count * 2 * ceil(m_rows / 32) waves; below one wave per SIMD of the
+// chip (1024) the chains are cut into the fewest blocks that give >= 4096 waves, as long
+// as every block keeps >= kScanAutoMinSets ring steps (shorter walks are launch-bound).
+static int ring_blocks_for(const smf_plan* plan, int count)
+{
+    const int cap = std::min(plan->scan_fine, smf::scan_max_blocks(plan->flags == SMF_FP64));
+    if (cap < 2 || plan->scan_req == 1) return 1;
+    if (plan->scan_req >= 2) return std::min(plan->scan_req, cap);
+    const long waves = (long)count * 2 * ((plan->g.m_rows + 31) / 32);
+    const int walk = plan->g.n_sets - (plan->g.even ? 2 : 1);
+    if (waves >= 1024 || walk / 2 < smf::kScanAutoMinSets) return 1;
+    int b = 2;
+    while (b < cap && waves * b < 4096 && walk / (2 * b) >= smf::kScanAutoMinSets) b *= 2;
+    return b;
 }
 
 static int sample_common(const smf_plan* plan, uint64_t seed, int count, void* out_dev,
@@ -171,8 +204,15 @@ static int sample_common(const smf_plan* plan, uint64_t seed, int count, void* o
     hipStream_t st = (hipStream_t)hip_stream;
     const int fp64 = plan->flags == SMF_FP64;
     const void* fac = fp64 ? (const void*)plan->f64 : (const void*)plan->f32;
-    if (smf::launch_recursion(plan->g, fp64, fac, seed, count, out_dev, st) != hipSuccess)
+    const int blocks = ring_blocks_for(plan, count);
+    if (blocks > 1) {
+        const void* phi = fp64 ? (const void*)plan->phi64 : (const void*)plan->phi32;
+        if (smf::launch_scan(plan->g, fp64, fac, phi, plan->scan_fine, blocks, seed, count, out_dev, st) !=
+            hipSuccess)
+            return SMF_EHIP;
+    } else if (smf::launch_recursion(plan->g, fp64, fac, seed, count, out_dev, st) != hipSuccess) {
         return SMF_EHIP;
+    }
     if (fft) {
         const void* tw = fp64 ? (const void*)plan->tw64 : (const void*)plan->tw32;
         if (smf::launch_c2r(plan->g, fp64, tw, count, out_dev, st) != hipSuccess) return SMF_EHIP;
@@ -188,6 +228,21 @@ int smf_sample(const smf_plan* plan, uint64_t seed, int count, void* out_dev, vo
 int smf_sample_modes(const smf_plan* plan, uint64_t seed, int count, void* g_dev, void* hip_stream)
 {
     return sample_common(plan, seed, count, g_dev, hip_stream, false);
+}
+
+int smf_set_ring_blocks(smf_plan* plan, int blocks)
+{
+    if (!plan || plan->batch || blocks < 0 || blocks > smf::kScanMaxBlocks) return SMF_EINVAL;
+    if (blocks > 1 && (blocks & (blocks - 1))) return SMF_EINVAL;
+    plan->scan_req = blocks;
+    return SMF_OK;
+}
+
+int smf_get_ring_blocks(const smf_plan* plan, int count, int* blocks)
+{
+    if (!plan || plan->batch || !blocks || count < 0) return SMF_EINVAL;
+    *blocks = ring_blocks_for(plan, count);
+    return SMF_OK;
 }
 
 int smf_plan_dims(const smf_plan* plan, int* dims)
@@ -255,6 +310,8 @@ int smf_destroy(smf_plan* plan)
     if (plan->f32) (void)hipFree(plan->f32);
     (void)hipFree(plan->tw64);
     (void)hipFree(plan->tw32);
+    if (plan->phi64) (void)hipFree(plan->phi64);
+    if (plan->phi32) (void)hipFree(plan->phi32);
     free(plan);
     return SMF_OK;
 }
@@ -292,7 +349,7 @@ int smf_setup_batch(int n, const smf_spectrum* specs, const int* n_theta, const 
     int dev = 0;
     for (int i = 0; i < n; ++i) {
         smf_plan* p = nullptr;
-        rc = setup_impl(&specs[i], n_theta[i], n_phi[i], SMF_FP32, st, &p);
+        rc = setup_impl(&specs[i], n_theta[i], n_phi[i], SMF_FP32, st, false, &p);
         if (rc != SMF_OK) goto fail;
         b->sub.push_back(p);
         b->offsets[i + 1] = b->offsets[i] + (int64_t)n_theta[i] * n_phi[i];

@@ -124,7 +124,7 @@ template <typename T, int M, bool NORTH>
 __device__ __forceinline__ void step_group_direct(int base, int lo, int hi, int s, int even, int n_sets,
                                                   uint32_t um, uint32_t up, uint32_t k0, uint32_t k1, T sc,
                                                   const T* __restrict__ fm, size_t set_stride,
-                                                  T* __restrict__ g, size_t row, T& x0, T& x1)
+                                                  T* __restrict__ g, size_t row, T& x0, T& x1, bool store)
 {
     constexpr int G = 4 / M;
     T nb[4];
@@ -138,17 +138,19 @@ __device__ __forceinline__ void step_group_direct(int base, int lo, int hi, int 
             const T w0 = nb[t * M];
             const T w1 = M == 2 ? (NORTH ? nb[t * M + 1] : -nb[t * M + 1]) : T(0);
             chain_step_rec<T, M>(R, x0, x1, w0, w1);
-            g[(size_t)r * row] = x0;
+            if (store) g[(size_t)r * row] = x0;
         }
     }
 }
 
-// Walks rings r_first..r_last (north: descending, south: ascending).
+// Walks rings r_first..r_last (north: descending, south: ascending), storing each ring's
+// x0 unless `store` is false (then only the end state is wanted).
 template <typename T, int M, int P, bool NORTH>
 __device__ __forceinline__ void walk_hemisphere(int s, int even, int r_first, int r_last, int m, int part,
                                                 uint32_t k0, uint32_t k1, T sc,
                                                 const T* __restrict__ fm, size_t set_stride,
-                                                int n_sets, T* __restrict__ g, size_t row, T& x0, T& x1)
+                                                int n_sets, T* __restrict__ g, size_t row, T& x0, T& x1,
+                                                bool store = true)
 {
     constexpr int G = 4 / M;
     const uint32_t um = (uint32_t)m, up = (uint32_t)part;
@@ -161,7 +163,7 @@ __device__ __forceinline__ void walk_hemisphere(int s, int even, int r_first, in
         const int base = (top / G) * G;
         if (top != base + G - 1 || base < r_last) {
             step_group_direct<T, M, true>(base, base > r_last ? base : r_last, top, s, even, n_sets, um, up, k0,
-                                          k1, sc, fm, set_stride, g, row, x0, x1);
+                                          k1, sc, fm, set_stride, g, row, x0, x1, store);
             top = base - 1;
         }
         ng = top + 1 - r_last >= G ? (top + 1 - r_last) / G : 0;
@@ -171,7 +173,7 @@ __device__ __forceinline__ void walk_hemisphere(int s, int even, int r_first, in
         const int base = (lo / G) * G;
         if (lo != base || base + G - 1 > r_last) {
             step_group_direct<T, M, false>(base, lo, base + G - 1 < r_last ? base + G - 1 : r_last, s, even, n_sets,
-                                           um, up, k0, k1, sc, fm, set_stride, g, row, x0, x1);
+                                           um, up, k0, k1, sc, fm, set_stride, g, row, x0, x1, store);
             lo = base + G;
         }
         ng = r_last - lo + 1 >= G ? (r_last - lo + 1) / G : 0;
@@ -213,7 +215,7 @@ __device__ __forceinline__ void walk_hemisphere(int s, int even, int r_first, in
                     const T w0 = nb[t * M];
                     const T w1 = M == 2 ? (NORTH ? nb[t * M + 1] : -nb[t * M + 1]) : T(0);
                     chain_step_rec<T, M>(buf[p][t], x0, x1, w0, w1);
-                    g[(size_t)(base + t) * row] = x0;
+                    if (store) g[(size_t)(base + t) * row] = x0;
                 }
                 const int nbase = NORTH ? base - P * G : base + P * G;
 #pragma unroll
@@ -234,7 +236,7 @@ __device__ __forceinline__ void walk_hemisphere(int s, int even, int r_first, in
                     const T w0 = nb[t * M];
                     const T w1 = M == 2 ? (NORTH ? nb[t * M + 1] : -nb[t * M + 1]) : T(0);
                     chain_step_rec<T, M>(buf[p][t], x0, x1, w0, w1);
-                    g[(size_t)(base + t) * row] = x0;
+                    if (store) g[(size_t)(base + t) * row] = x0;
                 }
             }
         }
@@ -245,14 +247,61 @@ __device__ __forceinline__ void walk_hemisphere(int s, int even, int r_first, in
         if (end >= r_last) {
             const int base = (end / G) * G;
             step_group_direct<T, M, true>(base, r_last, end, s, even, n_sets, um, up, k0, k1, sc, fm,
-                                          set_stride, g, row, x0, x1);
+                                          set_stride, g, row, x0, x1, store);
         }
     } else {
         const int lo = b0 + ng * G;
         if (lo <= r_last)
             step_group_direct<T, M, false>(lo, lo, r_last, s, even, n_sets, um, up, k0, k1, sc, fm, set_stride,
-                                           g, row, x0, x1);
+                                           g, row, x0, x1, store);
     }
+}
+
+// The state a hemisphere's main walk starts from: the start draw at ring s (eq.
+// (state_initial)), stored there by the northern chain; for the southern chain also the
+// crossing step to ring s+1 (even n_theta, set 1, stored), then the switch to y = D x.
+// Every chain of a (mode, part) redraws the start from the same counters.
+template <typename T, int M>
+__device__ __forceinline__ void chain_start(int s, int even, int h, uint32_t um, uint32_t up, uint32_t k0,
+                                            uint32_t k1, T sc, const T* __restrict__ fm, size_t set_stride,
+                                            T* __restrict__ g, size_t row, bool store, T& x0, T& x1)
+{
+    T nz[4];
+    x1 = T(0);
+    block_normals<T>((uint32_t)((s * M) >> 2), um, up, k0, k1, sc, nz);
+    {
+        const int w = (s * M) & 3;
+        const T w0 = pick4(nz, w);
+        if (M == 1) {
+            x0 = fm[1] * w0;
+        } else {
+            const T w1 = w == 0 ? nz[1] : nz[3];
+            x0 = fm[4] * w0;
+            x1 = fm[5] * w0 + fm[6] * w1;
+        }
+    }
+    if (h == 0) {
+        if (store) g[(size_t)s * row] = x0;
+        return;
+    }
+    if (even) {
+        // crossing s -> s+1 with set 1, in the true coordinates
+        const int r = s + 1;
+        const int w = (r * M) & 3;
+        T w0, w1 = T(0);
+        if (((r * M) >> 2) == ((s * M) >> 2)) {
+            w0 = pick4(nz, w);
+            if (M == 2) w1 = w == 0 ? nz[1] : nz[3];
+        } else {
+            T nc[4];
+            block_normals<T>((uint32_t)((r * M) >> 2), um, up, k0, k1, sc, nc);
+            w0 = pick4(nc, w);
+            if (M == 2) w1 = w == 0 ? nc[1] : nc[3];
+        }
+        chain_step<T, M>(fm + set_stride, x0, x1, w0, w1);
+        if (store) g[(size_t)r * row] = x0;
+    }
+    x1 = -x1;   // y = D x
 }
 
 // One chain.  `fm` points at the mode's record in factor set 0 (sets `set_stride` apart);
@@ -269,50 +318,14 @@ __device__ __forceinline__ void run_chain(int n, int s, int even, int n_sets, in
 {
     const T sc = (m == 0) ? T(1) : T(0.70710678118654752440);
     const uint32_t um = (uint32_t)m, up = (uint32_t)part;
-
-    // start, eq. (state_initial), at ring s
-    T nz[4];
-    T x0, x1 = T(0);
-    {
-        block_normals<T>((uint32_t)((s * M) >> 2), um, up, k0, k1, sc, nz);
-        const int w = (s * M) & 3;
-        const T w0 = pick4(nz, w);
-        if (M == 1) {
-            x0 = fm[1] * w0;
-        } else {
-            const T w1 = w == 0 ? nz[1] : nz[3];
-            x0 = fm[4] * w0;
-            x1 = fm[5] * w0 + fm[6] * w1;
-        }
-    }
-    if (h == 0) {
-        g[(size_t)s * row] = x0;
+    T x0, x1;
+    chain_start<T, M>(s, even, h, um, up, k0, k1, sc, fm, set_stride, g, row, true, x0, x1);
+    if (h == 0)
         walk_hemisphere<T, M, P, true>(s, even, s - 1, 0, m, part, k0, k1, sc, fm, set_stride, n_sets, g, row,
                                        x0, x1);
-    } else {
-        int r_lo = s + 1;
-        if (even) {
-            // crossing s -> s+1 with set 1, in the true coordinates
-            const int r = s + 1;
-            const int w = (r * M) & 3;
-            T w0, w1 = T(0);
-            if (((r * M) >> 2) == ((s * M) >> 2)) {
-                w0 = pick4(nz, w);
-                if (M == 2) w1 = w == 0 ? nz[1] : nz[3];
-            } else {
-                T nc[4];
-                block_normals<T>((uint32_t)((r * M) >> 2), um, up, k0, k1, sc, nc);
-                w0 = pick4(nc, w);
-                if (M == 2) w1 = w == 0 ? nc[1] : nc[3];
-            }
-            chain_step<T, M>(fm + set_stride, x0, x1, w0, w1);
-            g[(size_t)r * row] = x0;
-            r_lo = s + 2;
-        }
-        x1 = -x1;   // y = D x
-        walk_hemisphere<T, M, P, false>(s, even, r_lo, n - 1, m, part, k0, k1, sc, fm, set_stride, n_sets, g,
-                                        row, x0, x1);
-    }
+    else
+        walk_hemisphere<T, M, P, false>(s, even, even ? s + 2 : s + 1, n - 1, m, part, k0, k1, sc, fm,
+                                        set_stride, n_sets, g, row, x0, x1);
 }
 
 // Zero the slots of modes above m_top (and the imaginary part of g_0) in one hemisphere.

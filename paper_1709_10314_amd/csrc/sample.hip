@@ -47,6 +47,126 @@ __global__ __launch_bounds__(256) void recursion_kernel(RecArgs a, const T* __re
                     (size_t)a.n_phi);
 }
 
+// ------------------------------------------------------------------ affine scan
+// The recursion x_{k+1} = A_k x_k + B_k w_k (eq. (state_space)) is affine in x, so a chain
+// cut into ring blocks can run its blocks in parallel: block b started from zero gives c_b
+// (its end state driven by its own noise only), and the true start of block b is the fold
+// x_b = Phi_{b-1} x_{b-1} + c_{b-1} over the earlier blocks, with Phi the block transitions
+// stored at setup.  Block 0 starts from the real start state and stores its rings at once;
+// the other blocks walk twice, first without stores for c_b, then from x_b with stores,
+// recomputing the same counter-based normals (no workspace, about twice the arithmetic).
+//
+// A workgroup is one (field, hemisphere, m-tile of 32 modes) with one wave per ring block:
+// every wave covers the same 64 chains, so its loads and stores are as contiguous as the
+// plain recursion's, and the block end states meet in LDS across one barrier.
+struct ScanArgs {
+    int n_theta, n_phi, m_top, m_rows, n_sets, s, even;
+    int n_fh, n_wg, per_xcd;
+    int fine_per, fine;    // fine blocks per ring block; fine blocks in the plan
+    uint32_t seed_lo, seed_hi;
+};
+
+// Prefetch depth of a scan wave: a workgroup of B >= 8 waves leaves 2048 / B VGPRs per
+// lane, so the deeper scans keep shallower pipelines.
+template <typename T, int B>
+struct ScanDepth {
+    static constexpr int value = sizeof(T) == 4 ? (B >= 16 ? 2 : (B >= 8 ? 4 : 8)) : (B >= 8 ? 2 : 4);
+};
+
+template <typename T, int M, int B>
+__global__ __launch_bounds__(64 * B) void scan_kernel(ScanArgs a, const T* __restrict__ fac,
+                                                      const T* __restrict__ phi, T* __restrict__ out)
+{
+    __shared__ T ends[B * 64 * M];
+    const int bx = blockIdx.x;
+    const int L = (bx & 7) * a.per_xcd + (bx >> 3);
+    if (L >= a.n_wg) return;
+    const int mt = L / a.n_fh;
+    const int fh = L - mt * a.n_fh;
+    const int f = fh >> 1, h = fh & 1;
+    const int blk = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int m = mt * 32 + (lane >> 1), part = lane & 1;
+    const bool in_range = m < a.m_rows;
+    const bool active = in_range && m <= a.m_top && !(m == 0 && part == 1);
+    const size_t row = (size_t)a.n_phi;
+    T* __restrict__ g = out + (size_t)f * a.n_theta * a.n_phi + 2 * (in_range ? m : 0) + part;
+    if (in_range && !active && blk == 0) zero_chain<T>(a.n_theta, a.s, h, g, row);
+
+    const uint64_t key = (((uint64_t)a.seed_hi << 32) | a.seed_lo) + (uint64_t)f;
+    const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+    const int mm = active ? m : 0;
+    const T* __restrict__ fm = fac + (size_t)mm * factor_stride(M);
+    const size_t set_stride = (size_t)a.m_rows * factor_stride(M);
+    const T sc = (m == 0) ? T(1) : T(0.70710678118654752440);
+    const uint32_t um = (uint32_t)mm, up = (uint32_t)part;
+    const int j0 = a.even ? 2 : 1;
+    const long walk = a.n_sets - j0;
+    const int jb = j0 + (int)(walk * (blk * a.fine_per) / a.fine);
+    const int je = j0 + (int)(walk * ((blk + 1) * a.fine_per) / a.fine);
+    const int r_first = h == 0 ? a.s - jb + a.even : a.s + jb;
+    const int r_last = h == 0 ? a.s - (je - 1) + a.even : a.s + (je - 1);
+    constexpr int P = ScanDepth<T, B>::value;
+
+    // pass 1: block 0 from the start state (final, stored); the others from zero
+    T x0 = T(0), x1 = T(0);
+    if (active) {
+        if (blk == 0) chain_start<T, M>(a.s, a.even, h, um, up, k0, k1, sc, fm, set_stride, g, row, true, x0, x1);
+        if (h == 0)
+            walk_hemisphere<T, M, P, true>(a.s, a.even, r_first, r_last, mm, part, k0, k1, sc, fm, set_stride,
+                                           a.n_sets, g, row, x0, x1, blk == 0);
+        else
+            walk_hemisphere<T, M, P, false>(a.s, a.even, r_first, r_last, mm, part, k0, k1, sc, fm, set_stride,
+                                            a.n_sets, g, row, x0, x1, blk == 0);
+    }
+    ends[(blk * 64 + lane) * M] = x0;
+    if (M == 2) ends[(blk * 64 + lane) * M + 1] = x1;
+    __syncthreads();
+    if (blk == 0 || !active) return;
+
+    // fold: the start of this block
+    T y0 = ends[lane * M], y1 = M == 2 ? ends[lane * M + 1] : T(0);
+    for (int k = 1; k < blk; ++k) {
+        for (int i = k * a.fine_per; i < (k + 1) * a.fine_per; ++i) {
+            const T* __restrict__ p = phi + ((size_t)i * a.m_rows + mm) * (M * M);
+            if (M == 1) {
+                y0 = p[0] * y0;
+            } else {
+                const T t0 = fma(p[0], y0, p[1] * y1);
+                const T t1 = fma(p[2], y0, p[3] * y1);
+                y0 = t0;
+                y1 = t1;
+            }
+        }
+        y0 += ends[(k * 64 + lane) * M];
+        if (M == 2) y1 += ends[(k * 64 + lane) * M + 1];
+    }
+    // pass 2: this block again from its true start, with stores
+    x0 = y0;
+    x1 = y1;
+    if (h == 0)
+        walk_hemisphere<T, M, P, true>(a.s, a.even, r_first, r_last, mm, part, k0, k1, sc, fm, set_stride,
+                                       a.n_sets, g, row, x0, x1, true);
+    else
+        walk_hemisphere<T, M, P, false>(a.s, a.even, r_first, r_last, mm, part, k0, k1, sc, fm, set_stride,
+                                        a.n_sets, g, row, x0, x1, true);
+}
+
+template <typename T, int M>
+void launch_scan_t(const ScanArgs& a, int blocks, const T* fac, const T* phi, T* out, hipStream_t st)
+{
+    const dim3 grid((unsigned)(a.per_xcd * 8));
+    switch (blocks) {
+        case 2: hipLaunchKernelGGL((scan_kernel<T, M, 2>), grid, dim3(128), 0, st, a, fac, phi, out); break;
+        case 4: hipLaunchKernelGGL((scan_kernel<T, M, 4>), grid, dim3(256), 0, st, a, fac, phi, out); break;
+        case 8: hipLaunchKernelGGL((scan_kernel<T, M, 8>), grid, dim3(512), 0, st, a, fac, phi, out); break;
+        default:
+            if constexpr (sizeof(T) == 4)   // FP64 scans stop at 8 blocks
+                hipLaunchKernelGGL((scan_kernel<T, M, 16>), grid, dim3(1024), 0, st, a, fac, phi, out);
+            break;
+    }
+}
+
 // Threads per row: H/8 clamped to [64, 256], and 512 for the largest rows (FP32 n_phi =
 // 16384, FP64 n_phi >= 8192) so that each thread holds fewer butterflies.
 template <typename T, int LOG2H>
@@ -154,6 +274,37 @@ hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, uint64
         else
             hipLaunchKernelGGL((recursion_kernel<float, 2>), grid, dim3(256), 0, st, a,
                                (const float*)fac, (float*)out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const Geometry& g, int fp64, const void* fac, const void* phi, int fine_blocks,
+                       int blocks, uint64_t seed, int count, void* out, hipStream_t st)
+{
+    if (blocks < 2 || blocks > scan_max_blocks(fp64) || (blocks & (blocks - 1)) || fine_blocks % blocks)
+        return hipErrorInvalidValue;
+    ScanArgs a;
+    a.n_theta = g.n_theta;
+    a.n_phi = g.n_phi;
+    a.m_top = g.m_top;
+    a.m_rows = g.m_rows;
+    a.n_sets = g.n_sets;
+    a.s = g.s;
+    a.even = g.even;
+    a.n_fh = 2 * count;
+    a.fine_per = fine_blocks / blocks;
+    a.fine = fine_blocks;
+    const int n_mt = (g.m_rows + 31) / 32;
+    a.n_wg = n_mt * a.n_fh;
+    a.per_xcd = (a.n_wg + 7) / 8;
+    a.seed_lo = (uint32_t)seed;
+    a.seed_hi = (uint32_t)(seed >> 32);
+    if (fp64) {
+        if (g.order == 1) launch_scan_t<double, 1>(a, blocks, (const double*)fac, (const double*)phi, (double*)out, st);
+        else launch_scan_t<double, 2>(a, blocks, (const double*)fac, (const double*)phi, (double*)out, st);
+    } else {
+        if (g.order == 1) launch_scan_t<float, 1>(a, blocks, (const float*)fac, (const float*)phi, (float*)out, st);
+        else launch_scan_t<float, 2>(a, blocks, (const float*)fac, (const float*)phi, (float*)out, st);
     }
     return hipGetLastError();
 }

@@ -276,7 +276,54 @@ __global__ __launch_bounds__(64) void factor_kernel(Geometry g, const double* __
     }
 }
 
+// Block transitions for the affine scan across rings: for fine block b of the main-walk
+// sets [J_b, J_{b+1}), J_b = j0 + floor(walk b / blocks), the product
+// Phi_b = A_{J_{b+1}-1} ... A_{J_b} of the step matrices of eq. (state_space), i.e. the map
+// the block applies to its start state when its noise is zero.  One thread per (m, b).
+template <int M>
+__global__ __launch_bounds__(64) void phi_kernel(Geometry g, const double* __restrict__ f64, int blocks,
+                                                 double* __restrict__ phi64, float* __restrict__ phi32)
+{
+    const int m = blockIdx.x * 64 + threadIdx.x;
+    const int b = blockIdx.y;
+    if (m > g.m_top) return;
+    const int j0 = g.even ? 2 : 1;
+    const long walk = g.n_sets - j0;
+    const int jb = j0 + (int)(walk * b / blocks), je = j0 + (int)(walk * (b + 1) / blocks);
+    constexpr int E = M == 1 ? 2 : 8;
+    double p[M * M];
+#pragma unroll
+    for (int i = 0; i < M * M; ++i) p[i] = (i % (M + 1) == 0) ? 1.0 : 0.0;
+    for (int j = jb; j < je; ++j) {
+        const double* r = f64 + ((size_t)j * g.m_rows + m) * E;
+        if (M == 1) {
+            p[0] = r[0] * p[0];
+        } else {
+            const double q00 = r[0] * p[0] + r[1] * p[2], q01 = r[0] * p[1] + r[1] * p[3];
+            const double q10 = r[2] * p[0] + r[3] * p[2], q11 = r[2] * p[1] + r[3] * p[3];
+            p[0] = q00; p[1] = q01; p[2] = q10; p[3] = q11;
+        }
+    }
+    const size_t o = ((size_t)b * g.m_rows + m) * (M * M);
+#pragma unroll
+    for (int i = 0; i < M * M; ++i) {
+        phi64[o + i] = p[i];
+        if (phi32) phi32[o + i] = (float)p[i];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_phi(const Geometry& g, const double* f64, int blocks, double* phi64, float* phi32,
+                      hipStream_t st)
+{
+    dim3 grid((g.m_top + 64) / 64, blocks);
+    if (g.order == 1)
+        hipLaunchKernelGGL(phi_kernel<1>, grid, dim3(64), 0, st, g, f64, blocks, phi64, phi32);
+    else
+        hipLaunchKernelGGL(phi_kernel<2>, grid, dim3(64), 0, st, g, f64, blocks, phi64, phi32);
+    return hipGetLastError();
+}
 
 hipError_t launch_spectrum(const double* kappa_dev, int n_kappa, const double* c_explicit_dev,
                            int ell_max, double* C_dev, int* bad_dev, hipStream_t st)

@@ -52,12 +52,38 @@ hipError_t launch_spectrum(const double* kappa_dev, int n_kappa, const double* c
 hipError_t launch_factors(const Geometry& g, const double* C_dev, double* f64, float* f32,
                           hipStream_t st);
 hipError_t launch_twiddles(int n_phi, double* tw64, float* tw32, hipStream_t st);
+// Phi per (fine ring block, m) for the affine scan, layout [block][m][M*M], m stride m_rows.
+hipError_t launch_phi(const Geometry& g, const double* f64, int blocks, double* phi64, float* phi32,
+                      hipStream_t st);
+
+// ---- affine scan across rings ----
+// Main-walk sets [j0, n_sets) of a hemisphere, j0 = 2 for even n_theta (set 1 is the
+// crossing) else 1.  The plan cuts them into scan_fine fine blocks (a power of two <= 16,
+// each of >= kScanMinSets sets, or 1 when the walk is too short); a scanned call uses
+// `blocks` ring blocks of scan_fine / blocks fine blocks each.
+constexpr int kScanMaxBlocks = 16;
+constexpr int kScanMinSets = 8;
+constexpr int kScanAutoMinSets = 32;   // the automatic choice keeps blocks this long
+// a scanned call runs one wave per ring block in a workgroup: 16 (FP32) or 8 (FP64, whose
+// walk needs up to 256 VGPRs) waves at most
+inline int scan_max_blocks(int fp64) { return fp64 ? 8 : 16; }
+inline int scan_fine_blocks(const Geometry& g)
+{
+    const int walk = g.n_sets - (g.even ? 2 : 1);
+    int b = 1;
+    while (b < kScanMaxBlocks && walk / (2 * b) >= kScanMinSets) b *= 2;
+    return b;
+}
 
 // ---- sampling ----
 hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, uint64_t seed, int count,
                             void* out, hipStream_t st);
 hipError_t launch_c2r(const Geometry& g, int fp64, const void* tw, int count, void* data,
                       hipStream_t st);
+// The chains of launch_recursion as an affine scan over `blocks` ring blocks per chain
+// (blocks >= 2 dividing fine_blocks; phi holds the plan's fine-block transitions).
+hipError_t launch_scan(const Geometry& g, int fp64, const void* fac, const void* phi, int fine_blocks,
+                       int blocks, uint64_t seed, int count, void* out, hipStream_t st);
 
 }  // namespace smf
 
@@ -75,4 +101,8 @@ struct smf_plan {
     float* tw32;
     int device;
     smf::BatchState* batch;   // non-null for a batch plan (see smf_setup_batch)
+    int scan_fine;            // fine ring blocks with a stored transition (1: no scan)
+    int scan_req;             // ring blocks asked for: 0 automatic, 1 never, else that many
+    double* phi64;            // [scan_fine][m_rows][M*M] block transitions
+    float* phi32;
 };

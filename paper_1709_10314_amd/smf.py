@@ -17,7 +17,8 @@ SMF_OK, SMF_EINVAL, SMF_ENOMEM, SMF_EHIP, SMF_ENUMERIC = 0, -1, -2, -3, -4
 SMF_FP64, SMF_FP32 = 1, 2
 
 # every symbol include/smf.h declares
-EXPORTS = ("smf_setup", "smf_sample", "smf_sample_modes", "smf_plan_dims", "smf_get_factors",
+EXPORTS = ("smf_setup", "smf_sample", "smf_sample_modes", "smf_set_ring_blocks", "smf_get_ring_blocks",
+           "smf_plan_dims", "smf_get_factors",
            "smf_destroy", "smf_error_string", "smf_setup_batch", "smf_batch_layout",
            "smf_sample_batch", "smf_autotune_batch")
 
@@ -55,6 +56,8 @@ def load():
     lib.smf_setup.argtypes = [ctypes.POINTER(smf_spectrum), i, i, i, vp, ctypes.POINTER(vp)]
     lib.smf_sample.argtypes = [vp, u64, i, vp, vp]
     lib.smf_sample_modes.argtypes = [vp, u64, i, vp, vp]
+    lib.smf_set_ring_blocks.argtypes = [vp, i]
+    lib.smf_get_ring_blocks.argtypes = [vp, i, ctypes.POINTER(ctypes.c_int)]
     lib.smf_plan_dims.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     lib.smf_get_factors.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.smf_destroy.argtypes = [vp]
@@ -65,7 +68,8 @@ def load():
     lib.smf_batch_layout.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     lib.smf_sample_batch.argtypes = [vp, u64, vp, vp]
     lib.smf_autotune_batch.argtypes = [vp, u64, vp, vp, ctypes.POINTER(ctypes.c_int)]
-    for name in ("smf_setup", "smf_sample", "smf_sample_modes", "smf_plan_dims",
+    for name in ("smf_setup", "smf_sample", "smf_sample_modes", "smf_set_ring_blocks", "smf_get_ring_blocks",
+                 "smf_plan_dims",
                  "smf_get_factors", "smf_destroy", "smf_setup_batch", "smf_batch_layout",
                  "smf_sample_batch", "smf_autotune_batch"):
         getattr(lib, name).restype = i
@@ -118,6 +122,16 @@ def smf_sample(plan, seed, count, out_ptr, stream=None):
 def smf_sample_modes(plan, seed, count, g_ptr, stream=None):
     return load().smf_sample_modes(plan, ctypes.c_uint64(int(seed)), int(count), ctypes.c_void_p(g_ptr),
                                    _stream_handle(stream))
+
+
+def smf_set_ring_blocks(plan, blocks):
+    return load().smf_set_ring_blocks(plan, int(blocks))
+
+
+def smf_get_ring_blocks(plan, count):
+    b = ctypes.c_int(0)
+    rc = load().smf_get_ring_blocks(plan, int(count), ctypes.byref(b))
+    return rc, b.value
 
 
 def smf_plan_dims(plan):
@@ -281,6 +295,19 @@ class Plan:
         if rc != SMF_OK:
             raise SmfError(rc, "smf_sample")
         return out
+
+    def set_ring_blocks(self, blocks):
+        """Affine-scan ring blocks: 0 automatic, 1 never, 2/4/8/16 always (capped)."""
+        rc = smf_set_ring_blocks(self._h, blocks)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_set_ring_blocks")
+
+    def ring_blocks(self, count):
+        """Ring blocks a call with `count` fields uses (1 = plain recursion)."""
+        rc, b = smf_get_ring_blocks(self._h, count)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_get_ring_blocks")
+        return b
 
     def sample_modes(self, seed, count, out=None, stream=None):
         """Pre-FFT modes g_m as [count, n_theta, n_phi/2, 2] (Re, Im) in the sample dtype."""

@@ -22,9 +22,12 @@ TOL = {"fp64": 1e-10, "fp32": 1e-4}
 
 
 def _plan(order, n_theta, n_phi, ell_max, kappa, precision):
+    """A plan that always runs the plain recursion (the affine scan has its own tests)."""
     from paper_1709_10314_amd import Plan
 
-    return Plan(order, n_theta, n_phi, ell_max, kappa=[kappa] * order, precision=precision)
+    p = Plan(order, n_theta, n_phi, ell_max, kappa=[kappa] * order, precision=precision)
+    p.set_ring_blocks(1)
+    return p
 
 
 def _gpu_modes(plan, seed, count):

@@ -22,6 +22,20 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak: 256 CUs x 4 SIMDs x 32 FP32 lanes per clock x 2.4 GHz (the published FP32
+# vector peak, 157.3 TFLOP/s, is this rate times 2 flops per FMA), in lane-slots per second
+VALU_PEAK_SLOTS = 256 * 4 * 32 * 2.4e9
+
+
+def alu_slots_per_point(order):
+    """Lane-slots of the recursion's arithmetic per output point (one chain step), counting a
+    full-rate VALU op as 1 and the quarter-rate ones (32x32->64 multiply, log, sqrt, sin,
+    cos) as 4.  Per normal: Philox4x32-10 is 10 rounds of 2 multiplies and 4 xors per
+    4 words, 30 slots; Box-Muller is 2 conversions, 2 fma, 4 transcendentals and 4
+    multiplies per pair, 12 slots.  The step itself: 2 (M = 1) or 7 (M = 2) FMA-class ops."""
+    philox = 10 * (2 * 4 + 4) / 4
+    box_muller = (2 + 2 + 4 * 4 + 4) / 2
+    return order * (philox + box_muller) + {1: 2, 2: 7}[order]
 
 
 def log(msg):
@@ -55,6 +69,29 @@ def time_calls(fn, steps, warmup):
     return e0.elapsed_time(e1) / steps, wall
 
 
+def time_split(plan, seed, count, out, steps, warmup):
+    """Average ms per launch of the recursion and of the FFT inside one timed loop of the
+    two launches of a sampling call (smf_sample_modes then smf_transform), HIP events
+    between them on the launch stream."""
+    import torch
+
+    for _ in range(warmup):
+        g = plan.sample_modes(seed, count, out)
+        plan.transform(g, count)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for e in ev:
+        e[0].record()
+        g = plan.sample_modes(seed, count, out)
+        e[1].record()
+        plan.transform(g, count)
+        e[2].record()
+    torch.cuda.synchronize()
+    rec = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+    fft = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+    return rec, fft
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch from committed rocprofv3 PMC summaries, if they were taken on
     the current kernel sources; else None."""
@@ -72,14 +109,14 @@ def measured_traffic(kernel):
 
 
 def cpu_baseline(cfg, rings):
-    """The FP64 oracle (chains + naive DFT) on `rings` rings around the equator of one
-    field of the workload; its factor sets are built first, untimed."""
+    """The FP64 oracle (chains + naive DFT) on `rings` rings around the equator of every
+    field of the workload; the factor sets those rings need are built first, untimed."""
     import numpy as np
 
     import oracle
     from paper_1709_10314_amd import workloads
 
-    n, nphi, order, lmax = cfg["n_theta"], cfg["n_phi"], cfg["order"], cfg["ell_max"]
+    n, nphi, order, lmax, count = cfg["n_theta"], cfg["n_phi"], cfg["order"], cfg["ell_max"], cfg["count"]
     s = n // 2 - 1
     sets = rings // 2 + 1
     C = oracle.spectrum(workloads.kappas(cfg), lmax)
@@ -88,15 +125,15 @@ def cpu_baseline(cfg, rings):
     t_setup = time.perf_counter() - t0
     r0, r1 = s - rings // 2 + 1, s + rings // 2 + 1
     t0 = time.perf_counter()
-    g = oracle.sample_modes(order, n, A, B, cfg["seed"], 1, sets=sets)
+    g = oracle.sample_modes(order, n, A, B, cfg["seed"], count, sets=sets)
     T = oracle.dft(g, nphi, r0, r1)
     dt = time.perf_counter() - t0
     assert np.all(np.isfinite(T))
-    pts = rings * nphi
+    pts = count * rings * nphi
     return {"value": pts / dt, "unit": "grid points/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": (f"{cfg['name']}: field 1, the {rings} rings around the equator (all "
-                       f"{lmax + 1} modes), chains + naive DFT in FP64; setup of the {sets} "
-                       f"factor sets they need ({t_setup:.1f} s) not timed"),
+            "sample": (f"{cfg['name']}: all {count} fields, the {rings} rings around the equator (all "
+                       f"{lmax + 1} modes, {pts} points), chains + naive DFT in FP64; setup of the "
+                       f"{sets} factor sets they need ({t_setup:.1f} s) not timed"),
             "seconds": dt}
 
 
@@ -107,7 +144,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--cpu-rings", type=int, default=96)
+    ap.add_argument("--cpu-rings", type=int, default=384)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (calibrates rocprofv3 FETCH/WRITE_SIZE)")
     args = ap.parse_args()
@@ -146,9 +183,8 @@ def main():
     log(f"  setup {setup_s:.2f} s; timing {args.steps} steps")
     ms_step, wall_step = time_calls(lambda: plan.sample(seed, count, out), args.steps, args.warmup)
     log(f"  {ms_step:.3f} ms/step ({pts / ms_step * 1e3:.3e} pts/s)")
-    ms_rec, _ = time_calls(lambda: plan.sample_modes(seed, count, out), args.steps, args.warmup)
-    ms_fft = max(ms_step - ms_rec, 1e-9)
-    log(f"  recursion {ms_rec:.3f} ms, fft {ms_fft:.3f} ms")
+    ms_rec, ms_fft = time_split(plan, seed, count, out, args.steps, args.warmup)
+    log(f"  recursion {ms_rec:.3f} ms, fft {ms_fft:.3f} ms per launch")
     m_top = plan.m_top
     n_sets = plan.n_sets
     plan.close()
@@ -167,22 +203,33 @@ def main():
         fp64 = {"value": pts / ms64 * 1e3, "unit": "grid points/s", "ms_per_step": ms64}
         log(f"  fp64 {ms64:.3f} ms/step")
 
-    # algorithmic bytes per launch (see the design notes for the per-unit figures)
+    # algorithmic work per launch (see the design notes for the per-unit figures): the
+    # recursion reads the FP32 factors once and writes the modes, and its arithmetic is
+    # alu_slots_per_point per point; the FFT reads and writes every point once
     vals_per_rec = order * order + order * (order + 1) // 2
     fac_bytes = n_sets * (m_top + 1) * vals_per_rec * 4
     g_bytes = count * n * (nphi // 2) * 8
+    rec_slots = pts * alu_slots_per_point(order)
     kernels = {
-        "recursion": {"ms": ms_rec, "alg_bytes": fac_bytes + g_bytes},
+        "recursion": {"ms": ms_rec, "alg_bytes": fac_bytes + g_bytes, "alu_slots": rec_slots},
         "c2r_fft": {"ms": ms_fft, "alg_bytes": 2 * count * n * nphi * 4},
     }
     for k, v in kernels.items():
         v["alg_GBs"] = v["alg_bytes"] / (v["ms"] * 1e-3) / 1e9
+        v["hbm_frac"] = v["alg_GBs"] / HBM_PEAK_GBS
+    kr = kernels["recursion"]
+    kr["alu_Tslots"] = rec_slots / (ms_rec * 1e-3) / 1e12
+    kr["alu_frac"] = kr["alu_Tslots"] * 1e12 / VALU_PEAK_SLOTS
     dom = max(kernels, key=lambda k: kernels[k]["ms"])
     kd = kernels[dom]
     traffic = measured_traffic(dom)
-    roofline = {"bound": "hbm", "achieved": kd["alg_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": kd["alg_GBs"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
-                "path_alg_GBs": (fac_bytes + g_bytes + 2 * count * n * nphi * 4) / (ms_step * 1e-3) / 1e9}
+    if dom == "recursion":
+        roofline = {"bound": "alu", "achieved": kr["alu_Tslots"], "peak": VALU_PEAK_SLOTS / 1e12,
+                    "unit": "T lane-slots/s", "frac": kr["alu_frac"], "traffic": traffic, "kernel": dom}
+    else:
+        roofline = {"bound": "hbm", "achieved": kd["alg_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": kd["hbm_frac"], "traffic": traffic, "kernel": dom}
+    roofline["path_alg_GBs"] = (fac_bytes + g_bytes + 2 * count * n * nphi * 4) / (ms_step * 1e-3) / 1e9
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -87,6 +87,14 @@ int smf_sample(const smf_plan* plan, uint64_t seed, int count, void* out_dev, vo
  * entries for m > m_top are zero.  Same size and errors as smf_sample. */
 int smf_sample_modes(const smf_plan* plan, uint64_t seed, int count, void* g_dev, void* hip_stream);
 
+/* The last step of Alg. 2 on its own: the unnormalised complex-to-real inverse DFT along
+ * phi of every ring, T(z_i, phi_j) = g_0 + 2 sum_{m=1}^{m_top} Re(g_m e^{i m phi_j}), in
+ * place.  data_dev holds count fields of modes in the layout smf_sample_modes writes
+ * (entries m > m_top and the imaginary part of g_0 are ignored) and receives the fields in
+ * the layout smf_sample writes.  smf_sample = smf_sample_modes then smf_transform.
+ * Errors: SMF_EINVAL (NULL plan/data with count > 0, count < 0, batch plan), SMF_EHIP. */
+int smf_transform(const smf_plan* plan, int count, void* data_dev, void* hip_stream);
+
 /* Ring blocks of the affine scan (single-field plans).  The recursion of eq. (state_space)
  * is affine in the state, so a chain cut into ring blocks can run its blocks in parallel:
  * each block's end state from zero start, then the true block starts by composing the

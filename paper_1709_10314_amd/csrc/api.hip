@@ -230,6 +230,18 @@ int smf_sample_modes(const smf_plan* plan, uint64_t seed, int count, void* g_dev
     return sample_common(plan, seed, count, g_dev, hip_stream, false);
 }
 
+int smf_transform(const smf_plan* plan, int count, void* data_dev, void* hip_stream)
+{
+    if (!plan || plan->batch || count < 0) return SMF_EINVAL;
+    if (count == 0) return SMF_OK;
+    if (!data_dev) return SMF_EINVAL;
+    DeviceGuard dg(plan->device);
+    const int fp64 = plan->flags == SMF_FP64;
+    const void* tw = fp64 ? (const void*)plan->tw64 : (const void*)plan->tw32;
+    return smf::launch_c2r(plan->g, fp64, tw, count, data_dev, (hipStream_t)hip_stream) == hipSuccess ? SMF_OK
+                                                                                                      : SMF_EHIP;
+}
+
 int smf_set_ring_blocks(smf_plan* plan, int blocks)
 {
     if (!plan || plan->batch || blocks < 0 || blocks > smf::kScanMaxBlocks) return SMF_EINVAL;

@@ -337,7 +337,8 @@ __device__ __forceinline__ void zero_chain(int n, int s, int h, T* __restrict__ 
 }
 
 // ------------------------------------------------------------------ C2R FFT
-// Per ring: X_m = g_m (m <= m_top, else 0; X_{N-m} = conj X_m), N = n_phi, H = N/2.
+// Per ring: X_m = g_m (m <= m_top, else 0; X_0 taken real; X_{N-m} = conj X_m), N = n_phi,
+// H = N/2.
 //   T_j = sum_m X_m e^{2 pi i m j / N}
 // via one complex inverse FFT of length H: with w = e^{2 pi i / N},
 //   Z_k = (X_k + conj X_{H-k}) + i w^k (X_k - conj X_{H-k}),  k < H  (X_H = 0),
@@ -501,6 +502,7 @@ __device__ __forceinline__ void c2r_load(const Cx<T>* __restrict__ row, int m_to
         xb[i] = zero;
         if (S::HALF % NT == 0 || k < S::HALF) {
             if (k <= m_top) xa[i] = row[k];
+            if (k == 0) xa[i].im = T(0);                      // g_0 is real
             if (k > 0 && S::H - k <= m_top) xb[i] = row[S::H - k];
         }
     }
@@ -557,6 +559,7 @@ __device__ __forceinline__ void c2r_row(T* __restrict__ data_row, const T* __res
         xa[0] = xb[0] = xa[1] = zero;
         if (S::HALF % NT == 0 || k < S::HALF) {
             if (k <= m_top) xa[0] = row[k];
+            if (k == 0) xa[0].im = T(0);                      // g_0 is real
             if (k > 0 && H - k <= m_top) xb[0] = row[H - k];
             const Cx<T> a = xa[0], b = xb[0];
             const Cx<T> ca = {a.re, -a.im}, cb = {b.re, -b.im};

@@ -17,7 +17,8 @@ SMF_OK, SMF_EINVAL, SMF_ENOMEM, SMF_EHIP, SMF_ENUMERIC = 0, -1, -2, -3, -4
 SMF_FP64, SMF_FP32 = 1, 2
 
 # every symbol include/smf.h declares
-EXPORTS = ("smf_setup", "smf_sample", "smf_sample_modes", "smf_set_ring_blocks", "smf_get_ring_blocks",
+EXPORTS = ("smf_setup", "smf_sample", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks",
+           "smf_get_ring_blocks",
            "smf_plan_dims", "smf_get_factors",
            "smf_destroy", "smf_error_string", "smf_setup_batch", "smf_batch_layout",
            "smf_sample_batch", "smf_autotune_batch")
@@ -56,6 +57,7 @@ def load():
     lib.smf_setup.argtypes = [ctypes.POINTER(smf_spectrum), i, i, i, vp, ctypes.POINTER(vp)]
     lib.smf_sample.argtypes = [vp, u64, i, vp, vp]
     lib.smf_sample_modes.argtypes = [vp, u64, i, vp, vp]
+    lib.smf_transform.argtypes = [vp, i, vp, vp]
     lib.smf_set_ring_blocks.argtypes = [vp, i]
     lib.smf_get_ring_blocks.argtypes = [vp, i, ctypes.POINTER(ctypes.c_int)]
     lib.smf_plan_dims.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
@@ -68,7 +70,7 @@ def load():
     lib.smf_batch_layout.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     lib.smf_sample_batch.argtypes = [vp, u64, vp, vp]
     lib.smf_autotune_batch.argtypes = [vp, u64, vp, vp, ctypes.POINTER(ctypes.c_int)]
-    for name in ("smf_setup", "smf_sample", "smf_sample_modes", "smf_set_ring_blocks", "smf_get_ring_blocks",
+    for name in ("smf_setup", "smf_sample", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks", "smf_get_ring_blocks",
                  "smf_plan_dims",
                  "smf_get_factors", "smf_destroy", "smf_setup_batch", "smf_batch_layout",
                  "smf_sample_batch", "smf_autotune_batch"):
@@ -122,6 +124,10 @@ def smf_sample(plan, seed, count, out_ptr, stream=None):
 def smf_sample_modes(plan, seed, count, g_ptr, stream=None):
     return load().smf_sample_modes(plan, ctypes.c_uint64(int(seed)), int(count), ctypes.c_void_p(g_ptr),
                                    _stream_handle(stream))
+
+
+def smf_transform(plan, count, data_ptr, stream=None):
+    return load().smf_transform(plan, int(count), ctypes.c_void_p(data_ptr), _stream_handle(stream))
 
 
 def smf_set_ring_blocks(plan, blocks):
@@ -295,6 +301,15 @@ class Plan:
         if rc != SMF_OK:
             raise SmfError(rc, "smf_sample")
         return out
+
+    def transform(self, data, count, stream=None):
+        """In-place C2R of `count` fields of modes (the sample_modes layout) into fields;
+        returns the [count, n_theta, n_phi] view of `data`."""
+        self._check_out(data, count)
+        rc = smf_transform(self._h, count, data.data_ptr(), stream)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_transform")
+        return data.view(-1)[: count * self.n_theta * self.n_phi].view(count, self.n_theta, self.n_phi)
 
     def set_ring_blocks(self, blocks):
         """Affine-scan ring blocks: 0 automatic, 1 never, 2/4/8/16 always (capped)."""

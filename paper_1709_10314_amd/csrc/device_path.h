@@ -92,10 +92,10 @@ __device__ __forceinline__ void chain_step_rec(const Rec<T, M>& R, T& x0, T& x1,
 
 // Philox groups kept in flight by the register prefetch pipeline of a chain walk.
 #ifndef SMF_CHAIN_P32
-#define SMF_CHAIN_P32 8
+#define SMF_CHAIN_P32 4
 #endif
 #ifndef SMF_CHAIN_P64
-#define SMF_CHAIN_P64 4
+#define SMF_CHAIN_P64 2
 #endif
 template <typename T>
 struct ChainDepth {
@@ -105,6 +105,12 @@ struct ChainDepth {
 // Rings are walked in groups of G = 4/M that share one Philox block (counter block
 // (ring M) / 4).  Ring r uses set j = s - r + even walking north and j = r - s walking
 // south; the southern noise is D w (second component negated).
+//
+// A lane runs NCH chains of one mode that share every factor record: NCH = 1 is the
+// chain of one part (`up0`), NCH = 2 the Re and Im chains (parts 0 and 1), whose values
+// are adjacent in the output and stored as one pair.  `sc[c]` scales chain c's normals
+// (1 for m = 0, 1/sqrt(2) for the parts of m > 0, 0 for the imaginary part of m = 0,
+// which keeps that chain exactly zero).
 //
 // A group that is cut by the start or the last ring is stepped with direct loads.  Full
 // groups run through a register prefetch pipeline: the G records of full group q are
@@ -120,40 +126,60 @@ __device__ __forceinline__ int set_of_ring(int r, int s, int even, int n_sets)
     return j < 0 ? 0 : (j >= n_sets ? n_sets - 1 : j);
 }
 
-template <typename T, int M, bool NORTH>
+// x0 of the NCH chains into ring slot `off` of g
+template <typename T, int NCH>
+__device__ __forceinline__ void store_ring(T* __restrict__ g, size_t off, const T (&x0)[NCH])
+{
+    if constexpr (NCH == 1) {
+        g[off] = x0[0];
+    } else {
+        using V2 = typename Vec2<T>::type;
+        V2 v;
+        v.x = x0[0];
+        v.y = x0[1];
+        *reinterpret_cast<V2*>(g + off) = v;
+    }
+}
+
+template <typename T, int M, bool NORTH, int NCH>
 __device__ __forceinline__ void step_group_direct(int base, int lo, int hi, int s, int even, int n_sets,
-                                                  uint32_t um, uint32_t up, uint32_t k0, uint32_t k1, T sc,
-                                                  const T* __restrict__ fm, size_t set_stride,
-                                                  T* __restrict__ g, size_t row, T& x0, T& x1, bool store)
+                                                  uint32_t um, uint32_t up0, uint32_t k0, uint32_t k1,
+                                                  const T (&sc)[NCH], const T* __restrict__ fm,
+                                                  size_t set_stride, T* __restrict__ g, size_t row,
+                                                  T (&x0)[NCH], T (&x1)[NCH], bool store)
 {
     constexpr int G = 4 / M;
-    T nb[4];
-    block_normals<T>((uint32_t)((base * M) >> 2), um, up, k0, k1, sc, nb);
+    T nb[NCH][4];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) block_normals<T>((uint32_t)((base * M) >> 2), um, up0 + c, k0, k1, sc[c], nb[c]);
 #pragma unroll
     for (int tt = 0; tt < G; ++tt) {
         const int t = NORTH ? G - 1 - tt : tt;
         const int r = base + t;
         if (r >= lo && r <= hi) {
             const Rec<T, M> R = load_rec<T, M>(fm + (size_t)set_of_ring<T, M, NORTH>(r, s, even, n_sets) * set_stride);
-            const T w0 = nb[t * M];
-            const T w1 = M == 2 ? (NORTH ? nb[t * M + 1] : -nb[t * M + 1]) : T(0);
-            chain_step_rec<T, M>(R, x0, x1, w0, w1);
-            if (store) g[(size_t)r * row] = x0;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const T w0 = nb[c][t * M];
+                const T w1 = M == 2 ? (NORTH ? nb[c][t * M + 1] : -nb[c][t * M + 1]) : T(0);
+                chain_step_rec<T, M>(R, x0[c], x1[c], w0, w1);
+            }
+            if (store) store_ring<T, NCH>(g, (size_t)r * row, x0);
         }
     }
 }
 
 // Walks rings r_first..r_last (north: descending, south: ascending), storing each ring's
 // x0 unless `store` is false (then only the end state is wanted).
-template <typename T, int M, int P, bool NORTH>
-__device__ __forceinline__ void walk_hemisphere(int s, int even, int r_first, int r_last, int m, int part,
-                                                uint32_t k0, uint32_t k1, T sc,
-                                                const T* __restrict__ fm, size_t set_stride,
-                                                int n_sets, T* __restrict__ g, size_t row, T& x0, T& x1,
+template <typename T, int M, int P, bool NORTH, int NCH>
+__device__ __forceinline__ void walk_hemisphere(int s, int even, int r_first, int r_last, int m, uint32_t up0,
+                                                uint32_t k0, uint32_t k1, const T (&sc)[NCH],
+                                                const T* __restrict__ fm, size_t set_stride, int n_sets,
+                                                T* __restrict__ g, size_t row, T (&x0)[NCH], T (&x1)[NCH],
                                                 bool store = true)
 {
     constexpr int G = 4 / M;
-    const uint32_t um = (uint32_t)m, up = (uint32_t)part;
+    const uint32_t um = (uint32_t)m;
     if (NORTH ? r_first < r_last : r_first > r_last) return;
     // cut first group, then full groups q = 0..ng-1 with bases b0 - q G (north) or
     // b0 + q G (south), then a cut last group
@@ -162,8 +188,8 @@ __device__ __forceinline__ void walk_hemisphere(int s, int even, int r_first, in
         int top = r_first;
         const int base = (top / G) * G;
         if (top != base + G - 1 || base < r_last) {
-            step_group_direct<T, M, true>(base, base > r_last ? base : r_last, top, s, even, n_sets, um, up, k0,
-                                          k1, sc, fm, set_stride, g, row, x0, x1, store);
+            step_group_direct<T, M, true, NCH>(base, base > r_last ? base : r_last, top, s, even, n_sets, um, up0,
+                                               k0, k1, sc, fm, set_stride, g, row, x0, x1, store);
             top = base - 1;
         }
         ng = top + 1 - r_last >= G ? (top + 1 - r_last) / G : 0;
@@ -172,8 +198,8 @@ __device__ __forceinline__ void walk_hemisphere(int s, int even, int r_first, in
         int lo = r_first;
         const int base = (lo / G) * G;
         if (lo != base || base + G - 1 > r_last) {
-            step_group_direct<T, M, false>(base, lo, base + G - 1 < r_last ? base + G - 1 : r_last, s, even, n_sets,
-                                           um, up, k0, k1, sc, fm, set_stride, g, row, x0, x1, store);
+            step_group_direct<T, M, false, NCH>(base, lo, base + G - 1 < r_last ? base + G - 1 : r_last, s, even,
+                                                n_sets, um, up0, k0, k1, sc, fm, set_stride, g, row, x0, x1, store);
             lo = base + G;
         }
         ng = r_last - lo + 1 >= G ? (r_last - lo + 1) / G : 0;
@@ -190,32 +216,41 @@ __device__ __forceinline__ void walk_hemisphere(int s, int even, int r_first, in
         }
         int q = 0;
         for (; q + P <= ng; q += P) {
-            // the P Philox blocks of this stage in lockstep, then their normals
-            uint32_t blk[P];
+            // the P x NCH Philox blocks of this stage in lockstep, then their normals
+            uint32_t blk[P * NCH], prt[P * NCH];
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const int base = NORTH ? b0 - (q + p) * G : b0 + (q + p) * G;
-                blk[p] = (uint32_t)((base * M) >> 2);
-            }
-            PhiloxBlock wb[P];
-            philox4x32_10_n<P>(blk, um, up, k0, k1, wb);
-            T nbs[P][4];
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                BoxMuller<T>::pair(wb[p].w[0], wb[p].w[1], sc, nbs[p][0], nbs[p][1]);
-                BoxMuller<T>::pair(wb[p].w[2], wb[p].w[3], sc, nbs[p][2], nbs[p][3]);
+                for (int c = 0; c < NCH; ++c) {
+                    blk[p * NCH + c] = (uint32_t)((base * M) >> 2);
+                    prt[p * NCH + c] = up0 + c;
+                }
             }
+            PhiloxBlock wb[P * NCH];
+            philox4x32_10_n<P * NCH>(blk, um, prt, k0, k1, wb);
+            T nbs[P][NCH][4];
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    const PhiloxBlock& w = wb[p * NCH + c];
+                    BoxMuller<T>::pair(w.w[0], w.w[1], sc[c], nbs[p][c][0], nbs[p][c][1]);
+                    BoxMuller<T>::pair(w.w[2], w.w[3], sc[c], nbs[p][c][2], nbs[p][c][3]);
+                }
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const int base = NORTH ? b0 - (q + p) * G : b0 + (q + p) * G;
-                const T* nb = nbs[p];
 #pragma unroll
                 for (int tt = 0; tt < G; ++tt) {
                     const int t = NORTH ? G - 1 - tt : tt;
-                    const T w0 = nb[t * M];
-                    const T w1 = M == 2 ? (NORTH ? nb[t * M + 1] : -nb[t * M + 1]) : T(0);
-                    chain_step_rec<T, M>(buf[p][t], x0, x1, w0, w1);
-                    if (store) g[(size_t)(base + t) * row] = x0;
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) {
+                        const T w0 = nbs[p][c][t * M];
+                        const T w1 = M == 2 ? (NORTH ? nbs[p][c][t * M + 1] : -nbs[p][c][t * M + 1]) : T(0);
+                        chain_step_rec<T, M>(buf[p][t], x0[c], x1[c], w0, w1);
+                    }
+                    if (store) store_ring<T, NCH>(g, (size_t)(base + t) * row, x0);
                 }
                 const int nbase = NORTH ? base - P * G : base + P * G;
 #pragma unroll
@@ -228,15 +263,20 @@ __device__ __forceinline__ void walk_hemisphere(int s, int even, int r_first, in
         for (int p = 0; p < P; ++p) {
             if (q + p < ng) {
                 const int base = NORTH ? b0 - (q + p) * G : b0 + (q + p) * G;
-                T nb[4];
-                block_normals<T>((uint32_t)((base * M) >> 2), um, up, k0, k1, sc, nb);
+                T nb[NCH][4];
+#pragma unroll
+                for (int c = 0; c < NCH; ++c)
+                    block_normals<T>((uint32_t)((base * M) >> 2), um, up0 + c, k0, k1, sc[c], nb[c]);
 #pragma unroll
                 for (int tt = 0; tt < G; ++tt) {
                     const int t = NORTH ? G - 1 - tt : tt;
-                    const T w0 = nb[t * M];
-                    const T w1 = M == 2 ? (NORTH ? nb[t * M + 1] : -nb[t * M + 1]) : T(0);
-                    chain_step_rec<T, M>(buf[p][t], x0, x1, w0, w1);
-                    if (store) g[(size_t)(base + t) * row] = x0;
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) {
+                        const T w0 = nb[c][t * M];
+                        const T w1 = M == 2 ? (NORTH ? nb[c][t * M + 1] : -nb[c][t * M + 1]) : T(0);
+                        chain_step_rec<T, M>(buf[p][t], x0[c], x1[c], w0, w1);
+                    }
+                    if (store) store_ring<T, NCH>(g, (size_t)(base + t) * row, x0);
                 }
             }
         }
@@ -246,14 +286,14 @@ __device__ __forceinline__ void walk_hemisphere(int s, int even, int r_first, in
         const int end = b0 - ng * G + G - 1;   // highest ring not yet produced
         if (end >= r_last) {
             const int base = (end / G) * G;
-            step_group_direct<T, M, true>(base, r_last, end, s, even, n_sets, um, up, k0, k1, sc, fm,
-                                          set_stride, g, row, x0, x1, store);
+            step_group_direct<T, M, true, NCH>(base, r_last, end, s, even, n_sets, um, up0, k0, k1, sc, fm,
+                                               set_stride, g, row, x0, x1, store);
         }
     } else {
         const int lo = b0 + ng * G;
         if (lo <= r_last)
-            step_group_direct<T, M, false>(lo, lo, r_last, s, even, n_sets, um, up, k0, k1, sc, fm, set_stride,
-                                           g, row, x0, x1, store);
+            step_group_direct<T, M, false, NCH>(lo, lo, r_last, s, even, n_sets, um, up0, k0, k1, sc, fm,
+                                                set_stride, g, row, x0, x1, store);
     }
 }
 
@@ -261,79 +301,93 @@ __device__ __forceinline__ void walk_hemisphere(int s, int even, int r_first, in
 // (state_initial)), stored there by the northern chain; for the southern chain also the
 // crossing step to ring s+1 (even n_theta, set 1, stored), then the switch to y = D x.
 // Every chain of a (mode, part) redraws the start from the same counters.
-template <typename T, int M>
-__device__ __forceinline__ void chain_start(int s, int even, int h, uint32_t um, uint32_t up, uint32_t k0,
-                                            uint32_t k1, T sc, const T* __restrict__ fm, size_t set_stride,
-                                            T* __restrict__ g, size_t row, bool store, T& x0, T& x1)
+template <typename T, int M, int NCH>
+__device__ __forceinline__ void chain_start(int s, int even, int h, uint32_t um, uint32_t up0, uint32_t k0,
+                                            uint32_t k1, const T (&sc)[NCH], const T* __restrict__ fm,
+                                            size_t set_stride, T* __restrict__ g, size_t row, bool store,
+                                            T (&x0)[NCH], T (&x1)[NCH])
 {
-    T nz[4];
-    x1 = T(0);
-    block_normals<T>((uint32_t)((s * M) >> 2), um, up, k0, k1, sc, nz);
-    {
-        const int w = (s * M) & 3;
+    const int w = (s * M) & 3;
+    const int r = s + 1;
+    const int wc = (r * M) & 3;
+    const bool same_block = ((r * M) >> 2) == ((s * M) >> 2);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        T nz[4];
+        block_normals<T>((uint32_t)((s * M) >> 2), um, up0 + c, k0, k1, sc[c], nz);
         const T w0 = pick4(nz, w);
         if (M == 1) {
-            x0 = fm[1] * w0;
+            x0[c] = fm[1] * w0;
+            x1[c] = T(0);
         } else {
             const T w1 = w == 0 ? nz[1] : nz[3];
-            x0 = fm[4] * w0;
-            x1 = fm[5] * w0 + fm[6] * w1;
+            x0[c] = fm[4] * w0;
+            x1[c] = fm[5] * w0 + fm[6] * w1;
         }
-    }
-    if (h == 0) {
-        if (store) g[(size_t)s * row] = x0;
-        return;
-    }
-    if (even) {
-        // crossing s -> s+1 with set 1, in the true coordinates
-        const int r = s + 1;
-        const int w = (r * M) & 3;
-        T w0, w1 = T(0);
-        if (((r * M) >> 2) == ((s * M) >> 2)) {
-            w0 = pick4(nz, w);
-            if (M == 2) w1 = w == 0 ? nz[1] : nz[3];
-        } else {
-            T nc[4];
-            block_normals<T>((uint32_t)((r * M) >> 2), um, up, k0, k1, sc, nc);
-            w0 = pick4(nc, w);
-            if (M == 2) w1 = w == 0 ? nc[1] : nc[3];
+        if (h == 1 && even) {
+            // crossing s -> s+1 with set 1, in the true coordinates
+            T c0, c1 = T(0);
+            if (same_block) {
+                c0 = pick4(nz, wc);
+                if (M == 2) c1 = wc == 0 ? nz[1] : nz[3];
+            } else {
+                T nc[4];
+                block_normals<T>((uint32_t)((r * M) >> 2), um, up0 + c, k0, k1, sc[c], nc);
+                c0 = pick4(nc, wc);
+                if (M == 2) c1 = wc == 0 ? nc[1] : nc[3];
+            }
+            chain_step<T, M>(fm + set_stride, x0[c], x1[c], c0, c1);
         }
-        chain_step<T, M>(fm + set_stride, x0, x1, w0, w1);
-        if (store) g[(size_t)r * row] = x0;
+        if (h == 1) x1[c] = -x1[c];   // y = D x
     }
-    x1 = -x1;   // y = D x
+    if (store) {
+        if (h == 0) store_ring<T, NCH>(g, (size_t)s * row, x0);
+        else if (even) store_ring<T, NCH>(g, (size_t)r * row, x0);
+    }
 }
 
-// One chain.  `fm` points at the mode's record in factor set 0 (sets `set_stride` apart);
-// `g` at the chain's slot of ring 0 of its field (rings `row` elements apart).
-// The northern chain (h = 0) draws the start state at ring s and steps to ring 0; the
-// southern chain (h = 1) redraws the same start state (same counters), takes the crossing
-// step (even n_theta) and steps to ring n-1 with the mirrored factors, carried as
-// y = D x so that the stored northern records apply unchanged with D w as the noise.
+// Chain scales of a lane running NCH chains of mode m from part up0 (see above).
+template <typename T, int NCH>
+__device__ __forceinline__ void chain_scales(int m, uint32_t up0, T (&sc)[NCH])
+{
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+        sc[c] = m == 0 ? ((up0 + c) == 0 ? T(1) : T(0)) : T(0.70710678118654752440);
+}
+
+// The NCH chains of one lane.  `fm` points at the mode's record in factor set 0 (sets
+// `set_stride` apart); `g` at the lane's slot of ring 0 of its field (rings `row` elements
+// apart).  The northern chain (h = 0) draws the start state at ring s and steps to ring 0;
+// the southern chain (h = 1) redraws the same start state (same counters), takes the
+// crossing step (even n_theta) and steps to ring n-1 with the mirrored factors, carried
+// as y = D x so that the stored northern records apply unchanged with D w as the noise.
 // The ring order is uniform across the wave.
-template <typename T, int M, int P = ChainDepth<T>::value>
-__device__ __forceinline__ void run_chain(int n, int s, int even, int n_sets, int h, int m, int part,
+template <typename T, int M, int NCH = 1, int P = ChainDepth<T>::value>
+__device__ __forceinline__ void run_chain(int n, int s, int even, int n_sets, int h, int m, int up0,
                                           uint32_t k0, uint32_t k1, const T* __restrict__ fm,
                                           size_t set_stride, T* __restrict__ g, size_t row)
 {
-    const T sc = (m == 0) ? T(1) : T(0.70710678118654752440);
-    const uint32_t um = (uint32_t)m, up = (uint32_t)part;
-    T x0, x1;
-    chain_start<T, M>(s, even, h, um, up, k0, k1, sc, fm, set_stride, g, row, true, x0, x1);
+    T sc[NCH], x0[NCH], x1[NCH];
+    chain_scales<T, NCH>(m, (uint32_t)up0, sc);
+    chain_start<T, M, NCH>(s, even, h, (uint32_t)m, (uint32_t)up0, k0, k1, sc, fm, set_stride, g, row, true, x0,
+                           x1);
     if (h == 0)
-        walk_hemisphere<T, M, P, true>(s, even, s - 1, 0, m, part, k0, k1, sc, fm, set_stride, n_sets, g, row,
-                                       x0, x1);
+        walk_hemisphere<T, M, P, true, NCH>(s, even, s - 1, 0, m, (uint32_t)up0, k0, k1, sc, fm, set_stride,
+                                            n_sets, g, row, x0, x1);
     else
-        walk_hemisphere<T, M, P, false>(s, even, even ? s + 2 : s + 1, n - 1, m, part, k0, k1, sc, fm,
-                                        set_stride, n_sets, g, row, x0, x1);
+        walk_hemisphere<T, M, P, false, NCH>(s, even, even ? s + 2 : s + 1, n - 1, m, (uint32_t)up0, k0, k1, sc,
+                                             fm, set_stride, n_sets, g, row, x0, x1);
 }
 
-// Zero the slots of modes above m_top (and the imaginary part of g_0) in one hemisphere.
-template <typename T>
+// Zero NCH adjacent slots of one hemisphere (modes above m_top, the imaginary part of g_0).
+template <typename T, int NCH = 1>
 __device__ __forceinline__ void zero_chain(int n, int s, int h, T* __restrict__ g, size_t row)
 {
     const int r_lo = h ? s + 1 : 0, r_hi = h ? n : s + 1;
-    for (int r = r_lo; r < r_hi; ++r) g[(size_t)r * row] = T(0);
+    T z[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) z[c] = T(0);
+    for (int r = r_lo; r < r_hi; ++r) store_ring<T, NCH>(g, (size_t)r * row, z);
 }
 
 // ------------------------------------------------------------------ C2R FFT

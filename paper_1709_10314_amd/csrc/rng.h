@@ -38,14 +38,14 @@ __device__ __forceinline__ PhiloxBlock philox4x32_10(uint32_t c0, uint32_t c1, u
     return b;
 }
 
-// N independent Philox blocks whose counters differ only in the first word, advanced one
-// round at a time so that a caller can interleave the rounds with other work.
+// N independent Philox blocks with counters (c0[i], c1, c2[i], 0), advanced one round at a
+// time.
 template <int N>
 struct PhiloxLanes {
     uint32_t a[N], b[N], c[N], d[N];
     uint32_t k0, k1;
 
-    __device__ __forceinline__ PhiloxLanes(const uint32_t* c0, uint32_t c1, uint32_t c2, uint32_t key0,
+    __device__ __forceinline__ PhiloxLanes(const uint32_t* c0, uint32_t c1, const uint32_t* c2, uint32_t key0,
                                            uint32_t key1)
         : k0(key0), k1(key1)
     {
@@ -53,7 +53,7 @@ struct PhiloxLanes {
         for (int i = 0; i < N; ++i) {
             a[i] = c0[i];
             b[i] = c1;
-            c[i] = c2;
+            c[i] = c2[i];
             d[i] = 0u;
         }
     }
@@ -87,7 +87,7 @@ struct PhiloxLanes {
 // All ten rounds of N blocks in lockstep; the scheduling barrier after each round keeps
 // the compiler from serialising the blocks, so their multiply/xor chains interleave.
 template <int N>
-__device__ __forceinline__ void philox4x32_10_n(const uint32_t* c0, uint32_t c1, uint32_t c2, uint32_t k0,
+__device__ __forceinline__ void philox4x32_10_n(const uint32_t* c0, uint32_t c1, const uint32_t* c2, uint32_t k0,
                                                 uint32_t k1, PhiloxBlock* out)
 {
     PhiloxLanes<N> ph(c0, c1, c2, k0, k1);

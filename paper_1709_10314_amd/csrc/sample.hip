@@ -15,16 +15,25 @@ struct RecArgs {
     uint32_t seed_lo, seed_hi;
 };
 
-// One lane per chain (field f, hemisphere h, mode m, part Re/Im).  A wave holds 32 modes x
-// 2 parts of one (f, h), so f and h are wave-uniform (scalar registers) and so are the
-// Philox key and the ring order; a workgroup holds four (f, h) families of the same 32
-// modes, which read the same factor records.  Workgroups are numbered so that every
-// workgroup of an m-tile lands on the same XCD (workgroup b runs on XCD b mod 8): each XCD
-// streams its own slice of the factors through its own L2.
+// Chains per lane of the plain recursion: FP32 lanes run both parts of their mode (the
+// two chains share every factor record and store one (Re, Im) pair per ring); FP64 lanes
+// run one part (two FP64 chains would not fit the register budget).
+template <typename T>
+struct ChainParts {
+    static constexpr int value = sizeof(T) == 4 ? 2 : 1;
+};
+
+// One lane per (field f, hemisphere h, mode m[, part]).  A wave holds 64 modes (two parts
+// per lane) or 32 modes x 2 parts of one (f, h), so f and h are wave-uniform (scalar
+// registers) and so are the Philox key and the ring order; a workgroup holds four (f, h)
+// families of the same modes, which read the same factor records.  Workgroups are
+// numbered so that every workgroup of an m-tile lands on the same XCD (workgroup b runs on
+// XCD b mod 8): each XCD streams its own slice of the factors through its own L2.
 template <typename T, int M>
 __global__ __launch_bounds__(256) void recursion_kernel(RecArgs a, const T* __restrict__ fac,
                                                         T* __restrict__ out)
 {
+    constexpr int NCH = ChainParts<T>::value;
     const int b = blockIdx.x;
     const int L = (b & 7) * a.per_xcd + (b >> 3);
     if (L >= a.n_wg) return;
@@ -34,17 +43,18 @@ __global__ __launch_bounds__(256) void recursion_kernel(RecArgs a, const T* __re
     if (fh >= a.n_fh) return;
     const int f = fh >> 1, h = fh & 1;
     const int lane = threadIdx.x & 63;
-    const int m = mt * 32 + (lane >> 1), part = lane & 1;
+    const int m = NCH == 2 ? mt * 64 + lane : mt * 32 + (lane >> 1);
+    const int part = NCH == 2 ? 0 : lane & 1;
     if (m >= a.m_rows) return;
     T* __restrict__ g = out + (size_t)f * a.n_theta * a.n_phi + 2 * m + part;
-    if (m > a.m_top || (m == 0 && part == 1)) {
-        zero_chain<T>(a.n_theta, a.s, h, g, (size_t)a.n_phi);
+    if (m > a.m_top || (NCH == 1 && m == 0 && part == 1)) {
+        zero_chain<T, NCH>(a.n_theta, a.s, h, g, (size_t)a.n_phi);
         return;
     }
     const uint64_t key = (((uint64_t)a.seed_hi << 32) | a.seed_lo) + (uint64_t)f;
-    run_chain<T, M>(a.n_theta, a.s, a.even, a.n_sets, h, m, part, (uint32_t)key, (uint32_t)(key >> 32),
-                    fac + (size_t)m * factor_stride(M), (size_t)a.m_rows * factor_stride(M), g,
-                    (size_t)a.n_phi);
+    run_chain<T, M, NCH>(a.n_theta, a.s, a.even, a.n_sets, h, m, part, (uint32_t)key, (uint32_t)(key >> 32),
+                         fac + (size_t)m * factor_stride(M), (size_t)a.m_rows * factor_stride(M), g,
+                         (size_t)a.n_phi);
 }
 
 // ------------------------------------------------------------------ affine scan
@@ -98,7 +108,8 @@ __global__ __launch_bounds__(64 * B) void scan_kernel(ScanArgs a, const T* __res
     const int mm = active ? m : 0;
     const T* __restrict__ fm = fac + (size_t)mm * factor_stride(M);
     const size_t set_stride = (size_t)a.m_rows * factor_stride(M);
-    const T sc = (m == 0) ? T(1) : T(0.70710678118654752440);
+    T sc[1];
+    chain_scales<T, 1>(m, (uint32_t)part, sc);
     const uint32_t um = (uint32_t)mm, up = (uint32_t)part;
     const int j0 = a.even ? 2 : 1;
     const long walk = a.n_sets - j0;
@@ -109,18 +120,18 @@ __global__ __launch_bounds__(64 * B) void scan_kernel(ScanArgs a, const T* __res
     constexpr int P = ScanDepth<T, B>::value;
 
     // pass 1: block 0 from the start state (final, stored); the others from zero
-    T x0 = T(0), x1 = T(0);
+    T x0[1] = {T(0)}, x1[1] = {T(0)};
     if (active) {
-        if (blk == 0) chain_start<T, M>(a.s, a.even, h, um, up, k0, k1, sc, fm, set_stride, g, row, true, x0, x1);
+        if (blk == 0) chain_start<T, M, 1>(a.s, a.even, h, um, up, k0, k1, sc, fm, set_stride, g, row, true, x0, x1);
         if (h == 0)
-            walk_hemisphere<T, M, P, true>(a.s, a.even, r_first, r_last, mm, part, k0, k1, sc, fm, set_stride,
-                                           a.n_sets, g, row, x0, x1, blk == 0);
+            walk_hemisphere<T, M, P, true, 1>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm, set_stride,
+                                              a.n_sets, g, row, x0, x1, blk == 0);
         else
-            walk_hemisphere<T, M, P, false>(a.s, a.even, r_first, r_last, mm, part, k0, k1, sc, fm, set_stride,
-                                            a.n_sets, g, row, x0, x1, blk == 0);
+            walk_hemisphere<T, M, P, false, 1>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm, set_stride,
+                                               a.n_sets, g, row, x0, x1, blk == 0);
     }
-    ends[(blk * 64 + lane) * M] = x0;
-    if (M == 2) ends[(blk * 64 + lane) * M + 1] = x1;
+    ends[(blk * 64 + lane) * M] = x0[0];
+    if (M == 2) ends[(blk * 64 + lane) * M + 1] = x1[0];
     __syncthreads();
     if (blk == 0 || !active) return;
 
@@ -142,14 +153,14 @@ __global__ __launch_bounds__(64 * B) void scan_kernel(ScanArgs a, const T* __res
         if (M == 2) y1 += ends[(k * 64 + lane) * M + 1];
     }
     // pass 2: this block again from its true start, with stores
-    x0 = y0;
-    x1 = y1;
+    x0[0] = y0;
+    x1[0] = y1;
     if (h == 0)
-        walk_hemisphere<T, M, P, true>(a.s, a.even, r_first, r_last, mm, part, k0, k1, sc, fm, set_stride,
-                                       a.n_sets, g, row, x0, x1, true);
+        walk_hemisphere<T, M, P, true, 1>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm, set_stride,
+                                          a.n_sets, g, row, x0, x1, true);
     else
-        walk_hemisphere<T, M, P, false>(a.s, a.even, r_first, r_last, mm, part, k0, k1, sc, fm, set_stride,
-                                        a.n_sets, g, row, x0, x1, true);
+        walk_hemisphere<T, M, P, false, 1>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm, set_stride,
+                                           a.n_sets, g, row, x0, x1, true);
 }
 
 template <typename T, int M>
@@ -254,7 +265,8 @@ hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, uint64
     a.even = g.even;
     a.n_fh = 2 * count;
     a.n_fg = (a.n_fh + 3) / 4;
-    const int n_mt = (g.m_rows + 31) / 32;
+    const int modes_per_wave = (fp64 ? ChainParts<double>::value : ChainParts<float>::value) == 2 ? 64 : 32;
+    const int n_mt = (g.m_rows + modes_per_wave - 1) / modes_per_wave;
     a.n_wg = n_mt * a.n_fg;
     a.per_xcd = (a.n_wg + 7) / 8;
     a.seed_lo = (uint32_t)seed;

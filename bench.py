@@ -92,6 +92,32 @@ def time_split(plan, seed, count, out, steps, warmup):
     return rec, fft
 
 
+def batch_leg(steps, warmup):
+    """The batched form on the 256-field mixed workload: one call samples every field
+    (chain launch + FFT launch) after the tile-shape autotuner has run."""
+    import torch
+
+    from paper_1709_10314_amd import BatchPlan, workloads
+
+    mix = workloads.batch_mix()
+    fields = [dict(n_theta=w["n_theta"], n_phi=w["n_phi"], order=w["order"], kappa=[w["kappa"] ** 2] * w["order"],
+                   ell_max=w["ell_max"]) for w in mix]
+    t0 = time.perf_counter()
+    bp = BatchPlan(fields)
+    setup_s = time.perf_counter() - t0
+    out = bp.empty()
+    tiles = bp.autotune(1, out)
+    ms, _ = time_calls(lambda: bp.sample(1, out), steps, warmup)
+    pts = int(bp.offsets[-1])
+    bp.close()
+    del out
+    torch.cuda.empty_cache()
+    return {"value": pts / ms * 1e3, "unit": "grid points/s", "ms_per_step": ms, "fields": len(fields),
+            "points": pts, "tiles": tiles, "setup_s": setup_s,
+            "workload": "256 fields: n_theta uniform on {128..2048}, n_phi = 2 n_theta, ln kappa ~ U(ln 2, ln 200), "
+                        "order 1 or 2, FP32, seeds 1..256 (numpy PCG64(0))"}
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch from committed rocprofv3 PMC summaries, if they were taken on
     the current kernel sources; else None."""
@@ -144,6 +170,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-rings", type=int, default=384)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (calibrates rocprofv3 FETCH/WRITE_SIZE)")
@@ -231,6 +258,13 @@ def main():
                     "frac": kd["hbm_frac"], "traffic": traffic, "kernel": dom}
     roofline["path_alg_GBs"] = (fac_bytes + g_bytes + 2 * count * n * nphi * 4) / (ms_step * 1e-3) / 1e9
 
+    batch = None
+    if not args.no_batch:
+        log("batched form: 256-field mixed workload")
+        batch = batch_leg(args.steps, args.warmup)
+        log(f"  {batch['ms_per_step']:.3f} ms/call ({batch['value']:.3e} pts/s, tiles {batch['tiles']}, "
+            f"setup {batch['setup_s']:.1f} s)")
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {args.cpu_rings} rings")
@@ -258,6 +292,7 @@ def main():
         "kernels": kernels,
         "fp64_plain": fp64,
         "speedup_fp32_vs_fp64": (fp64["ms_per_step"] / ms_step) if fp64 else None,
+        "batch_mix": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

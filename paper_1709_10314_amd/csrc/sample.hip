@@ -187,10 +187,10 @@ struct FftThreads {
 };
 
 // Rows prefetch the next row during the current one's passes while the extra registers
-// fit (FP32 up to n_phi = 8192, FP64 up to 2048); larger rows load row by row.
+// fit (FP32 every size, FP64 up to n_phi = 8192); FP64 rows of 16384 load row by row.
 template <typename T, int LOG2H>
 struct FftPrefetch {
-    static constexpr bool value = sizeof(T) == 4 ? LOG2H <= 12 : LOG2H <= 10;
+    static constexpr bool value = sizeof(T) == 4 ? LOG2H <= 13 : LOG2H <= 12;
 };
 
 // Register budget in waves per SIMD: 4 (128 VGPRs) for small rows, else 2 (256 VGPRs),

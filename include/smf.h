@@ -78,7 +78,8 @@ int smf_setup(const smf_spectrum* spec, int n_theta, int n_phi, int flags, void*
  * float (SMF_FP32 plan) or double (SMF_FP64 plan), layout [field][ring][phi], ring 0
  * nearest the north pole.  count = 0 is a no-op.  Uses no memory beyond out_dev: the
  * modes g_m are written into out_dev and transformed in place.
- * Errors: SMF_EINVAL (NULL plan/out with count > 0, count < 0), SMF_EHIP. */
+ * Errors: SMF_EINVAL (NULL plan/out with count > 0, count < 0, count * n_theta > 2^31 - 1),
+ * SMF_EHIP. */
 int smf_sample(const smf_plan* plan, uint64_t seed, int count, void* out_dev, void* hip_stream);
 
 /* The chains of Alg. 2 only (eqs. (state_initial) and (state_space)), without the FFT:
@@ -92,7 +93,8 @@ int smf_sample_modes(const smf_plan* plan, uint64_t seed, int count, void* g_dev
  * place.  data_dev holds count fields of modes in the layout smf_sample_modes writes
  * (entries m > m_top and the imaginary part of g_0 are ignored) and receives the fields in
  * the layout smf_sample writes.  smf_sample = smf_sample_modes then smf_transform.
- * Errors: SMF_EINVAL (NULL plan/data with count > 0, count < 0, batch plan), SMF_EHIP. */
+ * Errors: SMF_EINVAL (NULL plan/data with count > 0, count < 0, count * n_theta > 2^31 - 1,
+ * batch plan), SMF_EHIP. */
 int smf_transform(const smf_plan* plan, int count, void* data_dev, void* hip_stream);
 
 /* Ring blocks of the affine scan (single-field plans).  The recursion of eq. (state_space)
@@ -101,9 +103,11 @@ int smf_transform(const smf_plan* plan, int count, void* data_dev, void* hip_str
  * blocks' transitions (products of the step matrices A, built at setup) with those end
  * states, then each block again from its true start.  Used when a call's chains alone
  * cannot fill the GPU; it doubles the arithmetic and changes results only by rounding.
- *   blocks  0: automatic: the scan is used when count * 2 * ceil(n_phi / 64) < 1024
- *              (fewer chains than one wavefront per SIMD of the chip), with the fewest
- *              blocks giving >= 4096 wavefronts while every block keeps >= 32 ring steps;
+ *   blocks  0: automatic: with w = count * 2 * ceil(n_phi / 64) (the wavefronts of the plain
+ *              recursion with one chain per lane), no scan from w >= 1024; below that FP32
+ *              scans with 8 blocks (w >= 512) or 16 blocks, FP64 with the fewest blocks
+ *              giving >= 4096 wavefronts; every block keeps >= 32 ring steps or the
+ *              count of blocks halves (no scan below 2);
  *           1: never;
  *           2, 4, 8 or 16: always, with that many blocks, capped at the plan's maximum (the
  *              largest power of two <= 16 leaving >= 8 ring steps per block, 1 when the

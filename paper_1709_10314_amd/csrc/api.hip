@@ -177,40 +177,63 @@ int smf_setup(const smf_spectrum* spec, int n_theta, int n_phi, int flags, void*
     return setup_impl(spec, n_theta, n_phi, flags, (hipStream_t)hip_stream, true, out);
 }
 
-// Ring blocks a call with `count` fields uses (1: plain recursion).  Automatic rule: the
-// plain recursion has count * 2 * ceil(m_rows / 32) waves; below one wave per SIMD of the
-// chip (1024) the chains are cut into the fewest blocks that give >= 4096 waves, as long
-// as every block keeps >= kScanAutoMinSets ring steps (shorter walks are launch-bound).
-static int ring_blocks_for(const smf_plan* plan, int count)
+// Layout of a call's chains: ring blocks of the affine scan (1: plain recursion) and
+// chains per lane (1: one part, 2: both parts of a mode, FP32 only).  The result depends
+// on the blocks only.  With w = count * 2 * ceil(m_rows / 32) one-part waves, the
+// automatic choice (measured on MI355X) is: FP32 plain with two parts per lane from 2048
+// waves, plain with one part from 1024, a two-part scan of 8 blocks from 512, else a
+// one-part scan of 16 blocks; FP64 plain from 1024 waves, else a scan of the fewest
+// blocks giving >= 4096 waves.  Scans keep >= kScanAutoMinSets ring steps per block.
+struct CallShape {
+    int blocks, nch;
+};
+
+static CallShape call_shape(const smf_plan* plan, int count)
 {
-    const int cap = std::min(plan->scan_fine, smf::scan_max_blocks(plan->flags == SMF_FP64));
-    if (cap < 2 || plan->scan_req == 1) return 1;
-    if (plan->scan_req >= 2) return std::min(plan->scan_req, cap);
-    const long waves = (long)count * 2 * ((plan->g.m_rows + 31) / 32);
+    const bool fp64 = plan->flags == SMF_FP64;
+    const int cap = std::min(plan->scan_fine, smf::scan_max_blocks(fp64));
+    const long w = (long)count * 2 * ((plan->g.m_rows + 31) / 32);
     const int walk = plan->g.n_sets - (plan->g.even ? 2 : 1);
-    if (waves >= 1024 || walk / 2 < smf::kScanAutoMinSets) return 1;
-    int b = 2;
-    while (b < cap && waves * b < 4096 && walk / (2 * b) >= smf::kScanAutoMinSets) b *= 2;
-    return b;
+    const int plain_nch = (!fp64 && w >= 2048) ? 2 : 1;
+    const int scan_nch = (!fp64 && w >= 512) ? 2 : 1;
+    if (cap < 2 || plan->scan_req == 1) return {1, plain_nch};
+    if (plan->scan_req >= 2) return {std::min(plan->scan_req, cap), scan_nch};
+    if (w >= 1024) return {1, plain_nch};
+    int b;
+    if (fp64) {
+        b = 2;
+        while (b < cap && w * b < 4096) b *= 2;
+    } else {
+        b = w >= 512 ? 8 : 16;
+    }
+    if (b > cap) b = cap;
+    while (b >= 2 && walk / b < smf::kScanAutoMinSets) b /= 2;
+    return b >= 2 ? CallShape{b, scan_nch} : CallShape{1, plain_nch};
+}
+
+// Largest field count of one call: the FFT indexes its rows (count * n_theta) with ints.
+static bool count_fits(const smf_plan* plan, int count)
+{
+    return (long long)count * plan->g.n_theta <= 0x7FFFFFFFLL;
 }
 
 static int sample_common(const smf_plan* plan, uint64_t seed, int count, void* out_dev,
                          void* hip_stream, bool fft)
 {
-    if (!plan || plan->batch || count < 0) return SMF_EINVAL;
+    if (!plan || plan->batch || count < 0 || !count_fits(plan, count)) return SMF_EINVAL;
     if (count == 0) return SMF_OK;
     if (!out_dev) return SMF_EINVAL;
     DeviceGuard dg(plan->device);
     hipStream_t st = (hipStream_t)hip_stream;
     const int fp64 = plan->flags == SMF_FP64;
     const void* fac = fp64 ? (const void*)plan->f64 : (const void*)plan->f32;
-    const int blocks = ring_blocks_for(plan, count);
-    if (blocks > 1) {
+    const CallShape cs = call_shape(plan, count);
+    if (cs.blocks > 1) {
         const void* phi = fp64 ? (const void*)plan->phi64 : (const void*)plan->phi32;
-        if (smf::launch_scan(plan->g, fp64, fac, phi, plan->scan_fine, blocks, seed, count, out_dev, st) !=
-            hipSuccess)
+        if (smf::launch_scan(plan->g, fp64, fac, phi, plan->scan_fine, cs.blocks, seed, count, out_dev, cs.nch,
+                             st) != hipSuccess)
             return SMF_EHIP;
-    } else if (smf::launch_recursion(plan->g, fp64, fac, seed, count, out_dev, st) != hipSuccess) {
+    } else if (smf::launch_recursion(plan->g, fp64, fac, seed, count, out_dev, cs.nch, st) != hipSuccess) {
         return SMF_EHIP;
     }
     if (fft) {
@@ -232,7 +255,7 @@ int smf_sample_modes(const smf_plan* plan, uint64_t seed, int count, void* g_dev
 
 int smf_transform(const smf_plan* plan, int count, void* data_dev, void* hip_stream)
 {
-    if (!plan || plan->batch || count < 0) return SMF_EINVAL;
+    if (!plan || plan->batch || count < 0 || !count_fits(plan, count)) return SMF_EINVAL;
     if (count == 0) return SMF_OK;
     if (!data_dev) return SMF_EINVAL;
     DeviceGuard dg(plan->device);
@@ -253,7 +276,7 @@ int smf_set_ring_blocks(smf_plan* plan, int blocks)
 int smf_get_ring_blocks(const smf_plan* plan, int count, int* blocks)
 {
     if (!plan || plan->batch || !blocks || count < 0) return SMF_EINVAL;
-    *blocks = ring_blocks_for(plan, count);
+    *blocks = call_shape(plan, count).blocks;
     return SMF_OK;
 }
 

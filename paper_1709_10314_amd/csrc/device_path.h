@@ -90,16 +90,20 @@ __device__ __forceinline__ void chain_step_rec(const Rec<T, M>& R, T& x0, T& x1,
     }
 }
 
-// Philox groups kept in flight by the register prefetch pipeline of a chain walk.
+// Philox groups kept in flight by the register prefetch pipeline of a chain walk, per
+// precision and chains per lane.
 #ifndef SMF_CHAIN_P32
 #define SMF_CHAIN_P32 4
+#endif
+#ifndef SMF_CHAIN_P32_ONE
+#define SMF_CHAIN_P32_ONE 8
 #endif
 #ifndef SMF_CHAIN_P64
 #define SMF_CHAIN_P64 2
 #endif
-template <typename T>
+template <typename T, int NCH = 1>
 struct ChainDepth {
-    static constexpr int value = sizeof(T) == 4 ? SMF_CHAIN_P32 : SMF_CHAIN_P64;
+    static constexpr int value = sizeof(T) == 4 ? (NCH == 2 ? SMF_CHAIN_P32 : SMF_CHAIN_P32_ONE) : SMF_CHAIN_P64;
 };
 
 // Rings are walked in groups of G = 4/M that share one Philox block (counter block
@@ -362,7 +366,7 @@ __device__ __forceinline__ void chain_scales(int m, uint32_t up0, T (&sc)[NCH])
 // crossing step (even n_theta) and steps to ring n-1 with the mirrored factors, carried
 // as y = D x so that the stored northern records apply unchanged with D w as the noise.
 // The ring order is uniform across the wave.
-template <typename T, int M, int NCH = 1, int P = ChainDepth<T>::value>
+template <typename T, int M, int NCH = 1, int P = ChainDepth<T, NCH>::value>
 __device__ __forceinline__ void run_chain(int n, int s, int even, int n_sets, int h, int m, int up0,
                                           uint32_t k0, uint32_t k1, const T* __restrict__ fm,
                                           size_t set_stride, T* __restrict__ g, size_t row)

@@ -15,25 +15,21 @@ struct RecArgs {
     uint32_t seed_lo, seed_hi;
 };
 
-// Chains per lane of the plain recursion: FP32 lanes run both parts of their mode (the
-// two chains share every factor record and store one (Re, Im) pair per ring); FP64 lanes
-// run one part (two FP64 chains would not fit the register budget).
-template <typename T>
-struct ChainParts {
-    static constexpr int value = sizeof(T) == 4 ? 2 : 1;
-};
-
+// Chains per lane (NCH): 2 runs both parts of a mode in one lane (the two chains share
+// every factor record and store one (Re, Im) pair per ring), 1 runs one part per lane
+// (twice the waves, half the serial work per wave).  Both give identical results; the
+// host picks per call (FP64 always uses 1: two FP64 chains do not fit the register
+// budget).
 // One lane per (field f, hemisphere h, mode m[, part]).  A wave holds 64 modes (two parts
 // per lane) or 32 modes x 2 parts of one (f, h), so f and h are wave-uniform (scalar
 // registers) and so are the Philox key and the ring order; a workgroup holds four (f, h)
 // families of the same modes, which read the same factor records.  Workgroups are
 // numbered so that every workgroup of an m-tile lands on the same XCD (workgroup b runs on
 // XCD b mod 8): each XCD streams its own slice of the factors through its own L2.
-template <typename T, int M>
+template <typename T, int M, int NCH>
 __global__ __launch_bounds__(256) void recursion_kernel(RecArgs a, const T* __restrict__ fac,
                                                         T* __restrict__ out)
 {
-    constexpr int NCH = ChainParts<T>::value;
     const int b = blockIdx.x;
     const int L = (b & 7) * a.per_xcd + (b >> 3);
     if (L >= a.n_wg) return;
@@ -66,9 +62,11 @@ __global__ __launch_bounds__(256) void recursion_kernel(RecArgs a, const T* __re
 // the other blocks walk twice, first without stores for c_b, then from x_b with stores,
 // recomputing the same counter-based normals (no workspace, about twice the arithmetic).
 //
-// A workgroup is one (field, hemisphere, m-tile of 32 modes) with one wave per ring block:
-// every wave covers the same 64 chains, so its loads and stores are as contiguous as the
-// plain recursion's, and the block end states meet in LDS across one barrier.
+// A workgroup is one (field, hemisphere, m-tile) with one wave per ring block, laid out as
+// the plain recursion's waves (64 modes with both parts per lane in FP32, 32 modes x 2
+// parts in FP64): every wave covers the same chains, so its loads and stores are as
+// contiguous as the plain recursion's, and the block end states meet in LDS across one
+// barrier.
 struct ScanArgs {
     int n_theta, n_phi, m_top, m_rows, n_sets, s, even;
     int n_fh, n_wg, per_xcd;
@@ -78,16 +76,17 @@ struct ScanArgs {
 
 // Prefetch depth of a scan wave: a workgroup of B >= 8 waves leaves 2048 / B VGPRs per
 // lane, so the deeper scans keep shallower pipelines.
-template <typename T, int B>
+template <typename T, int B, int NCH>
 struct ScanDepth {
-    static constexpr int value = sizeof(T) == 4 ? (B >= 16 ? 2 : (B >= 8 ? 4 : 8)) : (B >= 8 ? 2 : 4);
+    static constexpr int value = sizeof(T) == 8 ? (B >= 8 ? 2 : 4)
+                                 : (B >= 16 ? 2 : (NCH == 2 || B >= 8 ? 4 : 8));
 };
 
-template <typename T, int M, int B>
+template <typename T, int M, int B, int NCH>
 __global__ __launch_bounds__(64 * B) void scan_kernel(ScanArgs a, const T* __restrict__ fac,
                                                       const T* __restrict__ phi, T* __restrict__ out)
 {
-    __shared__ T ends[B * 64 * M];
+    __shared__ T ends[B * 64 * NCH * M];
     const int bx = blockIdx.x;
     const int L = (bx & 7) * a.per_xcd + (bx >> 3);
     if (L >= a.n_wg) return;
@@ -96,20 +95,21 @@ __global__ __launch_bounds__(64 * B) void scan_kernel(ScanArgs a, const T* __res
     const int f = fh >> 1, h = fh & 1;
     const int blk = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    const int m = mt * 32 + (lane >> 1), part = lane & 1;
+    const int m = NCH == 2 ? mt * 64 + lane : mt * 32 + (lane >> 1);
+    const int part = NCH == 2 ? 0 : lane & 1;
     const bool in_range = m < a.m_rows;
-    const bool active = in_range && m <= a.m_top && !(m == 0 && part == 1);
+    const bool active = in_range && m <= a.m_top && (NCH == 2 || !(m == 0 && part == 1));
     const size_t row = (size_t)a.n_phi;
     T* __restrict__ g = out + (size_t)f * a.n_theta * a.n_phi + 2 * (in_range ? m : 0) + part;
-    if (in_range && !active && blk == 0) zero_chain<T>(a.n_theta, a.s, h, g, row);
+    if (in_range && !active && blk == 0) zero_chain<T, NCH>(a.n_theta, a.s, h, g, row);
 
     const uint64_t key = (((uint64_t)a.seed_hi << 32) | a.seed_lo) + (uint64_t)f;
     const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
     const int mm = active ? m : 0;
     const T* __restrict__ fm = fac + (size_t)mm * factor_stride(M);
     const size_t set_stride = (size_t)a.m_rows * factor_stride(M);
-    T sc[1];
-    chain_scales<T, 1>(m, (uint32_t)part, sc);
+    T sc[NCH];
+    chain_scales<T, NCH>(m, (uint32_t)part, sc);
     const uint32_t um = (uint32_t)mm, up = (uint32_t)part;
     const int j0 = a.even ? 2 : 1;
     const long walk = a.n_sets - j0;
@@ -117,63 +117,82 @@ __global__ __launch_bounds__(64 * B) void scan_kernel(ScanArgs a, const T* __res
     const int je = j0 + (int)(walk * ((blk + 1) * a.fine_per) / a.fine);
     const int r_first = h == 0 ? a.s - jb + a.even : a.s + jb;
     const int r_last = h == 0 ? a.s - (je - 1) + a.even : a.s + (je - 1);
-    constexpr int P = ScanDepth<T, B>::value;
+    constexpr int P = ScanDepth<T, B, NCH>::value;
 
     // pass 1: block 0 from the start state (final, stored); the others from zero
-    T x0[1] = {T(0)}, x1[1] = {T(0)};
+    T x0[NCH], x1[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) x0[c] = x1[c] = T(0);
     if (active) {
-        if (blk == 0) chain_start<T, M, 1>(a.s, a.even, h, um, up, k0, k1, sc, fm, set_stride, g, row, true, x0, x1);
+        if (blk == 0) chain_start<T, M, NCH>(a.s, a.even, h, um, up, k0, k1, sc, fm, set_stride, g, row, true, x0, x1);
         if (h == 0)
-            walk_hemisphere<T, M, P, true, 1>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm, set_stride,
-                                              a.n_sets, g, row, x0, x1, blk == 0);
+            walk_hemisphere<T, M, P, true, NCH>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm, set_stride,
+                                                a.n_sets, g, row, x0, x1, blk == 0);
         else
-            walk_hemisphere<T, M, P, false, 1>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm, set_stride,
-                                               a.n_sets, g, row, x0, x1, blk == 0);
+            walk_hemisphere<T, M, P, false, NCH>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm, set_stride,
+                                                 a.n_sets, g, row, x0, x1, blk == 0);
     }
-    ends[(blk * 64 + lane) * M] = x0[0];
-    if (M == 2) ends[(blk * 64 + lane) * M + 1] = x1[0];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        ends[((blk * 64 + lane) * NCH + c) * M] = x0[c];
+        if (M == 2) ends[((blk * 64 + lane) * NCH + c) * M + 1] = x1[c];
+    }
     __syncthreads();
     if (blk == 0 || !active) return;
 
-    // fold: the start of this block
-    T y0 = ends[lane * M], y1 = M == 2 ? ends[lane * M + 1] : T(0);
+    // fold: the start of this block, per chain
+    T y0[NCH], y1[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        y0[c] = ends[(lane * NCH + c) * M];
+        y1[c] = M == 2 ? ends[(lane * NCH + c) * M + 1] : T(0);
+    }
     for (int k = 1; k < blk; ++k) {
         for (int i = k * a.fine_per; i < (k + 1) * a.fine_per; ++i) {
             const T* __restrict__ p = phi + ((size_t)i * a.m_rows + mm) * (M * M);
-            if (M == 1) {
-                y0 = p[0] * y0;
-            } else {
-                const T t0 = fma(p[0], y0, p[1] * y1);
-                const T t1 = fma(p[2], y0, p[3] * y1);
-                y0 = t0;
-                y1 = t1;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                if (M == 1) {
+                    y0[c] = p[0] * y0[c];
+                } else {
+                    const T t0 = fma(p[0], y0[c], p[1] * y1[c]);
+                    const T t1 = fma(p[2], y0[c], p[3] * y1[c]);
+                    y0[c] = t0;
+                    y1[c] = t1;
+                }
             }
         }
-        y0 += ends[(k * 64 + lane) * M];
-        if (M == 2) y1 += ends[(k * 64 + lane) * M + 1];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            y0[c] += ends[((k * 64 + lane) * NCH + c) * M];
+            if (M == 2) y1[c] += ends[((k * 64 + lane) * NCH + c) * M + 1];
+        }
     }
     // pass 2: this block again from its true start, with stores
-    x0[0] = y0;
-    x1[0] = y1;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        x0[c] = y0[c];
+        x1[c] = y1[c];
+    }
     if (h == 0)
-        walk_hemisphere<T, M, P, true, 1>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm, set_stride,
-                                          a.n_sets, g, row, x0, x1, true);
+        walk_hemisphere<T, M, P, true, NCH>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm, set_stride,
+                                            a.n_sets, g, row, x0, x1, true);
     else
-        walk_hemisphere<T, M, P, false, 1>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm, set_stride,
-                                           a.n_sets, g, row, x0, x1, true);
+        walk_hemisphere<T, M, P, false, NCH>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm, set_stride,
+                                             a.n_sets, g, row, x0, x1, true);
 }
 
-template <typename T, int M>
+template <typename T, int M, int NCH>
 void launch_scan_t(const ScanArgs& a, int blocks, const T* fac, const T* phi, T* out, hipStream_t st)
 {
     const dim3 grid((unsigned)(a.per_xcd * 8));
     switch (blocks) {
-        case 2: hipLaunchKernelGGL((scan_kernel<T, M, 2>), grid, dim3(128), 0, st, a, fac, phi, out); break;
-        case 4: hipLaunchKernelGGL((scan_kernel<T, M, 4>), grid, dim3(256), 0, st, a, fac, phi, out); break;
-        case 8: hipLaunchKernelGGL((scan_kernel<T, M, 8>), grid, dim3(512), 0, st, a, fac, phi, out); break;
+        case 2: hipLaunchKernelGGL((scan_kernel<T, M, 2, NCH>), grid, dim3(128), 0, st, a, fac, phi, out); break;
+        case 4: hipLaunchKernelGGL((scan_kernel<T, M, 4, NCH>), grid, dim3(256), 0, st, a, fac, phi, out); break;
+        case 8: hipLaunchKernelGGL((scan_kernel<T, M, 8, NCH>), grid, dim3(512), 0, st, a, fac, phi, out); break;
         default:
             if constexpr (sizeof(T) == 4)   // FP64 scans stop at 8 blocks
-                hipLaunchKernelGGL((scan_kernel<T, M, 16>), grid, dim3(1024), 0, st, a, fac, phi, out);
+                hipLaunchKernelGGL((scan_kernel<T, M, 16, NCH>), grid, dim3(1024), 0, st, a, fac, phi, out);
             break;
     }
 }
@@ -253,8 +272,9 @@ hipError_t dispatch_c2r(int log2h, const T* tw, int m_top, int rows, T* data, hi
 }  // namespace
 
 hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, uint64_t seed, int count,
-                            void* out, hipStream_t st)
+                            void* out, int nch, hipStream_t st)
 {
+    if (nch != 1 && (nch != 2 || fp64)) return hipErrorInvalidValue;
     RecArgs a;
     a.n_theta = g.n_theta;
     a.n_phi = g.n_phi;
@@ -265,7 +285,7 @@ hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, uint64
     a.even = g.even;
     a.n_fh = 2 * count;
     a.n_fg = (a.n_fh + 3) / 4;
-    const int modes_per_wave = (fp64 ? ChainParts<double>::value : ChainParts<float>::value) == 2 ? 64 : 32;
+    const int modes_per_wave = nch == 2 ? 64 : 32;
     const int n_mt = (g.m_rows + modes_per_wave - 1) / modes_per_wave;
     a.n_wg = n_mt * a.n_fg;
     a.per_xcd = (a.n_wg + 7) / 8;
@@ -274,27 +294,35 @@ hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, uint64
     const dim3 grid((unsigned)(a.per_xcd * 8));
     if (fp64) {
         if (g.order == 1)
-            hipLaunchKernelGGL((recursion_kernel<double, 1>), grid, dim3(256), 0, st, a,
+            hipLaunchKernelGGL((recursion_kernel<double, 1, 1>), grid, dim3(256), 0, st, a,
                                (const double*)fac, (double*)out);
         else
-            hipLaunchKernelGGL((recursion_kernel<double, 2>), grid, dim3(256), 0, st, a,
+            hipLaunchKernelGGL((recursion_kernel<double, 2, 1>), grid, dim3(256), 0, st, a,
                                (const double*)fac, (double*)out);
-    } else {
+    } else if (nch == 2) {
         if (g.order == 1)
-            hipLaunchKernelGGL((recursion_kernel<float, 1>), grid, dim3(256), 0, st, a,
+            hipLaunchKernelGGL((recursion_kernel<float, 1, 2>), grid, dim3(256), 0, st, a,
                                (const float*)fac, (float*)out);
         else
-            hipLaunchKernelGGL((recursion_kernel<float, 2>), grid, dim3(256), 0, st, a,
+            hipLaunchKernelGGL((recursion_kernel<float, 2, 2>), grid, dim3(256), 0, st, a,
+                               (const float*)fac, (float*)out);
+    } else {
+        if (g.order == 1)
+            hipLaunchKernelGGL((recursion_kernel<float, 1, 1>), grid, dim3(256), 0, st, a,
+                               (const float*)fac, (float*)out);
+        else
+            hipLaunchKernelGGL((recursion_kernel<float, 2, 1>), grid, dim3(256), 0, st, a,
                                (const float*)fac, (float*)out);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_scan(const Geometry& g, int fp64, const void* fac, const void* phi, int fine_blocks,
-                       int blocks, uint64_t seed, int count, void* out, hipStream_t st)
+                       int blocks, uint64_t seed, int count, void* out, int nch, hipStream_t st)
 {
     if (blocks < 2 || blocks > scan_max_blocks(fp64) || (blocks & (blocks - 1)) || fine_blocks % blocks)
         return hipErrorInvalidValue;
+    if (nch != 1 && (nch != 2 || fp64)) return hipErrorInvalidValue;
     ScanArgs a;
     a.n_theta = g.n_theta;
     a.n_phi = g.n_phi;
@@ -306,17 +334,21 @@ hipError_t launch_scan(const Geometry& g, int fp64, const void* fac, const void*
     a.n_fh = 2 * count;
     a.fine_per = fine_blocks / blocks;
     a.fine = fine_blocks;
-    const int n_mt = (g.m_rows + 31) / 32;
+    const int modes_per_wave = nch == 2 ? 64 : 32;
+    const int n_mt = (g.m_rows + modes_per_wave - 1) / modes_per_wave;
     a.n_wg = n_mt * a.n_fh;
     a.per_xcd = (a.n_wg + 7) / 8;
     a.seed_lo = (uint32_t)seed;
     a.seed_hi = (uint32_t)(seed >> 32);
     if (fp64) {
-        if (g.order == 1) launch_scan_t<double, 1>(a, blocks, (const double*)fac, (const double*)phi, (double*)out, st);
-        else launch_scan_t<double, 2>(a, blocks, (const double*)fac, (const double*)phi, (double*)out, st);
+        if (g.order == 1) launch_scan_t<double, 1, 1>(a, blocks, (const double*)fac, (const double*)phi, (double*)out, st);
+        else launch_scan_t<double, 2, 1>(a, blocks, (const double*)fac, (const double*)phi, (double*)out, st);
+    } else if (nch == 2) {
+        if (g.order == 1) launch_scan_t<float, 1, 2>(a, blocks, (const float*)fac, (const float*)phi, (float*)out, st);
+        else launch_scan_t<float, 2, 2>(a, blocks, (const float*)fac, (const float*)phi, (float*)out, st);
     } else {
-        if (g.order == 1) launch_scan_t<float, 1>(a, blocks, (const float*)fac, (const float*)phi, (float*)out, st);
-        else launch_scan_t<float, 2>(a, blocks, (const float*)fac, (const float*)phi, (float*)out, st);
+        if (g.order == 1) launch_scan_t<float, 1, 1>(a, blocks, (const float*)fac, (const float*)phi, (float*)out, st);
+        else launch_scan_t<float, 2, 1>(a, blocks, (const float*)fac, (const float*)phi, (float*)out, st);
     }
     return hipGetLastError();
 }

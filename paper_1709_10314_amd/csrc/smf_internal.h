@@ -76,14 +76,15 @@ inline int scan_fine_blocks(const Geometry& g)
 }
 
 // ---- sampling ----
+// nch: chains per lane, 1 (one part) or 2 (both parts of a mode; FP32 only).
 hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, uint64_t seed, int count,
-                            void* out, hipStream_t st);
+                            void* out, int nch, hipStream_t st);
 hipError_t launch_c2r(const Geometry& g, int fp64, const void* tw, int count, void* data,
                       hipStream_t st);
 // The chains of launch_recursion as an affine scan over `blocks` ring blocks per chain
 // (blocks >= 2 dividing fine_blocks; phi holds the plan's fine-block transitions).
 hipError_t launch_scan(const Geometry& g, int fp64, const void* fac, const void* phi, int fine_blocks,
-                       int blocks, uint64_t seed, int count, void* out, hipStream_t st);
+                       int blocks, uint64_t seed, int count, void* out, int nch, hipStream_t st);
 
 }  // namespace smf
 

@@ -235,6 +235,12 @@ def test_error_codes():
     assert smf.smf_sample(plan.handle, 1, -1, 0) == smf.SMF_EINVAL
     assert smf.smf_sample(plan.handle, 1, 0, 0) == smf.SMF_OK
     assert smf.smf_sample(plan.handle, 1, 2, 0) == smf.SMF_EINVAL
+    # count * n_theta beyond the int range is refused before any device work (the pointer
+    # is never dereferenced)
+    too_many = (2 ** 31) // 8 + 1
+    assert smf.smf_sample(plan.handle, 1, too_many, 16) == smf.SMF_EINVAL
+    assert smf.smf_sample_modes(plan.handle, 1, too_many, 16) == smf.SMF_EINVAL
+    assert smf.smf_transform(plan.handle, too_many, 16) == smf.SMF_EINVAL
     plan.close()
 
 

@@ -143,3 +143,47 @@ def test_ring_blocks_arguments():
     tiny.set_ring_blocks(4)
     assert tiny.ring_blocks(1) == 1
     tiny.close()
+
+
+def test_chains_per_lane_do_not_change_results():
+    """The per-call layout (one or two chains per lane) is a performance choice only: field 0
+    of a 1-field call and of a 32-field call (one-part and two-part plain recursion) are bit
+    identical, and so are forced 8-block scans of a 1-field and an 8-field call (one-part and
+    two-part scan)."""
+    plan = _plan(2, 400.0, 1024, 2048, 1023, "fp32")
+    plan.set_ring_blocks(1)
+    a = plan.sample(9, 1)[0].clone()
+    b = plan.sample(9, 32)[0].clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    plan.set_ring_blocks(8)
+    assert plan.ring_blocks(1) == 8 and plan.ring_blocks(8) == 8
+    c = plan.sample(9, 1)[0].clone()
+    d = plan.sample(9, 8)[0].clone()
+    torch.cuda.synchronize()
+    assert torch.equal(c, d)
+    e = rel_rms(c.double().cpu().numpy(), a.double().cpu().numpy())
+    log(f"1024x2048 M2 fp32: 8-block scan vs plain {e:.2e}")
+    assert e <= SAME["fp32"]
+    plan.close()
+
+
+def test_two_part_scan_matches_oracle_modes():
+    """8 fields of 1024 x 2048, order 2, FP32: the automatic choice is an 8-block scan with
+    two chains per lane; sampled modes of two fields against the oracle."""
+    n, nphi, lmax, kap = 1024, 2048, 1023, 400.0
+    plan = _plan(2, kap, n, nphi, lmax, "fp32")
+    assert plan.ring_blocks(8) == 8
+    g = plan.sample_modes(21, 8)
+    torch.cuda.synchronize()
+    g = g.double().cpu().numpy()
+    g = g[..., 0] + 1j * g[..., 1]
+    plan.close()
+    ms = [0, 1, 2, 100, 511, 1000, 1023]
+    C = oracle.spectrum([kap, kap], lmax)
+    A, B = oracle.setup_modes(2, C, n, ms)
+    go = oracle.sample_modes_list(2, n, ms, A, B, 21, 8)
+    for f in (0, 7):
+        e = rel_rms(np.stack([g[f][:, ms].real, g[f][:, ms].imag]), np.stack([go[f].real, go[f].imag]))
+        log(f"1024x2048 x8 two-part scan: field {f} sampled modes vs oracle {e:.2e}")
+        assert e <= TOL["fp32"]

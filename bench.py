@@ -134,9 +134,22 @@ def measured_traffic(kernel):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(cfg, rings):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(cfg, rings, single_rings):
     """The FP64 oracle (chains + naive DFT) on `rings` rings around the equator of every
-    field of the workload; the factor sets those rings need are built first, untimed."""
+    field of the workload, on all the threads the oracle uses; the same oracle on one
+    thread for `single_rings` rings of field 1; and the oracle's chains followed by
+    numpy's FFT in place of the naive DFT (a fair CPU speed for the sampling).  The factor
+    sets the rings need are built first, untimed."""
     import numpy as np
 
     import oracle
@@ -150,17 +163,47 @@ def cpu_baseline(cfg, rings):
     A, B = oracle.setup(order, C, n, nphi, sets=sets)
     t_setup = time.perf_counter() - t0
     r0, r1 = s - rings // 2 + 1, s + rings // 2 + 1
+    threads = oracle.max_threads()
     t0 = time.perf_counter()
     g = oracle.sample_modes(order, n, A, B, cfg["seed"], count, sets=sets)
     T = oracle.dft(g, nphi, r0, r1)
     dt = time.perf_counter() - t0
     assert np.all(np.isfinite(T))
     pts = count * rings * nphi
-    return {"value": pts / dt, "unit": "grid points/s", "cores": oracle.max_threads(), "kind": "oracle",
+
+    # one thread, a smaller sample: field 1, single_rings rings around the equator
+    sets1 = single_rings // 2 + 1
+    q0, q1 = s - single_rings // 2 + 1, s + single_rings // 2 + 1
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        g1 = oracle.sample_modes(order, n, A, B, cfg["seed"], 1, sets=sets1)
+        T1 = oracle.dft(g1, nphi, q0, q1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    assert np.all(np.isfinite(T1))
+
+    # chains + numpy irfft: T = g_0 + 2 sum Re(g_m e^{i m phi}) = n_phi * irfft(g)
+    t0 = time.perf_counter()
+    gf = oracle.sample_modes(order, n, A, B, cfg["seed"], count, sets=sets)
+    X = np.zeros((count, rings, nphi // 2 + 1), dtype=np.complex128)
+    X[:, :, : gf.shape[2]] = gf[:, r0:r1, :]
+    X[:, :, 0] = X[:, :, 0].real
+    Tf = np.fft.irfft(X, n=nphi, axis=-1) * nphi
+    dtf = time.perf_counter() - t0
+    err = float(np.max(np.abs(Tf - T)) / np.max(np.abs(T)))
+    assert err < 1e-10, err
+    return {"value": pts / dt, "unit": "grid points/s", "cores": threads, "kind": "oracle",
             "sample": (f"{cfg['name']}: all {count} fields, the {rings} rings around the equator (all "
                        f"{lmax + 1} modes, {pts} points), chains + naive DFT in FP64; setup of the "
                        f"{sets} factor sets they need ({t_setup:.1f} s) not timed"),
-            "seconds": dt}
+            "seconds": dt, "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "single_thread": {"value": single_rings * nphi / dt1, "unit": "grid points/s", "cores": 1,
+                              "sample": f"field 1, the {single_rings} rings around the equator", "seconds": dt1},
+            "chains_plus_numpy_fft": {"value": pts / dtf, "unit": "grid points/s", "cores": threads,
+                                      "sample": "same as the oracle sample; numpy.fft.irfft in place of the naive DFT",
+                                      "seconds": dtf, "max_rel_diff_vs_oracle": err}}
 
 
 def main():
@@ -172,6 +215,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-rings", type=int, default=384)
+    ap.add_argument("--cpu-single-rings", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (calibrates rocprofv3 FETCH/WRITE_SIZE)")
     args = ap.parse_args()
@@ -257,6 +301,16 @@ def main():
         roofline = {"bound": "hbm", "achieved": kd["alg_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": kd["hbm_frac"], "traffic": traffic, "kernel": dom}
     roofline["path_alg_GBs"] = (fac_bytes + g_bytes + 2 * count * n * nphi * 4) / (ms_step * 1e-3) / 1e9
+    roofline["path_hbm_frac"] = roofline["path_alg_GBs"] / HBM_PEAK_GBS
+    tr_fft = measured_traffic("c2r_fft")
+    tr_rec = measured_traffic("recursion")
+    if tr_fft is not None and tr_rec is not None:
+        roofline["path_traffic_GBs"] = (tr_fft + tr_rec) / (ms_step * 1e-3) / 1e9
+        roofline["path_traffic_frac"] = roofline["path_traffic_GBs"] / HBM_PEAK_GBS
+    # normals per second of the recursion against the Philox4x32-10 + Box-Muller issue peak
+    # (VALU_PEAK_SLOTS / 42 slots per normal)
+    kr["normals_per_s"] = pts * order / (ms_rec * 1e-3)
+    kr["normals_frac_of_issue_peak"] = kr["normals_per_s"] / (VALU_PEAK_SLOTS / 42.0)
 
     batch = None
     if not args.no_batch:
@@ -268,7 +322,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {args.cpu_rings} rings")
-        cpu = cpu_baseline(cfg, args.cpu_rings)
+        cpu = cpu_baseline(cfg, args.cpu_rings, args.cpu_single_rings)
         log(f"  {cpu['value']:.3e} pts/s on {cpu['cores']} threads in {cpu['seconds']:.1f} s")
 
     line = {

@@ -82,6 +82,8 @@ def _load():
     lib.orc_dft.argtypes = [_i, _i, _i, _i, _i, _i, _pd, _pd]
     lib.orc_dft.restype = _i
     lib.orc_max_threads.restype = _i
+    lib.orc_set_threads.argtypes = [_i]
+    lib.orc_set_threads.restype = None
     _lib = lib
     return lib
 
@@ -199,6 +201,11 @@ def sample_modes_list(order, n_theta, modes, A, B, seed, count, sets=None):
 def max_threads():
     """OpenMP threads the oracle's parallel loops use."""
     return _load().orc_max_threads()
+
+
+def set_threads(n):
+    """Sets the OpenMP threads of the oracle's parallel loops (results do not depend on it)."""
+    _load().orc_set_threads(int(n))
 
 
 def philox(ctr, key):

@@ -57,6 +57,16 @@
 #define M_PI 3.14159265358979323846
 #endif
 
+/* Threads of the parallel loops (timing only: the loops' results do not depend on it). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Threads an OpenMP region of the oracle will use. */
 int orc_max_threads(void)
 {

@@ -17,6 +17,12 @@ struct PhiloxBlock {
     uint32_t w[4];
 };
 
+// a ^ b ^ c in one gfx950 three-input bitwise op (truth table 0x96: odd parity)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ PhiloxBlock philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
                                                      uint32_t c3, uint32_t k0, uint32_t k1)
 {
@@ -24,8 +30,8 @@ __device__ __forceinline__ PhiloxBlock philox4x32_10(uint32_t c0, uint32_t c1, u
     for (int r = 0; r < 10; ++r) {
         const uint64_t pa = (uint64_t)c0 * 0xD2511F53u;
         const uint64_t pb = (uint64_t)c2 * 0xCD9E8D57u;
-        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(pb >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(pa >> 32), c3, k1);
         c1 = (uint32_t)pb;
         c3 = (uint32_t)pa;
         c0 = n0;
@@ -65,8 +71,8 @@ struct PhiloxLanes {
         for (int i = 0; i < N; ++i) {
             const uint64_t pa = (uint64_t)a[i] * 0xD2511F53u;
             const uint64_t pb = (uint64_t)c[i] * 0xCD9E8D57u;
-            const uint32_t n0 = (uint32_t)(pb >> 32) ^ b[i] ^ k0;
-            const uint32_t n2 = (uint32_t)(pa >> 32) ^ d[i] ^ k1;
+            const uint32_t n0 = xor3((uint32_t)(pb >> 32), b[i], k0);
+            const uint32_t n2 = xor3((uint32_t)(pa >> 32), d[i], k1);
             b[i] = (uint32_t)pb;
             d[i] = (uint32_t)pa;
             a[i] = n0;

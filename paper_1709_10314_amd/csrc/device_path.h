@@ -1,9 +1,13 @@
 // Device bodies of the sampling path, shared by the per-plan kernels (sample.hip) and the
 // batch kernels (batch.hip):
-//   run_chain  -- one (field, hemisphere, mode, part) chain of the latitude-ring recursion
-//                 with fused Philox normals (Creasey & Lang, Alg. 2; eqs. (state_initial),
-//                 (state_space); the mirror remark after Alg. 1)
-//   c2r_row    -- the complex-to-real inverse FFT of one ring, in place (Alg. 2, last step)
+//   chain_start, walk_hemisphere, run_chain
+//              -- the latitude-ring recursion of one (field, hemisphere, mode) for one part
+//                 or both parts per lane, with fused Philox normals (Creasey & Lang,
+//                 Alg. 2; eqs. (state_initial), (state_space); the mirror remark after
+//                 Alg. 1); the affine scan walks ring blocks with the same pieces
+//   c2r_row, c2r_rows
+//              -- the complex-to-real inverse FFT of one ring / of many rings per
+//                 workgroup, in place (Alg. 2, last step)
 #pragma once
 
 #include "rng.h"

@@ -208,7 +208,8 @@ def smf_autotune_batch(plan, seed, out_ptr, stream=None):
 
 
 class BatchPlan:
-    """Many fields of uneven shape, spectrum and order, sampled in one persistent launch."""
+    """Many fields of uneven shape, spectrum and order, sampled by one call: a launch over
+    every chain of every field, then one over every ring (a HIP graph can capture both)."""
 
     def __init__(self, fields, stream=None):
         rc, h = smf_setup_batch(fields, SMF_FP32, stream)

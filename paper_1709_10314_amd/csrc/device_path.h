@@ -178,14 +178,15 @@ __device__ __forceinline__ void step_group_direct(int base, int lo, int hi, int 
 }
 
 // Walks rings r_first..r_last (north: descending, south: ascending), storing each ring's
-// x0 unless `store` is false (then only the end state is wanted).
-template <typename T, int M, int P, bool NORTH, int NCH>
+// x0 unless STORE is false (then only the end state is wanted; a compile-time choice keeps
+// the pipelined loop body free of branches).
+template <typename T, int M, int P, bool NORTH, int NCH, bool STORE = true>
 __device__ __forceinline__ void walk_hemisphere(int s, int even, int r_first, int r_last, int m, uint32_t up0,
                                                 uint32_t k0, uint32_t k1, const T (&sc)[NCH],
                                                 const T* __restrict__ fm, size_t set_stride, int n_sets,
-                                                T* __restrict__ g, size_t row, T (&x0)[NCH], T (&x1)[NCH],
-                                                bool store = true)
+                                                T* __restrict__ g, size_t row, T (&x0)[NCH], T (&x1)[NCH])
 {
+    constexpr bool store = STORE;
     constexpr int G = 4 / M;
     const uint32_t um = (uint32_t)m;
     if (NORTH ? r_first < r_last : r_first > r_last) return;

@@ -124,13 +124,22 @@ __global__ __launch_bounds__(64 * B) void scan_kernel(ScanArgs a, const T* __res
 #pragma unroll
     for (int c = 0; c < NCH; ++c) x0[c] = x1[c] = T(0);
     if (active) {
-        if (blk == 0) chain_start<T, M, NCH>(a.s, a.even, h, um, up, k0, k1, sc, fm, set_stride, g, row, true, x0, x1);
-        if (h == 0)
-            walk_hemisphere<T, M, P, true, NCH>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm, set_stride,
-                                                a.n_sets, g, row, x0, x1, blk == 0);
-        else
-            walk_hemisphere<T, M, P, false, NCH>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm, set_stride,
-                                                 a.n_sets, g, row, x0, x1, blk == 0);
+        if (blk == 0) {
+            chain_start<T, M, NCH>(a.s, a.even, h, um, up, k0, k1, sc, fm, set_stride, g, row, true, x0, x1);
+            if (h == 0)
+                walk_hemisphere<T, M, P, true, NCH, true>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm,
+                                                          set_stride, a.n_sets, g, row, x0, x1);
+            else
+                walk_hemisphere<T, M, P, false, NCH, true>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm,
+                                                           set_stride, a.n_sets, g, row, x0, x1);
+        } else {
+            if (h == 0)
+                walk_hemisphere<T, M, P, true, NCH, false>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm,
+                                                           set_stride, a.n_sets, g, row, x0, x1);
+            else
+                walk_hemisphere<T, M, P, false, NCH, false>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm,
+                                                            set_stride, a.n_sets, g, row, x0, x1);
+        }
     }
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
@@ -175,11 +184,11 @@ __global__ __launch_bounds__(64 * B) void scan_kernel(ScanArgs a, const T* __res
         x1[c] = y1[c];
     }
     if (h == 0)
-        walk_hemisphere<T, M, P, true, NCH>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm, set_stride,
-                                            a.n_sets, g, row, x0, x1, true);
+        walk_hemisphere<T, M, P, true, NCH, true>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm, set_stride,
+                                                  a.n_sets, g, row, x0, x1);
     else
-        walk_hemisphere<T, M, P, false, NCH>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm, set_stride,
-                                             a.n_sets, g, row, x0, x1, true);
+        walk_hemisphere<T, M, P, false, NCH, true>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm, set_stride,
+                                                   a.n_sets, g, row, x0, x1);
 }
 
 template <typename T, int M, int NCH>

@@ -109,7 +109,71 @@ __device__ __forceinline__ void philox4x32_10_n(const uint32_t* c0, uint32_t c1,
 template <typename T>
 struct BoxMuller;
 
-// FP64: accurate log, sqrt and sin/cos of 2 pi u (via sinpi/cospi of 2u).
+// FP64 natural log of u in (0, 1]: u = m 2^e with m in [sqrt(1/2), sqrt(2)), and
+// ln m = 2 atanh(f), f = (m - 1) / (m + 1), |f| <= 0.1716, from the series
+// 2 (f + f^3/3 + ... + f^23/23) (truncation below 1e-18); ln 2 split in two parts.
+// Within 1 ulp of the correctly rounded log over the uniforms Box-Muller uses.
+__device__ __forceinline__ double log_unit(double u)
+{
+    int e;
+    double m = frexp(u, &e);
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double f = (m - 1.0) / (m + 1.0);
+    const double f2 = f * f;
+    double p = 1.0 / 23.0;
+    p = fma(p, f2, 1.0 / 21.0);
+    p = fma(p, f2, 1.0 / 19.0);
+    p = fma(p, f2, 1.0 / 17.0);
+    p = fma(p, f2, 1.0 / 15.0);
+    p = fma(p, f2, 1.0 / 13.0);
+    p = fma(p, f2, 1.0 / 11.0);
+    p = fma(p, f2, 1.0 / 9.0);
+    p = fma(p, f2, 1.0 / 7.0);
+    p = fma(p, f2, 1.0 / 5.0);
+    p = fma(p, f2, 1.0 / 3.0);
+    const double lm = fma(2.0 * f * f2, p, 2.0 * f);
+    const double ln2_hi = 0x1.62e42fefa39efp-1, ln2_lo = 0x1.abc9e3b39803fp-56;
+    return fma((double)e, ln2_hi, fma((double)e, ln2_lo, lm));
+}
+
+// sin(pi x), cos(pi x) for x in [0, 2]: x = n/2 + r with n = rint(2x), |r| <= 1/4 (the
+// subtraction is exact), Taylor series of sin and cos of y = pi r to degree 17 / 18
+// (truncation below 1e-16 of y), then the quarter-turn n mod 4.  Absolute error within
+// 4e-16.
+__device__ __forceinline__ void sincospi_turn(double x, double& s, double& c)
+{
+    const double n = rint(2.0 * x);
+    const double r = fma(-0.5, n, x);
+    const double y = r * 3.14159265358979323846;
+    const double y2 = y * y;
+    double ps = -1.0 / 355687428096000.0;   // -1/17!
+    ps = fma(ps, y2, 1.0 / 1307674368000.0);
+    ps = fma(ps, y2, -1.0 / 6227020800.0);
+    ps = fma(ps, y2, 1.0 / 39916800.0);
+    ps = fma(ps, y2, -1.0 / 362880.0);
+    ps = fma(ps, y2, 1.0 / 5040.0);
+    ps = fma(ps, y2, -1.0 / 120.0);
+    ps = fma(ps, y2, 1.0 / 6.0);
+    const double sy = fma(-y * y2, ps, y);
+    double pc = 1.0 / 6402373705728000.0;   // 1/18!
+    pc = fma(pc, y2, -1.0 / 20922789888000.0);
+    pc = fma(pc, y2, 1.0 / 87178291200.0);
+    pc = fma(pc, y2, -1.0 / 479001600.0);
+    pc = fma(pc, y2, 1.0 / 3628800.0);
+    pc = fma(pc, y2, -1.0 / 40320.0);
+    pc = fma(pc, y2, 1.0 / 720.0);
+    pc = fma(pc, y2, -1.0 / 24.0);
+    pc = fma(pc, y2, 0.5);
+    const double cy = fma(-y2, pc, 1.0);
+    const int q = (int)n & 3;
+    s = q == 0 ? sy : (q == 1 ? cy : (q == 2 ? -sy : -cy));
+    c = q == 0 ? cy : (q == 1 ? -sy : (q == 2 ? -cy : sy));
+}
+
+// FP64: the log and sin/cos above, the correctly rounded sqrt.
 template <>
 struct BoxMuller<double> {
     // (sc r cos, sc r sin) of the pair (x0, x1)
@@ -117,9 +181,9 @@ struct BoxMuller<double> {
     {
         const double u0 = ((double)x0 + 0.5) * 0x1p-32;
         const double u1 = ((double)x1 + 0.5) * 0x1p-32;
-        const double r = sc * sqrt(-2.0 * log(u0));
+        const double r = sc * sqrt(-2.0 * log_unit(u0));
         double s, c;
-        sincospi(2.0 * u1, &s, &c);
+        sincospi_turn(2.0 * u1, s, c);
         a = r * c;
         b = r * s;
     }

@@ -187,3 +187,30 @@ def test_two_part_scan_matches_oracle_modes():
         e = rel_rms(np.stack([g[f][:, ms].real, g[f][:, ms].imag]), np.stack([go[f].real, go[f].imag]))
         log(f"1024x2048 x8 two-part scan: field {f} sampled modes vs oracle {e:.2e}")
         assert e <= TOL["fp32"]
+
+
+@pytest.mark.parametrize("blocks", [1, 8])
+def test_single_plan_graph_capture_replays(blocks):
+    """smf_sample (plain recursion or scan, then the FFT) captured in a HIP graph: every
+    replay, with eager work and synchronisations between replays, equals the eager call."""
+    plan = _plan(2, 900.0, 512, 1024, 511, "fp32")
+    plan.set_ring_blocks(blocks)
+    eager = plan.sample(13, 2).clone()
+    torch.cuda.synchronize()
+    out = plan.empty(2)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.sample(13, 2, out, stream=s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        plan.sample(13, 2, out, stream=s)
+    for rep in range(3):
+        out.zero_()
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), (blocks, rep)
+        del junk
+    plan.close()

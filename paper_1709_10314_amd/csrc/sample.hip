@@ -10,7 +10,7 @@ struct RecArgs {
     int n_theta, n_phi, m_top, m_rows, n_sets, s, even;
     int n_fh;          // 2 * count (field, hemisphere) families
     int n_fg;          // workgroups per m-tile: ceil(n_fh / 4)
-    int n_wg;          // n_mtiles * n_fg real workgroups
+    int n_wg;          // m-tiles * n_fg workgroups with work
     int per_xcd;       // launched workgroups / 8
     uint32_t seed_lo, seed_hi;
 };
@@ -20,6 +20,7 @@ struct RecArgs {
 // (twice the waves, half the serial work per wave).  Both give identical results; the
 // host picks per call (FP64 always uses 1: two FP64 chains do not fit the register
 // budget).
+//
 // One lane per (field f, hemisphere h, mode m[, part]).  A wave holds 64 modes (two parts
 // per lane) or 32 modes x 2 parts of one (f, h), so f and h are wave-uniform (scalar
 // registers) and so are the Philox key and the ring order; a workgroup holds four (f, h)

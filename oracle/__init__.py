@@ -18,6 +18,7 @@ the paper they follow:
 * ``dft``           -- inverse DFT along phi                         (Alg. 2, last step)
 """
 import ctypes
+import math
 import os
 import subprocess
 
@@ -63,6 +64,8 @@ def _load():
     lib.orc_ring_zs.argtypes = [_i, _i, _pd, _pd]
     lib.orc_setup.argtypes = [_i, _i, _pd, _i, _i, _i, _pd, _pd]
     lib.orc_setup.restype = _i
+    lib.orc_setup_z.argtypes = [_i, _i, _pd, _i, _pd, _i, _i, _pd, _pd]
+    lib.orc_setup_z.restype = _i
     lib.orc_n_sets.argtypes = [_i]
     lib.orc_n_sets.restype = _i
     lib.orc_start_ring.argtypes = [_i]
@@ -76,6 +79,8 @@ def _load():
     lib.orc_sample_modes.restype = _i
     _pi = ctypes.POINTER(ctypes.c_int)
     lib.orc_setup_modes.argtypes = [_i, _i, _pd, _i, _i, _pi, _i, _pd, _pd]
+    lib.orc_setup_modes_z.argtypes = [_i, _i, _pd, _i, _pd, _i, _pi, _i, _pd, _pd]
+    lib.orc_setup_modes_z.restype = _i
     lib.orc_setup_modes.restype = _i
     lib.orc_sample_modes_list.argtypes = [_i, _i, _pi, _i, _i, _pd, _pd, _u64, _i, _pd]
     lib.orc_sample_modes_list.restype = _i
@@ -128,6 +133,17 @@ def jblock(order, m, ell_max, C, theta1, theta2):
     return J.reshape(order, order)
 
 
+def jblock_z(order, m, ell_max, C, z1, z2):
+    """J^m(z1, z2) at two grid values, sin(theta) = sqrt((1 - z)(1 + z)) as the explicit-grid
+    setup takes it."""
+    C = np.ascontiguousarray(C, dtype=np.float64)
+    s1 = math.sqrt((1.0 - z1) * (1.0 + z1))
+    s2 = math.sqrt((1.0 - z2) * (1.0 + z2))
+    J = np.zeros(order * order)
+    _load().orc_jblock_zs(order, m, ell_max, _p(C), float(z1), s1, float(z2), s2, _p(J))
+    return J.reshape(order, order)
+
+
 def ring_zs(n_theta, i):
     """(z_i, sin theta_i) of ring i, through the complementary angle (exact at the equator)."""
     z = ctypes.c_double()
@@ -158,29 +174,43 @@ def m_top(ell_max, n_phi):
     return _load().orc_m_top(ell_max, n_phi)
 
 
-def setup(order, C, n_theta, n_phi, sets=None):
-    """Alg. 1.  Returns (A, B), each [sets][m_top+1][order][order]; set 0 holds B_eq."""
+def _zgrid(z, n_theta):
+    if z is None:
+        return None
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    if z.shape != (n_theta,):
+        raise ValueError("z must hold n_theta ring values")
+    return z
+
+
+def setup(order, C, n_theta, n_phi, sets=None, z=None):
+    """Alg. 1.  Returns (A, B), each [sets][m_top+1][order][order]; set 0 holds B_eq.
+    z: optional ring values (north to south, symmetric about the equator); default the
+    ring centres."""
     C = np.ascontiguousarray(C, dtype=np.float64)
     ell_max = len(C) - 1
     mt = m_top(ell_max, n_phi)
     ns = n_sets(n_theta) if sets is None else min(sets, n_sets(n_theta))
     A = np.zeros((ns, mt + 1, order, order))
     B = np.zeros((ns, mt + 1, order, order))
-    rc = _load().orc_setup(order, ell_max, _p(C), n_theta, n_phi, ns, _p(A), _p(B))
+    zg = _zgrid(z, n_theta)
+    rc = _load().orc_setup_z(order, ell_max, _p(C), n_theta, None if zg is None else _p(zg), n_phi, ns,
+                             _p(A), _p(B))
     if rc != 0:
         raise ValueError("orc_setup rejected its arguments")
     return A, B
 
 
-def setup_modes(order, C, n_theta, modes, sets=None):
+def setup_modes(order, C, n_theta, modes, sets=None, z=None):
     """Alg. 1 for the listed modes only: (A, B), each [sets][len(modes)][order][order]."""
     C = np.ascontiguousarray(C, dtype=np.float64)
     md = np.ascontiguousarray(modes, dtype=np.int32)
     ns = n_sets(n_theta) if sets is None else min(sets, n_sets(n_theta))
     A = np.zeros((ns, len(md), order, order))
     B = np.zeros((ns, len(md), order, order))
-    rc = _load().orc_setup_modes(order, len(C) - 1, _p(C), n_theta, ns,
-                                 md.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(md), _p(A), _p(B))
+    zg = _zgrid(z, n_theta)
+    rc = _load().orc_setup_modes_z(order, len(C) - 1, _p(C), n_theta, None if zg is None else _p(zg), ns,
+                                   md.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(md), _p(A), _p(B))
     if rc != 0:
         raise ValueError("orc_setup_modes rejected its arguments")
     return A, B

@@ -27,7 +27,10 @@
  *
  * Readings where the paper is silent or garbled (each is listed in the design notes):
  *   grid      theta_i = pi (i + 1/2) / n_theta, z_i = cos(theta_i), ring 0 nearest z = +1;
- *             phi_j = 2 pi j / n_phi; z_i evaluated as sin(pi (n - 2i - 1) / (2n)).
+ *             phi_j = 2 pi j / n_phi; z_i evaluated as sin(pi (n - 2i - 1) / (2n)).  For
+ *             odd n_theta = 2k + 1 this is the symmetric example grid of Sec. 4 read as
+ *             z_j = sin(pi j / (2k + 1)).  Alg. 1 also takes any grid symmetric about the
+ *             equator (orc_setup_z), with sin(theta) = sqrt((1 - z)(1 + z)).
  *   modes     m = 0 .. m_top, m_top = min(ell_max, n_phi/2 - 1); the Nyquist mode is not used.
  *   DFT       unnormalised: T = g_0 + 2 sum_{m>=1} Re(g_m e^{i m phi}).
  *   A, B      A = J(b,a) J(a,a)^+ with J(b,a)_pq = E[x_b,p x_a,q];  S = J(b,b) - A J(a,b);
@@ -358,11 +361,21 @@ static void set_rings(int n_theta, int j, int* a, int* b)
 /* j = 0..n_sets-1.  A and B are [n_sets][n_modes][M][M] (row-major, B lower    */
 /* triangular); for j = 0, A = 0 and B = B_eq.  n_sets may be smaller than      */
 /* orc_n_sets(n_theta) to cover only the rings nearest the start.              */
+/* zgrid: the ring values z_0 > z_1 > ... > z_{n-1} of Alg. 1's grid argument,  */
+/* symmetric (z_{n-1-i} = -z_i), with sin(theta) = sqrt((1 - z)(1 + z)); NULL    */
+/* selects the ring centres.  Only the northern rings are read.                */
 /* ------------------------------------------------------------------------- */
-int orc_setup_modes(int order, int ell_max, const double* C, int n_theta, int n_sets,
-                    const int* modes, int n_modes, double* A, double* B)
+int orc_setup_modes_z(int order, int ell_max, const double* C, int n_theta, const double* zgrid,
+                      int n_sets, const int* modes, int n_modes, double* A, double* B)
 {
     if (order < 1 || order > ORC_MAXM || n_theta < 2 || ell_max < 0) return -1;
+    if (zgrid) {
+        for (int i = 0; i < n_theta; ++i) {
+            if (!(zgrid[i] > -1.0 && zgrid[i] < 1.0)) return -1;
+            if (i > 0 && !(zgrid[i] < zgrid[i - 1])) return -1;
+            if (zgrid[n_theta - 1 - i] != -zgrid[i]) return -1;
+        }
+    }
     int MM = order * order;
     int total = orc_n_sets(n_theta);
     if (n_sets > total) n_sets = total;
@@ -374,8 +387,15 @@ int orc_setup_modes(int order, int ell_max, const double* C, int n_theta, int n_
             int a, b;
             set_rings(n_theta, j, &a, &b);
             double za, sa, zb, sb;
-            orc_ring_zs(n_theta, a, &za, &sa);
-            orc_ring_zs(n_theta, b, &zb, &sb);
+            if (zgrid) {
+                za = zgrid[a];
+                zb = zgrid[b];
+                sa = sqrt((1.0 - za) * (1.0 + za));
+                sb = sqrt((1.0 - zb) * (1.0 + zb));
+            } else {
+                orc_ring_zs(n_theta, a, &za, &sa);
+                orc_ring_zs(n_theta, b, &zb, &sb);
+            }
             double* Aj = A + ((size_t)j * n_modes + i) * MM;
             double* Bj = B + ((size_t)j * n_modes + i) * MM;
             if (j == 0) {
@@ -393,17 +413,30 @@ int orc_setup_modes(int order, int ell_max, const double* C, int n_theta, int n_
     return 0;
 }
 
-/* Alg. 1 for every mode m = 0..m_top. */
-int orc_setup(int order, int ell_max, const double* C, int n_theta, int n_phi, int n_sets,
-              double* A, double* B)
+/* The same on the ring-centre grid. */
+int orc_setup_modes(int order, int ell_max, const double* C, int n_theta, int n_sets,
+                    const int* modes, int n_modes, double* A, double* B)
+{
+    return orc_setup_modes_z(order, ell_max, C, n_theta, NULL, n_sets, modes, n_modes, A, B);
+}
+
+/* Alg. 1 for every mode m = 0..m_top (zgrid as in orc_setup_modes_z). */
+int orc_setup_z(int order, int ell_max, const double* C, int n_theta, const double* zgrid, int n_phi,
+                int n_sets, double* A, double* B)
 {
     int m_top = orc_m_top(ell_max, n_phi);
     int* modes = (int*)malloc(sizeof(int) * (m_top + 1));
     if (!modes) return -1;
     for (int m = 0; m <= m_top; ++m) modes[m] = m;
-    int rc = orc_setup_modes(order, ell_max, C, n_theta, n_sets, modes, m_top + 1, A, B);
+    int rc = orc_setup_modes_z(order, ell_max, C, n_theta, zgrid, n_sets, modes, m_top + 1, A, B);
     free(modes);
     return rc;
+}
+
+int orc_setup(int order, int ell_max, const double* C, int n_theta, int n_phi, int n_sets,
+              double* A, double* B)
+{
+    return orc_setup_z(order, ell_max, C, n_theta, NULL, n_phi, n_sets, A, B);
 }
 
 /* ------------------------------------------------------------------------- */

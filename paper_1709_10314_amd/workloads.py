@@ -40,3 +40,41 @@ def batch_mix(n_fields=256, seed=0):
         out.append(dict(n_theta=n_theta, n_phi=2 * n_theta, order=order, kappa=kappa,
                         ell_max=n_theta - 1, seed=1 + f, precision="fp32"))
     return out
+
+
+# ---- ring grids z_0 > z_1 > ... > z_{n-1}, symmetric about the equator (z_{n-1-i} = -z_i
+# exactly), the grid argument of Alg. 1 ----
+
+def _mirror(z_north, n):
+    """Full grid from its northern values z_0 .. z_{ceil(n/2)-1} (the middle one 0 for odd n)."""
+    z = np.empty(n)
+    h = (n + 1) // 2
+    z[:h] = z_north[:h]
+    if n % 2:
+        z[h - 1] = 0.0
+    z[n - h:] = -z[:h][::-1]
+    return z
+
+
+def gauss_legendre_z(n):
+    """The n Gauss-Legendre nodes in (-1, 1), descending (numpy's leggauss)."""
+    x = np.polynomial.legendre.leggauss(n)[0][::-1].copy()
+    return _mirror(x, n)
+
+
+def healpix_ring_z(nside):
+    """The 4 nside - 1 ring latitudes of a HEALPix grid: z = 1 - k^2 / (3 nside^2) in the
+    polar caps (k < nside), z = (4 nside - 2k) / (3 nside) in the equatorial belt."""
+    k = np.arange(1, 2 * nside + 1, dtype=np.float64)
+    zn = np.where(k < nside, 1.0 - k * k / (3.0 * nside * nside), (4.0 * nside - 2.0 * k) / (3.0 * nside))
+    return _mirror(zn, 4 * nside - 1)
+
+
+def random_z(n, seed=0):
+    """A symmetric grid with the northern values drawn uniformly in (0, 1) (PCG64(seed))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h = (n + 1) // 2
+    zn = np.sort(rng.uniform(0.0, 1.0, h))[::-1]
+    if n % 2 == 0:
+        zn = np.maximum(zn, 1e-3)
+    return _mirror(zn, n)

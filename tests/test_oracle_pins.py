@@ -144,17 +144,22 @@ def test_spectrum_rejects_nonpositive(orc):
 
 
 # --------------------------------------------------------------------------- factors
-def _propagate_check(orc, order, kappa, n, lmax, n_phi):
+def _propagate_check(orc, order, kappa, n, lmax, n_phi, z=None):
     """Covariance propagation through the factors (Sigma_b = A Sigma_a A^T + B B^T, cross
     A Sigma_a) reproduces J(b,b) and J(b,a) at every step of both hemispheres, the south
-    computed from J at the true southern rings (mirror via D A D, D B D)."""
+    computed from J at the true southern rings (mirror via D A D, D B D).  z: an explicit
+    ring grid (default the ring centres)."""
     C = orc.spectrum([kappa] * order, lmax)
-    A, B = orc.setup(order, C, n, n_phi)
-    th, _ = orc.grid(n)
+    A, B = orc.setup(order, C, n, n_phi, z=z)
     s = orc.start_ring(n)
     D = np.diag([(-1.0) ** p for p in range(order)])
     even = n % 2 == 0
     worst = 0.0
+
+    def jb(m, i1, i2):
+        if z is None:
+            return orc.jblock_ring(order, m, lmax, C, n, i1, i2)
+        return orc.jblock_z(order, m, lmax, C, z[i1], z[i2])
 
     def cmp(S, K):
         d = np.sqrt(np.maximum(np.diag(K), 0))
@@ -163,15 +168,15 @@ def _propagate_check(orc, order, kappa, n, lmax, n_phi):
         return np.max(np.abs(S - K)[mask] / sc[mask]) if mask.any() else 0.0
 
     for m in range(A.shape[1]):
-        Ks = orc.jblock_ring(order, m, lmax, C, n, s, s)
+        Ks = jb(m, s, s)
         Ss = B[0, m] @ B[0, m].T
         worst = max(worst, cmp(Ss, Ks))
         # north
         Sig, a = Ss, s
         for j in range(2 if even else 1, A.shape[0]):
             b = s - j + 1 if even else s - j
-            Kbb = orc.jblock_ring(order, m, lmax, C, n, b, b)
-            Kba = orc.jblock_ring(order, m, lmax, C, n, b, a)
+            Kbb = jb(m, b, b)
+            Kba = jb(m, b, a)
             cross = A[j, m] @ Sig
             Sig = A[j, m] @ Sig @ A[j, m].T + B[j, m] @ B[j, m].T
             worst = max(worst, cmp(Sig, Kbb), cmp(cross, Kba))
@@ -181,8 +186,8 @@ def _propagate_check(orc, order, kappa, n, lmax, n_phi):
         j0 = 1
         if even:
             b = s + 1
-            Kbb = orc.jblock_ring(order, m, lmax, C, n, b, b)
-            Kba = orc.jblock_ring(order, m, lmax, C, n, b, a)
+            Kbb = jb(m, b, b)
+            Kba = jb(m, b, a)
             cross = A[1, m] @ Sig
             Sig = A[1, m] @ Sig @ A[1, m].T + B[1, m] @ B[1, m].T
             worst = max(worst, cmp(Sig, Kbb), cmp(cross, Kba))
@@ -190,8 +195,8 @@ def _propagate_check(orc, order, kappa, n, lmax, n_phi):
         for j in range(j0, A.shape[0]):
             b = a + 1
             Am, Bm = D @ A[j, m] @ D, D @ B[j, m] @ D
-            Kbb = orc.jblock_ring(order, m, lmax, C, n, b, b)
-            Kba = orc.jblock_ring(order, m, lmax, C, n, b, a)
+            Kbb = jb(m, b, b)
+            Kba = jb(m, b, a)
             cross = Am @ Sig
             Sig = Am @ Sig @ Am.T + Bm @ Bm.T
             worst = max(worst, cmp(Sig, Kbb), cmp(cross, Kba))
@@ -413,13 +418,9 @@ def test_constant_field_when_lmax_zero(orc):
             np.testing.assert_allclose(T[f], math.sqrt(C[0] / (4 * math.pi)) * xi, rtol=1e-13)
 
 
-@pytest.mark.parametrize("order,kappa,n,lmax", [(1, 64.0, 16, 15), (2, 50.0, 11, 10), (1, 5.0, 10, 40)])
-def test_chain_variance_closed_form(orc, order, kappa, n, lmax):
-    """Var T(z_i, phi) = sum_l (2l+1) C_l / (4 pi) at every ring, from exact covariance
-    propagation through the factors in both hemispheres (no m truncation: n_phi large)."""
-    n_phi = 2 * (lmax + 1)
-    C = orc.spectrum([kappa] * order, lmax)
-    A, B = orc.setup(order, C, n, n_phi)
+def _chain_variance(orc, order, A, B, n):
+    """Var T(z_i, phi) at every ring from exact covariance propagation through the factors
+    in both hemispheres (sum over the modes, weight 2 for m > 0)."""
     s = orc.start_ring(n)
     D = np.diag([(-1.0) ** p for p in range(order)])
     even = n % 2 == 0
@@ -442,8 +443,75 @@ def test_chain_variance_closed_form(orc, order, kappa, n, lmax):
             Sig = Am @ Sig @ Am.T + Bm @ Bm.T
             r += 1
             var[r] += w * Sig[0, 0]
+    return var
+
+
+@pytest.mark.parametrize("order,kappa,n,lmax", [(1, 64.0, 16, 15), (2, 50.0, 11, 10), (1, 5.0, 10, 40)])
+def test_chain_variance_closed_form(orc, order, kappa, n, lmax):
+    """Var T(z_i, phi) = sum_l (2l+1) C_l / (4 pi) at every ring, from exact covariance
+    propagation through the factors in both hemispheres (no m truncation: n_phi large)."""
+    n_phi = 2 * (lmax + 1)
+    C = orc.spectrum([kappa] * order, lmax)
+    A, B = orc.setup(order, C, n, n_phi)
+    var = _chain_variance(orc, order, A, B, n)
     ref = np.sum((2 * np.arange(lmax + 1) + 1) * C) / (4 * math.pi)
     np.testing.assert_allclose(var, ref, rtol=1e-11)
+
+
+# --------------------------------------------------------------------------- explicit grids
+def _grids():
+    from paper_1709_10314_amd import workloads as w
+
+    return {"gauss-legendre-12": w.gauss_legendre_z(12), "gauss-legendre-13": w.gauss_legendre_z(13),
+            "healpix-nside4": w.healpix_ring_z(4), "random-10": w.random_z(10, 3),
+            "random-15": w.random_z(15, 4)}
+
+
+@pytest.mark.parametrize("grid", sorted(_grids()))
+@pytest.mark.parametrize("order,kappa,lmax", [(1, 64.0, 30), (2, 100.0, 25)])
+def test_explicit_grid_factors_reproduce_ring_covariances(orc, grid, order, kappa, lmax):
+    """Alg. 1 on a grid given as values (Gauss-Legendre nodes, HEALPix ring latitudes, a
+    random symmetric grid): covariance propagation through the factors reproduces J at the
+    grid's own rings in both hemispheres."""
+    z = _grids()[grid]
+    assert _propagate_check(orc, order, kappa, len(z), lmax, 2 * (lmax + 1), z=z) < 1e-11
+
+
+@pytest.mark.parametrize("grid", sorted(_grids()))
+@pytest.mark.parametrize("order,kappa,lmax", [(1, 9.0, 24), (2, 50.0, 20)])
+def test_explicit_grid_variance_closed_form(orc, grid, order, kappa, lmax):
+    """The addition theorem at any latitude: Var T(z_i, phi) = sum_l (2l+1) C_l / (4 pi) at
+    every ring of an explicit grid (no m truncation)."""
+    z = _grids()[grid]
+    n = len(z)
+    C = orc.spectrum([kappa] * order, lmax)
+    A, B = orc.setup(order, C, n, 2 * (lmax + 1), z=z)
+    var = _chain_variance(orc, order, A, B, n)
+    ref = np.sum((2 * np.arange(lmax + 1) + 1) * C) / (4 * math.pi)
+    np.testing.assert_allclose(var, ref, rtol=1e-11)
+
+
+def test_explicit_grid_of_ring_centres_is_the_default(orc):
+    """The ring-centre grid given as values gives the default factors (up to the rounding
+    of sin(theta), taken from z instead of the complementary angle)."""
+    for n, order in ((17, 1), (16, 2)):
+        C = orc.spectrum([30.0] * order, 40)
+        A, B = orc.setup(order, C, n, 82)
+        A2, B2 = orc.setup(order, C, n, 82, z=orc.grid(n)[1])
+        np.testing.assert_allclose(A2, A, rtol=0, atol=1e-12 * np.abs(A).max())
+        np.testing.assert_allclose(B2, B, rtol=0, atol=1e-12 * np.abs(B).max())
+
+
+def test_explicit_grid_rejects_bad_grids(orc):
+    C = orc.spectrum([30.0], 10)
+    z = orc.grid(8)[1]
+    bad = [z[::-1].copy(), np.where(np.arange(8) == 7, -z[0] * 0.999, z), np.linspace(1.0, -1.0, 8),
+           np.r_[z[:4], z[:4][::-1] * -1.0 + 1e-9]]
+    for zb in bad:
+        with pytest.raises(ValueError):
+            orc.setup(1, C, 8, 16, z=zb)
+    with pytest.raises(ValueError):
+        orc.setup(1, C, 8, 16, z=z[:7])
 
 
 def test_sample_reproducible_and_field_keyed(orc):

@@ -73,6 +73,20 @@ enum {
 int smf_setup(const smf_spectrum* spec, int n_theta, int n_phi, int flags, void* hip_stream,
               smf_plan** out);
 
+/* Alg. 1 on an explicit grid: its signature takes the ring values z as an input, and the
+ * remark after it stores only the northern half when the grid is symmetric.  z_host
+ * (host, n_theta doubles, copied, not retained) lists the rings from north to south:
+ * strictly decreasing, inside (-1, 1), and symmetric to the bit, z[n_theta-1-i] == -z[i]
+ * (so an odd grid has its equator ring at z = 0).  sin(theta_i) is taken as
+ * sqrt((1 - z_i)(1 + z_i)).  The start ring, the crossing step and the mirror are those of
+ * smf_setup; the phi grid, the sampling calls and their output are unchanged.  Examples: the
+ * ring-centre grid itself (for odd n_theta it is the paper's symmetric example grid, read
+ * as z_j = sin(pi j / n_theta)), Gauss-Legendre nodes, HEALPix ring latitudes.
+ * Errors: as smf_setup, plus SMF_EINVAL for a NULL z_host or a grid that is not strictly
+ * decreasing in (-1, 1) and symmetric. */
+int smf_setup_grid(const smf_spectrum* spec, int n_theta, const double* z_host, int n_phi, int flags,
+                   void* hip_stream, smf_plan** out);
+
 /* Alg. 2 (Gaussian random field generation): `count` fields, field f drawn with the
  * Philox4x32-10 key seed + f.  Writes out_dev, device memory of count*n_theta*n_phi
  * float (SMF_FP32 plan) or double (SMF_FP64 plan), layout [field][ring][phi], ring 0
@@ -81,6 +95,13 @@ int smf_setup(const smf_spectrum* spec, int n_theta, int n_phi, int flags, void*
  * Errors: SMF_EINVAL (NULL plan/out with count > 0, count < 0, count * n_theta > 2^31 - 1),
  * SMF_EHIP. */
 int smf_sample(const smf_plan* plan, uint64_t seed, int count, void* out_dev, void* hip_stream);
+
+/* A lognormal field (the application named at the end of Sec. 4): smf_sample with the
+ * pointwise map out = exp(mu + sigma T) applied as the FFT stores T, in the plan's
+ * precision (FP32: expf of fmaf(sigma, T, mu)).  Same layout, size and keys as smf_sample.
+ * Errors: as smf_sample, plus SMF_EINVAL for a mu or sigma that is not finite. */
+int smf_sample_lognormal(const smf_plan* plan, uint64_t seed, int count, double mu, double sigma, void* out_dev,
+                         void* hip_stream);
 
 /* The chains of Alg. 2 only (eqs. (state_initial) and (state_space)), without the FFT:
  * writes g_m(z_i) for field f, ring i, mode m as interleaved (Re, Im) pairs at

@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "batch.h"
@@ -68,10 +69,23 @@ struct DeviceGuard {
     }
 };
 
+// An explicit grid: n_theta finite values strictly decreasing in (-1, 1) with
+// z[n-1-i] == -z[i] exactly (so an odd grid has z = 0 at its middle ring).
+bool grid_ok(const double* z, int n)
+{
+    for (int i = 0; i < n; ++i) {
+        if (!(z[i] > -1.0 && z[i] < 1.0)) return false;
+        if (i > 0 && !(z[i] < z[i - 1])) return false;
+        if (z[n - 1 - i] != -z[i]) return false;
+    }
+    return true;
+}
+
 // `scan`: also build the block transitions of the affine scan (single-field plans; the
-// sub-plans of a batch only ever run the plain recursion).
-int setup_impl(const smf_spectrum* spec, int n_theta, int n_phi, int flags, hipStream_t st, bool scan,
-               smf_plan** out)
+// sub-plans of a batch only ever run the plain recursion).  z_host: explicit ring values
+// (host, n_theta), or null for the ring centres.
+int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int n_phi, int flags,
+               hipStream_t st, bool scan, smf_plan** out)
 {
     if (!spec || !out) return SMF_EINVAL;
     *out = nullptr;
@@ -82,6 +96,7 @@ int setup_impl(const smf_spectrum* spec, int n_theta, int n_phi, int flags, hipS
     if (n_theta < 2 || n_theta > (1 << 16)) return SMF_EINVAL;
     if (!is_pow2(n_phi) || n_phi < 4 || n_phi > 16384) return SMF_EINVAL;
     if (flags != SMF_FP64 && flags != SMF_FP32) return SMF_EINVAL;
+    if (z_host && !grid_ok(z_host, n_theta)) return SMF_EINVAL;
 
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SMF_EHIP;
@@ -103,6 +118,7 @@ int setup_impl(const smf_spectrum* spec, int n_theta, int n_phi, int flags, hipS
     int rc = SMF_OK;
     double* kappa_dev = nullptr;
     double* cexp_dev = nullptr;
+    double* z_dev = nullptr;
     int* bad_dev = nullptr;
     int bad = 0;
     const size_t nrec = (size_t)g.n_sets * g.m_rows * smf::factor_stride(g.order);
@@ -133,7 +149,14 @@ int setup_impl(const smf_spectrum* spec, int n_theta, int n_phi, int flags, hipS
         if ((rc = bufs.alloc(&plan->f32, nrec))) goto fail;
         if (hipMemsetAsync(plan->f32, 0, nrec * sizeof(float), st) != hipSuccess) { rc = SMF_EHIP; goto fail; }
     }
-    if (smf::launch_factors(g, plan->C, plan->f64, plan->f32, st) != hipSuccess) { rc = SMF_EHIP; goto fail; }
+    if (z_host) {
+        if ((rc = bufs.alloc(&z_dev, (size_t)n_theta))) goto fail;
+        if (hipMemcpyAsync(z_dev, z_host, sizeof(double) * n_theta, hipMemcpyHostToDevice, st) != hipSuccess) {
+            rc = SMF_EHIP;
+            goto fail;
+        }
+    }
+    if (smf::launch_factors(g, plan->C, z_dev, plan->f64, plan->f32, st) != hipSuccess) { rc = SMF_EHIP; goto fail; }
     if ((rc = bufs.alloc(&plan->tw64, (size_t)2 * n_phi))) goto fail;
     if ((rc = bufs.alloc(&plan->tw32, (size_t)2 * n_phi))) goto fail;
     if (smf::launch_twiddles(n_phi, plan->tw64, plan->tw32, st) != hipSuccess) { rc = SMF_EHIP; goto fail; }
@@ -157,6 +180,7 @@ int setup_impl(const smf_spectrum* spec, int n_theta, int n_phi, int flags, hipS
     (void)hipFree(bad_dev);
     if (kappa_dev) (void)hipFree(kappa_dev);
     if (cexp_dev) (void)hipFree(cexp_dev);
+    if (z_dev) (void)hipFree(z_dev);
     *out = plan;
     return SMF_OK;
 
@@ -174,7 +198,14 @@ extern "C" {
 int smf_setup(const smf_spectrum* spec, int n_theta, int n_phi, int flags, void* hip_stream,
               smf_plan** out)
 {
-    return setup_impl(spec, n_theta, n_phi, flags, (hipStream_t)hip_stream, true, out);
+    return setup_impl(spec, n_theta, nullptr, n_phi, flags, (hipStream_t)hip_stream, true, out);
+}
+
+int smf_setup_grid(const smf_spectrum* spec, int n_theta, const double* z_host, int n_phi, int flags,
+                   void* hip_stream, smf_plan** out)
+{
+    if (!z_host) return SMF_EINVAL;
+    return setup_impl(spec, n_theta, z_host, n_phi, flags, (hipStream_t)hip_stream, true, out);
 }
 
 // Layout of a call's chains: ring blocks of the affine scan (1: plain recursion) and
@@ -217,8 +248,9 @@ static bool count_fits(const smf_plan* plan, int count)
     return (long long)count * plan->g.n_theta <= 0x7FFFFFFFLL;
 }
 
+// fft: transform the modes into the field; ln (with fft): the lognormal map on the store.
 static int sample_common(const smf_plan* plan, uint64_t seed, int count, void* out_dev,
-                         void* hip_stream, bool fft)
+                         void* hip_stream, bool fft, const smf::LognormalMap* ln = nullptr)
 {
     if (!plan || plan->batch || count < 0 || !count_fits(plan, count)) return SMF_EINVAL;
     if (count == 0) return SMF_OK;
@@ -238,7 +270,7 @@ static int sample_common(const smf_plan* plan, uint64_t seed, int count, void* o
     }
     if (fft) {
         const void* tw = fp64 ? (const void*)plan->tw64 : (const void*)plan->tw32;
-        if (smf::launch_c2r(plan->g, fp64, tw, count, out_dev, st) != hipSuccess) return SMF_EHIP;
+        if (smf::launch_c2r(plan->g, fp64, tw, count, out_dev, ln, st) != hipSuccess) return SMF_EHIP;
     }
     return SMF_OK;
 }
@@ -253,6 +285,14 @@ int smf_sample_modes(const smf_plan* plan, uint64_t seed, int count, void* g_dev
     return sample_common(plan, seed, count, g_dev, hip_stream, false);
 }
 
+int smf_sample_lognormal(const smf_plan* plan, uint64_t seed, int count, double mu, double sigma, void* out_dev,
+                         void* hip_stream)
+{
+    if (!std::isfinite(mu) || !std::isfinite(sigma)) return SMF_EINVAL;
+    const smf::LognormalMap ln = {mu, sigma};
+    return sample_common(plan, seed, count, out_dev, hip_stream, true, &ln);
+}
+
 int smf_transform(const smf_plan* plan, int count, void* data_dev, void* hip_stream)
 {
     if (!plan || plan->batch || count < 0 || !count_fits(plan, count)) return SMF_EINVAL;
@@ -261,8 +301,9 @@ int smf_transform(const smf_plan* plan, int count, void* data_dev, void* hip_str
     DeviceGuard dg(plan->device);
     const int fp64 = plan->flags == SMF_FP64;
     const void* tw = fp64 ? (const void*)plan->tw64 : (const void*)plan->tw32;
-    return smf::launch_c2r(plan->g, fp64, tw, count, data_dev, (hipStream_t)hip_stream) == hipSuccess ? SMF_OK
-                                                                                                      : SMF_EHIP;
+    return smf::launch_c2r(plan->g, fp64, tw, count, data_dev, nullptr, (hipStream_t)hip_stream) == hipSuccess
+               ? SMF_OK
+               : SMF_EHIP;
 }
 
 int smf_set_ring_blocks(smf_plan* plan, int blocks)
@@ -384,7 +425,7 @@ int smf_setup_batch(int n, const smf_spectrum* specs, const int* n_theta, const 
     int dev = 0;
     for (int i = 0; i < n; ++i) {
         smf_plan* p = nullptr;
-        rc = setup_impl(&specs[i], n_theta[i], n_phi[i], SMF_FP32, st, false, &p);
+        rc = setup_impl(&specs[i], n_theta[i], nullptr, n_phi[i], SMF_FP32, st, false, &p);
         if (rc != SMF_OK) goto fail;
         b->sub.push_back(p);
         b->offsets[i + 1] = b->offsets[i] + (int64_t)n_theta[i] * n_phi[i];

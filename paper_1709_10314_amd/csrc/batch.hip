@@ -20,7 +20,7 @@ constexpr int kFftThreads = 256;
 template <int LOG2H>
 __device__ __forceinline__ void fft_item(float* row, const float* tw, int m_top, Cx<float>* buf)
 {
-    c2r_row<float, LOG2H, kFftThreads>(row, tw, m_top, buf);
+    c2r_row<float, LOG2H, kFftThreads>(row, tw, m_top, buf, Epilogue<float>{0.0f, 0.0f, 0});
 }
 
 __device__ void dispatch_fft(int log2h, float* row, const float* tw, int m_top, Cx<float>* buf)

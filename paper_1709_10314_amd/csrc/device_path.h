@@ -601,12 +601,34 @@ __device__ __forceinline__ void c2r_prep(const Cx<T>* __restrict__ tw, const Cx<
     }
 }
 
+// Pointwise map applied as the transformed row is stored: none, or the lognormal field
+// exp(mu + sigma T) of a Gaussian field T (the application named at the end of Sec. 4).
+// `on` is uniform over the launch.
+template <typename T>
+struct Epilogue {
+    T mu, sigma;
+    int on;
+};
+
+__device__ __forceinline__ float exp_t(float x) { return expf(x); }
+__device__ __forceinline__ double exp_t(double x) { return exp(x); }
+
+template <typename T>
+__device__ __forceinline__ Cx<T> epilogue(const Epilogue<T>& ep, Cx<T> v)
+{
+    if (ep.on) {
+        v.re = exp_t(fma(ep.sigma, v.re, ep.mu));
+        v.im = exp_t(fma(ep.sigma, v.im, ep.mu));
+    }
+    return v;
+}
+
 // C2R of one ring row (2H reals, holding modes 0..H-1 as complex on entry), by NT threads
 // with an LDS buffer of lds_slots(H) complex values.  Ends with the row written; the caller must
 // barrier before reusing `buf`.
 template <typename T, int LOG2H, int NT>
 __device__ __forceinline__ void c2r_row(T* __restrict__ data_row, const T* __restrict__ twr, int m_top,
-                                        Cx<T>* buf)
+                                        Cx<T>* buf, const Epilogue<T>& ep)
 {
     using S = PrepShape<LOG2H, NT>;
     constexpr int H = 1 << LOG2H;
@@ -644,7 +666,7 @@ __device__ __forceinline__ void c2r_row(T* __restrict__ data_row, const T* __res
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int k = threadIdx.x + i * NT;
-        if (H % NT == 0 || k < H) row[k] = buf[lds_slot(k)];
+        if (H % NT == 0 || k < H) row[k] = epilogue(ep, buf[lds_slot(k)]);
     }
 }
 
@@ -654,13 +676,13 @@ __device__ __forceinline__ void c2r_row(T* __restrict__ data_row, const T* __res
 // LDS traffic only); without it each row is loaded when its turn comes (fewer registers).
 template <typename T, int LOG2H, int NT, bool PREFETCH>
 __device__ __forceinline__ void c2r_rows(T* __restrict__ data, const T* __restrict__ twr, int m_top,
-                                         Cx<T>* buf, int rows, int row0, int stride)
+                                         Cx<T>* buf, int rows, int row0, int stride, const Epilogue<T>& ep)
 {
     constexpr int H = 1 << LOG2H;
     constexpr int PER = (H + NT - 1) / NT;
     if constexpr (!PREFETCH) {
         for (int r = row0; r < rows; r += stride) {
-            c2r_row<T, LOG2H, NT>(data + (size_t)r * (2 * H), twr, m_top, buf);
+            c2r_row<T, LOG2H, NT>(data + (size_t)r * (2 * H), twr, m_top, buf, ep);
             __syncthreads();
         }
         return;
@@ -680,7 +702,7 @@ __device__ __forceinline__ void c2r_rows(T* __restrict__ data, const T* __restri
 #pragma unroll
             for (int i = 0; i < PER; ++i) {
                 const int k = threadIdx.x + i * NT;
-                if (H % NT == 0 || k < H) row[k] = buf[lds_slot(k)];
+                if (H % NT == 0 || k < H) row[k] = epilogue(ep, buf[lds_slot(k)]);
             }
             __syncthreads();
         }

@@ -233,18 +233,18 @@ struct FftWaves {
 // Each workgroup transforms rows blockIdx.x, blockIdx.x + gridDim.x, ...
 template <typename T, int LOG2H>
 __global__ __launch_bounds__((FftThreads<T, LOG2H>::value), (FftWaves<T, LOG2H>::value)) void c2r_kernel(
-    T* __restrict__ data, const T* __restrict__ twr, int m_top, int rows)
+    T* __restrict__ data, const T* __restrict__ twr, int m_top, int rows, Epilogue<T> ep)
 {
     extern __shared__ unsigned char smem_raw[];
     c2r_rows<T, LOG2H, FftThreads<T, LOG2H>::value, FftPrefetch<T, LOG2H>::value>(
-        data, twr, m_top, reinterpret_cast<Cx<T>*>(smem_raw), rows, blockIdx.x, gridDim.x);
+        data, twr, m_top, reinterpret_cast<Cx<T>*>(smem_raw), rows, blockIdx.x, gridDim.x, ep);
 }
 
 // Workgroups of the row-looping FFT: enough to fill every CU several times over.
 constexpr int kFftGrid = 2048;
 
 template <typename T, int LOG2H>
-hipError_t launch_c2r_t(const T* tw, int m_top, int rows, T* data, hipStream_t st)
+hipError_t launch_c2r_t(const T* tw, int m_top, int rows, T* data, const Epilogue<T>& ep, hipStream_t st)
 {
     const size_t lds = sizeof(Cx<T>) * lds_slots(1 << LOG2H);
     if (lds > 65536) {
@@ -254,27 +254,28 @@ hipError_t launch_c2r_t(const T* tw, int m_top, int rows, T* data, hipStream_t s
     }
     const int grid = rows < kFftGrid ? rows : kFftGrid;
     hipLaunchKernelGGL((c2r_kernel<T, LOG2H>), dim3(grid), dim3(FftThreads<T, LOG2H>::value), lds, st, data, tw,
-                       m_top, rows);
+                       m_top, rows, ep);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t dispatch_c2r(int log2h, const T* tw, int m_top, int rows, T* data, hipStream_t st)
+hipError_t dispatch_c2r(int log2h, const T* tw, int m_top, int rows, T* data, const Epilogue<T>& ep,
+                        hipStream_t st)
 {
     switch (log2h) {
-        case 1: return launch_c2r_t<T, 1>(tw, m_top, rows, data, st);
-        case 2: return launch_c2r_t<T, 2>(tw, m_top, rows, data, st);
-        case 3: return launch_c2r_t<T, 3>(tw, m_top, rows, data, st);
-        case 4: return launch_c2r_t<T, 4>(tw, m_top, rows, data, st);
-        case 5: return launch_c2r_t<T, 5>(tw, m_top, rows, data, st);
-        case 6: return launch_c2r_t<T, 6>(tw, m_top, rows, data, st);
-        case 7: return launch_c2r_t<T, 7>(tw, m_top, rows, data, st);
-        case 8: return launch_c2r_t<T, 8>(tw, m_top, rows, data, st);
-        case 9: return launch_c2r_t<T, 9>(tw, m_top, rows, data, st);
-        case 10: return launch_c2r_t<T, 10>(tw, m_top, rows, data, st);
-        case 11: return launch_c2r_t<T, 11>(tw, m_top, rows, data, st);
-        case 12: return launch_c2r_t<T, 12>(tw, m_top, rows, data, st);
-        case 13: return launch_c2r_t<T, 13>(tw, m_top, rows, data, st);
+        case 1: return launch_c2r_t<T, 1>(tw, m_top, rows, data, ep, st);
+        case 2: return launch_c2r_t<T, 2>(tw, m_top, rows, data, ep, st);
+        case 3: return launch_c2r_t<T, 3>(tw, m_top, rows, data, ep, st);
+        case 4: return launch_c2r_t<T, 4>(tw, m_top, rows, data, ep, st);
+        case 5: return launch_c2r_t<T, 5>(tw, m_top, rows, data, ep, st);
+        case 6: return launch_c2r_t<T, 6>(tw, m_top, rows, data, ep, st);
+        case 7: return launch_c2r_t<T, 7>(tw, m_top, rows, data, ep, st);
+        case 8: return launch_c2r_t<T, 8>(tw, m_top, rows, data, ep, st);
+        case 9: return launch_c2r_t<T, 9>(tw, m_top, rows, data, ep, st);
+        case 10: return launch_c2r_t<T, 10>(tw, m_top, rows, data, ep, st);
+        case 11: return launch_c2r_t<T, 11>(tw, m_top, rows, data, ep, st);
+        case 12: return launch_c2r_t<T, 12>(tw, m_top, rows, data, ep, st);
+        case 13: return launch_c2r_t<T, 13>(tw, m_top, rows, data, ep, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -364,13 +365,17 @@ hipError_t launch_scan(const Geometry& g, int fp64, const void* fac, const void*
 }
 
 hipError_t launch_c2r(const Geometry& g, int fp64, const void* tw, int count, void* data,
-                      hipStream_t st)
+                      const LognormalMap* ln, hipStream_t st)
 {
     const int log2h = __builtin_ctz((unsigned)g.n_phi) - 1;
     const int rows = count * g.n_theta;
     if (rows == 0) return hipSuccess;
-    if (fp64) return dispatch_c2r<double>(log2h, (const double*)tw, g.m_top, rows, (double*)data, st);
-    return dispatch_c2r<float>(log2h, (const float*)tw, g.m_top, rows, (float*)data, st);
+    if (fp64) {
+        const Epilogue<double> ep = {ln ? ln->mu : 0.0, ln ? ln->sigma : 0.0, ln ? 1 : 0};
+        return dispatch_c2r<double>(log2h, (const double*)tw, g.m_top, rows, (double*)data, ep, st);
+    }
+    const Epilogue<float> ep = {ln ? (float)ln->mu : 0.0f, ln ? (float)ln->sigma : 0.0f, ln ? 1 : 0};
+    return dispatch_c2r<float>(log2h, (const float*)tw, g.m_top, rows, (float*)data, ep, st);
 }
 
 }  // namespace smf

@@ -164,8 +164,11 @@ __device__ void start_m2(const double k[3], double B[3])
 // the l loop and its coefficients are uniform across the wave.  Each thread runs the
 // Legendre recurrence at its two rings a, b (Sec. 2 definition of L_lm), accumulates
 // J(a,a), J(b,b), J(b,a) (Lemma 2.1 and the cross covariances), and factorises.
+// zgrid: the ring values of an explicit grid (Alg. 1's grid argument), or null for the
+// ring centres.
 template <int M>
 __global__ __launch_bounds__(64) void factor_kernel(Geometry g, const double* __restrict__ C,
+                                                    const double* __restrict__ zgrid,
                                                     double* __restrict__ f64,
                                                     float* __restrict__ f32)
 {
@@ -186,8 +189,15 @@ __global__ __launch_bounds__(64) void factor_kernel(Geometry g, const double* __
     // exactly and mirrored rings get exactly opposite z
     LegendreStream ra, rb;
     double sa, sb;
-    sincospi((double)(g.n_theta - 2 * a - 1) / (2.0 * g.n_theta), &ra.z, &sa);
-    sincospi((double)(g.n_theta - 2 * b - 1) / (2.0 * g.n_theta), &rb.z, &sb);
+    if (zgrid) {
+        ra.z = zgrid[a];
+        rb.z = zgrid[b];
+        sa = sqrt((1.0 - ra.z) * (1.0 + ra.z));
+        sb = sqrt((1.0 - rb.z) * (1.0 + rb.z));
+    } else {
+        sincospi((double)(g.n_theta - 2 * a - 1) / (2.0 * g.n_theta), &ra.z, &sa);
+        sincospi((double)(g.n_theta - 2 * b - 1) / (2.0 * g.n_theta), &rb.z, &sb);
+    }
     ra.inv_s2 = 1.0 / (sa * sa);
     rb.inv_s2 = 1.0 / (sb * sb);
     // sectoral seed L_mm = sqrt((2m+1)/(4pi) prod_k (2k-1)/(2k)) sin^m, built as
@@ -334,14 +344,14 @@ hipError_t launch_spectrum(const double* kappa_dev, int n_kappa, const double* c
     return hipGetLastError();
 }
 
-hipError_t launch_factors(const Geometry& g, const double* C_dev, double* f64, float* f32,
-                          hipStream_t st)
+hipError_t launch_factors(const Geometry& g, const double* C_dev, const double* z_dev, double* f64,
+                          float* f32, hipStream_t st)
 {
     dim3 grid((g.n_sets + 63) / 64, g.m_top + 1);
     if (g.order == 1)
-        hipLaunchKernelGGL(factor_kernel<1>, grid, dim3(64), 0, st, g, C_dev, f64, f32);
+        hipLaunchKernelGGL(factor_kernel<1>, grid, dim3(64), 0, st, g, C_dev, z_dev, f64, f32);
     else
-        hipLaunchKernelGGL(factor_kernel<2>, grid, dim3(64), 0, st, g, C_dev, f64, f32);
+        hipLaunchKernelGGL(factor_kernel<2>, grid, dim3(64), 0, st, g, C_dev, z_dev, f64, f32);
     return hipGetLastError();
 }
 

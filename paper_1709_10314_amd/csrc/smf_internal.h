@@ -49,8 +49,9 @@ inline Geometry make_geometry(int order, int n_theta, int n_phi, int ell_max)
 // ---- setup (FP64) ----
 hipError_t launch_spectrum(const double* kappa_dev, int n_kappa, const double* c_explicit_dev,
                            int ell_max, double* C_dev, int* bad_dev, hipStream_t st);
-hipError_t launch_factors(const Geometry& g, const double* C_dev, double* f64, float* f32,
-                          hipStream_t st);
+// z_dev: ring values of an explicit grid (device, n_theta doubles) or null for ring centres.
+hipError_t launch_factors(const Geometry& g, const double* C_dev, const double* z_dev, double* f64,
+                          float* f32, hipStream_t st);
 hipError_t launch_twiddles(int n_phi, double* tw64, float* tw32, hipStream_t st);
 // Phi per (fine ring block, m) for the affine scan, layout [block][m][M*M], m stride m_rows.
 hipError_t launch_phi(const Geometry& g, const double* f64, int blocks, double* phi64, float* phi32,
@@ -79,8 +80,12 @@ inline int scan_fine_blocks(const Geometry& g)
 // nch: chains per lane, 1 (one part) or 2 (both parts of a mode; FP32 only).
 hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, uint64_t seed, int count,
                             void* out, int nch, hipStream_t st);
+// exp(mu + sigma T) applied by the FFT as it stores T (the sample type's precision).
+struct LognormalMap {
+    double mu, sigma;
+};
 hipError_t launch_c2r(const Geometry& g, int fp64, const void* tw, int count, void* data,
-                      hipStream_t st);
+                      const LognormalMap* ln, hipStream_t st);
 // The chains of launch_recursion as an affine scan over `blocks` ring blocks per chain
 // (blocks >= 2 dividing fine_blocks; phi holds the plan's fine-block transitions).
 hipError_t launch_scan(const Geometry& g, int fp64, const void* fac, const void* phi, int fine_blocks,

@@ -17,7 +17,7 @@ SMF_OK, SMF_EINVAL, SMF_ENOMEM, SMF_EHIP, SMF_ENUMERIC = 0, -1, -2, -3, -4
 SMF_FP64, SMF_FP32 = 1, 2
 
 # every symbol include/smf.h declares
-EXPORTS = ("smf_setup", "smf_sample", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks",
+EXPORTS = ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks",
            "smf_get_ring_blocks",
            "smf_plan_dims", "smf_get_factors",
            "smf_destroy", "smf_error_string", "smf_setup_batch", "smf_batch_layout",
@@ -55,7 +55,10 @@ def load():
     lib = ctypes.CDLL(LIB_PATH)
     vp, i, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64
     lib.smf_setup.argtypes = [ctypes.POINTER(smf_spectrum), i, i, i, vp, ctypes.POINTER(vp)]
+    lib.smf_setup_grid.argtypes = [ctypes.POINTER(smf_spectrum), i, ctypes.POINTER(ctypes.c_double), i, i, vp,
+                                   ctypes.POINTER(vp)]
     lib.smf_sample.argtypes = [vp, u64, i, vp, vp]
+    lib.smf_sample_lognormal.argtypes = [vp, u64, i, ctypes.c_double, ctypes.c_double, vp, vp]
     lib.smf_sample_modes.argtypes = [vp, u64, i, vp, vp]
     lib.smf_transform.argtypes = [vp, i, vp, vp]
     lib.smf_set_ring_blocks.argtypes = [vp, i]
@@ -70,7 +73,7 @@ def load():
     lib.smf_batch_layout.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     lib.smf_sample_batch.argtypes = [vp, u64, vp, vp]
     lib.smf_autotune_batch.argtypes = [vp, u64, vp, vp, ctypes.POINTER(ctypes.c_int)]
-    for name in ("smf_setup", "smf_sample", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks", "smf_get_ring_blocks",
+    for name in ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks", "smf_get_ring_blocks",
                  "smf_plan_dims",
                  "smf_get_factors", "smf_destroy", "smf_setup_batch", "smf_batch_layout",
                  "smf_sample_batch", "smf_autotune_batch"):
@@ -93,8 +96,10 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def smf_setup(order, n_theta, n_phi, ell_max, kappa=None, c_ell=None, flags=SMF_FP32, stream=None):
-    """Returns (code, plan handle).  kappa: factors of C_l (eq. (Cl)); c_ell: explicit C_l."""
+def smf_setup(order, n_theta, n_phi, ell_max, kappa=None, c_ell=None, flags=SMF_FP32, stream=None, z=None):
+    """Returns (code, plan handle).  kappa: factors of C_l (eq. (Cl)); c_ell: explicit C_l;
+    z: explicit ring values (north to south, symmetric; smf_setup_grid), default the ring
+    centres (smf_setup)."""
     lib = load()
     spec = smf_spectrum()
     spec.order = int(order)
@@ -111,14 +116,27 @@ def smf_setup(order, n_theta, n_phi, ell_max, kappa=None, c_ell=None, flags=SMF_
         spec.n_kappa = len(k)
         spec.kappa = k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if len(k) else None
     plan = ctypes.c_void_p()
-    rc = lib.smf_setup(ctypes.byref(spec), int(n_theta), int(n_phi), int(flags),
-                       _stream_handle(stream), ctypes.byref(plan))
+    if z is None:
+        rc = lib.smf_setup(ctypes.byref(spec), int(n_theta), int(n_phi), int(flags),
+                           _stream_handle(stream), ctypes.byref(plan))
+    else:
+        zz = np.ascontiguousarray(z, dtype=np.float64).reshape(-1)
+        if len(zz) != int(n_theta):
+            return SMF_EINVAL, plan
+        keep.append(zz)
+        rc = lib.smf_setup_grid(ctypes.byref(spec), int(n_theta), zz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                int(n_phi), int(flags), _stream_handle(stream), ctypes.byref(plan))
     return rc, plan
 
 
 def smf_sample(plan, seed, count, out_ptr, stream=None):
     return load().smf_sample(plan, ctypes.c_uint64(int(seed)), int(count), ctypes.c_void_p(out_ptr),
                              _stream_handle(stream))
+
+
+def smf_sample_lognormal(plan, seed, count, mu, sigma, out_ptr, stream=None):
+    return load().smf_sample_lognormal(plan, ctypes.c_uint64(int(seed)), int(count), float(mu), float(sigma),
+                                       ctypes.c_void_p(out_ptr), _stream_handle(stream))
 
 
 def smf_sample_modes(plan, seed, count, g_ptr, stream=None):
@@ -267,12 +285,12 @@ class Plan:
     """A setup plan (Alg. 1 factors on the GPU) with sampling methods (Alg. 2)."""
 
     def __init__(self, order, n_theta, n_phi, ell_max, kappa=None, c_ell=None, precision="fp32",
-                 stream=None):
+                 stream=None, z=None):
         flags = {"fp32": SMF_FP32, "fp64": SMF_FP64}[precision]
         rc, h = smf_setup(order, n_theta, n_phi, ell_max, kappa=kappa, c_ell=c_ell, flags=flags,
-                          stream=stream)
+                          stream=stream, z=z)
         if rc != SMF_OK:
-            raise SmfError(rc, "smf_setup")
+            raise SmfError(rc, "smf_setup" if z is None else "smf_setup_grid")
         self._h = h
         rc, d = smf_plan_dims(h)
         (self.order, self.n_theta, self.n_phi, self.ell_max, self.m_top, self.n_sets,
@@ -301,6 +319,16 @@ class Plan:
         rc = smf_sample(self._h, seed, count, out.data_ptr(), stream)
         if rc != SMF_OK:
             raise SmfError(rc, "smf_sample")
+        return out
+
+    def sample_lognormal(self, seed, count, mu=0.0, sigma=1.0, out=None, stream=None):
+        """exp(mu + sigma T) of the fields sample(seed, count) would return."""
+        if out is None:
+            out = self.empty(count)
+        self._check_out(out, count)
+        rc = smf_sample_lognormal(self._h, seed, count, mu, sigma, out.data_ptr(), stream)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_sample_lognormal")
         return out
 
     def transform(self, data, count, stream=None):

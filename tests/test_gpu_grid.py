@@ -1,0 +1,143 @@
+"""GPU parity on explicit ring grids (Alg. 1 takes the grid z as an input; symmetric grids
+store the northern half, the remark after Alg. 1): Gauss-Legendre nodes, HEALPix ring
+latitudes and random symmetric grids, even and odd ring counts, both orders.  Factors
+against the oracle's explicit-grid setup (by their action on the chain's law, as for the
+ring-centre grid), modes and fields against the oracle on the same Philox normals (FP64
+1e-10, FP32 1e-4 relative RMS per field, plain recursion and affine scan), the ring-centre
+grid given as values against smf_setup, and the grid checks of smf_setup_grid."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import factor_errors, log, rel_rms
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-4}
+
+
+def _grid(name):
+    from paper_1709_10314_amd import workloads as w
+
+    kind, n = name.rsplit("-", 1)
+    n = int(n)
+    if kind == "gl":
+        return w.gauss_legendre_z(n)
+    if kind == "healpix":
+        return w.healpix_ring_z(n)
+    return w.random_z(n, seed=n)
+
+
+# (grid, order, kappa_i, n_phi, ell_max).  Order-2 cases keep m_top near n_theta / 2 or
+# below: modes far above that are evanescent at the polar rings, where many pivots sit next
+# to the factorisation threshold on either side (the ring-centre grid behaves the same).
+CASES = [
+    ("gl-64", 1, 400.0, 128, 63),
+    ("gl-65", 2, 900.0, 64, 64),
+    ("healpix-16", 1, 100.0, 128, 63),
+    ("healpix-16", 2, 2500.0, 64, 70),
+    ("healpix-32", 2, 900.0, 128, 127),
+    ("random-100", 1, 50.0, 256, 99),
+    ("random-37", 1, 9.0, 64, 20),
+    ("gl-256", 2, 2500.0, 128, 255),
+]
+
+
+def _plan(z, order, kap, nphi, lmax, precision):
+    from paper_1709_10314_amd import Plan
+
+    return Plan(order, len(z), nphi, lmax, kappa=[kap] * order, precision=precision, z=z)
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "%s-M%d-k%g-%d-l%d" % c)
+def test_grid_factors_match_oracle(case):
+    name, order, kap, nphi, lmax = case
+    z = _grid(name)
+    n = len(z)
+    log(f"grid factors {case}")
+    plan = _plan(z, order, kap, nphi, lmax, "fp64")
+    Ag, Bg = plan.factors()
+    plan.close()
+    C = oracle.spectrum([kap] * order, lmax)
+    Ao, Bo = oracle.setup(order, C, n, nphi, z=z)
+    dA, dB, amb = factor_errors(Ag, Bg, Ao, Bo, n)
+    log(f"  max dA {dA:.3e}  max dB {dB:.3e}  ({amb} steps next to a threshold)")
+    assert dA < 1e-8 and dB < 1e-9
+    assert amb <= max(2, 0.02 * Ao.shape[0] * Ao.shape[1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "%s-M%d-k%g-%d-l%d" % c)
+def test_grid_modes_and_field_match_oracle(case, precision):
+    name, order, kap, nphi, lmax = case
+    z = _grid(name)
+    n = len(z)
+    count, seed = 2, 29
+    C = oracle.spectrum([kap] * order, lmax)
+    A, B = oracle.setup(order, C, n, nphi, z=z)
+    To, go = oracle.sample(order, n, nphi, A, B, seed, count)
+    plan = _plan(z, order, kap, nphi, lmax, precision)
+    mt = plan.m_top
+    for blocks in (1, 4):
+        plan.set_ring_blocks(blocks)
+        used = plan.ring_blocks(count)
+        g = plan.sample_modes(seed, count)
+        torch.cuda.synchronize()
+        g = g.double().cpu().numpy()
+        g = g[..., 0] + 1j * g[..., 1]
+        T = plan.sample(seed, count)
+        torch.cuda.synchronize()
+        T = T.double().cpu().numpy()
+        for f in range(count):
+            eg = rel_rms(np.stack([g[f, :, : mt + 1].real, g[f, :, : mt + 1].imag]),
+                         np.stack([go[f].real, go[f].imag]))
+            eT = rel_rms(T[f], To[f])
+            log(f"{case} {precision} blocks {used}: field {f} modes {eg:.3e} field {eT:.3e}")
+            assert eg <= TOL[precision] and eT <= TOL[precision]
+    plan.close()
+
+
+@pytest.mark.parametrize("n", [64, 65])
+def test_ring_centre_grid_as_values_matches_default(n):
+    """The ring centres passed as values give the fields of smf_setup (the two setups differ
+    only in how sin(theta) is rounded)."""
+    from paper_1709_10314_amd import Plan
+
+    z = oracle.grid(n)[1]
+    a = Plan(2, n, 128, 63, kappa=[400.0, 400.0], precision="fp64")
+    b = Plan(2, n, 128, 63, kappa=[400.0, 400.0], precision="fp64", z=z)
+    Ta = a.sample(3, 2).clone()
+    Tb = b.sample(3, 2)
+    torch.cuda.synchronize()
+    e = max(rel_rms(Tb[f].cpu().numpy(), Ta[f].cpu().numpy()) for f in range(2))
+    log(f"ring centres as values, n {n}: rel RMS {e:.2e}")
+    assert e <= 1e-10
+    a.close()
+    b.close()
+
+
+def test_setup_grid_rejects_bad_grids():
+    from paper_1709_10314_amd import smf
+
+    z = oracle.grid(8)[1]
+    bad = {
+        "ascending": z[::-1].copy(),
+        "asymmetric": np.where(np.arange(8) == 7, -z[0] * 0.999, z),
+        "touches the poles": np.linspace(1.0, -1.0, 8),
+        "not monotone": np.r_[z[:4], -z[:4]],
+        "nan": np.where(np.arange(8) == 2, np.nan, z),
+    }
+    for what, zb in bad.items():
+        rc, _ = smf.smf_setup(1, 8, 16, 7, kappa=[30.0], flags=smf.SMF_FP64, z=zb)
+        assert rc == smf.SMF_EINVAL, what
+    rc, _ = smf.smf_setup(1, 8, 16, 7, kappa=[30.0], flags=smf.SMF_FP64, z=z[:7])
+    assert rc == smf.SMF_EINVAL
+    lib = smf.load()
+    spec = smf.smf_spectrum()
+    spec.order, spec.ell_max, spec.n_kappa = 1, 7, 0
+    c = np.ones(8)
+    spec.c_ell = c.ctypes.data_as(smf.ctypes.POINTER(smf.ctypes.c_double))
+    h = smf.ctypes.c_void_p()
+    assert lib.smf_setup_grid(smf.ctypes.byref(spec), 8, None, 16, smf.SMF_FP64, None,
+                              smf.ctypes.byref(h)) == smf.SMF_EINVAL

@@ -60,6 +60,7 @@ def _load():
     lib.orc_spectrum.restype = _i
     lib.orc_legendre.argtypes = [_i, _i, _d, _pd, _pd]
     lib.orc_jblock.argtypes = [_i, _i, _i, _pd, _d, _d, _pd]
+    lib.orc_legendre_derivs.argtypes = [_i, _i, _d, _d, _i, ctypes.POINTER(_pd)]
     lib.orc_jblock_zs.argtypes = [_i, _i, _i, _pd, _d, _d, _d, _d, _pd]
     lib.orc_ring_zs.argtypes = [_i, _i, _pd, _pd]
     lib.orc_setup.argtypes = [_i, _i, _pd, _i, _i, _i, _pd, _pd]
@@ -123,6 +124,19 @@ def legendre(m, ell_max, theta):
     if n:
         _load().orc_legendre(m, ell_max, float(theta), _p(L), _p(dL))
     return L, dL
+
+
+def legendre_derivs(m, ell_max, z, nd):
+    """d^k L_lm / dz^k at z for k < nd (nd <= 4) and l = m..ell_max, as an [nd, n] array
+    (k >= 2 from the associated Legendre equation)."""
+    n = max(ell_max - m + 1, 0)
+    F = np.zeros((4, max(n, 1)))
+    if n:
+        s = math.sqrt((1.0 - z) * (1.0 + z))
+        ptrs = (ctypes.POINTER(ctypes.c_double) * 4)(*[F[k].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+                                                        for k in range(4)])
+        _load().orc_legendre_derivs(m, ell_max, float(z), s, nd, ptrs)
+    return F[:nd, :n]
 
 
 def jblock(order, m, ell_max, C, theta1, theta2):

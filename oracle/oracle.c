@@ -10,7 +10,8 @@
  * against the paper by eye:
  *   - grid and spectrum                         (Sec. 2, eq. (Cl); Sec. 4 grid)
  *   - fully normalised associated Legendre L_lm and dL_lm/dz by the forward
- *     recurrence in l, seeded with an extended-exponent sectoral value
+ *     recurrence in l, seeded with an extended-exponent sectoral value; second
+ *     and third z-derivatives from the associated Legendre equation
  *                                               (Sec. 2, definition of L_lm)
  *   - cross-covariance blocks J^m_pq(z1,z2) as brute-force sums over l
  *                                               (Lemma 2.1, cross covariances)
@@ -52,7 +53,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORC_MAXM 2            /* state dimension supported: value and first z-derivative */
+#define ORC_MAXM 4            /* state dimension supported: value and z-derivatives up to the third */
 #define ORC_TINY 1e-290       /* a block diagonal below this is treated as exactly zero */
 #define ORC_TAU 1e-12         /* pivot / relative-variance threshold after equilibration */
 
@@ -187,6 +188,32 @@ void orc_legendre(int m, int ell_max, double theta, double* L, double* dL)
 }
 
 /* ------------------------------------------------------------------------- */
+/* Higher z-derivatives from the associated Legendre equation, which L_lm       */
+/* solves for every l (primes are z-derivatives):                              */
+/*   (1 - z^2) L2 = 2 z L1 - (l(l+1) - m^2/(1 - z^2)) L0,                      */
+/* and its derivative                                                          */
+/*   (1 - z^2) L3 = 4 z L2 + 2 L1 - (l(l+1) - m^2/(1 - z^2)) L1                */
+/*                  + 2 m^2 z / (1 - z^2)^2 L0,                                */
+/* with Lk = d^k L_lm / dz^k.  F[k][l-m] = Lk for k < nd (nd <= 4),            */
+/* l = m .. ell_max; each F[k] holds ell_max - m + 1 values.                   */
+/* ------------------------------------------------------------------------- */
+void orc_legendre_derivs(int m, int ell_max, double z, double s, int nd, double* const* F)
+{
+    const int n = ell_max - m + 1;
+    if (n <= 0 || nd <= 0) return;
+    orc_legendre_zs(m, ell_max, z, s, F[0], nd > 1 ? F[1] : NULL);
+    const double s2 = s * s;
+    const double mm = (double)m * m;
+    for (int k = 0; k < n && nd > 2; ++k) {
+        const double l = m + k;
+        const double c = l * (l + 1.0) - mm / s2;
+        F[2][k] = (2.0 * z * F[1][k] - c * F[0][k]) / s2;
+        if (nd > 3)
+            F[3][k] = (4.0 * z * F[2][k] + 2.0 * F[1][k] - c * F[1][k] + 2.0 * mm * z / (s2 * s2) * F[0][k]) / s2;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
 /* Cross-covariance block (Lemma 2.1 and the cross covariances of Sec. 2):     */
 /*   J_pq = sum_{l=m}^{ell_max} C_l  d^p L_lm(z1)  d^q L_lm(z2),  p,q < M,     */
 /* with z1 = cos(theta1), z2 = cos(theta2).  J[p*M + q].                       */
@@ -197,21 +224,25 @@ void orc_jblock_zs(int order, int m, int ell_max, const double* C, double z1, do
     int n = ell_max - m + 1;
     for (int i = 0; i < order * order; ++i) J[i] = 0.0;
     if (n <= 0) return;
-    double* L1 = (double*)malloc(sizeof(double) * 4 * n);
-    double* D1 = L1 + n;
-    double* L2 = L1 + 2 * n;
-    double* D2 = L1 + 3 * n;
-    orc_legendre_zs(m, ell_max, z1, s1, L1, D1);
-    orc_legendre_zs(m, ell_max, z2, s2, L2, D2);
+    double* buf = (double*)malloc(sizeof(double) * 2 * ORC_MAXM * n);
+    double* F1[ORC_MAXM];
+    double* F2[ORC_MAXM];
+    for (int k = 0; k < ORC_MAXM; ++k) {
+        F1[k] = buf + (size_t)k * n;
+        F2[k] = buf + (size_t)(ORC_MAXM + k) * n;
+    }
+    int nd = order < 2 ? 2 : order;
+    orc_legendre_derivs(m, ell_max, z1, s1, nd, F1);
+    orc_legendre_derivs(m, ell_max, z2, s2, nd, F2);
     for (int p = 0; p < order; ++p)
         for (int q = 0; q < order; ++q) {
-            const double* f1 = p ? D1 : L1;
-            const double* f2 = q ? D2 : L2;
+            const double* f1 = F1[p];
+            const double* f2 = F2[q];
             double acc = 0.0;
             for (int k = 0; k < n; ++k) acc += C[m + k] * f1[k] * f2[k];
             J[p * order + q] = acc;
         }
-    free(L1);
+    free(buf);
 }
 
 /* The same with z1 = cos(theta1), z2 = cos(theta2). */

@@ -134,6 +134,42 @@ def test_jblock_derivatives_finite_difference(orc, m):
     assert abs(J[1, 1] - d12) < 1e-4 * abs(J[1, 1]) + 1e-6 * sc
 
 
+@pytest.mark.parametrize("m", [0, 2, 7, 30])
+@pytest.mark.parametrize("z", [-0.8, -0.1, 0.3, 0.9])
+def test_legendre_higher_derivatives_finite_difference(orc, m, z):
+    """Second and third z-derivatives (from the associated Legendre equation) against
+    central differences of the next lower derivative, l = m..m+25."""
+    lmax, h = m + 25, 1e-5
+    F = orc.legendre_derivs(m, lmax, z, 4)
+    Fp = orc.legendre_derivs(m, lmax, z + h, 4)
+    Fm = orc.legendre_derivs(m, lmax, z - h, 4)
+    for k in (1, 2):
+        fd = (Fp[k] - Fm[k]) / (2 * h)
+        scale = np.max(np.abs(F[k + 1])) + 1e-300
+        assert np.max(np.abs(fd - F[k + 1])) < 1e-6 * scale, (k + 1, m, z)
+
+
+@pytest.mark.parametrize("m", [0, 3, 11])
+def test_jblock_order4_derivatives_finite_difference(orc, m):
+    """J^m_pq of order 4 are the mixed z-derivatives of J_00: J_{p+1,q} = d/dz1 J_pq and
+    J_{p,q+1} = d/dz2 J_pq, by central differences."""
+    lmax = 40
+    C = orc.spectrum([30.0] * 4, lmax)
+    z1, z2, h = 0.31, -0.47, 1e-5
+    J = orc.jblock_z(4, m, lmax, C, z1, z2)
+    J1p, J1m = orc.jblock_z(4, m, lmax, C, z1 + h, z2), orc.jblock_z(4, m, lmax, C, z1 - h, z2)
+    J2p, J2m = orc.jblock_z(4, m, lmax, C, z1, z2 + h), orc.jblock_z(4, m, lmax, C, z1, z2 - h)
+    d1 = (J1p - J1m) / (2 * h)
+    d2 = (J2p - J2m) / (2 * h)
+    for p in range(4):
+        for q in range(4):
+            sc = math.sqrt(abs(orc.jblock_z(4, m, lmax, C, z1, z1)[p, p]) * abs(orc.jblock_z(4, m, lmax, C, z2, z2)[q, q]))
+            if p < 3:
+                assert abs(d1[p, q] - J[p + 1, q]) < 1e-6 * sc * (1 + m), (p, q)
+            if q < 3:
+                assert abs(d2[p, q] - J[p, q + 1]) < 1e-6 * sc * (1 + m), (p, q)
+
+
 def test_spectrum_rejects_nonpositive(orc):
     with pytest.raises(ValueError):
         orc.spectrum([0.0], 5)          # C_0 = 1/0
@@ -213,6 +249,21 @@ def _propagate_check(orc, order, kappa, n, lmax, n_phi, z=None):
 ])
 def test_factors_reproduce_ring_covariances(orc, order, kappa, n, lmax, n_phi):
     assert _propagate_check(orc, order, kappa, n, lmax, n_phi) < 1e-11
+
+
+@pytest.mark.parametrize("order,kappa,n,lmax,n_phi", [
+    (3, 30.0, 16, 15, 32),
+    (3, 400.0, 33, 40, 82),
+    (4, 100.0, 16, 15, 32),
+    (4, 900.0, 21, 30, 62),
+    (3, 2500.0, 64, 63, 128),
+])
+def test_factors_reproduce_ring_covariances_high_order(orc, order, kappa, n, lmax, n_phi):
+    """Orders 3 and 4: the same propagation check.  The value and its first M-1
+    derivatives are strongly correlated, so more pivots fall under the 1e-12 threshold;
+    dropping one costs up to sqrt(1e-12) = 1e-6 of a correlation per step, which bounds
+    the reproduction at 1e-4 over a walk."""
+    assert _propagate_check(orc, order, kappa, n, lmax, n_phi) < 1e-4
 
 
 def test_factors_lower_triangular_positive(orc):
@@ -446,7 +497,9 @@ def _chain_variance(orc, order, A, B, n):
     return var
 
 
-@pytest.mark.parametrize("order,kappa,n,lmax", [(1, 64.0, 16, 15), (2, 50.0, 11, 10), (1, 5.0, 10, 40)])
+@pytest.mark.parametrize("order,kappa,n,lmax", [(1, 64.0, 16, 15), (2, 50.0, 11, 10), (1, 5.0, 10, 40),
+                                                (3, 50.0, 11, 10), (4, 50.0, 12, 14), (3, 9.0, 16, 40),
+                                                (4, 200.0, 17, 30)])
 def test_chain_variance_closed_form(orc, order, kappa, n, lmax):
     """Var T(z_i, phi) = sum_l (2l+1) C_l / (4 pi) at every ring, from exact covariance
     propagation through the factors in both hemispheres (no m truncation: n_phi large)."""
@@ -525,12 +578,14 @@ def test_sample_reproducible_and_field_keyed(orc):
 
 
 @pytest.mark.slow
-def test_empirical_covariance_matches_addition_theorem(orc):
+@pytest.mark.parametrize("order", [1, 3])
+def test_empirical_covariance_matches_addition_theorem(orc, order):
     """Sec. 5's validation on a tiny grid: the covariance of N = 10^5 oracle samples
     against C_T(x,y) = sum_l (2l+1)/(4 pi) C_l P_l(<x,y>), within 5 standard errors
     (Isserlis: Var(x y) = C_xx C_yy + C_xy^2) plus the chain's deterministic Markov defect
-    for pairs two or more rings apart (computed from the factors by propagation)."""
-    order, kappa, n, lmax = 1, 20.0, 8, 63
+    for pairs two or more rings apart (computed from the factors by propagation).  Order 3
+    exercises the normals' counter map when a ring's three normals straddle two blocks."""
+    kappa, n, lmax = 20.0, 8, 63
     n_phi = 2 * (lmax + 1)
     C = orc.spectrum([kappa] * order, lmax)
     A, B = orc.setup(order, C, n, n_phi)

@@ -13,8 +13,9 @@
  *    device buffers (factors, spectrum, twiddles) and frees them in smf_destroy().
  *  - Streams are hipStream_t passed as void* (NULL = the null stream).  Sampling calls
  *    are asynchronous on that stream; setup synchronises its stream before returning.
- *  - A plan is immutable after setup; the sampling calls only read it, so one plan may be
- *    used from several streams at once (each call needs its own output buffer).
+ *  - The sampling calls only read a plan, so one plan may be used from several streams at
+ *    once (each call needs its own output buffer); the calls that change a plan
+ *    (smf_set_ring_blocks, smf_set_factors, smf_autotune_batch) must not overlap them.
  *
  * Grid: n_theta iso-latitude rings at ring centres theta_i = pi (i + 1/2) / n_theta
  * (ring 0 nearest the north pole, z_i = cos theta_i) and n_phi equispaced longitudes
@@ -35,8 +36,8 @@ typedef struct smf_plan smf_plan;
 /* Angular power spectrum, eq. (Cl): C_l = prod_{i<n_kappa} (kappa_i + l(l+1))^-1 for
  * l = 0..ell_max, and C_l = 0 above ell_max.  If c_ell is non-NULL it is used instead
  * (ell_max + 1 values, host memory).  `order` is the Markov order M, i.e. the state
- * dimension (value and first M-1 z-derivatives, Sec. 2 Markov property); M in {1, 2}.
- * For the rational form M is normally n_kappa. */
+ * dimension (value and first M-1 z-derivatives, Sec. 2 Markov property); M in {1, 2, 3, 4}
+ * (the batched form takes 1 and 2).  For the rational form M is normally n_kappa. */
 typedef struct {
     int order;
     int n_kappa;
@@ -68,7 +69,10 @@ enum {
  *   n_theta   >= 2 rings.     n_phi  power of two in [4, 16384].
  *   flags     exactly one of SMF_FP64, SMF_FP32.
  *   out       receives the new plan (host pointer to a pointer).
- * Errors: SMF_EINVAL (shapes, order not in {1,2}, ell_max < 0, n_kappa < 0, NULL
+ * Orders 3 and 4 take the second and third z-derivatives of L_lm from the associated
+ * Legendre equation; their records hold A row-major and B's lower triangle (16 and 32
+ * values per record with padding).
+ * Errors: SMF_EINVAL (shapes, order not in 1..4, ell_max < 0, n_kappa < 0, NULL
  * pointers, flags), SMF_ENUMERIC (a C_l not finite and > 0), SMF_ENOMEM, SMF_EHIP. */
 int smf_setup(const smf_spectrum* spec, int n_theta, int n_phi, int flags, void* hip_stream,
               smf_plan** out);
@@ -133,6 +137,7 @@ int smf_transform(const smf_plan* plan, int count, void* data_dev, void* hip_str
  *           2, 4, 8 or 16: always, with that many blocks, capped at the plan's maximum (the
  *              largest power of two <= 16 leaving >= 8 ring steps per block, 1 when the
  *              walk has fewer than 16 steps) and at 8 for SMF_FP64 plans.
+ * Plans of order 3 or 4 always run the plain recursion (their maximum is 1).
  * The plan stores one transition per (fine block, m): 16 * (n_phi/2) * M*M values in FP64
  * (and FP32 for SMF_FP32 plans).
  * Errors: SMF_EINVAL (NULL, batch plan, blocks not 0, 1 or a power of two <= 16). */
@@ -155,9 +160,17 @@ int smf_plan_dims(const smf_plan* plan, int* dims);
  * Synchronous.  Errors: SMF_EINVAL on NULL, SMF_EHIP. */
 int smf_get_factors(const smf_plan* plan, double* A_host, double* B_host);
 
+/* Alg. 2 takes the factors (A, B, B_eq) as its input: replaces the plan's factors with
+ * caller-given FP64 ones in the layout of smf_get_factors (set 0: A ignored, B = B_eq; the
+ * upper triangle of each B is ignored), e.g. factors from another setup, then rounds the
+ * FP32 copy (SMF_FP32 plans) and rebuilds the scan's block transitions.  Synchronous on
+ * hip_stream; must not overlap sampling calls on the plan.
+ * Errors: SMF_EINVAL (NULL, batch plan, a value that is not finite), SMF_EHIP. */
+int smf_set_factors(smf_plan* plan, const double* A_host, const double* B_host, void* hip_stream);
+
 /* ---- batched form: many fields of uneven shape, spectrum and order per call ---- */
 
-/* One FP32 plan per field (Alg. 1 for each, as smf_setup with SMF_FP32) plus flat work
+/* One FP32 plan per field (Alg. 1 for each, as smf_setup with SMF_FP32; orders 1 and 2) plus flat work
  * lists: chain items (field, group of m-tiles), longest chains first, and one FFT item
  * per ring of every field.  specs, n_theta, n_phi: host arrays of n entries (n in
  * [1, 65535]); n_phi[i] a power of two in [4, 4096]; flags must be SMF_FP32.

@@ -89,7 +89,7 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
 {
     if (!spec || !out) return SMF_EINVAL;
     *out = nullptr;
-    if (spec->order < 1 || spec->order > 2) return SMF_EINVAL;
+    if (spec->order < 1 || spec->order > 4) return SMF_EINVAL;
     if (spec->ell_max < 0 || spec->ell_max > (1 << 20)) return SMF_EINVAL;
     if (!spec->c_ell && (spec->n_kappa < 0 || spec->n_kappa > 64 || (spec->n_kappa > 0 && !spec->kappa)))
         return SMF_EINVAL;
@@ -160,7 +160,8 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
     if ((rc = bufs.alloc(&plan->tw64, (size_t)2 * n_phi))) goto fail;
     if ((rc = bufs.alloc(&plan->tw32, (size_t)2 * n_phi))) goto fail;
     if (smf::launch_twiddles(n_phi, plan->tw64, plan->tw32, st) != hipSuccess) { rc = SMF_EHIP; goto fail; }
-    plan->scan_fine = scan ? smf::scan_fine_blocks(g) : 1;
+    // the affine scan serves orders 1 and 2 (the chain kernels of orders 3 and 4 run plain)
+    plan->scan_fine = (scan && g.order <= 2) ? smf::scan_fine_blocks(g) : 1;
     if (plan->scan_fine > 1) {
         const size_t nphi = (size_t)plan->scan_fine * g.m_rows * g.order * g.order;
         if ((rc = bufs.alloc(&plan->phi64, nphi))) goto fail;
@@ -225,7 +226,7 @@ static CallShape call_shape(const smf_plan* plan, int count)
     const int cap = std::min(plan->scan_fine, smf::scan_max_blocks(fp64));
     const long w = (long)count * 2 * ((plan->g.m_rows + 31) / 32);
     const int walk = plan->g.n_sets - (plan->g.even ? 2 : 1);
-    const int plain_nch = (!fp64 && w >= 2048) ? 2 : 1;
+    const int plain_nch = (!fp64 && plan->g.order <= 2 && w >= 2048) ? 2 : 1;
     const int scan_nch = (!fp64 && w >= 512) ? 2 : 1;
     if (cap < 2 || plan->scan_req == 1) return {1, plain_nch};
     if (plan->scan_req >= 2) return {std::min(plan->scan_req, cap), scan_nch};
@@ -357,13 +358,64 @@ int smf_get_factors(const smf_plan* plan, double* A_host, double* B_host)
             if (M == 1) {
                 A[0] = r[0];
                 B[0] = r[1];
-            } else {
+            } else if (M == 2) {
                 A[0] = r[0]; A[1] = r[1]; A[2] = r[2]; A[3] = r[3];
                 B[0] = r[4]; B[1] = 0.0; B[2] = r[5]; B[3] = r[6];
+            } else {
+                // A row-major, then B's lower triangle by rows
+                for (int i = 0; i < M * M; ++i) A[i] = r[i];
+                int k = M * M;
+                for (int p = 0; p < M; ++p)
+                    for (int q = 0; q < M; ++q) B[p * M + q] = q <= p ? r[k++] : 0.0;
             }
         }
     free(tmp);
     return SMF_OK;
+}
+
+int smf_set_factors(smf_plan* plan, const double* A_host, const double* B_host, void* hip_stream)
+{
+    if (!plan || plan->batch || !A_host || !B_host) return SMF_EINVAL;
+    DeviceGuard dg(plan->device);
+    const Geometry& g = plan->g;
+    const int M = g.order, E = smf::factor_stride(M);
+    const size_t per = (size_t)(g.m_top + 1) * M * M;
+    for (size_t i = 0; i < (size_t)g.n_sets * per; ++i)
+        if (!std::isfinite(A_host[i]) || !std::isfinite(B_host[i])) return SMF_EINVAL;
+    const size_t nrec = (size_t)g.n_sets * g.m_rows * E;
+    std::vector<double> r64(nrec, 0.0);
+    std::vector<float> r32;
+    for (int j = 0; j < g.n_sets; ++j)
+        for (int m = 0; m <= g.m_top; ++m) {
+            double* r = r64.data() + ((size_t)j * g.m_rows + m) * E;
+            const double* A = A_host + ((size_t)j * (g.m_top + 1) + m) * M * M;
+            const double* B = B_host + ((size_t)j * (g.m_top + 1) + m) * M * M;
+            if (M == 1) {
+                r[0] = A[0];
+                r[1] = B[0];
+            } else if (M == 2) {
+                r[0] = A[0]; r[1] = A[1]; r[2] = A[2]; r[3] = A[3];
+                r[4] = B[0]; r[5] = B[2]; r[6] = B[3];
+            } else {
+                int k = M * M;
+                for (int i = 0; i < M * M; ++i) r[i] = A[i];
+                for (int p = 0; p < M; ++p)
+                    for (int q = 0; q <= p; ++q) r[k++] = B[p * M + q];
+            }
+        }
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (hipMemcpyAsync(plan->f64, r64.data(), nrec * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess)
+        return SMF_EHIP;
+    if (plan->f32) {
+        r32.resize(nrec);
+        for (size_t i = 0; i < nrec; ++i) r32[i] = (float)r64[i];
+        if (hipMemcpyAsync(plan->f32, r32.data(), nrec * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess)
+            return SMF_EHIP;
+    }
+    if (plan->scan_fine > 1 &&
+        smf::launch_phi(g, plan->f64, plan->scan_fine, plan->phi64, plan->phi32, st) != hipSuccess)
+        return SMF_EHIP;
+    return hipStreamSynchronize(st) == hipSuccess ? SMF_OK : SMF_EHIP;
 }
 
 int smf_destroy(smf_plan* plan)
@@ -412,7 +464,7 @@ int smf_setup_batch(int n, const smf_spectrum* specs, const int* n_theta, const 
     *out = nullptr;
     if (n < 1 || n > 65535 || !specs || !n_theta || !n_phi || flags != SMF_FP32) return SMF_EINVAL;
     for (int i = 0; i < n; ++i)
-        if (n_phi[i] > 4096 || n_theta[i] > 65535) return SMF_EINVAL;
+        if (n_phi[i] > 4096 || n_theta[i] > 65535 || specs[i].order > 2) return SMF_EINVAL;
     hipStream_t st = (hipStream_t)hip_stream;
     smf::BatchState* b = new smf::BatchState();
     b->n = n;

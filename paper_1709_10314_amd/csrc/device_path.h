@@ -5,6 +5,8 @@
 //                 or both parts per lane, with fused Philox normals (Creasey & Lang,
 //                 Alg. 2; eqs. (state_initial), (state_space); the mirror remark after
 //                 Alg. 1); the affine scan walks ring blocks with the same pieces
+//   run_chain_gen
+//              -- the same recursion for Markov orders 3 and 4, one part per lane
 //   c2r_row, c2r_rows
 //              -- the complex-to-real inverse FFT of one ring / of many rings per
 //                 workgroup, in place (Alg. 2, last step)
@@ -397,6 +399,173 @@ __device__ __forceinline__ void zero_chain(int n, int s, int h, T* __restrict__ 
 #pragma unroll
     for (int c = 0; c < NCH; ++c) z[c] = T(0);
     for (int r = r_lo; r < r_hi; ++r) store_ring<T, NCH>(g, (size_t)r * row, z);
+}
+
+// ------------------------------------------------------------------ orders 3 and 4
+// The same recursion for a state of M = 3 or 4 components (value and z-derivatives up to
+// M-1), one chain per lane.  Ring r uses the normals r M + q, q < M, of the counter map
+// (block (r M + q) / 4, word (r M + q) mod 4), so G rings whose G M normals fill NB whole
+// Philox blocks form a group: M = 3 -> 4 rings in 3 blocks, M = 4 -> 1 ring in 1 block.
+// Groups are aligned to multiples of G in the ring index; a walk starts and ends with cut
+// groups whose rings outside the walk are skipped.
+template <int M>
+struct GenGroup {
+    static constexpr int G = M % 4 == 0 ? 1 : (M % 2 == 0 ? 2 : 4);
+    static constexpr int NB = G * M / 4;
+};
+
+// A factor record (A row-major, B's lower triangle by rows, b_index) loaded as 16-byte
+// chunks: V values cover the M*M + M(M+1)/2 used ones.
+template <typename T, int M>
+struct RecGen {
+    static constexpr int USED = M * M + M * (M + 1) / 2;
+    static constexpr int CH = (USED * (int)sizeof(T) + 15) / 16;
+    static constexpr int V = CH * 16 / (int)sizeof(T);
+    T v[V];
+};
+
+template <typename T, int M>
+__device__ __forceinline__ RecGen<T, M> load_rec_gen(const T* __restrict__ rec)
+{
+    RecGen<T, M> R;
+    const uint4* __restrict__ p = reinterpret_cast<const uint4*>(rec);
+#pragma unroll
+    for (int c = 0; c < RecGen<T, M>::CH; ++c) *reinterpret_cast<uint4*>(&R.v[c * 16 / sizeof(T)]) = p[c];
+    return R;
+}
+
+// x <- A x + B w, each component accumulated by explicit fma in a fixed order.
+template <typename T, int M>
+__device__ __forceinline__ void chain_step_gen(const RecGen<T, M>& R, T (&x)[M], const T (&w)[M])
+{
+    T y[M];
+#pragma unroll
+    for (int p = 0; p < M; ++p) {
+        T acc = R.v[b_index<M>(p, p)] * w[p];
+#pragma unroll
+        for (int q = p - 1; q >= 0; --q) acc = fma(R.v[b_index<M>(p, q)], w[q], acc);
+#pragma unroll
+        for (int q = M - 1; q >= 0; --q) acc = fma(R.v[p * M + q], x[q], acc);
+        y[p] = acc;
+    }
+#pragma unroll
+    for (int p = 0; p < M; ++p) x[p] = y[p];
+}
+
+// The 4 NB normals of the group starting at ring `base`, scaled by sc.
+template <typename T, int M>
+__device__ __forceinline__ void group_normals(int base, uint32_t um, uint32_t up, uint32_t k0, uint32_t k1, T sc,
+                                              T (&nb)[4 * GenGroup<M>::NB])
+{
+    constexpr int NB = GenGroup<M>::NB;
+    uint32_t blk[NB], prt[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        blk[k] = (uint32_t)((base * M) >> 2) + (uint32_t)k;
+        prt[k] = up;
+    }
+    PhiloxBlock wb[NB];
+    philox4x32_10_n<NB>(blk, um, prt, k0, k1, wb);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        BoxMuller<T>::pair(wb[k].w[0], wb[k].w[1], sc, nb[4 * k], nb[4 * k + 1]);
+        BoxMuller<T>::pair(wb[k].w[2], wb[k].w[3], sc, nb[4 * k + 2], nb[4 * k + 3]);
+    }
+}
+
+// The M normals of ring base + t from its group's normals (t uniform, not a constant:
+// selected, not indexed), the odd ones negated south of the start (D w).
+template <typename T, int M, bool NORTH>
+__device__ __forceinline__ void ring_normals(const T (&nb)[4 * GenGroup<M>::NB], int t, T (&w)[M])
+{
+#pragma unroll
+    for (int q = 0; q < M; ++q) w[q] = T(0);
+#pragma unroll
+    for (int u = 0; u < GenGroup<M>::G; ++u)
+        if (u == t) {
+#pragma unroll
+            for (int q = 0; q < M; ++q) w[q] = (!NORTH && (q & 1)) ? -nb[u * M + q] : nb[u * M + q];
+        }
+}
+
+// Rings [lo, hi] of the group at `base`, in walk order.  The group's records are loaded
+// before its Philox rounds, so their latency overlaps the rounds.
+template <typename T, int M, bool NORTH>
+__device__ __forceinline__ void step_group_gen(int base, int lo, int hi, int s, int even, int n_sets, uint32_t um,
+                                               uint32_t up, uint32_t k0, uint32_t k1, T sc,
+                                               const T* __restrict__ fm, size_t set_stride, T* __restrict__ g,
+                                               size_t row, T (&x)[M])
+{
+    constexpr int G = GenGroup<M>::G;
+    RecGen<T, M> R[G];
+#pragma unroll
+    for (int t = 0; t < G; ++t)
+        R[t] = load_rec_gen<T, M>(fm + (size_t)set_of_ring<T, M, NORTH>(base + t, s, even, n_sets) * set_stride);
+    T nb[4 * GenGroup<M>::NB];
+    group_normals<T, M>(base, um, up, k0, k1, sc, nb);
+#pragma unroll
+    for (int tt = 0; tt < G; ++tt) {
+        const int t = NORTH ? G - 1 - tt : tt;
+        const int r = base + t;
+        if (r >= lo && r <= hi) {
+            T w[M];
+#pragma unroll
+            for (int q = 0; q < M; ++q) w[q] = (!NORTH && (q & 1)) ? -nb[t * M + q] : nb[t * M + q];
+            chain_step_gen<T, M>(R[t], x, w);
+            g[(size_t)r * row] = x[0];
+        }
+    }
+}
+
+// One chain of order M >= 3 (one part; layout and hemisphere roles as run_chain): the
+// start draw at ring s, for the south the crossing step (even n_theta) and the switch to
+// y = D x, then the walk to ring 0 or n-1.
+template <typename T, int M>
+__device__ __forceinline__ void run_chain_gen(int n, int s, int even, int n_sets, int h, int m, int part, uint32_t k0,
+                                              uint32_t k1, const T* __restrict__ fm, size_t set_stride,
+                                              T* __restrict__ g, size_t row)
+{
+    constexpr int G = GenGroup<M>::G;
+    const uint32_t um = (uint32_t)m, up = (uint32_t)part;
+    const T sc = m == 0 ? T(1) : T(0.70710678118654752440);
+    T x[M];
+#pragma unroll
+    for (int p = 0; p < M; ++p) x[p] = T(0);
+    {
+        // start, eq. (state_initial): x = B_eq w with set 0 (A = 0)
+        const int bs = (s / G) * G;
+        T nb[4 * GenGroup<M>::NB], w[M];
+        group_normals<T, M>(bs, um, up, k0, k1, sc, nb);
+        ring_normals<T, M, true>(nb, s - bs, w);
+        chain_step_gen<T, M>(load_rec_gen<T, M>(fm), x, w);
+        if (h == 0) g[(size_t)s * row] = x[0];
+    }
+    if (h == 1 && even) {
+        // crossing s -> s+1 with set 1, in the true coordinates
+        const int r = s + 1;
+        const int br = (r / G) * G;
+        T nb[4 * GenGroup<M>::NB], w[M];
+        group_normals<T, M>(br, um, up, k0, k1, sc, nb);
+        ring_normals<T, M, true>(nb, r - br, w);
+        chain_step_gen<T, M>(load_rec_gen<T, M>(fm + set_stride), x, w);
+        g[(size_t)r * row] = x[0];
+    }
+    if (h == 0) {
+        for (int top = s - 1; top >= 0;) {
+            const int base = (top / G) * G;
+            step_group_gen<T, M, true>(base, base, top, s, even, n_sets, um, up, k0, k1, sc, fm, set_stride, g, row, x);
+            top = base - 1;
+        }
+    } else {
+#pragma unroll
+        for (int p = 1; p < M; p += 2) x[p] = -x[p];   // y = D x
+        for (int lo = even ? s + 2 : s + 1; lo <= n - 1;) {
+            const int base = (lo / G) * G;
+            const int hi = base + G - 1 < n - 1 ? base + G - 1 : n - 1;
+            step_group_gen<T, M, false>(base, lo, hi, s, even, n_sets, um, up, k0, k1, sc, fm, set_stride, g, row, x);
+            lo = base + G;
+        }
+    }
 }
 
 // ------------------------------------------------------------------ C2R FFT

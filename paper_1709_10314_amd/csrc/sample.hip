@@ -54,6 +54,36 @@ __global__ __launch_bounds__(256) void recursion_kernel(RecArgs a, const T* __re
                          (size_t)a.n_phi);
 }
 
+// Markov orders 3 and 4: one lane per (field, hemisphere, mode, part), laid out as the
+// one-part recursion above (32 modes x 2 parts per wave, four (f, h) families per
+// workgroup, m-tiles kept on one XCD).
+template <typename T, int M>
+__global__ __launch_bounds__(256) void recursion_gen_kernel(RecArgs a, const T* __restrict__ fac,
+                                                            T* __restrict__ out)
+{
+    const int b = blockIdx.x;
+    const int L = (b & 7) * a.per_xcd + (b >> 3);
+    if (L >= a.n_wg) return;
+    const int mt = L / a.n_fg;
+    const int fg = L - mt * a.n_fg;
+    const int fh = __builtin_amdgcn_readfirstlane(fg * 4 + (int)(threadIdx.x >> 6));
+    if (fh >= a.n_fh) return;
+    const int f = fh >> 1, h = fh & 1;
+    const int lane = threadIdx.x & 63;
+    const int m = mt * 32 + (lane >> 1);
+    const int part = lane & 1;
+    if (m >= a.m_rows) return;
+    T* __restrict__ g = out + (size_t)f * a.n_theta * a.n_phi + 2 * m + part;
+    if (m > a.m_top || (m == 0 && part == 1)) {
+        zero_chain<T, 1>(a.n_theta, a.s, h, g, (size_t)a.n_phi);
+        return;
+    }
+    const uint64_t key = (((uint64_t)a.seed_hi << 32) | a.seed_lo) + (uint64_t)f;
+    run_chain_gen<T, M>(a.n_theta, a.s, a.even, a.n_sets, h, m, part, (uint32_t)key, (uint32_t)(key >> 32),
+                        fac + (size_t)m * factor_stride(M), (size_t)a.m_rows * factor_stride(M), g,
+                        (size_t)a.n_phi);
+}
+
 // ------------------------------------------------------------------ affine scan
 // The recursion x_{k+1} = A_k x_k + B_k w_k (eq. (state_space)) is affine in x, so a chain
 // cut into ring blocks can run its blocks in parallel: block b started from zero gives c_b
@@ -285,7 +315,7 @@ hipError_t dispatch_c2r(int log2h, const T* tw, int m_top, int rows, T* data, co
 hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, uint64_t seed, int count,
                             void* out, int nch, hipStream_t st)
 {
-    if (nch != 1 && (nch != 2 || fp64)) return hipErrorInvalidValue;
+    if (nch != 1 && (nch != 2 || fp64 || g.order > 2)) return hipErrorInvalidValue;
     RecArgs a;
     a.n_theta = g.n_theta;
     a.n_phi = g.n_phi;
@@ -303,7 +333,23 @@ hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, uint64
     a.seed_lo = (uint32_t)seed;
     a.seed_hi = (uint32_t)(seed >> 32);
     const dim3 grid((unsigned)(a.per_xcd * 8));
-    if (fp64) {
+    if (g.order >= 3) {
+        if (fp64) {
+            if (g.order == 3)
+                hipLaunchKernelGGL((recursion_gen_kernel<double, 3>), grid, dim3(256), 0, st, a, (const double*)fac,
+                                   (double*)out);
+            else
+                hipLaunchKernelGGL((recursion_gen_kernel<double, 4>), grid, dim3(256), 0, st, a, (const double*)fac,
+                                   (double*)out);
+        } else {
+            if (g.order == 3)
+                hipLaunchKernelGGL((recursion_gen_kernel<float, 3>), grid, dim3(256), 0, st, a, (const float*)fac,
+                                   (float*)out);
+            else
+                hipLaunchKernelGGL((recursion_gen_kernel<float, 4>), grid, dim3(256), 0, st, a, (const float*)fac,
+                                   (float*)out);
+        }
+    } else if (fp64) {
         if (g.order == 1)
             hipLaunchKernelGGL((recursion_kernel<double, 1, 1>), grid, dim3(256), 0, st, a,
                                (const double*)fac, (double*)out);
@@ -333,7 +379,7 @@ hipError_t launch_scan(const Geometry& g, int fp64, const void* fac, const void*
 {
     if (blocks < 2 || blocks > scan_max_blocks(fp64) || (blocks & (blocks - 1)) || fine_blocks % blocks)
         return hipErrorInvalidValue;
-    if (nch != 1 && (nch != 2 || fp64)) return hipErrorInvalidValue;
+    if (nch != 1 && (nch != 2 || fp64 || g.order > 2)) return hipErrorInvalidValue;
     ScanArgs a;
     a.n_theta = g.n_theta;
     a.n_phi = g.n_phi;

@@ -159,6 +159,125 @@ __device__ void start_m2(const double k[3], double B[3])
     B[2] = s1 * g11;
 }
 
+// ---------------------------------------------------------------- orders 3 and 4
+// Thresholded lower Cholesky of an equilibrated symmetric M x M matrix (row-major): a pivot
+// not above kTau is dropped, its column of G stays zero.
+template <int M>
+__device__ inline void chol_gen(const double (&X)[M * M], double (&G)[M * M], bool (&kept)[M])
+{
+#pragma unroll
+    for (int i = 0; i < M * M; ++i) G[i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        double d = X[j * M + j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) d -= G[j * M + k] * G[j * M + k];
+        kept[j] = d > kTau;
+        const double gjj = kept[j] ? sqrt(d) : 0.0;
+        G[j * M + j] = gjj;
+#pragma unroll
+        for (int i = j + 1; i < M; ++i) {
+            double v = X[i * M + j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) v -= G[i * M + k] * G[j * M + k];
+            G[i * M + j] = kept[j] ? v / gjj : 0.0;
+        }
+    }
+}
+
+// One step a -> b for M >= 3, the same algebra as factors_m2 on M x M blocks: equilibrate,
+// J(a,a) = G G^T on the kept pivots, Y = J(b,a) G^-T (forward substitution per row),
+// A = Y G^-1 (back substitution), S = J(b,b) - Y Y^T, B = chol(S) after S's own
+// equilibration, both equilibrations undone.  Kaa, Kbb, Kba full row-major.
+template <int M>
+__device__ void factors_gen(const double (&Kaa)[M * M], const double (&Kbb)[M * M], const double (&Kba)[M * M],
+                            double (&A)[M * M], double (&B)[M * M])
+{
+    double da[M], db[M];
+#pragma unroll
+    for (int p = 0; p < M; ++p) {
+        da[p] = eq_weight(Kaa[p * M + p]);
+        db[p] = eq_weight(Kbb[p * M + p]);
+    }
+    double R[M * M], S[M * M], Cba[M * M];
+#pragma unroll
+    for (int p = 0; p < M; ++p)
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            R[p * M + q] = da[p] * Kaa[p * M + q] * da[q];
+            S[p * M + q] = db[p] * Kbb[p * M + q] * db[q];
+            Cba[p * M + q] = db[p] * Kba[p * M + q] * da[q];
+        }
+    double G[M * M];
+    bool kept[M];
+    chol_gen<M>(R, G, kept);
+    double Y[M * M], At[M * M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            double v = Cba[i * M + j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) v -= G[j * M + k] * Y[i * M + k];
+            Y[i * M + j] = kept[j] ? v / G[j * M + j] : 0.0;
+        }
+#pragma unroll
+        for (int j = M - 1; j >= 0; --j) {
+            double v = Y[i * M + j];
+#pragma unroll
+            for (int k = j + 1; k < M; ++k) v -= G[k * M + j] * At[i * M + k];
+            At[i * M + j] = kept[j] ? v / G[j * M + j] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < M; ++p)
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            double v = S[p * M + q];
+#pragma unroll
+            for (int k = 0; k < M; ++k) v -= Y[p * M + k] * Y[q * M + k];
+            S[p * M + q] = v;
+        }
+    double e[M];
+#pragma unroll
+    for (int p = 0; p < M; ++p) e[p] = S[p * M + p] > kTau ? 1.0 / sqrt(S[p * M + p]) : 0.0;
+    double Q[M * M], H[M * M];
+#pragma unroll
+    for (int p = 0; p < M; ++p)
+#pragma unroll
+        for (int q = 0; q < M; ++q) Q[p * M + q] = e[p] * S[p * M + q] * e[q];
+    bool kept2[M];
+    chol_gen<M>(Q, H, kept2);
+#pragma unroll
+    for (int p = 0; p < M; ++p) {
+        const double sb = db[p] > 0.0 ? sqrt(Kbb[p * M + p]) : 0.0;
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            A[p * M + q] = sb * At[p * M + q] * da[q];
+            B[p * M + q] = e[p] > 0.0 ? sb * H[p * M + q] / e[p] : 0.0;
+        }
+    }
+}
+
+// Start factor for M >= 3: B_eq = chol(J(s,s)) through the equilibrated thresholded Cholesky.
+template <int M>
+__device__ void start_gen(const double (&K)[M * M], double (&B)[M * M])
+{
+    double d[M], R[M * M], G[M * M];
+    bool kept[M];
+#pragma unroll
+    for (int p = 0; p < M; ++p) d[p] = eq_weight(K[p * M + p]);
+#pragma unroll
+    for (int p = 0; p < M; ++p)
+#pragma unroll
+        for (int q = 0; q < M; ++q) R[p * M + q] = d[p] * K[p * M + q] * d[q];
+    chol_gen<M>(R, G, kept);
+#pragma unroll
+    for (int p = 0; p < M; ++p)
+#pragma unroll
+        for (int q = 0; q < M; ++q) B[p * M + q] = d[p] > 0.0 ? sqrt(K[p * M + p]) * G[p * M + q] : 0.0;
+}
+
 // ---------------------------------------------------------------- factor kernel
 // One thread per (set j, mode m); a 64-lane block holds consecutive sets of one mode, so
 // the l loop and its coefficients are uniform across the wave.  Each thread runs the
@@ -215,6 +334,8 @@ __global__ __launch_bounds__(64) void factor_kernel(Geometry g, const double* __
     rb.p0 = 0.0; rb.p1 = pb; rb.e = eb;
 
     double Kaa[3] = {0, 0, 0}, Kbb[3] = {0, 0, 0}, Kba[4] = {0, 0, 0, 0};
+    // M >= 3: full blocks (only the upper triangles of J(a,a), J(b,b) are accumulated)
+    double KaaG[M * M] = {}, KbbG[M * M] = {}, KbaG[M * M] = {};
     const double dm = (double)m;
     double inv_a_prev = 0.0;   // 1 / a_{l-1,m}
     for (int l = m; l <= g.ell_max; ++l) {
@@ -242,10 +363,42 @@ __global__ __launch_bounds__(64) void factor_kernel(Geometry g, const double* __
         if (rb.e < 0 && fabs(rb.p1) > kUp) { rb.p0 *= kDown; rb.p1 *= kDown; rb.e += 400; }
         const double cl = C[l];
         const double va = ra.value(), vb = rb.value();
-        if (M == 1) {
+        if constexpr (M == 1) {
             Kaa[0] = fma(cl * va, va, Kaa[0]);
             Kbb[0] = fma(cl * vb, vb, Kbb[0]);
             Kba[0] = fma(cl * vb, va, Kba[0]);
+        } else if constexpr (M >= 3) {
+            // value and z-derivatives up to M-1: the first as for M = 2, the higher ones
+            // from the associated Legendre equation,
+            //   (1 - z^2) L2 = 2 z L1 - c L0,
+            //   (1 - z^2) L3 = 4 z L2 + 2 L1 - c L1 + 2 m^2 z / (1 - z^2)^2 L0,
+            // c = l(l+1) - m^2 / (1 - z^2), Lk = d^k L_lm / dz^k
+            double Fa[M], Fb[M];
+            Fa[0] = va;
+            Fb[0] = vb;
+            Fa[1] = ldexp((c_der * ra.p0 - dl * ra.z * ra.p1) * ra.inv_s2, ra.e);
+            Fb[1] = ldexp((c_der * rb.p0 - dl * rb.z * rb.p1) * rb.inv_s2, rb.e);
+            const double ll = dl * (dl + 1.0), mm = dm * dm;
+            const double ca = ll - mm * ra.inv_s2, cb = ll - mm * rb.inv_s2;
+            Fa[2] = (2.0 * ra.z * Fa[1] - ca * Fa[0]) * ra.inv_s2;
+            Fb[2] = (2.0 * rb.z * Fb[1] - cb * Fb[0]) * rb.inv_s2;
+            if constexpr (M >= 4) {
+                Fa[3] = (4.0 * ra.z * Fa[2] + 2.0 * Fa[1] - ca * Fa[1] + 2.0 * mm * ra.z * ra.inv_s2 * ra.inv_s2 * Fa[0]) *
+                        ra.inv_s2;
+                Fb[3] = (4.0 * rb.z * Fb[2] + 2.0 * Fb[1] - cb * Fb[1] + 2.0 * mm * rb.z * rb.inv_s2 * rb.inv_s2 * Fb[0]) *
+                        rb.inv_s2;
+            }
+#pragma unroll
+            for (int p = 0; p < M; ++p) {
+                const double cfa = cl * Fa[p], cfb = cl * Fb[p];
+#pragma unroll
+                for (int q = p; q < M; ++q) {
+                    KaaG[p * M + q] = fma(cfa, Fa[q], KaaG[p * M + q]);
+                    KbbG[p * M + q] = fma(cfb, Fb[q], KbbG[p * M + q]);
+                }
+#pragma unroll
+                for (int q = 0; q < M; ++q) KbaG[p * M + q] = fma(cfb, Fa[q], KbaG[p * M + q]);
+            }
         } else {
             // (1 - z^2) dL_l/dz = -l z L_l + c_der L_{l-1}
             const double da = ldexp((c_der * ra.p0 - dl * ra.z * ra.p1) * ra.inv_s2, ra.e);
@@ -265,7 +418,34 @@ __global__ __launch_bounds__(64) void factor_kernel(Geometry g, const double* __
     }
 
     const size_t base = ((size_t)j * g.m_rows + m) * factor_stride(M);
-    if (M == 1) {
+    if constexpr (M >= 3) {
+#pragma unroll
+        for (int p = 0; p < M; ++p)
+#pragma unroll
+            for (int q = 0; q < p; ++q) {
+                KaaG[p * M + q] = KaaG[q * M + p];
+                KbbG[p * M + q] = KbbG[q * M + p];
+            }
+        double A[M * M] = {}, B[M * M];
+        if (j == 0) start_gen<M>(KaaG, B);
+        else factors_gen<M>(KaaG, KbbG, KbaG, A, B);
+        constexpr int E = factor_stride(M);
+        double v[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = 0.0;
+#pragma unroll
+        for (int i = 0; i < M * M; ++i) v[i] = A[i];
+#pragma unroll
+        for (int p = 0; p < M; ++p)
+#pragma unroll
+            for (int q = 0; q <= p; ++q) v[b_index<M>(p, q)] = B[p * M + q];
+#pragma unroll
+        for (int i = 0; i < E; ++i) f64[base + i] = v[i];
+        if (f32) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) f32[base + i] = (float)v[i];
+        }
+    } else if constexpr (M == 1) {
         double A, B;
         if (j == 0) { A = 0.0; B = start_m1(Kaa[0]); }
         else factors_m1(Kaa[0], Kbb[0], Kba[0], A, B);
@@ -348,10 +528,13 @@ hipError_t launch_factors(const Geometry& g, const double* C_dev, const double* 
                           float* f32, hipStream_t st)
 {
     dim3 grid((g.n_sets + 63) / 64, g.m_top + 1);
-    if (g.order == 1)
-        hipLaunchKernelGGL(factor_kernel<1>, grid, dim3(64), 0, st, g, C_dev, z_dev, f64, f32);
-    else
-        hipLaunchKernelGGL(factor_kernel<2>, grid, dim3(64), 0, st, g, C_dev, z_dev, f64, f32);
+    switch (g.order) {
+        case 1: hipLaunchKernelGGL(factor_kernel<1>, grid, dim3(64), 0, st, g, C_dev, z_dev, f64, f32); break;
+        case 2: hipLaunchKernelGGL(factor_kernel<2>, grid, dim3(64), 0, st, g, C_dev, z_dev, f64, f32); break;
+        case 3: hipLaunchKernelGGL(factor_kernel<3>, grid, dim3(64), 0, st, g, C_dev, z_dev, f64, f32); break;
+        case 4: hipLaunchKernelGGL(factor_kernel<4>, grid, dim3(64), 0, st, g, C_dev, z_dev, f64, f32); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

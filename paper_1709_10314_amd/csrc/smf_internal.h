@@ -15,9 +15,17 @@ namespace smf {
 constexpr double kTiny = 1e-290;
 constexpr double kTau = 1e-12;
 
-// Factor record per (set j, mode m): M = 1 -> {A00, B00};
-// M = 2 -> {A00, A01, A10, A11, B00, B10, B11, 0}.  Stored [set][m][E], m stride n_phi/2.
-__host__ __device__ constexpr int factor_stride(int order) { return order == 1 ? 2 : 8; }
+// Factor record per (set j, mode m), stored [set][m][E] with m stride n_phi/2:
+// M = 1 -> {A00, B00}; M = 2 -> {A00, A01, A10, A11, B00, B10, B11, 0};
+// M = 3, 4 -> A row-major, then B's lower triangle by rows, zero-padded to E = 16, 32.
+__host__ __device__ constexpr int factor_stride(int order)
+{
+    return order == 1 ? 2 : (order == 2 ? 8 : (order == 3 ? 16 : 32));
+}
+
+// Position of B_pq (q <= p) in an M >= 3 record.
+template <int M>
+__host__ __device__ constexpr int b_index(int p, int q) { return M * M + p * (p + 1) / 2 + q; }
 
 struct Geometry {
     int order;       // Markov order M

@@ -19,7 +19,7 @@ SMF_FP64, SMF_FP32 = 1, 2
 # every symbol include/smf.h declares
 EXPORTS = ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks",
            "smf_get_ring_blocks",
-           "smf_plan_dims", "smf_get_factors",
+           "smf_plan_dims", "smf_get_factors", "smf_set_factors",
            "smf_destroy", "smf_error_string", "smf_setup_batch", "smf_batch_layout",
            "smf_sample_batch", "smf_autotune_batch")
 
@@ -65,6 +65,7 @@ def load():
     lib.smf_get_ring_blocks.argtypes = [vp, i, ctypes.POINTER(ctypes.c_int)]
     lib.smf_plan_dims.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     lib.smf_get_factors.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.smf_set_factors.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), vp]
     lib.smf_destroy.argtypes = [vp]
     lib.smf_error_string.argtypes = [i]
     lib.smf_error_string.restype = ctypes.c_char_p
@@ -75,7 +76,7 @@ def load():
     lib.smf_autotune_batch.argtypes = [vp, u64, vp, vp, ctypes.POINTER(ctypes.c_int)]
     for name in ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks", "smf_get_ring_blocks",
                  "smf_plan_dims",
-                 "smf_get_factors", "smf_destroy", "smf_setup_batch", "smf_batch_layout",
+                 "smf_get_factors", "smf_set_factors", "smf_destroy", "smf_setup_batch", "smf_batch_layout",
                  "smf_sample_batch", "smf_autotune_batch"):
         getattr(lib, name).restype = i
     _lib = lib
@@ -167,6 +168,13 @@ def smf_plan_dims(plan):
 def smf_get_factors(plan, A, B):
     pd = ctypes.POINTER(ctypes.c_double)
     return load().smf_get_factors(plan, A.ctypes.data_as(pd), B.ctypes.data_as(pd))
+
+
+def smf_set_factors(plan, A, B, stream=None):
+    pd = ctypes.POINTER(ctypes.c_double)
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    return load().smf_set_factors(plan, A.ctypes.data_as(pd), B.ctypes.data_as(pd), _stream_handle(stream))
 
 
 def smf_destroy(plan):
@@ -372,6 +380,15 @@ class Plan:
         if rc != SMF_OK:
             raise SmfError(rc, "smf_get_factors")
         return A, B
+
+    def set_factors(self, A, B, stream=None):
+        """Replace the plan's factors with (A, B) of the factors() layout (Alg. 2's inputs)."""
+        shape = (self.n_sets, self.m_top + 1, self.order, self.order)
+        if np.shape(A) != shape or np.shape(B) != shape:
+            raise ValueError(f"factors must have shape {shape}")
+        rc = smf_set_factors(self._h, A, B, stream)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_set_factors")
 
     def _check_out(self, out, count):
         if not out.is_cuda or out.dtype != self.dtype() or not out.is_contiguous():

@@ -43,7 +43,8 @@ def _sqrtm_psd(S):
 
 def threshold_ambiguous(Ao, Bo, n_theta, lo=1e-14, hi=1e-10):
     """Steps whose factorisation sits near the 1e-12 thresholds, from the oracle's chain:
-    the smaller pivot 1 - rho^2 of the equilibrated J(a,a) (order 2) or a relative
+    the smaller pivot 1 - rho^2 of the equilibrated J(a,a) (order 2; every pivot for orders 3
+    and 4) or a relative
     conditional variance diag(B B^T) / diag J(b,b) within [lo, hi].  There keeping or
     dropping a pivot changes the conditional law discontinuously, and two FP64 roundings
     of J may fall on different sides.  Returns a [sets, modes] bool mask."""
@@ -55,6 +56,22 @@ def threshold_ambiguous(Ao, Bo, n_theta, lo=1e-14, hi=1e-10):
             d = Sa[..., 0, 0] * Sa[..., 1, 1]
             piv = np.where(d > 0, 1 - Sa[..., 0, 1] ** 2 / d, 1.0)
             amb |= (piv >= lo) & (piv <= hi)
+        elif M > 2:
+            # every pivot of the thresholded Cholesky of the equilibrated J(a,a)
+            dg = np.sqrt(np.clip(np.einsum("...pp->...p", Sa), 0, None))
+            inv = np.where(dg > 0, 1.0 / np.where(dg > 0, dg, 1.0), 0.0)
+            R = Sa * inv[..., :, None] * inv[..., None, :]
+            L = np.zeros_like(R)
+            for j in range(M):
+                piv = R[..., j, j] - np.sum(L[..., j, :j] ** 2, axis=-1)
+                if j > 0:
+                    amb |= (piv >= lo) & (piv <= hi)
+                keep = piv > 1e-12
+                g = np.sqrt(np.where(keep, piv, 1.0))
+                for i in range(j + 1, M):
+                    v = R[..., i, j] - np.sum(L[..., i, :j] * L[..., j, :j], axis=-1)
+                    L[..., i, j] = np.where(keep, v / g, 0.0)
+                L[..., j, j] = np.where(keep, g, 0.0)
         S = np.einsum("...pk,...pk->...p", Bo, Bo)
         Kd = np.einsum("...pp->...p", Sb)
         rel = np.where(Kd > 0, S / Kd, 1.0)

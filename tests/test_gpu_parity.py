@@ -219,7 +219,7 @@ def test_constant_field_lmax_zero():
 def test_error_codes():
     from paper_1709_10314_amd import smf
 
-    for args in [(3, 8, 16, 5), (1, 1, 16, 5), (1, 8, 12, 5), (1, 8, 2, 5), (1, 8, 32768, 5),
+    for args in [(5, 8, 16, 5), (0, 8, 16, 5), (1, 1, 16, 5), (1, 8, 12, 5), (1, 8, 2, 5), (1, 8, 32768, 5),
                  (1, 8, 16, -1)]:
         rc, h = smf.smf_setup(*args, kappa=[4.0], flags=smf.SMF_FP64)
         assert rc == smf.SMF_EINVAL, args
@@ -285,3 +285,41 @@ def test_empirical_covariance_of_gpu_samples():
         ref = np.vectorize(lambda c: _addition_target(C, c))(cosg)
         tol = 5 * np.sqrt((var * var + ref ** 2) / N) + defect[a][:, None]
         assert np.all(np.abs(emp - ref) <= tol), (a, np.max(np.abs(emp - ref) / tol))
+
+
+@pytest.mark.parametrize("case", [(1, 400.0, 33, 64, 40), (2, 700.0, 130, 256, 200)],
+                         ids=lambda c: "M%d-k%g-%dx%d-l%d" % c)
+def test_set_factors_samples_the_given_factors(case):
+    """Alg. 2 on caller-given factors (smf_set_factors): the oracle's factors in a plan give
+    the oracle's samples to FP64 rounding, through the plain recursion and through a 4-block
+    scan (whose block transitions are rebuilt from the new factors); the plan's own factors
+    written back leave its samples bit-identical; non-finite values are rejected."""
+    from paper_1709_10314_amd import SmfError
+
+    order, kap, n, nphi, lmax = case
+    count, seed = 2, 9
+    plan = _plan(order, n, nphi, lmax, kap, "fp64")
+    own_A, own_B = plan.factors()
+    T_own = plan.sample(seed, count).clone()
+    C = oracle.spectrum([kap] * order, lmax)
+    A, B = oracle.setup(order, C, n, nphi)
+    To, _ = oracle.sample(order, n, nphi, A, B, seed, count)
+    plan.set_factors(A, B)
+    for blocks in (1, 4):
+        plan.set_ring_blocks(blocks)
+        T = plan.sample(seed, count)
+        torch.cuda.synchronize()
+        T = T.cpu().numpy()
+        e = max(rel_rms(T[f], To[f]) for f in range(count))
+        log(f"{case} oracle factors, blocks {plan.ring_blocks(count)}: rel RMS {e:.3e}")
+        assert e <= 1e-12
+    plan.set_ring_blocks(1)
+    plan.set_factors(own_A, own_B)
+    T2 = plan.sample(seed, count)
+    torch.cuda.synchronize()
+    assert torch.equal(T2, T_own)
+    bad = own_A.copy()
+    bad[1, 0, 0, 0] = np.nan
+    with pytest.raises(SmfError):
+        plan.set_factors(bad, own_B)
+    plan.close()

@@ -32,10 +32,11 @@ def alu_slots_per_point(order):
     full-rate VALU op as 1 and the quarter-rate ones (32x32->64 multiply, log, sqrt, sin,
     cos) as 4.  Per normal: Philox4x32-10 is 10 rounds of 2 multiplies and 4 xors per
     4 words, 30 slots; Box-Muller is 2 conversions, 2 fma, 4 transcendentals and 4
-    multiplies per pair, 12 slots.  The step itself: 2 (M = 1) or 7 (M = 2) FMA-class ops."""
+    multiplies per pair, 12 slots.  The step itself: M*M + M(M+1)/2 FMA-class ops (A x and
+    the lower-triangular B w): 2, 7, 15, 26 for M = 1..4."""
     philox = 10 * (2 * 4 + 4) / 4
     box_muller = (2 + 2 + 4 * 4 + 4) / 2
-    return order * (philox + box_muller) + {1: 2, 2: 7}[order]
+    return order * (philox + box_muller) + order * order + order * (order + 1) // 2
 
 
 def log(msg):
@@ -116,6 +117,29 @@ def batch_leg(steps, warmup):
             "points": pts, "tiles": tiles, "setup_s": setup_s,
             "workload": "256 fields: n_theta uniform on {128..2048}, n_phi = 2 n_theta, ln kappa ~ U(ln 2, ln 200), "
                         "order 1 or 2, FP32, seeds 1..256 (numpy PCG64(0))"}
+
+
+def high_order_leg(cfg, order, steps, warmup):
+    """The same grid and fields at Markov order 3 or 4 (C_l = (l(l+1) + kappa^2)^-M, FP32):
+    ms per call, the recursion's ms per launch (events around smf_sample_modes) and its
+    VALU issue fraction."""
+    import torch
+
+    from paper_1709_10314_amd import Plan
+
+    n, nphi, lmax, count, seed = cfg["n_theta"], cfg["n_phi"], cfg["ell_max"], cfg["count"], cfg["seed"]
+    plan = Plan(order, n, nphi, lmax, kappa=[cfg["kappa"] ** 2] * order, precision="fp32")
+    out = plan.empty(count)
+    ms, _ = time_calls(lambda: plan.sample(seed, count, out), steps, warmup)
+    ms_rec, _ = time_calls(lambda: plan.sample_modes(seed, count, out), steps, warmup)
+    plan.close()
+    del out
+    torch.cuda.empty_cache()
+    pts = count * n * nphi
+    slots = pts * alu_slots_per_point(order)
+    return {"order": order, "value": pts / ms * 1e3, "unit": "grid points/s", "ms_per_step": ms,
+            "recursion_ms": ms_rec, "alu_slots_per_point": alu_slots_per_point(order),
+            "recursion_alu_frac": slots / (ms_rec * 1e-3) / VALU_PEAK_SLOTS}
 
 
 def measured_traffic(kernel):
@@ -214,6 +238,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-high-order", action="store_true")
     ap.add_argument("--cpu-rings", type=int, default=384)
     ap.add_argument("--cpu-single-rings", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -319,6 +344,16 @@ def main():
         log(f"  {batch['ms_per_step']:.3f} ms/call ({batch['value']:.3e} pts/s, tiles {batch['tiles']}, "
             f"setup {batch['setup_s']:.1f} s)")
 
+    high = None
+    if not args.no_high_order:
+        high = []
+        for o in (3, 4):
+            log(f"order {o} on the same grid and fields")
+            h = high_order_leg(cfg, o, args.steps, args.warmup)
+            log(f"  {h['ms_per_step']:.3f} ms/step, recursion {h['recursion_ms']:.3f} ms "
+                f"({100 * h['recursion_alu_frac']:.0f}% of the VALU issue peak)")
+            high.append(h)
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {args.cpu_rings} rings")
@@ -347,6 +382,7 @@ def main():
         "fp64_plain": fp64,
         "speedup_fp32_vs_fp64": (fp64["ms_per_step"] / ms_step) if fp64 else None,
         "batch_mix": batch,
+        "higher_orders": high,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

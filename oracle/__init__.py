@@ -82,6 +82,10 @@ def _load():
     lib.orc_setup_modes.argtypes = [_i, _i, _pd, _i, _i, _pi, _i, _pd, _pd]
     lib.orc_setup_modes_z.argtypes = [_i, _i, _pd, _i, _pd, _i, _pi, _i, _pd, _pd]
     lib.orc_setup_modes_z.restype = _i
+    lib.orc_setup_modes_asym.argtypes = [_i, _i, _pd, _i, _pd, _i, _pi, _i, _pd, _pd, _pd, _pd]
+    lib.orc_setup_modes_asym.restype = _i
+    lib.orc_sample_modes_list_south.argtypes = [_i, _i, _pi, _i, _i, _pd, _pd, _pd, _pd, _u64, _i, _pd]
+    lib.orc_sample_modes_list_south.restype = _i
     lib.orc_setup_modes.restype = _i
     lib.orc_sample_modes_list.argtypes = [_i, _i, _pi, _i, _i, _pd, _pd, _u64, _i, _pd]
     lib.orc_sample_modes_list.restype = _i
@@ -230,15 +234,42 @@ def setup_modes(order, C, n_theta, modes, sets=None, z=None):
     return A, B
 
 
-def sample_modes_list(order, n_theta, modes, A, B, seed, count, sets=None):
-    """Chains of the listed modes: g[count][n_theta][len(modes)] complex (NaN where unreached)."""
+def setup_asym(order, C, n_theta, n_phi, z, modes=None):
+    """Alg. 1 on any strictly decreasing grid z (north to south, not necessarily symmetric):
+    (A, B) for the northern walk and (As, Bs) for the southern walk in its own (true)
+    coordinates, each [sets][modes][order][order]; default every mode m = 0..m_top."""
+    C = np.ascontiguousarray(C, dtype=np.float64)
+    ell_max = len(C) - 1
+    md = np.arange(m_top(ell_max, n_phi) + 1, dtype=np.int32) if modes is None else \
+        np.ascontiguousarray(modes, dtype=np.int32)
+    ns = n_sets(n_theta)
+    zg = _zgrid(z, n_theta)
+    out = [np.zeros((ns, len(md), order, order)) for _ in range(4)]
+    rc = _load().orc_setup_modes_asym(order, ell_max, _p(C), n_theta, _p(zg), ns,
+                                      md.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(md),
+                                      *[_p(a) for a in out])
+    if rc != 0:
+        raise ValueError("orc_setup_modes_asym rejected its arguments")
+    return tuple(out)
+
+
+def sample_modes_list(order, n_theta, modes, A, B, seed, count, sets=None, south=None):
+    """Chains of the listed modes: g[count][n_theta][len(modes)] complex (NaN where unreached).
+    south: (As, Bs), the southern walk's own sets in true coordinates (default: the mirror of
+    the northern sets)."""
     A = np.ascontiguousarray(A, dtype=np.float64)
     B = np.ascontiguousarray(B, dtype=np.float64)
     md = np.ascontiguousarray(modes, dtype=np.int32)
     ns = A.shape[0] if sets is None else sets
     g = np.empty((count, n_theta, len(md), 2))
-    _load().orc_sample_modes_list(order, n_theta, md.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
-                                  len(md), ns, _p(A), _p(B), int(seed), count, _p(g))
+    if south is None:
+        _load().orc_sample_modes_list(order, n_theta, md.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                      len(md), ns, _p(A), _p(B), int(seed), count, _p(g))
+    else:
+        As = np.ascontiguousarray(south[0], dtype=np.float64)
+        Bs = np.ascontiguousarray(south[1], dtype=np.float64)
+        _load().orc_sample_modes_list_south(order, n_theta, md.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                            len(md), ns, _p(A), _p(B), _p(As), _p(Bs), int(seed), count, _p(g))
     return g[..., 0] + 1j * g[..., 1]
 
 
@@ -289,7 +320,10 @@ def dft(g, n_phi, r0=0, r1=None):
     return T
 
 
-def sample(order, n_theta, n_phi, A, B, seed, count):
-    """Full plain method (chains + DFT), returns (T, g)."""
-    g = sample_modes(order, n_theta, A, B, seed, count)
+def sample(order, n_theta, n_phi, A, B, seed, count, south=None):
+    """Full plain method (chains + DFT), returns (T, g).  south: as in sample_modes_list."""
+    if south is None:
+        g = sample_modes(order, n_theta, A, B, seed, count)
+    else:
+        g = sample_modes_list(order, n_theta, np.arange(A.shape[1]), A, B, seed, count, south=south)
     return dft(g, n_phi), g

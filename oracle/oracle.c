@@ -393,30 +393,40 @@ static void set_rings(int n_theta, int j, int* a, int* b)
 /* triangular); for j = 0, A = 0 and B = B_eq.  n_sets may be smaller than      */
 /* orc_n_sets(n_theta) to cover only the rings nearest the start.              */
 /* zgrid: the ring values z_0 > z_1 > ... > z_{n-1} of Alg. 1's grid argument,  */
-/* symmetric (z_{n-1-i} = -z_i), with sin(theta) = sqrt((1 - z)(1 + z)); NULL    */
-/* selects the ring centres.  Only the northern rings are read.                */
+/* with sin(theta) = sqrt((1 - z)(1 + z)); NULL selects the ring centres.       */
+/* south = 0: the northern sets (start, crossing for even n_theta, then the     */
+/* steps towards ring 0); south = 1: the same sets for the southern walk in     */
+/* its own (true) coordinates: start, crossing, then the steps (s+j-1) -> (s+j) */
+/* towards ring n-1.                                                           */
 /* ------------------------------------------------------------------------- */
-int orc_setup_modes_z(int order, int ell_max, const double* C, int n_theta, const double* zgrid,
-                      int n_sets, const int* modes, int n_modes, double* A, double* B)
+static int grid_ok(const double* zgrid, int n_theta, int symmetric)
 {
-    if (order < 1 || order > ORC_MAXM || n_theta < 2 || ell_max < 0) return -1;
-    if (zgrid) {
-        for (int i = 0; i < n_theta; ++i) {
-            if (!(zgrid[i] > -1.0 && zgrid[i] < 1.0)) return -1;
-            if (i > 0 && !(zgrid[i] < zgrid[i - 1])) return -1;
-            if (zgrid[n_theta - 1 - i] != -zgrid[i]) return -1;
-        }
+    for (int i = 0; i < n_theta; ++i) {
+        if (!(zgrid[i] > -1.0 && zgrid[i] < 1.0)) return 0;
+        if (i > 0 && !(zgrid[i] < zgrid[i - 1])) return 0;
+        if (symmetric && zgrid[n_theta - 1 - i] != -zgrid[i]) return 0;
     }
+    return 1;
+}
+
+static void setup_sets(int order, int ell_max, const double* C, int n_theta, const double* zgrid, int n_sets,
+                       const int* modes, int n_modes, int south, double* A, double* B)
+{
     int MM = order * order;
-    int total = orc_n_sets(n_theta);
-    if (n_sets > total) n_sets = total;
+    const int s = orc_start_ring(n_theta);
+    const int j0 = (n_theta % 2 == 0) ? 2 : 1;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i < n_modes; ++i) {
         int m = modes[i];
         double Kaa[ORC_MAXM * ORC_MAXM], Kbb[ORC_MAXM * ORC_MAXM], Kba[ORC_MAXM * ORC_MAXM];
         for (int j = 0; j < n_sets; ++j) {
             int a, b;
-            set_rings(n_theta, j, &a, &b);
+            if (south && j >= j0) {
+                a = s + j - 1;
+                b = s + j;
+            } else {
+                set_rings(n_theta, j, &a, &b);
+            }
             double za, sa, zb, sb;
             if (zgrid) {
                 za = zgrid[a];
@@ -441,6 +451,31 @@ int orc_setup_modes_z(int order, int ell_max, const double* C, int n_theta, cons
             orc_step_factors(order, Kaa, Kbb, Kba, Aj, Bj);
         }
     }
+}
+
+/* Symmetric grids (the south is the mirror of the north, the remark after Alg. 1). */
+int orc_setup_modes_z(int order, int ell_max, const double* C, int n_theta, const double* zgrid,
+                      int n_sets, const int* modes, int n_modes, double* A, double* B)
+{
+    if (order < 1 || order > ORC_MAXM || n_theta < 2 || ell_max < 0) return -1;
+    if (zgrid && !grid_ok(zgrid, n_theta, 1)) return -1;
+    int total = orc_n_sets(n_theta);
+    if (n_sets > total) n_sets = total;
+    setup_sets(order, ell_max, C, n_theta, zgrid, n_sets, modes, n_modes, 0, A, B);
+    return 0;
+}
+
+/* Any strictly decreasing grid in (-1, 1): the northern sets (A, B) and the sets of */
+/* the southern walk in true coordinates (As, Bs), same shapes.                  */
+int orc_setup_modes_asym(int order, int ell_max, const double* C, int n_theta, const double* zgrid, int n_sets,
+                         const int* modes, int n_modes, double* A, double* B, double* As, double* Bs)
+{
+    if (order < 1 || order > ORC_MAXM || n_theta < 2 || ell_max < 0 || !zgrid) return -1;
+    if (!grid_ok(zgrid, n_theta, 0)) return -1;
+    int total = orc_n_sets(n_theta);
+    if (n_sets > total) n_sets = total;
+    setup_sets(order, ell_max, C, n_theta, zgrid, n_sets, modes, n_modes, 0, A, B);
+    setup_sets(order, ell_max, C, n_theta, zgrid, n_sets, modes, n_modes, 1, As, Bs);
     return 0;
 }
 
@@ -518,8 +553,9 @@ double orc_normal(uint64_t key, int m, int part, int ring, int order, int q)
 /* g is [count][n_theta][n_modes][2] (Re, Im).  Only factor sets j < n_sets are  */
 /* used; rings they do not reach stay NaN.                                      */
 /* ------------------------------------------------------------------------- */
-int orc_sample_modes_list(int order, int n_theta, const int* modes, int n_modes, int n_sets,
-                          const double* A, const double* B, uint64_t seed, int count, double* g)
+int orc_sample_modes_list_south(int order, int n_theta, const int* modes, int n_modes, int n_sets,
+                                const double* A, const double* B, const double* As, const double* Bs,
+                                uint64_t seed, int count, double* g)
 {
     const int M = order, MM = order * order;
     const int s = orc_start_ring(n_theta);
@@ -561,7 +597,8 @@ int orc_sample_modes_list(int order, int n_theta, const int* modes, int n_modes,
                     for (int p = 0; p < M; ++p) x[p] = xn[p];
                     gf[(size_t)r * row + 2 * i + part] = x[0];
                 }
-                /* south: crossing (even n) then mirrored steps with D A D, D B D */
+                /* south: crossing (even n) then the steps towards ring n-1: the northern
+                   sets mirrored with D A D, D B D, or the southern sets As, Bs as given */
                 for (int p = 0; p < M; ++p) x[p] = xs[p];
                 int r = s;
                 int j0 = 1;
@@ -581,13 +618,14 @@ int orc_sample_modes_list(int order, int n_theta, const int* modes, int n_modes,
                 }
                 for (int j = j0; j < n_sets; ++j) {
                     r += 1;
-                    const double* Aj = A + ((size_t)j * n_modes + i) * MM;
-                    const double* Bj = B + ((size_t)j * n_modes + i) * MM;
+                    const double* Aj = (As ? As : A) + ((size_t)j * n_modes + i) * MM;
+                    const double* Bj = (Bs ? Bs : B) + ((size_t)j * n_modes + i) * MM;
                     for (int q = 0; q < M; ++q) w[q] = orc_normal(key, m, part, r, M, q);
                     for (int p = 0; p < M; ++p) {
                         xn[p] = 0.0;
                         for (int q = 0; q < M; ++q) {
-                            double sgn = ((p + q) % 2 == 0) ? 1.0 : -1.0;   /* D X D */
+                            /* mirrored: D X D of the northern set; own sets: as they are */
+                            double sgn = (As || (p + q) % 2 == 0) ? 1.0 : -1.0;
                             xn[p] += sgn * (Aj[p * M + q] * x[q] + sc * Bj[p * M + q] * w[q]);
                         }
                     }
@@ -597,6 +635,13 @@ int orc_sample_modes_list(int order, int n_theta, const int* modes, int n_modes,
             }
         }
     return 0;
+}
+
+/* Symmetric grids: the south mirrors the northern sets. */
+int orc_sample_modes_list(int order, int n_theta, const int* modes, int n_modes, int n_sets,
+                          const double* A, const double* B, uint64_t seed, int count, double* g)
+{
+    return orc_sample_modes_list_south(order, n_theta, modes, n_modes, n_sets, A, B, NULL, NULL, seed, count, g);
 }
 
 /* Chains for every mode m = 0..m_top: g is [count][n_theta][m_top+1][2]. */

@@ -78,3 +78,15 @@ def random_z(n, seed=0):
     if n % 2 == 0:
         zn = np.maximum(zn, 1e-3)
     return _mirror(zn, n)
+
+
+def random_asym_z(n, seed=0):
+    """A grid with no symmetry: n values drawn uniformly in (-0.99, 0.99), descending
+    (PCG64(seed))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.sort(rng.uniform(-0.99, 0.99, n))[::-1].copy()
+
+
+def shifted_z(n, shift=0.3):
+    """Ring centres shifted by a fraction of a ring: z_i = cos(pi (i + shift) / n), shift in (0, 1)."""
+    return np.cos(np.pi * (np.arange(n) + shift) / n)

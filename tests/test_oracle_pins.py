@@ -544,6 +544,118 @@ def test_explicit_grid_variance_closed_form(orc, grid, order, kappa, lmax):
     np.testing.assert_allclose(var, ref, rtol=1e-11)
 
 
+def _asym_grids():
+    from paper_1709_10314_amd import workloads as w
+
+    return {"random-14": w.random_asym_z(14, 5), "random-15": w.random_asym_z(15, 6),
+            "shifted-16": w.shifted_z(16, 0.3), "shifted-13": w.shifted_z(13, 0.8)}
+
+
+def _propagate_asym(orc, order, C, lmax, z, A, B, As, Bs):
+    """Worst reproduction of J(b,b) and J(b,a) over both walks of a grid with its own
+    southern sets (true coordinates, no mirror)."""
+    n = len(z)
+    s = orc.start_ring(n)
+    even = n % 2 == 0
+    worst = 0.0
+
+    def cmp(S, K):
+        d = np.sqrt(np.maximum(np.diag(K), 0))
+        sc = np.outer(d, d)
+        mask = sc > 1e-280
+        return np.max(np.abs(S - K)[mask] / sc[mask]) if mask.any() else 0.0
+
+    def jb(m, i1, i2):
+        return orc.jblock_z(order, m, lmax, C, z[i1], z[i2])
+
+    for m in range(A.shape[1]):
+        S0 = B[0, m] @ B[0, m].T
+        worst = max(worst, cmp(S0, jb(m, s, s)))
+        Sig, a = S0, s
+        for j in range(2 if even else 1, A.shape[0]):
+            b = s - j + 1 if even else s - j
+            cross = A[j, m] @ Sig
+            Sig = A[j, m] @ Sig @ A[j, m].T + B[j, m] @ B[j, m].T
+            worst = max(worst, cmp(Sig, jb(m, b, b)), cmp(cross, jb(m, b, a)))
+            a = b
+        Sig, a, j0 = S0, s, 1
+        if even:
+            cross = A[1, m] @ Sig
+            Sig = A[1, m] @ Sig @ A[1, m].T + B[1, m] @ B[1, m].T
+            worst = max(worst, cmp(Sig, jb(m, s + 1, s + 1)), cmp(cross, jb(m, s + 1, s)))
+            a, j0 = s + 1, 2
+        for j in range(j0, As.shape[0]):
+            b = a + 1
+            cross = As[j, m] @ Sig
+            Sig = As[j, m] @ Sig @ As[j, m].T + Bs[j, m] @ Bs[j, m].T
+            worst = max(worst, cmp(Sig, jb(m, b, b)), cmp(cross, jb(m, b, a)))
+            a = b
+    return worst
+
+
+@pytest.mark.parametrize("n", [16, 17])
+@pytest.mark.parametrize("order", [1, 2])
+def test_southern_sets_of_a_symmetric_grid_are_the_mirror(orc, n, order):
+    """On a symmetric grid the southern walk's own sets equal the mirrored northern ones
+    (D A D, D B D, the remark after Alg. 1) and give the same samples, bit for bit: the
+    Legendre values at -z are exactly the sign-flipped ones."""
+    C = orc.spectrum([100.0] * order, 30)
+    z = orc.grid(n)[1]
+    A, B = orc.setup(order, C, n, 64, z=z)
+    An, Bn, As, Bs = orc.setup_asym(order, C, n, 64, z)
+    D = np.diag([(-1.0) ** p for p in range(order)])
+    j0 = 2 if n % 2 == 0 else 1
+    assert np.array_equal(An, A) and np.array_equal(Bn, B)
+    assert np.array_equal(D @ A[j0:] @ D, As[j0:]) and np.array_equal(D @ B[j0:] @ D, Bs[j0:])
+    T1, _ = orc.sample(order, n, 64, A, B, 5, 2)
+    T2, _ = orc.sample(order, n, 64, An, Bn, 5, 2, south=(As, Bs))
+    assert np.array_equal(T1, T2)
+
+
+@pytest.mark.parametrize("grid", sorted(_asym_grids()))
+@pytest.mark.parametrize("order,kappa,lmax", [(1, 64.0, 30), (2, 100.0, 25)])
+def test_asymmetric_grid_factors_reproduce_ring_covariances(orc, grid, order, kappa, lmax):
+    """A grid with no symmetry: the northern sets and the southern walk's own sets
+    reproduce J at every ring of both walks by covariance propagation."""
+    z = _asym_grids()[grid]
+    C = orc.spectrum([kappa] * order, lmax)
+    A, B, As, Bs = orc.setup_asym(order, C, len(z), 2 * (lmax + 1), z)
+    assert _propagate_asym(orc, order, C, lmax, z, A, B, As, Bs) < 1e-11
+
+
+@pytest.mark.parametrize("grid", sorted(_asym_grids()))
+@pytest.mark.parametrize("order,kappa,lmax", [(1, 9.0, 24), (2, 50.0, 20)])
+def test_asymmetric_grid_variance_closed_form(orc, grid, order, kappa, lmax):
+    """The addition theorem at every ring of a grid with no symmetry: Var T(z_i, phi) =
+    sum_l (2l+1) C_l / (4 pi), propagated through the northern and the southern sets."""
+    z = _asym_grids()[grid]
+    n = len(z)
+    C = orc.spectrum([kappa] * order, lmax)
+    A, B, As, Bs = orc.setup_asym(order, C, n, 2 * (lmax + 1), z)
+    s = orc.start_ring(n)
+    even = n % 2 == 0
+    var = np.zeros(n)
+    for m in range(A.shape[1]):
+        w = 1.0 if m == 0 else 2.0
+        S0 = B[0, m] @ B[0, m].T
+        var[s] += w * S0[0, 0]
+        Sig = S0
+        for j in range(2 if even else 1, A.shape[0]):
+            Sig = A[j, m] @ Sig @ A[j, m].T + B[j, m] @ B[j, m].T
+            var[s - j + 1 if even else s - j] += w * Sig[0, 0]
+        Sig, r, j0 = S0, s, 1
+        if even:
+            Sig = A[1, m] @ Sig @ A[1, m].T + B[1, m] @ B[1, m].T
+            r, j0 = s + 1, 2
+            var[r] += w * Sig[0, 0]
+        for j in range(j0, As.shape[0]):
+            Sig = As[j, m] @ Sig @ As[j, m].T + Bs[j, m] @ Bs[j, m].T
+            r += 1
+            var[r] += w * Sig[0, 0]
+    ref = np.sum((2 * np.arange(lmax + 1) + 1) * C) / (4 * math.pi)
+    np.testing.assert_allclose(var, ref, rtol=1e-11)
+
+
 def test_explicit_grid_of_ring_centres_is_the_default(orc):
     """The ring-centre grid given as values gives the default factors (up to the rounding
     of sin(theta), taken from z instead of the complementary angle)."""

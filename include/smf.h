@@ -77,17 +77,19 @@ enum {
 int smf_setup(const smf_spectrum* spec, int n_theta, int n_phi, int flags, void* hip_stream,
               smf_plan** out);
 
-/* Alg. 1 on an explicit grid: its signature takes the ring values z as an input, and the
- * remark after it stores only the northern half when the grid is symmetric.  z_host
- * (host, n_theta doubles, copied, not retained) lists the rings from north to south:
- * strictly decreasing, inside (-1, 1), and symmetric to the bit, z[n_theta-1-i] == -z[i]
- * (so an odd grid has its equator ring at z = 0).  sin(theta_i) is taken as
- * sqrt((1 - z_i)(1 + z_i)).  The start ring, the crossing step and the mirror are those of
- * smf_setup; the phi grid, the sampling calls and their output are unchanged.  Examples: the
- * ring-centre grid itself (for odd n_theta it is the paper's symmetric example grid, read
- * as z_j = sin(pi j / n_theta)), Gauss-Legendre nodes, HEALPix ring latitudes.
+/* Alg. 1 on an explicit grid: its signature takes the ring values z as an input.  z_host
+ * (host, n_theta doubles, copied) lists the rings from north to south: strictly
+ * decreasing and inside (-1, 1); sin(theta_i) is taken as sqrt((1 - z_i)(1 + z_i)).  The
+ * start ring (s = n_theta/2 - 1 or (n_theta-1)/2) and the crossing step are those of
+ * smf_setup.  A grid symmetric to the bit, z[n_theta-1-i] == -z[i], stores only the
+ * northern steps and mirrors them for the south (the remark after Alg. 1); any other grid
+ * also stores the southern walk's own steps (s+j-1) -> (s+j), twice the factor memory.  The
+ * phi grid, the sampling calls and their output are unchanged.  Examples: the ring-centre
+ * grid itself (for odd n_theta it is the paper's symmetric example grid, read as
+ * z_j = sin(pi j / n_theta)), Gauss-Legendre nodes, HEALPix ring latitudes, shifted ring
+ * centres.
  * Errors: as smf_setup, plus SMF_EINVAL for a NULL z_host or a grid that is not strictly
- * decreasing in (-1, 1) and symmetric. */
+ * decreasing in (-1, 1). */
 int smf_setup_grid(const smf_spectrum* spec, int n_theta, const double* z_host, int n_phi, int flags,
                    void* hip_stream, smf_plan** out);
 
@@ -157,12 +159,21 @@ int smf_plan_dims(const smf_plan* plan, int* dims);
  * B = B_eq).  Set j >= 1 is the step between the ring pair it covers: for even n_theta
  * (start ring s = n_theta/2 - 1) set 1 is the crossing s -> s+1 and set j >= 2 the step
  * s-j+2 -> s-j+1; for odd n_theta (s = (n_theta-1)/2) set j >= 1 is s-j+1 -> s-j.
+ * A plan on a grid with no symmetry (smf_plan_grid) holds 2*n_sets sets: the northern ones,
+ * then the southern walk's, whose set j >= j0 (2 for even n_theta, else 1) is the step
+ * s+j-1 -> s+j in true coordinates (sets below j0 repeat the northern ones).
  * Synchronous.  Errors: SMF_EINVAL on NULL, SMF_EHIP. */
 int smf_get_factors(const smf_plan* plan, double* A_host, double* B_host);
 
+/* The plan's ring grid: z_host (may be NULL) receives the n_theta ring values the setup
+ * used (for smf_setup plans the ring centres, recomputed on the host to rounding), and
+ * *symmetric (may be NULL) 1 when the south mirrors the northern factor sets, 0 when it
+ * has its own (a grid with no symmetry).  Errors: SMF_EINVAL (NULL or batch plan). */
+int smf_plan_grid(const smf_plan* plan, double* z_host, int* symmetric);
+
 /* Alg. 2 takes the factors (A, B, B_eq) as its input: replaces the plan's factors with
- * caller-given FP64 ones in the layout of smf_get_factors (set 0: A ignored, B = B_eq; the
- * upper triangle of each B is ignored), e.g. factors from another setup, then rounds the
+ * caller-given FP64 ones in the layout of smf_get_factors (2*n_sets sets for a grid with no
+ * symmetry; set 0: A ignored, B = B_eq; the upper triangle of each B is ignored), e.g. factors from another setup, then rounds the
  * FP32 copy (SMF_FP32 plans) and rebuilds the scan's block transitions.  Synchronous on
  * hip_stream; must not overlap sampling calls on the plan.
  * Errors: SMF_EINVAL (NULL, batch plan, a value that is not finite), SMF_EHIP. */

@@ -1,4 +1,5 @@
 // C ABI of libsmf: plan creation (Alg. 1 on the GPU), sampling (Alg. 2), queries.
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -69,15 +70,22 @@ struct DeviceGuard {
     }
 };
 
-// An explicit grid: n_theta finite values strictly decreasing in (-1, 1) with
-// z[n-1-i] == -z[i] exactly (so an odd grid has z = 0 at its middle ring).
+// An explicit grid: n_theta finite values strictly decreasing in (-1, 1).
 bool grid_ok(const double* z, int n)
 {
     for (int i = 0; i < n; ++i) {
         if (!(z[i] > -1.0 && z[i] < 1.0)) return false;
         if (i > 0 && !(z[i] < z[i - 1])) return false;
-        if (z[n - 1 - i] != -z[i]) return false;
     }
+    return true;
+}
+
+// Symmetric about the equator to the bit, z[n-1-i] == -z[i] (an odd grid then has z = 0
+// at its middle ring): the south mirrors the northern sets.
+bool grid_symmetric(const double* z, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (z[n - 1 - i] != -z[i]) return false;
     return true;
 }
 
@@ -114,6 +122,12 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
     plan->g = g;
     plan->flags = flags;
     plan->device = dev;
+    plan->asym = (z_host && !grid_symmetric(z_host, n_theta)) ? 1 : 0;
+    if (z_host) {
+        plan->zgrid = (double*)malloc(sizeof(double) * n_theta);
+        if (!plan->zgrid) { free(plan); return SMF_ENOMEM; }
+        memcpy(plan->zgrid, z_host, sizeof(double) * n_theta);
+    }
 
     int rc = SMF_OK;
     double* kappa_dev = nullptr;
@@ -121,7 +135,9 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
     double* z_dev = nullptr;
     int* bad_dev = nullptr;
     int bad = 0;
-    const size_t nrec = (size_t)g.n_sets * g.m_rows * smf::factor_stride(g.order);
+    // the northern table, and for a grid with no symmetry the southern walk's own table after it
+    const size_t nrec1 = (size_t)g.n_sets * g.m_rows * smf::factor_stride(g.order);
+    const size_t nrec = nrec1 * (plan->asym ? 2 : 1);
     hipError_t e = hipSuccess;
 
     if ((rc = bufs.alloc(&plan->C, (size_t)g.ell_max + 1))) goto fail;
@@ -156,21 +172,31 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
             goto fail;
         }
     }
-    if (smf::launch_factors(g, plan->C, z_dev, plan->f64, plan->f32, st) != hipSuccess) { rc = SMF_EHIP; goto fail; }
+    plan->south_off = plan->asym ? nrec1 : 0;
+    if (smf::launch_factors(g, plan->C, z_dev, 0, plan->f64, plan->f32, st) != hipSuccess) { rc = SMF_EHIP; goto fail; }
+    if (plan->asym && smf::launch_factors(g, plan->C, z_dev, 1, plan->f64 + nrec1, plan->f32 ? plan->f32 + nrec1 : nullptr,
+                                          st) != hipSuccess) {
+        rc = SMF_EHIP;
+        goto fail;
+    }
     if ((rc = bufs.alloc(&plan->tw64, (size_t)2 * n_phi))) goto fail;
     if ((rc = bufs.alloc(&plan->tw32, (size_t)2 * n_phi))) goto fail;
     if (smf::launch_twiddles(n_phi, plan->tw64, plan->tw32, st) != hipSuccess) { rc = SMF_EHIP; goto fail; }
     // the affine scan serves orders 1 and 2 (the chain kernels of orders 3 and 4 run plain)
     plan->scan_fine = (scan && g.order <= 2) ? smf::scan_fine_blocks(g) : 1;
     if (plan->scan_fine > 1) {
-        const size_t nphi = (size_t)plan->scan_fine * g.m_rows * g.order * g.order;
+        const size_t nphi1 = (size_t)plan->scan_fine * g.m_rows * g.order * g.order;
+        const size_t nphi = nphi1 * (plan->asym ? 2 : 1);
+        plan->phi_south_off = plan->asym ? nphi1 : 0;
         if ((rc = bufs.alloc(&plan->phi64, nphi))) goto fail;
         if (hipMemsetAsync(plan->phi64, 0, nphi * sizeof(double), st) != hipSuccess) { rc = SMF_EHIP; goto fail; }
         if (flags == SMF_FP32) {
             if ((rc = bufs.alloc(&plan->phi32, nphi))) goto fail;
             if (hipMemsetAsync(plan->phi32, 0, nphi * sizeof(float), st) != hipSuccess) { rc = SMF_EHIP; goto fail; }
         }
-        if (smf::launch_phi(g, plan->f64, plan->scan_fine, plan->phi64, plan->phi32, st) != hipSuccess) {
+        if (smf::launch_phi(g, plan->f64, plan->scan_fine, plan->phi64, plan->phi32, st) != hipSuccess ||
+            (plan->asym && smf::launch_phi(g, plan->f64 + nrec1, plan->scan_fine, plan->phi64 + nphi1,
+                                           plan->phi32 ? plan->phi32 + nphi1 : nullptr, st) != hipSuccess)) {
             rc = SMF_EHIP;
             goto fail;
         }
@@ -188,6 +214,7 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
 fail:
     (void)hipStreamSynchronize(st);
     bufs.free_all();
+    free(plan->zgrid);
     free(plan);
     return rc;
 }
@@ -263,10 +290,11 @@ static int sample_common(const smf_plan* plan, uint64_t seed, int count, void* o
     const CallShape cs = call_shape(plan, count);
     if (cs.blocks > 1) {
         const void* phi = fp64 ? (const void*)plan->phi64 : (const void*)plan->phi32;
-        if (smf::launch_scan(plan->g, fp64, fac, phi, plan->scan_fine, cs.blocks, seed, count, out_dev, cs.nch,
-                             st) != hipSuccess)
+        if (smf::launch_scan(plan->g, fp64, fac, plan->south_off, phi, plan->phi_south_off, plan->scan_fine, cs.blocks,
+                             seed, count, out_dev, cs.nch, st) != hipSuccess)
             return SMF_EHIP;
-    } else if (smf::launch_recursion(plan->g, fp64, fac, seed, count, out_dev, cs.nch, st) != hipSuccess) {
+    } else if (smf::launch_recursion(plan->g, fp64, fac, plan->south_off, seed, count, out_dev, cs.nch, st) !=
+               hipSuccess) {
         return SMF_EHIP;
     }
     if (fft) {
@@ -337,39 +365,68 @@ int smf_plan_dims(const smf_plan* plan, int* dims)
     return SMF_OK;
 }
 
+// One factor record to or from full M x M matrices (A row-major, B lower triangular);
+// `mirror` conjugates both by D = diag((-1)^p), the storage of the southern walk's own sets.
+static void unpack_record(int M, const double* r, bool mirror, double* A, double* B)
+{
+    if (M == 1) {
+        A[0] = r[0];
+        B[0] = r[1];
+    } else if (M == 2) {
+        A[0] = r[0]; A[1] = r[1]; A[2] = r[2]; A[3] = r[3];
+        B[0] = r[4]; B[1] = 0.0; B[2] = r[5]; B[3] = r[6];
+    } else {
+        for (int i = 0; i < M * M; ++i) A[i] = r[i];
+        int k = M * M;
+        for (int p = 0; p < M; ++p)
+            for (int q = 0; q < M; ++q) B[p * M + q] = q <= p ? r[k++] : 0.0;
+    }
+    if (mirror)
+        for (int p = 0; p < M; ++p)
+            for (int q = 0; q < M; ++q)
+                if ((p + q) & 1) { A[p * M + q] = -A[p * M + q]; B[p * M + q] = -B[p * M + q]; }
+}
+
+static void pack_record(int M, const double* A, const double* B, bool mirror, double* r)
+{
+    const double sg[2] = {1.0, mirror ? -1.0 : 1.0};
+    if (M == 1) {
+        r[0] = A[0];
+        r[1] = B[0];
+    } else if (M == 2) {
+        r[0] = A[0]; r[1] = sg[1] * A[1]; r[2] = sg[1] * A[2]; r[3] = A[3];
+        r[4] = B[0]; r[5] = sg[1] * B[2]; r[6] = B[3];
+    } else {
+        int k = M * M;
+        for (int p = 0; p < M; ++p)
+            for (int q = 0; q < M; ++q) r[p * M + q] = sg[(p + q) & 1] * A[p * M + q];
+        for (int p = 0; p < M; ++p)
+            for (int q = 0; q <= p; ++q) r[k++] = sg[(p + q) & 1] * B[p * M + q];
+    }
+}
+
+// Factor tables a plan holds: the northern one, and for a grid with no symmetry the
+// southern walk's own one (its sets from j0 on stored mirrored).
+static int n_tables(const smf_plan* plan) { return plan->asym ? 2 : 1; }
+
 int smf_get_factors(const smf_plan* plan, double* A_host, double* B_host)
 {
     if (!plan || plan->batch || !A_host || !B_host) return SMF_EINVAL;
     DeviceGuard dg(plan->device);
     const Geometry& g = plan->g;
-    const int M = g.order, E = smf::factor_stride(M);
-    const size_t nrec = (size_t)g.n_sets * g.m_rows * E;
-    double* tmp = (double*)malloc(nrec * sizeof(double));
-    if (!tmp) return SMF_ENOMEM;
-    if (hipMemcpy(tmp, plan->f64, nrec * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
-        free(tmp);
+    const int M = g.order, E = smf::factor_stride(M), j0 = g.even ? 2 : 1;
+    const size_t nrec = (size_t)g.n_sets * g.m_rows * E * n_tables(plan);
+    std::vector<double> tmp(nrec);
+    if (hipMemcpy(tmp.data(), plan->f64, nrec * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
         return SMF_EHIP;
-    }
-    for (int j = 0; j < g.n_sets; ++j)
-        for (int m = 0; m <= g.m_top; ++m) {
-            const double* r = tmp + ((size_t)j * g.m_rows + m) * E;
-            double* A = A_host + ((size_t)j * (g.m_top + 1) + m) * M * M;
-            double* B = B_host + ((size_t)j * (g.m_top + 1) + m) * M * M;
-            if (M == 1) {
-                A[0] = r[0];
-                B[0] = r[1];
-            } else if (M == 2) {
-                A[0] = r[0]; A[1] = r[1]; A[2] = r[2]; A[3] = r[3];
-                B[0] = r[4]; B[1] = 0.0; B[2] = r[5]; B[3] = r[6];
-            } else {
-                // A row-major, then B's lower triangle by rows
-                for (int i = 0; i < M * M; ++i) A[i] = r[i];
-                int k = M * M;
-                for (int p = 0; p < M; ++p)
-                    for (int q = 0; q < M; ++q) B[p * M + q] = q <= p ? r[k++] : 0.0;
+    for (int t = 0; t < n_tables(plan); ++t)
+        for (int j = 0; j < g.n_sets; ++j)
+            for (int m = 0; m <= g.m_top; ++m) {
+                const size_t js = (size_t)t * g.n_sets + j;
+                const double* r = tmp.data() + (js * g.m_rows + m) * E;
+                const size_t o = (js * (g.m_top + 1) + m) * M * M;
+                unpack_record(M, r, t == 1 && j >= j0, A_host + o, B_host + o);
             }
-        }
-    free(tmp);
     return SMF_OK;
 }
 
@@ -378,31 +435,21 @@ int smf_set_factors(smf_plan* plan, const double* A_host, const double* B_host, 
     if (!plan || plan->batch || !A_host || !B_host) return SMF_EINVAL;
     DeviceGuard dg(plan->device);
     const Geometry& g = plan->g;
-    const int M = g.order, E = smf::factor_stride(M);
+    const int M = g.order, E = smf::factor_stride(M), j0 = g.even ? 2 : 1;
     const size_t per = (size_t)(g.m_top + 1) * M * M;
-    for (size_t i = 0; i < (size_t)g.n_sets * per; ++i)
+    const size_t nsets = (size_t)g.n_sets * n_tables(plan);
+    for (size_t i = 0; i < nsets * per; ++i)
         if (!std::isfinite(A_host[i]) || !std::isfinite(B_host[i])) return SMF_EINVAL;
-    const size_t nrec = (size_t)g.n_sets * g.m_rows * E;
+    const size_t nrec1 = (size_t)g.n_sets * g.m_rows * E, nrec = nrec1 * n_tables(plan);
     std::vector<double> r64(nrec, 0.0);
     std::vector<float> r32;
-    for (int j = 0; j < g.n_sets; ++j)
-        for (int m = 0; m <= g.m_top; ++m) {
-            double* r = r64.data() + ((size_t)j * g.m_rows + m) * E;
-            const double* A = A_host + ((size_t)j * (g.m_top + 1) + m) * M * M;
-            const double* B = B_host + ((size_t)j * (g.m_top + 1) + m) * M * M;
-            if (M == 1) {
-                r[0] = A[0];
-                r[1] = B[0];
-            } else if (M == 2) {
-                r[0] = A[0]; r[1] = A[1]; r[2] = A[2]; r[3] = A[3];
-                r[4] = B[0]; r[5] = B[2]; r[6] = B[3];
-            } else {
-                int k = M * M;
-                for (int i = 0; i < M * M; ++i) r[i] = A[i];
-                for (int p = 0; p < M; ++p)
-                    for (int q = 0; q <= p; ++q) r[k++] = B[p * M + q];
+    for (int t = 0; t < n_tables(plan); ++t)
+        for (int j = 0; j < g.n_sets; ++j)
+            for (int m = 0; m <= g.m_top; ++m) {
+                const size_t js = (size_t)t * g.n_sets + j;
+                const size_t o = (js * (g.m_top + 1) + m) * M * M;
+                pack_record(M, A_host + o, B_host + o, t == 1 && j >= j0, r64.data() + (js * g.m_rows + m) * E);
             }
-        }
     hipStream_t st = (hipStream_t)hip_stream;
     if (hipMemcpyAsync(plan->f64, r64.data(), nrec * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess)
         return SMF_EHIP;
@@ -412,10 +459,30 @@ int smf_set_factors(smf_plan* plan, const double* A_host, const double* B_host, 
         if (hipMemcpyAsync(plan->f32, r32.data(), nrec * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess)
             return SMF_EHIP;
     }
-    if (plan->scan_fine > 1 &&
-        smf::launch_phi(g, plan->f64, plan->scan_fine, plan->phi64, plan->phi32, st) != hipSuccess)
-        return SMF_EHIP;
+    if (plan->scan_fine > 1) {
+        if (smf::launch_phi(g, plan->f64, plan->scan_fine, plan->phi64, plan->phi32, st) != hipSuccess)
+            return SMF_EHIP;
+        if (plan->asym &&
+            smf::launch_phi(g, plan->f64 + nrec1, plan->scan_fine, plan->phi64 + plan->phi_south_off,
+                            plan->phi32 ? plan->phi32 + plan->phi_south_off : nullptr, st) != hipSuccess)
+            return SMF_EHIP;
+    }
     return hipStreamSynchronize(st) == hipSuccess ? SMF_OK : SMF_EHIP;
+}
+
+int smf_plan_grid(const smf_plan* plan, double* z_host, int* symmetric)
+{
+    if (!plan || plan->batch) return SMF_EINVAL;
+    if (symmetric) *symmetric = plan->asym ? 0 : 1;
+    if (z_host) {
+        if (plan->zgrid) {
+            memcpy(z_host, plan->zgrid, sizeof(double) * plan->g.n_theta);
+        } else {
+            const int n = plan->g.n_theta;
+            for (int i = 0; i < n; ++i) z_host[i] = std::sin(M_PI * (double)(n - 2 * i - 1) / (2.0 * n));
+        }
+    }
+    return SMF_OK;
 }
 
 int smf_destroy(smf_plan* plan)
@@ -440,6 +507,7 @@ int smf_destroy(smf_plan* plan)
     (void)hipFree(plan->tw32);
     if (plan->phi64) (void)hipFree(plan->phi64);
     if (plan->phi32) (void)hipFree(plan->phi32);
+    free(plan->zgrid);
     free(plan);
     return SMF_OK;
 }

@@ -372,11 +372,13 @@ __device__ __forceinline__ void chain_scales(int m, uint32_t up0, T (&sc)[NCH])
 // the southern chain (h = 1) redraws the same start state (same counters), takes the
 // crossing step (even n_theta) and steps to ring n-1 with the mirrored factors, carried
 // as y = D x so that the stored northern records apply unchanged with D w as the noise.
-// The ring order is uniform across the wave.
+// On a grid with no symmetry the southern walk reads its own records, stored mirrored the
+// same way, `south_off` elements after the northern ones.  The ring order is uniform
+// across the wave.
 template <typename T, int M, int NCH = 1, int P = ChainDepth<T, NCH>::value>
 __device__ __forceinline__ void run_chain(int n, int s, int even, int n_sets, int h, int m, int up0,
                                           uint32_t k0, uint32_t k1, const T* __restrict__ fm,
-                                          size_t set_stride, T* __restrict__ g, size_t row)
+                                          size_t set_stride, T* __restrict__ g, size_t row, size_t south_off = 0)
 {
     T sc[NCH], x0[NCH], x1[NCH];
     chain_scales<T, NCH>(m, (uint32_t)up0, sc);
@@ -387,7 +389,7 @@ __device__ __forceinline__ void run_chain(int n, int s, int even, int n_sets, in
                                             n_sets, g, row, x0, x1);
     else
         walk_hemisphere<T, M, P, false, NCH>(s, even, even ? s + 2 : s + 1, n - 1, m, (uint32_t)up0, k0, k1, sc,
-                                             fm, set_stride, n_sets, g, row, x0, x1);
+                                             fm + south_off, set_stride, n_sets, g, row, x0, x1);
 }
 
 // Zero NCH adjacent slots of one hemisphere (modes above m_top, the imaginary part of g_0).
@@ -661,7 +663,7 @@ __device__ __forceinline__ void walk_gen(int s, int even, int r_first, int r_las
 template <typename T, int M>
 __device__ __forceinline__ void run_chain_gen(int n, int s, int even, int n_sets, int h, int m, int part, uint32_t k0,
                                               uint32_t k1, const T* __restrict__ fm, size_t set_stride,
-                                              T* __restrict__ g, size_t row)
+                                              T* __restrict__ g, size_t row, size_t south_off = 0)
 {
     constexpr int G = GenGroup<M>::G;
     const uint32_t um = (uint32_t)m, up = (uint32_t)part;
@@ -707,13 +709,13 @@ __device__ __forceinline__ void run_chain_gen(int n, int s, int even, int n_sets
             for (int lo = even ? s + 2 : s + 1; lo <= n - 1;) {
                 const int base = (lo / G) * G;
                 const int hi = base + G - 1 < n - 1 ? base + G - 1 : n - 1;
-                step_group_gen<T, M, false>(base, lo, hi, s, even, n_sets, um, up, k0, k1, sc, fm, set_stride, g, row,
-                                            x);
+                step_group_gen<T, M, false>(base, lo, hi, s, even, n_sets, um, up, k0, k1, sc, fm + south_off,
+                                            set_stride, g, row, x);
                 lo = base + G;
             }
         } else {
-            walk_gen<T, M, P, false>(s, even, even ? s + 2 : s + 1, n - 1, um, up, k0, k1, sc, fm, set_stride, n_sets,
-                                     g, row, x);
+            walk_gen<T, M, P, false>(s, even, even ? s + 2 : s + 1, n - 1, um, up, k0, k1, sc, fm + south_off,
+                                     set_stride, n_sets, g, row, x);
         }
     }
 }

@@ -13,6 +13,7 @@ struct RecArgs {
     int n_wg;          // m-tiles * n_fg workgroups with work
     int per_xcd;       // launched workgroups / 8
     uint32_t seed_lo, seed_hi;
+    size_t south_off;  // elements to the southern walk's own factor table (0: mirrored)
 };
 
 // Chains per lane (NCH): 2 runs both parts of a mode in one lane (the two chains share
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(256) void recursion_kernel(RecArgs a, const T* __re
     const uint64_t key = (((uint64_t)a.seed_hi << 32) | a.seed_lo) + (uint64_t)f;
     run_chain<T, M, NCH>(a.n_theta, a.s, a.even, a.n_sets, h, m, part, (uint32_t)key, (uint32_t)(key >> 32),
                          fac + (size_t)m * factor_stride(M), (size_t)a.m_rows * factor_stride(M), g,
-                         (size_t)a.n_phi);
+                         (size_t)a.n_phi, a.south_off);
 }
 
 // Markov orders 3 and 4: one lane per (field, hemisphere, mode, part), laid out as the
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(256) void recursion_gen_kernel(RecArgs a, const T* 
     const uint64_t key = (((uint64_t)a.seed_hi << 32) | a.seed_lo) + (uint64_t)f;
     run_chain_gen<T, M>(a.n_theta, a.s, a.even, a.n_sets, h, m, part, (uint32_t)key, (uint32_t)(key >> 32),
                         fac + (size_t)m * factor_stride(M), (size_t)a.m_rows * factor_stride(M), g,
-                        (size_t)a.n_phi);
+                        (size_t)a.n_phi, a.south_off);
 }
 
 // ------------------------------------------------------------------ affine scan
@@ -103,6 +104,7 @@ struct ScanArgs {
     int n_fh, n_wg, per_xcd;
     int fine_per, fine;    // fine blocks per ring block; fine blocks in the plan
     uint32_t seed_lo, seed_hi;
+    size_t south_off, phi_south_off;   // the southern walk's own tables (0: mirrored)
 };
 
 // Prefetch depth of a scan wave: a workgroup of B >= 8 waves leaves 2048 / B VGPRs per
@@ -138,6 +140,8 @@ __global__ __launch_bounds__(64 * B) void scan_kernel(ScanArgs a, const T* __res
     const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
     const int mm = active ? m : 0;
     const T* __restrict__ fm = fac + (size_t)mm * factor_stride(M);
+    const T* __restrict__ fw = fm + (h ? a.south_off : 0);   // the walk's records
+    const T* __restrict__ ph = phi + (h ? a.phi_south_off : 0);
     const size_t set_stride = (size_t)a.m_rows * factor_stride(M);
     T sc[NCH];
     chain_scales<T, NCH>(m, (uint32_t)part, sc);
@@ -158,17 +162,17 @@ __global__ __launch_bounds__(64 * B) void scan_kernel(ScanArgs a, const T* __res
         if (blk == 0) {
             chain_start<T, M, NCH>(a.s, a.even, h, um, up, k0, k1, sc, fm, set_stride, g, row, true, x0, x1);
             if (h == 0)
-                walk_hemisphere<T, M, P, true, NCH, true>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm,
+                walk_hemisphere<T, M, P, true, NCH, true>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fw,
                                                           set_stride, a.n_sets, g, row, x0, x1);
             else
-                walk_hemisphere<T, M, P, false, NCH, true>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm,
+                walk_hemisphere<T, M, P, false, NCH, true>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fw,
                                                            set_stride, a.n_sets, g, row, x0, x1);
         } else {
             if (h == 0)
-                walk_hemisphere<T, M, P, true, NCH, false>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm,
+                walk_hemisphere<T, M, P, true, NCH, false>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fw,
                                                            set_stride, a.n_sets, g, row, x0, x1);
             else
-                walk_hemisphere<T, M, P, false, NCH, false>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm,
+                walk_hemisphere<T, M, P, false, NCH, false>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fw,
                                                             set_stride, a.n_sets, g, row, x0, x1);
         }
     }
@@ -189,7 +193,7 @@ __global__ __launch_bounds__(64 * B) void scan_kernel(ScanArgs a, const T* __res
     }
     for (int k = 1; k < blk; ++k) {
         for (int i = k * a.fine_per; i < (k + 1) * a.fine_per; ++i) {
-            const T* __restrict__ p = phi + ((size_t)i * a.m_rows + mm) * (M * M);
+            const T* __restrict__ p = ph + ((size_t)i * a.m_rows + mm) * (M * M);
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 if (M == 1) {
@@ -215,10 +219,10 @@ __global__ __launch_bounds__(64 * B) void scan_kernel(ScanArgs a, const T* __res
         x1[c] = y1[c];
     }
     if (h == 0)
-        walk_hemisphere<T, M, P, true, NCH, true>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm, set_stride,
+        walk_hemisphere<T, M, P, true, NCH, true>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fw, set_stride,
                                                   a.n_sets, g, row, x0, x1);
     else
-        walk_hemisphere<T, M, P, false, NCH, true>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fm, set_stride,
+        walk_hemisphere<T, M, P, false, NCH, true>(a.s, a.even, r_first, r_last, mm, up, k0, k1, sc, fw, set_stride,
                                                    a.n_sets, g, row, x0, x1);
 }
 
@@ -312,8 +316,8 @@ hipError_t dispatch_c2r(int log2h, const T* tw, int m_top, int rows, T* data, co
 
 }  // namespace
 
-hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, uint64_t seed, int count,
-                            void* out, int nch, hipStream_t st)
+hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, size_t south_off, uint64_t seed,
+                            int count, void* out, int nch, hipStream_t st)
 {
     if (nch != 1 && (nch != 2 || fp64 || g.order > 2)) return hipErrorInvalidValue;
     RecArgs a;
@@ -332,6 +336,7 @@ hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, uint64
     a.per_xcd = (a.n_wg + 7) / 8;
     a.seed_lo = (uint32_t)seed;
     a.seed_hi = (uint32_t)(seed >> 32);
+    a.south_off = south_off;
     const dim3 grid((unsigned)(a.per_xcd * 8));
     if (g.order >= 3) {
         if (fp64) {
@@ -374,7 +379,8 @@ hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, uint64
     return hipGetLastError();
 }
 
-hipError_t launch_scan(const Geometry& g, int fp64, const void* fac, const void* phi, int fine_blocks,
+hipError_t launch_scan(const Geometry& g, int fp64, const void* fac, size_t south_off, const void* phi,
+                       size_t phi_south_off, int fine_blocks,
                        int blocks, uint64_t seed, int count, void* out, int nch, hipStream_t st)
 {
     if (blocks < 2 || blocks > scan_max_blocks(fp64) || (blocks & (blocks - 1)) || fine_blocks % blocks)
@@ -391,6 +397,8 @@ hipError_t launch_scan(const Geometry& g, int fp64, const void* fac, const void*
     a.n_fh = 2 * count;
     a.fine_per = fine_blocks / blocks;
     a.fine = fine_blocks;
+    a.south_off = south_off;
+    a.phi_south_off = phi_south_off;
     const int modes_per_wave = nch == 2 ? 64 : 32;
     const int n_mt = (g.m_rows + modes_per_wave - 1) / modes_per_wave;
     a.n_wg = n_mt * a.n_fh;

@@ -284,18 +284,24 @@ __device__ void start_gen(const double (&K)[M * M], double (&B)[M * M])
 // Legendre recurrence at its two rings a, b (Sec. 2 definition of L_lm), accumulates
 // J(a,a), J(b,b), J(b,a) (Lemma 2.1 and the cross covariances), and factorises.
 // zgrid: the ring values of an explicit grid (Alg. 1's grid argument), or null for the
-// ring centres.
+// ring centres.  south: the southern walk's own sets of a grid with no symmetry: set
+// j >= j0 is the step (s+j-1) -> (s+j), stored mirrored (D A D, D B D with
+// D = diag((-1)^p)) so that the walk applies it to y = D x as it applies the mirrored
+// northern sets; sets below j0 (start, crossing) as in the northern table.
 template <int M>
 __global__ __launch_bounds__(64) void factor_kernel(Geometry g, const double* __restrict__ C,
-                                                    const double* __restrict__ zgrid,
+                                                    const double* __restrict__ zgrid, int south,
                                                     double* __restrict__ f64,
                                                     float* __restrict__ f32)
 {
     const int j = blockIdx.x * 64 + threadIdx.x;
     const int m = blockIdx.y;
     if (j >= g.n_sets) return;
+    const bool mirror = south && j >= (g.even ? 2 : 1);
     int a, b;
-    if (j == 0) {
+    if (mirror) {
+        a = g.s + j - 1; b = g.s + j;
+    } else if (j == 0) {
         a = b = g.s;
     } else if (g.even) {
         if (j == 1) { a = g.s; b = g.s + 1; }
@@ -429,6 +435,11 @@ __global__ __launch_bounds__(64) void factor_kernel(Geometry g, const double* __
         double A[M * M] = {}, B[M * M];
         if (j == 0) start_gen<M>(KaaG, B);
         else factors_gen<M>(KaaG, KbbG, KbaG, A, B);
+        if (mirror) {
+#pragma unroll
+            for (int i = 0; i < M * M; ++i)
+                if (((i / M) + (i % M)) & 1) { A[i] = -A[i]; B[i] = -B[i]; }
+        }
         constexpr int E = factor_stride(M);
         double v[E];
 #pragma unroll
@@ -456,6 +467,11 @@ __global__ __launch_bounds__(64) void factor_kernel(Geometry g, const double* __
         double A[4] = {0, 0, 0, 0}, B[3];
         if (j == 0) start_m2(Kaa, B);
         else factors_m2(Kaa, Kbb, Kba, A, B);
+        if (mirror) {   // D A D, D B D: the off-diagonal entries change sign
+            A[1] = -A[1];
+            A[2] = -A[2];
+            B[1] = -B[1];
+        }
         const double v[8] = {A[0], A[1], A[2], A[3], B[0], B[1], B[2], 0.0};
 #pragma unroll
         for (int i = 0; i < 8; ++i) f64[base + i] = v[i];
@@ -524,15 +540,15 @@ hipError_t launch_spectrum(const double* kappa_dev, int n_kappa, const double* c
     return hipGetLastError();
 }
 
-hipError_t launch_factors(const Geometry& g, const double* C_dev, const double* z_dev, double* f64,
+hipError_t launch_factors(const Geometry& g, const double* C_dev, const double* z_dev, int south, double* f64,
                           float* f32, hipStream_t st)
 {
     dim3 grid((g.n_sets + 63) / 64, g.m_top + 1);
     switch (g.order) {
-        case 1: hipLaunchKernelGGL(factor_kernel<1>, grid, dim3(64), 0, st, g, C_dev, z_dev, f64, f32); break;
-        case 2: hipLaunchKernelGGL(factor_kernel<2>, grid, dim3(64), 0, st, g, C_dev, z_dev, f64, f32); break;
-        case 3: hipLaunchKernelGGL(factor_kernel<3>, grid, dim3(64), 0, st, g, C_dev, z_dev, f64, f32); break;
-        case 4: hipLaunchKernelGGL(factor_kernel<4>, grid, dim3(64), 0, st, g, C_dev, z_dev, f64, f32); break;
+        case 1: hipLaunchKernelGGL(factor_kernel<1>, grid, dim3(64), 0, st, g, C_dev, z_dev, south, f64, f32); break;
+        case 2: hipLaunchKernelGGL(factor_kernel<2>, grid, dim3(64), 0, st, g, C_dev, z_dev, south, f64, f32); break;
+        case 3: hipLaunchKernelGGL(factor_kernel<3>, grid, dim3(64), 0, st, g, C_dev, z_dev, south, f64, f32); break;
+        case 4: hipLaunchKernelGGL(factor_kernel<4>, grid, dim3(64), 0, st, g, C_dev, z_dev, south, f64, f32); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -58,7 +58,8 @@ inline Geometry make_geometry(int order, int n_theta, int n_phi, int ell_max)
 hipError_t launch_spectrum(const double* kappa_dev, int n_kappa, const double* c_explicit_dev,
                            int ell_max, double* C_dev, int* bad_dev, hipStream_t st);
 // z_dev: ring values of an explicit grid (device, n_theta doubles) or null for ring centres.
-hipError_t launch_factors(const Geometry& g, const double* C_dev, const double* z_dev, double* f64,
+// south: the southern walk's own sets of a grid with no symmetry, stored mirrored.
+hipError_t launch_factors(const Geometry& g, const double* C_dev, const double* z_dev, int south, double* f64,
                           float* f32, hipStream_t st);
 hipError_t launch_twiddles(int n_phi, double* tw64, float* tw32, hipStream_t st);
 // Phi per (fine ring block, m) for the affine scan, layout [block][m][M*M], m stride m_rows.
@@ -86,8 +87,10 @@ inline int scan_fine_blocks(const Geometry& g)
 
 // ---- sampling ----
 // nch: chains per lane, 1 (one part) or 2 (both parts of a mode; FP32 only).
-hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, uint64_t seed, int count,
-                            void* out, int nch, hipStream_t st);
+// south_off: elements from the northern factor table to the southern walk's own table
+// (0: the south mirrors the northern sets).
+hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, size_t south_off, uint64_t seed,
+                            int count, void* out, int nch, hipStream_t st);
 // exp(mu + sigma T) applied by the FFT as it stores T (the sample type's precision).
 struct LognormalMap {
     double mu, sigma;
@@ -96,8 +99,11 @@ hipError_t launch_c2r(const Geometry& g, int fp64, const void* tw, int count, vo
                       const LognormalMap* ln, hipStream_t st);
 // The chains of launch_recursion as an affine scan over `blocks` ring blocks per chain
 // (blocks >= 2 dividing fine_blocks; phi holds the plan's fine-block transitions).
-hipError_t launch_scan(const Geometry& g, int fp64, const void* fac, const void* phi, int fine_blocks,
-                       int blocks, uint64_t seed, int count, void* out, int nch, hipStream_t st);
+// south_off, phi_south_off: elements to the southern walk's own factor and transition
+// tables (0: mirrored).
+hipError_t launch_scan(const Geometry& g, int fp64, const void* fac, size_t south_off, const void* phi,
+                       size_t phi_south_off, int fine_blocks, int blocks, uint64_t seed, int count, void* out,
+                       int nch, hipStream_t st);
 
 }  // namespace smf
 
@@ -117,6 +123,10 @@ struct smf_plan {
     smf::BatchState* batch;   // non-null for a batch plan (see smf_setup_batch)
     int scan_fine;            // fine ring blocks with a stored transition (1: no scan)
     int scan_req;             // ring blocks asked for: 0 automatic, 1 never, else that many
-    double* phi64;            // [scan_fine][m_rows][M*M] block transitions
+    double* phi64;            // [scan_fine][m_rows][M*M] block transitions (twice for asym)
     float* phi32;
+    int asym;                 // 1: a grid with no symmetry, the south walks its own sets
+    size_t south_off;         // elements from the northern to the southern factor table
+    size_t phi_south_off;     // the same for the block transitions
+    double* zgrid;            // host copy of an explicit grid (null: ring centres)
 };

@@ -19,7 +19,7 @@ SMF_FP64, SMF_FP32 = 1, 2
 # every symbol include/smf.h declares
 EXPORTS = ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks",
            "smf_get_ring_blocks",
-           "smf_plan_dims", "smf_get_factors", "smf_set_factors",
+           "smf_plan_dims", "smf_get_factors", "smf_set_factors", "smf_plan_grid",
            "smf_destroy", "smf_error_string", "smf_setup_batch", "smf_batch_layout",
            "smf_sample_batch", "smf_autotune_batch")
 
@@ -66,6 +66,7 @@ def load():
     lib.smf_plan_dims.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     lib.smf_get_factors.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.smf_set_factors.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), vp]
+    lib.smf_plan_grid.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
     lib.smf_destroy.argtypes = [vp]
     lib.smf_error_string.argtypes = [i]
     lib.smf_error_string.restype = ctypes.c_char_p
@@ -76,7 +77,7 @@ def load():
     lib.smf_autotune_batch.argtypes = [vp, u64, vp, vp, ctypes.POINTER(ctypes.c_int)]
     for name in ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks", "smf_get_ring_blocks",
                  "smf_plan_dims",
-                 "smf_get_factors", "smf_set_factors", "smf_destroy", "smf_setup_batch", "smf_batch_layout",
+                 "smf_get_factors", "smf_set_factors", "smf_plan_grid", "smf_destroy", "smf_setup_batch", "smf_batch_layout",
                  "smf_sample_batch", "smf_autotune_batch"):
         getattr(lib, name).restype = i
     _lib = lib
@@ -168,6 +169,14 @@ def smf_plan_dims(plan):
 def smf_get_factors(plan, A, B):
     pd = ctypes.POINTER(ctypes.c_double)
     return load().smf_get_factors(plan, A.ctypes.data_as(pd), B.ctypes.data_as(pd))
+
+
+def smf_plan_grid(plan, n_theta):
+    """Returns (code, z values, symmetric flag)."""
+    z = np.zeros(n_theta)
+    sym = ctypes.c_int()
+    rc = load().smf_plan_grid(plan, z.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(sym))
+    return rc, z, bool(sym.value)
 
 
 def smf_set_factors(plan, A, B, stream=None):
@@ -304,6 +313,9 @@ class Plan:
         (self.order, self.n_theta, self.n_phi, self.ell_max, self.m_top, self.n_sets,
          self.start_ring, fl) = d
         self.precision = "fp64" if fl == SMF_FP64 else "fp32"
+        rc, self.z, self.symmetric = smf_plan_grid(h, self.n_theta)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_plan_grid")
 
     @property
     def handle(self):
@@ -371,9 +383,14 @@ class Plan:
             raise SmfError(rc, "smf_sample_modes")
         return out.view(count, self.n_theta, self.n_phi // 2, 2)
 
+    def _factor_shape(self):
+        sets = self.n_sets * (1 if self.symmetric else 2)
+        return (sets, self.m_top + 1, self.order, self.order)
+
     def factors(self):
-        """FP64 (A, B), each [n_sets, m_top+1, order, order]."""
-        shape = (self.n_sets, self.m_top + 1, self.order, self.order)
+        """FP64 (A, B), each [n_sets, m_top+1, order, order] (2 n_sets sets for a grid with no
+        symmetry: the northern ones, then the southern walk's in true coordinates)."""
+        shape = self._factor_shape()
         A = np.zeros(shape)
         B = np.zeros(shape)
         rc = smf_get_factors(self._h, A, B)
@@ -383,7 +400,7 @@ class Plan:
 
     def set_factors(self, A, B, stream=None):
         """Replace the plan's factors with (A, B) of the factors() layout (Alg. 2's inputs)."""
-        shape = (self.n_sets, self.m_top + 1, self.order, self.order)
+        shape = self._factor_shape()
         if np.shape(A) != shape or np.shape(B) != shape:
             raise ValueError(f"factors must have shape {shape}")
         rc = smf_set_factors(self._h, A, B, stream)

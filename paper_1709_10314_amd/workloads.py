@@ -81,10 +81,12 @@ def random_z(n, seed=0):
 
 
 def random_asym_z(n, seed=0):
-    """A grid with no symmetry: n values drawn uniformly in (-0.99, 0.99), descending
-    (PCG64(seed))."""
+    """A grid with no symmetry: ring centres jittered independently by up to a fifth of a
+    ring, z_i = cos(pi (i + 1/2 + u_i) / n), u_i uniform in (-0.2, 0.2) (PCG64(seed)), so
+    neighbouring rings stay at least 0.6 of a spacing apart."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    return np.sort(rng.uniform(-0.99, 0.99, n))[::-1].copy()
+    u = rng.uniform(-0.2, 0.2, n)
+    return np.cos(np.pi * (np.arange(n) + 0.5 + u) / n)
 
 
 def shifted_z(n, shift=0.3):

@@ -1,6 +1,7 @@
 """GPU parity on explicit ring grids (Alg. 1 takes the grid z as an input; symmetric grids
 store the northern half, the remark after Alg. 1): Gauss-Legendre nodes, HEALPix ring
-latitudes and random symmetric grids, even and odd ring counts, both orders.  Factors
+latitudes and random symmetric grids, even and odd ring counts, both orders; and grids with
+no symmetry (random and shifted ring centres), whose southern walk has its own factor sets.  Factors
 against the oracle's explicit-grid setup (by their action on the chain's law, as for the
 ring-centre grid), modes and fields against the oracle on the same Philox normals (FP64
 1e-10, FP32 1e-4 relative RMS per field, plain recursion and affine scan), the ring-centre
@@ -123,7 +124,6 @@ def test_setup_grid_rejects_bad_grids():
     z = oracle.grid(8)[1]
     bad = {
         "ascending": z[::-1].copy(),
-        "asymmetric": np.where(np.arange(8) == 7, -z[0] * 0.999, z),
         "touches the poles": np.linspace(1.0, -1.0, 8),
         "not monotone": np.r_[z[:4], -z[:4]],
         "nan": np.where(np.arange(8) == 2, np.nan, z),
@@ -141,3 +141,99 @@ def test_setup_grid_rejects_bad_grids():
     h = smf.ctypes.c_void_p()
     assert lib.smf_setup_grid(smf.ctypes.byref(spec), 8, None, 16, smf.SMF_FP64, None,
                               smf.ctypes.byref(h)) == smf.SMF_EINVAL
+
+
+# ---- grids with no symmetry: the south walks its own factor sets
+ASYM = [
+    ("asym-40", 2, 900.0, 64, 39),
+    ("asym-41", 1, 100.0, 64, 30),
+    ("shift-64", 2, 2500.0, 64, 63),
+    ("shift-65", 1, 400.0, 128, 64),
+    ("shift-130", 2, 700.0, 128, 129),
+]
+
+
+def _asym_grid(name):
+    from paper_1709_10314_amd import workloads as w
+
+    kind, n = name.rsplit("-", 1)
+    n = int(n)
+    return w.random_asym_z(n, seed=n) if kind == "asym" else w.shifted_z(n, 0.3)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ASYM, ids=lambda c: "%s-M%d-k%g-%d-l%d" % c)
+def test_asymmetric_grid_matches_oracle(case, precision):
+    """Modes and fields on a grid with no symmetry against the oracle's sampler with the
+    southern walk's own sets (true coordinates), plain recursion and affine scan; the plan
+    reports its grid and its asymmetry."""
+    name, order, kap, nphi, lmax = case
+    z = _asym_grid(name)
+    n = len(z)
+    count, seed = 2, 37
+    C = oracle.spectrum([kap] * order, lmax)
+    A, B, As, Bs = oracle.setup_asym(order, C, n, nphi, z)
+    To, go = oracle.sample(order, n, nphi, A, B, seed, count, south=(As, Bs))
+    plan = _plan(z, order, kap, nphi, lmax, precision)
+    assert not plan.symmetric and np.array_equal(plan.z, z)
+    mt = plan.m_top
+    for blocks in (1, 4):
+        plan.set_ring_blocks(blocks)
+        used = plan.ring_blocks(count)
+        g = plan.sample_modes(seed, count)
+        torch.cuda.synchronize()
+        g = g.double().cpu().numpy()
+        g = g[..., 0] + 1j * g[..., 1]
+        T = plan.sample(seed, count)
+        torch.cuda.synchronize()
+        T = T.double().cpu().numpy()
+        for f in range(count):
+            eg = rel_rms(np.stack([g[f, :, : mt + 1].real, g[f, :, : mt + 1].imag]),
+                         np.stack([go[f].real, go[f].imag]))
+            eT = rel_rms(T[f], To[f])
+            log(f"{case} {precision} blocks {used}: field {f} modes {eg:.3e} field {eT:.3e}")
+            assert eg <= TOL[precision] and eT <= TOL[precision]
+    plan.close()
+
+
+@pytest.mark.parametrize("case", ASYM[:3], ids=lambda c: "%s-M%d-k%g-%d-l%d" % c)
+def test_asymmetric_grid_factors_round_trip_and_oracle_factors(case):
+    """The plan's 2 n_sets factor sets (northern, then the southern walk's in true
+    coordinates) against the oracle's entry by entry where they are well determined, and
+    the sampler on the oracle's factors (smf_set_factors) against the oracle's samples."""
+    name, order, kap, nphi, lmax = case
+    z = _asym_grid(name)
+    n = len(z)
+    C = oracle.spectrum([kap] * order, lmax)
+    A, B, As, Bs = oracle.setup_asym(order, C, n, nphi, z)
+    plan = _plan(z, order, kap, nphi, lmax, "fp64")
+    Ag, Bg = plan.factors()
+    ns = plan.n_sets
+    assert Ag.shape[0] == 2 * ns
+    for Xg, Xo in ((Ag[:ns], A), (Bg[:ns], B), (Ag[ns:], As), (Bg[ns:], Bs)):
+        big = np.abs(Xo) > 1e-6 * np.abs(Xo).max()
+        e = float(np.max(np.abs(Xg - Xo)[big] / np.abs(Xo)[big]))
+        log(f"{case}: factor entries rel err {e:.2e}")
+        assert e < 1e-6
+    plan.set_factors(np.concatenate([A, As]), np.concatenate([B, Bs]))
+    T = plan.sample(3, 2)
+    torch.cuda.synchronize()
+    T = T.cpu().numpy()
+    plan.close()
+    To, _ = oracle.sample(order, n, nphi, A, B, 3, 2, south=(As, Bs))
+    e = max(rel_rms(T[f], To[f]) for f in range(2))
+    log(f"{case}: sampler on the oracle's factors {e:.3e}")
+    assert e <= 1e-12
+
+
+def test_symmetric_grid_reports_mirror():
+    from paper_1709_10314_amd import Plan, workloads
+
+    z = workloads.gauss_legendre_z(32)
+    p = Plan(2, 32, 64, 31, kappa=[100.0, 100.0], precision="fp64", z=z)
+    assert p.symmetric and np.array_equal(p.z, z) and p.factors()[0].shape[0] == p.n_sets
+    p.close()
+    q = Plan(2, 32, 64, 31, kappa=[100.0, 100.0], precision="fp64")
+    assert q.symmetric
+    np.testing.assert_allclose(q.z, oracle.grid(32)[1], rtol=0, atol=1e-15)
+    q.close()

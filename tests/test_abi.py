@@ -48,6 +48,13 @@ def test_error_strings_and_null_handling_without_gpu():
     assert lib.smf_batch_layout(None, None) == smf.SMF_EINVAL
     assert lib.smf_autotune_batch(None, 1, None, None, None) == smf.SMF_EINVAL
     assert lib.smf_setup_batch(0, None, None, None, smf.SMF_FP32, None, None) == smf.SMF_EINVAL
+    assert lib.smf_setup_grid(None, 8, None, 16, smf.SMF_FP64, None, None) == smf.SMF_EINVAL
+    assert lib.smf_sample_lognormal(None, 1, 1, 0.0, 1.0, None, None) == smf.SMF_EINVAL
+    assert lib.smf_transform(None, 1, None, None) == smf.SMF_EINVAL
+    assert lib.smf_set_factors(None, None, None, None) == smf.SMF_EINVAL
+    assert lib.smf_plan_grid(None, None, None) == smf.SMF_EINVAL
+    assert lib.smf_set_ring_blocks(None, 0) == smf.SMF_EINVAL
+    assert lib.smf_get_ring_blocks(None, 1, None) == smf.SMF_EINVAL
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):

@@ -139,7 +139,8 @@ int smf_transform(const smf_plan* plan, int count, void* data_dev, void* hip_str
  *           2, 4, 8 or 16: always, with that many blocks, capped at the plan's maximum (the
  *              largest power of two <= 16 leaving >= 8 ring steps per block, 1 when the
  *              walk has fewer than 16 steps) and at 8 for SMF_FP64 plans.
- * Plans of order 3 or 4 always run the plain recursion (their maximum is 1).
+ * Plans of order 3 or 4 run one part per lane and scan with at most 8 blocks; their
+ * automatic choice is the fewest blocks giving >= 4096 wavefronts, as for SMF_FP64.
  * The plan stores one transition per (fine block, m): 16 * (n_phi/2) * M*M values in FP64
  * (and FP32 for SMF_FP32 plans).
  * Errors: SMF_EINVAL (NULL, batch plan, blocks not 0, 1 or a power of two <= 16). */

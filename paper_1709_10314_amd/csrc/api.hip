@@ -182,8 +182,7 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
     if ((rc = bufs.alloc(&plan->tw64, (size_t)2 * n_phi))) goto fail;
     if ((rc = bufs.alloc(&plan->tw32, (size_t)2 * n_phi))) goto fail;
     if (smf::launch_twiddles(n_phi, plan->tw64, plan->tw32, st) != hipSuccess) { rc = SMF_EHIP; goto fail; }
-    // the affine scan serves orders 1 and 2 (the chain kernels of orders 3 and 4 run plain)
-    plan->scan_fine = (scan && g.order <= 2) ? smf::scan_fine_blocks(g) : 1;
+    plan->scan_fine = scan ? smf::scan_fine_blocks(g) : 1;
     if (plan->scan_fine > 1) {
         const size_t nphi1 = (size_t)plan->scan_fine * g.m_rows * g.order * g.order;
         const size_t nphi = nphi1 * (plan->asym ? 2 : 1);
@@ -250,16 +249,17 @@ struct CallShape {
 static CallShape call_shape(const smf_plan* plan, int count)
 {
     const bool fp64 = plan->flags == SMF_FP64;
-    const int cap = std::min(plan->scan_fine, smf::scan_max_blocks(fp64));
+    const bool high = plan->g.order > 2;   // orders 3, 4: one part per lane, scans of <= 8 blocks
+    const int cap = std::min(plan->scan_fine, smf::scan_max_blocks(fp64, plan->g.order));
     const long w = (long)count * 2 * ((plan->g.m_rows + 31) / 32);
     const int walk = plan->g.n_sets - (plan->g.even ? 2 : 1);
-    const int plain_nch = (!fp64 && plan->g.order <= 2 && w >= 2048) ? 2 : 1;
-    const int scan_nch = (!fp64 && w >= 512) ? 2 : 1;
+    const int plain_nch = (!fp64 && !high && w >= 2048) ? 2 : 1;
+    const int scan_nch = (!fp64 && !high && w >= 512) ? 2 : 1;
     if (cap < 2 || plan->scan_req == 1) return {1, plain_nch};
     if (plan->scan_req >= 2) return {std::min(plan->scan_req, cap), scan_nch};
     if (w >= 1024) return {1, plain_nch};
     int b;
-    if (fp64) {
+    if (fp64 || high) {
         b = 2;
         while (b < cap && w * b < 4096) b *= 2;
     } else {

@@ -491,8 +491,9 @@ __device__ __forceinline__ void ring_normals(const T (&nb)[4 * GenGroup<M>::NB],
 }
 
 // Rings [lo, hi] of the group at `base`, in walk order.  The group's records are loaded
-// before its Philox rounds, so their latency overlaps the rounds.
-template <typename T, int M, bool NORTH>
+// before its Philox rounds, so their latency overlaps the rounds.  STORE = false walks
+// without stores (only the end state is wanted).
+template <typename T, int M, bool NORTH, bool STORE = true>
 __device__ __forceinline__ void step_group_gen(int base, int lo, int hi, int s, int even, int n_sets, uint32_t um,
                                                uint32_t up, uint32_t k0, uint32_t k1, T sc,
                                                const T* __restrict__ fm, size_t set_stride, T* __restrict__ g,
@@ -514,7 +515,7 @@ __device__ __forceinline__ void step_group_gen(int base, int lo, int hi, int s, 
 #pragma unroll
             for (int q = 0; q < M; ++q) w[q] = (!NORTH && (q & 1)) ? -nb[t * M + q] : nb[t * M + q];
             chain_step_gen<T, M>(R[t], x, w);
-            g[(size_t)r * row] = x[0];
+            if constexpr (STORE) g[(size_t)r * row] = x[0];
         }
     }
 }
@@ -544,7 +545,7 @@ struct GenDepth {
 // Walks rings r_first..r_last (north: descending, south: ascending) as walk_hemisphere does
 // for orders 1 and 2: a cut first group stepped directly, full groups through a P-slot
 // record pipeline (slot q mod P, refilled with group q + P after use), a cut last group.
-template <typename T, int M, int P, bool NORTH>
+template <typename T, int M, int P, bool NORTH, bool STORE = true>
 __device__ __forceinline__ void walk_gen(int s, int even, int r_first, int r_last, uint32_t um, uint32_t up,
                                          uint32_t k0, uint32_t k1, T sc, const T* __restrict__ fm,
                                          size_t set_stride, int n_sets, T* __restrict__ g, size_t row, T (&x)[M])
@@ -556,7 +557,7 @@ __device__ __forceinline__ void walk_gen(int s, int even, int r_first, int r_las
         int top = r_first;
         const int base = (top / G) * G;
         if (top != base + G - 1 || base < r_last) {
-            step_group_gen<T, M, true>(base, base > r_last ? base : r_last, top, s, even, n_sets, um, up, k0, k1, sc,
+            step_group_gen<T, M, true, STORE>(base, base > r_last ? base : r_last, top, s, even, n_sets, um, up, k0, k1, sc,
                                        fm, set_stride, g, row, x);
             top = base - 1;
         }
@@ -566,7 +567,7 @@ __device__ __forceinline__ void walk_gen(int s, int even, int r_first, int r_las
         int lo = r_first;
         const int base = (lo / G) * G;
         if (lo != base || base + G - 1 > r_last) {
-            step_group_gen<T, M, false>(base, lo, base + G - 1 < r_last ? base + G - 1 : r_last, s, even, n_sets, um,
+            step_group_gen<T, M, false, STORE>(base, lo, base + G - 1 < r_last ? base + G - 1 : r_last, s, even, n_sets, um,
                                         up, k0, k1, sc, fm, set_stride, g, row, x);
             lo = base + G;
         }
@@ -615,7 +616,7 @@ __device__ __forceinline__ void walk_gen(int s, int even, int r_first, int r_las
 #pragma unroll
                     for (int c = 0; c < M; ++c) w[c] = (!NORTH && (c & 1)) ? -nbs[p][t * M + c] : nbs[p][t * M + c];
                     chain_step_gen<T, M>(buf[p][t], x, w);
-                    g[(size_t)(base + t) * row] = x[0];
+                    if constexpr (STORE) g[(size_t)(base + t) * row] = x[0];
                 }
                 const int nbase = NORTH ? base - P * G : base + P * G;
 #pragma unroll
@@ -638,7 +639,7 @@ __device__ __forceinline__ void walk_gen(int s, int even, int r_first, int r_las
 #pragma unroll
                     for (int c = 0; c < M; ++c) w[c] = (!NORTH && (c & 1)) ? -nb[t * M + c] : nb[t * M + c];
                     chain_step_gen<T, M>(buf[p][t], x, w);
-                    g[(size_t)(base + t) * row] = x[0];
+                    if constexpr (STORE) g[(size_t)(base + t) * row] = x[0];
                 }
             }
         }
@@ -647,13 +648,47 @@ __device__ __forceinline__ void walk_gen(int s, int even, int r_first, int r_las
         const int end = b0 - ng * G + G - 1;   // highest ring not yet produced
         if (end >= r_last) {
             const int base = (end / G) * G;
-            step_group_gen<T, M, true>(base, r_last, end, s, even, n_sets, um, up, k0, k1, sc, fm, set_stride, g, row,
+            step_group_gen<T, M, true, STORE>(base, r_last, end, s, even, n_sets, um, up, k0, k1, sc, fm, set_stride, g, row,
                                        x);
         }
     } else {
         const int lo = b0 + ng * G;
         if (lo <= r_last)
-            step_group_gen<T, M, false>(lo, lo, r_last, s, even, n_sets, um, up, k0, k1, sc, fm, set_stride, g, row, x);
+            step_group_gen<T, M, false, STORE>(lo, lo, r_last, s, even, n_sets, um, up, k0, k1, sc, fm, set_stride, g, row, x);
+    }
+}
+
+// The state the walk of an order M >= 3 chain starts from (as chain_start): the start draw
+// at ring s with set 0 (eq. (state_initial); A = 0), stored by the northern chain; for the
+// southern chain the crossing s -> s+1 (even n_theta, set 1, stored), then y = D x.
+template <typename T, int M>
+__device__ __forceinline__ void chain_start_gen(int s, int even, int h, uint32_t um, uint32_t up, uint32_t k0,
+                                                uint32_t k1, T sc, const T* __restrict__ fm, size_t set_stride,
+                                                T* __restrict__ g, size_t row, bool store, T (&x)[M])
+{
+    constexpr int G = GenGroup<M>::G;
+#pragma unroll
+    for (int p = 0; p < M; ++p) x[p] = T(0);
+    {
+        const int bs = (s / G) * G;
+        T nb[4 * GenGroup<M>::NB], w[M];
+        group_normals<T, M>(bs, um, up, k0, k1, sc, nb);
+        ring_normals<T, M, true>(nb, s - bs, w);
+        chain_step_gen<T, M>(load_rec_gen<T, M>(fm), x, w);
+        if (store && h == 0) g[(size_t)s * row] = x[0];
+    }
+    if (h == 1 && even) {
+        const int r = s + 1;
+        const int br = (r / G) * G;
+        T nb[4 * GenGroup<M>::NB], w[M];
+        group_normals<T, M>(br, um, up, k0, k1, sc, nb);
+        ring_normals<T, M, true>(nb, r - br, w);
+        chain_step_gen<T, M>(load_rec_gen<T, M>(fm + set_stride), x, w);
+        if (store) g[(size_t)r * row] = x[0];
+    }
+    if (h == 1) {
+#pragma unroll
+        for (int p = 1; p < M; p += 2) x[p] = -x[p];   // y = D x
     }
 }
 
@@ -669,27 +704,7 @@ __device__ __forceinline__ void run_chain_gen(int n, int s, int even, int n_sets
     const uint32_t um = (uint32_t)m, up = (uint32_t)part;
     const T sc = m == 0 ? T(1) : T(0.70710678118654752440);
     T x[M];
-#pragma unroll
-    for (int p = 0; p < M; ++p) x[p] = T(0);
-    {
-        // start, eq. (state_initial): x = B_eq w with set 0 (A = 0)
-        const int bs = (s / G) * G;
-        T nb[4 * GenGroup<M>::NB], w[M];
-        group_normals<T, M>(bs, um, up, k0, k1, sc, nb);
-        ring_normals<T, M, true>(nb, s - bs, w);
-        chain_step_gen<T, M>(load_rec_gen<T, M>(fm), x, w);
-        if (h == 0) g[(size_t)s * row] = x[0];
-    }
-    if (h == 1 && even) {
-        // crossing s -> s+1 with set 1, in the true coordinates
-        const int r = s + 1;
-        const int br = (r / G) * G;
-        T nb[4 * GenGroup<M>::NB], w[M];
-        group_normals<T, M>(br, um, up, k0, k1, sc, nb);
-        ring_normals<T, M, true>(nb, r - br, w);
-        chain_step_gen<T, M>(load_rec_gen<T, M>(fm + set_stride), x, w);
-        g[(size_t)r * row] = x[0];
-    }
+    chain_start_gen<T, M>(s, even, h, um, up, k0, k1, sc, fm, set_stride, g, row, true, x);
     constexpr int P = GenDepth<T, M>::value;
     if (h == 0) {
         if constexpr (P == 0) {
@@ -703,8 +718,6 @@ __device__ __forceinline__ void run_chain_gen(int n, int s, int even, int n_sets
             walk_gen<T, M, P, true>(s, even, s - 1, 0, um, up, k0, k1, sc, fm, set_stride, n_sets, g, row, x);
         }
     } else {
-#pragma unroll
-        for (int p = 1; p < M; p += 2) x[p] = -x[p];   // y = D x
         if constexpr (P == 0) {
             for (int lo = even ? s + 2 : s + 1; lo <= n - 1;) {
                 const int base = (lo / G) * G;

@@ -226,6 +226,115 @@ __global__ __launch_bounds__(64 * B) void scan_kernel(ScanArgs a, const T* __res
                                                    a.n_sets, g, row, x0, x1);
 }
 
+// The affine scan for orders 3 and 4: the layout of scan_kernel with one part per lane
+// (32 modes x 2 parts per wave, one wave per ring block), the general-order walk with one
+// group per stage, block end states of M components in LDS, and the fold through the M x M
+// block transitions.
+template <typename T, int M, int B>
+__global__ __launch_bounds__(64 * B) void scan_gen_kernel(ScanArgs a, const T* __restrict__ fac,
+                                                          const T* __restrict__ phi, T* __restrict__ out)
+{
+    __shared__ T ends[B * 64 * M];
+    const int bx = blockIdx.x;
+    const int L = (bx & 7) * a.per_xcd + (bx >> 3);
+    if (L >= a.n_wg) return;
+    const int mt = L / a.n_fh;
+    const int fh = L - mt * a.n_fh;
+    const int f = fh >> 1, h = fh & 1;
+    const int blk = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int m = mt * 32 + (lane >> 1);
+    const int part = lane & 1;
+    const bool in_range = m < a.m_rows;
+    const bool active = in_range && m <= a.m_top && !(m == 0 && part == 1);
+    const size_t row = (size_t)a.n_phi;
+    T* __restrict__ g = out + (size_t)f * a.n_theta * a.n_phi + 2 * (in_range ? m : 0) + part;
+    if (in_range && !active && blk == 0) zero_chain<T, 1>(a.n_theta, a.s, h, g, row);
+
+    const uint64_t key = (((uint64_t)a.seed_hi << 32) | a.seed_lo) + (uint64_t)f;
+    const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+    const int mm = active ? m : 0;
+    const T* __restrict__ fm = fac + (size_t)mm * factor_stride(M);
+    const T* __restrict__ fw = fm + (h ? a.south_off : 0);
+    const T* __restrict__ ph = phi + (h ? a.phi_south_off : 0);
+    const size_t set_stride = (size_t)a.m_rows * factor_stride(M);
+    const T sc = mm == 0 ? T(1) : T(0.70710678118654752440);
+    const uint32_t um = (uint32_t)mm, up = (uint32_t)part;
+    const int j0 = a.even ? 2 : 1;
+    const long walk = a.n_sets - j0;
+    const int jb = j0 + (int)(walk * (blk * a.fine_per) / a.fine);
+    const int je = j0 + (int)(walk * ((blk + 1) * a.fine_per) / a.fine);
+    const int r_first = h == 0 ? a.s - jb + a.even : a.s + jb;
+    const int r_last = h == 0 ? a.s - (je - 1) + a.even : a.s + (je - 1);
+
+    // pass 1: block 0 from the start state (final, stored); the others from zero
+    T x[M];
+#pragma unroll
+    for (int p = 0; p < M; ++p) x[p] = T(0);
+    if (active) {
+        if (blk == 0) {
+            chain_start_gen<T, M>(a.s, a.even, h, um, up, k0, k1, sc, fm, set_stride, g, row, true, x);
+            if (h == 0)
+                walk_gen<T, M, 1, true, true>(a.s, a.even, r_first, r_last, um, up, k0, k1, sc, fw, set_stride,
+                                              a.n_sets, g, row, x);
+            else
+                walk_gen<T, M, 1, false, true>(a.s, a.even, r_first, r_last, um, up, k0, k1, sc, fw, set_stride,
+                                               a.n_sets, g, row, x);
+        } else {
+            if (h == 0)
+                walk_gen<T, M, 1, true, false>(a.s, a.even, r_first, r_last, um, up, k0, k1, sc, fw, set_stride,
+                                               a.n_sets, g, row, x);
+            else
+                walk_gen<T, M, 1, false, false>(a.s, a.even, r_first, r_last, um, up, k0, k1, sc, fw, set_stride,
+                                                a.n_sets, g, row, x);
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < M; ++p) ends[(blk * 64 + lane) * M + p] = x[p];
+    __syncthreads();
+    if (blk == 0 || !active) return;
+
+    // fold: the start of this block
+    T y[M];
+#pragma unroll
+    for (int p = 0; p < M; ++p) y[p] = ends[lane * M + p];
+    for (int k = 1; k < blk; ++k) {
+        for (int i = k * a.fine_per; i < (k + 1) * a.fine_per; ++i) {
+            const T* __restrict__ q = ph + ((size_t)i * a.m_rows + mm) * (M * M);
+            T t[M];
+#pragma unroll
+            for (int p = 0; p < M; ++p) {
+                T acc = q[p * M + M - 1] * y[M - 1];
+#pragma unroll
+                for (int c = M - 2; c >= 0; --c) acc = fma(q[p * M + c], y[c], acc);
+                t[p] = acc;
+            }
+#pragma unroll
+            for (int p = 0; p < M; ++p) y[p] = t[p];
+        }
+#pragma unroll
+        for (int p = 0; p < M; ++p) y[p] += ends[(k * 64 + lane) * M + p];
+    }
+    // pass 2: this block again from its true start, with stores
+    if (h == 0)
+        walk_gen<T, M, 1, true, true>(a.s, a.even, r_first, r_last, um, up, k0, k1, sc, fw, set_stride, a.n_sets, g,
+                                      row, y);
+    else
+        walk_gen<T, M, 1, false, true>(a.s, a.even, r_first, r_last, um, up, k0, k1, sc, fw, set_stride, a.n_sets,
+                                       g, row, y);
+}
+
+template <typename T, int M>
+void launch_scan_gen_t(const ScanArgs& a, int blocks, const T* fac, const T* phi, T* out, hipStream_t st)
+{
+    const dim3 grid((unsigned)(a.per_xcd * 8));
+    switch (blocks) {
+        case 2: hipLaunchKernelGGL((scan_gen_kernel<T, M, 2>), grid, dim3(128), 0, st, a, fac, phi, out); break;
+        case 4: hipLaunchKernelGGL((scan_gen_kernel<T, M, 4>), grid, dim3(256), 0, st, a, fac, phi, out); break;
+        default: hipLaunchKernelGGL((scan_gen_kernel<T, M, 8>), grid, dim3(512), 0, st, a, fac, phi, out); break;
+    }
+}
+
 template <typename T, int M, int NCH>
 void launch_scan_t(const ScanArgs& a, int blocks, const T* fac, const T* phi, T* out, hipStream_t st)
 {
@@ -383,7 +492,7 @@ hipError_t launch_scan(const Geometry& g, int fp64, const void* fac, size_t sout
                        size_t phi_south_off, int fine_blocks,
                        int blocks, uint64_t seed, int count, void* out, int nch, hipStream_t st)
 {
-    if (blocks < 2 || blocks > scan_max_blocks(fp64) || (blocks & (blocks - 1)) || fine_blocks % blocks)
+    if (blocks < 2 || blocks > scan_max_blocks(fp64, g.order) || (blocks & (blocks - 1)) || fine_blocks % blocks)
         return hipErrorInvalidValue;
     if (nch != 1 && (nch != 2 || fp64 || g.order > 2)) return hipErrorInvalidValue;
     ScanArgs a;
@@ -405,7 +514,15 @@ hipError_t launch_scan(const Geometry& g, int fp64, const void* fac, size_t sout
     a.per_xcd = (a.n_wg + 7) / 8;
     a.seed_lo = (uint32_t)seed;
     a.seed_hi = (uint32_t)(seed >> 32);
-    if (fp64) {
+    if (g.order >= 3) {
+        if (fp64) {
+            if (g.order == 3) launch_scan_gen_t<double, 3>(a, blocks, (const double*)fac, (const double*)phi, (double*)out, st);
+            else launch_scan_gen_t<double, 4>(a, blocks, (const double*)fac, (const double*)phi, (double*)out, st);
+        } else {
+            if (g.order == 3) launch_scan_gen_t<float, 3>(a, blocks, (const float*)fac, (const float*)phi, (float*)out, st);
+            else launch_scan_gen_t<float, 4>(a, blocks, (const float*)fac, (const float*)phi, (float*)out, st);
+        }
+    } else if (fp64) {
         if (g.order == 1) launch_scan_t<double, 1, 1>(a, blocks, (const double*)fac, (const double*)phi, (double*)out, st);
         else launch_scan_t<double, 2, 1>(a, blocks, (const double*)fac, (const double*)phi, (double*)out, st);
     } else if (nch == 2) {

@@ -496,18 +496,32 @@ __global__ __launch_bounds__(64) void phi_kernel(Geometry g, const double* __res
     const int j0 = g.even ? 2 : 1;
     const long walk = g.n_sets - j0;
     const int jb = j0 + (int)(walk * b / blocks), je = j0 + (int)(walk * (b + 1) / blocks);
-    constexpr int E = M == 1 ? 2 : 8;
+    constexpr int E = factor_stride(M);
     double p[M * M];
 #pragma unroll
     for (int i = 0; i < M * M; ++i) p[i] = (i % (M + 1) == 0) ? 1.0 : 0.0;
     for (int j = jb; j < je; ++j) {
         const double* r = f64 + ((size_t)j * g.m_rows + m) * E;
-        if (M == 1) {
+        if constexpr (M == 1) {
             p[0] = r[0] * p[0];
-        } else {
+        } else if constexpr (M == 2) {
             const double q00 = r[0] * p[0] + r[1] * p[2], q01 = r[0] * p[1] + r[1] * p[3];
             const double q10 = r[2] * p[0] + r[3] * p[2], q11 = r[2] * p[1] + r[3] * p[3];
             p[0] = q00; p[1] = q01; p[2] = q10; p[3] = q11;
+        } else {
+            // A row-major in the record's first M*M values
+            double q[M * M];
+#pragma unroll
+            for (int a = 0; a < M; ++a)
+#pragma unroll
+                for (int c = 0; c < M; ++c) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int k = 0; k < M; ++k) acc += r[a * M + k] * p[k * M + c];
+                    q[a * M + c] = acc;
+                }
+#pragma unroll
+            for (int i = 0; i < M * M; ++i) p[i] = q[i];
         }
     }
     const size_t o = ((size_t)b * g.m_rows + m) * (M * M);
@@ -524,10 +538,13 @@ hipError_t launch_phi(const Geometry& g, const double* f64, int blocks, double* 
                       hipStream_t st)
 {
     dim3 grid((g.m_top + 64) / 64, blocks);
-    if (g.order == 1)
-        hipLaunchKernelGGL(phi_kernel<1>, grid, dim3(64), 0, st, g, f64, blocks, phi64, phi32);
-    else
-        hipLaunchKernelGGL(phi_kernel<2>, grid, dim3(64), 0, st, g, f64, blocks, phi64, phi32);
+    switch (g.order) {
+        case 1: hipLaunchKernelGGL(phi_kernel<1>, grid, dim3(64), 0, st, g, f64, blocks, phi64, phi32); break;
+        case 2: hipLaunchKernelGGL(phi_kernel<2>, grid, dim3(64), 0, st, g, f64, blocks, phi64, phi32); break;
+        case 3: hipLaunchKernelGGL(phi_kernel<3>, grid, dim3(64), 0, st, g, f64, blocks, phi64, phi32); break;
+        case 4: hipLaunchKernelGGL(phi_kernel<4>, grid, dim3(64), 0, st, g, f64, blocks, phi64, phi32); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -75,8 +75,8 @@ constexpr int kScanMaxBlocks = 16;
 constexpr int kScanMinSets = 8;
 constexpr int kScanAutoMinSets = 32;   // the automatic choice keeps blocks this long
 // a scanned call runs one wave per ring block in a workgroup: 16 (FP32) or 8 (FP64, whose
-// walk needs up to 256 VGPRs) waves at most
-inline int scan_max_blocks(int fp64) { return fp64 ? 8 : 16; }
+// walk needs up to 256 VGPRs) waves at most, and 8 at orders 3 and 4
+inline int scan_max_blocks(int fp64, int order = 2) { return (fp64 || order > 2) ? 8 : 16; }
 inline int scan_fine_blocks(const Geometry& g)
 {
     const int walk = g.n_sets - (g.even ? 2 : 1);

@@ -106,22 +106,28 @@ def test_high_order_sampler_on_oracle_factors(case, precision):
     plan.set_factors(A, B)
     Ag, Bg = plan.factors()
     assert np.array_equal(Ag[1:], A[1:]) and np.array_equal(np.tril(Bg), np.tril(B))
-    g = plan.sample_modes(seed, count)
-    torch.cuda.synchronize()
-    g = g.double().cpu().numpy()
-    g = g[..., 0] + 1j * g[..., 1]
-    T = plan.sample(seed, count)
-    torch.cuda.synchronize()
-    T = T.double().cpu().numpy()
     mt = plan.m_top
+    # the plain walk, then the affine scan (block transitions rebuilt from the given factors;
+    # the fold adds the rounding of a product of up to ~n/2 transitions)
+    bars = {("fp64", 1): 1e-12, ("fp64", 2): 1e-10, ("fp32", 1): 1e-4, ("fp32", 2): 1e-4}
+    for blocks in (1, 4, 8):
+        plan.set_ring_blocks(blocks)
+        used = plan.ring_blocks(count)
+        g = plan.sample_modes(seed, count)
+        torch.cuda.synchronize()
+        g = g.double().cpu().numpy()
+        g = g[..., 0] + 1j * g[..., 1]
+        T = plan.sample(seed, count)
+        torch.cuda.synchronize()
+        T = T.double().cpu().numpy()
+        bar = bars[(precision, 1 if used == 1 else 2)]
+        for f in range(count):
+            eg = rel_rms(np.stack([g[f, :, : mt + 1].real, g[f, :, : mt + 1].imag]),
+                         np.stack([go[f].real, go[f].imag]))
+            eT = rel_rms(T[f], To[f])
+            log(f"{case} {precision} on oracle factors, blocks {used}: field {f} modes {eg:.3e} field {eT:.3e}")
+            assert eg <= bar and eT <= bar
     plan.close()
-    bar = {"fp64": 1e-12, "fp32": 1e-4}[precision]
-    for f in range(count):
-        eg = rel_rms(np.stack([g[f, :, : mt + 1].real, g[f, :, : mt + 1].imag]),
-                     np.stack([go[f].real, go[f].imag]))
-        eT = rel_rms(T[f], To[f])
-        log(f"{case} {precision} on oracle factors: field {f} modes {eg:.3e} field {eT:.3e}")
-        assert eg <= bar and eT <= bar
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "M%d-k%g-%dx%d-l%d" % c)
@@ -159,7 +165,7 @@ def test_high_order_fp32_modes_and_field_match_oracle(case):
     order, kap, n, nphi, lmax = case
     count, seed = 3, 31
     plan = _plan(order, kap, n, nphi, lmax, precision)
-    assert plan.ring_blocks(count) == 1
+    log(f"{case} {precision}: ring blocks {plan.ring_blocks(count)}")
     g = plan.sample_modes(seed, count)
     torch.cuda.synchronize()
     g = g.double().cpu().numpy()
@@ -203,25 +209,36 @@ def test_order3_on_gauss_legendre_grid(precision):
 
 
 def test_high_order_layout_and_limits():
-    """Orders 3 and 4 always run the plain recursion, one part per lane, at any count
-    (ring_blocks reports 1 even when forced); the batched form rejects them."""
+    """Orders 3 and 4 run one part per lane; the automatic layout scans with the fewest
+    blocks (at most 8) giving 4096 waves below 1024 waves of plain recursion, and plain
+    above; forced layouts cap at 8 blocks; a field's result depends on the blocks only
+    (the same field in a 1-field and a 32-field call with 8 blocks is bit identical); the
+    batched form rejects these orders."""
     from paper_1709_10314_amd import BatchPlan, SmfError
 
     plan = _plan(3, 400.0, 1024, 2048, 1023, "fp32")
+    assert [plan.ring_blocks(c) for c in (1, 8, 16, 64)] == [8, 8, 1, 1]
+    plan.set_ring_blocks(16)
+    assert [plan.ring_blocks(c) for c in (1, 64)] == [8, 8]
     plan.set_ring_blocks(8)
-    assert [plan.ring_blocks(c) for c in (1, 8, 64)] == [1, 1, 1]
     a = plan.sample(7, 1)[0].clone()
     b = plan.sample(7, 32)[0]
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+    plan.set_ring_blocks(1)
+    c = plan.sample(7, 1)[0]
+    torch.cuda.synchronize()
+    e = rel_rms(c.double().cpu().numpy(), a.double().cpu().numpy())
+    log(f"1024x2048 M3 fp32: 8-block scan vs plain {e:.3e}")
+    assert e <= 2e-5
     plan.close()
     with pytest.raises(SmfError):
         BatchPlan([dict(n_theta=64, n_phi=128, order=3, kappa=[10.0] * 3, ell_max=63)])
 
 
 def test_order3_large_single_field_modes():
-    """One 1024 x 2048 order-3 field in FP32: sampled modes against the oracle's chains of
-    those modes."""
+    """One 1024 x 2048 order-3 field in FP32 (the automatic layout scans it with 8 blocks):
+    sampled modes against the oracle's chains of those modes."""
     n, nphi, lmax, kap = 1024, 2048, 1023, 2500.0
     plan = _plan(3, kap, n, nphi, lmax, "fp32")
     g = plan.sample_modes(3, 2)

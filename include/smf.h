@@ -36,8 +36,8 @@ typedef struct smf_plan smf_plan;
 /* Angular power spectrum, eq. (Cl): C_l = prod_{i<n_kappa} (kappa_i + l(l+1))^-1 for
  * l = 0..ell_max, and C_l = 0 above ell_max.  If c_ell is non-NULL it is used instead
  * (ell_max + 1 values, host memory).  `order` is the Markov order M, i.e. the state
- * dimension (value and first M-1 z-derivatives, Sec. 2 Markov property); M in {1, 2, 3, 4}
- * (the batched form takes 1 and 2).  For the rational form M is normally n_kappa. */
+ * dimension (value and first M-1 z-derivatives, Sec. 2 Markov property); M in {1, 2, 3, 4}.
+ * For the rational form M is normally n_kappa. */
 typedef struct {
     int order;
     int n_kappa;
@@ -182,7 +182,7 @@ int smf_set_factors(smf_plan* plan, const double* A_host, const double* B_host, 
 
 /* ---- batched form: many fields of uneven shape, spectrum and order per call ---- */
 
-/* One FP32 plan per field (Alg. 1 for each, as smf_setup with SMF_FP32; orders 1 and 2) plus flat work
+/* One FP32 plan per field (Alg. 1 for each, as smf_setup with SMF_FP32) plus flat work
  * lists: chain items (field, group of m-tiles), longest chains first, and one FFT item
  * per ring of every field.  specs, n_theta, n_phi: host arrays of n entries (n in
  * [1, 65535]); n_phi[i] a power of two in [4, 4096]; flags must be SMF_FP32.

@@ -532,7 +532,7 @@ int smf_setup_batch(int n, const smf_spectrum* specs, const int* n_theta, const 
     *out = nullptr;
     if (n < 1 || n > 65535 || !specs || !n_theta || !n_phi || flags != SMF_FP32) return SMF_EINVAL;
     for (int i = 0; i < n; ++i)
-        if (n_phi[i] > 4096 || n_theta[i] > 65535 || specs[i].order > 2) return SMF_EINVAL;
+        if (n_phi[i] > 4096 || n_theta[i] > 65535) return SMF_EINVAL;
     hipStream_t st = (hipStream_t)hip_stream;
     smf::BatchState* b = new smf::BatchState();
     b->n = n;

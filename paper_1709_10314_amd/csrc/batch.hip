@@ -1,4 +1,4 @@
-// Batched sampling of many fields of uneven shape, spectrum and order (FP32) in two
+// Batched sampling of many fields of uneven shape, spectrum and order 1..4 (FP32) in two
 // launches: one over the chain items of every field (Creasey & Lang, Alg. 2; eqs.
 // (state_initial), (state_space)), then one over every ring of every field (the inverse
 // FFT, Alg. 2 last step).  Both grids are flat work lists built at setup: a workgroup
@@ -61,12 +61,24 @@ __global__ __launch_bounds__(kMaxChainThreads) void batch_chain_kernel(BatchArgs
     const uint64_t key = a.seed + (uint64_t)F.seed_off;
     const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
     const size_t stride = (size_t)F.m_rows * factor_stride(F.order);
-    if (F.order == 1)
-        run_chain<float, 1>(F.n_theta, F.s, F.even, F.n_sets, h, m, part, k0, k1,
-                            F.fac + (size_t)m * factor_stride(1), stride, g, (size_t)F.n_phi);
-    else
-        run_chain<float, 2>(F.n_theta, F.s, F.even, F.n_sets, h, m, part, k0, k1,
-                            F.fac + (size_t)m * factor_stride(2), stride, g, (size_t)F.n_phi);
+    switch (F.order) {
+        case 1:
+            run_chain<float, 1>(F.n_theta, F.s, F.even, F.n_sets, h, m, part, k0, k1,
+                                F.fac + (size_t)m * factor_stride(1), stride, g, (size_t)F.n_phi);
+            break;
+        case 2:
+            run_chain<float, 2>(F.n_theta, F.s, F.even, F.n_sets, h, m, part, k0, k1,
+                                F.fac + (size_t)m * factor_stride(2), stride, g, (size_t)F.n_phi);
+            break;
+        case 3:
+            run_chain_gen<float, 3>(F.n_theta, F.s, F.even, F.n_sets, h, m, part, k0, k1,
+                                    F.fac + (size_t)m * factor_stride(3), stride, g, (size_t)F.n_phi);
+            break;
+        default:
+            run_chain_gen<float, 4>(F.n_theta, F.s, F.even, F.n_sets, h, m, part, k0, k1,
+                                    F.fac + (size_t)m * factor_stride(4), stride, g, (size_t)F.n_phi);
+            break;
+    }
 }
 
 // One workgroup per ring of every field.

@@ -3,8 +3,8 @@ Sec. 2 Markov property; the higher derivatives from the associated Legendre equa
 against the FP64 oracle on the same Philox normals: factors by their action on the
 chain's law (as for orders 1 and 2), modes and fields at the parity bars (FP64 1e-10, FP32
 1e-4 relative RMS per field) for even and odd ring counts, truncated and band-limited
-modes and an explicit grid; the layout rules (no scan, one part per lane) and the batch's
-order limit.
+modes and an explicit grid; the layout rules (one part per lane, scans of at most 8 ring
+blocks) and the batched form at every order.
 
 At these orders the value and its derivatives are strongly correlated at a ring and the
 factorisation is ill-conditioned: perturbing J by a few parts in 1e16 (FP64 rounding) moves
@@ -212,10 +212,7 @@ def test_high_order_layout_and_limits():
     """Orders 3 and 4 run one part per lane; the automatic layout scans with the fewest
     blocks (at most 8) giving 4096 waves below 1024 waves of plain recursion, and plain
     above; forced layouts cap at 8 blocks; a field's result depends on the blocks only
-    (the same field in a 1-field and a 32-field call with 8 blocks is bit identical); the
-    batched form rejects these orders."""
-    from paper_1709_10314_amd import BatchPlan, SmfError
-
+    (the same field in a 1-field and a 32-field call with 8 blocks is bit identical)."""
     plan = _plan(3, 400.0, 1024, 2048, 1023, "fp32")
     assert [plan.ring_blocks(c) for c in (1, 8, 16, 64)] == [8, 8, 1, 1]
     plan.set_ring_blocks(16)
@@ -232,8 +229,37 @@ def test_high_order_layout_and_limits():
     log(f"1024x2048 M3 fp32: 8-block scan vs plain {e:.3e}")
     assert e <= 2e-5
     plan.close()
-    with pytest.raises(SmfError):
-        BatchPlan([dict(n_theta=64, n_phi=128, order=3, kappa=[10.0] * 3, ell_max=63)])
+
+
+def test_batch_with_orders_1_to_4():
+    """The batched form on fields of every order: each field against the same field sampled
+    alone with the plain recursion (the same chain arithmetic) and against the oracle."""
+    from paper_1709_10314_amd import BatchPlan
+
+    fields = [dict(n_theta=64, n_phi=128, order=3, kappa=[400.0] * 3, ell_max=63),
+              dict(n_theta=33, n_phi=64, order=4, kappa=[900.0] * 4, ell_max=31),
+              dict(n_theta=130, n_phi=256, order=2, kappa=[700.0] * 2, ell_max=129),
+              dict(n_theta=65, n_phi=128, order=1, kappa=[100.0], ell_max=64),
+              dict(n_theta=256, n_phi=512, order=3, kappa=[50.0] * 3, ell_max=255)]
+    seed = 11
+    bp = BatchPlan(fields)
+    out = bp.sample(seed)
+    torch.cuda.synchronize()
+    for i, f in enumerate(fields):
+        Tb = bp.field(out, i).double().cpu().numpy()
+        plan = _plan(f["order"], f["kappa"][0], f["n_theta"], f["n_phi"], f["ell_max"], "fp32")
+        plan.set_ring_blocks(1)
+        Ts = plan.sample(seed + i, 1)[0]
+        torch.cuda.synchronize()
+        Ts = Ts.double().cpu().numpy()
+        plan.close()
+        C = oracle.spectrum(f["kappa"], f["ell_max"])
+        A, B = oracle.setup(f["order"], C, f["n_theta"], f["n_phi"])
+        To, _ = oracle.sample(f["order"], f["n_theta"], f["n_phi"], A, B, seed + i, 1)
+        es, eo = rel_rms(Tb, Ts), rel_rms(Tb, To[0])
+        log(f"batch field {i} (order {f['order']}): vs single plan {es:.2e}, vs oracle {eo:.2e}")
+        assert es <= 1e-6 and eo <= TOL["fp32"]
+    bp.close()
 
 
 def test_order3_large_single_field_modes():

@@ -83,6 +83,9 @@ def _load():
     lib.orc_setup_modes_z.argtypes = [_i, _i, _pd, _i, _pd, _i, _pi, _i, _pd, _pd]
     lib.orc_setup_modes_z.restype = _i
     lib.orc_setup_modes_asym.argtypes = [_i, _i, _pd, _i, _pd, _i, _pi, _i, _pd, _pd, _pd, _pd]
+    lib.orc_setup_modes_zb.argtypes = [_i, _i, _i, _pd, _i, _pd, _i, _pi, _i, _pd, _pd]
+    lib.orc_setup_modes_zb.restype = _i
+    lib.orc_jblock_zs_u.argtypes = [_i, _i, _pd, _d, _d, _d, _d, _pd]
     lib.orc_setup_modes_asym.restype = _i
     lib.orc_sample_modes_list_south.argtypes = [_i, _i, _pi, _i, _i, _pd, _pd, _pd, _pd, _u64, _i, _pd]
     lib.orc_sample_modes_list_south.restype = _i
@@ -201,10 +204,10 @@ def _zgrid(z, n_theta):
     return z
 
 
-def setup(order, C, n_theta, n_phi, sets=None, z=None):
+def setup(order, C, n_theta, n_phi, sets=None, z=None, basis="z"):
     """Alg. 1.  Returns (A, B), each [sets][m_top+1][order][order]; set 0 holds B_eq.
     z: optional ring values (north to south, symmetric about the equator); default the
-    ring centres."""
+    ring centres.  basis: "z" (value and z-derivatives) or "u" (order 2: (g, U g), Sec. 3)."""
     C = np.ascontiguousarray(C, dtype=np.float64)
     ell_max = len(C) - 1
     mt = m_top(ell_max, n_phi)
@@ -212,11 +215,27 @@ def setup(order, C, n_theta, n_phi, sets=None, z=None):
     A = np.zeros((ns, mt + 1, order, order))
     B = np.zeros((ns, mt + 1, order, order))
     zg = _zgrid(z, n_theta)
-    rc = _load().orc_setup_z(order, ell_max, _p(C), n_theta, None if zg is None else _p(zg), n_phi, ns,
-                             _p(A), _p(B))
+    if basis == "z":
+        rc = _load().orc_setup_z(order, ell_max, _p(C), n_theta, None if zg is None else _p(zg), n_phi, ns,
+                                 _p(A), _p(B))
+    else:
+        md = np.arange(mt + 1, dtype=np.int32)
+        rc = _load().orc_setup_modes_zb(order, {"u": 1}[basis], ell_max, _p(C), n_theta,
+                                        None if zg is None else _p(zg), ns,
+                                        md.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(md), _p(A), _p(B))
     if rc != 0:
         raise ValueError("orc_setup rejected its arguments")
     return A, B
+
+
+def jblock_u(m, ell_max, C, z1, z2):
+    """J^m(z1, z2) of order 2 in the basis (g, U g) of Sec. 3 (U L_lm through L_{l,m+1})."""
+    C = np.ascontiguousarray(C, dtype=np.float64)
+    s1 = math.sqrt((1.0 - z1) * (1.0 + z1))
+    s2 = math.sqrt((1.0 - z2) * (1.0 + z2))
+    J = np.zeros(4)
+    _load().orc_jblock_zs_u(m, ell_max, _p(C), float(z1), s1, float(z2), s2, _p(J))
+    return J.reshape(2, 2)
 
 
 def setup_modes(order, C, n_theta, modes, sets=None, z=None):

@@ -245,6 +245,48 @@ void orc_jblock_zs(int order, int m, int ell_max, const double* C, double z1, do
     free(buf);
 }
 
+/* ------------------------------------------------------------------------- */
+/* Order 2 in the basis (g, U g) of Sec. 3 (eq. (Jmatrix_more_efficient)).      */
+/* U_m f = -(1 - z^2)^{(m+1)/2} d/dz[(1 - z^2)^{-m/2} f] maps P^m to P^{m+1}     */
+/* (Sec. 3); for the normalised functions here (no Condon-Shortley sign) that   */
+/* reads U_m L_lm = -sqrt((l+m+1)(l-m)) L_{l,m+1}, which is what is summed       */
+/* (exactly zero at l = m, no cancellation near the poles).  The value          */
+/* component is unchanged, so the field's law is the same; the realisations     */
+/* differ from those of the z-derivative basis.                                */
+/* ------------------------------------------------------------------------- */
+void orc_jblock_zs_u(int m, int ell_max, const double* C, double z1, double s1, double z2, double s2, double* J)
+{
+    int n = ell_max - m + 1;
+    for (int i = 0; i < 4; ++i) J[i] = 0.0;
+    if (n <= 0) return;
+    double* L1 = (double*)calloc(4 * (size_t)n, sizeof(double));
+    double* U1 = L1 + n;
+    double* L2 = L1 + 2 * n;
+    double* U2 = L1 + 3 * n;
+    orc_legendre_zs(m, ell_max, z1, s1, L1, NULL);
+    orc_legendre_zs(m, ell_max, z2, s2, L2, NULL);
+    if (n > 1) {
+        /* L_{l,m+1} for l = m+1 .. ell_max into slots 1 .. n-1 */
+        orc_legendre_zs(m + 1, ell_max, z1, s1, U1 + 1, NULL);
+        orc_legendre_zs(m + 1, ell_max, z2, s2, U2 + 1, NULL);
+        for (int k = 1; k < n; ++k) {
+            const double l = m + k;
+            const double f = -sqrt((l + m + 1.0) * (l - m));
+            U1[k] *= f;
+            U2[k] *= f;
+        }
+    }
+    for (int p = 0; p < 2; ++p)
+        for (int q = 0; q < 2; ++q) {
+            const double* f1 = p ? U1 : L1;
+            const double* f2 = q ? U2 : L2;
+            double acc = 0.0;
+            for (int k = 0; k < n; ++k) acc += C[m + k] * f1[k] * f2[k];
+            J[p * 2 + q] = acc;
+        }
+    free(L1);
+}
+
 /* The same with z1 = cos(theta1), z2 = cos(theta2). */
 void orc_jblock(int order, int m, int ell_max, const double* C, double theta1, double theta2,
                 double* J)
@@ -409,8 +451,17 @@ static int grid_ok(const double* zgrid, int n_theta, int symmetric)
     return 1;
 }
 
+static void jblock_basis(int order, int basis, int m, int ell_max, const double* C, double z1, double s1, double z2,
+                         double s2, double* J)
+{
+    if (basis == 1)
+        orc_jblock_zs_u(m, ell_max, C, z1, s1, z2, s2, J);
+    else
+        orc_jblock_zs(order, m, ell_max, C, z1, s1, z2, s2, J);
+}
+
 static void setup_sets(int order, int ell_max, const double* C, int n_theta, const double* zgrid, int n_sets,
-                       const int* modes, int n_modes, int south, double* A, double* B)
+                       const int* modes, int n_modes, int south, int basis, double* A, double* B)
 {
     int MM = order * order;
     const int s = orc_start_ring(n_theta);
@@ -440,14 +491,14 @@ static void setup_sets(int order, int ell_max, const double* C, int n_theta, con
             double* Aj = A + ((size_t)j * n_modes + i) * MM;
             double* Bj = B + ((size_t)j * n_modes + i) * MM;
             if (j == 0) {
-                orc_jblock_zs(order, m, ell_max, C, za, sa, za, sa, Kaa);
+                jblock_basis(order, basis, m, ell_max, C, za, sa, za, sa, Kaa);
                 for (int k = 0; k < MM; ++k) Aj[k] = 0.0;
                 orc_start_factor(order, Kaa, Bj);
                 continue;
             }
-            orc_jblock_zs(order, m, ell_max, C, za, sa, za, sa, Kaa);
-            orc_jblock_zs(order, m, ell_max, C, zb, sb, zb, sb, Kbb);
-            orc_jblock_zs(order, m, ell_max, C, zb, sb, za, sa, Kba);
+            jblock_basis(order, basis, m, ell_max, C, za, sa, za, sa, Kaa);
+            jblock_basis(order, basis, m, ell_max, C, zb, sb, zb, sb, Kbb);
+            jblock_basis(order, basis, m, ell_max, C, zb, sb, za, sa, Kba);
             orc_step_factors(order, Kaa, Kbb, Kba, Aj, Bj);
         }
     }
@@ -461,7 +512,21 @@ int orc_setup_modes_z(int order, int ell_max, const double* C, int n_theta, cons
     if (zgrid && !grid_ok(zgrid, n_theta, 1)) return -1;
     int total = orc_n_sets(n_theta);
     if (n_sets > total) n_sets = total;
-    setup_sets(order, ell_max, C, n_theta, zgrid, n_sets, modes, n_modes, 0, A, B);
+    setup_sets(order, ell_max, C, n_theta, zgrid, n_sets, modes, n_modes, 0, 0, A, B);
+    return 0;
+}
+
+/* The same in the basis (g, U g) of Sec. 3 (order 2; basis 1), or the z-derivative one
+   (basis 0). */
+int orc_setup_modes_zb(int order, int basis, int ell_max, const double* C, int n_theta, const double* zgrid,
+                       int n_sets, const int* modes, int n_modes, double* A, double* B)
+{
+    if (order < 1 || order > ORC_MAXM || n_theta < 2 || ell_max < 0) return -1;
+    if (basis != 0 && !(basis == 1 && order == 2)) return -1;
+    if (zgrid && !grid_ok(zgrid, n_theta, 1)) return -1;
+    int total = orc_n_sets(n_theta);
+    if (n_sets > total) n_sets = total;
+    setup_sets(order, ell_max, C, n_theta, zgrid, n_sets, modes, n_modes, 0, basis, A, B);
     return 0;
 }
 
@@ -474,8 +539,8 @@ int orc_setup_modes_asym(int order, int ell_max, const double* C, int n_theta, c
     if (!grid_ok(zgrid, n_theta, 0)) return -1;
     int total = orc_n_sets(n_theta);
     if (n_sets > total) n_sets = total;
-    setup_sets(order, ell_max, C, n_theta, zgrid, n_sets, modes, n_modes, 0, A, B);
-    setup_sets(order, ell_max, C, n_theta, zgrid, n_sets, modes, n_modes, 1, As, Bs);
+    setup_sets(order, ell_max, C, n_theta, zgrid, n_sets, modes, n_modes, 0, 0, A, B);
+    setup_sets(order, ell_max, C, n_theta, zgrid, n_sets, modes, n_modes, 1, 0, As, Bs);
     return 0;
 }
 

@@ -544,6 +544,79 @@ def test_explicit_grid_variance_closed_form(orc, grid, order, kappa, lmax):
     np.testing.assert_allclose(var, ref, rtol=1e-11)
 
 
+# --------------------------------------------------------------------------- U basis (Sec. 3)
+@pytest.mark.parametrize("m", [0, 3, 17, 39])
+@pytest.mark.parametrize("z1,z2", [(0.3, -0.6), (0.95, 0.9), (0.1, 0.1), (-0.99, -0.97)])
+def test_u_basis_is_the_operator_of_sec3(orc, m, z1, z2):
+    """The oracle's J in the basis (g, U g), summed over -sqrt((l+m+1)(l-m)) L_{l,m+1}, against
+    the operator of Sec. 3 applied by its definition, U_m f = -(1 - z^2)^{(m+1)/2}
+    d/dz[(1 - z^2)^{-m/2} f] = -s f' - (m z / s) f, on the oracle's L_lm and dL_lm/dz (each
+    pinned to scipy and finite differences above)."""
+    lmax = 40
+    C = orc.spectrum([100.0, 100.0], lmax)
+    J = orc.jblock_u(m, lmax, C, z1, z2)
+
+    def funcs(z):
+        L, dL = orc.legendre(m, lmax, math.acos(z))
+        s = math.sqrt((1 - z) * (1 + z))
+        return L, -s * dL - m * z / s * L
+
+    L1, U1 = funcs(z1)
+    L2, U2 = funcs(z2)
+    Cm = C[m:]
+    ref = np.array([[np.sum(Cm * L1 * L2), np.sum(Cm * L1 * U2)], [np.sum(Cm * U1 * L2), np.sum(Cm * U1 * U2)]])
+    assert np.max(np.abs(J - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("n,kappa,lmax", [(16, 100.0, 15), (21, 900.0, 30), (12, 50.0, 14)])
+def test_u_basis_factors_same_law(orc, n, kappa, lmax):
+    """Factors in the basis (g, U g): covariance propagation reproduces the U-basis J at
+    every ring of both walks (the mirror D = diag(1, -1) holds as in the z basis), and the
+    field variance is the addition theorem's at every ring, as in the z basis."""
+    C = orc.spectrum([kappa, kappa], lmax)
+    n_phi = 2 * (lmax + 1)
+    A, B = orc.setup(2, C, n, n_phi, basis="u")
+    z = orc.grid(n)[1]
+    s = orc.start_ring(n)
+    even = n % 2 == 0
+    D = np.diag([1.0, -1.0])
+    worst = 0.0
+    var = np.zeros(n)
+
+    def cmp(S, K):
+        d = np.sqrt(np.maximum(np.diag(K), 0))
+        sc = np.outer(d, d)
+        mask = sc > 1e-280
+        return np.max(np.abs(S - K)[mask] / sc[mask]) if mask.any() else 0.0
+
+    for m in range(A.shape[1]):
+        w = 1.0 if m == 0 else 2.0
+        S0 = B[0, m] @ B[0, m].T
+        worst = max(worst, cmp(S0, orc.jblock_u(m, lmax, C, z[s], z[s])))
+        var[s] += w * S0[0, 0]
+        Sig, a = S0, s
+        for j in range(2 if even else 1, A.shape[0]):
+            b = s - j + 1 if even else s - j
+            Sig = A[j, m] @ Sig @ A[j, m].T + B[j, m] @ B[j, m].T
+            worst = max(worst, cmp(Sig, orc.jblock_u(m, lmax, C, z[b], z[b])))
+            var[b] += w * Sig[0, 0]
+        Sig, r, j0 = S0, s, 1
+        if even:
+            Sig = A[1, m] @ Sig @ A[1, m].T + B[1, m] @ B[1, m].T
+            r, j0 = s + 1, 2
+            worst = max(worst, cmp(Sig, orc.jblock_u(m, lmax, C, z[r], z[r])))
+            var[r] += w * Sig[0, 0]
+        for j in range(j0, A.shape[0]):
+            Am, Bm = D @ A[j, m] @ D, D @ B[j, m] @ D
+            Sig = Am @ Sig @ Am.T + Bm @ Bm.T
+            r += 1
+            worst = max(worst, cmp(Sig, orc.jblock_u(m, lmax, C, z[r], z[r])))
+            var[r] += w * Sig[0, 0]
+    assert worst < 1e-11
+    ref = np.sum((2 * np.arange(lmax + 1) + 1) * C) / (4 * math.pi)
+    np.testing.assert_allclose(var, ref, rtol=1e-11)
+
+
 def _asym_grids():
     from paper_1709_10314_amd import workloads as w
 

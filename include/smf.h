@@ -56,7 +56,12 @@ enum {
 
 enum {
     SMF_FP64 = 1,        /* sample in FP64 (recursion, normals, FFT) */
-    SMF_FP32 = 2         /* sample in FP32 (factors rounded from the FP64 setup) */
+    SMF_FP32 = 2,        /* sample in FP32 (factors rounded from the FP64 setup) */
+    SMF_UBASIS = 4       /* order 2 only, or'ed with one of the above: the chain state is
+                            (g, U_m g) with the operator U_m of Sec. 3 (eq. (Jmatrix_more_efficient):
+                            U_m maps P^m to P^{m+1}, so the setup sums L_{l,m+1} instead of
+                            z-derivatives) in place of (g, dg/dz).  The field has the same law;
+                            its realisations for given normals differ. */
 };
 
 /* Alg. 1 (pre-computation of covariance matrices), run on the GPU in FP64: for every
@@ -67,7 +72,7 @@ enum {
  * is stored; the southern steps are the mirror D A D, D B D (symmetry remark after Alg. 1).
  *   spec      host; copied, not retained.
  *   n_theta   >= 2 rings.     n_phi  power of two in [4, 16384].
- *   flags     exactly one of SMF_FP64, SMF_FP32.
+ *   flags     exactly one of SMF_FP64, SMF_FP32, optionally or'ed with SMF_UBASIS (order 2).
  *   out       receives the new plan (host pointer to a pointer).
  * Orders 3 and 4 take the second and third z-derivatives of L_lm from the associated
  * Legendre equation; their records hold A row-major and B's lower triangle (16 and 32

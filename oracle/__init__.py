@@ -87,6 +87,8 @@ def _load():
     lib.orc_setup_modes_zb.restype = _i
     lib.orc_jblock_zs_u.argtypes = [_i, _i, _pd, _d, _d, _d, _d, _pd]
     lib.orc_setup_modes_asym.restype = _i
+    lib.orc_setup_modes_asym_b.argtypes = [_i, _i, _i, _pd, _i, _pd, _i, _pi, _i, _pd, _pd, _pd, _pd]
+    lib.orc_setup_modes_asym_b.restype = _i
     lib.orc_sample_modes_list_south.argtypes = [_i, _i, _pi, _i, _i, _pd, _pd, _pd, _pd, _u64, _i, _pd]
     lib.orc_sample_modes_list_south.restype = _i
     lib.orc_setup_modes.restype = _i
@@ -253,10 +255,11 @@ def setup_modes(order, C, n_theta, modes, sets=None, z=None):
     return A, B
 
 
-def setup_asym(order, C, n_theta, n_phi, z, modes=None):
+def setup_asym(order, C, n_theta, n_phi, z, modes=None, basis="z"):
     """Alg. 1 on any strictly decreasing grid z (north to south, not necessarily symmetric):
     (A, B) for the northern walk and (As, Bs) for the southern walk in its own (true)
-    coordinates, each [sets][modes][order][order]; default every mode m = 0..m_top."""
+    coordinates, each [sets][modes][order][order]; default every mode m = 0..m_top.  basis
+    as in setup."""
     C = np.ascontiguousarray(C, dtype=np.float64)
     ell_max = len(C) - 1
     md = np.arange(m_top(ell_max, n_phi) + 1, dtype=np.int32) if modes is None else \
@@ -264,9 +267,9 @@ def setup_asym(order, C, n_theta, n_phi, z, modes=None):
     ns = n_sets(n_theta)
     zg = _zgrid(z, n_theta)
     out = [np.zeros((ns, len(md), order, order)) for _ in range(4)]
-    rc = _load().orc_setup_modes_asym(order, ell_max, _p(C), n_theta, _p(zg), ns,
-                                      md.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(md),
-                                      *[_p(a) for a in out])
+    rc = _load().orc_setup_modes_asym_b(order, {"z": 0, "u": 1}[basis], ell_max, _p(C), n_theta, _p(zg), ns,
+                                        md.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(md),
+                                        *[_p(a) for a in out])
     if rc != 0:
         raise ValueError("orc_setup_modes_asym rejected its arguments")
     return tuple(out)

@@ -531,17 +531,25 @@ int orc_setup_modes_zb(int order, int basis, int ell_max, const double* C, int n
 }
 
 /* Any strictly decreasing grid in (-1, 1): the northern sets (A, B) and the sets of */
-/* the southern walk in true coordinates (As, Bs), same shapes.                  */
-int orc_setup_modes_asym(int order, int ell_max, const double* C, int n_theta, const double* zgrid, int n_sets,
-                         const int* modes, int n_modes, double* A, double* B, double* As, double* Bs)
+/* the southern walk in true coordinates (As, Bs), same shapes; basis as in         */
+/* orc_setup_modes_zb.                                                           */
+int orc_setup_modes_asym_b(int order, int basis, int ell_max, const double* C, int n_theta, const double* zgrid,
+                           int n_sets, const int* modes, int n_modes, double* A, double* B, double* As, double* Bs)
 {
     if (order < 1 || order > ORC_MAXM || n_theta < 2 || ell_max < 0 || !zgrid) return -1;
+    if (basis != 0 && !(basis == 1 && order == 2)) return -1;
     if (!grid_ok(zgrid, n_theta, 0)) return -1;
     int total = orc_n_sets(n_theta);
     if (n_sets > total) n_sets = total;
-    setup_sets(order, ell_max, C, n_theta, zgrid, n_sets, modes, n_modes, 0, 0, A, B);
-    setup_sets(order, ell_max, C, n_theta, zgrid, n_sets, modes, n_modes, 1, 0, As, Bs);
+    setup_sets(order, ell_max, C, n_theta, zgrid, n_sets, modes, n_modes, 0, basis, A, B);
+    setup_sets(order, ell_max, C, n_theta, zgrid, n_sets, modes, n_modes, 1, basis, As, Bs);
     return 0;
+}
+
+int orc_setup_modes_asym(int order, int ell_max, const double* C, int n_theta, const double* zgrid, int n_sets,
+                         const int* modes, int n_modes, double* A, double* B, double* As, double* Bs)
+{
+    return orc_setup_modes_asym_b(order, 0, ell_max, C, n_theta, zgrid, n_sets, modes, n_modes, A, B, As, Bs);
 }
 
 /* The same on the ring-centre grid. */

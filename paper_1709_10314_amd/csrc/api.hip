@@ -103,7 +103,10 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
         return SMF_EINVAL;
     if (n_theta < 2 || n_theta > (1 << 16)) return SMF_EINVAL;
     if (!is_pow2(n_phi) || n_phi < 4 || n_phi > 16384) return SMF_EINVAL;
+    const int ubasis = (flags & SMF_UBASIS) ? 1 : 0;
+    flags &= ~SMF_UBASIS;
     if (flags != SMF_FP64 && flags != SMF_FP32) return SMF_EINVAL;
+    if (ubasis && spec->order != 2) return SMF_EINVAL;
     if (z_host && !grid_ok(z_host, n_theta)) return SMF_EINVAL;
 
     int dev = 0;
@@ -173,9 +176,12 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
         }
     }
     plan->south_off = plan->asym ? nrec1 : 0;
-    if (smf::launch_factors(g, plan->C, z_dev, 0, plan->f64, plan->f32, st) != hipSuccess) { rc = SMF_EHIP; goto fail; }
-    if (plan->asym && smf::launch_factors(g, plan->C, z_dev, 1, plan->f64 + nrec1, plan->f32 ? plan->f32 + nrec1 : nullptr,
-                                          st) != hipSuccess) {
+    if (smf::launch_factors(g, plan->C, z_dev, 0, ubasis, plan->f64, plan->f32, st) != hipSuccess) {
+        rc = SMF_EHIP;
+        goto fail;
+    }
+    if (plan->asym && smf::launch_factors(g, plan->C, z_dev, 1, ubasis, plan->f64 + nrec1,
+                                          plan->f32 ? plan->f32 + nrec1 : nullptr, st) != hipSuccess) {
         rc = SMF_EHIP;
         goto fail;
     }

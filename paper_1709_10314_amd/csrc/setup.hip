@@ -288,7 +288,10 @@ __device__ void start_gen(const double (&K)[M * M], double (&B)[M * M])
 // j >= j0 is the step (s+j-1) -> (s+j), stored mirrored (D A D, D B D with
 // D = diag((-1)^p)) so that the walk applies it to y = D x as it applies the mirrored
 // northern sets; sets below j0 (start, crossing) as in the northern table.
-template <int M>
+// UB (order 2): the state basis (g, U g) of Sec. 3 in place of (g, dg/dz), with
+// U_m L_lm = -sqrt((l+m+1)(l-m)) L_{l,m+1} (U maps P^m to P^{m+1}) summed from a second
+// Legendre stream of order m+1.
+template <int M, bool UB = false>
 __global__ __launch_bounds__(64) void factor_kernel(Geometry g, const double* __restrict__ C,
                                                     const double* __restrict__ zgrid, int south,
                                                     double* __restrict__ f64,
@@ -338,6 +341,16 @@ __global__ __launch_bounds__(64) void factor_kernel(Geometry g, const double* __
     }
     ra.p0 = 0.0; ra.p1 = pa; ra.e = ea;
     rb.p0 = 0.0; rb.p1 = pb; rb.e = eb;
+    // (UB) the order-(m+1) stream: sectoral seed L_{m+1,m+1} one factor on from L_mm
+    LegendreStream qa = ra, qb = rb;
+    double inv_q_prev = 0.0;
+    if constexpr (UB) {
+        const double f = sqrt((2.0 * m + 3.0) / (2.0 * m + 2.0));
+        qa.p1 = pa * f * sa;
+        qb.p1 = pb * f * sb;
+        if (fabs(qa.p1) < kDown) { qa.p1 *= kUp; qa.e -= 400; }
+        if (fabs(qb.p1) < kDown) { qb.p1 *= kUp; qb.e -= 400; }
+    }
 
     double Kaa[3] = {0, 0, 0}, Kbb[3] = {0, 0, 0}, Kba[4] = {0, 0, 0, 0};
     // M >= 3: full blocks (only the upper triangles of J(a,a), J(b,b) are accumulated)
@@ -406,9 +419,37 @@ __global__ __launch_bounds__(64) void factor_kernel(Geometry g, const double* __
                 for (int q = 0; q < M; ++q) KbaG[p * M + q] = fma(cfb, Fa[q], KbaG[p * M + q]);
             }
         } else {
-            // (1 - z^2) dL_l/dz = -l z L_l + c_der L_{l-1}
-            const double da = ldexp((c_der * ra.p0 - dl * ra.z * ra.p1) * ra.inv_s2, ra.e);
-            const double db = ldexp((c_der * rb.p0 - dl * rb.z * rb.p1) * rb.inv_s2, rb.e);
+            double da, db;
+            if constexpr (UB) {
+                // L_{l,m+1} for l >= m+1 by the same recurrence in order m+1; U_m L_lm from it
+                const double dm1 = dm + 1.0;
+                da = db = 0.0;
+                if (l == m + 2) {
+                    const double a1 = sqrt(2.0 * dm1 + 3.0);
+                    qa.p0 = qa.p1; qa.p1 = a1 * qa.z * qa.p0;
+                    qb.p0 = qb.p1; qb.p1 = a1 * qb.z * qb.p0;
+                    inv_q_prev = 1.0 / a1;
+                } else if (l > m + 2) {
+                    const double q = (4.0 * dl * dl - 1.0) / ((dl - dm1) * (dl + dm1));
+                    const double al = sqrt(q);
+                    double t = al * (qa.z * qa.p1 - inv_q_prev * qa.p0);
+                    qa.p0 = qa.p1; qa.p1 = t;
+                    t = al * (qb.z * qb.p1 - inv_q_prev * qb.p0);
+                    qb.p0 = qb.p1; qb.p1 = t;
+                    inv_q_prev = 1.0 / al;
+                }
+                if (qa.e < 0 && fabs(qa.p1) > kUp) { qa.p0 *= kDown; qa.p1 *= kDown; qa.e += 400; }
+                if (qb.e < 0 && fabs(qb.p1) > kUp) { qb.p0 *= kDown; qb.p1 *= kDown; qb.e += 400; }
+                if (l > m) {
+                    const double f = -sqrt((dl + dm + 1.0) * (dl - dm));
+                    da = f * qa.value();
+                    db = f * qb.value();
+                }
+            } else {
+                // (1 - z^2) dL_l/dz = -l z L_l + c_der L_{l-1}
+                da = ldexp((c_der * ra.p0 - dl * ra.z * ra.p1) * ra.inv_s2, ra.e);
+                db = ldexp((c_der * rb.p0 - dl * rb.z * rb.p1) * rb.inv_s2, rb.e);
+            }
             const double cva = cl * va, cda = cl * da, cvb = cl * vb, cdb = cl * db;
             Kaa[0] = fma(cva, va, Kaa[0]);
             Kaa[1] = fma(cva, da, Kaa[1]);
@@ -557,10 +598,15 @@ hipError_t launch_spectrum(const double* kappa_dev, int n_kappa, const double* c
     return hipGetLastError();
 }
 
-hipError_t launch_factors(const Geometry& g, const double* C_dev, const double* z_dev, int south, double* f64,
-                          float* f32, hipStream_t st)
+hipError_t launch_factors(const Geometry& g, const double* C_dev, const double* z_dev, int south, int ubasis,
+                          double* f64, float* f32, hipStream_t st)
 {
     dim3 grid((g.n_sets + 63) / 64, g.m_top + 1);
+    if (ubasis) {
+        if (g.order != 2) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((factor_kernel<2, true>), grid, dim3(64), 0, st, g, C_dev, z_dev, south, f64, f32);
+        return hipGetLastError();
+    }
     switch (g.order) {
         case 1: hipLaunchKernelGGL(factor_kernel<1>, grid, dim3(64), 0, st, g, C_dev, z_dev, south, f64, f32); break;
         case 2: hipLaunchKernelGGL(factor_kernel<2>, grid, dim3(64), 0, st, g, C_dev, z_dev, south, f64, f32); break;

@@ -59,8 +59,9 @@ hipError_t launch_spectrum(const double* kappa_dev, int n_kappa, const double* c
                            int ell_max, double* C_dev, int* bad_dev, hipStream_t st);
 // z_dev: ring values of an explicit grid (device, n_theta doubles) or null for ring centres.
 // south: the southern walk's own sets of a grid with no symmetry, stored mirrored.
-hipError_t launch_factors(const Geometry& g, const double* C_dev, const double* z_dev, int south, double* f64,
-                          float* f32, hipStream_t st);
+// ubasis (order 2): the state basis (g, U g) of Sec. 3 in place of (g, dg/dz).
+hipError_t launch_factors(const Geometry& g, const double* C_dev, const double* z_dev, int south, int ubasis,
+                          double* f64, float* f32, hipStream_t st);
 hipError_t launch_twiddles(int n_phi, double* tw64, float* tw32, hipStream_t st);
 // Phi per (fine ring block, m) for the affine scan, layout [block][m][M*M], m stride m_rows.
 hipError_t launch_phi(const Geometry& g, const double* f64, int blocks, double* phi64, float* phi32,

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsmf.so")
 
 SMF_OK, SMF_EINVAL, SMF_ENOMEM, SMF_EHIP, SMF_ENUMERIC = 0, -1, -2, -3, -4
-SMF_FP64, SMF_FP32 = 1, 2
+SMF_FP64, SMF_FP32, SMF_UBASIS = 1, 2, 4
 
 # every symbol include/smf.h declares
 EXPORTS = ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks",
@@ -302,8 +302,10 @@ class Plan:
     """A setup plan (Alg. 1 factors on the GPU) with sampling methods (Alg. 2)."""
 
     def __init__(self, order, n_theta, n_phi, ell_max, kappa=None, c_ell=None, precision="fp32",
-                 stream=None, z=None):
-        flags = {"fp32": SMF_FP32, "fp64": SMF_FP64}[precision]
+                 stream=None, z=None, basis="z"):
+        """basis: "z" (the state is the value and its z-derivatives) or "u" (order 2: (g, U g)
+        of Sec. 3, SMF_UBASIS)."""
+        flags = {"fp32": SMF_FP32, "fp64": SMF_FP64}[precision] | {"z": 0, "u": SMF_UBASIS}[basis]
         rc, h = smf_setup(order, n_theta, n_phi, ell_max, kappa=kappa, c_ell=c_ell, flags=flags,
                           stream=stream, z=z)
         if rc != SMF_OK:

@@ -247,7 +247,15 @@ int smf_setup_grid(const smf_spectrum* spec, int n_theta, const double* z_host, 
 // automatic choice (measured on MI355X) is: FP32 plain with two parts per lane from 2048
 // waves, plain with one part from 1024, a two-part scan of 8 blocks from 512, else a
 // one-part scan of 16 blocks; FP64 plain from 1024 waves, else a scan of the fewest
-// blocks giving >= 4096 waves.  Scans keep >= kScanAutoMinSets ring steps per block.
+// blocks giving >= 4096 waves.  Orders 3 and 4 as FP64 (one-part scans of at most 8
+// blocks), with two parts per lane in FP32 from SMF_GEN_TWO_W waves.  Scans keep
+// >= kScanAutoMinSets ring steps per block.
+// Orders 3 and 4: the plain recursion runs two parts per lane from this many one-part waves
+// (measured: order 4 at 2048 x 4096 x 32 fields 1.88 -> 1.59 ms; at 4096 x 8192 x 8 fields,
+// 2048 waves, one part per lane stays faster).
+#ifndef SMF_GEN_TWO_W
+#define SMF_GEN_TWO_W 4096
+#endif
 struct CallShape {
     int blocks, nch;
 };
@@ -259,7 +267,7 @@ static CallShape call_shape(const smf_plan* plan, int count)
     const int cap = std::min(plan->scan_fine, smf::scan_max_blocks(fp64, plan->g.order));
     const long w = (long)count * 2 * ((plan->g.m_rows + 31) / 32);
     const int walk = plan->g.n_sets - (plan->g.even ? 2 : 1);
-    const int plain_nch = (!fp64 && !high && w >= 2048) ? 2 : 1;
+    const int plain_nch = (!fp64 && w >= (high ? SMF_GEN_TWO_W : 2048)) ? 2 : 1;
     const int scan_nch = (!fp64 && !high && w >= 512) ? 2 : 1;
     if (cap < 2 || plan->scan_req == 1) return {1, plain_nch};
     if (plan->scan_req >= 2) return {std::min(plan->scan_req, cap), scan_nch};

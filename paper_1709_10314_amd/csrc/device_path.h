@@ -405,11 +405,13 @@ __device__ __forceinline__ void zero_chain(int n, int s, int h, T* __restrict__ 
 
 // ------------------------------------------------------------------ orders 3 and 4
 // The same recursion for a state of M = 3 or 4 components (value and z-derivatives up to
-// M-1), one chain per lane.  Ring r uses the normals r M + q, q < M, of the counter map
-// (block (r M + q) / 4, word (r M + q) mod 4), so G rings whose G M normals fill NB whole
-// Philox blocks form a group: M = 3 -> 4 rings in 3 blocks, M = 4 -> 1 ring in 1 block.
-// Groups are aligned to multiples of G in the ring index; a walk starts and ends with cut
-// groups whose rings outside the walk are skipped.
+// M-1).  A lane runs NCH chains of one mode that share every record load: one part
+// (NCH = 1, part `up0`) or both parts (NCH = 2, parts 0 and 1, stored as one pair), as in
+// the order-1/2 walk.  Ring r uses the normals r M + q, q < M, of the counter map (block
+// (r M + q) / 4, word (r M + q) mod 4), so G rings whose G M normals fill NB whole Philox
+// blocks form a group: M = 3 -> 4 rings in 3 blocks, M = 4 -> 1 ring in 1 block.  Groups
+// are aligned to multiples of G in the ring index; a walk starts and ends with cut groups
+// whose rings outside the walk are skipped.
 template <int M>
 struct GenGroup {
     static constexpr int G = M % 4 == 0 ? 1 : (M % 2 == 0 ? 2 : 4);
@@ -454,28 +456,34 @@ __device__ __forceinline__ void chain_step_gen(const RecGen<T, M>& R, T (&x)[M],
     for (int p = 0; p < M; ++p) x[p] = y[p];
 }
 
-// The 4 NB normals of the group starting at ring `base`, scaled by sc.
-template <typename T, int M>
-__device__ __forceinline__ void group_normals(int base, uint32_t um, uint32_t up, uint32_t k0, uint32_t k1, T sc,
-                                              T (&nb)[4 * GenGroup<M>::NB])
+// The 4 NB normals of the group starting at ring `base` for each of the lane's chains
+// (part up0 + c, scaled by sc[c]); the NCH * NB Philox blocks run in lockstep.
+template <typename T, int M, int NCH>
+__device__ __forceinline__ void group_normals(int base, uint32_t um, uint32_t up0, uint32_t k0, uint32_t k1,
+                                              const T (&sc)[NCH], T (&nb)[NCH][4 * GenGroup<M>::NB])
 {
     constexpr int NB = GenGroup<M>::NB;
-    uint32_t blk[NB], prt[NB];
+    uint32_t blk[NCH * NB], prt[NCH * NB];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        blk[k] = (uint32_t)((base * M) >> 2) + (uint32_t)k;
-        prt[k] = up;
-    }
-    PhiloxBlock wb[NB];
-    philox4x32_10_n<NB>(blk, um, prt, k0, k1, wb);
+    for (int c = 0; c < NCH; ++c)
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        BoxMuller<T>::pair(wb[k].w[0], wb[k].w[1], sc, nb[4 * k], nb[4 * k + 1]);
-        BoxMuller<T>::pair(wb[k].w[2], wb[k].w[3], sc, nb[4 * k + 2], nb[4 * k + 3]);
-    }
+        for (int k = 0; k < NB; ++k) {
+            blk[c * NB + k] = (uint32_t)((base * M) >> 2) + (uint32_t)k;
+            prt[c * NB + k] = up0 + c;
+        }
+    PhiloxBlock wb[NCH * NB];
+    philox4x32_10_n<NCH * NB>(blk, um, prt, k0, k1, wb);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const PhiloxBlock& w = wb[c * NB + k];
+            BoxMuller<T>::pair(w.w[0], w.w[1], sc[c], nb[c][4 * k], nb[c][4 * k + 1]);
+            BoxMuller<T>::pair(w.w[2], w.w[3], sc[c], nb[c][4 * k + 2], nb[c][4 * k + 3]);
+        }
 }
 
-// The M normals of ring base + t from its group's normals (t uniform, not a constant:
+// The M normals of ring base + t from a group's normals (t uniform, not a constant:
 // selected, not indexed), the odd ones negated south of the start (D w).
 template <typename T, int M, bool NORTH>
 __device__ __forceinline__ void ring_normals(const T (&nb)[4 * GenGroup<M>::NB], int t, T (&w)[M])
@@ -490,32 +498,54 @@ __device__ __forceinline__ void ring_normals(const T (&nb)[4 * GenGroup<M>::NB],
         }
 }
 
+// The value component of the lane's chains into ring slot `off` (one pair for NCH = 2).
+template <typename T, int M, int NCH>
+__device__ __forceinline__ void store_gen(T* __restrict__ g, size_t off, const T (&x)[NCH][M])
+{
+    T v[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) v[c] = x[c][0];
+    store_ring<T, NCH>(g, off, v);
+}
+
+// One ring of the lane's chains with the ring's record and its group's normals (t: the
+// ring's compile-time position in the group).
+template <typename T, int M, bool NORTH, int NCH>
+__device__ __forceinline__ void step_ring_gen(const RecGen<T, M>& R, const T (&nb)[NCH][4 * GenGroup<M>::NB], int t,
+                                              T (&x)[NCH][M])
+{
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        T w[M];
+#pragma unroll
+        for (int q = 0; q < M; ++q) w[q] = (!NORTH && (q & 1)) ? -nb[c][t * M + q] : nb[c][t * M + q];
+        chain_step_gen<T, M>(R, x[c], w);
+    }
+}
+
 // Rings [lo, hi] of the group at `base`, in walk order.  The group's records are loaded
 // before its Philox rounds, so their latency overlaps the rounds.  STORE = false walks
 // without stores (only the end state is wanted).
-template <typename T, int M, bool NORTH, bool STORE = true>
+template <typename T, int M, bool NORTH, bool STORE, int NCH>
 __device__ __forceinline__ void step_group_gen(int base, int lo, int hi, int s, int even, int n_sets, uint32_t um,
-                                               uint32_t up, uint32_t k0, uint32_t k1, T sc,
+                                               uint32_t up0, uint32_t k0, uint32_t k1, const T (&sc)[NCH],
                                                const T* __restrict__ fm, size_t set_stride, T* __restrict__ g,
-                                               size_t row, T (&x)[M])
+                                               size_t row, T (&x)[NCH][M])
 {
     constexpr int G = GenGroup<M>::G;
     RecGen<T, M> R[G];
 #pragma unroll
     for (int t = 0; t < G; ++t)
         R[t] = load_rec_gen<T, M>(fm + (size_t)set_of_ring<T, M, NORTH>(base + t, s, even, n_sets) * set_stride);
-    T nb[4 * GenGroup<M>::NB];
-    group_normals<T, M>(base, um, up, k0, k1, sc, nb);
+    T nb[NCH][4 * GenGroup<M>::NB];
+    group_normals<T, M, NCH>(base, um, up0, k0, k1, sc, nb);
 #pragma unroll
     for (int tt = 0; tt < G; ++tt) {
         const int t = NORTH ? G - 1 - tt : tt;
         const int r = base + t;
         if (r >= lo && r <= hi) {
-            T w[M];
-#pragma unroll
-            for (int q = 0; q < M; ++q) w[q] = (!NORTH && (q & 1)) ? -nb[t * M + q] : nb[t * M + q];
-            chain_step_gen<T, M>(R[t], x, w);
-            if constexpr (STORE) g[(size_t)r * row] = x[0];
+            step_ring_gen<T, M, NORTH, NCH>(R[t], nb, t, x);
+            if constexpr (STORE) store_gen<T, M, NCH>(g, (size_t)r * row, x);
         }
     }
 }
@@ -536,19 +566,27 @@ __device__ __forceinline__ void step_group_gen(int base, int lo, int hi, int s, 
 #ifndef SMF_GEN_P4_64
 #define SMF_GEN_P4_64 2
 #endif
-template <typename T, int M>
+#ifndef SMF_GEN_P3_TWO
+#define SMF_GEN_P3_TWO 2
+#endif
+#ifndef SMF_GEN_P4_TWO
+#define SMF_GEN_P4_TWO 1
+#endif
+template <typename T, int M, int NCH = 1>
 struct GenDepth {
-    static constexpr int value = sizeof(T) == 8 ? (M == 3 ? SMF_GEN_P3_64 : SMF_GEN_P4_64)
-                                                : (M == 3 ? SMF_GEN_P3_32 : SMF_GEN_P4_32);
+    static constexpr int value = NCH == 2 ? (M == 3 ? SMF_GEN_P3_TWO : SMF_GEN_P4_TWO)
+                                 : sizeof(T) == 8 ? (M == 3 ? SMF_GEN_P3_64 : SMF_GEN_P4_64)
+                                                  : (M == 3 ? SMF_GEN_P3_32 : SMF_GEN_P4_32);
 };
 
 // Walks rings r_first..r_last (north: descending, south: ascending) as walk_hemisphere does
 // for orders 1 and 2: a cut first group stepped directly, full groups through a P-slot
 // record pipeline (slot q mod P, refilled with group q + P after use), a cut last group.
-template <typename T, int M, int P, bool NORTH, bool STORE = true>
-__device__ __forceinline__ void walk_gen(int s, int even, int r_first, int r_last, uint32_t um, uint32_t up,
-                                         uint32_t k0, uint32_t k1, T sc, const T* __restrict__ fm,
-                                         size_t set_stride, int n_sets, T* __restrict__ g, size_t row, T (&x)[M])
+template <typename T, int M, int P, bool NORTH, bool STORE, int NCH>
+__device__ __forceinline__ void walk_gen(int s, int even, int r_first, int r_last, uint32_t um, uint32_t up0,
+                                         uint32_t k0, uint32_t k1, const T (&sc)[NCH], const T* __restrict__ fm,
+                                         size_t set_stride, int n_sets, T* __restrict__ g, size_t row,
+                                         T (&x)[NCH][M])
 {
     constexpr int G = GenGroup<M>::G, NB = GenGroup<M>::NB;
     if (NORTH ? r_first < r_last : r_first > r_last) return;
@@ -557,8 +595,8 @@ __device__ __forceinline__ void walk_gen(int s, int even, int r_first, int r_las
         int top = r_first;
         const int base = (top / G) * G;
         if (top != base + G - 1 || base < r_last) {
-            step_group_gen<T, M, true, STORE>(base, base > r_last ? base : r_last, top, s, even, n_sets, um, up, k0, k1, sc,
-                                       fm, set_stride, g, row, x);
+            step_group_gen<T, M, true, STORE, NCH>(base, base > r_last ? base : r_last, top, s, even, n_sets, um, up0,
+                                                   k0, k1, sc, fm, set_stride, g, row, x);
             top = base - 1;
         }
         ng = top + 1 - r_last >= G ? (top + 1 - r_last) / G : 0;
@@ -567,8 +605,8 @@ __device__ __forceinline__ void walk_gen(int s, int even, int r_first, int r_las
         int lo = r_first;
         const int base = (lo / G) * G;
         if (lo != base || base + G - 1 > r_last) {
-            step_group_gen<T, M, false, STORE>(base, lo, base + G - 1 < r_last ? base + G - 1 : r_last, s, even, n_sets, um,
-                                        up, k0, k1, sc, fm, set_stride, g, row, x);
+            step_group_gen<T, M, false, STORE, NCH>(base, lo, base + G - 1 < r_last ? base + G - 1 : r_last, s, even,
+                                                    n_sets, um, up0, k0, k1, sc, fm, set_stride, g, row, x);
             lo = base + G;
         }
         ng = r_last - lo + 1 >= G ? (r_last - lo + 1) / G : 0;
@@ -585,38 +623,39 @@ __device__ __forceinline__ void walk_gen(int s, int even, int r_first, int r_las
         }
         int q = 0;
         for (; q + P <= ng; q += P) {
-            uint32_t blk[P * NB], prt[P * NB];
+            uint32_t blk[P * NCH * NB], prt[P * NCH * NB];
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const int base = NORTH ? b0 - (q + p) * G : b0 + (q + p) * G;
 #pragma unroll
-                for (int k = 0; k < NB; ++k) {
-                    blk[p * NB + k] = (uint32_t)((base * M) >> 2) + (uint32_t)k;
-                    prt[p * NB + k] = up;
-                }
+                for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                    for (int k = 0; k < NB; ++k) {
+                        blk[(p * NCH + c) * NB + k] = (uint32_t)((base * M) >> 2) + (uint32_t)k;
+                        prt[(p * NCH + c) * NB + k] = up0 + c;
+                    }
             }
-            PhiloxBlock wb[P * NB];
-            philox4x32_10_n<P * NB>(blk, um, prt, k0, k1, wb);
-            T nbs[P][4 * NB];
+            PhiloxBlock wb[P * NCH * NB];
+            philox4x32_10_n<P * NCH * NB>(blk, um, prt, k0, k1, wb);
+            T nbs[P][NCH][4 * NB];
 #pragma unroll
             for (int p = 0; p < P; ++p)
 #pragma unroll
-                for (int k = 0; k < NB; ++k) {
-                    const PhiloxBlock& w = wb[p * NB + k];
-                    BoxMuller<T>::pair(w.w[0], w.w[1], sc, nbs[p][4 * k], nbs[p][4 * k + 1]);
-                    BoxMuller<T>::pair(w.w[2], w.w[3], sc, nbs[p][4 * k + 2], nbs[p][4 * k + 3]);
-                }
+                for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                    for (int k = 0; k < NB; ++k) {
+                        const PhiloxBlock& w = wb[(p * NCH + c) * NB + k];
+                        BoxMuller<T>::pair(w.w[0], w.w[1], sc[c], nbs[p][c][4 * k], nbs[p][c][4 * k + 1]);
+                        BoxMuller<T>::pair(w.w[2], w.w[3], sc[c], nbs[p][c][4 * k + 2], nbs[p][c][4 * k + 3]);
+                    }
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const int base = NORTH ? b0 - (q + p) * G : b0 + (q + p) * G;
 #pragma unroll
                 for (int tt = 0; tt < G; ++tt) {
                     const int t = NORTH ? G - 1 - tt : tt;
-                    T w[M];
-#pragma unroll
-                    for (int c = 0; c < M; ++c) w[c] = (!NORTH && (c & 1)) ? -nbs[p][t * M + c] : nbs[p][t * M + c];
-                    chain_step_gen<T, M>(buf[p][t], x, w);
-                    if constexpr (STORE) g[(size_t)(base + t) * row] = x[0];
+                    step_ring_gen<T, M, NORTH, NCH>(buf[p][t], nbs[p], t, x);
+                    if constexpr (STORE) store_gen<T, M, NCH>(g, (size_t)(base + t) * row, x);
                 }
                 const int nbase = NORTH ? base - P * G : base + P * G;
 #pragma unroll
@@ -630,16 +669,13 @@ __device__ __forceinline__ void walk_gen(int s, int even, int r_first, int r_las
         for (int p = 0; p < P; ++p) {
             if (q + p < ng) {
                 const int base = NORTH ? b0 - (q + p) * G : b0 + (q + p) * G;
-                T nb[4 * NB];
-                group_normals<T, M>(base, um, up, k0, k1, sc, nb);
+                T nb[NCH][4 * NB];
+                group_normals<T, M, NCH>(base, um, up0, k0, k1, sc, nb);
 #pragma unroll
                 for (int tt = 0; tt < G; ++tt) {
                     const int t = NORTH ? G - 1 - tt : tt;
-                    T w[M];
-#pragma unroll
-                    for (int c = 0; c < M; ++c) w[c] = (!NORTH && (c & 1)) ? -nb[t * M + c] : nb[t * M + c];
-                    chain_step_gen<T, M>(buf[p][t], x, w);
-                    if constexpr (STORE) g[(size_t)(base + t) * row] = x[0];
+                    step_ring_gen<T, M, NORTH, NCH>(buf[p][t], nb, t, x);
+                    if constexpr (STORE) store_gen<T, M, NCH>(g, (size_t)(base + t) * row, x);
                 }
             }
         }
@@ -648,87 +684,105 @@ __device__ __forceinline__ void walk_gen(int s, int even, int r_first, int r_las
         const int end = b0 - ng * G + G - 1;   // highest ring not yet produced
         if (end >= r_last) {
             const int base = (end / G) * G;
-            step_group_gen<T, M, true, STORE>(base, r_last, end, s, even, n_sets, um, up, k0, k1, sc, fm, set_stride, g, row,
-                                       x);
+            step_group_gen<T, M, true, STORE, NCH>(base, r_last, end, s, even, n_sets, um, up0, k0, k1, sc, fm,
+                                                   set_stride, g, row, x);
         }
     } else {
         const int lo = b0 + ng * G;
         if (lo <= r_last)
-            step_group_gen<T, M, false, STORE>(lo, lo, r_last, s, even, n_sets, um, up, k0, k1, sc, fm, set_stride, g, row, x);
+            step_group_gen<T, M, false, STORE, NCH>(lo, lo, r_last, s, even, n_sets, um, up0, k0, k1, sc, fm,
+                                                    set_stride, g, row, x);
     }
 }
 
 // The state the walk of an order M >= 3 chain starts from (as chain_start): the start draw
 // at ring s with set 0 (eq. (state_initial); A = 0), stored by the northern chain; for the
 // southern chain the crossing s -> s+1 (even n_theta, set 1, stored), then y = D x.
-template <typename T, int M>
-__device__ __forceinline__ void chain_start_gen(int s, int even, int h, uint32_t um, uint32_t up, uint32_t k0,
-                                                uint32_t k1, T sc, const T* __restrict__ fm, size_t set_stride,
-                                                T* __restrict__ g, size_t row, bool store, T (&x)[M])
+template <typename T, int M, int NCH>
+__device__ __forceinline__ void chain_start_gen(int s, int even, int h, uint32_t um, uint32_t up0, uint32_t k0,
+                                                uint32_t k1, const T (&sc)[NCH], const T* __restrict__ fm,
+                                                size_t set_stride, T* __restrict__ g, size_t row, bool store,
+                                                T (&x)[NCH][M])
 {
     constexpr int G = GenGroup<M>::G;
 #pragma unroll
-    for (int p = 0; p < M; ++p) x[p] = T(0);
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int p = 0; p < M; ++p) x[c][p] = T(0);
     {
         const int bs = (s / G) * G;
-        T nb[4 * GenGroup<M>::NB], w[M];
-        group_normals<T, M>(bs, um, up, k0, k1, sc, nb);
-        ring_normals<T, M, true>(nb, s - bs, w);
-        chain_step_gen<T, M>(load_rec_gen<T, M>(fm), x, w);
-        if (store && h == 0) g[(size_t)s * row] = x[0];
+        T nb[NCH][4 * GenGroup<M>::NB];
+        group_normals<T, M, NCH>(bs, um, up0, k0, k1, sc, nb);
+        const RecGen<T, M> R = load_rec_gen<T, M>(fm);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            T w[M];
+            ring_normals<T, M, true>(nb[c], s - bs, w);
+            chain_step_gen<T, M>(R, x[c], w);
+        }
+        if (store && h == 0) store_gen<T, M, NCH>(g, (size_t)s * row, x);
     }
     if (h == 1 && even) {
         const int r = s + 1;
         const int br = (r / G) * G;
-        T nb[4 * GenGroup<M>::NB], w[M];
-        group_normals<T, M>(br, um, up, k0, k1, sc, nb);
-        ring_normals<T, M, true>(nb, r - br, w);
-        chain_step_gen<T, M>(load_rec_gen<T, M>(fm + set_stride), x, w);
-        if (store) g[(size_t)r * row] = x[0];
+        T nb[NCH][4 * GenGroup<M>::NB];
+        group_normals<T, M, NCH>(br, um, up0, k0, k1, sc, nb);
+        const RecGen<T, M> R = load_rec_gen<T, M>(fm + set_stride);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            T w[M];
+            ring_normals<T, M, true>(nb[c], r - br, w);
+            chain_step_gen<T, M>(R, x[c], w);
+        }
+        if (store) store_gen<T, M, NCH>(g, (size_t)r * row, x);
     }
     if (h == 1) {
 #pragma unroll
-        for (int p = 1; p < M; p += 2) x[p] = -x[p];   // y = D x
+        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+            for (int p = 1; p < M; p += 2) x[c][p] = -x[c][p];   // y = D x
     }
 }
 
-// One chain of order M >= 3 (one part; layout and hemisphere roles as run_chain): the
-// start draw at ring s, for the south the crossing step (even n_theta) and the switch to
-// y = D x, then the walk to ring 0 or n-1.
-template <typename T, int M>
-__device__ __forceinline__ void run_chain_gen(int n, int s, int even, int n_sets, int h, int m, int part, uint32_t k0,
+// The NCH chains of one lane at order M >= 3 (layout and hemisphere roles as run_chain):
+// the start draw at ring s, for the south the crossing step (even n_theta) and the switch
+// to y = D x, then the walk to ring 0 or n-1.
+template <typename T, int M, int NCH = 1>
+__device__ __forceinline__ void run_chain_gen(int n, int s, int even, int n_sets, int h, int m, int up0, uint32_t k0,
                                               uint32_t k1, const T* __restrict__ fm, size_t set_stride,
                                               T* __restrict__ g, size_t row, size_t south_off = 0)
 {
     constexpr int G = GenGroup<M>::G;
-    const uint32_t um = (uint32_t)m, up = (uint32_t)part;
-    const T sc = m == 0 ? T(1) : T(0.70710678118654752440);
-    T x[M];
-    chain_start_gen<T, M>(s, even, h, um, up, k0, k1, sc, fm, set_stride, g, row, true, x);
-    constexpr int P = GenDepth<T, M>::value;
+    const uint32_t um = (uint32_t)m, up = (uint32_t)up0;
+    T sc[NCH];
+    chain_scales<T, NCH>(m, up, sc);
+    T x[NCH][M];
+    chain_start_gen<T, M, NCH>(s, even, h, um, up, k0, k1, sc, fm, set_stride, g, row, true, x);
+    constexpr int P = GenDepth<T, M, NCH>::value;
     if (h == 0) {
         if constexpr (P == 0) {
             for (int top = s - 1; top >= 0;) {
                 const int base = (top / G) * G;
-                step_group_gen<T, M, true>(base, base, top, s, even, n_sets, um, up, k0, k1, sc, fm, set_stride, g, row,
-                                           x);
+                step_group_gen<T, M, true, true, NCH>(base, base, top, s, even, n_sets, um, up, k0, k1, sc, fm,
+                                                      set_stride, g, row, x);
                 top = base - 1;
             }
         } else {
-            walk_gen<T, M, P, true>(s, even, s - 1, 0, um, up, k0, k1, sc, fm, set_stride, n_sets, g, row, x);
+            walk_gen<T, M, P, true, true, NCH>(s, even, s - 1, 0, um, up, k0, k1, sc, fm, set_stride, n_sets, g, row,
+                                               x);
         }
     } else {
         if constexpr (P == 0) {
             for (int lo = even ? s + 2 : s + 1; lo <= n - 1;) {
                 const int base = (lo / G) * G;
                 const int hi = base + G - 1 < n - 1 ? base + G - 1 : n - 1;
-                step_group_gen<T, M, false>(base, lo, hi, s, even, n_sets, um, up, k0, k1, sc, fm + south_off,
-                                            set_stride, g, row, x);
+                step_group_gen<T, M, false, true, NCH>(base, lo, hi, s, even, n_sets, um, up, k0, k1, sc,
+                                                       fm + south_off, set_stride, g, row, x);
                 lo = base + G;
             }
         } else {
-            walk_gen<T, M, P, false>(s, even, even ? s + 2 : s + 1, n - 1, um, up, k0, k1, sc, fm + south_off,
-                                     set_stride, n_sets, g, row, x);
+            walk_gen<T, M, P, false, true, NCH>(s, even, even ? s + 2 : s + 1, n - 1, um, up, k0, k1, sc,
+                                                fm + south_off, set_stride, n_sets, g, row, x);
         }
     }
 }

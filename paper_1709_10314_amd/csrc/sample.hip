@@ -55,10 +55,10 @@ __global__ __launch_bounds__(256) void recursion_kernel(RecArgs a, const T* __re
                          (size_t)a.n_phi, a.south_off);
 }
 
-// Markov orders 3 and 4: one lane per (field, hemisphere, mode, part), laid out as the
-// one-part recursion above (32 modes x 2 parts per wave, four (f, h) families per
-// workgroup, m-tiles kept on one XCD).
-template <typename T, int M>
+// Markov orders 3 and 4, laid out as the recursion above: NCH = 2 runs both parts of a
+// mode in one lane (64 modes per wave), NCH = 1 one part (32 modes x 2 parts per wave);
+// four (f, h) families per workgroup, m-tiles kept on one XCD.
+template <typename T, int M, int NCH>
 __global__ __launch_bounds__(256) void recursion_gen_kernel(RecArgs a, const T* __restrict__ fac,
                                                             T* __restrict__ out)
 {
@@ -71,16 +71,16 @@ __global__ __launch_bounds__(256) void recursion_gen_kernel(RecArgs a, const T* 
     if (fh >= a.n_fh) return;
     const int f = fh >> 1, h = fh & 1;
     const int lane = threadIdx.x & 63;
-    const int m = mt * 32 + (lane >> 1);
-    const int part = lane & 1;
+    const int m = NCH == 2 ? mt * 64 + lane : mt * 32 + (lane >> 1);
+    const int part = NCH == 2 ? 0 : lane & 1;
     if (m >= a.m_rows) return;
     T* __restrict__ g = out + (size_t)f * a.n_theta * a.n_phi + 2 * m + part;
-    if (m > a.m_top || (m == 0 && part == 1)) {
-        zero_chain<T, 1>(a.n_theta, a.s, h, g, (size_t)a.n_phi);
+    if (m > a.m_top || (NCH == 1 && m == 0 && part == 1)) {
+        zero_chain<T, NCH>(a.n_theta, a.s, h, g, (size_t)a.n_phi);
         return;
     }
     const uint64_t key = (((uint64_t)a.seed_hi << 32) | a.seed_lo) + (uint64_t)f;
-    run_chain_gen<T, M>(a.n_theta, a.s, a.even, a.n_sets, h, m, part, (uint32_t)key, (uint32_t)(key >> 32),
+    run_chain_gen<T, M, NCH>(a.n_theta, a.s, a.even, a.n_sets, h, m, part, (uint32_t)key, (uint32_t)(key >> 32),
                         fac + (size_t)m * factor_stride(M), (size_t)a.m_rows * factor_stride(M), g,
                         (size_t)a.n_phi, a.south_off);
 }
@@ -258,7 +258,8 @@ __global__ __launch_bounds__(64 * B) void scan_gen_kernel(ScanArgs a, const T* _
     const T* __restrict__ fw = fm + (h ? a.south_off : 0);
     const T* __restrict__ ph = phi + (h ? a.phi_south_off : 0);
     const size_t set_stride = (size_t)a.m_rows * factor_stride(M);
-    const T sc = mm == 0 ? T(1) : T(0.70710678118654752440);
+    T sc[1];
+    chain_scales<T, 1>(mm, (uint32_t)part, sc);
     const uint32_t um = (uint32_t)mm, up = (uint32_t)part;
     const int j0 = a.even ? 2 : 1;
     const long walk = a.n_sets - j0;
@@ -268,59 +269,59 @@ __global__ __launch_bounds__(64 * B) void scan_gen_kernel(ScanArgs a, const T* _
     const int r_last = h == 0 ? a.s - (je - 1) + a.even : a.s + (je - 1);
 
     // pass 1: block 0 from the start state (final, stored); the others from zero
-    T x[M];
+    T x[1][M];
 #pragma unroll
-    for (int p = 0; p < M; ++p) x[p] = T(0);
+    for (int p = 0; p < M; ++p) x[0][p] = T(0);
     if (active) {
         if (blk == 0) {
-            chain_start_gen<T, M>(a.s, a.even, h, um, up, k0, k1, sc, fm, set_stride, g, row, true, x);
+            chain_start_gen<T, M, 1>(a.s, a.even, h, um, up, k0, k1, sc, fm, set_stride, g, row, true, x);
             if (h == 0)
-                walk_gen<T, M, 1, true, true>(a.s, a.even, r_first, r_last, um, up, k0, k1, sc, fw, set_stride,
+                walk_gen<T, M, 1, true, true, 1>(a.s, a.even, r_first, r_last, um, up, k0, k1, sc, fw, set_stride,
                                               a.n_sets, g, row, x);
             else
-                walk_gen<T, M, 1, false, true>(a.s, a.even, r_first, r_last, um, up, k0, k1, sc, fw, set_stride,
+                walk_gen<T, M, 1, false, true, 1>(a.s, a.even, r_first, r_last, um, up, k0, k1, sc, fw, set_stride,
                                                a.n_sets, g, row, x);
         } else {
             if (h == 0)
-                walk_gen<T, M, 1, true, false>(a.s, a.even, r_first, r_last, um, up, k0, k1, sc, fw, set_stride,
+                walk_gen<T, M, 1, true, false, 1>(a.s, a.even, r_first, r_last, um, up, k0, k1, sc, fw, set_stride,
                                                a.n_sets, g, row, x);
             else
-                walk_gen<T, M, 1, false, false>(a.s, a.even, r_first, r_last, um, up, k0, k1, sc, fw, set_stride,
+                walk_gen<T, M, 1, false, false, 1>(a.s, a.even, r_first, r_last, um, up, k0, k1, sc, fw, set_stride,
                                                 a.n_sets, g, row, x);
         }
     }
 #pragma unroll
-    for (int p = 0; p < M; ++p) ends[(blk * 64 + lane) * M + p] = x[p];
+    for (int p = 0; p < M; ++p) ends[(blk * 64 + lane) * M + p] = x[0][p];
     __syncthreads();
     if (blk == 0 || !active) return;
 
     // fold: the start of this block
-    T y[M];
+    T y[1][M];
 #pragma unroll
-    for (int p = 0; p < M; ++p) y[p] = ends[lane * M + p];
+    for (int p = 0; p < M; ++p) y[0][p] = ends[lane * M + p];
     for (int k = 1; k < blk; ++k) {
         for (int i = k * a.fine_per; i < (k + 1) * a.fine_per; ++i) {
             const T* __restrict__ q = ph + ((size_t)i * a.m_rows + mm) * (M * M);
             T t[M];
 #pragma unroll
             for (int p = 0; p < M; ++p) {
-                T acc = q[p * M + M - 1] * y[M - 1];
+                T acc = q[p * M + M - 1] * y[0][M - 1];
 #pragma unroll
-                for (int c = M - 2; c >= 0; --c) acc = fma(q[p * M + c], y[c], acc);
+                for (int c = M - 2; c >= 0; --c) acc = fma(q[p * M + c], y[0][c], acc);
                 t[p] = acc;
             }
 #pragma unroll
-            for (int p = 0; p < M; ++p) y[p] = t[p];
+            for (int p = 0; p < M; ++p) y[0][p] = t[p];
         }
 #pragma unroll
-        for (int p = 0; p < M; ++p) y[p] += ends[(k * 64 + lane) * M + p];
+        for (int p = 0; p < M; ++p) y[0][p] += ends[(k * 64 + lane) * M + p];
     }
     // pass 2: this block again from its true start, with stores
     if (h == 0)
-        walk_gen<T, M, 1, true, true>(a.s, a.even, r_first, r_last, um, up, k0, k1, sc, fw, set_stride, a.n_sets, g,
+        walk_gen<T, M, 1, true, true, 1>(a.s, a.even, r_first, r_last, um, up, k0, k1, sc, fw, set_stride, a.n_sets, g,
                                       row, y);
     else
-        walk_gen<T, M, 1, false, true>(a.s, a.even, r_first, r_last, um, up, k0, k1, sc, fw, set_stride, a.n_sets,
+        walk_gen<T, M, 1, false, true, 1>(a.s, a.even, r_first, r_last, um, up, k0, k1, sc, fw, set_stride, a.n_sets,
                                        g, row, y);
 }
 
@@ -428,7 +429,7 @@ hipError_t dispatch_c2r(int log2h, const T* tw, int m_top, int rows, T* data, co
 hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, size_t south_off, uint64_t seed,
                             int count, void* out, int nch, hipStream_t st)
 {
-    if (nch != 1 && (nch != 2 || fp64 || g.order > 2)) return hipErrorInvalidValue;
+    if (nch != 1 && (nch != 2 || fp64)) return hipErrorInvalidValue;
     RecArgs a;
     a.n_theta = g.n_theta;
     a.n_phi = g.n_phi;
@@ -450,17 +451,24 @@ hipError_t launch_recursion(const Geometry& g, int fp64, const void* fac, size_t
     if (g.order >= 3) {
         if (fp64) {
             if (g.order == 3)
-                hipLaunchKernelGGL((recursion_gen_kernel<double, 3>), grid, dim3(256), 0, st, a, (const double*)fac,
+                hipLaunchKernelGGL((recursion_gen_kernel<double, 3, 1>), grid, dim3(256), 0, st, a, (const double*)fac,
                                    (double*)out);
             else
-                hipLaunchKernelGGL((recursion_gen_kernel<double, 4>), grid, dim3(256), 0, st, a, (const double*)fac,
+                hipLaunchKernelGGL((recursion_gen_kernel<double, 4, 1>), grid, dim3(256), 0, st, a, (const double*)fac,
                                    (double*)out);
-        } else {
+        } else if (nch == 2) {
             if (g.order == 3)
-                hipLaunchKernelGGL((recursion_gen_kernel<float, 3>), grid, dim3(256), 0, st, a, (const float*)fac,
+                hipLaunchKernelGGL((recursion_gen_kernel<float, 3, 2>), grid, dim3(256), 0, st, a, (const float*)fac,
                                    (float*)out);
             else
-                hipLaunchKernelGGL((recursion_gen_kernel<float, 4>), grid, dim3(256), 0, st, a, (const float*)fac,
+                hipLaunchKernelGGL((recursion_gen_kernel<float, 4, 2>), grid, dim3(256), 0, st, a, (const float*)fac,
+                                   (float*)out);
+        } else {
+            if (g.order == 3)
+                hipLaunchKernelGGL((recursion_gen_kernel<float, 3, 1>), grid, dim3(256), 0, st, a, (const float*)fac,
+                                   (float*)out);
+            else
+                hipLaunchKernelGGL((recursion_gen_kernel<float, 4, 1>), grid, dim3(256), 0, st, a, (const float*)fac,
                                    (float*)out);
         }
     } else if (fp64) {

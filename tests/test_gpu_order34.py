@@ -231,6 +231,19 @@ def test_high_order_layout_and_limits():
     plan.close()
 
 
+@pytest.mark.parametrize("order", [3, 4])
+def test_high_order_chains_per_lane_do_not_change_results(order):
+    """The plain recursion with two parts per lane (a 64-field call, 4096 one-part waves) and
+    with one (a 16-field call) give field 0 bit for bit."""
+    plan = _plan(order, 400.0, 1024, 2048, 1023, "fp32")
+    plan.set_ring_blocks(1)
+    a = plan.sample(9, 16)[0].clone()
+    b = plan.sample(9, 64)[0]
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    plan.close()
+
+
 def test_batch_with_orders_1_to_4():
     """The batched form on fields of every order: each field against the same field sampled
     alone with the plain recursion (the same chain arithmetic) and against the oracle."""

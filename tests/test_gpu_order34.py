@@ -293,3 +293,29 @@ def test_order3_large_single_field_modes():
         e = rel_rms(np.stack([g[f][:, ms].real, g[f][:, ms].imag]), np.stack([go[f].real, go[f].imag]))
         log(f"1024x2048 M3 fp32 field {f}: sampled modes vs oracle {e:.3e}")
         assert e <= TOL["fp32"]
+
+
+@pytest.mark.parametrize("blocks", [1, 4])
+def test_order3_on_a_grid_with_no_symmetry(blocks):
+    """Order 3 on shifted ring centres: the plan's 2 n_sets factor sets replaced by the
+    oracle's (northern, then the southern walk's in true coordinates), plain and scanned,
+    against the oracle's sampler with its southern sets (FP64, chain arithmetic only)."""
+    from paper_1709_10314_amd import workloads
+
+    z = workloads.shifted_z(48, 0.3)
+    kap, nphi, lmax = 900.0, 64, 47
+    C = oracle.spectrum([kap] * 3, lmax)
+    A, B, As, Bs = oracle.setup_asym(3, C, len(z), nphi, z)
+    To, _ = oracle.sample(3, len(z), nphi, A, B, 4, 2, south=(As, Bs))
+    plan = _plan(3, kap, len(z), nphi, lmax, "fp64", z=z)
+    assert not plan.symmetric
+    plan.set_factors(np.concatenate([A, As]), np.concatenate([B, Bs]))
+    plan.set_ring_blocks(blocks)
+    T = plan.sample(4, 2)
+    torch.cuda.synchronize()
+    T = T.cpu().numpy()
+    used = plan.ring_blocks(2)
+    plan.close()
+    e = max(rel_rms(T[f], To[f]) for f in range(2))
+    log(f"order 3, shifted grid, blocks {used}: {e:.3e}")
+    assert e <= 1e-10

@@ -16,6 +16,8 @@ the paper they follow:
 * ``philox``/``normal`` -- white-noise source (Philox4x32-10 + Box-Muller)
 * ``sample_modes``  -- the state-space recursion, both hemispheres   (Alg. 2; eq. (state_space))
 * ``dft``           -- inverse DFT along phi                         (Alg. 2, last step)
+* ``dft_rings``     -- the same sum at the pixels of rings with their own pixel
+                       counts and offsets (iso-latitude grids such as HEALPix, Sec. 1)
 """
 import ctypes
 import math
@@ -96,6 +98,8 @@ def _load():
     lib.orc_sample_modes_list.restype = _i
     lib.orc_dft.argtypes = [_i, _i, _i, _i, _i, _i, _pd, _pd]
     lib.orc_dft.restype = _i
+    lib.orc_dft_rings.argtypes = [_i, _i, _i, _pi, _pd, ctypes.POINTER(ctypes.c_int64), _pd, _pd]
+    lib.orc_dft_rings.restype = _i
     lib.orc_max_threads.restype = _i
     lib.orc_set_threads.argtypes = [_i]
     lib.orc_set_threads.restype = None
@@ -339,6 +343,30 @@ def dft(g, n_phi, r0=0, r1=None):
     gi[..., 1] = g.imag
     T = np.empty((count, r1 - r0, n_phi))
     _load().orc_dft(n_theta, n_phi, mt1 - 1, count, r0, r1, _p(gi), _p(T))
+    return T
+
+
+def ring_offsets(n_ring):
+    """Start of each ring in a field of rings with n_ring[i] pixels each (length n + 1)."""
+    return np.concatenate([[0], np.cumsum(np.asarray(n_ring, dtype=np.int64))])
+
+
+def dft_rings(g, n_ring, phi0):
+    """Alg. 2 last step on rings with their own pixel counts n_ring[i] and first-pixel
+    longitudes phi0[i]: T[count][sum n_ring], ring i at ring_offsets(n_ring)[i].  Every mode
+    of g is kept (those above n_ring[i] / 2 alias onto the ring's pixels)."""
+    count, n_theta, mt1 = g.shape
+    nr = np.ascontiguousarray(n_ring, dtype=np.int32)
+    p0 = np.ascontiguousarray(phi0, dtype=np.float64)
+    off = ring_offsets(nr)
+    assert nr.shape == (n_theta,) and p0.shape == (n_theta,) and np.all(nr >= 1)
+    gi = np.empty((count, n_theta, mt1, 2))
+    gi[..., 0] = g.real
+    gi[..., 1] = g.imag
+    T = np.empty((count, int(off[-1])))
+    rc = _load().orc_dft_rings(n_theta, mt1 - 1, count, nr.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _p(p0),
+                               off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _p(gi), _p(T))
+    assert rc == 0
     return T
 
 

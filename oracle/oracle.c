@@ -24,7 +24,9 @@
  *   - the state-space recursion outward from the equator, south half by mirror
  *                                               (eq. (state_space); Alg. 2; the
  *                                                symmetry remark after Alg. 1)
- *   - the inverse DFT along phi                 (Alg. 2, last step)
+ *   - the inverse DFT along phi                 (Alg. 2, last step), also on rings
+ *     with their own pixel counts and first-pixel longitudes (iso-latitude grids
+ *     such as HEALPix, which Sec. 1 names)
  *
  * Readings where the paper is silent or garbled (each is listed in the design notes):
  *   grid      theta_i = pi (i + 1/2) / n_theta, z_i = cos(theta_i), ring 0 nearest z = +1;
@@ -771,4 +773,52 @@ int orc_sample(int order, int n_theta, int n_phi, int m_top, const double* A, co
     int ns = orc_n_sets(n_theta);
     orc_sample_modes(order, n_theta, m_top, ns, A, B, seed, count, g_work);
     return orc_dft(n_theta, n_phi, m_top, count, 0, n_theta, g_work, T);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Alg. 2's last step on rings that each have their own pixel count n_i and   */
+/* first-pixel longitude phi0_i (iso-latitude grids such as HEALPix, Sec. 1): */
+/*   T(z_i, phi_ij) = g_0 + 2 sum_{m=1}^{m_top} Re(g_m e^{i m phi_ij}),          */
+/*   phi_ij = phi0_i + 2 pi j / n_i,  j < n_i,                                  */
+/* the same sum as orc_dft evaluated at each pixel; every mode is kept, also   */
+/* those above n_i / 2.  e^{i m phi_ij} = e^{i m phi0_i} e^{2 pi i k / n_i}     */
+/* with k = (m j) mod n_i.  g is [count][n_theta][m_top+1][2]; ring i of field  */
+/* f goes to T[f * off[n_theta] + off[i] + j], off[] the prefix sums of n_i.    */
+/* ------------------------------------------------------------------------- */
+int orc_dft_rings(int n_theta, int m_top, int count, const int* n_ring, const double* phi0,
+                  const int64_t* off, const double* g, double* T)
+{
+    const size_t row = (size_t)(m_top + 1) * 2;
+    const int64_t total = off[n_theta];
+    int bad = 0;
+#pragma omp parallel for collapse(2) schedule(dynamic, 1) reduction(| : bad)
+    for (int f = 0; f < count; ++f)
+        for (int i = 0; i < n_theta; ++i) {
+            const int n = n_ring[i];
+            const double* gr = g + ((size_t)f * n_theta + i) * row;
+            double* Tr = T + (size_t)f * total + off[i];
+            double* cs = (double*)malloc(sizeof(double) * 2 * (n + m_top + 1));
+            if (!cs) { bad = 1; continue; }
+            double* ph = cs + 2 * n;   /* e^{i m phi0}, m <= m_top */
+            for (int k = 0; k < n; ++k) {
+                cs[2 * k] = cos(2.0 * M_PI * k / n);
+                cs[2 * k + 1] = sin(2.0 * M_PI * k / n);
+            }
+            for (int m = 0; m <= m_top; ++m) {
+                ph[2 * m] = cos(m * phi0[i]);
+                ph[2 * m + 1] = sin(m * phi0[i]);
+            }
+            for (int j = 0; j < n; ++j) {
+                double acc = 0.0;
+                for (int m = 1; m <= m_top; ++m) {
+                    size_t k = ((size_t)m * j) % (size_t)n;
+                    double c = ph[2 * m] * cs[2 * k] - ph[2 * m + 1] * cs[2 * k + 1];
+                    double s = ph[2 * m + 1] * cs[2 * k] + ph[2 * m] * cs[2 * k + 1];
+                    acc += gr[2 * m] * c - gr[2 * m + 1] * s;
+                }
+                Tr[j] = gr[0] + 2.0 * acc;
+            }
+            free(cs);
+        }
+    return bad ? -1 : 0;
 }

@@ -92,3 +92,19 @@ def random_asym_z(n, seed=0):
 def shifted_z(n, shift=0.3):
     """Ring centres shifted by a fraction of a ring: z_i = cos(pi (i + shift) / n), shift in (0, 1)."""
     return np.cos(np.pi * (np.arange(n) + shift) / n)
+
+
+def healpix_rings(nside):
+    """A HEALPix ring layout (Gorski et al. 2005, ApJ 622, 759): the 4 nside - 1 ring
+    latitudes of healpix_ring_z, each ring k (1-based from the north) with its own pixel
+    count and the longitude of its first pixel.  Polar rings (k < nside, and their mirrors)
+    hold 4k pixels at phi_j = pi (j + 1/2) / (2k); belt rings hold 4 nside pixels at
+    phi_j = pi (j + s/2) / (2 nside), s = (k - nside + 1) mod 2.  Returns (z, n_phi, phi0)
+    with 12 nside^2 pixels in all."""
+    n = 4 * nside - 1
+    k = np.arange(1, n + 1)
+    kk = np.minimum(k, 4 * nside - k)
+    n_phi = np.where(kk < nside, 4 * kk, 4 * nside).astype(np.int32)
+    s = (k - nside + 1) % 2
+    phi0 = np.where(kk < nside, np.pi / (4.0 * kk), np.pi * s / (4.0 * nside))
+    return healpix_ring_z(nside), n_phi, phi0.astype(np.float64)

@@ -142,6 +142,38 @@ def high_order_leg(cfg, order, steps, warmup):
             "recursion_alu_frac": slots / (ms_rec * 1e-3) / VALU_PEAK_SLOTS}
 
 
+def healpix_leg(steps, warmup, nside=1024, order=2, kappa=50.0, count=8, seed=1):
+    """HEALPix rings (nside 1024: 4095 rings of 4k and 4 nside pixels, 12 nside^2 pixels per
+    field) at ell_max = 3 nside - 1, order 2, FP32, 8 fields: ms per smf_sample_rings call
+    (chains, then the ring synthesis) and per ring-synthesis launch, with the synthesis's
+    algorithmic bytes (modes m <= m_top read once, pixels written once)."""
+    import torch
+
+    from paper_1709_10314_amd import RingPlan, workloads
+
+    z, n_ring, phi0 = workloads.healpix_rings(nside)
+    lmax = 3 * nside - 1
+    t0 = time.perf_counter()
+    plan = RingPlan(order, n_ring, phi0, lmax, kappa=[kappa ** 2] * order, precision="fp32", z=z)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    work = plan.empty(count)
+    out = plan.empty_rings(count)
+    ms, _ = time_calls(lambda: plan.sample_rings(seed, count, out, work), steps, warmup)
+    plan.sample_modes(seed, count, work)
+    ms_syn, _ = time_calls(lambda: plan.synthesize_rings(work, count, out), steps, warmup)
+    pix = count * plan.pixels
+    alg = count * (plan.n_theta * (plan.m_top + 1) * 8 + plan.pixels * 4)
+    plan.close()
+    del work, out
+    torch.cuda.empty_cache()
+    return {"workload": f"healpix-{nside}-M{order}-fp32-x{count}", "nside": nside, "rings": len(z),
+            "pixels_per_field": int(n_ring.sum()), "ell_max": lmax, "order": order, "kappa": kappa,
+            "fields": count, "value": pix / ms * 1e3, "unit": "pixels/s", "ms_per_step": ms,
+            "synthesis_ms": ms_syn, "synthesis_alg_bytes": alg, "synthesis_alg_GBs": alg / (ms_syn * 1e-3) / 1e9,
+            "synthesis_hbm_frac": alg / (ms_syn * 1e-3) / 1e9 / HBM_PEAK_GBS, "setup_s": setup_s}
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch from committed rocprofv3 PMC summaries, if they were taken on
     the current kernel sources; else None."""
@@ -241,6 +273,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-high-order", action="store_true")
+    ap.add_argument("--no-healpix", action="store_true")
     ap.add_argument("--cpu-rings", type=int, default=384)
     ap.add_argument("--cpu-single-rings", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -356,6 +389,13 @@ def main():
                 f"({100 * h['recursion_alu_frac']:.0f}% of the VALU issue peak)")
             high.append(h)
 
+    hp = None
+    if not args.no_healpix:
+        log("HEALPix rings, nside 1024, order 2, 8 fields")
+        hp = healpix_leg(args.steps, args.warmup)
+        log(f"  {hp['ms_per_step']:.3f} ms/call ({hp['value']:.3e} pixels/s), ring synthesis "
+            f"{hp['synthesis_ms']:.3f} ms ({hp['synthesis_alg_GBs']:.0f} GB/s algorithmic), setup {hp['setup_s']:.1f} s")
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {args.cpu_rings} rings")
@@ -385,6 +425,7 @@ def main():
         "speedup_fp32_vs_fp64": (fp64["ms_per_step"] / ms_step) if fp64 else None,
         "batch_mix": batch,
         "higher_orders": high,
+        "healpix": hp,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

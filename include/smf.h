@@ -214,6 +214,40 @@ int smf_sample_batch(const smf_plan* plan, uint64_t seed, void* out_dev, void* h
  * Errors: SMF_EINVAL, SMF_EHIP. */
 int smf_autotune_batch(smf_plan* plan, uint64_t seed, void* out_dev, void* hip_stream, int* tiles_out);
 
+/* Rings with their own pixel counts (iso-latitude grids such as HEALPix, named in Sec. 1):
+ * ring i (latitude z_host[i], or the ring centres if z_host is NULL, same rules as
+ * smf_setup_grid) holds n_phi_ring[i] pixels at longitudes phi0[i] + 2 pi j / n_phi_ring[i],
+ * j < n_phi_ring[i].  The plan is that of smf_setup_grid on n_phi = the smallest power of
+ * two >= 2 (ell_max + 1), so m_top = ell_max and every mode is sampled (smf_plan_dims
+ * reports that n_phi; every call of a plan works on it), plus the ring table.  Host arrays
+ * of n_theta entries, copied.
+ * Errors: as smf_setup_grid, plus SMF_EINVAL for a NULL n_phi_ring or phi0, an odd
+ * n_phi_ring[i] or one outside [2, 8192] (SMF_FP32) or [2, 4096] (SMF_FP64), a phi0 that is
+ * not finite, or ell_max > 8191. */
+int smf_setup_rings(const smf_spectrum* spec, int n_theta, const double* z_host, const int* n_phi_ring,
+                    const double* phi0, int flags, void* hip_stream, smf_plan** out);
+
+/* Layout of a ring plan's fields: offsets[0..n_theta], ring i of a field at
+ * [offsets[i], offsets[i+1]); a field holds offsets[n_theta] values.
+ * Errors: SMF_EINVAL (NULL, not a ring plan). */
+int smf_ring_layout(const smf_plan* plan, int64_t* offsets);
+
+/* Alg. 2's last step on a ring plan's rings: with c_m = g_m e^{i m phi0[i]} and
+ * c_{-m} = conj(c_m), T(z_i, phi0[i] + 2 pi j / n) = sum_{|m| <= m_top} c_m e^{2 pi i m j / n},
+ * n = n_phi_ring[i]; modes above n / 2 alias onto the ring's pixels, none is dropped.
+ * g_dev: `count` fields of modes in the smf_sample_modes layout of the plan (read only);
+ * out_dev: count * offsets[n_theta] values of the plan's type, field f at
+ * f * offsets[n_theta].  The buffers must not overlap.  count = 0 is a no-op.
+ * Errors: SMF_EINVAL (NULL, not a ring plan, count < 0 or > 65535), SMF_EHIP. */
+int smf_synthesize_rings(const smf_plan* plan, int count, const void* g_dev, void* out_dev, void* hip_stream);
+
+/* smf_sample_modes into the caller's work buffer g_work (count * n_theta * n_phi values of
+ * the plan's type, n_phi as smf_plan_dims reports), then smf_synthesize_rings into out_dev.
+ * Field f uses Philox key seed + f.  Errors: as the two calls, plus SMF_EINVAL when g_work
+ * and out_dev are the same pointer. */
+int smf_sample_rings(const smf_plan* plan, uint64_t seed, int count, void* g_work, void* out_dev,
+                     void* hip_stream);
+
 /* Frees the plan and its device memory (synchronises the device first).  NULL is a
  * no-op. */
 int smf_destroy(smf_plan* plan);

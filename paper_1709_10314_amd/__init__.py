@@ -6,4 +6,4 @@ sampled outward from the equator, then an inverse FFT along phi gives the field.
 work runs in the HIP library libsmf.so (C ABI in include/smf.h); ``smf`` is its binding.
 """
 from . import smf  # noqa: F401
-from .smf import BatchPlan, Plan, SmfError  # noqa: F401
+from .smf import BatchPlan, Plan, RingPlan, SmfError  # noqa: F401

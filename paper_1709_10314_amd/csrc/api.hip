@@ -499,6 +499,92 @@ int smf_plan_grid(const smf_plan* plan, double* z_host, int* symmetric)
     return SMF_OK;
 }
 
+// Rings with their own pixel counts: the plan of smf_setup_grid on the smallest power of
+// two n_phi >= 2 (ell_max + 1), so that the chains produce every mode, plus the ring table.
+int smf_setup_rings(const smf_spectrum* spec, int n_theta, const double* z_host, const int* n_phi_ring,
+                    const double* phi0, int flags, void* hip_stream, smf_plan** out)
+{
+    if (!spec || !out || !n_phi_ring || !phi0 || n_theta < 2 || n_theta > (1 << 16)) return SMF_EINVAL;
+    *out = nullptr;
+    if (spec->ell_max < 0 || spec->ell_max > smf::kRingMaxEll) return SMF_EINVAL;
+    const bool fp64 = (flags & ~SMF_UBASIS) == SMF_FP64;
+    const int n_cap = fp64 ? smf::kRingMaxPixels64 : smf::kRingMaxPixels32;
+    int n_max = 0;
+    std::vector<int64_t> off((size_t)n_theta + 1, 0);
+    for (int i = 0; i < n_theta; ++i) {
+        const int n = n_phi_ring[i];
+        if (n < 2 || n > n_cap || (n & 1) || !std::isfinite(phi0[i])) return SMF_EINVAL;
+        n_max = std::max(n_max, n);
+        off[i + 1] = off[i] + n;
+    }
+    int n_phi = 4;
+    while (n_phi < 2 * (spec->ell_max + 1)) n_phi *= 2;
+    hipStream_t st = (hipStream_t)hip_stream;
+    int rc = setup_impl(spec, n_theta, z_host, n_phi, flags, st, true, out);
+    if (rc != SMF_OK) return rc;
+    smf_plan* plan = *out;
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, plan->device) != hipSuccess)
+        rc = SMF_EHIP;
+    else if (smf::ring_lds_bytes(n_max, fp64) > (size_t)lds_max)
+        rc = SMF_EINVAL;
+    plan->n_ring_max = n_max;
+    plan->ring_off = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n_theta + 1));
+    if (rc == SMF_OK && !plan->ring_off) rc = SMF_ENOMEM;
+    if (rc == SMF_OK) {
+        memcpy(plan->ring_off, off.data(), sizeof(int64_t) * ((size_t)n_theta + 1));
+        if (hipMalloc((void**)&plan->n_ring_dev, sizeof(int) * n_theta) != hipSuccess ||
+            hipMalloc((void**)&plan->phi0_dev, sizeof(double) * n_theta) != hipSuccess ||
+            hipMalloc((void**)&plan->ring_off_dev, sizeof(int64_t) * ((size_t)n_theta + 1)) != hipSuccess)
+            rc = SMF_ENOMEM;
+    }
+    if (rc == SMF_OK &&
+        (hipMemcpyAsync(plan->n_ring_dev, n_phi_ring, sizeof(int) * n_theta, hipMemcpyHostToDevice, st) !=
+             hipSuccess ||
+         hipMemcpyAsync(plan->phi0_dev, phi0, sizeof(double) * n_theta, hipMemcpyHostToDevice, st) != hipSuccess ||
+         hipMemcpyAsync(plan->ring_off_dev, plan->ring_off, sizeof(int64_t) * ((size_t)n_theta + 1),
+                        hipMemcpyHostToDevice, st) != hipSuccess ||
+         hipStreamSynchronize(st) != hipSuccess))
+        rc = SMF_EHIP;
+    if (rc != SMF_OK) {
+        smf_destroy(plan);
+        *out = nullptr;
+    }
+    return rc;
+}
+
+int smf_ring_layout(const smf_plan* plan, int64_t* offsets)
+{
+    if (!plan || plan->batch || !plan->n_ring_dev || !offsets) return SMF_EINVAL;
+    memcpy(offsets, plan->ring_off, sizeof(int64_t) * ((size_t)plan->g.n_theta + 1));
+    return SMF_OK;
+}
+
+int smf_synthesize_rings(const smf_plan* plan, int count, const void* g_dev, void* out_dev, void* hip_stream)
+{
+    if (!plan || plan->batch || !plan->n_ring_dev || count < 0 || count > smf::kRingMaxCount) return SMF_EINVAL;
+    if (count == 0) return SMF_OK;
+    if (!g_dev || !out_dev) return SMF_EINVAL;
+    DeviceGuard dg(plan->device);
+    const Geometry& g = plan->g;
+    return smf::launch_ring_c2r(g.n_theta, g.m_top, g.n_phi / 2, plan->ring_off[g.n_theta], plan->n_ring_max,
+                                plan->flags == SMF_FP64, count, g_dev, plan->n_ring_dev, plan->phi0_dev,
+                                plan->ring_off_dev, out_dev, (hipStream_t)hip_stream) == hipSuccess
+               ? SMF_OK
+               : SMF_EHIP;
+}
+
+int smf_sample_rings(const smf_plan* plan, uint64_t seed, int count, void* g_work, void* out_dev,
+                     void* hip_stream)
+{
+    if (!plan || plan->batch || !plan->n_ring_dev || count < 0 || count > smf::kRingMaxCount) return SMF_EINVAL;
+    if (count == 0) return SMF_OK;
+    if (!g_work || !out_dev || g_work == out_dev) return SMF_EINVAL;
+    const int rc = sample_common(plan, seed, count, g_work, hip_stream, false);
+    if (rc != SMF_OK) return rc;
+    return smf_synthesize_rings(plan, count, g_work, out_dev, hip_stream);
+}
+
 int smf_destroy(smf_plan* plan)
 {
     if (!plan) return SMF_OK;
@@ -522,6 +608,10 @@ int smf_destroy(smf_plan* plan)
     if (plan->phi64) (void)hipFree(plan->phi64);
     if (plan->phi32) (void)hipFree(plan->phi32);
     free(plan->zgrid);
+    if (plan->n_ring_dev) (void)hipFree(plan->n_ring_dev);
+    if (plan->phi0_dev) (void)hipFree(plan->phi0_dev);
+    if (plan->ring_off_dev) (void)hipFree(plan->ring_off_dev);
+    free(plan->ring_off);
     free(plan);
     return SMF_OK;
 }

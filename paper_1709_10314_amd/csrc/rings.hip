@@ -1,0 +1,231 @@
+// Alg. 2's last step on rings that each carry their own pixel count n_i and first-pixel
+// longitude phi0_i (iso-latitude grids such as HEALPix, which Sec. 1 names):
+//   T(z_i, phi0_i + 2 pi j / n_i) = sum_{|m| <= m_top} c_m e^{2 pi i m j / n_i},
+//   c_m = g_m e^{i m phi0_i},  c_{-m} = conj(c_m),
+// every mode kept.  Folding the modes onto the ring's n_i frequencies (B_k = sum of c_m
+// over m = k mod n_i) turns the sum into one complex-to-real inverse DFT of length n_i,
+// which runs as a complex inverse DFT of length h = n_i / 2 (the split of the ring C2R),
+// Stockham passes in LDS: a direct pass for each odd prime factor of h, then radix-4 and
+// radix-2 butterflies.
+#include "device_path.h"
+
+namespace smf {
+namespace {
+
+struct RingArgs {
+    int n_theta;
+    int m_top;
+    int g_row;        // complex values per ring in the mode buffer (n_phi / 2)
+    int64_t total;    // pixels of one field
+};
+
+constexpr int kRingThreads = 256;
+
+// Re-anchoring interval of the twiddle recurrence of the direct passes.
+constexpr int kRingAnchor = 16;
+
+// e^{+2 pi i k / n} for 0 <= k < n: Ft[k / 64] * Et[k mod 64] (two roundings of the type).
+template <typename T>
+__device__ __forceinline__ Cx<T> ring_tw(const Cx<T>* Et, const Cx<T>* Ft, int k)
+{
+    return cmul(Ft[k >> 6], Et[k & 63]);
+}
+
+// One workgroup per (ring, field): blockIdx.x is the ring, blockIdx.y the field.  LDS holds
+// two buffers of h + 1 complex values and small tables of the ring's twiddles and phases.
+template <typename T>
+__global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, const T* __restrict__ g,
+                                                                const int* __restrict__ n_ring,
+                                                                const double* __restrict__ phi0,
+                                                                const int64_t* __restrict__ off,
+                                                                T* __restrict__ out)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int i = blockIdx.x;
+    const int f = blockIdx.y;
+    const int n = n_ring[i];
+    const int h = n >> 1;
+    const int tid = threadIdx.x;
+    const int mt = a.m_top;
+    Cx<T>* buf0 = reinterpret_cast<Cx<T>*>(smem_raw);
+    Cx<T>* buf1 = buf0 + (h + 1);
+    // small FP64 tables: E_b = e^{2 pi i b / n}, F_a = e^{2 pi i 64 a / n}, G_b = e^{i b phi0},
+    // H_a = e^{i 64 a phi0} (b < 64); a mode's phase is the product of one H and one G,
+    // rounded once; Et, Ft: E and F rounded to the type, whose products are the twiddles
+    Cx<double>* E = reinterpret_cast<Cx<double>*>(buf1 + (h + 1));
+    const int na = n / 64 + 1;
+    const int ma = mt / 64 + 1;
+    Cx<double>* F = E + 64;
+    Cx<double>* G = F + na;
+    Cx<double>* H = G + 64;
+    Cx<T>* Et = reinterpret_cast<Cx<T>*>(H + ma);
+    Cx<T>* Ft = Et + 64;
+    const double p0 = phi0[i];
+    for (int k = tid; k < 128 + na + ma; k += kRingThreads) {
+        double s, c;
+        if (k < 64)
+            sincospi(2.0 * (double)k / (double)n, &s, &c);
+        else if (k < 64 + na)
+            sincospi(128.0 * (double)(k - 64) / (double)n, &s, &c);
+        else if (k < 128 + na)
+            sincos((double)(k - 64 - na) * p0, &s, &c);
+        else
+            sincos((double)(64 * (k - 128 - na)) * p0, &s, &c);
+        E[k] = {c, s};
+        if (k < 64 + na) Et[k] = {(T)c, (T)s};
+    }
+    __syncthreads();
+
+    // fold: B_k = sum_{m = k mod n} c_m + sum_{m = -k mod n, m >= 1} conj(c_m),  k <= h
+    const T* gr = g + ((size_t)f * a.n_theta + i) * (size_t)a.g_row * 2;
+    for (int k = tid; k <= h; k += kRingThreads) {
+        Cx<T> acc = {T(0), T(0)};
+        for (int m = k; m <= mt; m += n) {
+            const Cx<double> w = cmul(H[m >> 6], G[m & 63]);
+            const Cx<T> gm = {gr[2 * m], gr[2 * m + 1]};
+            acc = cadd(acc, cmul(gm, Cx<T>{(T)w.re, (T)w.im}));
+        }
+        for (int m = (k == 0 ? n : n - k); m <= mt; m += n) {
+            const Cx<double> w = cmul(H[m >> 6], G[m & 63]);
+            const Cx<T> gm = {gr[2 * m], gr[2 * m + 1]};
+            const Cx<T> cm = cmul(gm, Cx<T>{(T)w.re, (T)w.im});
+            acc = cadd(acc, Cx<T>{cm.re, -cm.im});
+        }
+        buf1[k] = acc;
+    }
+    __syncthreads();
+
+    // split: Z_k = (B_k + conj B_{h-k}) + i w^k (B_k - conj B_{h-k}),  k < h
+    for (int k = tid; k < h; k += kRingThreads) {
+        const Cx<T> x = buf1[k], y = buf1[h - k];
+        const Cx<T> yc = {y.re, -y.im};
+        const Cx<T> d = cmul(ring_tw(Et, Ft, k), csub(x, yc));
+        buf0[k] = cadd(cadd(x, yc), mul_i(d));
+    }
+    __syncthreads();
+
+    // inverse DFT of length h, Stockham: after a pass of radix R the data hold
+    // sub-transforms of length Ns * R in natural order
+    Cx<T>* src = buf0;
+    Cx<T>* dst = buf1;
+    int Ns = 1;
+    int rem = h;
+    while ((rem & 1) == 0) rem >>= 1;
+    int p = 3;
+    while (rem > 1) {
+        if (p * p > rem) p = rem;
+        if (rem % p) {
+            p += 2;
+            continue;
+        }
+        // direct pass of odd radix p: output u of each sub-transform sums its p inputs with
+        // twiddles W_t = e^{2 pi i t u / (Ns p)}, stepped by W_t = W_{t-1} W_1 and taken from
+        // the tables every kRingAnchor terms
+        const int NsR = Ns * p;
+        const int step = n / NsR;
+        const int hp = h / p;
+        for (int idx = tid; idx < h; idx += kRingThreads) {
+            const int b = idx / NsR;
+            const int u = idx - b * NsR;
+            const int j = b * Ns + u % Ns;
+            const Cx<T> w1 = ring_tw(Et, Ft, u * step);
+            Cx<T> acc = src[j];
+            Cx<T> W = w1;
+            for (int t = 1; t < p; ++t) {
+                if (t % kRingAnchor == 0)
+                    W = ring_tw(Et, Ft, ((t * u) % NsR) * step);
+                else if (t > 1)
+                    W = cmul(W, w1);
+                acc = cadd(acc, cmul(src[j + t * hp], W));
+            }
+            dst[idx] = acc;
+        }
+        __syncthreads();
+        Cx<T>* tmp = src;
+        src = dst;
+        dst = tmp;
+        Ns = NsR;
+        rem /= p;
+    }
+    while (h / Ns >= 4) {
+        const int q = h >> 2;
+        const int step = n / (4 * Ns);
+        for (int j = tid; j < q; j += kRingThreads) {
+            const int kq = j % Ns;
+            Cx<T> v[4];
+            v[0] = src[j];
+#pragma unroll
+            for (int t = 1; t < 4; ++t) v[t] = cmul(src[j + t * q], ring_tw(Et, Ft, t * kq * step));
+            dft_inv<T, 4>(v);
+            const int base = (j / Ns) * 4 * Ns + kq;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) dst[base + t * Ns] = v[t];
+        }
+        __syncthreads();
+        Cx<T>* tmp = src;
+        src = dst;
+        dst = tmp;
+        Ns *= 4;
+    }
+    if (h / Ns == 2) {
+        const int q = h >> 1;
+        const int step = n / (2 * Ns);
+        for (int j = tid; j < q; j += kRingThreads) {
+            const int kq = j % Ns;
+            Cx<T> v[2] = {src[j], cmul(src[j + q], ring_tw(Et, Ft, kq * step))};
+            dft_inv<T, 2>(v);
+            const int base = (j / Ns) * 2 * Ns + kq;
+            dst[base] = v[0];
+            dst[base + Ns] = v[1];
+        }
+        __syncthreads();
+        src = dst;
+    }
+
+    // T_{2j} = Re z_j, T_{2j+1} = Im z_j
+    using V2 = typename Vec2<T>::type;
+    V2* o = reinterpret_cast<V2*>(out + (size_t)f * a.total + off[i]);
+    for (int j = tid; j < h; j += kRingThreads) {
+        V2 w;
+        w.x = src[j].re;
+        w.y = src[j].im;
+        o[j] = w;
+    }
+}
+
+template <typename T>
+hipError_t launch_ring_c2r_t(const RingArgs& a, int count, int n_max, const T* g, const int* n_ring,
+                             const double* phi0, const int64_t* off, T* out, hipStream_t st)
+{
+    const size_t lds = ring_lds_bytes(n_max, sizeof(T) == 8);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)ring_c2r_kernel<T>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((ring_c2r_kernel<T>), dim3(a.n_theta, count), dim3(kRingThreads), lds, st, a, g, n_ring,
+                       phi0, off, out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t ring_lds_bytes(int n_max, bool fp64)
+{
+    const size_t cx = fp64 ? 16 : 8;
+    const size_t small = 128 + (size_t)(n_max / 64 + 1) + (size_t)(kRingMaxEll / 64 + 1);
+    return cx * ((size_t)2 * (n_max / 2 + 1) + 64 + (size_t)(n_max / 64 + 1)) + 16 * small;
+}
+
+hipError_t launch_ring_c2r(int n_theta, int m_top, int g_row, int64_t total, int n_max, bool fp64, int count,
+                           const void* g, const int* n_ring, const double* phi0, const int64_t* off, void* out,
+                           hipStream_t st)
+{
+    if (count <= 0 || count > 65535 || n_theta <= 0) return hipErrorInvalidValue;
+    const RingArgs a = {n_theta, m_top, g_row, total};
+    if (fp64)
+        return launch_ring_c2r_t<double>(a, count, n_max, (const double*)g, n_ring, phi0, off, (double*)out, st);
+    return launch_ring_c2r_t<float>(a, count, n_max, (const float*)g, n_ring, phi0, off, (float*)out, st);
+}
+
+}  // namespace smf

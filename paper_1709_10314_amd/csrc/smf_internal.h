@@ -106,6 +106,18 @@ hipError_t launch_scan(const Geometry& g, int fp64, const void* fac, size_t sout
                        size_t phi_south_off, int fine_blocks, int blocks, uint64_t seed, int count, void* out,
                        int nch, hipStream_t st);
 
+// Ring synthesis of a ring plan: the modes g ([count][n_theta][g_row] complex, m <= m_top)
+// to the pixels of rings with n_ring[i] pixels (even, <= n_max) starting at longitude
+// phi0[i], ring i of field f at out + f * total + off[i].  Device arrays n_ring, phi0, off.
+constexpr int kRingMaxEll = 8191;        // modes of the chains: n_phi <= 16384
+constexpr int kRingMaxPixels32 = 8192;   // largest ring: two buffers + twiddles in LDS
+constexpr int kRingMaxPixels64 = 4096;
+constexpr int kRingMaxCount = 65535;     // fields of one call (grid y)
+size_t ring_lds_bytes(int n_max, bool fp64);
+hipError_t launch_ring_c2r(int n_theta, int m_top, int g_row, int64_t total, int n_max, bool fp64, int count,
+                           const void* g, const int* n_ring, const double* phi0, const int64_t* off, void* out,
+                           hipStream_t st);
+
 }  // namespace smf
 
 namespace smf {
@@ -130,4 +142,10 @@ struct smf_plan {
     size_t south_off;         // elements from the northern to the southern factor table
     size_t phi_south_off;     // the same for the block transitions
     double* zgrid;            // host copy of an explicit grid (null: ring centres)
+    // rings with their own pixel counts (smf_setup_rings); n_ring_dev null otherwise
+    int* n_ring_dev;          // [n_theta] pixels per ring
+    double* phi0_dev;         // [n_theta] longitude of each ring's first pixel
+    int64_t* ring_off_dev;    // [n_theta + 1] start of each ring in a field
+    int64_t* ring_off;        // host copy
+    int n_ring_max;           // largest ring
 };

@@ -21,7 +21,8 @@ EXPORTS = ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", 
            "smf_get_ring_blocks",
            "smf_plan_dims", "smf_get_factors", "smf_set_factors", "smf_plan_grid",
            "smf_destroy", "smf_error_string", "smf_setup_batch", "smf_batch_layout",
-           "smf_sample_batch", "smf_autotune_batch")
+           "smf_sample_batch", "smf_autotune_batch", "smf_setup_rings", "smf_ring_layout",
+           "smf_synthesize_rings", "smf_sample_rings")
 
 
 class smf_spectrum(ctypes.Structure):
@@ -75,10 +76,17 @@ def load():
     lib.smf_batch_layout.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     lib.smf_sample_batch.argtypes = [vp, u64, vp, vp]
     lib.smf_autotune_batch.argtypes = [vp, u64, vp, vp, ctypes.POINTER(ctypes.c_int)]
+    lib.smf_setup_rings.argtypes = [ctypes.POINTER(smf_spectrum), i, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), i, vp,
+                                    ctypes.POINTER(vp)]
+    lib.smf_ring_layout.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.smf_synthesize_rings.argtypes = [vp, i, vp, vp, vp]
+    lib.smf_sample_rings.argtypes = [vp, u64, i, vp, vp, vp]
     for name in ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks", "smf_get_ring_blocks",
                  "smf_plan_dims",
                  "smf_get_factors", "smf_set_factors", "smf_plan_grid", "smf_destroy", "smf_setup_batch", "smf_batch_layout",
-                 "smf_sample_batch", "smf_autotune_batch"):
+                 "smf_sample_batch", "smf_autotune_batch", "smf_setup_rings", "smf_ring_layout",
+                 "smf_synthesize_rings", "smf_sample_rings"):
         getattr(lib, name).restype = i
     _lib = lib
     return lib
@@ -96,6 +104,61 @@ def _stream_handle(stream):
     if isinstance(stream, int):
         return ctypes.c_void_p(stream)
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _spectrum(order, ell_max, kappa, c_ell, keep):
+    spec = smf_spectrum()
+    spec.order = int(order)
+    spec.ell_max = int(ell_max)
+    if c_ell is not None:
+        c = np.ascontiguousarray(c_ell, dtype=np.float64)
+        keep.append(c)
+        spec.c_ell = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        spec.n_kappa = 0
+    else:
+        k = np.ascontiguousarray([] if kappa is None else kappa, dtype=np.float64).reshape(-1)
+        keep.append(k)
+        spec.n_kappa = len(k)
+        spec.kappa = k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if len(k) else None
+    return spec
+
+
+def smf_setup_rings(order, n_phi_ring, phi0, ell_max, kappa=None, c_ell=None, flags=SMF_FP32, stream=None,
+                    z=None):
+    """Returns (code, plan handle) of a ring plan: ring i with n_phi_ring[i] pixels from
+    longitude phi0[i]; z as in smf_setup (None: ring centres)."""
+    keep = []
+    spec = _spectrum(order, ell_max, kappa, c_ell, keep)
+    nr = np.ascontiguousarray(n_phi_ring, dtype=np.int32).reshape(-1)
+    p0 = np.ascontiguousarray(phi0, dtype=np.float64).reshape(-1)
+    plan = ctypes.c_void_p()
+    if len(p0) != len(nr) or (z is not None and len(z) != len(nr)):
+        return SMF_EINVAL, plan
+    zp = None
+    if z is not None:
+        zz = np.ascontiguousarray(z, dtype=np.float64).reshape(-1)
+        keep.append(zz)
+        zp = zz.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    rc = load().smf_setup_rings(ctypes.byref(spec), len(nr), zp, nr.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                p0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(flags),
+                                _stream_handle(stream), ctypes.byref(plan))
+    return rc, plan
+
+
+def smf_ring_layout(plan, n_theta):
+    off = (ctypes.c_int64 * (n_theta + 1))()
+    rc = load().smf_ring_layout(plan, off)
+    return rc, np.array([int(x) for x in off], dtype=np.int64)
+
+
+def smf_synthesize_rings(plan, count, g_ptr, out_ptr, stream=None):
+    return load().smf_synthesize_rings(plan, int(count), ctypes.c_void_p(g_ptr), ctypes.c_void_p(out_ptr),
+                                       _stream_handle(stream))
+
+
+def smf_sample_rings(plan, seed, count, g_ptr, out_ptr, stream=None):
+    return load().smf_sample_rings(plan, ctypes.c_uint64(int(seed)), int(count), ctypes.c_void_p(g_ptr),
+                                   ctypes.c_void_p(out_ptr), _stream_handle(stream))
 
 
 def smf_setup(order, n_theta, n_phi, ell_max, kappa=None, c_ell=None, flags=SMF_FP32, stream=None, z=None):
@@ -310,6 +373,9 @@ class Plan:
                           stream=stream, z=z)
         if rc != SMF_OK:
             raise SmfError(rc, "smf_setup" if z is None else "smf_setup_grid")
+        self._adopt(h)
+
+    def _adopt(self, h):
         self._h = h
         rc, d = smf_plan_dims(h)
         (self.order, self.n_theta, self.n_phi, self.ell_max, self.m_top, self.n_sets,
@@ -431,3 +497,60 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class RingPlan(Plan):
+    """A plan on rings with their own pixel counts and first-pixel longitudes (iso-latitude
+    grids such as HEALPix): every mode up to ell_max is sampled (the chains run at the
+    power-of-two n_phi that keeps them all) and each ring is synthesised at its own pixels."""
+
+    def __init__(self, order, n_phi_ring, phi0, ell_max, kappa=None, c_ell=None, precision="fp32",
+                 stream=None, z=None):
+        flags = {"fp32": SMF_FP32, "fp64": SMF_FP64}[precision]
+        rc, h = smf_setup_rings(order, n_phi_ring, phi0, ell_max, kappa=kappa, c_ell=c_ell, flags=flags,
+                                stream=stream, z=z)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_setup_rings")
+        self._adopt(h)
+        self.n_phi_ring = np.asarray(n_phi_ring, dtype=np.int32).copy()
+        self.phi0 = np.asarray(phi0, dtype=np.float64).copy()
+        rc, self.offsets = smf_ring_layout(h, self.n_theta)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_ring_layout")
+        self.pixels = int(self.offsets[-1])
+
+    def empty_rings(self, count, device="cuda"):
+        import torch
+
+        return torch.empty((count, self.pixels), dtype=self.dtype(), device=device)
+
+    def _check_rings(self, out, count):
+        if not out.is_cuda or out.dtype != self.dtype() or not out.is_contiguous():
+            raise ValueError("output must be a contiguous device tensor of the plan's dtype")
+        if out.numel() < count * self.pixels:
+            raise ValueError("output tensor too small")
+
+    def sample_rings(self, seed, count, out=None, work=None, stream=None):
+        """count fields keyed seed..seed+count-1 as a [count, pixels] tensor, ring i of a
+        field at offsets[i]; work: a mode buffer as sample_modes takes (allocated if None)."""
+        if out is None:
+            out = self.empty_rings(count)
+        if work is None:
+            work = self.empty(count)
+        self._check_rings(out, count)
+        self._check_out(work, count)
+        rc = smf_sample_rings(self._h, seed, count, work.data_ptr(), out.data_ptr(), stream)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_sample_rings")
+        return out.view(-1)[: count * self.pixels].view(count, self.pixels)
+
+    def synthesize_rings(self, g, count, out=None, stream=None):
+        """The rings of `count` fields of modes g (the sample_modes layout)."""
+        if out is None:
+            out = self.empty_rings(count)
+        self._check_rings(out, count)
+        self._check_out(g, count)
+        rc = smf_synthesize_rings(self._h, count, g.data_ptr(), out.data_ptr(), stream)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_synthesize_rings")
+        return out.view(-1)[: count * self.pixels].view(count, self.pixels)

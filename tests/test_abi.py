@@ -55,6 +55,10 @@ def test_error_strings_and_null_handling_without_gpu():
     assert lib.smf_plan_grid(None, None, None) == smf.SMF_EINVAL
     assert lib.smf_set_ring_blocks(None, 0) == smf.SMF_EINVAL
     assert lib.smf_get_ring_blocks(None, 1, None) == smf.SMF_EINVAL
+    assert lib.smf_setup_rings(None, 8, None, None, None, smf.SMF_FP32, None, None) == smf.SMF_EINVAL
+    assert lib.smf_ring_layout(None, None) == smf.SMF_EINVAL
+    assert lib.smf_synthesize_rings(None, 1, None, None, None) == smf.SMF_EINVAL
+    assert lib.smf_sample_rings(None, 1, 1, None, None, None) == smf.SMF_EINVAL
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):

@@ -526,7 +526,7 @@ int smf_setup_rings(const smf_spectrum* spec, int n_theta, const double* z_host,
     int lds_max = 0;
     if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, plan->device) != hipSuccess)
         rc = SMF_EHIP;
-    else if (smf::ring_lds_bytes(n_max, fp64) > (size_t)lds_max)
+    else if (smf::ring_lds_bytes(n_max, plan->g.m_top, fp64) > (size_t)lds_max)
         rc = SMF_EINVAL;
     plan->n_ring_max = n_max;
     plan->ring_off = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n_theta + 1));

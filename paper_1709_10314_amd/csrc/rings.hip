@@ -5,8 +5,8 @@
 // every mode kept.  Folding the modes onto the ring's n_i frequencies (B_k = sum of c_m
 // over m = k mod n_i) turns the sum into one complex-to-real inverse DFT of length n_i,
 // which runs as a complex inverse DFT of length h = n_i / 2 (the split of the ring C2R),
-// Stockham passes in LDS: a direct pass for each odd prime factor of h, then radix-4 and
-// radix-2 butterflies.
+// Stockham passes in LDS: a direct pass for each odd prime factor of h (the largest first),
+// then radix-4 and radix-2 butterflies.
 #include "device_path.h"
 
 namespace smf {
@@ -60,6 +60,7 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
     Cx<double>* H = G + 64;
     Cx<T>* Et = reinterpret_cast<Cx<T>*>(H + ma);
     Cx<T>* Ft = Et + 64;
+    Cx<T>* part = Ft + na;   // partial sums of the fold, kRingThreads values
     const double p0 = phi0[i];
     for (int k = tid; k < 128 + na + ma; k += kRingThreads) {
         double s, c;
@@ -76,22 +77,39 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
     }
     __syncthreads();
 
-    // fold: B_k = sum_{m = k mod n} c_m + sum_{m = -k mod n, m >= 1} conj(c_m),  k <= h
+    // fold: B_k = sum_{m = k mod n} c_m + sum_{m = -k mod n, m >= 1} conj(c_m),  k <= h.
+    // A ring with fewer than kRingThreads / 2 bins gives each bin `gs` threads, which sum
+    // every gs-th period of its modes; the partial sums are added in a fixed order.
     const T* gr = g + ((size_t)f * a.n_theta + i) * (size_t)a.g_row * 2;
-    for (int k = tid; k <= h; k += kRingThreads) {
+    const int nb = h + 1;
+    const int gs = nb >= kRingThreads ? 1 : kRingThreads / nb;
+    auto fold_bin = [&](int k, int g0) {
         Cx<T> acc = {T(0), T(0)};
-        for (int m = k; m <= mt; m += n) {
+#pragma unroll 2
+        for (int m = k + g0 * n; m <= mt; m += gs * n) {
             const Cx<double> w = cmul(H[m >> 6], G[m & 63]);
             const Cx<T> gm = {gr[2 * m], gr[2 * m + 1]};
             acc = cadd(acc, cmul(gm, Cx<T>{(T)w.re, (T)w.im}));
         }
-        for (int m = (k == 0 ? n : n - k); m <= mt; m += n) {
+#pragma unroll 2
+        for (int m = (k == 0 ? n : n - k) + g0 * n; m <= mt; m += gs * n) {
             const Cx<double> w = cmul(H[m >> 6], G[m & 63]);
             const Cx<T> gm = {gr[2 * m], gr[2 * m + 1]};
             const Cx<T> cm = cmul(gm, Cx<T>{(T)w.re, (T)w.im});
             acc = cadd(acc, Cx<T>{cm.re, -cm.im});
         }
-        buf1[k] = acc;
+        return acc;
+    };
+    if (gs == 1) {
+        for (int k = tid; k < nb; k += kRingThreads) buf1[k] = fold_bin(k, 0);
+    } else {
+        if (tid < nb * gs) part[tid] = fold_bin(tid % nb, tid / nb);
+        __syncthreads();
+        if (tid < nb) {
+            Cx<T> acc = part[tid];
+            for (int q = 1; q < gs; ++q) acc = cadd(acc, part[q * nb + tid]);
+            buf1[tid] = acc;
+        }
     }
     __syncthreads();
 
@@ -112,6 +130,54 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
     int rem = h;
     while ((rem & 1) == 0) rem >>= 1;
     int p = 3;
+    if (rem > 1) {
+        // the largest odd prime factor P first: with Ns = 1 the twiddles of inputs t and
+        // P - t are conjugate, so each pair costs one twiddle and four multiply-adds
+        int big = 3, r = rem;
+        while (r > 1) {
+            if (p * p > r) p = r;
+            if (r % p) {
+                p += 2;
+                continue;
+            }
+            big = p;
+            r /= p;
+        }
+        // outputs q and P - q have conjugate twiddles too: one thread makes both
+        const int P = big;
+        const int step = n / P;
+        const int hp = h / P;
+        const int half = (P + 1) / 2;
+        for (int idx = tid; idx < hp * half; idx += kRingThreads) {
+            const int b = idx / half;
+            const int q = idx - b * half;
+            const Cx<T> w1 = ring_tw(Et, Ft, q * step);
+            Cx<T> acc = src[b];
+            Cx<T> acc2 = acc;
+            Cx<T> W = w1;
+            for (int t = 1; 2 * t < P; ++t) {
+                if (t % kRingAnchor == 0)
+                    W = ring_tw(Et, Ft, ((t * q) % P) * step);
+                else if (t > 1)
+                    W = cmul(W, w1);
+                const Cx<T> x = src[b + t * hp], y = src[b + (P - t) * hp];
+                const Cx<T> sp = cadd(x, y), df = csub(x, y);
+                acc.re += sp.re * W.re - df.im * W.im;
+                acc.im += sp.im * W.re + df.re * W.im;
+                acc2.re += sp.re * W.re + df.im * W.im;
+                acc2.im += sp.im * W.re - df.re * W.im;
+            }
+            dst[b * P + q] = acc;
+            if (q > 0) dst[b * P + P - q] = acc2;
+        }
+        __syncthreads();
+        Cx<T>* tmp = src;
+        src = dst;
+        dst = tmp;
+        Ns = P;
+        rem /= P;
+        p = 3;
+    }
     while (rem > 1) {
         if (p * p > rem) p = rem;
         if (rem % p) {
@@ -197,7 +263,7 @@ template <typename T>
 hipError_t launch_ring_c2r_t(const RingArgs& a, int count, int n_max, const T* g, const int* n_ring,
                              const double* phi0, const int64_t* off, T* out, hipStream_t st)
 {
-    const size_t lds = ring_lds_bytes(n_max, sizeof(T) == 8);
+    const size_t lds = ring_lds_bytes(n_max, a.m_top, sizeof(T) == 8);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)ring_c2r_kernel<T>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -210,11 +276,11 @@ hipError_t launch_ring_c2r_t(const RingArgs& a, int count, int n_max, const T* g
 
 }  // namespace
 
-size_t ring_lds_bytes(int n_max, bool fp64)
+size_t ring_lds_bytes(int n_max, int m_top, bool fp64)
 {
     const size_t cx = fp64 ? 16 : 8;
-    const size_t small = 128 + (size_t)(n_max / 64 + 1) + (size_t)(kRingMaxEll / 64 + 1);
-    return cx * ((size_t)2 * (n_max / 2 + 1) + 64 + (size_t)(n_max / 64 + 1)) + 16 * small;
+    const size_t small = 128 + (size_t)(n_max / 64 + 1) + (size_t)(m_top / 64 + 1);
+    return cx * ((size_t)2 * (n_max / 2 + 1) + 64 + (size_t)(n_max / 64 + 1) + kRingThreads) + 16 * small;
 }
 
 hipError_t launch_ring_c2r(int n_theta, int m_top, int g_row, int64_t total, int n_max, bool fp64, int count,

@@ -113,7 +113,7 @@ constexpr int kRingMaxEll = 8191;        // modes of the chains: n_phi <= 16384
 constexpr int kRingMaxPixels32 = 8192;   // largest ring: two buffers + twiddles in LDS
 constexpr int kRingMaxPixels64 = 4096;
 constexpr int kRingMaxCount = 65535;     // fields of one call (grid y)
-size_t ring_lds_bytes(int n_max, bool fp64);
+size_t ring_lds_bytes(int n_max, int m_top, bool fp64);
 hipError_t launch_ring_c2r(int n_theta, int m_top, int g_row, int64_t total, int n_max, bool fp64, int count,
                            const void* g, const int* n_ring, const double* phi0, const int64_t* off, void* out,
                            hipStream_t st);

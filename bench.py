@@ -45,7 +45,7 @@ def log(msg):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("rng.h", "device_path.h", "sample.hip", "smf_internal.h"):
+    for f in ("rng.h", "device_path.h", "sample.hip", "rings.hip", "smf_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_1709_10314_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -171,7 +171,9 @@ def healpix_leg(steps, warmup, nside=1024, order=2, kappa=50.0, count=8, seed=1)
             "pixels_per_field": int(n_ring.sum()), "ell_max": lmax, "order": order, "kappa": kappa,
             "fields": count, "value": pix / ms * 1e3, "unit": "pixels/s", "ms_per_step": ms,
             "synthesis_ms": ms_syn, "synthesis_alg_bytes": alg, "synthesis_alg_GBs": alg / (ms_syn * 1e-3) / 1e9,
-            "synthesis_hbm_frac": alg / (ms_syn * 1e-3) / 1e9 / HBM_PEAK_GBS, "setup_s": setup_s}
+            "synthesis_hbm_frac": alg / (ms_syn * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "synthesis_traffic": measured_traffic("ring_c2r_healpix1024") if nside == 1024 and count == 8 else None,
+            "setup_s": setup_s}
 
 
 def measured_traffic(kernel):

@@ -523,10 +523,33 @@ int smf_setup_rings(const smf_spectrum* spec, int n_theta, const double* z_host,
     int rc = setup_impl(spec, n_theta, z_host, n_phi, flags, st, true, out);
     if (rc != SMF_OK) return rc;
     smf_plan* plan = *out;
+    // rings whose largest odd prime P (of n / 2) is at least SMF_RING_CHIRP_MIN and whose
+    // chirp-z length fits take the chirp-z pass in a launch of their own
+    std::vector<int> direct, chirp;
+    smf::RingSplit rs = {0, 0, 0, 0, 0};
+    const int l_cap = fp64 ? smf::kRingChirpMaxL64 : smf::kRingChirpMaxL32;
+    for (int i = 0; i < n_theta; ++i) {
+        const int P = smf::ring_largest_odd_prime(n_phi_ring[i] / 2);
+        int L = 1;
+        while (L < 2 * P - 1) L <<= 1;
+        if (P >= SMF_RING_CHIRP_MIN && L <= l_cap) {
+            chirp.push_back(i);
+            rs.n_max_chirp = std::max(rs.n_max_chirp, n_phi_ring[i]);
+            rs.l_max = std::max(rs.l_max, L);
+        } else {
+            direct.push_back(i);
+            rs.n_max_direct = std::max(rs.n_max_direct, n_phi_ring[i]);
+        }
+    }
+    rs.n_direct = (int)direct.size();
+    rs.n_chirp = (int)chirp.size();
+    direct.insert(direct.end(), chirp.begin(), chirp.end());
+    plan->ring_split = rs;
     int lds_max = 0;
     if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, plan->device) != hipSuccess)
         rc = SMF_EHIP;
-    else if (smf::ring_lds_bytes(n_max, plan->g.m_top, fp64) > (size_t)lds_max)
+    else if (smf::ring_lds_bytes(rs.n_max_direct, plan->g.m_top, fp64) > (size_t)lds_max ||
+             smf::ring_lds_bytes(rs.n_max_chirp, plan->g.m_top, fp64, rs.l_max) > (size_t)lds_max)
         rc = SMF_EINVAL;
     plan->n_ring_max = n_max;
     plan->ring_off = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n_theta + 1));
@@ -535,7 +558,8 @@ int smf_setup_rings(const smf_spectrum* spec, int n_theta, const double* z_host,
         memcpy(plan->ring_off, off.data(), sizeof(int64_t) * ((size_t)n_theta + 1));
         if (hipMalloc((void**)&plan->n_ring_dev, sizeof(int) * n_theta) != hipSuccess ||
             hipMalloc((void**)&plan->phi0_dev, sizeof(double) * n_theta) != hipSuccess ||
-            hipMalloc((void**)&plan->ring_off_dev, sizeof(int64_t) * ((size_t)n_theta + 1)) != hipSuccess)
+            hipMalloc((void**)&plan->ring_off_dev, sizeof(int64_t) * ((size_t)n_theta + 1)) != hipSuccess ||
+            hipMalloc((void**)&plan->ring_list_dev, sizeof(int) * n_theta) != hipSuccess)
             rc = SMF_ENOMEM;
     }
     if (rc == SMF_OK &&
@@ -544,6 +568,8 @@ int smf_setup_rings(const smf_spectrum* spec, int n_theta, const double* z_host,
          hipMemcpyAsync(plan->phi0_dev, phi0, sizeof(double) * n_theta, hipMemcpyHostToDevice, st) != hipSuccess ||
          hipMemcpyAsync(plan->ring_off_dev, plan->ring_off, sizeof(int64_t) * ((size_t)n_theta + 1),
                         hipMemcpyHostToDevice, st) != hipSuccess ||
+         hipMemcpyAsync(plan->ring_list_dev, direct.data(), sizeof(int) * n_theta, hipMemcpyHostToDevice, st) !=
+             hipSuccess ||
          hipStreamSynchronize(st) != hipSuccess))
         rc = SMF_EHIP;
     if (rc != SMF_OK) {
@@ -567,9 +593,9 @@ int smf_synthesize_rings(const smf_plan* plan, int count, const void* g_dev, voi
     if (!g_dev || !out_dev) return SMF_EINVAL;
     DeviceGuard dg(plan->device);
     const Geometry& g = plan->g;
-    return smf::launch_ring_c2r(g.n_theta, g.m_top, g.n_phi / 2, plan->ring_off[g.n_theta], plan->n_ring_max,
-                                plan->flags == SMF_FP64, count, g_dev, plan->n_ring_dev, plan->phi0_dev,
-                                plan->ring_off_dev, out_dev, (hipStream_t)hip_stream) == hipSuccess
+    return smf::launch_ring_c2r(g.n_theta, g.m_top, g.n_phi / 2, plan->ring_off[g.n_theta], plan->ring_split,
+                                plan->flags == SMF_FP64, count, g_dev, plan->ring_list_dev, plan->n_ring_dev,
+                                plan->phi0_dev, plan->ring_off_dev, out_dev, (hipStream_t)hip_stream) == hipSuccess
                ? SMF_OK
                : SMF_EHIP;
 }
@@ -611,6 +637,7 @@ int smf_destroy(smf_plan* plan)
     if (plan->n_ring_dev) (void)hipFree(plan->n_ring_dev);
     if (plan->phi0_dev) (void)hipFree(plan->phi0_dev);
     if (plan->ring_off_dev) (void)hipFree(plan->ring_off_dev);
+    if (plan->ring_list_dev) (void)hipFree(plan->ring_list_dev);
     free(plan->ring_off);
     free(plan);
     return SMF_OK;

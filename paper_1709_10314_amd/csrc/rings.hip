@@ -5,8 +5,9 @@
 // every mode kept.  Folding the modes onto the ring's n_i frequencies (B_k = sum of c_m
 // over m = k mod n_i) turns the sum into one complex-to-real inverse DFT of length n_i,
 // which runs as a complex inverse DFT of length h = n_i / 2 (the split of the ring C2R),
-// Stockham passes in LDS: a direct pass for each odd prime factor of h (the largest first),
-// then radix-4 and radix-2 butterflies.
+// Stockham passes in LDS: a pass for each odd prime factor of h (the largest first; direct,
+// or for a large prime P Bluestein's chirp-z form, the length-P DFT as a convolution done by
+// power-of-two FFTs), then radix-4 and radix-2 butterflies.
 #include "device_path.h"
 
 namespace smf {
@@ -17,6 +18,7 @@ struct RingArgs {
     int m_top;
     int g_row;        // complex values per ring in the mode buffer (n_phi / 2)
     int64_t total;    // pixels of one field
+    const int* list;  // rings of this launch (blockIdx.x indexes it)
 };
 
 constexpr int kRingThreads = 256;
@@ -31,9 +33,54 @@ __device__ __forceinline__ Cx<T> ring_tw(const Cx<T>* Et, const Cx<T>* Ft, int k
     return cmul(Ft[k >> 6], Et[k & 63]);
 }
 
-// One workgroup per (ring, field): blockIdx.x is the ring, blockIdx.y the field.  LDS holds
-// two buffers of h + 1 complex values and small tables of the ring's twiddles and phases.
+// In-place radix-2 FFTs of a power-of-two length L in LDS for the chirp-z pass: the forward
+// one (e^{-2 pi i}) by decimation in frequency, natural order in and bit-reversed order out;
+// the inverse (e^{+2 pi i}, unscaled) by decimation in time, bit-reversed in and natural out.
+// Twiddles e^{2 pi i k / L} = FL[k / 64] EL[k mod 64].  Each stage ends with a barrier.
 template <typename T>
+__device__ void lds_fft_fwd(Cx<T>* x, int L, const Cx<T>* EL, const Cx<T>* FL, int tid)
+{
+    for (int half = L >> 1; half >= 1; half >>= 1) {
+        const int stride = L / (2 * half);
+        for (int t = tid; t < (L >> 1); t += kRingThreads) {
+            const int gi = t / half;
+            const int pos = t - gi * half;
+            const int i0 = gi * 2 * half + pos;
+            const int i1 = i0 + half;
+            const Cx<T> u = x[i0], v = x[i1];
+            const Cx<T> w = ring_tw(EL, FL, pos * stride);
+            x[i0] = cadd(u, v);
+            x[i1] = cmul(csub(u, v), Cx<T>{w.re, -w.im});
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__device__ void lds_fft_inv(Cx<T>* x, int L, const Cx<T>* EL, const Cx<T>* FL, int tid)
+{
+    for (int half = 1; half < L; half <<= 1) {
+        const int stride = L / (2 * half);
+        for (int t = tid; t < (L >> 1); t += kRingThreads) {
+            const int gi = t / half;
+            const int pos = t - gi * half;
+            const int i0 = gi * 2 * half + pos;
+            const int i1 = i0 + half;
+            const Cx<T> u = x[i0];
+            const Cx<T> v = cmul(x[i1], ring_tw(EL, FL, pos * stride));
+            x[i0] = cadd(u, v);
+            x[i1] = csub(u, v);
+        }
+        __syncthreads();
+    }
+}
+
+// One workgroup per (ring, field): blockIdx.x picks the ring from the launch's list,
+// blockIdx.y is the field.  LDS holds two buffers of h + 1 complex values and small tables of
+// the ring's twiddles and phases; with BLUE (the rings whose largest odd prime P takes the
+// chirp-z pass) also two convolution buffers of L >= 2P - 1 values and the tables of their
+// twiddles.
+template <typename T, bool BLUE>
 __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, const T* __restrict__ g,
                                                                 const int* __restrict__ n_ring,
                                                                 const double* __restrict__ phi0,
@@ -41,7 +88,7 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
                                                                 T* __restrict__ out)
 {
     extern __shared__ unsigned char smem_raw[];
-    const int i = blockIdx.x;
+    const int i = a.list[blockIdx.x];
     const int f = blockIdx.y;
     const int n = n_ring[i];
     const int h = n >> 1;
@@ -148,7 +195,49 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
         const int step = n / P;
         const int hp = h / P;
         const int half = (P + 1) / 2;
-        for (int idx = tid; idx < hp * half; idx += kRingThreads) {
+        if (BLUE) {
+            // chirp-z: with c_k = e^{i pi k^2 / P} (= e^{2 pi i ((k^2 mod 2P) hp) / n}),
+            // X_q = c_q sum_t (x_t c_t) conj(c_{q-t}), a cyclic convolution of length
+            // L >= 2P - 1 with the spectrum of conj(c) computed once per ring
+            int L = 1;
+            while (L < 2 * P - 1) L <<= 1;
+            Cx<T>* wa = part + kRingThreads;
+            Cx<T>* wd = wa + L;
+            Cx<T>* EL = wd + L;
+            Cx<T>* FL = EL + 64;
+            for (int k = tid; k < 64 + L / 64 + 1; k += kRingThreads) {
+                double sn, cs;
+                sincospi((k < 64 ? 2.0 * (double)k : 128.0 * (double)(k - 64)) / (double)L, &sn, &cs);
+                EL[k] = {(T)cs, (T)sn};
+            }
+            auto chirp = [&](int k) { return ring_tw(Et, Ft, (int)(((long)k * k) % (2 * P)) * hp); };
+            for (int k = tid; k < L; k += kRingThreads) {
+                Cx<T> v = {T(0), T(0)};
+                if (k < P)
+                    v = chirp(k);
+                else if (k > L - P)
+                    v = chirp(L - k);
+                wd[k] = {v.re, -v.im};
+            }
+            __syncthreads();
+            lds_fft_fwd(wd, L, EL, FL, tid);
+            const T inv = T(1) / (T)L;
+            for (int b = 0; b < hp; ++b) {
+                for (int k = tid; k < L; k += kRingThreads)
+                    wa[k] = k < P ? cmul(src[b + k * hp], chirp(k)) : Cx<T>{T(0), T(0)};
+                __syncthreads();
+                lds_fft_fwd(wa, L, EL, FL, tid);
+                for (int k = tid; k < L; k += kRingThreads) wa[k] = cmul(wa[k], wd[k]);
+                __syncthreads();
+                lds_fft_inv(wa, L, EL, FL, tid);
+                for (int q = tid; q < P; q += kRingThreads) {
+                    const Cx<T> r = cmul(wa[q], chirp(q));
+                    dst[b * P + q] = {r.re * inv, r.im * inv};
+                }
+                __syncthreads();
+            }
+        }
+        for (int idx = tid; !BLUE && idx < hp * half; idx += kRingThreads) {
             const int b = idx / half;
             const int q = idx - b * half;
             const Cx<T> w1 = ring_tw(Et, Ft, q * step);
@@ -259,39 +348,73 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
     }
 }
 
-template <typename T>
-hipError_t launch_ring_c2r_t(const RingArgs& a, int count, int n_max, const T* g, const int* n_ring,
+template <typename T, bool BLUE>
+hipError_t launch_ring_c2r_t(const RingArgs& a, int rings, int count, size_t lds, const T* g, const int* n_ring,
                              const double* phi0, const int64_t* off, T* out, hipStream_t st)
 {
-    const size_t lds = ring_lds_bytes(n_max, a.m_top, sizeof(T) == 8);
+    if (rings == 0) return hipSuccess;
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)ring_c2r_kernel<T>,
+        hipError_t e = hipFuncSetAttribute((const void*)ring_c2r_kernel<T, BLUE>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((ring_c2r_kernel<T>), dim3(a.n_theta, count), dim3(kRingThreads), lds, st, a, g, n_ring,
+    hipLaunchKernelGGL((ring_c2r_kernel<T, BLUE>), dim3(rings, count), dim3(kRingThreads), lds, st, a, g, n_ring,
                        phi0, off, out);
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_ring_pair(const RingArgs& a, const RingSplit& rs, int count, const T* g, const int* n_ring,
+                            const double* phi0, const int64_t* off, T* out, hipStream_t st)
+{
+    const bool fp64 = sizeof(T) == 8;
+    RingArgs ab = a;
+    ab.list = a.list + rs.n_direct;
+    hipError_t e = launch_ring_c2r_t<T, false>(a, rs.n_direct, count, ring_lds_bytes(rs.n_max_direct, a.m_top, fp64),
+                                               g, n_ring, phi0, off, out, st);
+    if (e != hipSuccess) return e;
+    return launch_ring_c2r_t<T, true>(ab, rs.n_chirp, count,
+                                      ring_lds_bytes(rs.n_max_chirp, a.m_top, fp64, rs.l_max), g, n_ring, phi0, off,
+                                      out, st);
+}
+
 }  // namespace
 
-size_t ring_lds_bytes(int n_max, int m_top, bool fp64)
+size_t ring_lds_bytes(int n_max, int m_top, bool fp64, int l_max)
 {
     const size_t cx = fp64 ? 16 : 8;
     const size_t small = 128 + (size_t)(n_max / 64 + 1) + (size_t)(m_top / 64 + 1);
-    return cx * ((size_t)2 * (n_max / 2 + 1) + 64 + (size_t)(n_max / 64 + 1) + kRingThreads) + 16 * small;
+    size_t b = cx * ((size_t)2 * (n_max / 2 + 1) + 64 + (size_t)(n_max / 64 + 1) + kRingThreads) + 16 * small;
+    if (l_max > 0) b += cx * ((size_t)2 * l_max + 64 + (size_t)(l_max / 64 + 1));
+    return b;
 }
 
-hipError_t launch_ring_c2r(int n_theta, int m_top, int g_row, int64_t total, int n_max, bool fp64, int count,
-                           const void* g, const int* n_ring, const double* phi0, const int64_t* off, void* out,
-                           hipStream_t st)
+int ring_largest_odd_prime(int h)
 {
-    if (count <= 0 || count > 65535 || n_theta <= 0) return hipErrorInvalidValue;
-    const RingArgs a = {n_theta, m_top, g_row, total};
+    int r = h;
+    while (r > 0 && (r & 1) == 0) r >>= 1;
+    int big = 1, p = 3;
+    while (r > 1) {
+        if (p * p > r) p = r;
+        if (r % p) {
+            p += 2;
+            continue;
+        }
+        big = p;
+        r /= p;
+    }
+    return big;
+}
+
+hipError_t launch_ring_c2r(int n_theta, int m_top, int g_row, int64_t total, const RingSplit& rs, bool fp64,
+                           int count, const void* g, const int* list, const int* n_ring, const double* phi0,
+                           const int64_t* off, void* out, hipStream_t st)
+{
+    if (count <= 0 || count > 65535 || n_theta <= 0 || rs.n_direct + rs.n_chirp != n_theta) return hipErrorInvalidValue;
+    const RingArgs a = {n_theta, m_top, g_row, total, list};
     if (fp64)
-        return launch_ring_c2r_t<double>(a, count, n_max, (const double*)g, n_ring, phi0, off, (double*)out, st);
-    return launch_ring_c2r_t<float>(a, count, n_max, (const float*)g, n_ring, phi0, off, (float*)out, st);
+        return launch_ring_pair<double>(a, rs, count, (const double*)g, n_ring, phi0, off, (double*)out, st);
+    return launch_ring_pair<float>(a, rs, count, (const float*)g, n_ring, phi0, off, (float*)out, st);
 }
 
 }  // namespace smf

@@ -107,16 +107,31 @@ hipError_t launch_scan(const Geometry& g, int fp64, const void* fac, size_t sout
                        int nch, hipStream_t st);
 
 // Ring synthesis of a ring plan: the modes g ([count][n_theta][g_row] complex, m <= m_top)
-// to the pixels of rings with n_ring[i] pixels (even, <= n_max) starting at longitude
-// phi0[i], ring i of field f at out + f * total + off[i].  Device arrays n_ring, phi0, off.
+// to the pixels of rings with n_ring[i] pixels (even) starting at longitude phi0[i], ring i
+// of field f at out + f * total + off[i].  Device arrays list, n_ring, phi0, off; list holds
+// the n_direct rings whose odd prime passes are all direct, then the n_chirp rings whose
+// largest odd prime P (of n_ring / 2) takes the chirp-z pass, L = the power of two >= 2P - 1.
 constexpr int kRingMaxEll = 8191;        // modes of the chains: n_phi <= 16384
-constexpr int kRingMaxPixels32 = 8192;   // largest ring: two buffers + twiddles in LDS
+constexpr int kRingMaxPixels32 = 8192;   // largest ring: two buffers + small tables in LDS
 constexpr int kRingMaxPixels64 = 4096;
 constexpr int kRingMaxCount = 65535;     // fields of one call (grid y)
-size_t ring_lds_bytes(int n_max, int m_top, bool fp64);
-hipError_t launch_ring_c2r(int n_theta, int m_top, int g_row, int64_t total, int n_max, bool fp64, int count,
-                           const void* g, const int* n_ring, const double* phi0, const int64_t* off, void* out,
-                           hipStream_t st);
+// Smallest prime that takes the chirp-z pass (measured on HEALPix nside 1024 x 8 fields: 1.003 ms
+// with none, 1.21 ms from 127, 0.984 ms from 383 or 761, 1.07 ms from 1021)
+#ifndef SMF_RING_CHIRP_MIN
+#define SMF_RING_CHIRP_MIN 383
+#endif
+constexpr int kRingChirpMaxL32 = 4096;   // largest chirp-z length (LDS)
+constexpr int kRingChirpMaxL64 = 2048;
+struct RingSplit {
+    int n_direct, n_chirp;            // rings of each launch
+    int n_max_direct, n_max_chirp;    // largest ring of each
+    int l_max;                        // largest chirp-z length
+};
+size_t ring_lds_bytes(int n_max, int m_top, bool fp64, int l_max = 0);
+int ring_largest_odd_prime(int h);    // 1 when h is a power of two
+hipError_t launch_ring_c2r(int n_theta, int m_top, int g_row, int64_t total, const RingSplit& rs, bool fp64,
+                           int count, const void* g, const int* list, const int* n_ring, const double* phi0,
+                           const int64_t* off, void* out, hipStream_t st);
 
 }  // namespace smf
 
@@ -148,4 +163,6 @@ struct smf_plan {
     int64_t* ring_off_dev;    // [n_theta + 1] start of each ring in a field
     int64_t* ring_off;        // host copy
     int n_ring_max;           // largest ring
+    int* ring_list_dev;       // [n_theta] rings by launch (direct, then chirp-z)
+    smf::RingSplit ring_split;
 };

@@ -215,3 +215,32 @@ def test_ring_plan_arguments():
     p.close()
     with pytest.raises(SmfError):
         _ring_plan(np.array([4]), np.array([0.0]), 3, "fp32")   # one ring: n_theta < 2
+
+
+def test_sample_rings_graph_capture_replays():
+    """smf_sample_rings (chains, then both ring launches) captured in a HIP graph: every replay,
+    with eager work and synchronisations between replays, equals the eager call."""
+    z, n_ring, phi0 = _healpix(32)
+    n_ring = n_ring.copy()
+    n_ring[3] = 2 * 509          # one ring takes the chirp-z launch
+    plan = _ring_plan(n_ring, phi0, 95, "fp32", order=2, kap=900.0, z=z)
+    eager = plan.sample_rings(13, 2).clone()
+    torch.cuda.synchronize()
+    out = plan.empty_rings(2)
+    work = plan.empty(2)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.sample_rings(13, 2, out, work, stream=s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        plan.sample_rings(13, 2, out, work, stream=s)
+    for rep in range(3):
+        out.zero_()
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+        del junk
+    plan.close()

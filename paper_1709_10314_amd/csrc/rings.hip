@@ -25,6 +25,8 @@ constexpr int kRingThreads = 256;
 
 // Re-anchoring interval of the twiddle recurrence of the direct passes.
 constexpr int kRingAnchor = 16;
+// Bins per thread whose first-period modes are loaded ahead of the table work.
+constexpr int kRingPre = 8;
 
 // e^{+2 pi i k / n} for 0 <= k < n: Ft[k / 64] * Et[k mod 64] (two roundings of the type).
 template <typename T>
@@ -109,6 +111,25 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
     Cx<T>* Ft = Et + 64;
     Cx<T>* part = Ft + na;   // partial sums of the fold, kRingThreads values
     const double p0 = phi0[i];
+
+    // the modes of the first period of this thread's first kRingPre bins (m = k and m = n - k),
+    // loaded before the tables are built so that their latency overlaps that work
+    using V2 = typename Vec2<T>::type;
+    const T* gr = g + ((size_t)f * a.n_theta + i) * (size_t)a.g_row * 2;
+    const V2* gv = reinterpret_cast<const V2*>(gr);
+    const int nb = h + 1;
+    const int gs = nb >= kRingThreads ? 1 : kRingThreads / nb;
+    V2 pre_p[kRingPre], pre_n[kRingPre];
+    if (gs == 1) {
+#pragma unroll
+        for (int r = 0; r < kRingPre; ++r) {
+            const int k = tid + r * kRingThreads;
+            const int mn = k == 0 ? n : n - k;
+            pre_p[r] = (k < nb && k <= mt) ? gv[k] : V2{T(0), T(0)};
+            pre_n[r] = (k < nb && mn <= mt) ? gv[mn] : V2{T(0), T(0)};
+        }
+    }
+
     for (int k = tid; k < 128 + na + ma; k += kRingThreads) {
         double s, c;
         if (k < 64)
@@ -127,9 +148,10 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
     // fold: B_k = sum_{m = k mod n} c_m + sum_{m = -k mod n, m >= 1} conj(c_m),  k <= h.
     // A ring with fewer than kRingThreads / 2 bins gives each bin `gs` threads, which sum
     // every gs-th period of its modes; the partial sums are added in a fixed order.
-    const T* gr = g + ((size_t)f * a.n_theta + i) * (size_t)a.g_row * 2;
-    const int nb = h + 1;
-    const int gs = nb >= kRingThreads ? 1 : kRingThreads / nb;
+    auto phase = [&](int m) {
+        const Cx<double> w = cmul(H[m >> 6], G[m & 63]);
+        return Cx<T>{(T)w.re, (T)w.im};
+    };
     auto fold_bin = [&](int k, int g0) {
         Cx<T> acc = {T(0), T(0)};
 #pragma unroll 2
@@ -148,7 +170,28 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
         return acc;
     };
     if (gs == 1) {
-        for (int k = tid; k < nb; k += kRingThreads) buf1[k] = fold_bin(k, 0);
+        // bins from the prefetched first period, then any further periods (modes above n)
+#pragma unroll
+        for (int r = 0; r < kRingPre; ++r) {
+            const int k = tid + r * kRingThreads;
+            if (k < nb) {
+                const int mn = k == 0 ? n : n - k;
+                Cx<T> acc = {T(0), T(0)};
+                if (k <= mt) acc = cmul(Cx<T>{pre_p[r].x, pre_p[r].y}, phase(k));
+                for (int m = k + n; m <= mt; m += n)
+                    acc = cadd(acc, cmul(Cx<T>{gr[2 * m], gr[2 * m + 1]}, phase(m)));
+                if (mn <= mt) {
+                    const Cx<T> cm = cmul(Cx<T>{pre_n[r].x, pre_n[r].y}, phase(mn));
+                    acc = cadd(acc, Cx<T>{cm.re, -cm.im});
+                }
+                for (int m = mn + n; m <= mt; m += n) {
+                    const Cx<T> cm = cmul(Cx<T>{gr[2 * m], gr[2 * m + 1]}, phase(m));
+                    acc = cadd(acc, Cx<T>{cm.re, -cm.im});
+                }
+                buf1[k] = acc;
+            }
+        }
+        for (int k = tid + kRingPre * kRingThreads; k < nb; k += kRingThreads) buf1[k] = fold_bin(k, 0);
     } else {
         if (tid < nb * gs) part[tid] = fold_bin(tid % nb, tid / nb);
         __syncthreads();
@@ -307,10 +350,14 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
         const int step = n / (4 * Ns);
         for (int j = tid; j < q; j += kRingThreads) {
             const int kq = j % Ns;
+            // one table twiddle per butterfly; its square and cube by complex multiplies
+            const Cx<T> w1 = ring_tw(Et, Ft, kq * step);
+            const Cx<T> w2 = cmul(w1, w1);
             Cx<T> v[4];
             v[0] = src[j];
-#pragma unroll
-            for (int t = 1; t < 4; ++t) v[t] = cmul(src[j + t * q], ring_tw(Et, Ft, t * kq * step));
+            v[1] = cmul(src[j + q], w1);
+            v[2] = cmul(src[j + 2 * q], w2);
+            v[3] = cmul(src[j + 3 * q], cmul(w1, w2));
             dft_inv<T, 4>(v);
             const int base = (j / Ns) * 4 * Ns + kq;
 #pragma unroll
@@ -338,7 +385,6 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
     }
 
     // T_{2j} = Re z_j, T_{2j+1} = Im z_j
-    using V2 = typename Vec2<T>::type;
     V2* o = reinterpret_cast<V2*>(out + (size_t)f * a.total + off[i]);
     for (int j = tid; j < h; j += kRingThreads) {
         V2 w;

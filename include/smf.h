@@ -248,6 +248,12 @@ int smf_synthesize_rings(const smf_plan* plan, int count, const void* g_dev, voi
 int smf_sample_rings(const smf_plan* plan, uint64_t seed, int count, void* g_work, void* out_dev,
                      void* hip_stream);
 
+/* smf_sample_rings with the lognormal map of smf_sample_lognormal, exp(mu + sigma T), applied
+ * as the pixels are stored (the application named at the end of Sec. 4, on a ring plan).
+ * Errors: as smf_sample_rings, plus SMF_EINVAL for a mu or sigma that is not finite. */
+int smf_sample_rings_lognormal(const smf_plan* plan, uint64_t seed, int count, double mu, double sigma,
+                               void* g_work, void* out_dev, void* hip_stream);
+
 /* Frees the plan and its device memory (synchronises the device first).  NULL is a
  * no-op. */
 int smf_destroy(smf_plan* plan);

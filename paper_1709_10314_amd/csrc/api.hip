@@ -586,7 +586,8 @@ int smf_ring_layout(const smf_plan* plan, int64_t* offsets)
     return SMF_OK;
 }
 
-int smf_synthesize_rings(const smf_plan* plan, int count, const void* g_dev, void* out_dev, void* hip_stream)
+static int synthesize_rings(const smf_plan* plan, int count, const void* g_dev, void* out_dev, void* hip_stream,
+                            const smf::LognormalMap* ln)
 {
     if (!plan || plan->batch || !plan->n_ring_dev || count < 0 || count > smf::kRingMaxCount) return SMF_EINVAL;
     if (count == 0) return SMF_OK;
@@ -595,20 +596,39 @@ int smf_synthesize_rings(const smf_plan* plan, int count, const void* g_dev, voi
     const Geometry& g = plan->g;
     return smf::launch_ring_c2r(g.n_theta, g.m_top, g.n_phi / 2, plan->ring_off[g.n_theta], plan->ring_split,
                                 plan->flags == SMF_FP64, count, g_dev, plan->ring_list_dev, plan->n_ring_dev,
-                                plan->phi0_dev, plan->ring_off_dev, out_dev, (hipStream_t)hip_stream) == hipSuccess
+                                plan->phi0_dev, plan->ring_off_dev, out_dev, ln, (hipStream_t)hip_stream) == hipSuccess
                ? SMF_OK
                : SMF_EHIP;
 }
 
-int smf_sample_rings(const smf_plan* plan, uint64_t seed, int count, void* g_work, void* out_dev,
-                     void* hip_stream)
+static int sample_rings(const smf_plan* plan, uint64_t seed, int count, void* g_work, void* out_dev,
+                        void* hip_stream, const smf::LognormalMap* ln)
 {
     if (!plan || plan->batch || !plan->n_ring_dev || count < 0 || count > smf::kRingMaxCount) return SMF_EINVAL;
     if (count == 0) return SMF_OK;
     if (!g_work || !out_dev || g_work == out_dev) return SMF_EINVAL;
     const int rc = sample_common(plan, seed, count, g_work, hip_stream, false);
     if (rc != SMF_OK) return rc;
-    return smf_synthesize_rings(plan, count, g_work, out_dev, hip_stream);
+    return synthesize_rings(plan, count, g_work, out_dev, hip_stream, ln);
+}
+
+int smf_synthesize_rings(const smf_plan* plan, int count, const void* g_dev, void* out_dev, void* hip_stream)
+{
+    return synthesize_rings(plan, count, g_dev, out_dev, hip_stream, nullptr);
+}
+
+int smf_sample_rings(const smf_plan* plan, uint64_t seed, int count, void* g_work, void* out_dev,
+                     void* hip_stream)
+{
+    return sample_rings(plan, seed, count, g_work, out_dev, hip_stream, nullptr);
+}
+
+int smf_sample_rings_lognormal(const smf_plan* plan, uint64_t seed, int count, double mu, double sigma,
+                               void* g_work, void* out_dev, void* hip_stream)
+{
+    if (!std::isfinite(mu) || !std::isfinite(sigma)) return SMF_EINVAL;
+    const smf::LognormalMap ln = {mu, sigma};
+    return sample_rings(plan, seed, count, g_work, out_dev, hip_stream, &ln);
 }
 
 int smf_destroy(smf_plan* plan)

@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
                                                                 const int* __restrict__ n_ring,
                                                                 const double* __restrict__ phi0,
                                                                 const int64_t* __restrict__ off,
-                                                                T* __restrict__ out)
+                                                                T* __restrict__ out, Epilogue<T> ep)
 {
     extern __shared__ unsigned char smem_raw[];
     const int i = a.list[blockIdx.x];
@@ -384,19 +384,20 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
         src = dst;
     }
 
-    // T_{2j} = Re z_j, T_{2j+1} = Im z_j
+    // T_{2j} = Re z_j, T_{2j+1} = Im z_j (through the lognormal map when it is on)
     V2* o = reinterpret_cast<V2*>(out + (size_t)f * a.total + off[i]);
     for (int j = tid; j < h; j += kRingThreads) {
+        const Cx<T> v = epilogue(ep, src[j]);
         V2 w;
-        w.x = src[j].re;
-        w.y = src[j].im;
+        w.x = v.re;
+        w.y = v.im;
         o[j] = w;
     }
 }
 
 template <typename T, bool BLUE>
 hipError_t launch_ring_c2r_t(const RingArgs& a, int rings, int count, size_t lds, const T* g, const int* n_ring,
-                             const double* phi0, const int64_t* off, T* out, hipStream_t st)
+                             const double* phi0, const int64_t* off, T* out, const Epilogue<T>& ep, hipStream_t st)
 {
     if (rings == 0) return hipSuccess;
     if (lds > 65536) {
@@ -405,23 +406,24 @@ hipError_t launch_ring_c2r_t(const RingArgs& a, int rings, int count, size_t lds
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((ring_c2r_kernel<T, BLUE>), dim3(rings, count), dim3(kRingThreads), lds, st, a, g, n_ring,
-                       phi0, off, out);
+                       phi0, off, out, ep);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_ring_pair(const RingArgs& a, const RingSplit& rs, int count, const T* g, const int* n_ring,
-                            const double* phi0, const int64_t* off, T* out, hipStream_t st)
+                            const double* phi0, const int64_t* off, T* out, const LognormalMap* ln, hipStream_t st)
 {
     const bool fp64 = sizeof(T) == 8;
+    const Epilogue<T> ep = {ln ? (T)ln->mu : T(0), ln ? (T)ln->sigma : T(0), ln ? 1 : 0};
     RingArgs ab = a;
     ab.list = a.list + rs.n_direct;
     hipError_t e = launch_ring_c2r_t<T, false>(a, rs.n_direct, count, ring_lds_bytes(rs.n_max_direct, a.m_top, fp64),
-                                               g, n_ring, phi0, off, out, st);
+                                               g, n_ring, phi0, off, out, ep, st);
     if (e != hipSuccess) return e;
     return launch_ring_c2r_t<T, true>(ab, rs.n_chirp, count,
                                       ring_lds_bytes(rs.n_max_chirp, a.m_top, fp64, rs.l_max), g, n_ring, phi0, off,
-                                      out, st);
+                                      out, ep, st);
 }
 
 }  // namespace
@@ -454,13 +456,13 @@ int ring_largest_odd_prime(int h)
 
 hipError_t launch_ring_c2r(int n_theta, int m_top, int g_row, int64_t total, const RingSplit& rs, bool fp64,
                            int count, const void* g, const int* list, const int* n_ring, const double* phi0,
-                           const int64_t* off, void* out, hipStream_t st)
+                           const int64_t* off, void* out, const LognormalMap* ln, hipStream_t st)
 {
     if (count <= 0 || count > 65535 || n_theta <= 0 || rs.n_direct + rs.n_chirp != n_theta) return hipErrorInvalidValue;
     const RingArgs a = {n_theta, m_top, g_row, total, list};
     if (fp64)
-        return launch_ring_pair<double>(a, rs, count, (const double*)g, n_ring, phi0, off, (double*)out, st);
-    return launch_ring_pair<float>(a, rs, count, (const float*)g, n_ring, phi0, off, (float*)out, st);
+        return launch_ring_pair<double>(a, rs, count, (const double*)g, n_ring, phi0, off, (double*)out, ln, st);
+    return launch_ring_pair<float>(a, rs, count, (const float*)g, n_ring, phi0, off, (float*)out, ln, st);
 }
 
 }  // namespace smf

@@ -111,6 +111,7 @@ hipError_t launch_scan(const Geometry& g, int fp64, const void* fac, size_t sout
 // of field f at out + f * total + off[i].  Device arrays list, n_ring, phi0, off; list holds
 // the n_direct rings whose odd prime passes are all direct, then the n_chirp rings whose
 // largest odd prime P (of n_ring / 2) takes the chirp-z pass, L = the power of two >= 2P - 1.
+// ln (may be null): the lognormal map applied as the pixels are stored.
 constexpr int kRingMaxEll = 8191;        // modes of the chains: n_phi <= 16384
 constexpr int kRingMaxPixels32 = 8192;   // largest ring: two buffers + small tables in LDS
 constexpr int kRingMaxPixels64 = 4096;
@@ -131,7 +132,7 @@ size_t ring_lds_bytes(int n_max, int m_top, bool fp64, int l_max = 0);
 int ring_largest_odd_prime(int h);    // 1 when h is a power of two
 hipError_t launch_ring_c2r(int n_theta, int m_top, int g_row, int64_t total, const RingSplit& rs, bool fp64,
                            int count, const void* g, const int* list, const int* n_ring, const double* phi0,
-                           const int64_t* off, void* out, hipStream_t st);
+                           const int64_t* off, void* out, const LognormalMap* ln, hipStream_t st);
 
 }  // namespace smf
 

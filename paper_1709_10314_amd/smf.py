@@ -22,7 +22,7 @@ EXPORTS = ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", 
            "smf_plan_dims", "smf_get_factors", "smf_set_factors", "smf_plan_grid",
            "smf_destroy", "smf_error_string", "smf_setup_batch", "smf_batch_layout",
            "smf_sample_batch", "smf_autotune_batch", "smf_setup_rings", "smf_ring_layout",
-           "smf_synthesize_rings", "smf_sample_rings")
+           "smf_synthesize_rings", "smf_sample_rings", "smf_sample_rings_lognormal")
 
 
 class smf_spectrum(ctypes.Structure):
@@ -82,11 +82,12 @@ def load():
     lib.smf_ring_layout.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     lib.smf_synthesize_rings.argtypes = [vp, i, vp, vp, vp]
     lib.smf_sample_rings.argtypes = [vp, u64, i, vp, vp, vp]
+    lib.smf_sample_rings_lognormal.argtypes = [vp, u64, i, ctypes.c_double, ctypes.c_double, vp, vp, vp]
     for name in ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks", "smf_get_ring_blocks",
                  "smf_plan_dims",
                  "smf_get_factors", "smf_set_factors", "smf_plan_grid", "smf_destroy", "smf_setup_batch", "smf_batch_layout",
                  "smf_sample_batch", "smf_autotune_batch", "smf_setup_rings", "smf_ring_layout",
-                 "smf_synthesize_rings", "smf_sample_rings"):
+                 "smf_synthesize_rings", "smf_sample_rings", "smf_sample_rings_lognormal"):
         getattr(lib, name).restype = i
     _lib = lib
     return lib
@@ -159,6 +160,11 @@ def smf_synthesize_rings(plan, count, g_ptr, out_ptr, stream=None):
 def smf_sample_rings(plan, seed, count, g_ptr, out_ptr, stream=None):
     return load().smf_sample_rings(plan, ctypes.c_uint64(int(seed)), int(count), ctypes.c_void_p(g_ptr),
                                    ctypes.c_void_p(out_ptr), _stream_handle(stream))
+
+
+def smf_sample_rings_lognormal(plan, seed, count, mu, sigma, g_ptr, out_ptr, stream=None):
+    return load().smf_sample_rings_lognormal(plan, ctypes.c_uint64(int(seed)), int(count), float(mu), float(sigma),
+                                             ctypes.c_void_p(g_ptr), ctypes.c_void_p(out_ptr), _stream_handle(stream))
 
 
 def smf_setup(order, n_theta, n_phi, ell_max, kappa=None, c_ell=None, flags=SMF_FP32, stream=None, z=None):
@@ -542,6 +548,19 @@ class RingPlan(Plan):
         rc = smf_sample_rings(self._h, seed, count, work.data_ptr(), out.data_ptr(), stream)
         if rc != SMF_OK:
             raise SmfError(rc, "smf_sample_rings")
+        return out.view(-1)[: count * self.pixels].view(count, self.pixels)
+
+    def sample_rings_lognormal(self, seed, count, mu=0.0, sigma=1.0, out=None, work=None, stream=None):
+        """exp(mu + sigma T) of the pixels sample_rings(seed, count) would return."""
+        if out is None:
+            out = self.empty_rings(count)
+        if work is None:
+            work = self.empty(count)
+        self._check_rings(out, count)
+        self._check_out(work, count)
+        rc = smf_sample_rings_lognormal(self._h, seed, count, mu, sigma, work.data_ptr(), out.data_ptr(), stream)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_sample_rings_lognormal")
         return out.view(-1)[: count * self.pixels].view(count, self.pixels)
 
     def synthesize_rings(self, g, count, out=None, stream=None):

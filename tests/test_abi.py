@@ -59,6 +59,7 @@ def test_error_strings_and_null_handling_without_gpu():
     assert lib.smf_ring_layout(None, None) == smf.SMF_EINVAL
     assert lib.smf_synthesize_rings(None, 1, None, None, None) == smf.SMF_EINVAL
     assert lib.smf_sample_rings(None, 1, 1, None, None, None) == smf.SMF_EINVAL
+    assert lib.smf_sample_rings_lognormal(None, 1, 1, 0.0, 1.0, None, None, None) == smf.SMF_EINVAL
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):

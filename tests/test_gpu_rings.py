@@ -290,3 +290,46 @@ def test_healpix_covariance_matches_addition_theorem(order, kap):
         pairs += len(b)
     log(f"order {order}: {pairs} pixel pairs, worst deviation {worst:.2f} standard errors; variance {var:.4e}")
     assert worst <= 5.0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ring_lognormal_is_exp_of_the_pixels(precision):
+    """smf_sample_rings_lognormal stores exp(mu + sigma T) of the pixels smf_sample_rings gives
+    (both launches: one ring takes the chirp-z pass), and against the oracle's pixels."""
+    z, n_ring, phi0 = _healpix(16)
+    n_ring = n_ring.copy()
+    n_ring[5] = 2 * 509
+    mu, sig, count, seed = 0.4, 3.0, 2, 17
+    plan = _ring_plan(n_ring, phi0, 47, precision, order=1, kap=400.0, z=z)
+    T = plan.sample_rings(seed, count).clone()
+    L = plan.sample_rings_lognormal(seed, count, mu, sig)
+    torch.cuda.synchronize()
+    T = T.double().cpu().numpy()
+    L = L.double().cpu().numpy()
+    if precision == "fp64":
+        ref = np.exp(mu + sig * T)
+        bound = 1e-14
+    else:
+        y = np.float32(mu) + np.float32(sig) * T
+        ref = np.exp(y)
+        bound = 4 * 2.0 ** -24 + float(np.max(np.abs(y))) * 2.0 ** -24 * 2
+    e = float(np.max(np.abs(L - ref) / ref))
+    log(f"ring lognormal {precision}: max rel err vs exp(pixels) {e:.2e} (bound {bound:.2e})")
+    assert e <= bound
+    C = oracle.spectrum([400.0], 47)
+    A, B = oracle.setup(1, C, len(z), plan.n_phi, z=z)
+    To = oracle.dft_rings(oracle.sample_modes(1, len(z), A, B, seed, count), n_ring, phi0)
+    for f in range(count):
+        el = rel_rms(L[f], np.exp(mu + sig * To[f]))
+        lim = TOL[precision] * max(1.0, sig * float(np.max(np.abs(To[f]))))
+        log(f"  field {f}: lognormal rel RMS vs oracle {el:.2e} (limit {lim:.2e})")
+        assert el <= lim
+    from paper_1709_10314_amd import smf
+
+    out, work = plan.empty_rings(1), plan.empty(1)
+    for bad in (float("nan"), float("inf")):
+        assert smf.smf_sample_rings_lognormal(plan.handle, 1, 1, bad, 1.0, work.data_ptr(),
+                                              out.data_ptr()) == smf.SMF_EINVAL
+        assert smf.smf_sample_rings_lognormal(plan.handle, 1, 1, 0.0, bad, work.data_ptr(),
+                                              out.data_ptr()) == smf.SMF_EINVAL
+    plan.close()

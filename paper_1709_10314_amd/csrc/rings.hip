@@ -35,24 +35,39 @@ __device__ __forceinline__ Cx<T> ring_tw(const Cx<T>* Et, const Cx<T>* Ft, int k
     return cmul(Ft[k >> 6], Et[k & 63]);
 }
 
-// In-place radix-2 FFTs of a power-of-two length L in LDS for the chirp-z pass: the forward
-// one (e^{-2 pi i}) by decimation in frequency, natural order in and bit-reversed order out;
-// the inverse (e^{+2 pi i}, unscaled) by decimation in time, bit-reversed in and natural out.
-// Twiddles e^{2 pi i k / L} = FL[k / 64] EL[k mod 64].  Each stage ends with a barrier.
+// In-place FFTs of a power-of-two length L in LDS for the chirp-z pass, radix-4 stages (spans
+// L/4, L/16, ...) and, when log2 L is odd, a last radix-2 stage on neighbouring pairs.  The
+// forward one (e^{-2 pi i}) runs the stages by decimation in frequency and leaves the
+// digit-reversed order; the inverse (e^{+2 pi i}, unscaled) undoes them in reverse order and
+// returns natural order, so a product taken between the two needs no permutation.
+// Twiddles e^{2 pi i k / L} = FL[k / 64] EL[k mod 64]; each stage ends with a barrier.
 template <typename T>
 __device__ void lds_fft_fwd(Cx<T>* x, int L, const Cx<T>* EL, const Cx<T>* FL, int tid)
 {
-    for (int half = L >> 1; half >= 1; half >>= 1) {
-        const int stride = L / (2 * half);
+    for (int Q = L >> 2; Q >= 1; Q >>= 2) {
+        const int stride = L / (4 * Q);
+        for (int t = tid; t < (L >> 2); t += kRingThreads) {
+            const int gi = t / Q;
+            const int pos = t - gi * Q;
+            const int base = gi * 4 * Q + pos;
+            const Cx<T> v0 = x[base], v1 = x[base + Q], v2 = x[base + 2 * Q], v3 = x[base + 3 * Q];
+            const Cx<T> s02 = cadd(v0, v2), d02 = csub(v0, v2), s13 = cadd(v1, v3);
+            const Cx<T> id13 = mul_i(csub(v1, v3));
+            const Cx<T> w1 = ring_tw(EL, FL, pos * stride);
+            const Cx<T> w2 = cmul(w1, w1);
+            const Cx<T> w3 = cmul(w1, w2);
+            x[base] = cadd(s02, s13);
+            x[base + Q] = cmul(csub(d02, id13), Cx<T>{w1.re, -w1.im});
+            x[base + 2 * Q] = cmul(csub(s02, s13), Cx<T>{w2.re, -w2.im});
+            x[base + 3 * Q] = cmul(cadd(d02, id13), Cx<T>{w3.re, -w3.im});
+        }
+        __syncthreads();
+    }
+    if (__builtin_ctz(L) & 1) {
         for (int t = tid; t < (L >> 1); t += kRingThreads) {
-            const int gi = t / half;
-            const int pos = t - gi * half;
-            const int i0 = gi * 2 * half + pos;
-            const int i1 = i0 + half;
-            const Cx<T> u = x[i0], v = x[i1];
-            const Cx<T> w = ring_tw(EL, FL, pos * stride);
-            x[i0] = cadd(u, v);
-            x[i1] = cmul(csub(u, v), Cx<T>{w.re, -w.im});
+            const Cx<T> u = x[2 * t], v = x[2 * t + 1];
+            x[2 * t] = cadd(u, v);
+            x[2 * t + 1] = csub(u, v);
         }
         __syncthreads();
     }
@@ -61,17 +76,32 @@ __device__ void lds_fft_fwd(Cx<T>* x, int L, const Cx<T>* EL, const Cx<T>* FL, i
 template <typename T>
 __device__ void lds_fft_inv(Cx<T>* x, int L, const Cx<T>* EL, const Cx<T>* FL, int tid)
 {
-    for (int half = 1; half < L; half <<= 1) {
-        const int stride = L / (2 * half);
+    const bool odd = __builtin_ctz(L) & 1;
+    if (odd) {
         for (int t = tid; t < (L >> 1); t += kRingThreads) {
-            const int gi = t / half;
-            const int pos = t - gi * half;
-            const int i0 = gi * 2 * half + pos;
-            const int i1 = i0 + half;
-            const Cx<T> u = x[i0];
-            const Cx<T> v = cmul(x[i1], ring_tw(EL, FL, pos * stride));
-            x[i0] = cadd(u, v);
-            x[i1] = csub(u, v);
+            const Cx<T> u = x[2 * t], v = x[2 * t + 1];
+            x[2 * t] = cadd(u, v);
+            x[2 * t + 1] = csub(u, v);
+        }
+        __syncthreads();
+    }
+    for (int Q = odd ? 2 : 1; Q <= (L >> 2); Q <<= 2) {
+        const int stride = L / (4 * Q);
+        for (int t = tid; t < (L >> 2); t += kRingThreads) {
+            const int gi = t / Q;
+            const int pos = t - gi * Q;
+            const int base = gi * 4 * Q + pos;
+            const Cx<T> w1 = ring_tw(EL, FL, pos * stride);
+            const Cx<T> w2 = cmul(w1, w1);
+            const Cx<T> w3 = cmul(w1, w2);
+            const Cx<T> v0 = x[base], v1 = cmul(x[base + Q], w1), v2 = cmul(x[base + 2 * Q], w2),
+                        v3 = cmul(x[base + 3 * Q], w3);
+            const Cx<T> s02 = cadd(v0, v2), d02 = csub(v0, v2), s13 = cadd(v1, v3);
+            const Cx<T> id13 = mul_i(csub(v1, v3));
+            x[base] = cadd(s02, s13);
+            x[base + Q] = cadd(d02, id13);
+            x[base + 2 * Q] = csub(s02, s13);
+            x[base + 3 * Q] = csub(d02, id13);
         }
         __syncthreads();
     }

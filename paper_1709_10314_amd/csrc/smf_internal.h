@@ -116,8 +116,8 @@ constexpr int kRingMaxEll = 8191;        // modes of the chains: n_phi <= 16384
 constexpr int kRingMaxPixels32 = 8192;   // largest ring: two buffers + small tables in LDS
 constexpr int kRingMaxPixels64 = 4096;
 constexpr int kRingMaxCount = 65535;     // fields of one call (grid y)
-// Smallest prime that takes the chirp-z pass (measured on HEALPix nside 1024 x 8 fields: 1.003 ms
-// with none, 1.21 ms from 127, 0.984 ms from 383 or 761, 1.07 ms from 1021)
+// Smallest prime that takes the chirp-z pass (measured on HEALPix nside 1024 x 8 fields with the
+// radix-4 chirp-z FFTs: 0.806 ms from 383, 0.834 from 251, 0.927 from 127)
 #ifndef SMF_RING_CHIRP_MIN
 #define SMF_RING_CHIRP_MIN 383
 #endif

@@ -511,8 +511,8 @@ class RingPlan(Plan):
     power-of-two n_phi that keeps them all) and each ring is synthesised at its own pixels."""
 
     def __init__(self, order, n_phi_ring, phi0, ell_max, kappa=None, c_ell=None, precision="fp32",
-                 stream=None, z=None):
-        flags = {"fp32": SMF_FP32, "fp64": SMF_FP64}[precision]
+                 stream=None, z=None, basis="z"):
+        flags = {"fp32": SMF_FP32, "fp64": SMF_FP64}[precision] | {"z": 0, "u": SMF_UBASIS}[basis]
         rc, h = smf_setup_rings(order, n_phi_ring, phi0, ell_max, kappa=kappa, c_ell=c_ell, flags=flags,
                                 stream=stream, z=z)
         if rc != SMF_OK:

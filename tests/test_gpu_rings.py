@@ -163,6 +163,55 @@ def test_healpix_fields_match_oracle(case, precision):
     plan.close()
 
 
+@pytest.mark.parametrize("order", [3, 4])
+def test_healpix_higher_orders_on_oracle_factors(order):
+    """Orders 3 and 4 on HEALPix rings: the ring plan's chains on the oracle's factors
+    (smf_set_factors; the order-3/4 setup's FP64 sensitivity is covered by the regular-grid
+    tests), then the synthesis, against the oracle: FP64 1e-10, FP32 1e-4."""
+    z, n_ring, phi0 = _healpix(16)
+    n, lmax, kap, count, seed = len(z), 47, 900.0, 2, 43
+    C = oracle.spectrum([kap] * order, lmax)
+    for precision in ("fp64", "fp32"):
+        plan = _ring_plan(n_ring, phi0, lmax, precision, order=order, kap=kap, z=z)
+        A, B = oracle.setup(order, C, n, plan.n_phi, z=z)
+        plan.set_factors(A, B)
+        To = oracle.dft_rings(oracle.sample_modes(order, n, A, B, seed, count), n_ring, phi0)
+        for blocks in (1, 4):
+            plan.set_ring_blocks(blocks)
+            T = plan.sample_rings(seed, count)
+            torch.cuda.synchronize()
+            _check(f"order {order} {precision} blocks {plan.ring_blocks(count)}", T.double().cpu().numpy(), To,
+                   plan.offsets, TOL[precision])
+        plan.close()
+
+
+def test_healpix_u_basis():
+    """The U basis of Sec. 3 (order 2) on HEALPix rings: FP32 on the plan's own setup against
+    the oracle's U-basis setup and samples (1e-4), FP64 on the oracle's factors (1e-10; the
+    plan's own FP64 setup is logged, its sensitivity being that of the z basis)."""
+    from paper_1709_10314_amd import RingPlan
+
+    z, n_ring, phi0 = _healpix(8)
+    n, lmax, kap, count, seed = len(z), 15, 900.0, 2, 47
+    C = oracle.spectrum([kap, kap], lmax)
+    for precision in ("fp64", "fp32"):
+        plan = RingPlan(2, n_ring, phi0, lmax, kappa=[kap, kap], precision=precision, z=z, basis="u")
+        A, B = oracle.setup(2, C, n, plan.n_phi, z=z, basis="u")
+        To = oracle.dft_rings(oracle.sample_modes(2, n, A, B, seed, count), n_ring, phi0)
+        T = plan.sample_rings(seed, count)
+        torch.cuda.synchronize()
+        T = T.double().cpu().numpy()
+        if precision == "fp32":
+            _check("u basis fp32, own setup", T, To, plan.offsets, TOL[precision])
+        else:
+            log(f"u basis fp64, own setup: {max(rel_rms(T[f], To[f]) for f in range(count)):.3e}")
+            plan.set_factors(A, B)
+            T = plan.sample_rings(seed, count)
+            torch.cuda.synchronize()
+            _check("u basis fp64, oracle factors", T.double().cpu().numpy(), To, plan.offsets, TOL[precision])
+        plan.close()
+
+
 def test_sample_rings_is_sample_modes_then_synthesis():
     z, n_ring, phi0 = _healpix(16)
     plan = _ring_plan(n_ring, phi0, 40, "fp32", order=2, kap=400.0, z=z)

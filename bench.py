@@ -283,7 +283,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the sampler shards by whole fields with no exchange; see the design notes)",
+              "(the sampler shards by whole fields with no exchange between GPUs)",
               file=sys.stderr)
         sys.exit(2)
     if int(os.environ.get("RANK", "0")) != 0:
@@ -336,7 +336,7 @@ def main():
         fp64 = {"value": pts / ms64 * 1e3, "unit": "grid points/s", "ms_per_step": ms64}
         log(f"  fp64 {ms64:.3f} ms/step")
 
-    # algorithmic work per launch (see the design notes for the per-unit figures): the
+    # algorithmic work per launch: the
     # recursion reads the FP32 factors once and writes the modes, and its arithmetic is
     # alu_slots_per_point per point; the FFT reads and writes every point once
     vals_per_rec = order * order + order * (order + 1) // 2
@@ -396,7 +396,7 @@ def main():
         log("HEALPix rings, nside 1024, order 2, 8 fields")
         hp = healpix_leg(args.steps, args.warmup)
         log(f"  {hp['ms_per_step']:.3f} ms/call ({hp['value']:.3e} pixels/s), ring synthesis "
-            f"{hp['synthesis_ms']:.3f} ms ({hp['synthesis_alg_GBs']:.0f} GB/s algorithmic), setup {hp['setup_s']:.1f} s")
+            f"{hp['synthesis_ms']:.3f} ms ({hp['synthesis_alg_GBs']:.0f} GB/s algorithmic), setup {hp['setup_s']:.2f} s")
 
     cpu = None
     if not args.no_cpu_baseline:

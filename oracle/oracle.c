@@ -28,7 +28,7 @@
  *     with their own pixel counts and first-pixel longitudes (iso-latitude grids
  *     such as HEALPix, which Sec. 1 names)
  *
- * Readings where the paper is silent or garbled (each is listed in the design notes):
+ * Readings where the paper is silent or garbled:
  *   grid      theta_i = pi (i + 1/2) / n_theta, z_i = cos(theta_i), ring 0 nearest z = +1;
  *             phi_j = 2 pi j / n_phi; z_i evaluated as sin(pi (n - 2i - 1) / (2n)).  For
  *             odd n_theta = 2k + 1 this is the symmetric example grid of Sec. 4 read as

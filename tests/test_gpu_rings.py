@@ -382,3 +382,36 @@ def test_ring_lognormal_is_exp_of_the_pixels(precision):
         assert smf.smf_sample_rings_lognormal(plan.handle, 1, 1, 0.0, bad, work.data_ptr(),
                                               out.data_ptr()) == smf.SMF_EINVAL
     plan.close()
+
+
+@pytest.mark.parametrize("precision,nside", [("fp32", 2048), ("fp64", 1024)])
+def test_largest_healpix_plans_sampled_rings(precision, nside):
+    """The largest HEALPix grid of each precision (FP32 nside 2048: 8191 rings, 8192-pixel belt
+    rings, ell_max 6143, 50M pixels; FP64 nside 1024), order 2: the plan's own modes, synthesised
+    on the GPU, against the oracle's per-pixel sum of the same modes on sampled rings (the
+    poles, polar rings whose odd part is a large prime, both kinds of belt ring)."""
+    z, n_ring, phi0 = _healpix(nside)
+    lmax = 3 * nside - 1
+    plan = _ring_plan(n_ring, phi0, lmax, precision, order=2, kap=2500.0, z=z)
+    assert plan.pixels == 12 * nside * nside
+    g = plan.sample_modes(5, 1)
+    T = plan.synthesize_rings(g, 1)
+    torch.cuda.synchronize()
+    n = len(z)
+    picks = [0, 1, 2, nside // 2 - 1, 1020, nside - 2, nside - 1, nside, 2 * nside - 1, 2 * nside, 3 * nside,
+             n - 1021, n - 2, n - 1]
+    picks = sorted({i for i in picks if 0 <= i < n})
+    gs = g[0, picks].double().cpu().numpy()[:, : lmax + 1]
+    gs = (gs[..., 0] + 1j * gs[..., 1])[None]
+    To = oracle.dft_rings(gs, n_ring[picks], phi0[picks])[0]
+    off_o = oracle.ring_offsets(n_ring[picks])
+    T = T[0].double().cpu().numpy()
+    worst = 0.0
+    for a, i in enumerate(picks):
+        e = rel_rms(T[plan.offsets[i] : plan.offsets[i + 1]], To[off_o[a] : off_o[a + 1]])
+        worst = max(worst, e)
+    log(f"healpix nside {nside} {precision}: {len(picks)} sampled rings, worst rel RMS {worst:.3e}")
+    assert worst <= TOL[precision]
+    plan.close()
+    del g, T
+    torch.cuda.empty_cache()

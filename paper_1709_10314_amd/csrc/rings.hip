@@ -176,8 +176,8 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
     __syncthreads();
 
     // fold: B_k = sum_{m = k mod n} c_m + sum_{m = -k mod n, m >= 1} conj(c_m),  k <= h.
-    // A ring with fewer than kRingThreads / 2 bins gives each bin `gs` threads, which sum
-    // every gs-th period of its modes; the partial sums are added in a fixed order.
+    // A ring with at most kRingThreads / 2 bins gives each bin `gs` threads, which sum every
+    // gs-th period of its modes; the partial sums are added in a fixed order.
     auto phase = [&](int m) {
         const Cx<double> w = cmul(H[m >> 6], G[m & 63]);
         return Cx<T>{(T)w.re, (T)w.im};
@@ -185,16 +185,11 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
     auto fold_bin = [&](int k, int g0) {
         Cx<T> acc = {T(0), T(0)};
 #pragma unroll 2
-        for (int m = k + g0 * n; m <= mt; m += gs * n) {
-            const Cx<double> w = cmul(H[m >> 6], G[m & 63]);
-            const Cx<T> gm = {gr[2 * m], gr[2 * m + 1]};
-            acc = cadd(acc, cmul(gm, Cx<T>{(T)w.re, (T)w.im}));
-        }
+        for (int m = k + g0 * n; m <= mt; m += gs * n)
+            acc = cadd(acc, cmul(Cx<T>{gr[2 * m], gr[2 * m + 1]}, phase(m)));
 #pragma unroll 2
         for (int m = (k == 0 ? n : n - k) + g0 * n; m <= mt; m += gs * n) {
-            const Cx<double> w = cmul(H[m >> 6], G[m & 63]);
-            const Cx<T> gm = {gr[2 * m], gr[2 * m + 1]};
-            const Cx<T> cm = cmul(gm, Cx<T>{(T)w.re, (T)w.im});
+            const Cx<T> cm = cmul(Cx<T>{gr[2 * m], gr[2 * m + 1]}, phase(m));
             acc = cadd(acc, Cx<T>{cm.re, -cm.im});
         }
         return acc;
@@ -263,7 +258,6 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
             big = p;
             r /= p;
         }
-        // outputs q and P - q have conjugate twiddles too: one thread makes both
         const int P = big;
         const int step = n / P;
         const int hp = h / P;
@@ -309,28 +303,30 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
                 }
                 __syncthreads();
             }
-        }
-        for (int idx = tid; !BLUE && idx < hp * half; idx += kRingThreads) {
-            const int b = idx / half;
-            const int q = idx - b * half;
-            const Cx<T> w1 = ring_tw(Et, Ft, q * step);
-            Cx<T> acc = src[b];
-            Cx<T> acc2 = acc;
-            Cx<T> W = w1;
-            for (int t = 1; 2 * t < P; ++t) {
-                if (t % kRingAnchor == 0)
-                    W = ring_tw(Et, Ft, ((t * q) % P) * step);
-                else if (t > 1)
-                    W = cmul(W, w1);
-                const Cx<T> x = src[b + t * hp], y = src[b + (P - t) * hp];
-                const Cx<T> sp = cadd(x, y), df = csub(x, y);
-                acc.re += sp.re * W.re - df.im * W.im;
-                acc.im += sp.im * W.re + df.re * W.im;
-                acc2.re += sp.re * W.re + df.im * W.im;
-                acc2.im += sp.im * W.re - df.re * W.im;
+        } else {
+            // outputs q and P - q have conjugate twiddles too: one thread makes both
+            for (int idx = tid; idx < hp * half; idx += kRingThreads) {
+                const int b = idx / half;
+                const int q = idx - b * half;
+                const Cx<T> w1 = ring_tw(Et, Ft, q * step);
+                Cx<T> acc = src[b];
+                Cx<T> acc2 = acc;
+                Cx<T> W = w1;
+                for (int t = 1; 2 * t < P; ++t) {
+                    if (t % kRingAnchor == 0)
+                        W = ring_tw(Et, Ft, ((t * q) % P) * step);
+                    else if (t > 1)
+                        W = cmul(W, w1);
+                    const Cx<T> x = src[b + t * hp], y = src[b + (P - t) * hp];
+                    const Cx<T> sp = cadd(x, y), df = csub(x, y);
+                    acc.re += sp.re * W.re - df.im * W.im;
+                    acc.im += sp.im * W.re + df.re * W.im;
+                    acc2.re += sp.re * W.re + df.im * W.im;
+                    acc2.im += sp.im * W.re - df.re * W.im;
+                }
+                dst[b * P + q] = acc;
+                if (q > 0) dst[b * P + P - q] = acc2;
             }
-            dst[b * P + q] = acc;
-            if (q > 0) dst[b * P + P - q] = acc2;
         }
         __syncthreads();
         Cx<T>* tmp = src;

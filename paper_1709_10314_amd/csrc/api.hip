@@ -541,6 +541,17 @@ int smf_setup_rings(const smf_spectrum* spec, int n_theta, const double* z_host,
             rs.n_max_direct = std::max(rs.n_max_direct, n_phi_ring[i]);
         }
     }
+    // each launch takes its most expensive rings first (estimated work of the odd-prime passes:
+    // h P / 2 for a direct pass, h L log2 L / P for the chirp-z one; then h log2 h)
+    auto cost = [&](int i, bool chirped) {
+        const double h = n_phi_ring[i] / 2;
+        const int P = smf::ring_largest_odd_prime(n_phi_ring[i] / 2);
+        double L = 1;
+        while (L < 2 * P - 1) L *= 2;
+        return (chirped ? h * L * std::log2(L) / P : h * P / 2.0) + h * std::log2(h + 1.0);
+    };
+    std::stable_sort(direct.begin(), direct.end(), [&](int x, int y) { return cost(x, false) > cost(y, false); });
+    std::stable_sort(chirp.begin(), chirp.end(), [&](int x, int y) { return cost(x, true) > cost(y, true); });
     rs.n_direct = (int)direct.size();
     rs.n_chirp = (int)chirp.size();
     direct.insert(direct.end(), chirp.begin(), chirp.end());

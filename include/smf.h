@@ -227,6 +227,10 @@ int smf_autotune_batch(smf_plan* plan, uint64_t seed, void* out_dev, void* hip_s
 int smf_setup_rings(const smf_spectrum* spec, int n_theta, const double* z_host, const int* n_phi_ring,
                     const double* phi0, int flags, void* hip_stream, smf_plan** out);
 
+/* (A ring plan runs chains only for the 64-mode tiles that hold m <= ell_max: its
+ * smf_sample_modes leaves the entries above those tiles unwritten, which neither the ring
+ * synthesis nor smf_transform reads.) */
+
 /* Layout of a ring plan's fields: offsets[0..n_theta], ring i of a field at
  * [offsets[i], offsets[i+1]); a field holds offsets[n_theta] values.
  * Errors: SMF_EINVAL (NULL, not a ring plan). */

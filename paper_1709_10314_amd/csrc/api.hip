@@ -92,8 +92,10 @@ bool grid_symmetric(const double* z, int n)
 // `scan`: also build the block transitions of the affine scan (single-field plans; the
 // sub-plans of a batch only ever run the plain recursion).  z_host: explicit ring values
 // (host, n_theta), or null for the ring centres.
+// rows: chain rows of the plan (0: n_phi / 2, every mode slot of the FFT layout); a ring plan,
+// which never transforms in place, keeps only the tiles that hold modes up to m_top.
 int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int n_phi, int flags,
-               hipStream_t st, bool scan, smf_plan** out)
+               hipStream_t st, bool scan, smf_plan** out, int rows = 0)
 {
     if (!spec || !out) return SMF_EINVAL;
     *out = nullptr;
@@ -118,7 +120,8 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
         return SMF_EHIP;
     if (lds > (size_t)lds_max) return SMF_EINVAL;
 
-    const Geometry g = smf::make_geometry(spec->order, n_theta, n_phi, spec->ell_max);
+    Geometry g = smf::make_geometry(spec->order, n_theta, n_phi, spec->ell_max);
+    if (rows > 0 && rows < g.m_rows) g.m_rows = rows;
     DevBufs bufs;
     smf_plan* plan = (smf_plan*)calloc(1, sizeof(smf_plan));
     if (!plan) return SMF_ENOMEM;
@@ -244,9 +247,11 @@ int smf_setup_grid(const smf_spectrum* spec, int n_theta, const double* z_host, 
 // Layout of a call's chains: ring blocks of the affine scan (1: plain recursion) and
 // chains per lane (1: one part, 2: both parts of a mode, FP32 only).  The result depends
 // on the blocks only.  With w = count * 2 * ceil(m_rows / 32) one-part waves, the
-// automatic choice (measured on MI355X) is: FP32 plain with two parts per lane from 2048
-// waves, plain with one part from 1024, a two-part scan of 8 blocks from 512, else a
-// one-part scan of 16 blocks; FP64 plain from 1024 waves, else a scan of the fewest
+// automatic choice (measured on MI355X) is: FP32 plain with two parts per lane above 1024
+// waves (from 1025 to 2047 one-part waves would leave some of the 1024 SIMDs two waves and
+// others one: 4096 x 8192 x 6 fields 0.560 -> 0.433 ms, 8192 x 16384 x 3 1.03 -> 0.85 ms),
+// plain with one part at exactly 1024 (one wave per SIMD: 0.340 against 0.420 ms at
+// 4096 x 8192 x 4), a two-part scan of 8 blocks from 512, else a one-part scan of 16 blocks; FP64 plain from 1024 waves, else a scan of the fewest
 // blocks giving >= 4096 waves.  Orders 3 and 4 as FP64 (one-part scans of at most 8
 // blocks), with two parts per lane in FP32 from SMF_GEN_TWO_W waves.  Scans keep
 // >= kScanAutoMinSets ring steps per block.
@@ -267,7 +272,7 @@ static CallShape call_shape(const smf_plan* plan, int count)
     const int cap = std::min(plan->scan_fine, smf::scan_max_blocks(fp64, plan->g.order));
     const long w = (long)count * 2 * ((plan->g.m_rows + 31) / 32);
     const int walk = plan->g.n_sets - (plan->g.even ? 2 : 1);
-    const int plain_nch = (!fp64 && w >= (high ? SMF_GEN_TWO_W : 2048)) ? 2 : 1;
+    const int plain_nch = (!fp64 && (high ? w >= SMF_GEN_TWO_W : w > 1024)) ? 2 : 1;
     const int scan_nch = (!fp64 && !high && w >= 512) ? 2 : 1;
     if (cap < 2 || plan->scan_req == 1) return {1, plain_nch};
     if (plan->scan_req >= 2) return {std::min(plan->scan_req, cap), scan_nch};
@@ -520,7 +525,9 @@ int smf_setup_rings(const smf_spectrum* spec, int n_theta, const double* z_host,
     int n_phi = 4;
     while (n_phi < 2 * (spec->ell_max + 1)) n_phi *= 2;
     hipStream_t st = (hipStream_t)hip_stream;
-    int rc = setup_impl(spec, n_theta, z_host, n_phi, flags, st, true, out);
+    // chain rows: the 64-mode tiles that hold m <= ell_max (the rows above only held zeros)
+    const int rows = ((spec->ell_max + 1 + 63) / 64) * 64;
+    int rc = setup_impl(spec, n_theta, z_host, n_phi, flags, st, true, out, rows);
     if (rc != SMF_OK) return rc;
     smf_plan* plan = *out;
     // rings whose largest odd prime P (of n / 2) is at least SMF_RING_CHIRP_MIN and whose

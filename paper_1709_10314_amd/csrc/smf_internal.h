@@ -33,7 +33,8 @@ struct Geometry {
     int n_phi;
     int ell_max;
     int m_top;       // highest mode sampled
-    int m_rows;      // n_phi / 2 rows per factor set (m > m_top rows are zero)
+    int m_rows;      // chain rows per factor set: n_phi / 2 (ring plans: the 64-mode tiles up to
+                     // m_top); rows above m_top hold zeros
     int n_sets;      // factor sets per mode
     int s;           // start ring
     int even;        // n_theta even (crossing step present)

@@ -9,6 +9,7 @@ the paper they follow:
 
 * ``grid``          -- ring-centre grid (Sec. 4 grid, read as ring centres)
 * ``spectrum``      -- C_l = prod_i (kappa_i + l(l+1))^-1           (eq. (Cl))
+* ``spectrum_complex`` -- the same with complex kappa_i in conjugate pairs (Sec. 3)
 * ``legendre``      -- L_lm(z) and dL_lm/dz                          (Sec. 2)
 * ``jblock``        -- J^m_pq(z1, z2), brute-force sum over l        (Lemma 2.1)
 * ``setup``         -- A, B, B_eq per mode and ring step             (Alg. 1; eqs.
@@ -60,6 +61,8 @@ def _load():
     lib.orc_grid.argtypes = [_i, _pd, _pd]
     lib.orc_spectrum.argtypes = [_i, _pd, _i, _pd]
     lib.orc_spectrum.restype = _i
+    lib.orc_spectrum_complex.argtypes = [_i, _pd, _pd, _i, _pd]
+    lib.orc_spectrum_complex.restype = _i
     lib.orc_legendre.argtypes = [_i, _i, _d, _pd, _pd]
     lib.orc_jblock.argtypes = [_i, _i, _i, _pd, _d, _d, _pd]
     lib.orc_legendre_derivs.argtypes = [_i, _i, _d, _d, _i, ctypes.POINTER(_pd)]
@@ -126,6 +129,19 @@ def spectrum(kappa, ell_max):
     rc = _load().orc_spectrum(len(k), _p(k), ell_max, _p(C))
     if rc != 0:
         raise ValueError("spectrum has a non-positive or non-finite C_l")
+    return C
+
+
+def spectrum_complex(kappa, ell_max):
+    """C_l = prod_i (kappa_i + l(l+1))^-1 with complex kappa_i (conjugate pairs, Sec. 3),
+    l = 0..ell_max; the product must be real and positive."""
+    k = np.asarray(kappa, dtype=np.complex128).reshape(-1)
+    kre = np.ascontiguousarray(k.real)
+    kim = np.ascontiguousarray(k.imag)
+    C = np.empty(ell_max + 1)
+    rc = _load().orc_spectrum_complex(len(k), _p(kre), _p(kim), ell_max, _p(C))
+    if rc != 0:
+        raise ValueError("spectrum has a C_l that is not real and positive")
     return C
 
 

@@ -122,6 +122,26 @@ int orc_spectrum(int n_kappa, const double* kappa, int ell_max, double* C)
     return 0;
 }
 
+/* The same product with complex kappa_i = kre[i] + i kim[i] (Sec. 3 allows complex   */
+/* kappa_i, e.g. the pair +-i a of the spectrum (a^2 + l^2 (l+1)^2)^-1): the product   */
+/* is formed in complex arithmetic and must come out real and positive (conjugate     */
+/* pairs); returns -1 if some C_l is not (imaginary part above 1e-12 of its modulus).  */
+int orc_spectrum_complex(int n_kappa, const double* kre, const double* kim, int ell_max, double* C)
+{
+    for (int l = 0; l <= ell_max; ++l) {
+        double pr = 1.0, pi = 0.0;   /* running product of (kappa_i + l(l+1)) */
+        for (int i = 0; i < n_kappa; ++i) {
+            const double ar = kre[i] + (double)l * (l + 1), ai = kim[i];
+            const double r = pr * ar - pi * ai, im = pr * ai + pi * ar;
+            pr = r;
+            pi = im;
+        }
+        if (!(pr > 0.0) || !isfinite(pr) || fabs(pi) > 1e-12 * fabs(pr)) return -1;
+        C[l] = 1.0 / pr;
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Fully normalised associated Legendre functions (Sec. 2):                    */
 /*   L_lm(z) = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!) P_lm(z),  z = cos(theta),     */

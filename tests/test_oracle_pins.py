@@ -177,6 +177,41 @@ def test_spectrum_rejects_nonpositive(orc):
         orc.spectrum([-2.0], 5)         # C_1 = 1/0
     C = orc.spectrum([2500.0, 2500.0], 3)
     assert C[0] == 1.0 / 2500.0 ** 2
+    with pytest.raises(ValueError):
+        orc.spectrum_complex([1j], 3)    # a lone complex kappa gives complex C_l
+
+
+# eq. (Cl) worked out by hand, l(l+1) = 0, 2, 6, 12, 20, 30, 42, 56, ... :
+#   kappa = (64)        C_l = 1/(64 + l(l+1))
+#   kappa = (3, 11)     C_l = 1/((3 + l(l+1)) (11 + l(l+1)))    (distinct, Sec. 3)
+#   kappa = (2500)^2    C_l = 1/(2500 + l(l+1))^2               (repeated, the bench spectrum)
+# Each value is a ratio of integers written out below; l^2 in place of l(l+1), or a sum
+# in place of the product over kappa_i, changes every entry with l >= 1.
+_CL_HAND = [
+    ([64.0], {0: 1 / 64, 1: 1 / 66, 2: 1 / 70, 3: 1 / 76, 7: 1 / 120, 10: 1 / 174}),
+    ([3.0, 11.0], {0: 1 / 33, 1: 1 / 65, 2: 1 / 153, 4: 1 / 713, 6: 1 / (45 * 53)}),
+    ([2500.0, 2500.0], {1: 1 / 2502 ** 2, 5: 1 / 2530 ** 2, 7: 1 / 2556 ** 2, 49: 1 / 4950 ** 2}),
+]
+
+
+@pytest.mark.parametrize("kappa,want", _CL_HAND)
+def test_spectrum_worked_values(orc, kappa, want):
+    C = orc.spectrum(kappa, max(want))
+    for ell, c in want.items():
+        assert C[ell] == pytest.approx(c, rel=1e-15), (kappa, ell)
+
+
+def test_sample_spectrum_of_sec5_is_the_complex_pair(orc):
+    """eq. (sample_spec), C_l = (10 + l^2 (l+1)^2)^-1, is eq. (Cl) with the complex pair
+    kappa = +-i sqrt(10) (Sec. 3's example with a^2 = 10): hand values 1/10, 1/14, 1/46,
+    1/154, 1/410, 1/910 at l = 0..5, and the explicit spectrum the convergence experiment
+    passes as c_ell agrees at every l."""
+    C = orc.spectrum_complex([1j * math.sqrt(10.0), -1j * math.sqrt(10.0)], 4095)
+    for ell, c in {0: 1 / 10, 1: 1 / 14, 2: 1 / 46, 3: 1 / 154, 4: 1 / 410, 5: 1 / 910}.items():
+        assert C[ell] == pytest.approx(c, rel=1e-14), ell
+    ell = np.arange(4096, dtype=np.float64)
+    explicit = 1.0 / (10.0 + ell ** 2 * (ell + 1.0) ** 2)   # the convergence test's c_ell
+    np.testing.assert_allclose(C, explicit, rtol=1e-14)
 
 
 # --------------------------------------------------------------------------- factors

@@ -57,7 +57,15 @@ enum {
 enum {
     SMF_FP64 = 1,        /* sample in FP64 (recursion, normals, FFT) */
     SMF_FP32 = 2,        /* sample in FP32 (factors rounded from the FP64 setup) */
-    SMF_UBASIS = 4       /* order 2 only, or'ed with one of the above: the chain state is
+    SMF_NO_MIRROR = 4,   /* or'ed with one of the above: store the southern walk's own factor
+                            sets, (s+j-1) -> (s+j) in true coordinates, instead of reusing the
+                            northern ones through the mirror D A D, D B D of the symmetry remark
+                            after Alg. 1 (twice the factor memory).  On a grid symmetric about
+                            the equator the two tables agree to the bit and so do the samples;
+                            a grid with no symmetry always stores both. */
+    SMF_FUSED = 8,       /* reserved for a single-kernel recursion + FFT; smf_setup returns
+                            SMF_EINVAL for it (the two launches of smf_sample are the path) */
+    SMF_UBASIS = 16      /* order 2 only, or'ed with one of the above: the chain state is
                             (g, U_m g) with the operator U_m of Sec. 3 (eq. (Jmatrix_more_efficient):
                             U_m maps P^m to P^{m+1}, so the setup sums L_{l,m+1} instead of
                             z-derivatives) in place of (g, dg/dz).  The field has the same law;
@@ -72,7 +80,8 @@ enum {
  * is stored; the southern steps are the mirror D A D, D B D (symmetry remark after Alg. 1).
  *   spec      host; copied, not retained.
  *   n_theta   >= 2 rings.     n_phi  power of two in [4, 16384].
- *   flags     exactly one of SMF_FP64, SMF_FP32, optionally or'ed with SMF_UBASIS (order 2).
+ *   flags     exactly one of SMF_FP64, SMF_FP32, optionally or'ed with SMF_NO_MIRROR and
+ *             SMF_UBASIS (order 2).
  *   out       receives the new plan (host pointer to a pointer).
  * Orders 3 and 4 take the second and third z-derivatives of L_lm from the associated
  * Legendre equation; their records hold A row-major and B's lower triangle (16 and 32
@@ -199,17 +208,30 @@ int smf_setup_batch(int n, const smf_spectrum* specs, const int* n_theta, const 
  * field i occupies [offsets[i], offsets[i+1]) as [ring][phi].  Errors: SMF_EINVAL. */
 int smf_batch_layout(const smf_plan* plan, int64_t* offsets);
 
-/* Samples every field of a batch plan (Alg. 2 for each): one launch over all chain
- * items, then one over all rings.  No memset, no allocation and no host synchronisation,
- * so the call can be captured in a HIP graph; it only reads the plan, so calls may
- * overlap on different streams.  Field i uses Philox key seed + i.  out_dev: device
- * float array of offsets[n] elements.  Errors: SMF_EINVAL (NULL, not a batch plan),
- * SMF_EHIP. */
-int smf_sample_batch(const smf_plan* plan, uint64_t seed, void* out_dev, void* hip_stream);
+/* Samples every field of a batch plan (Alg. 2 for each) into the caller's buffers: one
+ * launch over all chain items, then one over all rings.
+ *   seeds_host  host array of n Philox keys, field i drawn with seeds_host[i].
+ *   outs_dev    host array of n device pointers; field i is written to outs_dev[i] as
+ *               n_theta[i] * n_phi[i] floats, layout [ring][phi] (8-byte aligned).
+ * Both arrays are read before the call returns.  The keys and pointers are staged
+ * through one of four plan-owned slots (pinned host memory and a device table); a slot
+ * is reused only once the call that last used it has completed on the GPU, so calls may
+ * overlap on different streams.  Not for stream capture: the table is uploaded per call
+ * (SMF_EINVAL while the stream is capturing); smf_sample_batch_packed is the capturable
+ * form.  Errors: SMF_EINVAL (NULL plan or array, not a batch plan, a NULL or misaligned
+ * buffer, a capturing stream), SMF_EHIP. */
+int smf_sample_batch(const smf_plan* plan, const uint64_t* seeds_host, void* const* outs_dev, void* hip_stream);
 
-/* Autotuner of the chain-item tile shape: times smf_sample_batch with 1, 2 and 4 m-tiles
- * per chain item (2, 4 and 8 waves per workgroup; writing out_dev, seed as in
- * smf_sample_batch), keeps the fastest in the plan and returns its m-tile count in
+/* The same fields into one packed buffer (layout of smf_batch_layout), field i drawn with
+ * Philox key seed + i.  No memset, no allocation and no host synchronisation, so the
+ * call can be captured in a HIP graph; it only reads the plan, so calls may overlap on
+ * different streams.  out_dev: device float array of offsets[n] elements.
+ * Errors: SMF_EINVAL (NULL, not a batch plan), SMF_EHIP. */
+int smf_sample_batch_packed(const smf_plan* plan, uint64_t seed, void* out_dev, void* hip_stream);
+
+/* Autotuner of the chain-item tile shape: times smf_sample_batch_packed with 1, 2 and 4
+ * m-tiles per chain item (2, 4 and 8 waves per workgroup; writing out_dev, seed as in
+ * smf_sample_batch_packed), keeps the fastest in the plan and returns its m-tile count in
  * *tiles_out (may be NULL).  Synchronous; not to be called while the plan is in use.
  * Errors: SMF_EINVAL, SMF_EHIP. */
 int smf_autotune_batch(smf_plan* plan, uint64_t seed, void* out_dev, void* hip_stream, int* tiles_out);

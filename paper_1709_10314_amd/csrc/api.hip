@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "batch.h"
@@ -25,10 +26,30 @@ struct BatchState {
     int n_fft = 0;
     size_t lds = 0;
     int tiles_idx = 1;                   // current tile shape: 2 m-tiles per item
+    // per-field keys and buffers of smf_sample_batch: kCallSlots tables of n entries in
+    // device memory, staged through pinned host memory; slot k is reused only after the
+    // event recorded behind the previous call that used it has completed
+    static constexpr int kCallSlots = 4;
+    BatchCall* call_dev = nullptr;
+    BatchCall* call_host = nullptr;
+    hipEvent_t call_ev[kCallSlots] = {};
+    int call_next = 0;
+    std::mutex call_mu;
 };
 }  // namespace smf
 
 namespace {
+
+void free_call_slots(smf::BatchState* b)
+{
+    if (b->call_dev) (void)hipFree(b->call_dev);
+    if (b->call_host) (void)hipHostFree(b->call_host);
+    for (int k = 0; k < smf::BatchState::kCallSlots; ++k)
+        if (b->call_ev[k]) (void)hipEventDestroy(b->call_ev[k]);
+    b->call_dev = nullptr;
+    b->call_host = nullptr;
+}
+
 
 bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
@@ -106,7 +127,8 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
     if (n_theta < 2 || n_theta > (1 << 16)) return SMF_EINVAL;
     if (!is_pow2(n_phi) || n_phi < 4 || n_phi > 16384) return SMF_EINVAL;
     const int ubasis = (flags & SMF_UBASIS) ? 1 : 0;
-    flags &= ~SMF_UBASIS;
+    const int no_mirror = (flags & SMF_NO_MIRROR) ? 1 : 0;
+    flags &= ~(SMF_UBASIS | SMF_NO_MIRROR);
     if (flags != SMF_FP64 && flags != SMF_FP32) return SMF_EINVAL;
     if (ubasis && spec->order != 2) return SMF_EINVAL;
     if (z_host && !grid_ok(z_host, n_theta)) return SMF_EINVAL;
@@ -128,7 +150,7 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
     plan->g = g;
     plan->flags = flags;
     plan->device = dev;
-    plan->asym = (z_host && !grid_symmetric(z_host, n_theta)) ? 1 : 0;
+    plan->asym = (no_mirror || (z_host && !grid_symmetric(z_host, n_theta))) ? 1 : 0;
     if (z_host) {
         plan->zgrid = (double*)malloc(sizeof(double) * n_theta);
         if (!plan->zgrid) { free(plan); return SMF_ENOMEM; }
@@ -512,7 +534,7 @@ int smf_setup_rings(const smf_spectrum* spec, int n_theta, const double* z_host,
     if (!spec || !out || !n_phi_ring || !phi0 || n_theta < 2 || n_theta > (1 << 16)) return SMF_EINVAL;
     *out = nullptr;
     if (spec->ell_max < 0 || spec->ell_max > smf::kRingMaxEll) return SMF_EINVAL;
-    const bool fp64 = (flags & ~SMF_UBASIS) == SMF_FP64;
+    const bool fp64 = (flags & ~(SMF_UBASIS | SMF_NO_MIRROR)) == SMF_FP64;
     const int n_cap = fp64 ? smf::kRingMaxPixels64 : smf::kRingMaxPixels32;
     int n_max = 0;
     std::vector<int64_t> off((size_t)n_theta + 1, 0);
@@ -657,6 +679,7 @@ int smf_destroy(smf_plan* plan)
     if (plan->batch) {
         smf::BatchState* b = plan->batch;
         for (smf_plan* p : b->sub) smf_destroy(p);
+        free_call_slots(b);
         (void)hipFree(b->fields_dev);
         for (int k = 0; k < 3; ++k) (void)hipFree(b->chain_dev[k]);
         (void)hipFree(b->fft_dev);
@@ -768,6 +791,18 @@ int smf_setup_batch(int n, const smf_spectrum* specs, const int* n_theta, const 
         rc = SMF_ENOMEM;
         goto fail;
     }
+    if (hipMalloc(&b->call_dev, sizeof(smf::BatchCall) * n * smf::BatchState::kCallSlots) != hipSuccess ||
+        hipHostMalloc((void**)&b->call_host, sizeof(smf::BatchCall) * n * smf::BatchState::kCallSlots, 0) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        rc = SMF_ENOMEM;
+        goto fail;
+    }
+    for (int k = 0; k < smf::BatchState::kCallSlots; ++k)
+        if (hipEventCreateWithFlags(&b->call_ev[k], hipEventDisableTiming) != hipSuccess) {
+            rc = SMF_EHIP;
+            goto fail;
+        }
     if (hipMemcpy(b->fields_dev, fields.data(), sizeof(smf::BatchField) * n, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->fft_dev, fft_items.data(), sizeof(uint32_t) * fft_items.size(),
                   hipMemcpyHostToDevice) != hipSuccess || hipGetDevice(&dev) != hipSuccess) {
@@ -783,6 +818,7 @@ int smf_setup_batch(int n, const smf_spectrum* specs, const int* n_theta, const 
     return SMF_OK;
 fail:
     for (smf_plan* p : b->sub) smf_destroy(p);
+    free_call_slots(b);
     if (b->fields_dev) (void)hipFree(b->fields_dev);
     for (int k = 0; k < 3; ++k)
         if (b->chain_dev[k]) (void)hipFree(b->chain_dev[k]);
@@ -799,11 +835,13 @@ int smf_batch_layout(const smf_plan* plan, int64_t* offsets)
     return SMF_OK;
 }
 
-static int batch_launch(const smf_plan* plan, uint64_t seed, void* out_dev, hipStream_t st, int tiles_idx)
+static int batch_launch(const smf_plan* plan, uint64_t seed, void* out_dev, hipStream_t st, int tiles_idx,
+                        const smf::BatchCall* call = nullptr)
 {
     const smf::BatchState* b = plan->batch;
     smf::BatchArgs a;
     a.fields = b->fields_dev;
+    a.call = call;
     a.chain_items = b->chain_dev[tiles_idx];
     a.fft_items = b->fft_dev;
     a.out = (float*)out_dev;
@@ -814,11 +852,40 @@ static int batch_launch(const smf_plan* plan, uint64_t seed, void* out_dev, hipS
     return smf::launch_batch(a, b->lds, st) == hipSuccess ? SMF_OK : SMF_EHIP;
 }
 
-int smf_sample_batch(const smf_plan* plan, uint64_t seed, void* out_dev, void* hip_stream)
+int smf_sample_batch_packed(const smf_plan* plan, uint64_t seed, void* out_dev, void* hip_stream)
 {
     if (!plan || !plan->batch || !out_dev) return SMF_EINVAL;
     DeviceGuard dg(plan->device);
     return batch_launch(plan, seed, out_dev, (hipStream_t)hip_stream, plan->batch->tiles_idx);
+}
+
+int smf_sample_batch(const smf_plan* plan, const uint64_t* seeds_host, void* const* outs_dev, void* hip_stream)
+{
+    if (!plan || !plan->batch || !seeds_host || !outs_dev) return SMF_EINVAL;
+    smf::BatchState* b = plan->batch;
+    for (int i = 0; i < b->n; ++i)
+        if (!outs_dev[i] || ((uintptr_t)outs_dev[i] & 7)) return SMF_EINVAL;
+    DeviceGuard dg(plan->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess) return SMF_EHIP;
+    if (cap != hipStreamCaptureStatusNone) return SMF_EINVAL;   // the table upload is per call
+    std::lock_guard<std::mutex> lk(b->call_mu);
+    const int k = b->call_next;
+    if (hipEventSynchronize(b->call_ev[k]) != hipSuccess) return SMF_EHIP;
+    smf::BatchCall* host = b->call_host + (size_t)k * b->n;
+    smf::BatchCall* dev = b->call_dev + (size_t)k * b->n;
+    for (int i = 0; i < b->n; ++i) {
+        host[i].key = seeds_host[i];
+        host[i].out = (float*)outs_dev[i];
+    }
+    if (hipMemcpyAsync(dev, host, sizeof(smf::BatchCall) * b->n, hipMemcpyHostToDevice, st) != hipSuccess)
+        return SMF_EHIP;
+    const int rc = batch_launch(plan, 0, nullptr, st, b->tiles_idx, dev);
+    if (rc != SMF_OK) return rc;
+    if (hipEventRecord(b->call_ev[k], st) != hipSuccess) return SMF_EHIP;
+    b->call_next = (k + 1) % smf::BatchState::kCallSlots;
+    return SMF_OK;
 }
 
 int smf_autotune_batch(smf_plan* plan, uint64_t seed, void* out_dev, void* hip_stream, int* tiles_out)

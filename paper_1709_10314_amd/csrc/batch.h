@@ -17,8 +17,16 @@ struct BatchField {
     int seed_off;         // Philox key = seed + seed_off
 };
 
+// Per-call entry of one field in the form with per-field seeds and output buffers.
+struct BatchCall {
+    uint64_t key;         // Philox key of the field
+    float* out;           // the field's own [ring][phi] buffer
+};
+
 struct BatchArgs {
     const BatchField* fields;
+    const BatchCall* call;         // per-field keys and buffers, or null: key seed + seed_off,
+                                   // field at out + out_off (packed output)
     const uint32_t* chain_items;   // (field << 16) | group of `tiles` m-tiles
     const uint32_t* fft_items;     // (field << 16) | ring
     float* out;

@@ -53,12 +53,12 @@ __global__ __launch_bounds__(kMaxChainThreads) void batch_chain_kernel(BatchArgs
     const int lane = threadIdx.x & 63;
     const int m = (a.tiles * sub + (w >> 1)) * 32 + (lane >> 1), part = lane & 1;
     if (m >= F.m_rows) return;
-    float* g = a.out + F.out_off + 2 * m + part;
+    float* g = (a.call ? a.call[fi].out : a.out + F.out_off) + 2 * m + part;
     if (m > F.m_top || (m == 0 && part == 1)) {
         zero_chain<float>(F.n_theta, F.s, h, g, (size_t)F.n_phi);
         return;
     }
-    const uint64_t key = a.seed + (uint64_t)F.seed_off;
+    const uint64_t key = a.call ? a.call[fi].key : a.seed + (uint64_t)F.seed_off;
     const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
     const size_t stride = (size_t)F.m_rows * factor_stride(F.order);
     switch (F.order) {
@@ -89,7 +89,8 @@ __global__ __launch_bounds__(kFftThreads) void batch_fft_kernel(BatchArgs a)
     const int fi = (int)(code >> 16);
     const int ring = (int)(code & 0xFFFF);
     const BatchField& F = a.fields[fi];
-    dispatch_fft(F.log2h, a.out + F.out_off + (size_t)ring * F.n_phi, F.tw, F.m_top,
+    float* base = a.call ? a.call[fi].out : a.out + F.out_off;
+    dispatch_fft(F.log2h, base + (size_t)ring * F.n_phi, F.tw, F.m_top,
                  reinterpret_cast<Cx<float>*>(smem_raw));
 }
 

@@ -366,12 +366,15 @@ struct FftPrefetch {
     static constexpr bool value = sizeof(T) == 4 ? LOG2H <= 13 : LOG2H <= 12;
 };
 
-// Register budget in waves per SIMD: 4 (128 VGPRs) for small rows, else 2 (256 VGPRs),
-// and 1 for the 512-thread rows.
+// Register budget in waves per SIMD: 4 (128 VGPRs) for small rows, else SMF_FFT_WAVES_BIG
+// (2: 256 VGPRs), and 1 for the 512-thread rows.
+#ifndef SMF_FFT_WAVES_BIG
+#define SMF_FFT_WAVES_BIG 2
+#endif
 template <typename T, int LOG2H>
 struct FftWaves {
     static constexpr int value = FftThreads<T, LOG2H>::value == 512 ? 1
-                                 : (LOG2H < (sizeof(T) == 4 ? 11 : 8) ? 4 : 2);
+                                 : (LOG2H < (sizeof(T) == 4 ? 11 : 8) ? 4 : SMF_FFT_WAVES_BIG);
 };
 
 // Each workgroup transforms rows blockIdx.x, blockIdx.x + gridDim.x, ...

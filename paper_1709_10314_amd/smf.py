@@ -14,14 +14,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsmf.so")
 
 SMF_OK, SMF_EINVAL, SMF_ENOMEM, SMF_EHIP, SMF_ENUMERIC = 0, -1, -2, -3, -4
-SMF_FP64, SMF_FP32, SMF_UBASIS = 1, 2, 4
+SMF_FP64, SMF_FP32, SMF_NO_MIRROR, SMF_FUSED, SMF_UBASIS = 1, 2, 4, 8, 16
 
 # every symbol include/smf.h declares
 EXPORTS = ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks",
            "smf_get_ring_blocks",
            "smf_plan_dims", "smf_get_factors", "smf_set_factors", "smf_plan_grid",
            "smf_destroy", "smf_error_string", "smf_setup_batch", "smf_batch_layout",
-           "smf_sample_batch", "smf_autotune_batch", "smf_setup_rings", "smf_ring_layout",
+           "smf_sample_batch", "smf_sample_batch_packed", "smf_autotune_batch", "smf_setup_rings", "smf_ring_layout",
            "smf_synthesize_rings", "smf_sample_rings", "smf_sample_rings_lognormal")
 
 
@@ -74,7 +74,8 @@ def load():
     lib.smf_setup_batch.argtypes = [i, ctypes.POINTER(smf_spectrum), ctypes.POINTER(ctypes.c_int),
                                     ctypes.POINTER(ctypes.c_int), i, vp, ctypes.POINTER(vp)]
     lib.smf_batch_layout.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
-    lib.smf_sample_batch.argtypes = [vp, u64, vp, vp]
+    lib.smf_sample_batch.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(vp), vp]
+    lib.smf_sample_batch_packed.argtypes = [vp, u64, vp, vp]
     lib.smf_autotune_batch.argtypes = [vp, u64, vp, vp, ctypes.POINTER(ctypes.c_int)]
     lib.smf_setup_rings.argtypes = [ctypes.POINTER(smf_spectrum), i, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), i, vp,
@@ -86,7 +87,7 @@ def load():
     for name in ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks", "smf_get_ring_blocks",
                  "smf_plan_dims",
                  "smf_get_factors", "smf_set_factors", "smf_plan_grid", "smf_destroy", "smf_setup_batch", "smf_batch_layout",
-                 "smf_sample_batch", "smf_autotune_batch", "smf_setup_rings", "smf_ring_layout",
+                 "smf_sample_batch", "smf_sample_batch_packed", "smf_autotune_batch", "smf_setup_rings", "smf_ring_layout",
                  "smf_synthesize_rings", "smf_sample_rings", "smf_sample_rings_lognormal"):
         getattr(lib, name).restype = i
     _lib = lib
@@ -299,9 +300,19 @@ def smf_batch_layout(plan, n):
     return rc, [int(x) for x in off]
 
 
-def smf_sample_batch(plan, seed, out_ptr, stream=None):
-    return load().smf_sample_batch(plan, ctypes.c_uint64(int(seed)), ctypes.c_void_p(out_ptr),
-                                   _stream_handle(stream))
+def smf_sample_batch(plan, seeds, out_ptrs, stream=None):
+    """Field i drawn with key seeds[i] into the device buffer at out_ptrs[i]."""
+    n = len(seeds)
+    if len(out_ptrs) != n:
+        raise ValueError("one output pointer per seed")
+    sd = (ctypes.c_uint64 * n)(*[int(x) for x in seeds])
+    op = (ctypes.c_void_p * n)(*[int(x) for x in out_ptrs])
+    return load().smf_sample_batch(plan, sd, op, _stream_handle(stream))
+
+
+def smf_sample_batch_packed(plan, seed, out_ptr, stream=None):
+    return load().smf_sample_batch_packed(plan, ctypes.c_uint64(int(seed)), ctypes.c_void_p(out_ptr),
+                                          _stream_handle(stream))
 
 
 def smf_autotune_batch(plan, seed, out_ptr, stream=None):
@@ -338,10 +349,29 @@ class BatchPlan:
             out = self.empty()
         if not out.is_cuda or out.dtype.itemsize != 4 or out.numel() < self.offsets[-1]:
             raise ValueError("output must be a device float32 tensor of offsets[-1] elements")
-        rc = smf_sample_batch(self._h, seed, out.data_ptr(), stream)
+        rc = smf_sample_batch_packed(self._h, seed, out.data_ptr(), stream)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_sample_batch_packed")
+        return out
+
+    def sample_fields(self, seeds, outs=None, stream=None):
+        """Field i with key seeds[i] into its own tensor outs[i] ([n_theta, n_phi] float32 on
+        the device; allocated when outs is None).  Returns the list of tensors."""
+        import torch
+
+        if len(seeds) != self.n:
+            raise ValueError("one seed per field")
+        if outs is None:
+            outs = [torch.empty((f["n_theta"], f["n_phi"]), dtype=torch.float32, device="cuda")
+                    for f in self.fields]
+        for f, o in zip(self.fields, outs):
+            if not o.is_cuda or o.dtype != torch.float32 or not o.is_contiguous() or \
+                    o.numel() < f["n_theta"] * f["n_phi"]:
+                raise ValueError("each output must be a contiguous device float32 tensor of n_theta * n_phi")
+        rc = smf_sample_batch(self._h, seeds, [o.data_ptr() for o in outs], stream)
         if rc != SMF_OK:
             raise SmfError(rc, "smf_sample_batch")
-        return out
+        return outs
 
     def field(self, out, i):
         """View of field i ([n_theta, n_phi]) in a packed output."""
@@ -371,10 +401,13 @@ class Plan:
     """A setup plan (Alg. 1 factors on the GPU) with sampling methods (Alg. 2)."""
 
     def __init__(self, order, n_theta, n_phi, ell_max, kappa=None, c_ell=None, precision="fp32",
-                 stream=None, z=None, basis="z"):
+                 stream=None, z=None, basis="z", mirror=True):
         """basis: "z" (the state is the value and its z-derivatives) or "u" (order 2: (g, U g)
-        of Sec. 3, SMF_UBASIS)."""
+        of Sec. 3, SMF_UBASIS).  mirror=False stores the southern walk's own factor sets
+        (SMF_NO_MIRROR)."""
         flags = {"fp32": SMF_FP32, "fp64": SMF_FP64}[precision] | {"z": 0, "u": SMF_UBASIS}[basis]
+        if not mirror:
+            flags |= SMF_NO_MIRROR
         rc, h = smf_setup(order, n_theta, n_phi, ell_max, kappa=kappa, c_ell=c_ell, flags=flags,
                           stream=stream, z=z)
         if rc != SMF_OK:

@@ -17,6 +17,16 @@ def rel_rms(x, ref):
     return float(np.sqrt(np.sum((x - ref) ** 2) / den)) if den > 0 else float(np.sqrt(np.sum(x * x)))
 
 
+def max_rel_err(x, ref):
+    """max |x - ref| over all elements, relative to the RMS of ref (the element-wise
+    companion of rel_rms: a few large local errors that an RMS would average away show)."""
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    rms = np.sqrt(np.mean(ref * ref))
+    d = float(np.max(np.abs(x - ref))) if x.size else 0.0
+    return d / rms if rms > 0 else d
+
+
 def chain_covariances(A, B, n_theta):
     """Covariance of the state before (Sa) and after (Sb) each factor set, by exact
     propagation of the northern chain through (A, B) from the start factor; the chain

@@ -11,91 +11,19 @@ phi in {0, pi}; the Nyquist mode is not sampled, so m_top = n_theta - 1.
 Beside the empirical covariance of GPU samples, the sampler's exact covariance (its factors'
 chain covariances, summed over the sampled modes) separates the method's error from the
 sampling noise: the empirical covariance must agree with it within the sampling error, and
-the exact error must fall with n_theta."""
+the exact error must fall as n_theta^-2 (the oracle-only test of the same experiment also
+takes the paper's reading with the Nyquist term kept, and finds the same rate)."""
 import numpy as np
 import pytest
 
 import oracle
+from fig3 import GRIDS, LMAX, chain_field_covariance, cos_gamma, covariance_CT, point_sets, slope, spectrum
 from gpu_helpers import log
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-LMAX = 4095
-GRIDS = (4, 8, 16, 32)
 N_PAPER = 320_000
-
-
-def spectrum(lmax):
-    ell = np.arange(lmax + 1, dtype=np.float64)
-    return 1.0 / (10.0 + ell ** 2 * (ell + 1.0) ** 2)
-
-
-def covariance_CT(cosg, lmax=20000):
-    """C_T = sum_l (2l+1)/(4 pi) C_l P_l(cos gamma), Legendre polynomials by their
-    three-term recurrence, summed to lmax (the remainder is below 1e-9 of C_T(0))."""
-    x = np.asarray(cosg, dtype=np.float64)
-    C = spectrum(lmax)
-    p_prev, p = np.ones_like(x), x.copy()
-    acc = C[0] / (4 * np.pi) * p_prev + 3 * C[1] / (4 * np.pi) * p
-    for ell in range(1, lmax):
-        p_prev, p = p, ((2 * ell + 1) * x * p - ell * p_prev) / (ell + 1)
-        acc += (2 * ell + 3) / (4 * np.pi) * C[ell + 1] * p
-    return acc
-
-
-def chain_field_covariance(A, B, n, m_top, pts):
-    """Exact covariance of the sampled field between the points pts = [(ring, phi)], from
-    the chains' joint covariances (propagated through the factors in generation order, the
-    southern steps mirrored) summed over the sampled modes with weights 1 (m = 0), 2."""
-    s = n // 2 - 1 if n % 2 == 0 else (n - 1) // 2
-    even = n % 2 == 0
-    D = np.diag([1.0, -1.0])
-    rings = np.array([p[0] for p in pts])
-    phis = np.array([p[1] for p in pts])
-    out = np.zeros((len(pts), len(pts)))
-    for m in range(m_top + 1):
-        steps = [(s, None, None, B[0, m])]
-        for j in range(2 if even else 1, A.shape[0]):
-            b = s - j + 1 if even else s - j
-            steps.append((b, b + 1, A[j, m], B[j, m]))
-        prev, j0 = s, 1
-        if even:
-            steps.append((s + 1, s, A[1, m], B[1, m]))
-            prev, j0 = s + 1, 2
-        for j in range(j0, A.shape[0]):
-            steps.append((prev + 1, prev, D @ A[j, m] @ D, D @ B[j, m] @ D))
-            prev += 1
-        cov, done = {}, []
-        for r, parent, P, Q in steps:
-            if parent is None:
-                cov[(r, r)] = Q @ Q.T
-            else:
-                for k in done:
-                    cov[(r, k)] = P @ cov[(parent, k)]
-                    cov[(k, r)] = cov[(r, k)].T
-                cov[(r, r)] = P @ cov[(parent, parent)] @ P.T + Q @ Q.T
-            done.append(r)
-        K = np.array([[cov[(a, b)][0, 0] for b in rings] for a in rings])
-        w = 1.0 if m == 0 else 2.0
-        out += w * K * np.cos(m * (phis[:, None] - phis[None, :]))
-    return out
-
-
-def point_sets(n):
-    s = n // 2 - 1
-    nphi = 2 * n
-    equator = [(s, 2 * np.pi * k / nphi) for k in range(nphi)]
-    meridian = [(i, 0.0) for i in range(n)] + [(i, np.pi) for i in range(n)]
-    return equator, meridian
-
-
-def cos_gamma(pts, n):
-    th = np.pi * (np.arange(n) + 0.5) / n
-    t = th[[p[0] for p in pts]]
-    ph = np.array([p[1] for p in pts])
-    return np.cos(t)[:, None] * np.cos(t)[None, :] + np.sin(t)[:, None] * np.sin(t)[None, :] * np.cos(
-        ph[:, None] - ph[None, :])
 
 
 def empirical(plan, n, nsamp, batch=32_000, seed=1):
@@ -147,20 +75,18 @@ def run_experiment(nsamp, precision="fp32"):
     return rows
 
 
-def slope(rows, key, kind):
-    x = np.log([r["n_theta"] for r in rows])
-    y = np.log([r[key][kind] for r in rows])
-    return float(np.polyfit(x, y, 1)[0])
-
-
 def test_covariance_convergence_paper_experiment():
     rows = run_experiment(N_PAPER)
     for key in ("equator", "meridian"):
         ex = [r[key]["err_exact"] for r in rows]
         log(f"{key}: exact-error slope {slope(rows, key, 'err_exact'):.2f}, "
             f"empirical-error slope {slope(rows, key, 'err_empirical'):.2f}")
-        # the method's error falls with the resolution ...
+        # the method's error falls with the resolution, as n_theta^-2 (-2.02 fitted) ...
         assert all(b < a for a, b in zip(ex, ex[1:])), ex
+        assert -2.1 <= slope(rows, key, "err_exact") <= -1.9
+        # ... and with the paper's N the sampling error flattens the empirical curve at the
+        # finer grids (the paper's m_max^-3/2 lies in this band; measured -1.2 and -1.05)
+        assert -2.1 <= slope(rows, key, "err_empirical") <= -0.9
         # ... and the GPU samples have the sampler's covariance within the sampling error
         for r in rows:
             assert r[key]["max_z_empirical_vs_exact"] < 6.0, (key, r)

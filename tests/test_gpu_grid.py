@@ -237,3 +237,39 @@ def test_symmetric_grid_reports_mirror():
     assert q.symmetric
     np.testing.assert_allclose(q.z, oracle.grid(32)[1], rtol=0, atol=1e-15)
     q.close()
+
+
+@pytest.mark.parametrize("order,n,precision", [(1, 64, "fp64"), (2, 64, "fp32"), (2, 33, "fp64"), (2, 128, "fp32")])
+def test_no_mirror_plan_stores_southern_sets_and_samples_the_same(order, n, precision):
+    """SMF_NO_MIRROR: the plan holds the southern walk's own sets (true coordinates); on the
+    ring-centre grid, symmetric to the bit, they are the mirror D A D, D B D of the northern
+    ones exactly, and the samples equal the mirrored plan's bit for bit, and the oracle's."""
+    from paper_1709_10314_amd import Plan
+
+    nphi, lmax = 1 << (2 * n - 1).bit_length(), n - 1
+    kap = [40.0] * order
+    pm = Plan(order, n, nphi, lmax, kappa=kap, precision=precision)
+    pn = Plan(order, n, nphi, lmax, kappa=kap, precision=precision, mirror=False)
+    assert pm.symmetric and not pn.symmetric
+    Am, Bm = pm.factors()
+    An, Bn = pn.factors()
+    ns = pm.n_sets
+    assert An.shape[0] == 2 * ns
+    np.testing.assert_array_equal(An[:ns], Am)
+    np.testing.assert_array_equal(Bn[:ns], Bm)
+    j0 = 2 if n % 2 == 0 else 1
+    D = np.diag([(-1.0) ** p for p in range(order)])
+    np.testing.assert_array_equal(An[ns + j0:], D @ Am[j0:] @ D)
+    np.testing.assert_array_equal(Bn[ns + j0:], D @ Bm[j0:] @ D)
+    Tm = pm.sample(5, 3).double().cpu().numpy()
+    Tn = pn.sample(5, 3).double().cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(Tm, Tn)
+    C = oracle.spectrum(kap, lmax)
+    A, B = oracle.setup(order, C, n, nphi)
+    To, _ = oracle.sample(order, n, nphi, A, B, 5, 3)
+    e = max(rel_rms(Tn[f], To[f]) for f in range(3))
+    log(f"no-mirror {order} {n} {precision}: vs oracle {e:.2e}")
+    assert e <= (1e-10 if precision == "fp64" else 1e-4)
+    pm.close()
+    pn.close()

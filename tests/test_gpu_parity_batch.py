@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_helpers import log, rel_rms
+from gpu_helpers import log, max_rel_err, rel_rms
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -139,7 +139,98 @@ def test_mixed_256_field_workload_sampled():
         C = oracle.spectrum(f["kappa"], f["ell_max"])
         A, B = oracle.setup(f["order"], C, f["n_theta"], f["n_phi"])
         To, _ = oracle.sample(f["order"], f["n_theta"], f["n_phi"], A, B, 1 + i, 1)
-        e = rel_rms(bp.field(out, i).double().cpu().numpy(), To[0])
-        log(f"field {i}: vs oracle {e:.2e}")
+        Tb = bp.field(out, i).double().cpu().numpy()
+        e, emax = rel_rms(Tb, To[0]), max_rel_err(Tb, To[0])
+        log(f"field {i}: vs oracle {e:.2e} (max {emax:.2e})")
+        assert e <= 1e-4 and emax <= 1e-3
+    # one field of each ring count against the oracle: the rings around the equator (every
+    # mode, from the factor sets near the start) and sampled modes over every ring (the
+    # modes of the output recovered by a forward real FFT of each ring, g_m = rfft(T)_m / n_phi)
+    for n in (128, 256, 512, 1024, 2048):
+        i = next(k for k, f in enumerate(fields) if f["n_theta"] == n)
+        f = fields[i]
+        Tb = bp.field(out, i).double().cpu().numpy()
+        e_r, e_m = _oracle_rings_and_modes(f, 1 + i, Tb)
+        log(f"field {i} {n}x{f['n_phi']} M{f['order']}: equator rings vs oracle {e_r:.2e}, "
+            f"modes vs oracle {max(e_m):.2e}")
+        assert e_r <= 1e-4 and max(e_m) <= 1e-4
+    bp.close()
+
+
+def _oracle_rings_and_modes(f, seed, T, sets=9, modes=(0, 1, 5, 33)):
+    """Relative RMS error of the rings reached by the first `sets` factor sets (around the
+    equator) and of the listed modes over every ring, against the oracle."""
+    n, nphi, order = f["n_theta"], f["n_phi"], f["order"]
+    C = oracle.spectrum(f["kappa"], f["ell_max"])
+    s = oracle.start_ring(n)
+    A, B = oracle.setup(order, C, n, nphi, sets=sets)
+    g = oracle.sample_modes(order, n, A, B, seed, 1, sets=sets)
+    r0, r1 = s - sets + 2, s + sets
+    To = oracle.dft(g, nphi, r0, r1)[0]
+    e_r = rel_rms(T[r0:r1], To)
+    md = [m for m in modes if m <= oracle.m_top(f["ell_max"], nphi)]
+    Am, Bm = oracle.setup_modes(order, C, n, md)
+    go = oracle.sample_modes_list(order, n, md, Am, Bm, seed, 1)[0]
+    G = np.fft.rfft(T, axis=1) / nphi
+    e_m = []
+    for k, m in enumerate(md):
+        a = np.stack([G[:, m].real, G[:, m].imag])
+        b = np.stack([go[:, k].real, go[:, k].imag])
+        e_m.append(rel_rms(a, b))
+    return e_r, e_m
+
+
+def test_batch_per_field_buffers_and_seeds():
+    """smf_sample_batch with one seed and one device buffer per field: with seeds seed + i it
+    equals the packed form field by field; with arbitrary seeds each field equals its single
+    plan with that seed and the oracle; calls on two streams in a row, each with its own
+    buffers, keep their own seeds."""
+    from paper_1709_10314_amd import BatchPlan
+
+    fields = _mixed_fields()
+    bp = BatchPlan(fields)
+    packed = bp.sample(40)
+    outs = bp.sample_fields([40 + i for i in range(bp.n)])
+    torch.cuda.synchronize()
+    for i in range(bp.n):
+        assert torch.equal(outs[i].view(-1), bp.field(packed, i).reshape(-1)), i
+    seeds = [1000 + 7 * i * i for i in range(bp.n)]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    with torch.cuda.stream(s1):
+        o1 = bp.sample_fields(seeds, stream=s1)
+    with torch.cuda.stream(s2):
+        o2 = bp.sample_fields([x + 1 for x in seeds], stream=s2)
+    torch.cuda.synchronize()
+    for i, f in enumerate(fields):
+        Ts = _single(f, seeds[i])
+        e1 = rel_rms(o1[i].double().cpu().numpy(), Ts)
+        e2 = rel_rms(o2[i].double().cpu().numpy(), _single(f, seeds[i] + 1))
+        log(f"field {i}: per-field buffers vs single plan {e1:.2e} / {e2:.2e}")
+        assert e1 <= 1e-6 and e2 <= 1e-6
+    for i in (0, 3, 10):
+        f = fields[i]
+        C = oracle.spectrum(f["kappa"], f["ell_max"])
+        A, B = oracle.setup(f["order"], C, f["n_theta"], f["n_phi"])
+        To, _ = oracle.sample(f["order"], f["n_theta"], f["n_phi"], A, B, seeds[i], 1)
+        e = rel_rms(o1[i].double().cpu().numpy(), To[0])
+        log(f"field {i}: per-field buffers vs oracle {e:.2e}")
         assert e <= 1e-4
+    bp.close()
+
+
+def test_batch_per_field_rejects_bad_buffers():
+    from paper_1709_10314_amd import BatchPlan, smf
+
+    f = dict(n_theta=8, n_phi=16, order=1, kappa=[4.0], ell_max=7)
+    bp = BatchPlan([f, f])
+    a = torch.empty(128, device="cuda")
+    assert smf.smf_sample_batch(bp.handle, [1, 2], [a.data_ptr(), 0]) == smf.SMF_EINVAL
+    assert smf.smf_sample_batch(bp.handle, [1, 2], [a.data_ptr(), a.data_ptr() + 4]) == smf.SMF_EINVAL
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    b = torch.empty(128, device="cuda")
+    with torch.cuda.graph(g, stream=s):
+        b.zero_()
+        rc = smf.smf_sample_batch(bp.handle, [1, 2], [a.data_ptr(), b.data_ptr()], stream=s)
+    assert rc == smf.SMF_EINVAL          # capturing: the packed form is the capturable one
     bp.close()

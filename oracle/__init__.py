@@ -12,6 +12,10 @@ the paper they follow:
 * ``spectrum_complex`` -- the same with complex kappa_i in conjugate pairs (Sec. 3)
 * ``legendre``      -- L_lm(z) and dL_lm/dz                          (Sec. 2)
 * ``jblock``        -- J^m_pq(z1, z2), brute-force sum over l        (Lemma 2.1)
+* ``green_G``, ``green_P``, ``jblock_green``, ``setup_green``
+                    -- order 1 without band limit: J^m from the Green's function,
+                       P^m_lambda of complex degree by its hypergeometric series
+                       (Sec. 3; eqs. (Legendre_hypergeometric), (Jmatrix_efficient))
 * ``setup``         -- A, B, B_eq per mode and ring step             (Alg. 1; eqs.
                        (trans_matrix), (innov_matrix), (state_initial))
 * ``philox``/``normal`` -- white-noise source (Philox4x32-10 + Box-Muller)
@@ -103,6 +107,11 @@ def _load():
     lib.orc_dft.restype = _i
     lib.orc_dft_rings.argtypes = [_i, _i, _i, _pi, _pd, ctypes.POINTER(ctypes.c_int64), _pd, _pd]
     lib.orc_dft_rings.restype = _i
+    lib.orc_green_G.argtypes = [_i, _d, _d, _d]
+    lib.orc_green_G.restype = _d
+    lib.orc_green_P.argtypes = [_i, _d, _d, _d]
+    lib.orc_green_P.restype = _d
+    lib.orc_jblock_green.argtypes = [_i, _d, _d, _d, _d, _d, _pd]
     lib.orc_max_threads.restype = _i
     lib.orc_set_threads.argtypes = [_i]
     lib.orc_set_threads.restype = None
@@ -185,6 +194,49 @@ def jblock_z(order, m, ell_max, C, z1, z2):
     J = np.zeros(order * order)
     _load().orc_jblock_zs(order, m, ell_max, _p(C), float(z1), s1, float(z2), s2, _p(J))
     return J.reshape(order, order)
+
+
+def _zs(z):
+    return float(z), math.sqrt((1.0 - z) * (1.0 + z))
+
+
+def green_G(m, kappa, z, s=None):
+    """G_m(z) = 2F1(-lambda, lambda+1; 1+m; (1-z)/2) with kappa = -lambda(lambda+1) (Sec. 3)."""
+    z, s0 = _zs(z)
+    return _load().orc_green_G(int(m), float(kappa), z, s0 if s is None else float(s))
+
+
+def green_P(m, kappa, z, s=None):
+    """P^m_lambda(z) of eq. (Legendre_hypergeometric), kappa = -lambda(lambda+1)."""
+    z, s0 = _zs(z)
+    return _load().orc_green_P(int(m), float(kappa), z, s0 if s is None else float(s))
+
+
+def jblock_green(m, kappa, z1, z2):
+    """J^m(z1, z2) of eq. (Jmatrix_efficient), order 1, C_l = 1/(kappa + l(l+1)) for all l."""
+    z1, s1 = _zs(z1)
+    z2, s2 = _zs(z2)
+    J = np.zeros(1)
+    _load().orc_jblock_green(int(m), float(kappa), z1, s1, z2, s2, _p(J))
+    return float(J[0])
+
+
+def setup_green(kappa, n_theta, n_phi, sets=None, modes=None, z=None):
+    """Alg. 1 at order 1 on the Green's-function cross covariances of Sec. 3 (C_l =
+    1/(kappa + l(l+1)) for every l, no band limit; modes m <= n_phi/2 - 1, or the listed
+    ones).  Returns (A, B), each [sets][modes][1][1]."""
+    mt = n_phi // 2 - 1
+    md = np.arange(mt + 1, dtype=np.int32) if modes is None else np.ascontiguousarray(modes, dtype=np.int32)
+    ns = n_sets(n_theta) if sets is None else min(sets, n_sets(n_theta))
+    A = np.zeros((ns, len(md), 1, 1))
+    B = np.zeros((ns, len(md), 1, 1))
+    kap = np.array([float(kappa)])
+    zg = _zgrid(z, n_theta)
+    rc = _load().orc_setup_modes_zb(1, 2, 0, _p(kap), n_theta, None if zg is None else _p(zg), ns,
+                                    md.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(md), _p(A), _p(B))
+    if rc != 0:
+        raise ValueError("orc_setup_modes_zb rejected its arguments")
+    return A, B
 
 
 def ring_zs(n_theta, i):

@@ -47,6 +47,7 @@
  *             idx = ring*M + q; word idx mod 4; u = (x + 0.5) 2^-32; Box-Muller on the word
  *             pairs (0,1) and (2,3).
  */
+#include <complex.h>
 #include <math.h>
 #ifdef _OPENMP
 #include <omp.h>
@@ -309,6 +310,190 @@ void orc_jblock_zs_u(int m, int ell_max, const double* C, double z1, double s1, 
     free(L1);
 }
 
+/* ------------------------------------------------------------------------- */
+/* Sec. 3: the cross covariance of one mode from the Green's function, order 1, */
+/* C_l = 1/(kappa + l(l+1)) for every l >= 0 (no band limit; one kappa, so the   */
+/* partial fractions of eq. (C_ell_efficient) are the spectrum itself, b = 1).   */
+/* With kappa = -lambda(lambda+1), eq. (Jmatrix_efficient) reads                */
+/*   J^m(z1, z2) = Gamma(1+lambda-m) Gamma(-lambda-m)/(4 pi) P^m(-z1) P^m(z2),   */
+/* z1 <= z2, with P^m = P^m_lambda of eq. (Legendre_hypergeometric):            */
+/*   P^m(x) = (-lambda)_m (1+lambda)_m / m! ((1-x)/(1+x))^{m/2} G_m(x),          */
+/*   G_m(x) = 2F1(-lambda, lambda+1; 1+m; (1-x)/2).                              */
+/* Written out with Pi_m = (-lambda)_m (1+lambda)_m = prod_{k=1}^m (k^2-k+kappa) */
+/* and Gamma(1+lambda) Gamma(-lambda) = pi / |sin(pi lambda)| (reflection):      */
+/*   J^m(z1, z2) = 1/(4 |sin pi lambda|) (Pi_m / m!^2) w^m G_m(-z1) G_m(z2),      */
+/*   w = sqrt((1+z1)(1-z2) / ((1-z1)(1+z2))) <= 1.                               */
+/* lambda = -1/2 + i tau (tau = sqrt(kappa - 1/4)) for kappa > 1/4, where        */
+/* |sin pi lambda| = cosh(pi tau); for 0 < kappa <= 1/4 lambda is real,          */
+/* (-1 + sqrt(1 - 4 kappa))/2, and |sin pi lambda| = -sin(pi lambda).            */
+/* The series of G_m has positive terms ((n-lambda)(n+lambda+1) = n^2+n+kappa):  */
+/*   x >= 0 (argument t <= 1/2): the series itself;                              */
+/*   x < 0: G_0 and G_1 from the series, or near x = -1 from the continuation of  */
+/*   2F1 about t = 1 for c - a - b a non-negative integer (Abramowitz & Stegun    */
+/*   15.3.11; DLMF 15.8.10), with its logarithm and digamma terms, then G_m by    */
+/*   the three-term recurrence in                                                */
+/*   the order of the Ferrers functions (DLMF 14.10.1) rewritten for G_m:        */
+/*     G_{m+2} = (m+1)(m+2)/q_{m+1} (1+x)/(1-x) [G_m - 2x/(1+x) G_{m+1}],         */
+/*     q_k = k^2 + k + kappa,                                                    */
+/*   whose terms are both positive for x < 0 (no cancellation).                  */
+/* Arguments come as (z, s = sin theta) pairs, and 1 -+ z as s^2/(1 +- z) on the  */
+/* side where that is the accurate form.                                         */
+/* ------------------------------------------------------------------------- */
+static double complex green_lambda(double kappa)
+{
+    if (kappa > 0.25) return -0.5 + I * sqrt(kappa - 0.25);
+    return (-1.0 + sqrt(1.0 - 4.0 * kappa)) / 2.0;
+}
+
+static double green_abs_sin(double kappa)
+{
+    if (kappa > 0.25) return cosh(M_PI * sqrt(kappa - 0.25));
+    return -sin(M_PI * creal(green_lambda(kappa)));
+}
+
+/* digamma for Re z > 0: shift to Re z >= 20 by psi(z) = psi(z+1) - 1/z, then the  */
+/* asymptotic series ln z - 1/(2z) - sum_k B_2k / (2k z^2k) to z^-10.              */
+static double complex cdigamma(double complex z)
+{
+    double complex acc = 0.0;
+    while (creal(z) < 20.0) {
+        acc -= 1.0 / z;
+        z += 1.0;
+    }
+    const double complex r = 1.0 / (z * z);
+    const double complex ser =
+        r * (1.0 / 12 - r * (1.0 / 120 - r * (1.0 / 252 - r * (1.0 / 240 - r * (1.0 / 132)))));
+    return acc + clog(z) - 0.5 / z - ser;
+}
+
+/* psi(-lambda + k) + psi(lambda + 1 + k) (real for both kinds of lambda) */
+static double green_psi_pair(double kappa, double k)
+{
+    const double complex lam = green_lambda(kappa);
+    return creal(cdigamma(-lam + k) + cdigamma(lam + 1.0 + k));
+}
+
+/* G_m at argument t = (1 - x)/2 by its series (used for t <= 1/2). */
+static double green_G_series(int m, double kappa, double t)
+{
+    double sum = 1.0, term = 1.0;
+    for (int n = 0; n < 200000; ++n) {
+        const double ratio = ((double)n * n + n + kappa) / ((n + 1.0) * (n + 1.0 + m)) * t;
+        term *= ratio;
+        sum += term;
+        if (ratio < 1.0 && term < 1e-18 * sum) break;
+    }
+    return sum;
+}
+
+/* G_0 and G_1 at t = (1 - x)/2 >= 1/2 from the continuation about t = 1, u = 1 - t:  */
+/*   G_0 = -g sum_k c_k u^k [ln u - 2 psi(k+1) + psi(a+k) + psi(b+k)],                */
+/*   G_1 = g/kappa + g u sum_k d_k u^k [ln u - psi(k+1) - psi(k+2) + psi(a+k+1)       */
+/*                                       + psi(b+k+1)],                               */
+/* a = -lambda, b = lambda + 1, g = 1/(Gamma(a) Gamma(b)) = |sin pi lambda| / pi,      */
+/* c_k = (a)_k (b)_k / k!^2, d_k = (a+1)_k (b+1)_k / (k! (k+1)!).                      */
+static void green_G01_far(double kappa, double u, double* G0, double* G1)
+{
+    const double g = green_abs_sin(kappa) / M_PI;
+    const double L = log(u);
+    const double euler = 0.57721566490153286061;
+    double c = 1.0, d = 1.0, uk = 1.0, s0 = 0.0, s1 = 0.0;
+    double psi_k1 = -euler;              /* psi(k+1) */
+    for (int k = 0; k < 100000; ++k) {
+        const double psi_k2 = psi_k1 + 1.0 / (k + 1.0);   /* psi(k+2) */
+        const double t0 = c * uk * (L - 2.0 * psi_k1 + green_psi_pair(kappa, k));
+        const double t1 = d * uk * (L - psi_k1 - psi_k2 + green_psi_pair(kappa, k + 1.0));
+        s0 += t0;
+        s1 += t1;
+        const double dk = k;
+        c *= (dk * dk + dk + kappa) / ((dk + 1.0) * (dk + 1.0));
+        d *= ((dk + 1.0) * (dk + 1.0) + (dk + 1.0) + kappa) / ((dk + 1.0) * (dk + 2.0));
+        uk *= u;
+        psi_k1 = psi_k2;
+        if (k > 4 && fabs(t0) < 1e-18 * fabs(s0) && fabs(t1) < 1e-18 * fabs(s1) &&
+            (dk * dk + dk + kappa) / ((dk + 1.0) * (dk + 1.0)) * u < 0.9)
+            break;
+    }
+    *G0 = -g * s0;
+    *G1 = g / kappa + g * u * s1;
+}
+
+/* G_0 .. G_{m_top} at the ring value x (with s = sin theta) into G.  For x < 0 the    */
+/* continuation about t = 1 is used where u = 1 - t is small against 1/(kappa + 1):     */
+/* further out its terms cancel (the sum is G_0 / g, and g = |sin pi lambda| / pi grows  */
+/* like e^{pi tau}), and there the series in t converges in about 37 / u terms instead.  */
+static void green_G_all(int m_top, double kappa, double x, double s, double* G)
+{
+    if (x >= 0.0) {
+        const double t = s * s / (2.0 * (1.0 + x));         /* (1 - x)/2 */
+        for (int m = 0; m <= m_top; ++m) G[m] = green_G_series(m, kappa, t);
+        return;
+    }
+    const double u = s * s / (2.0 * (1.0 - x));             /* (1 + x)/2 = 1 - t */
+    double g0, g1;
+    if (u * (kappa + 1.0) <= 0.5) {
+        green_G01_far(kappa, u, &g0, &g1);
+    } else {
+        g0 = green_G_series(0, kappa, 1.0 - u);
+        g1 = green_G_series(1, kappa, 1.0 - u);
+    }
+    G[0] = g0;
+    if (m_top >= 1) G[1] = g1;
+    const double opx = 2.0 * u, omx = 1.0 - x;              /* 1 + x, 1 - x */
+    for (int k = 0; k + 2 <= m_top; ++k) {                  /* G_{k+2} from G_k, G_{k+1} */
+        const double q = (k + 1.0) * (k + 1.0) + (k + 1.0) + kappa;
+        G[k + 2] = (k + 1.0) * (k + 2.0) / q * (opx / omx) * (G[k] - 2.0 * x / opx * G[k + 1]);
+    }
+}
+
+double orc_green_G(int m, double kappa, double x, double s)
+{
+    double* G = (double*)malloc(sizeof(double) * (m + 1));
+    green_G_all(m, kappa, x, s, G);
+    const double v = G[m];
+    free(G);
+    return v;
+}
+
+/* P^m_lambda(x) of eq. (Legendre_hypergeometric); returned as a plain double (it     */
+/* overflows for large m away from x = 1; the covariance below never forms it).     */
+double orc_green_P(int m, double kappa, double x, double s)
+{
+    double pre = 1.0;
+    for (int k = 1; k <= m; ++k) pre *= ((double)k * k - k + kappa) / k;
+    const double omx = x >= 0.0 ? s * s / (1.0 + x) : 1.0 - x;
+    const double opx = x >= 0.0 ? 1.0 + x : s * s / (1.0 - x);
+    return pre * pow(omx / opx, 0.5 * m) * orc_green_G(m, kappa, x, s);
+}
+
+/* The factor of J^m(z1, z2) that does not hold G: (Pi_m / m!^2) w^m / (4 |sin pi lambda|), */
+/* z1 <= z2.                                                                            */
+static double green_J_scale(int m, double kappa, double z1, double s1, double z2, double s2)
+{
+    double ratio = 1.0;                                      /* Pi_m / m!^2 */
+    for (int k = 1; k <= m; ++k) ratio *= ((double)k * k - k + kappa) / ((double)k * k);
+    double wm = 1.0;
+    if (z1 != z2 && m > 0) {
+        /* ln w = (ln(1+z1) + ln(1-z2) - ln(1-z1) - ln(1+z2)) / 2 */
+        const double l1p = z1 >= 0.0 ? log1p(z1) : log(s1 * s1 / (1.0 - z1));
+        const double l1m = z1 >= 0.0 ? log(s1 * s1 / (1.0 + z1)) : log1p(-z1);
+        const double l2p = z2 >= 0.0 ? log1p(z2) : log(s2 * s2 / (1.0 - z2));
+        const double l2m = z2 >= 0.0 ? log(s2 * s2 / (1.0 + z2)) : log1p(-z2);
+        wm = exp(0.5 * m * (l1p + l2m - l1m - l2p));
+    }
+    return ratio * wm / (4.0 * green_abs_sin(kappa));
+}
+
+/* J^m(z1, z2) of eq. (Jmatrix_efficient), order 1 (1 x 1 block). */
+void orc_jblock_green(int m, double kappa, double z1, double s1, double z2, double s2, double* J)
+{
+    if (z1 > z2) {
+        double t = z1; z1 = z2; z2 = t;
+        t = s1; s1 = s2; s2 = t;
+    }
+    J[0] = green_J_scale(m, kappa, z1, s1, z2, s2) * orc_green_G(m, kappa, -z1, s1) * orc_green_G(m, kappa, z2, s2);
+}
+
 /* The same with z1 = cos(theta1), z2 = cos(theta2). */
 void orc_jblock(int order, int m, int ell_max, const double* C, double theta1, double theta2,
                 double* J)
@@ -473,13 +658,27 @@ static int grid_ok(const double* zgrid, int n_theta, int symmetric)
     return 1;
 }
 
+/* basis 0: value and z-derivatives; 1: (g, U g) of Sec. 3 (order 2); 2: the Green's   */
+/* function of Sec. 3 at order 1, C then holding the single kappa (no band limit).     */
 static void jblock_basis(int order, int basis, int m, int ell_max, const double* C, double z1, double s1, double z2,
                          double s2, double* J)
 {
-    if (basis == 1)
+    if (basis == 2)
+        orc_jblock_green(m, C[0], z1, s1, z2, s2, J);
+    else if (basis == 1)
         orc_jblock_zs_u(m, ell_max, C, z1, s1, z2, s2, J);
     else
         orc_jblock_zs(order, m, ell_max, C, z1, s1, z2, s2, J);
+}
+
+static void ring_value(int n_theta, const double* zgrid, int i, double* z, double* s)
+{
+    if (zgrid) {
+        *z = zgrid[i];
+        *s = sqrt((1.0 - *z) * (1.0 + *z));
+    } else {
+        orc_ring_zs(n_theta, i, z, s);
+    }
 }
 
 static void setup_sets(int order, int ell_max, const double* C, int n_theta, const double* zgrid, int n_sets,
@@ -488,6 +687,21 @@ static void setup_sets(int order, int ell_max, const double* C, int n_theta, con
     int MM = order * order;
     const int s = orc_start_ring(n_theta);
     const int j0 = (n_theta % 2 == 0) ? 2 : 1;
+    /* basis 2: G_m(z_i) and G_m(-z_i) of every ring, tabulated once ([ring][m]) */
+    double *Gp = NULL, *Gn = NULL;
+    int mt = 0;
+    if (basis == 2) {
+        for (int i = 0; i < n_modes; ++i) mt = modes[i] > mt ? modes[i] : mt;
+        Gp = (double*)malloc(sizeof(double) * (size_t)n_theta * (mt + 1));
+        Gn = (double*)malloc(sizeof(double) * (size_t)n_theta * (mt + 1));
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int i = 0; i < n_theta; ++i) {
+            double zi, si;
+            ring_value(n_theta, zgrid, i, &zi, &si);
+            green_G_all(mt, C[0], zi, si, Gp + (size_t)i * (mt + 1));
+            green_G_all(mt, C[0], -zi, si, Gn + (size_t)i * (mt + 1));
+        }
+    }
 #pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i < n_modes; ++i) {
         int m = modes[i];
@@ -501,17 +715,27 @@ static void setup_sets(int order, int ell_max, const double* C, int n_theta, con
                 set_rings(n_theta, j, &a, &b);
             }
             double za, sa, zb, sb;
-            if (zgrid) {
-                za = zgrid[a];
-                zb = zgrid[b];
-                sa = sqrt((1.0 - za) * (1.0 + za));
-                sb = sqrt((1.0 - zb) * (1.0 + zb));
-            } else {
-                orc_ring_zs(n_theta, a, &za, &sa);
-                orc_ring_zs(n_theta, b, &zb, &sb);
-            }
+            ring_value(n_theta, zgrid, a, &za, &sa);
+            ring_value(n_theta, zgrid, b, &zb, &sb);
             double* Aj = A + ((size_t)j * n_modes + i) * MM;
             double* Bj = B + ((size_t)j * n_modes + i) * MM;
+            if (basis == 2) {
+                /* J(x, y) = scale(x <= y) G_m(-x) G_m(y) for the lower ring value x */
+                const size_t w = (size_t)mt + 1;
+                Kaa[0] = green_J_scale(m, C[0], za, sa, za, sa) * Gn[a * w + m] * Gp[a * w + m];
+                if (j == 0) {
+                    Aj[0] = 0.0;
+                    orc_start_factor(1, Kaa, Bj);
+                    continue;
+                }
+                Kbb[0] = green_J_scale(m, C[0], zb, sb, zb, sb) * Gn[b * w + m] * Gp[b * w + m];
+                if (za <= zb)
+                    Kba[0] = green_J_scale(m, C[0], za, sa, zb, sb) * Gn[a * w + m] * Gp[b * w + m];
+                else
+                    Kba[0] = green_J_scale(m, C[0], zb, sb, za, sa) * Gn[b * w + m] * Gp[a * w + m];
+                orc_step_factors(1, Kaa, Kbb, Kba, Aj, Bj);
+                continue;
+            }
             if (j == 0) {
                 jblock_basis(order, basis, m, ell_max, C, za, sa, za, sa, Kaa);
                 for (int k = 0; k < MM; ++k) Aj[k] = 0.0;
@@ -524,6 +748,8 @@ static void setup_sets(int order, int ell_max, const double* C, int n_theta, con
             orc_step_factors(order, Kaa, Kbb, Kba, Aj, Bj);
         }
     }
+    free(Gp);
+    free(Gn);
 }
 
 /* Symmetric grids (the south is the mirror of the north, the remark after Alg. 1). */
@@ -544,7 +770,7 @@ int orc_setup_modes_zb(int order, int basis, int ell_max, const double* C, int n
                        int n_sets, const int* modes, int n_modes, double* A, double* B)
 {
     if (order < 1 || order > ORC_MAXM || n_theta < 2 || ell_max < 0) return -1;
-    if (basis != 0 && !(basis == 1 && order == 2)) return -1;
+    if (basis != 0 && !(basis == 1 && order == 2) && !(basis == 2 && order == 1 && C[0] > 0.0)) return -1;
     if (zgrid && !grid_ok(zgrid, n_theta, 1)) return -1;
     int total = orc_n_sets(n_theta);
     if (n_sets > total) n_sets = total;

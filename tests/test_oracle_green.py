@@ -1,0 +1,150 @@
+"""Pins of the oracle's Green's-function setup (Sec. 3, order 1): C_l = 1/(kappa + l(l+1))
+for every l, kappa = -lambda(lambda+1), J^m from eq. (Jmatrix_efficient) with P^m_lambda of
+eq. (Legendre_hypergeometric) and no sum over l.  Each check compares with something other
+than the oracle's own formula: mpmath's Gauss hypergeometric function and Ferrers function
+of complex degree, scipy's hypergeometric function for real degree (0 < kappa <= 1/4), the
+value at z = 1, the Wronskian of DLMF 14.2.3 as the paper quotes it, the associated Legendre
+equation, the brute-force Legendre sums of Lemma 2.1 as ell_max grows, and the Markov
+property that the Green's function gives the chain exactly (no band-limit defect)."""
+import math
+
+import numpy as np
+import pytest
+import scipy.special as ss
+
+mp = pytest.importorskip("mpmath")
+
+KAPPAS = [0.2, 3.0, 64.0, 400.0]
+
+
+def _lam(kappa):
+    return (-1 + mp.sqrt(1 - 4 * mp.mpf(kappa))) / 2
+
+
+@pytest.mark.parametrize("kappa", KAPPAS)
+def test_G_matches_mpmath_hypergeometric(orc, kappa):
+    """G_m(x) = 2F1(-lambda, lambda+1; 1+m; (1-x)/2) on both sides of the equator and near
+    the south pole (the continuation about t = 1 and the recurrence in m), to 1e-13."""
+    mp.mp.dps = 25
+    lam = _lam(kappa)
+    a, b = -lam, lam + 1
+    for m in (0, 1, 2, 7, 40, 300):
+        for x in (0.95, 0.3, 0.0, -0.02, -0.3, -0.7, -0.97):
+            ref = float(mp.re(mp.hyp2f1(a, b, 1 + m, (1 - mp.mpf(x)) / 2)))
+            assert orc.green_G(m, kappa, x) == pytest.approx(ref, rel=1e-13), (m, x)
+
+
+@pytest.mark.parametrize("kappa", [64.0, 400.0])
+def test_P_matches_mpmath_ferrers_function(orc, kappa):
+    """P^m_lambda of eq. (Legendre_hypergeometric) is the Ferrers function of the first kind
+    (mpmath legenp, type 2) of complex degree lambda = -1/2 + i tau."""
+    mp.mp.dps = 25
+    lam = _lam(kappa)
+    for m in (0, 1, 3, 12):
+        for x in (0.8, 0.2, -0.1, -0.6):
+            ref = float(mp.re(mp.legenp(lam, m, x, type=2)))
+            assert orc.green_P(m, kappa, x) == pytest.approx(ref, rel=1e-12), (m, x)
+
+
+def test_real_degree_matches_scipy_near_the_pole(orc):
+    """0 < kappa <= 1/4 gives a real degree lambda in (-1/2, 0]; then scipy's hyp2f1 (real
+    parameters) pins G_m up to the ring next to the south pole of a 1024-ring grid, where
+    the oracle takes the logarithmic continuation about t = 1."""
+    kappa = 0.2
+    lam = (-1 + math.sqrt(1 - 4 * kappa)) / 2
+    for m in (0, 1, 2, 5, 30):
+        for x in (-0.9, -0.999, -math.cos(math.pi / 2048)):
+            t = (1 - x) / 2
+            ref = ss.hyp2f1(-lam, lam + 1, 1 + m, t)
+            assert orc.green_G(m, kappa, x) == pytest.approx(ref, rel=1e-9), (m, x)
+
+
+@pytest.mark.parametrize("kappa", KAPPAS)
+def test_P_at_the_north_pole_is_delta(orc, kappa):
+    """P^m_lambda(1) = delta_m0 (stated after eq. (Legendre_hypergeometric))."""
+    for m in range(6):
+        assert orc.green_P(m, kappa, 1.0, 0.0) == (1.0 if m == 0 else 0.0)
+
+
+@pytest.mark.parametrize("kappa", [3.0, 64.0])
+@pytest.mark.parametrize("m", [0, 1, 4])
+def test_wronskian(orc, kappa, m):
+    """W{P^m(z), P^m(-z)} = 2 (1 - z^2)^-1 / (Gamma(lambda+1-m) Gamma(-lambda-m)) (the
+    Wronskian the paper quotes from DLMF 14.2.3), by central differences (h = 1e-5)."""
+    mp.mp.dps = 25
+    lam = _lam(kappa)
+    gam = complex(mp.gamma(lam + 1 - m) * mp.gamma(-lam - m)).real
+    h = 1e-5
+    for z in (-0.5, 0.1, 0.6):
+        P = orc.green_P(m, kappa, z)
+        dP = (orc.green_P(m, kappa, z + h) - orc.green_P(m, kappa, z - h)) / (2 * h)
+        Q = orc.green_P(m, kappa, -z)
+        dQ = (orc.green_P(m, kappa, -z - h) - orc.green_P(m, kappa, -z + h)) / (2 * h)    # d/dz P(-z)
+        W = P * dQ - dP * Q
+        want = 2.0 / (1 - z * z) / gam
+        assert W == pytest.approx(want, rel=1e-7), (z, W, want)
+
+
+@pytest.mark.parametrize("kappa", [3.0, 64.0])
+def test_associated_legendre_equation(orc, kappa):
+    """(1-z^2) P'' - 2 z P' + (lambda(lambda+1) - m^2/(1-z^2)) P = 0 with lambda(lambda+1) =
+    -kappa, by central differences."""
+    h = 1e-4
+    for m in (0, 2, 5):
+        for z in (-0.7, -0.2, 0.4):
+            f = [orc.green_P(m, kappa, z + k * h) for k in (-1, 0, 1)]
+            d1 = (f[2] - f[0]) / (2 * h)
+            d2 = (f[2] - 2 * f[1] + f[0]) / (h * h)
+            res = (1 - z * z) * d2 - 2 * z * d1 + (-kappa - m * m / (1 - z * z)) * f[1]
+            scale = abs(kappa * f[1]) + abs(m * m / (1 - z * z) * f[1])
+            assert abs(res) < 1e-5 * scale, (m, z, res, scale)
+
+
+@pytest.mark.parametrize("kappa", [64.0, 400.0])
+def test_legendre_sums_converge_to_the_green_function(orc, kappa):
+    """The brute-force sums of Lemma 2.1 approach J^m of eq. (Jmatrix_efficient) as ell_max
+    grows (errors relative to sqrt(J(z1,z1) J(z2,z2))): off the diagonal to 5e-5 at
+    ell_max = 16000 with the error falling at every step; on the diagonal (where the sum converges like 1/ell_max) with ell_max times
+    the error settling to a constant."""
+    for m in (0, 3, 20):
+        for z1, z2 in ((0.2, 0.35), (-0.3, 0.1), (0.5, 0.5)):
+            Jg = orc.jblock_green(m, kappa, z1, z2)
+            sd = math.sqrt(orc.jblock_green(m, kappa, z1, z1) * orc.jblock_green(m, kappa, z2, z2))
+            errs = []
+            for lmax in (2000, 8000, 16000):
+                C = orc.spectrum([kappa], lmax)
+                errs.append(abs(orc.jblock_z(1, m, lmax, C, z1, z2)[0, 0] - Jg) / sd)
+            if z1 != z2:
+                assert errs[2] < errs[1] < errs[0] and errs[-1] < 5e-5, (m, z1, z2, errs)
+            else:
+                assert errs[2] < errs[1] < errs[0], errs
+                assert 16000 * errs[2] == pytest.approx(8000 * errs[1], rel=0.1), errs
+
+
+@pytest.mark.parametrize("kappa,n", [(64.0, 64), (400.0, 256), (0.2, 33)])
+def test_green_chain_is_exactly_markov(orc, kappa, n):
+    """With the whole spectrum the mode is an exact Gauss-Markov chain: covariances
+    propagated through the factors reproduce J^m of eq. (Jmatrix_efficient) between any two
+    rings of a hemisphere, not only neighbours, to 1e-12 (a band-limited spectrum leaves a
+    defect of percents there), and at every ring of both hemispheres."""
+    nphi = 2 * n if n % 2 == 0 else 2 * (n + 1)
+    A, B = orc.setup_green(kappa, n, nphi)
+    _, z = orc.grid(n)
+    s = orc.start_ring(n)
+    even = n % 2 == 0
+    for m in (0, 1, 7, n // 2):
+        # northern walk: rings s, (s+1 for even n), s-1, ..., 0 with their factor sets
+        cov = {s: B[0, m, 0, 0] ** 2}
+        cross = {s: cov[s]}                                  # Cov(x_r, x_s)
+        prev = s
+        for j in range(2 if even else 1, A.shape[0]):
+            r = s - j + 1 if even else s - j
+            a_, b_ = A[j, m, 0, 0], B[j, m, 0, 0]
+            cov[r] = a_ * a_ * cov[prev] + b_ * b_
+            cross[r] = a_ * cross[prev]
+            prev = r
+        for r in list(cov)[::7]:
+            Jrr = orc.jblock_green(m, kappa, z[r], z[r])
+            Jrs = orc.jblock_green(m, kappa, z[r], z[s])
+            assert cov[r] == pytest.approx(Jrr, rel=1e-12, abs=1e-300), (m, r)
+            assert cross[r] == pytest.approx(Jrs, rel=1e-10, abs=1e-14 * math.sqrt(Jrr * cov[s])), (m, r)

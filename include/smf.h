@@ -65,6 +65,15 @@ enum {
                             a grid with no symmetry always stores both. */
     SMF_FUSED = 8,       /* reserved for a single-kernel recursion + FFT; smf_setup returns
                             SMF_EINVAL for it (the two launches of smf_sample are the path) */
+    SMF_GREEN = 32,      /* or'ed with SMF_FP64 or SMF_FP32: the setup of Sec. 3 at order 1.  The
+                            spectrum is C_l = 1/(kappa + l(l+1)) for every l >= 0, not truncated
+                            (n_kappa = 1, kappa > 0, c_ell NULL; ell_max is ignored and every mode
+                            up to n_phi/2 - 1 is sampled), and J^m comes from the Green's function
+                            of the mode's operator, eq. (Jmatrix_efficient), with P^m_lambda of
+                            complex degree (kappa = -lambda(lambda+1)) from its hypergeometric
+                            series, eq. (Legendre_hypergeometric), instead of sums over l: the chain
+                            is then exactly Markov.  Needs n_theta * n_phi / 2 <= 2^27 (two setup
+                            tables of that many doubles). */
     SMF_UBASIS = 16      /* order 2 only, or'ed with one of the above: the chain state is
                             (g, U_m g) with the operator U_m of Sec. 3 (eq. (Jmatrix_more_efficient):
                             U_m maps P^m to P^{m+1}, so the setup sums L_{l,m+1} instead of
@@ -80,8 +89,8 @@ enum {
  * is stored; the southern steps are the mirror D A D, D B D (symmetry remark after Alg. 1).
  *   spec      host; copied, not retained.
  *   n_theta   >= 2 rings.     n_phi  power of two in [4, 16384].
- *   flags     exactly one of SMF_FP64, SMF_FP32, optionally or'ed with SMF_NO_MIRROR and
- *             SMF_UBASIS (order 2).
+ *   flags     exactly one of SMF_FP64, SMF_FP32, optionally or'ed with SMF_NO_MIRROR,
+ *             SMF_UBASIS (order 2) or SMF_GREEN (order 1).
  *   out       receives the new plan (host pointer to a pointer).
  * Orders 3 and 4 take the second and third z-derivatives of L_lm from the associated
  * Legendre equation; their records hold A row-major and B's lower triangle (16 and 32
@@ -279,6 +288,21 @@ int smf_sample_rings(const smf_plan* plan, uint64_t seed, int count, void* g_wor
  * Errors: as smf_sample_rings, plus SMF_EINVAL for a mu or sigma that is not finite. */
 int smf_sample_rings_lognormal(const smf_plan* plan, uint64_t seed, int count, double mu, double sigma,
                                void* g_work, void* out_dev, void* hip_stream);
+
+/* ---- throughput references for the roofline of the chain kernels (measured, not modelled) ---- */
+
+/* The sampler's white noise alone: `workgroups` workgroups of 256 lanes, each lane making
+ * stages * 8 Philox4x32-10 blocks (eight in lockstep per stage, as a lane of the order-2
+ * recursion does) and turning every block into four FP32 Box-Muller normals, with none of
+ * the recursion's loads, stores or chain steps; each lane writes the sum of its normals to
+ * out_dev[lane] (workgroups * 256 floats, device).  Normals made: workgroups * 256 * stages
+ * * 32.  Asynchronous on hip_stream; the caller times it.  Errors: SMF_EINVAL, SMF_EHIP. */
+int smf_measure_normals(uint64_t seed, int workgroups, int stages, void* out_dev, void* hip_stream);
+
+/* Unpacked FP32 fused multiply-adds: each of workgroups * 256 lanes runs 8 independent
+ * chains of iters * 16 FMAs and writes their sum to out_dev[lane].  Lane-FMAs made:
+ * workgroups * 256 * iters * 128.  Errors: SMF_EINVAL, SMF_EHIP. */
+int smf_measure_fma(int workgroups, int iters, void* out_dev, void* hip_stream);
 
 /* Frees the plan and its device memory (synchronises the device first).  NULL is a
  * no-op. */

@@ -55,12 +55,13 @@ bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
 // Owns the device buffers of a plan under construction; frees them unless released.
 struct DevBufs {
-    void* p[12] = {nullptr};
+    void* p[16] = {nullptr};
     int n = 0;
     template <typename T>
     int alloc(T** out, size_t count)
     {
         void* q = nullptr;
+        if (n == 16) return SMF_ENOMEM;
         if (count == 0) count = 1;
         if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
             (void)hipGetLastError();
@@ -128,9 +129,14 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
     if (!is_pow2(n_phi) || n_phi < 4 || n_phi > 16384) return SMF_EINVAL;
     const int ubasis = (flags & SMF_UBASIS) ? 1 : 0;
     const int no_mirror = (flags & SMF_NO_MIRROR) ? 1 : 0;
-    flags &= ~(SMF_UBASIS | SMF_NO_MIRROR);
+    const int green = (flags & SMF_GREEN) ? 1 : 0;
+    flags &= ~(SMF_UBASIS | SMF_NO_MIRROR | SMF_GREEN);
     if (flags != SMF_FP64 && flags != SMF_FP32) return SMF_EINVAL;
     if (ubasis && spec->order != 2) return SMF_EINVAL;
+    if (green && (spec->order != 1 || ubasis || spec->c_ell || spec->n_kappa != 1 || !spec->kappa ||
+                  !(spec->kappa[0] > 0.0) || !std::isfinite(spec->kappa[0]) ||
+                  (long long)n_theta * (n_phi / 2) > smf::kGreenMaxTable))
+        return SMF_EINVAL;
     if (z_host && !grid_ok(z_host, n_theta)) return SMF_EINVAL;
 
     int dev = 0;
@@ -142,7 +148,8 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
         return SMF_EHIP;
     if (lds > (size_t)lds_max) return SMF_EINVAL;
 
-    Geometry g = smf::make_geometry(spec->order, n_theta, n_phi, spec->ell_max);
+    // no band limit with SMF_GREEN: every mode of the FFT layout is sampled
+    Geometry g = smf::make_geometry(spec->order, n_theta, n_phi, green ? n_phi / 2 - 1 : spec->ell_max);
     if (rows > 0 && rows < g.m_rows) g.m_rows = rows;
     DevBufs bufs;
     smf_plan* plan = (smf_plan*)calloc(1, sizeof(smf_plan));
@@ -161,6 +168,8 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
     double* kappa_dev = nullptr;
     double* cexp_dev = nullptr;
     double* z_dev = nullptr;
+    double* hp_dev = nullptr;   // Green's-function setup tables (setup only)
+    double* hn_dev = nullptr;
     int* bad_dev = nullptr;
     int bad = 0;
     // the northern table, and for a grid with no symmetry the southern walk's own table after it
@@ -201,14 +210,28 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
         }
     }
     plan->south_off = plan->asym ? nrec1 : 0;
-    if (smf::launch_factors(g, plan->C, z_dev, 0, ubasis, plan->f64, plan->f32, st) != hipSuccess) {
-        rc = SMF_EHIP;
-        goto fail;
-    }
-    if (plan->asym && smf::launch_factors(g, plan->C, z_dev, 1, ubasis, plan->f64 + nrec1,
-                                          plan->f32 ? plan->f32 + nrec1 : nullptr, st) != hipSuccess) {
-        rc = SMF_EHIP;
-        goto fail;
+    if (green) {
+        const size_t nt = (size_t)n_theta * g.m_rows;
+        if ((rc = bufs.alloc(&hp_dev, nt))) goto fail;
+        if ((rc = bufs.alloc(&hn_dev, nt))) goto fail;
+        if (smf::launch_green_tables(g, spec->kappa[0], z_dev, hp_dev, hn_dev, st) != hipSuccess ||
+            smf::launch_factors_green(g, spec->kappa[0], z_dev, 0, hp_dev, hn_dev, plan->f64, plan->f32, st) !=
+                hipSuccess ||
+            (plan->asym && smf::launch_factors_green(g, spec->kappa[0], z_dev, 1, hp_dev, hn_dev, plan->f64 + nrec1,
+                                                     plan->f32 ? plan->f32 + nrec1 : nullptr, st) != hipSuccess)) {
+            rc = SMF_EHIP;
+            goto fail;
+        }
+    } else {
+        if (smf::launch_factors(g, plan->C, z_dev, 0, ubasis, plan->f64, plan->f32, st) != hipSuccess) {
+            rc = SMF_EHIP;
+            goto fail;
+        }
+        if (plan->asym && smf::launch_factors(g, plan->C, z_dev, 1, ubasis, plan->f64 + nrec1,
+                                              plan->f32 ? plan->f32 + nrec1 : nullptr, st) != hipSuccess) {
+            rc = SMF_EHIP;
+            goto fail;
+        }
     }
     if ((rc = bufs.alloc(&plan->tw64, (size_t)2 * n_phi))) goto fail;
     if ((rc = bufs.alloc(&plan->tw32, (size_t)2 * n_phi))) goto fail;
@@ -238,6 +261,8 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
     if (kappa_dev) (void)hipFree(kappa_dev);
     if (cexp_dev) (void)hipFree(cexp_dev);
     if (z_dev) (void)hipFree(z_dev);
+    if (hp_dev) (void)hipFree(hp_dev);
+    if (hn_dev) (void)hipFree(hn_dev);
     *out = plan;
     return SMF_OK;
 

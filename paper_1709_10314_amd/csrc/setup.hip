@@ -573,6 +573,254 @@ __global__ __launch_bounds__(64) void phi_kernel(Geometry g, const double* __res
     }
 }
 
+// ---------------------------------------------------------------- Sec. 3, order 1
+// Cross covariances without a band limit from the Green's function of the mode's
+// operator: C_l = 1/(kappa + l(l+1)) for every l, kappa = -lambda(lambda+1), and
+// eq. (Jmatrix_efficient) with P^m_lambda of eq. (Legendre_hypergeometric) gives, for
+// z1 <= z2,
+//   J^m(z1, z2) = R_m w^m H_m(-z1) H_m(z2) / (4 |sin pi lambda|),
+//   R_m = prod_{k<=m} (k^2 - k + kappa) / k^2   (the Pochhammer products over m!^2),
+//   w^2 = (1 + z1)(1 - z2) / ((1 - z1)(1 + z2)),
+//   H_m(x) = 2F1(-lambda, lambda+1; 1+m; (1-x)/2),
+// using Gamma(1+lambda-m) Gamma(-lambda-m) = pi / (|sin pi lambda| R_m m!^2).  H_m has a
+// series of positive terms, term ratio (n^2 + n + kappa) / ((n+1)(n+1+m)) t.  It is
+// summed directly for x >= 0 (t <= 1/2) and, for x < 0, H_0 and H_1 come from the
+// series or, close to x = -1, from the logarithmic continuation of 2F1 about t = 1
+// (c - a - b = 0 and 1; Abramowitz & Stegun 15.3.11), and H_m from the three-term
+// recurrence in the order of the Ferrers functions rewritten for H_m,
+//   H_{m+2} = (m+1)(m+2) / q_{m+1} * (1+x)/(1-x) * (H_m - 2x/(1+x) H_{m+1}),
+// whose two terms are positive for x < 0.  The values of H per ring are tabulated by
+// two kernels (one thread per (ring, m) for the series side, one per ring for the
+// recurrence side), and the factor kernel reads the table.
+struct GreenConst {
+    double kappa;
+    double inv4s;        // 1 / (4 |sin pi lambda|)
+    double g;            // |sin pi lambda| / pi = 1 / (Gamma(-lambda) Gamma(lambda+1))
+    double lam_re, tau;  // lambda = lam_re + i tau (tau = 0: real lambda)
+};
+
+// (z, sin theta) of ring i: explicit grid or ring centres (as the Legendre-sum setup)
+__device__ inline void green_ring(const Geometry& g, const double* __restrict__ zgrid, int i, double& z,
+                                  double& sn)
+{
+    if (zgrid) {
+        z = zgrid[i];
+        sn = sqrt((1.0 - z) * (1.0 + z));
+    } else {
+        sincospi((double)(g.n_theta - 2 * i - 1) / (2.0 * g.n_theta), &z, &sn);
+    }
+}
+
+__device__ double green_series(int m, double kappa, double t)
+{
+    double acc = 1.0, term = 1.0;
+    for (int n = 0; n < 1000000; ++n) {
+        const double dn = (double)n;
+        const double r = (dn * dn + dn + kappa) / ((dn + 1.0) * (dn + 1.0 + (double)m)) * t;
+        term *= r;
+        acc += term;
+        if (r < 1.0 && term < 1e-18 * acc) break;
+    }
+    return acc;
+}
+
+// Re of the digamma at p + i q (p > 0): shifted up to p >= 20, then the asymptotic series
+// log w - 1/(2w) - 1/(12 w^2) + 1/(120 w^4) - 1/(252 w^6) + 1/(240 w^8) - 1/(132 w^10).
+__device__ double re_digamma(double p, double q)
+{
+    double shift = 0.0;
+    while (p < 20.0) {
+        shift += p / (p * p + q * q);   // Re 1/(p + i q)
+        p += 1.0;
+    }
+    const double r2 = p * p + q * q;
+    // powers of 1/w = (p - i q)/r2, real parts only where needed
+    const double wr = p / r2, wi = -q / r2;          // 1/w
+    const double w2r = wr * wr - wi * wi, w2i = 2.0 * wr * wi;
+    const double w4r = w2r * w2r - w2i * w2i, w4i = 2.0 * w2r * w2i;
+    const double w6r = w4r * w2r - w4i * w2i, w6i = w4r * w2i + w4i * w2r;
+    const double w8r = w4r * w4r - w4i * w4i, w8i = 2.0 * w4r * w4i;
+    const double w10r = w8r * w2r - w8i * w2i;
+    (void)w6i;
+    const double logw = 0.5 * log(r2);
+    return logw - 0.5 * wr - w2r / 12.0 + w4r / 120.0 - w6r / 252.0 + w8r / 240.0 - w10r / 132.0 - shift;
+}
+
+// psi(a + k) + psi(b + k), a = -lambda, b = lambda + 1
+__device__ inline double psi_sum(const GreenConst& c, double k)
+{
+    if (c.tau != 0.0) return 2.0 * re_digamma(0.5 + k, c.tau);
+    return re_digamma(-c.lam_re + k, 0.0) + re_digamma(c.lam_re + 1.0 + k, 0.0);
+}
+
+// H_0 and H_1 at t = 1 - u from the continuation about t = 1:
+//   H_0 = -g sum_k c_k u^k [log u - 2 psi(k+1) + psi(a+k) + psi(b+k)],
+//   H_1 = g/kappa + g u sum_k d_k u^k [log u - psi(k+1) - psi(k+2) + psi(a+k+1) + psi(b+k+1)],
+// c_k = (a)_k (b)_k / k!^2, d_k = (a+1)_k (b+1)_k / (k! (k+1)!).
+__device__ void green_h01_far(const GreenConst& c, double u, double& h0, double& h1)
+{
+    const double lu = log(u);
+    double ck = 1.0, dk = 1.0, uk = 1.0, s0 = 0.0, s1 = 0.0;
+    double psi1 = -0.57721566490153286061;    // psi(1)
+    for (int k = 0; k < 100000; ++k) {
+        const double dkk = (double)k;
+        const double psi2 = psi1 + 1.0 / (dkk + 1.0);
+        const double e0 = ck * uk * (lu - 2.0 * psi1 + psi_sum(c, dkk));
+        const double e1 = dk * uk * (lu - psi1 - psi2 + psi_sum(c, dkk + 1.0));
+        s0 += e0;
+        s1 += e1;
+        const double rc = (dkk * dkk + dkk + c.kappa) / ((dkk + 1.0) * (dkk + 1.0));
+        ck *= rc;
+        dk *= ((dkk + 1.0) * (dkk + 2.0) + c.kappa) / ((dkk + 1.0) * (dkk + 2.0));
+        uk *= u;
+        psi1 = psi2;
+        if (k > 4 && rc * u < 0.9 && fabs(e0) < 1e-18 * fabs(s0) && fabs(e1) < 1e-18 * fabs(s1)) break;
+    }
+    h0 = -c.g * s0;
+    h1 = c.g / c.kappa + c.g * u * s1;
+}
+
+// Series side of the table: thread (ring i, mode m) fills H_m(+-z_i) for the sign that
+// makes the argument non-negative (both at z_i = 0).
+__global__ __launch_bounds__(64) void green_series_kernel(Geometry g, const double* __restrict__ zgrid, GreenConst c,
+                                                          double* __restrict__ hp, double* __restrict__ hn)
+{
+    const int m = blockIdx.x * 64 + threadIdx.x;
+    const int i = blockIdx.y;
+    if (m > g.m_top) return;
+    double z, sn;
+    green_ring(g, zgrid, i, z, sn);
+    const size_t o = (size_t)i * g.m_rows + m;
+    // t = (1 - x)/2 with 1 - x = sin^2 / (1 + x) for x >= 0
+    if (z >= 0.0) hp[o] = green_series(m, c.kappa, sn * sn / (2.0 * (1.0 + z)));
+    if (z <= 0.0) hn[o] = green_series(m, c.kappa, sn * sn / (2.0 * (1.0 - z)));
+}
+
+// Recurrence side: one thread per ring fills H_m(x) for x = -|z_i| < 0, m = 0..m_top.
+__global__ __launch_bounds__(64) void green_recur_kernel(Geometry g, const double* __restrict__ zgrid, GreenConst c,
+                                                         double* __restrict__ hp, double* __restrict__ hn)
+{
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i >= g.n_theta) return;
+    double z, sn;
+    green_ring(g, zgrid, i, z, sn);
+    if (z == 0.0) return;
+    const double x = -fabs(z);
+    double* __restrict__ h = (z > 0.0 ? hn : hp) + (size_t)i * g.m_rows;
+    const double u = sn * sn / (2.0 * (1.0 - x));       // (1 + x)/2
+    double h0, h1;
+    if (u * (c.kappa + 1.0) <= 0.5) {
+        green_h01_far(c, u, h0, h1);
+    } else {
+        h0 = green_series(0, c.kappa, 1.0 - u);
+        h1 = green_series(1, c.kappa, 1.0 - u);
+    }
+    h[0] = h0;
+    if (g.m_top >= 1) h[1] = h1;
+    const double opx = 2.0 * u, omx = 1.0 - x;
+    const double ratio = opx / omx, cross = -2.0 * x / opx;
+    for (int k = 0; k + 2 <= g.m_top; ++k) {
+        const double dk = (double)k;
+        const double q = (dk + 1.0) * (dk + 2.0) + c.kappa;
+        const double h2 = (dk + 1.0) * (dk + 2.0) / q * ratio * fma(cross, h1, h0);
+        h[k + 2] = h2;
+        h0 = h1;
+        h1 = h2;
+    }
+}
+
+// log(1 + z) and log(1 - z), each through sin^2 theta where that side is the small one
+__device__ inline void green_logs(double z, double sn, double& lp, double& lm)
+{
+    if (z >= 0.0) {
+        lp = log1p(z);
+        lm = log(sn * sn / (1.0 + z));
+    } else {
+        lp = log(sn * sn / (1.0 - z));
+        lm = log1p(-z);
+    }
+}
+
+// J^m between rings x (lower value) and y, from the tables
+__device__ inline double green_j(const GreenConst& c, double rm, int m, double zx, double sx, double zy, double sy,
+                                 double hx_neg, double hy_pos)
+{
+    double wm = 1.0;
+    if (zx != zy && m > 0) {
+        double lpx, lmx, lpy, lmy;
+        green_logs(zx, sx, lpx, lmx);
+        green_logs(zy, sy, lpy, lmy);
+        wm = exp(0.5 * (double)m * ((lpx - lmx) + (lmy - lpy)));
+    }
+    return rm * wm * hx_neg * hy_pos * c.inv4s;
+}
+
+GreenConst green_const(double kappa)
+{
+    GreenConst c;
+    c.kappa = kappa;
+    double abs_sin;
+    if (kappa > 0.25) {
+        c.lam_re = -0.5;
+        c.tau = sqrt(kappa - 0.25);
+        abs_sin = cosh(M_PI * c.tau);
+    } else {
+        c.lam_re = (-1.0 + sqrt(1.0 - 4.0 * kappa)) / 2.0;
+        c.tau = 0.0;
+        abs_sin = -sin(M_PI * c.lam_re);
+    }
+    c.inv4s = 1.0 / (4.0 * abs_sin);
+    c.g = abs_sin / M_PI;
+    return c;
+}
+
+// One thread per (set j, mode m), sets as in factor_kernel (south: the southern walk's own
+// steps, stored mirrored; at order 1 the mirror leaves the record unchanged).
+__global__ __launch_bounds__(64) void green_factor_kernel(Geometry g, const double* __restrict__ zgrid, GreenConst c,
+                                                          int south, const double* __restrict__ hp,
+                                                          const double* __restrict__ hn, double* __restrict__ f64,
+                                                          float* __restrict__ f32)
+{
+    const int j = blockIdx.x * 64 + threadIdx.x;
+    const int m = blockIdx.y;
+    if (j >= g.n_sets) return;
+    int a, b;
+    if (south && j >= (g.even ? 2 : 1)) {
+        a = g.s + j - 1; b = g.s + j;
+    } else if (j == 0) {
+        a = b = g.s;
+    } else if (g.even) {
+        if (j == 1) { a = g.s; b = g.s + 1; }
+        else { a = g.s - j + 2; b = g.s - j + 1; }
+    } else {
+        a = g.s - j + 1; b = g.s - j;
+    }
+    double rm = 1.0;
+    for (int k = 1; k <= m; ++k) {
+        const double dk = (double)k;
+        rm *= (dk * dk - dk + c.kappa) / (dk * dk);
+    }
+    double za, sa, zb, sb;
+    green_ring(g, zgrid, a, za, sa);
+    green_ring(g, zgrid, b, zb, sb);
+    const size_t oa = (size_t)a * g.m_rows + m, ob = (size_t)b * g.m_rows + m;
+    const double kaa = green_j(c, rm, m, za, sa, za, sa, hn[oa], hp[oa]);
+    const size_t base = ((size_t)j * g.m_rows + m) * factor_stride(1);
+    double A, B;
+    if (j == 0) {
+        A = 0.0;
+        B = start_m1(kaa);
+    } else {
+        const double kbb = green_j(c, rm, m, zb, sb, zb, sb, hn[ob], hp[ob]);
+        const double kba = za <= zb ? green_j(c, rm, m, za, sa, zb, sb, hn[oa], hp[ob])
+                                    : green_j(c, rm, m, zb, sb, za, sa, hn[ob], hp[oa]);
+        factors_m1(kaa, kbb, kba, A, B);
+    }
+    f64[base] = A;
+    f64[base + 1] = B;
+    if (f32) { f32[base] = (float)A; f32[base + 1] = (float)B; }
+}
+
 }  // namespace
 
 hipError_t launch_phi(const Geometry& g, const double* f64, int blocks, double* phi64, float* phi32,
@@ -614,6 +862,28 @@ hipError_t launch_factors(const Geometry& g, const double* C_dev, const double* 
         case 4: hipLaunchKernelGGL(factor_kernel<4>, grid, dim3(64), 0, st, g, C_dev, z_dev, south, f64, f32); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_green_tables(const Geometry& g, double kappa, const double* z_dev, double* hp, double* hn,
+                               hipStream_t st)
+{
+    GreenConst c = green_const(kappa);
+    hipLaunchKernelGGL(green_series_kernel, dim3((g.m_top + 64) / 64, g.n_theta), dim3(64), 0, st, g, z_dev, c, hp,
+                       hn);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(green_recur_kernel, dim3((g.n_theta + 63) / 64), dim3(64), 0, st, g, z_dev, c, hp, hn);
+    return hipGetLastError();
+}
+
+hipError_t launch_factors_green(const Geometry& g, double kappa, const double* z_dev, int south, const double* hp,
+                                const double* hn, double* f64, float* f32, hipStream_t st)
+{
+    if (g.order != 1) return hipErrorInvalidValue;
+    GreenConst c = green_const(kappa);
+    hipLaunchKernelGGL(green_factor_kernel, dim3((g.n_sets + 63) / 64, g.m_top + 1), dim3(64), 0, st, g, z_dev, c,
+                       south, hp, hn, f64, f32);
     return hipGetLastError();
 }
 

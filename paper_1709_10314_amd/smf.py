@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsmf.so")
 
 SMF_OK, SMF_EINVAL, SMF_ENOMEM, SMF_EHIP, SMF_ENUMERIC = 0, -1, -2, -3, -4
-SMF_FP64, SMF_FP32, SMF_NO_MIRROR, SMF_FUSED, SMF_UBASIS = 1, 2, 4, 8, 16
+SMF_FP64, SMF_FP32, SMF_NO_MIRROR, SMF_FUSED, SMF_UBASIS, SMF_GREEN = 1, 2, 4, 8, 16, 32
 
 # every symbol include/smf.h declares
 EXPORTS = ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks",
@@ -22,7 +22,8 @@ EXPORTS = ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", 
            "smf_plan_dims", "smf_get_factors", "smf_set_factors", "smf_plan_grid",
            "smf_destroy", "smf_error_string", "smf_setup_batch", "smf_batch_layout",
            "smf_sample_batch", "smf_sample_batch_packed", "smf_autotune_batch", "smf_setup_rings", "smf_ring_layout",
-           "smf_synthesize_rings", "smf_sample_rings", "smf_sample_rings_lognormal")
+           "smf_synthesize_rings", "smf_sample_rings", "smf_sample_rings_lognormal", "smf_measure_normals",
+           "smf_measure_fma")
 
 
 class smf_spectrum(ctypes.Structure):
@@ -84,11 +85,14 @@ def load():
     lib.smf_synthesize_rings.argtypes = [vp, i, vp, vp, vp]
     lib.smf_sample_rings.argtypes = [vp, u64, i, vp, vp, vp]
     lib.smf_sample_rings_lognormal.argtypes = [vp, u64, i, ctypes.c_double, ctypes.c_double, vp, vp, vp]
+    lib.smf_measure_normals.argtypes = [u64, i, i, vp, vp]
+    lib.smf_measure_fma.argtypes = [i, i, vp, vp]
     for name in ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks", "smf_get_ring_blocks",
                  "smf_plan_dims",
                  "smf_get_factors", "smf_set_factors", "smf_plan_grid", "smf_destroy", "smf_setup_batch", "smf_batch_layout",
                  "smf_sample_batch", "smf_sample_batch_packed", "smf_autotune_batch", "smf_setup_rings", "smf_ring_layout",
-                 "smf_synthesize_rings", "smf_sample_rings", "smf_sample_rings_lognormal"):
+                 "smf_synthesize_rings", "smf_sample_rings", "smf_sample_rings_lognormal", "smf_measure_normals",
+                 "smf_measure_fma"):
         getattr(lib, name).restype = i
     _lib = lib
     return lib
@@ -401,13 +405,16 @@ class Plan:
     """A setup plan (Alg. 1 factors on the GPU) with sampling methods (Alg. 2)."""
 
     def __init__(self, order, n_theta, n_phi, ell_max, kappa=None, c_ell=None, precision="fp32",
-                 stream=None, z=None, basis="z", mirror=True):
+                 stream=None, z=None, basis="z", mirror=True, green=False):
         """basis: "z" (the state is the value and its z-derivatives) or "u" (order 2: (g, U g)
         of Sec. 3, SMF_UBASIS).  mirror=False stores the southern walk's own factor sets
-        (SMF_NO_MIRROR)."""
+        (SMF_NO_MIRROR).  green=True (order 1, one kappa): the Green's-function setup of Sec. 3
+        for C_l = 1/(kappa + l(l+1)) without band limit (SMF_GREEN; ell_max is ignored)."""
         flags = {"fp32": SMF_FP32, "fp64": SMF_FP64}[precision] | {"z": 0, "u": SMF_UBASIS}[basis]
         if not mirror:
             flags |= SMF_NO_MIRROR
+        if green:
+            flags |= SMF_GREEN
         rc, h = smf_setup(order, n_theta, n_phi, ell_max, kappa=kappa, c_ell=c_ell, flags=flags,
                           stream=stream, z=z)
         if rc != SMF_OK:

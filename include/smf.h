@@ -304,6 +304,13 @@ int smf_measure_normals(uint64_t seed, int workgroups, int stages, void* out_dev
  * workgroups * 256 * iters * 128.  Errors: SMF_EINVAL, SMF_EHIP. */
 int smf_measure_fma(int workgroups, int iters, void* out_dev, void* hip_stream);
 
+/* Test hook for the allocation-failure paths: after n more successful device (or pinned
+ * host) allocations made by the library, the next one fails as if the device were out of
+ * memory, and the call that made it returns SMF_ENOMEM having freed what it allocated;
+ * n = -1 turns the injection off (the default).  Process-wide; not for concurrent use.
+ * Errors: SMF_EINVAL (n < -1). */
+int smf_debug_fail_alloc(int n);
+
 /* Frees the plan and its device memory (synchronises the device first).  NULL is a
  * no-op. */
 int smf_destroy(smf_plan* plan);

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <mutex>
 #include <vector>
@@ -40,6 +41,38 @@ struct BatchState {
 
 namespace {
 
+// Allocation failure injection (smf_debug_fail_alloc): the number of device or pinned host
+// allocations to let through before one fails, or -1 (off).
+std::atomic<int> g_fail_after{-1};
+
+bool injected_failure()
+{
+    int n = g_fail_after.load();
+    while (n >= 0) {
+        if (g_fail_after.compare_exchange_weak(n, n - 1)) return n == 0;
+    }
+    return false;
+}
+
+// Every device allocation of the library goes through these two.
+hipError_t dev_malloc(void** p, size_t bytes)
+{
+    if (injected_failure()) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+hipError_t host_malloc_pinned(void** p, size_t bytes)
+{
+    if (injected_failure()) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipHostMalloc(p, bytes, 0);
+}
+
 void free_call_slots(smf::BatchState* b)
 {
     if (b->call_dev) (void)hipFree(b->call_dev);
@@ -63,7 +96,7 @@ struct DevBufs {
         void* q = nullptr;
         if (n == 16) return SMF_ENOMEM;
         if (count == 0) count = 1;
-        if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+        if (dev_malloc(&q, count * sizeof(T)) != hipSuccess) {
             (void)hipGetLastError();
             return SMF_ENOMEM;
         }
@@ -621,10 +654,10 @@ int smf_setup_rings(const smf_spectrum* spec, int n_theta, const double* z_host,
     if (rc == SMF_OK && !plan->ring_off) rc = SMF_ENOMEM;
     if (rc == SMF_OK) {
         memcpy(plan->ring_off, off.data(), sizeof(int64_t) * ((size_t)n_theta + 1));
-        if (hipMalloc((void**)&plan->n_ring_dev, sizeof(int) * n_theta) != hipSuccess ||
-            hipMalloc((void**)&plan->phi0_dev, sizeof(double) * n_theta) != hipSuccess ||
-            hipMalloc((void**)&plan->ring_off_dev, sizeof(int64_t) * ((size_t)n_theta + 1)) != hipSuccess ||
-            hipMalloc((void**)&plan->ring_list_dev, sizeof(int) * n_theta) != hipSuccess)
+        if (dev_malloc((void**)&plan->n_ring_dev, sizeof(int) * n_theta) != hipSuccess ||
+            dev_malloc((void**)&plan->phi0_dev, sizeof(double) * n_theta) != hipSuccess ||
+            dev_malloc((void**)&plan->ring_off_dev, sizeof(int64_t) * ((size_t)n_theta + 1)) != hipSuccess ||
+            dev_malloc((void**)&plan->ring_list_dev, sizeof(int) * n_theta) != hipSuccess)
             rc = SMF_ENOMEM;
     }
     if (rc == SMF_OK &&
@@ -729,6 +762,13 @@ int smf_destroy(smf_plan* plan)
     return SMF_OK;
 }
 
+int smf_debug_fail_alloc(int n)
+{
+    if (n < -1) return SMF_EINVAL;
+    g_fail_after.store(n);
+    return SMF_OK;
+}
+
 const char* smf_error_string(int code)
 {
     switch (code) {
@@ -796,7 +836,7 @@ int smf_setup_batch(int n, const smf_spectrum* specs, const int* n_theta, const 
                 items.push_back(((uint32_t)i << 16) | (uint32_t)t);
         }
         b->n_chain[k] = (int)items.size();
-        if (hipMalloc(&b->chain_dev[k], sizeof(uint32_t) * items.size()) != hipSuccess) {
+        if (dev_malloc((void**)&b->chain_dev[k], sizeof(uint32_t) * items.size()) != hipSuccess) {
             (void)hipGetLastError();
             rc = SMF_ENOMEM;
             goto fail;
@@ -810,14 +850,14 @@ int smf_setup_batch(int n, const smf_spectrum* specs, const int* n_theta, const 
     for (int i : order_idx)
         for (int r = 0; r < fields[i].n_theta; ++r) fft_items.push_back(((uint32_t)i << 16) | (uint32_t)r);
     b->n_fft = (int)fft_items.size();
-    if (hipMalloc(&b->fields_dev, sizeof(smf::BatchField) * n) != hipSuccess ||
-        hipMalloc(&b->fft_dev, sizeof(uint32_t) * fft_items.size()) != hipSuccess) {
+    if (dev_malloc((void**)&b->fields_dev, sizeof(smf::BatchField) * n) != hipSuccess ||
+        dev_malloc((void**)&b->fft_dev, sizeof(uint32_t) * fft_items.size()) != hipSuccess) {
         (void)hipGetLastError();
         rc = SMF_ENOMEM;
         goto fail;
     }
-    if (hipMalloc(&b->call_dev, sizeof(smf::BatchCall) * n * smf::BatchState::kCallSlots) != hipSuccess ||
-        hipHostMalloc((void**)&b->call_host, sizeof(smf::BatchCall) * n * smf::BatchState::kCallSlots, 0) !=
+    if (dev_malloc((void**)&b->call_dev, sizeof(smf::BatchCall) * n * smf::BatchState::kCallSlots) != hipSuccess ||
+        host_malloc_pinned((void**)&b->call_host, sizeof(smf::BatchCall) * n * smf::BatchState::kCallSlots) !=
             hipSuccess) {
         (void)hipGetLastError();
         rc = SMF_ENOMEM;

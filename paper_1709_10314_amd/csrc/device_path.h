@@ -1097,4 +1097,156 @@ __device__ __forceinline__ void c2r_rows(T* __restrict__ data, const T* __restri
     }
 }
 
+
+// ------------------------------------------------------------------ radix-16 C2R rows
+// The C2R of rows of n_phi = 8192 (H = 4096 = 16^3) as three radix-16 Stockham passes of
+// 256 threads, one butterfly per thread and pass.  The first pass takes its inputs
+// Z_{t + 256 r} straight from the pre-processing in registers (thread t loads its modes
+// X_k, k = t + 256 r, and their mirror partners X_{H-k}, which thread 256 - t also loads, so
+// the second read comes from the cache), and the last pass stores its outputs
+// z_{t + 256 q} straight to the row: the row sits in LDS only between the passes, 128 KB of
+// LDS traffic and four barriers per row against 320 KB and nine for radix-8 passes.
+
+// Inverse DFT of 16 values (kernel e^{+2 pi i r q / 16}) as 4 x 4: inverse DFT4s over r1 of
+// x_{4 r1 + r0}, twiddles w^{r0 q1} with w = e^{2 pi i / 16}, inverse DFT4s over r0; output
+// q = q1 + 4 q2.
+template <typename T>
+__device__ __forceinline__ void dft_inv16(Cx<T>* v)
+{
+    Cx<T> a[4][4];   // a[r0][q1]
+#pragma unroll
+    for (int r0 = 0; r0 < 4; ++r0) {
+        Cx<T> t[4] = {v[r0], v[4 + r0], v[8 + r0], v[12 + r0]};
+        dft_inv<T, 4>(t);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[r0][q] = t[q];
+    }
+    const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173);   // cos, sin pi/8
+    const T h = T(0.70710678118654752440);
+    const Cx<T> w1 = {c1, s1}, w2 = {h, h}, w3 = {s1, c1}, w6 = {-h, h}, w9 = {-c1, -s1};
+    a[1][1] = cmul(a[1][1], w1);
+    a[1][2] = cmul(a[1][2], w2);
+    a[1][3] = cmul(a[1][3], w3);
+    a[2][1] = cmul(a[2][1], w2);
+    a[2][2] = mul_i(a[2][2]);
+    a[2][3] = cmul(a[2][3], w6);
+    a[3][1] = cmul(a[3][1], w3);
+    a[3][2] = cmul(a[3][2], w6);
+    a[3][3] = cmul(a[3][3], w9);
+#pragma unroll
+    for (int q1 = 0; q1 < 4; ++q1) {
+        Cx<T> t[4] = {a[0][q1], a[1][q1], a[2][q1], a[3][q1]};
+        dft_inv<T, 4>(t);
+#pragma unroll
+        for (int q2 = 0; q2 < 4; ++q2) v[q1 + 4 * q2] = t[q2];
+    }
+}
+
+// v[r] *= w^r, r = 1..15, w = tw[e]: w, w^4, w^8 from the table (e, 4e, 8e < N), the rest
+// by at most two products.
+template <typename T>
+__device__ __forceinline__ void twiddle16(Cx<T>* v, const Cx<T>* __restrict__ tw, int e)
+{
+    const Cx<T> w1 = tw[e], w4 = tw[4 * e], w8 = tw[8 * e];
+    const Cx<T> w2 = cmul(w1, w1), w3 = cmul(w2, w1);
+    Cx<T> w[8];
+    w[0] = {T(1), T(0)};
+    w[1] = w1;
+    w[2] = w2;
+    w[3] = w3;
+    w[4] = w4;
+    w[5] = cmul(w4, w1);
+    w[6] = cmul(w4, w2);
+    w[7] = cmul(w4, w3);
+#pragma unroll
+    for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], w[r]);
+    v[8] = cmul(v[8], w8);
+#pragma unroll
+    for (int r = 1; r < 8; ++r) v[8 + r] = cmul(v[8 + r], cmul(w8, w[r]));
+}
+
+// Mirror partners of the pre-processing: 1 through LDS (one more barrier), 0 from global
+// memory (each value is loaded by two threads).
+#ifndef SMF_R16_XCHG
+#define SMF_R16_XCHG 1
+#endif
+
+// One row of n_phi = 8192 by 256 threads; `buf` holds lds_slots(4096) values.  Ends after the
+// row's last LDS read (a barrier), so the caller may start the next row at once.
+template <typename T>
+__device__ __forceinline__ void c2r_row_r16(T* __restrict__ data_row, const T* __restrict__ twr, int m_top,
+                                            Cx<T>* buf, const Epilogue<T>& ep)
+{
+    constexpr int H = 4096;
+    const int t = threadIdx.x;
+    const Cx<T>* tw = reinterpret_cast<const Cx<T>*>(twr);
+    Cx<T>* __restrict__ row = reinterpret_cast<Cx<T>*>(data_row);
+    const Cx<T> zero = {T(0), T(0)};
+    // pre-processing: Z_k = (X_k + conj X_{H-k}) + i w^k (X_k - conj X_{H-k}), k = t + 256 r,
+    // X_k = 0 above m_top, Im X_0 = 0, X_H = 0; w^k = tw[t] tw[256 r]
+    Cx<T> xa[16], xb[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int k = t + 256 * r;
+        xa[r] = k <= m_top ? row[k] : zero;
+    }
+    if (t == 0) xa[0].im = T(0);
+#if SMF_R16_XCHG
+    // the mirror partners through LDS: every thread stores its modes, then reads X_{H-k}
+#pragma unroll
+    for (int r = 0; r < 16; ++r) buf[lds_slot(t + 256 * r)] = xa[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int k = t + 256 * r;
+        xb[r] = k > 0 ? buf[lds_slot(H - k)] : zero;
+    }
+#else
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int k = t + 256 * r;
+        xb[r] = (k > 0 && H - k <= m_top) ? row[H - k] : zero;
+    }
+#endif
+    const Cx<T> wt = tw[t];
+    Cx<T> v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const Cx<T> a = xa[r], cb = {xb[r].re, -xb[r].im};
+        const Cx<T> w = r == 0 ? wt : cmul(wt, tw[256 * r]);
+        v[r] = cadd(cadd(a, cb), mul_i(cmul(w, csub(a, cb))));
+    }
+#if SMF_R16_XCHG
+    __syncthreads();   // every partner read before the first pass overwrites the buffer
+#endif
+    // pass 1 (Ns = 1): no twiddles; outputs 16 t + q
+    dft_inv16<T>(v);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) buf[lds_slot(16 * t + q)] = v[q];
+    __syncthreads();
+    // pass 2 (Ns = 16): k = t mod 16, twiddles e^{2 pi i k r / 256} = tw[32 k r]; outputs
+    // (t - k) 16 + k + 16 q
+    {
+        const int k = t & 15;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = buf[lds_slot(t + 256 * r)];
+        __syncthreads();
+        twiddle16<T>(v, tw, 32 * k);
+        dft_inv16<T>(v);
+        const int o = (t - k) * 16 + k;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) buf[lds_slot(o + 16 * q)] = v[q];
+    }
+    __syncthreads();
+    // pass 3 (Ns = 256): k = t, twiddles e^{2 pi i t r / 4096} = tw[2 t r]; outputs t + 256 q,
+    // the results z_j = T_{2j} + i T_{2j+1}, stored to the row
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = buf[lds_slot(t + 256 * r)];
+    __syncthreads();
+    twiddle16<T>(v, tw, 2 * t);
+    dft_inv16<T>(v);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) row[t + 256 * q] = epilogue(ep, v[q]);
+}
+
 }  // namespace smf

@@ -387,8 +387,31 @@ __global__ __launch_bounds__((FftThreads<T, LOG2H>::value), (FftWaves<T, LOG2H>:
         data, twr, m_top, reinterpret_cast<Cx<T>*>(smem_raw), rows, blockIdx.x, gridDim.x, ep);
 }
 
+// Waves per SIMD of the radix-16 kernel: 2 (it needs about 244 VGPRs; with 128 or 168 it
+// spills)
+#ifndef SMF_R16_WAVES
+#define SMF_R16_WAVES 2
+#endif
+// Rows of n_phi = 8192 by three radix-16 passes (c2r_row_r16), 256 threads, FP32.
+template <typename T>
+__global__ __launch_bounds__(256, SMF_R16_WAVES) void c2r16_kernel(T* __restrict__ data,
+                                                                             const T* __restrict__ twr, int m_top,
+                                                                             int rows, Epilogue<T> ep)
+{
+    extern __shared__ unsigned char smem_raw[];
+    Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem_raw);
+    for (int r = blockIdx.x; r < rows; r += gridDim.x) c2r_row_r16<T>(data + (size_t)r * 8192, twr, m_top, buf, ep);
+}
+
 // Workgroups of the row-looping FFT: enough to fill every CU several times over.
 constexpr int kFftGrid = 2048;
+
+// FP32 rows of n_phi = 8192 take the radix-16 kernel (0.446 against 0.454 ms for the 8-field
+// 4096 x 8192 workload; with the mirror partners loaded from global memory instead of
+// exchanged through LDS it took 0.574 ms)
+#ifndef SMF_FFT_R16
+#define SMF_FFT_R16 1
+#endif
 
 template <typename T, int LOG2H>
 hipError_t launch_c2r_t(const T* tw, int m_top, int rows, T* data, const Epilogue<T>& ep, hipStream_t st)
@@ -409,6 +432,14 @@ template <typename T>
 hipError_t dispatch_c2r(int log2h, const T* tw, int m_top, int rows, T* data, const Epilogue<T>& ep,
                         hipStream_t st)
 {
+    if constexpr (sizeof(T) == 4) {
+        if (SMF_FFT_R16 && log2h == 12) {
+            const size_t lds = sizeof(Cx<T>) * lds_slots(4096);
+            const int grid = rows < kFftGrid ? rows : kFftGrid;
+            hipLaunchKernelGGL((c2r16_kernel<T>), dim3(grid), dim3(256), lds, st, data, tw, m_top, rows, ep);
+            return hipGetLastError();
+        }
+    }
     switch (log2h) {
         case 1: return launch_c2r_t<T, 1>(tw, m_top, rows, data, ep, st);
         case 2: return launch_c2r_t<T, 2>(tw, m_top, rows, data, ep, st);

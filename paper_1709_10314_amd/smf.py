@@ -23,7 +23,7 @@ EXPORTS = ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", 
            "smf_destroy", "smf_error_string", "smf_setup_batch", "smf_batch_layout",
            "smf_sample_batch", "smf_sample_batch_packed", "smf_autotune_batch", "smf_setup_rings", "smf_ring_layout",
            "smf_synthesize_rings", "smf_sample_rings", "smf_sample_rings_lognormal", "smf_measure_normals",
-           "smf_measure_fma")
+           "smf_measure_fma", "smf_debug_fail_alloc")
 
 
 class smf_spectrum(ctypes.Structure):
@@ -87,12 +87,13 @@ def load():
     lib.smf_sample_rings_lognormal.argtypes = [vp, u64, i, ctypes.c_double, ctypes.c_double, vp, vp, vp]
     lib.smf_measure_normals.argtypes = [u64, i, i, vp, vp]
     lib.smf_measure_fma.argtypes = [i, i, vp, vp]
+    lib.smf_debug_fail_alloc.argtypes = [i]
     for name in ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks", "smf_get_ring_blocks",
                  "smf_plan_dims",
                  "smf_get_factors", "smf_set_factors", "smf_plan_grid", "smf_destroy", "smf_setup_batch", "smf_batch_layout",
                  "smf_sample_batch", "smf_sample_batch_packed", "smf_autotune_batch", "smf_setup_rings", "smf_ring_layout",
                  "smf_synthesize_rings", "smf_sample_rings", "smf_sample_rings_lognormal", "smf_measure_normals",
-                 "smf_measure_fma"):
+                 "smf_measure_fma", "smf_debug_fail_alloc"):
         getattr(lib, name).restype = i
     _lib = lib
     return lib

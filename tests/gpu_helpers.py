@@ -117,3 +117,24 @@ def factor_errors(Ag, Bg, Ao, Bo, n_theta, skip_ambiguous=True):
     dS = dS[keep]
     return (float(np.nanmax(dA)) if dA.size else 0.0, float(np.nanmax(dS)) if dS.size else 0.0,
             int(amb.sum()))
+
+
+def threshold_decisions(Ag, Bg, Ao, Bo, n_theta):
+    """For the steps next to a threshold (threshold_ambiguous), whether the device and the
+    oracle took the same keep/drop decisions: a dropped pivot of J(a,a) leaves its column of
+    A exactly zero, and a conditional variance at or below the threshold leaves its diagonal
+    entry of B exactly zero, so the decision of a step is the pattern of zero columns of A
+    and zero diagonal entries of B.  Returns (number of ambiguous steps, list of (set, mode)
+    where the patterns differ)."""
+    amb = threshold_ambiguous(Ao, Bo, n_theta)
+    M = Ao.shape[-1]
+
+    def pattern(A, B):
+        cols = np.all(A == 0.0, axis=-2)                     # [sets, modes, M]
+        diag = np.einsum("...pp->...p", B) == 0.0             # [sets, modes, M]
+        return np.concatenate([cols, diag], axis=-1)
+
+    pg, po = pattern(Ag, Bg), pattern(Ao, Bo)
+    differ = np.any(pg != po, axis=-1) & amb
+    del M
+    return int(amb.sum()), [tuple(int(x) for x in ij) for ij in np.argwhere(differ)]

@@ -4,8 +4,11 @@ factors (FP64 setup) compared by their action on the chain's law (gpu_helpers.fa
 the conditional-mean map on a unit-variance input within 1e-8 and the conditional
 covariance within 1e-9, in units of the marginal standard deviations, except at the few
 steps whose pivot or relative conditional variance lies within two decades of the 1e-12
-threshold, where keeping or dropping the pivot is decided by rounding (their number is
-bounded).  Both sides sum J
+threshold, where keeping or dropping the pivot is decided by rounding: their number is held
+to the measured count plus 10% and 2, the steps where the device and the oracle decided
+differently are listed (gpu_helpers.threshold_decisions), and every mode holding one must
+still meet the field bar over all rings (FP64 1e-10 on the small grids; at full size every
+sampled mode, FP32 1e-4).  Both sides sum J
 with different FP64 roundings; the order-2 transition solves with J(a,a), whose smaller
 pivot 1 - rho^2 falls toward the 1e-12 threshold at evanescent modes, so its error grows
 as eps / sqrt(1 - rho^2)."""
@@ -13,12 +16,21 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_helpers import factor_errors, log, rel_rms
+from gpu_helpers import factor_errors, log, max_rel_err, rel_rms, threshold_decisions
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-10, "fp32": 1e-4}
+
+# Steps next to a threshold (gpu_helpers.threshold_ambiguous) measured on each workload; the
+# tests allow the measured count plus 10% and 2 (the count is a property of the oracle's
+# factors, so it moves only if the setup's arithmetic does)
+AMBIGUOUS = {(2, 100.0, 24, 128, 63): 3, (2, 700.0, 130, 256, 200): 143, 4096: 376, 8192: 463}
+
+
+def _amb_bound(key):
+    return int(1.1 * AMBIGUOUS.get(key, 0)) + 2
 
 
 def _plan(order, n_theta, n_phi, ell_max, kappa, precision):
@@ -63,9 +75,31 @@ def test_factors_match_oracle(case):
     Ao, Bo = oracle.setup(order, C, n, nphi)
     assert Ag.shape == Ao.shape
     dA, dB, amb = factor_errors(Ag, Bg, Ao, Bo, n)
-    log(f"  max dA {dA:.3e}  max dB {dB:.3e}  ({amb} of {Ao.shape[0] * Ao.shape[1]} steps next to a threshold)")
+    n_amb, differ = threshold_decisions(Ag, Bg, Ao, Bo, n)
+    log(f"  max dA {dA:.3e}  max dB {dB:.3e}  ({amb} of {Ao.shape[0] * Ao.shape[1]} steps next to a threshold, "
+        f"{len(differ)} decided differently)")
     assert dA < 1e-8 and dB < 1e-9
-    assert amb <= max(2, 0.02 * Ao.shape[0] * Ao.shape[1])
+    assert amb == n_amb and amb <= _amb_bound(case)
+    _check_differing_modes(order, kap, n, nphi, lmax, differ)
+
+
+def _check_differing_modes(order, kap, n, nphi, lmax, differ, count=2, seed=23):
+    """Where the device and the oracle decided a threshold step differently, the affected
+    modes' chains over every ring (the device's own factors on the device, the oracle's on
+    the oracle, same normals) must still meet the FP64 field bar."""
+    modes = sorted({m for _, m in differ})
+    if not modes:
+        return
+    plan = _plan(order, n, nphi, lmax, kap, "fp64")
+    g = _gpu_modes(plan, seed, count)
+    plan.close()
+    C = oracle.spectrum([kap] * order, lmax)
+    Am, Bm = oracle.setup_modes(order, C, n, modes)
+    go = oracle.sample_modes_list(order, n, modes, Am, Bm, seed, count)
+    for k, m in enumerate(modes):
+        e = rel_rms(np.stack([g[:, :, m].real, g[:, :, m].imag]), np.stack([go[:, :, k].real, go[:, :, k].imag]))
+        log(f"  mode {m} (a step decided differently): chains vs oracle {e:.3e}")
+        assert e <= TOL["fp64"], (m, e)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -89,8 +123,9 @@ def test_modes_and_field_match_oracle(case, precision):
         eg = rel_rms(np.stack([g[f, :, : mt + 1].real, g[f, :, : mt + 1].imag]),
                      np.stack([go[f].real, go[f].imag]))
         eT = rel_rms(T[f], To[f])
-        log(f"  field {f}: modes {eg:.3e}  field {eT:.3e}")
-        assert eg <= TOL[precision] and eT <= TOL[precision]
+        mT = max_rel_err(T[f], To[f])
+        log(f"  field {f}: modes {eg:.3e}  field {eT:.3e} (max {mT:.3e})")
+        assert eg <= TOL[precision] and eT <= TOL[precision] and mT <= 10 * TOL[precision]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -126,9 +161,10 @@ def test_plain_1024x2048_x16_full_size():
     C = oracle.spectrum([kap], lmax)
     Ao, Bo = oracle.setup(1, C, n, nphi)
     dA, dB, amb = factor_errors(Ag, Bg, Ao, Bo, n)
-    log(f"  factors dA {dA:.3e} dB {dB:.3e} ({amb} steps next to a threshold)")
+    n_amb, differ = threshold_decisions(Ag, Bg, Ao, Bo, n)
+    log(f"  factors dA {dA:.3e} dB {dB:.3e} ({amb} steps next to a threshold, {len(differ)} decided differently)")
     assert dA < 1e-8 and dB < 1e-9
-    assert amb <= 0.02 * Ao.shape[0] * Ao.shape[1]
+    assert amb <= _amb_bound(1024) and not differ
     log("  oracle chains")
     go = oracle.sample_modes(1, n, Ao, Bo, 1, count)
     rings = [0, 1, 100, 400, 510, 511, 512, 513, 700, 1000, 1022, 1023]
@@ -168,22 +204,27 @@ def _full_size_precision_form(n, nphi, lmax, kap, count):
     ge = oracle.sample_modes(order, n, Ae, Be, 1, count, sets=sets)
     To = oracle.dft(ge[:, rings, :], nphi)
     for f in range(count):
-        eT = rel_rms(Tr[f], To[f])
-        log(f"  field {f}: near-equator field {eT:.3e}")
-        assert eT <= 1e-4
+        eT, mT = rel_rms(Tr[f], To[f]), max_rel_err(Tr[f], To[f])
+        log(f"  field {f}: near-equator field {eT:.3e} (max {mT:.3e})")
+        assert eT <= 1e-4 and mT <= 1e-3
     modes = [0, 1, 2, 3, 97, lmax // 2, lmax // 2 + 1, lmax - 2, lmax - 1, lmax]
     log(f"  oracle: all rings of modes {modes}")
     Am, Bm = oracle.setup_modes(order, C, n, modes)
     dA, dB, amb = factor_errors(Ag[:, modes], Bg[:, modes], Am, Bm, n)
-    log(f"  factors dA {dA:.3e} dB {dB:.3e} ({amb} steps next to a threshold)")
+    n_amb, differ = threshold_decisions(Ag[:, modes], Bg[:, modes], Am, Bm, n)
+    log(f"  factors dA {dA:.3e} dB {dB:.3e} ({amb} steps next to a threshold, {len(differ)} decided differently)")
     assert dA < 1e-8 and dB < 1e-9
-    assert amb <= 0.02 * Am.shape[0] * Am.shape[1]
+    assert amb <= _amb_bound(n)
     gm = oracle.sample_modes_list(order, n, modes, Am, Bm, 1, count)
     for f in range(count):
         eg = rel_rms(np.stack([g[f][:, modes].real, g[f][:, modes].imag]),
                      np.stack([gm[f].real, gm[f].imag]))
         log(f"  field {f}: sampled modes {eg:.3e}")
         assert eg <= 1e-4
+    # every sampled mode, including those with a step decided differently, over every ring
+    for k, m in enumerate(modes):
+        e = rel_rms(np.stack([g[:, :, m].real, g[:, :, m].imag]), np.stack([gm[:, :, k].real, gm[:, :, k].imag]))
+        assert e <= 1e-4, (m, e)
 
 
 def test_precision_4096x8192_x8_full_size():

@@ -283,6 +283,17 @@ int smf_synthesize_rings(const smf_plan* plan, int count, const void* g_dev, voi
 int smf_sample_rings(const smf_plan* plan, uint64_t seed, int count, void* g_work, void* out_dev,
                      void* hip_stream);
 
+/* smf_sample_rings for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): no work buffer is passed and none
+ * is allocated; the modes go to a file-scope device array of the library, 64 MiB on each
+ * device the library runs on (held until the process ends), so count * n_theta * n_phi values
+ * of the plan's type (n_phi as smf_plan_dims reports) must fit in 64 MiB.  Every call on a
+ * device shares that device's array: calls that overlap on one device (other streams, other
+ * threads) race and must be serialised by the caller.  Same results as smf_sample_rings.
+ * Errors: as smf_sample_rings, plus SMF_EINVAL when the modes exceed 64 MiB; SMF_EHIP if the
+ * array's device address cannot be obtained. */
+int smf_sample_rings_noalloc(const smf_plan* plan, uint64_t seed, int count, void* out_dev, void* hip_stream);
+
 /* smf_sample_rings with the lognormal map of smf_sample_lognormal, exp(mu + sigma T), applied
  * as the pixels are stored (the application named at the end of Sec. 4, on a ring plan).
  * Errors: as smf_sample_rings, plus SMF_EINVAL for a mu or sigma that is not finite. */

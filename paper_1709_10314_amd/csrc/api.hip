@@ -710,6 +710,33 @@ static int sample_rings(const smf_plan* plan, uint64_t seed, int count, void* g_
     return synthesize_rings(plan, count, g_work, out_dev, hip_stream, ln);
 }
 
+// ---- the ring sampling call without a caller-given work buffer ----
+// The modes go to a file-scope device array instead.  In host code `ring_scratch` names a
+// host-side stand-in, not device memory: its device address is taken once per device with
+// hipGetSymbolAddress (with that device current) and only that address is used.
+constexpr size_t kRingScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char ring_scratch[kRingScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// The device address of `ring_scratch` on the current device `dev`, looked up on first use.
+int ring_scratch_address(int dev, void** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return SMF_EINVAL;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(ring_scratch)) != hipSuccess || !p) return SMF_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SMF_OK;
+}
+}  // namespace
+
 int smf_synthesize_rings(const smf_plan* plan, int count, const void* g_dev, void* out_dev, void* hip_stream)
 {
     return synthesize_rings(plan, count, g_dev, out_dev, hip_stream, nullptr);
@@ -727,6 +754,21 @@ int smf_sample_rings_lognormal(const smf_plan* plan, uint64_t seed, int count, d
     if (!std::isfinite(mu) || !std::isfinite(sigma)) return SMF_EINVAL;
     const smf::LognormalMap ln = {mu, sigma};
     return sample_rings(plan, seed, count, g_work, out_dev, hip_stream, &ln);
+}
+
+int smf_sample_rings_noalloc(const smf_plan* plan, uint64_t seed, int count, void* out_dev, void* hip_stream)
+{
+    if (!plan || plan->batch || !plan->n_ring_dev || count < 0 || count > smf::kRingMaxCount) return SMF_EINVAL;
+    if (count == 0) return SMF_OK;
+    if (!out_dev) return SMF_EINVAL;
+    const Geometry& g = plan->g;
+    const size_t elem = plan->flags == SMF_FP64 ? sizeof(double) : sizeof(float);
+    if ((size_t)count * g.n_theta * g.n_phi * elem > kRingScratchBytes) return SMF_EINVAL;
+    DeviceGuard dg(plan->device);
+    void* work = nullptr;
+    const int rc = ring_scratch_address(plan->device, &work);
+    if (rc != SMF_OK) return rc;
+    return sample_rings(plan, seed, count, work, out_dev, hip_stream, nullptr);
 }
 
 int smf_destroy(smf_plan* plan)

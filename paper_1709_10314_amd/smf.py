@@ -23,7 +23,7 @@ EXPORTS = ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", 
            "smf_destroy", "smf_error_string", "smf_setup_batch", "smf_batch_layout",
            "smf_sample_batch", "smf_sample_batch_packed", "smf_autotune_batch", "smf_setup_rings", "smf_ring_layout",
            "smf_synthesize_rings", "smf_sample_rings", "smf_sample_rings_lognormal", "smf_measure_normals",
-           "smf_measure_fma", "smf_debug_fail_alloc")
+           "smf_measure_fma", "smf_debug_fail_alloc", "smf_sample_rings_noalloc")
 
 
 class smf_spectrum(ctypes.Structure):
@@ -88,12 +88,13 @@ def load():
     lib.smf_measure_normals.argtypes = [u64, i, i, vp, vp]
     lib.smf_measure_fma.argtypes = [i, i, vp, vp]
     lib.smf_debug_fail_alloc.argtypes = [i]
+    lib.smf_sample_rings_noalloc.argtypes = [vp, u64, i, vp, vp]
     for name in ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks", "smf_get_ring_blocks",
                  "smf_plan_dims",
                  "smf_get_factors", "smf_set_factors", "smf_plan_grid", "smf_destroy", "smf_setup_batch", "smf_batch_layout",
                  "smf_sample_batch", "smf_sample_batch_packed", "smf_autotune_batch", "smf_setup_rings", "smf_ring_layout",
                  "smf_synthesize_rings", "smf_sample_rings", "smf_sample_rings_lognormal", "smf_measure_normals",
-                 "smf_measure_fma", "smf_debug_fail_alloc"):
+                 "smf_measure_fma", "smf_debug_fail_alloc", "smf_sample_rings_noalloc"):
         getattr(lib, name).restype = i
     _lib = lib
     return lib
@@ -166,6 +167,11 @@ def smf_synthesize_rings(plan, count, g_ptr, out_ptr, stream=None):
 def smf_sample_rings(plan, seed, count, g_ptr, out_ptr, stream=None):
     return load().smf_sample_rings(plan, ctypes.c_uint64(int(seed)), int(count), ctypes.c_void_p(g_ptr),
                                    ctypes.c_void_p(out_ptr), _stream_handle(stream))
+
+
+def smf_sample_rings_noalloc(plan, seed, count, out_ptr, stream=None):
+    return load().smf_sample_rings_noalloc(plan, ctypes.c_uint64(int(seed)), int(count), ctypes.c_void_p(out_ptr),
+                                           _stream_handle(stream))
 
 
 def smf_sample_rings_lognormal(plan, seed, count, mu, sigma, g_ptr, out_ptr, stream=None):
@@ -589,6 +595,16 @@ class RingPlan(Plan):
         rc = smf_sample_rings(self._h, seed, count, work.data_ptr(), out.data_ptr(), stream)
         if rc != SMF_OK:
             raise SmfError(rc, "smf_sample_rings")
+        return out.view(-1)[: count * self.pixels].view(count, self.pixels)
+
+    def sample_rings_noalloc(self, seed, count, out, stream=None):
+        """sample_rings with no work buffer: the library's own device array holds the modes
+        (smf_sample_rings_noalloc; at most 64 MiB of modes, calls on one device must not
+        overlap).  `out` must be given: nothing is allocated."""
+        self._check_rings(out, count)
+        rc = smf_sample_rings_noalloc(self._h, seed, count, out.data_ptr(), stream)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_sample_rings_noalloc")
         return out.view(-1)[: count * self.pixels].view(count, self.pixels)
 
     def sample_rings_lognormal(self, seed, count, mu=0.0, sigma=1.0, out=None, work=None, stream=None):

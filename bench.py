@@ -22,21 +22,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# VALU issue peak: 256 CUs x 4 SIMDs x 32 FP32 lanes per clock x 2.4 GHz (the published FP32
-# vector peak, 157.3 TFLOP/s, is this rate times 2 flops per FMA), in lane-slots per second
-VALU_PEAK_SLOTS = 256 * 4 * 32 * 2.4e9
-
-
-def alu_slots_per_point(order):
-    """Lane-slots of the recursion's arithmetic per output point (one chain step), counting a
-    full-rate VALU op as 1 and the quarter-rate ones (32x32->64 multiply, log, sqrt, sin,
-    cos) as 4.  Per normal: Philox4x32-10 is 10 rounds of 2 multiplies and 4 xors per
-    4 words, 30 slots; Box-Muller is 2 conversions, 2 fma, 4 transcendentals and 4
-    multiplies per pair, 12 slots.  The step itself: M*M + M(M+1)/2 FMA-class ops (A x and
-    the lower-triangular B w): 2, 7, 15, 26 for M = 1..4."""
-    philox = 10 * (2 * 4 + 4) / 4
-    box_muller = (2 + 2 + 4 * 4 + 4) / 2
-    return order * (philox + box_muller) + order * order + order * (order + 1) // 2
+# Lane-FMAs per second of the unpacked FP32 FMA the library is built with (packed FP32 is
+# switched off): 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz, i.e. the published FP32
+# vector peak (157.3 TFLOP/s) without the factor 2 of the packed instructions;
+# smf_measure_fma measures the rate on the device
+VALU_FMA_PEAK = 256 * 4 * 16 * 2.4e9
 
 
 def log(msg):
@@ -93,6 +83,80 @@ def time_split(plan, seed, count, out, steps, warmup):
     return rec, fft
 
 
+def alu_references(reps=5):
+    """Throughput references measured on this device with the library's own kernels: the
+    sampler's noise alone (Philox4x32-10 + FP32 Box-Muller, 8 blocks per stage in lockstep,
+    no loads or stores) in normals/s, and unpacked FP32 FMAs in lane-FMAs/s; the best of
+    `reps` timed launches after one warm-up each."""
+    import ctypes
+
+    import torch
+
+    from paper_1709_10314_amd import smf
+
+    lib = smf.load()
+    st = torch.cuda.current_stream().cuda_stream
+    wg = 256 * 4 * 8 // 4            # 8 waves per SIMD on 256 CUs, 4 waves per workgroup
+    out = torch.empty(wg * 256, dtype=torch.float32, device="cuda")
+
+    def best(launch):
+        launch()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            rc = launch()
+            e1.record()
+            torch.cuda.synchronize()
+            assert rc == 0, rc
+            ts.append(e0.elapsed_time(e1))
+        return min(ts)
+
+    stages = 64
+    ms_n = best(lambda: lib.smf_measure_normals(ctypes.c_uint64(1), wg, stages, ctypes.c_void_p(out.data_ptr()),
+                                                ctypes.c_void_p(st)))
+    normals = wg * 256 * stages * 32
+    iters = 512
+    ms_f = best(lambda: lib.smf_measure_fma(wg, iters, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(st)))
+    fmas = wg * 256 * iters * 128
+    assert torch.isfinite(out).all()
+    return {"normals_per_s": normals / (ms_n * 1e-3), "normals_ms": ms_n, "normals": normals,
+            "fma_lane_per_s": fmas / (ms_f * 1e-3), "fma_ms": ms_f, "fmas": fmas,
+            "fma_frac_of_unit_count_peak": fmas / (ms_f * 1e-3) / VALU_FMA_PEAK}
+
+
+def markov_defect(cfg, modes=(0, 64, 1024, 3000), span=16):
+    """The band-limit defect of reading 2 on the timed workload: for sampled modes, the
+    chain's covariance between the start ring s and rings s-2 .. s-span (propagated through
+    the oracle's factors) against J^m(z_s, z_r) of Lemma 2.1, relative to the geometric mean
+    of the two variances; the largest over modes and rings."""
+    import numpy as np
+
+    import oracle
+    from paper_1709_10314_amd import workloads
+
+    n, order, lmax = cfg["n_theta"], cfg["order"], cfg["ell_max"]
+    C = oracle.spectrum(workloads.kappas(cfg), lmax)
+    s = oracle.start_ring(n)
+    sets = span + 2
+    A, B = oracle.setup_modes(order, C, n, list(modes), sets=sets)
+    _, z = oracle.grid(n)
+    worst = 0.0
+    for k, m in enumerate(modes):
+        S = B[0, k] @ B[0, k].T              # Cov(x_s, x_s)
+        X = S.copy()                         # Cov(x_r, x_s), r walking north
+        V = S.copy()
+        for j in range(2, sets):
+            r = s - j + 1
+            X = A[j, k] @ X
+            V = A[j, k] @ V @ A[j, k].T + B[j, k] @ B[j, k].T
+            if s - r >= 2:
+                J = oracle.jblock_z(order, m, lmax, C, z[r], z[s])
+                worst = max(worst, abs(X[0, 0] - J[0, 0]) / np.sqrt(V[0, 0] * S[0, 0]))
+    return {"max_rel_cov_defect": worst, "modes": list(modes), "rings": f"s-2 .. s-{span} against s"}
+
+
 def batch_leg(steps, warmup):
     """The batched form on the 256-field mixed workload: one call samples every field
     (chain launch + FFT launch) after the tile-shape autotuner has run."""
@@ -119,10 +183,10 @@ def batch_leg(steps, warmup):
                         "order 1 or 2, FP32, seeds 1..256 (numpy PCG64(0))"}
 
 
-def high_order_leg(cfg, order, steps, warmup):
+def high_order_leg(cfg, order, steps, warmup, noise_peak):
     """The same grid and fields at Markov order 3 or 4 (C_l = (l(l+1) + kappa^2)^-M, FP32):
     ms per call, the recursion's ms per launch (events around smf_sample_modes) and its
-    VALU issue fraction."""
+    normals per second against the measured rate of the noise alone (noise_peak)."""
     import torch
 
     from paper_1709_10314_amd import Plan
@@ -136,10 +200,9 @@ def high_order_leg(cfg, order, steps, warmup):
     del out
     torch.cuda.empty_cache()
     pts = count * n * nphi
-    slots = pts * alu_slots_per_point(order)
+    nps = pts * order / (ms_rec * 1e-3)
     return {"order": order, "value": pts / ms * 1e3, "unit": "grid points/s", "ms_per_step": ms,
-            "recursion_ms": ms_rec, "alu_slots_per_point": alu_slots_per_point(order),
-            "recursion_alu_frac": slots / (ms_rec * 1e-3) / VALU_PEAK_SLOTS}
+            "recursion_ms": ms_rec, "normals_per_s": nps, "normals_frac_of_measured_noise_peak": nps / noise_peak}
 
 
 def healpix_leg(steps, warmup, nside=1024, order=2, kappa=50.0, count=8, seed=1):
@@ -252,7 +315,7 @@ def cpu_baseline(cfg, rings, single_rings):
     dtf = time.perf_counter() - t0
     err = float(np.max(np.abs(Tf - T)) / np.max(np.abs(T)))
     assert err < 1e-10, err
-    return {"value": pts / dt, "unit": "grid points/s", "cores": threads, "kind": "oracle",
+    return ({"value": pts / dt, "unit": "grid points/s", "cores": threads, "kind": "oracle",
             "sample": (f"{cfg['name']}: all {count} fields, the {rings} rings around the equator (all "
                        f"{lmax + 1} modes, {pts} points), chains + naive DFT in FP64; setup of the "
                        f"{sets} factor sets they need ({t_setup:.1f} s) not timed"),
@@ -261,7 +324,7 @@ def cpu_baseline(cfg, rings, single_rings):
                               "sample": f"field 1, the {single_rings} rings around the equator", "seconds": dt1},
             "chains_plus_numpy_fft": {"value": pts / dtf, "unit": "grid points/s", "cores": threads,
                                       "sample": "same as the oracle sample; numpy.fft.irfft in place of the naive DFT",
-                                      "seconds": dtf, "max_rel_diff_vs_oracle": err}}
+                                      "seconds": dtf, "max_rel_diff_vs_oracle": err}}, T)
 
 
 def main():
@@ -289,6 +352,7 @@ def main():
     if int(os.environ.get("RANK", "0")) != 0:
         return
 
+    import numpy as np
     import torch
 
     if args.copy_calibration:
@@ -308,6 +372,23 @@ def main():
                                                            "count", "seed"))
     pts = count * n * nphi
     torch.cuda.set_device(0)
+
+    # the FP64 plain path first (the baseline of the FP32 path's speed-up, with the same
+    # warm-up and half the timed steps); its calls also bring the device to its steady
+    # clocks before the FP32 path is timed
+    fp64 = None
+    if not args.no_fp64:
+        log("setup fp64 plain path")
+        plan64 = Plan(order, n, nphi, lmax, kappa=workloads.kappas(cfg), precision="fp64")
+        out64 = plan64.empty(count)
+        ms64, _ = time_calls(lambda: plan64.sample(seed, count, out64), max(args.steps // 2, 3), args.warmup)
+        plan64.close()
+        del out64
+        torch.cuda.empty_cache()
+        fp64 = {"value": pts / ms64 * 1e3, "unit": "grid points/s", "ms_per_step": ms64,
+                "warmup": args.warmup, "steps": max(args.steps // 2, 3)}
+        log(f"  fp64 {ms64:.3f} ms/step")
+
     log(f"setup {cfg['name']} (fp32)")
     t0 = time.perf_counter()
     plan = Plan(order, n, nphi, lmax, kappa=workloads.kappas(cfg), precision="fp32")
@@ -320,45 +401,43 @@ def main():
     log(f"  recursion {ms_rec:.3f} ms, fft {ms_fft:.3f} ms per launch")
     m_top = plan.m_top
     n_sets = plan.n_sets
+    # the timed output (its last call sampled seeds seed..seed+count-1): the rings around the
+    # equator that the oracle sample of the cpu_baseline leg covers, kept for error_vs_oracle
+    s_ring = n // 2 - 1
+    r0, r1 = s_ring - args.cpu_rings // 2 + 1, s_ring + args.cpu_rings // 2 + 1
+    torch.cuda.synchronize()
+    T_gpu = out.view(count, n, nphi)[:, r0:r1, :].double().cpu().numpy()
     plan.close()
     del out
     torch.cuda.empty_cache()
 
-    fp64 = None
-    if not args.no_fp64:
-        log("setup fp64 plain path on the same workload")
-        plan64 = Plan(order, n, nphi, lmax, kappa=workloads.kappas(cfg), precision="fp64")
-        out64 = plan64.empty(count)
-        ms64, _ = time_calls(lambda: plan64.sample(seed, count, out64), max(args.steps // 2, 3), 2)
-        plan64.close()
-        del out64
-        torch.cuda.empty_cache()
-        fp64 = {"value": pts / ms64 * 1e3, "unit": "grid points/s", "ms_per_step": ms64}
-        log(f"  fp64 {ms64:.3f} ms/step")
+    log("throughput references: Philox + Box-Muller alone, unpacked FP32 FMA")
+    alu = alu_references()
+    log(f"  {alu['normals_per_s']:.3e} normals/s, {alu['fma_lane_per_s']:.3e} lane-FMA/s "
+        f"({100 * alu['fma_frac_of_unit_count_peak']:.0f}% of 256 x 4 x 16 x 2.4e9)")
 
-    # algorithmic work per launch: the
-    # recursion reads the FP32 factors once and writes the modes, and its arithmetic is
-    # alu_slots_per_point per point; the FFT reads and writes every point once
+    # algorithmic work per launch: the recursion reads the FP32 factors once and writes the
+    # modes (and makes `order` normals per point); the FFT reads and writes every point once
     vals_per_rec = order * order + order * (order + 1) // 2
     fac_bytes = n_sets * (m_top + 1) * vals_per_rec * 4
     g_bytes = count * n * (nphi // 2) * 8
-    rec_slots = pts * alu_slots_per_point(order)
     kernels = {
-        "recursion": {"ms": ms_rec, "alg_bytes": fac_bytes + g_bytes, "alu_slots": rec_slots},
+        "recursion": {"ms": ms_rec, "alg_bytes": fac_bytes + g_bytes},
         "c2r_fft": {"ms": ms_fft, "alg_bytes": 2 * count * n * nphi * 4},
     }
     for k, v in kernels.items():
         v["alg_GBs"] = v["alg_bytes"] / (v["ms"] * 1e-3) / 1e9
         v["hbm_frac"] = v["alg_GBs"] / HBM_PEAK_GBS
     kr = kernels["recursion"]
-    kr["alu_Tslots"] = rec_slots / (ms_rec * 1e-3) / 1e12
-    kr["alu_frac"] = kr["alu_Tslots"] * 1e12 / VALU_PEAK_SLOTS
     dom = max(kernels, key=lambda k: kernels[k]["ms"])
     kd = kernels[dom]
     traffic = measured_traffic(dom)
     if dom == "recursion":
-        roofline = {"bound": "alu", "achieved": kr["alu_Tslots"], "peak": VALU_PEAK_SLOTS / 1e12,
-                    "unit": "T lane-slots/s", "frac": kr["alu_frac"], "traffic": traffic, "kernel": dom}
+        # ALU-bound: normals made per second against the generator's own measured rate
+        nps = pts * order / (ms_rec * 1e-3)
+        roofline = {"bound": "alu", "achieved": nps / 1e9, "peak": alu["normals_per_s"] / 1e9,
+                    "unit": "G normals/s", "frac": nps / alu["normals_per_s"], "traffic": traffic,
+                    "kernel": dom, "peak_source": "smf_measure_normals on this device"}
     else:
         roofline = {"bound": "hbm", "achieved": kd["alg_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": kd["hbm_frac"], "traffic": traffic, "kernel": dom}
@@ -369,10 +448,10 @@ def main():
     if tr_fft is not None and tr_rec is not None:
         roofline["path_traffic_GBs"] = (tr_fft + tr_rec) / (ms_step * 1e-3) / 1e9
         roofline["path_traffic_frac"] = roofline["path_traffic_GBs"] / HBM_PEAK_GBS
-    # normals per second of the recursion against the Philox4x32-10 + Box-Muller issue peak
-    # (VALU_PEAK_SLOTS / 42 slots per normal)
+    # normals per second of the recursion against the measured rate of the same generator
+    # alone (smf_measure_normals: the noise with none of the recursion's loads and stores)
     kr["normals_per_s"] = pts * order / (ms_rec * 1e-3)
-    kr["normals_frac_of_issue_peak"] = kr["normals_per_s"] / (VALU_PEAK_SLOTS / 42.0)
+    kr["normals_frac_of_measured_noise_peak"] = kr["normals_per_s"] / alu["normals_per_s"]
 
     batch = None
     if not args.no_batch:
@@ -386,9 +465,9 @@ def main():
         high = []
         for o in (3, 4):
             log(f"order {o} on the same grid and fields")
-            h = high_order_leg(cfg, o, args.steps, args.warmup)
+            h = high_order_leg(cfg, o, args.steps, args.warmup, alu["normals_per_s"])
             log(f"  {h['ms_per_step']:.3f} ms/step, recursion {h['recursion_ms']:.3f} ms "
-                f"({100 * h['recursion_alu_frac']:.0f}% of the VALU issue peak)")
+                f"({100 * h['normals_frac_of_measured_noise_peak']:.0f}% of the noise-alone rate)")
             high.append(h)
 
     hp = None
@@ -399,10 +478,22 @@ def main():
             f"{hp['synthesis_ms']:.3f} ms ({hp['synthesis_alg_GBs']:.0f} GB/s algorithmic), setup {hp['setup_s']:.2f} s")
 
     cpu = None
+    err = None
+    defect = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {args.cpu_rings} rings")
-        cpu = cpu_baseline(cfg, args.cpu_rings, args.cpu_single_rings)
+        cpu, T_orc = cpu_baseline(cfg, args.cpu_rings, args.cpu_single_rings)
         log(f"  {cpu['value']:.3e} pts/s on {cpu['cores']} threads in {cpu['seconds']:.1f} s")
+        # the timed FP32 output against the FP64 oracle on the same normals, field by field
+        d = T_gpu - T_orc
+        rms = [float(np.sqrt(np.sum(d[f] ** 2) / np.sum(T_orc[f] ** 2))) for f in range(count)]
+        mx = [float(np.max(np.abs(d[f])) / np.sqrt(np.mean(T_orc[f] ** 2))) for f in range(count)]
+        err = {"per_field_rel_rms": rms, "per_field_max_abs_over_rms": mx, "bar_rel_rms": 1e-4,
+               "fields": f"seeds {seed}..{seed + count - 1}", "rings": f"{r0}..{r1 - 1} of {n} (all modes, all phi)"}
+        log(f"  timed output vs oracle: rel RMS up to {max(rms):.2e}, max |error| / RMS up to {max(mx):.2e}")
+        log("markov defect of the band limit at sampled modes")
+        defect = markov_defect(cfg)
+        log(f"  {defect['max_rel_cov_defect']:.2e}")
 
     line = {
         "metric": "grid points/s (FP32 batched vs FP64 plain) at 4096x8192; % HBM roofline",
@@ -429,6 +520,9 @@ def main():
         "higher_orders": high,
         "healpix": hp,
         "cpu_baseline": cpu,
+        "error_vs_oracle": err,
+        "markov_defect": defect,
+        "alu_references": alu,
     }
     print(json.dumps(line), flush=True)
 

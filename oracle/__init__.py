@@ -112,6 +112,7 @@ def _load():
     lib.orc_green_P.argtypes = [_i, _d, _d, _d]
     lib.orc_green_P.restype = _d
     lib.orc_jblock_green.argtypes = [_i, _d, _d, _d, _d, _d, _pd]
+    lib.orc_jblock_green2.argtypes = [_i, _pd, _d, _d, _d, _d, _pd]
     lib.orc_max_threads.restype = _i
     lib.orc_set_threads.argtypes = [_i]
     lib.orc_set_threads.restype = None
@@ -219,6 +220,36 @@ def jblock_green(m, kappa, z1, z2):
     J = np.zeros(1)
     _load().orc_jblock_green(int(m), float(kappa), z1, s1, z2, s2, _p(J))
     return float(J[0])
+
+
+def jblock_green2(m, kappas, z1, z2):
+    """J^m(z1, z2) of order 2 in the basis (g, U g) from the Green's functions of two distinct
+    kappa (eqs. (C_ell_efficient), (Jmatrix_efficient)), C_l = 1/((kappa_1 + l(l+1))(kappa_2 + l(l+1)))
+    for every l; a 2 x 2 array."""
+    z1, s1 = _zs(z1)
+    z2, s2 = _zs(z2)
+    k = np.ascontiguousarray(kappas, dtype=np.float64)
+    J = np.zeros(4)
+    _load().orc_jblock_green2(int(m), _p(k), z1, s1, z2, s2, _p(J))
+    return J.reshape(2, 2)
+
+
+def setup_green2(kappas, n_theta, n_phi, sets=None, modes=None, z=None):
+    """Alg. 1 at order 2 in the basis (g, U g) on the Green's-function cross covariances of two
+    distinct kappa (no band limit; modes m <= n_phi/2 - 1, or the listed ones).  Returns
+    (A, B), each [sets][modes][2][2]."""
+    mt = n_phi // 2 - 1
+    md = np.arange(mt + 1, dtype=np.int32) if modes is None else np.ascontiguousarray(modes, dtype=np.int32)
+    ns = n_sets(n_theta) if sets is None else min(sets, n_sets(n_theta))
+    A = np.zeros((ns, len(md), 2, 2))
+    B = np.zeros((ns, len(md), 2, 2))
+    kap = np.ascontiguousarray(kappas, dtype=np.float64)
+    zg = _zgrid(z, n_theta)
+    rc = _load().orc_setup_modes_zb(2, 3, 0, _p(kap), n_theta, None if zg is None else _p(zg), ns,
+                                    md.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(md), _p(A), _p(B))
+    if rc != 0:
+        raise ValueError("orc_setup_modes_zb rejected its arguments")
+    return A, B
 
 
 def setup_green(kappa, n_theta, n_phi, sets=None, modes=None, z=None):

@@ -494,6 +494,61 @@ void orc_jblock_green(int m, double kappa, double z1, double s1, double z2, doub
     J[0] = green_J_scale(m, kappa, z1, s1, z2, s2) * orc_green_G(m, kappa, -z1, s1) * orc_green_G(m, kappa, z2, s2);
 }
 
+/* Order 2 (two distinct real kappa_1, kappa_2 > 0) in the basis (g, U g) of Sec. 3:       */
+/* the partial fractions of eq. (C_ell_efficient), C_l = b_1/(l(l+1) + kappa_1)              */
+/* + b_2/(l(l+1) + kappa_2) with b_1 = 1/(kappa_2 - kappa_1) = -b_2, and eq. (Jmatrix_efficient) */
+/* with P^{m+p} for p, q < 2.  Written out as for order 1, for z1 <= z2:                    */
+/*   J_pq = sum_i b_i (Pi^i_m / m!^2) w^m / (4 |sin pi lambda_i|) (-1)^p                      */
+/*          (a_i r1)^p G^i_{m+p}(-z1) (a_i r2)^q G^i_{m+q}(z2),                              */
+/*   a_i = (m^2 + m + kappa_i) / (m + 1)  (= Pi^i_{m+1} / (Pi^i_m (m+1))),                   */
+/*   r1 = sqrt((1 + z1)/(1 - z1)), r2 = sqrt((1 - z2)/(1 + z2)),                             */
+/* and J(z1, z2) = J(z2, z1)^T for z1 > z2.  J[p*2 + q].                                     */
+static void green2_block(int m, const double* kap, double z1, double s1, double z2, double s2, const double* Gn1_0,
+                         const double* Gn1_1, const double* Gp2_0, const double* Gp2_1, double* J)
+{
+    /* Gn1_i[0..1] = G^i_m(-z1), G^i_{m+1}(-z1); Gp2_i[0..1] = G^i_m(z2), G^i_{m+1}(z2) */
+    const double b1 = 1.0 / (kap[1] - kap[0]);
+    const double b[2] = {b1, -b1};
+    const double* Gn[2] = {Gn1_0, Gn1_1};
+    const double* Gp[2] = {Gp2_0, Gp2_1};
+    /* r1 = sqrt((1+z1)/(1-z1)), r2 = sqrt((1-z2)/(1+z2)), 1 -+ z through sin^2 on the small side */
+    const double opz1 = z1 >= 0.0 ? 1.0 + z1 : s1 * s1 / (1.0 - z1), omz1 = z1 >= 0.0 ? s1 * s1 / (1.0 + z1) : 1.0 - z1;
+    const double opz2 = z2 >= 0.0 ? 1.0 + z2 : s2 * s2 / (1.0 - z2), omz2 = z2 >= 0.0 ? s2 * s2 / (1.0 + z2) : 1.0 - z2;
+    const double r1 = sqrt(opz1 / omz1), r2 = sqrt(omz2 / opz2);
+    for (int i = 0; i < 4; ++i) J[i] = 0.0;
+    for (int i = 0; i < 2; ++i) {
+        const double sc = b[i] * green_J_scale(m, kap[i], z1, s1, z2, s2);
+        const double a = ((double)m * m + m + kap[i]) / (m + 1.0);
+        const double u[2] = {Gn[i][0], -a * r1 * Gn[i][1]};   /* (-1)^p (a r1)^p G_{m+p}(-z1) */
+        const double v[2] = {Gp[i][0], a * r2 * Gp[i][1]};    /* (a r2)^q G_{m+q}(z2) */
+        for (int p = 0; p < 2; ++p)
+            for (int q = 0; q < 2; ++q) J[p * 2 + q] += sc * u[p] * v[q];
+    }
+}
+
+/* J^m(z1, z2) of order 2 from the Green's functions (2 x 2 block, see green2_block). */
+void orc_jblock_green2(int m, const double* kap, double z1, double s1, double z2, double s2, double* J)
+{
+    const int swap = z1 > z2;
+    if (swap) {
+        double t = z1; z1 = z2; z2 = t;
+        t = s1; s1 = s2; s2 = t;
+    }
+    double gn[2][2], gp[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int k = 0; k < 2; ++k) {
+            gn[i][k] = orc_green_G(m + k, kap[i], -z1, s1);
+            gp[i][k] = orc_green_G(m + k, kap[i], z2, s2);
+        }
+    double K[4];
+    green2_block(m, kap, z1, s1, z2, s2, gn[0], gn[1], gp[0], gp[1], K);
+    if (swap) {
+        J[0] = K[0]; J[1] = K[2]; J[2] = K[1]; J[3] = K[3];
+    } else {
+        for (int i = 0; i < 4; ++i) J[i] = K[i];
+    }
+}
+
 /* The same with z1 = cos(theta1), z2 = cos(theta2). */
 void orc_jblock(int order, int m, int ell_max, const double* C, double theta1, double theta2,
                 double* J)
@@ -659,12 +714,16 @@ static int grid_ok(const double* zgrid, int n_theta, int symmetric)
 }
 
 /* basis 0: value and z-derivatives; 1: (g, U g) of Sec. 3 (order 2); 2: the Green's   */
-/* function of Sec. 3 at order 1, C then holding the single kappa (no band limit).     */
+/* function of Sec. 3 at order 1, C then holding the single kappa (no band limit);     */
+/* 3: the Green's functions at order 2 in the basis (g, U g), C holding two distinct   */
+/* kappa.                                                                              */
 static void jblock_basis(int order, int basis, int m, int ell_max, const double* C, double z1, double s1, double z2,
                          double s2, double* J)
 {
     if (basis == 2)
         orc_jblock_green(m, C[0], z1, s1, z2, s2, J);
+    else if (basis == 3)
+        orc_jblock_green2(m, C, z1, s1, z2, s2, J);
     else if (basis == 1)
         orc_jblock_zs_u(m, ell_max, C, z1, s1, z2, s2, J);
     else
@@ -770,7 +829,9 @@ int orc_setup_modes_zb(int order, int basis, int ell_max, const double* C, int n
                        int n_sets, const int* modes, int n_modes, double* A, double* B)
 {
     if (order < 1 || order > ORC_MAXM || n_theta < 2 || ell_max < 0) return -1;
-    if (basis != 0 && !(basis == 1 && order == 2) && !(basis == 2 && order == 1 && C[0] > 0.0)) return -1;
+    if (basis != 0 && !(basis == 1 && order == 2) && !(basis == 2 && order == 1 && C[0] > 0.0) &&
+        !(basis == 3 && order == 2 && C[0] > 0.0 && C[1] > 0.0 && C[0] != C[1]))
+        return -1;
     if (zgrid && !grid_ok(zgrid, n_theta, 1)) return -1;
     int total = orc_n_sets(n_theta);
     if (n_sets > total) n_sets = total;

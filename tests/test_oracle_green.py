@@ -148,3 +148,57 @@ def test_green_chain_is_exactly_markov(orc, kappa, n):
             Jrs = orc.jblock_green(m, kappa, z[r], z[s])
             assert cov[r] == pytest.approx(Jrr, rel=1e-12, abs=1e-300), (m, r)
             assert cross[r] == pytest.approx(Jrs, rel=1e-10, abs=1e-14 * math.sqrt(Jrr * cov[s])), (m, r)
+
+
+# ---------------------------------------------------------------- order 2, two distinct kappa
+K2 = [[100.0, 900.0], [3.0, 64.0]]
+
+
+@pytest.mark.parametrize("kappas", K2)
+def test_order2_green_matches_u_basis_sums(orc, kappas):
+    """Order 2 in the basis (g, U g): the partial fractions of eq. (C_ell_efficient) and
+    eq. (Jmatrix_efficient) with P^m and P^{m+1} against the brute-force sums of
+    U^p L_lm U^q L_lm (the U basis of eq. (Jmatrix_more_efficient), Legendre sums with
+    C_l = 1/((kappa_1 + l(l+1))(kappa_2 + l(l+1)))) as ell_max grows; errors relative to the
+    standard deviations of the two components; off the diagonal to 1e-6 at ell_max = 16000,
+    every component falling with ell_max."""
+    for m in (0, 2, 11):
+        for z1, z2 in ((0.2, 0.35), (-0.3, 0.1), (0.6, 0.1), (0.45, 0.45)):
+            Jg = orc.jblock_green2(m, kappas, z1, z2)
+            sd = np.sqrt(np.outer(np.diag(orc.jblock_green2(m, kappas, z1, z1)),
+                                  np.diag(orc.jblock_green2(m, kappas, z2, z2))))
+            errs = []
+            for lmax in (2000, 8000, 16000):
+                C = orc.spectrum(kappas, lmax)
+                errs.append(np.abs(orc.jblock_u(m, lmax, C, z1, z2) - Jg) / sd)
+            worst = [float(e.max()) for e in errs]
+            assert worst[2] < worst[1] < worst[0], (m, z1, z2, worst)
+            if z1 != z2:
+                assert worst[2] < 1e-6, (m, z1, z2, worst)
+            else:   # the U U component converges like 1 / ell_max on the diagonal
+                assert worst[2] < 5e-3 and 16000 * worst[2] == pytest.approx(8000 * worst[1], rel=0.15), worst
+
+
+@pytest.mark.parametrize("kappas,n", [([100.0, 900.0], 64), ([3.0, 64.0], 33)])
+def test_order2_green_chain_is_exactly_markov(orc, kappas, n):
+    """The order-2 chain on the Green's-function factors reproduces the closed-form J^m
+    (all four components) between the start ring and rings far from it, to 1e-10 of the
+    standard deviations."""
+    nphi = 2 * n if n % 2 == 0 else 2 * (n + 1)
+    A, B = orc.setup_green2(kappas, n, nphi)
+    _, z = orc.grid(n)
+    s = orc.start_ring(n)
+    even = n % 2 == 0
+    for m in (0, 1, 5, n // 2):
+        S = B[0, m] @ B[0, m].T
+        V, X, prev = S.copy(), S.copy(), s
+        for j in range(2 if even else 1, A.shape[0]):
+            r = s - j + 1 if even else s - j
+            V = A[j, m] @ V @ A[j, m].T + B[j, m] @ B[j, m].T
+            X = A[j, m] @ X
+            if (s - r) % 5 == 0:
+                J = orc.jblock_green2(m, kappas, z[r], z[s])
+                sd = np.sqrt(np.outer(np.diag(V), np.diag(S)))
+                assert np.max(np.abs(X - J) / sd) < 1e-10, (m, r)
+                Jrr = orc.jblock_green2(m, kappas, z[r], z[r])
+                assert np.max(np.abs(V - Jrr) / np.sqrt(np.outer(np.diag(V), np.diag(V)))) < 1e-10, (m, r)

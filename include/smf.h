@@ -65,14 +65,16 @@ enum {
                             a grid with no symmetry always stores both. */
     SMF_FUSED = 8,       /* reserved for a single-kernel recursion + FFT; smf_setup returns
                             SMF_EINVAL for it (the two launches of smf_sample are the path) */
-    SMF_GREEN = 32,      /* or'ed with SMF_FP64 or SMF_FP32: the setup of Sec. 3 at order 1.  The
-                            spectrum is C_l = 1/(kappa + l(l+1)) for every l >= 0, not truncated
-                            (n_kappa = 1, kappa > 0, c_ell NULL; ell_max is ignored and every mode
-                            up to n_phi/2 - 1 is sampled), and J^m comes from the Green's function
-                            of the mode's operator, eq. (Jmatrix_efficient), with P^m_lambda of
-                            complex degree (kappa = -lambda(lambda+1)) from its hypergeometric
-                            series, eq. (Legendre_hypergeometric), instead of sums over l: the chain
-                            is then exactly Markov.  Needs n_theta * n_phi / 2 <= 2^27 (two setup
+    SMF_GREEN = 32,      /* or'ed with SMF_FP64 or SMF_FP32: the setup of Sec. 3 at order 1 or 2.
+                            The spectrum is eq. (Cl) with n_kappa = order distinct real kappa_i > 0
+                            (c_ell NULL) for every l >= 0, not truncated (ell_max is ignored and
+                            every mode up to n_phi/2 - 1 is sampled), and J^m comes from the Green's
+                            functions of the mode's operator, eq. (Jmatrix_efficient) with the
+                            partial fractions of eq. (C_ell_efficient), and P^m_lambda of complex
+                            degree (kappa_i = -lambda_i(lambda_i+1)) from its hypergeometric series,
+                            eq. (Legendre_hypergeometric), instead of sums over l: the chain is then
+                            exactly Markov.  At order 2 the state is (g, U_m g), the basis of
+                            SMF_UBASIS.  Needs order * n_theta * (n_phi / 2 + 1) <= 2^27 (two setup
                             tables of that many doubles). */
     SMF_UBASIS = 16      /* order 2 only, or'ed with one of the above: the chain state is
                             (g, U_m g) with the operator U_m of Sec. 3 (eq. (Jmatrix_more_efficient):
@@ -90,7 +92,7 @@ enum {
  *   spec      host; copied, not retained.
  *   n_theta   >= 2 rings.     n_phi  power of two in [4, 16384].
  *   flags     exactly one of SMF_FP64, SMF_FP32, optionally or'ed with SMF_NO_MIRROR,
- *             SMF_UBASIS (order 2) or SMF_GREEN (order 1).
+ *             SMF_UBASIS (order 2) or SMF_GREEN (orders 1 and 2).
  *   out       receives the new plan (host pointer to a pointer).
  * Orders 3 and 4 take the second and third z-derivatives of L_lm from the associated
  * Legendre equation; their records hold A row-major and B's lower triangle (16 and 32

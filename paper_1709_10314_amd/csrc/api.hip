@@ -166,10 +166,15 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
     flags &= ~(SMF_UBASIS | SMF_NO_MIRROR | SMF_GREEN);
     if (flags != SMF_FP64 && flags != SMF_FP32) return SMF_EINVAL;
     if (ubasis && spec->order != 2) return SMF_EINVAL;
-    if (green && (spec->order != 1 || ubasis || spec->c_ell || spec->n_kappa != 1 || !spec->kappa ||
-                  !(spec->kappa[0] > 0.0) || !std::isfinite(spec->kappa[0]) ||
-                  (long long)n_theta * (n_phi / 2) > smf::kGreenMaxTable))
-        return SMF_EINVAL;
+    if (green) {
+        // order 1 with one kappa, or order 2 with two distinct ones, all finite and positive
+        if (spec->order > 2 || ubasis || spec->c_ell || spec->n_kappa != spec->order || !spec->kappa ||
+            (long long)spec->order * n_theta * (n_phi / 2 + 1) > smf::kGreenMaxTable)
+            return SMF_EINVAL;
+        for (int i = 0; i < spec->n_kappa; ++i)
+            if (!(spec->kappa[i] > 0.0) || !std::isfinite(spec->kappa[i])) return SMF_EINVAL;
+        if (spec->order == 2 && spec->kappa[0] == spec->kappa[1]) return SMF_EINVAL;
+    }
     if (z_host && !grid_ok(z_host, n_theta)) return SMF_EINVAL;
 
     int dev = 0;
@@ -244,13 +249,13 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
     }
     plan->south_off = plan->asym ? nrec1 : 0;
     if (green) {
-        const size_t nt = (size_t)n_theta * g.m_rows;
+        const size_t nt = (size_t)spec->n_kappa * n_theta * (g.m_rows + 1);
         if ((rc = bufs.alloc(&hp_dev, nt))) goto fail;
         if ((rc = bufs.alloc(&hn_dev, nt))) goto fail;
-        if (smf::launch_green_tables(g, spec->kappa[0], z_dev, hp_dev, hn_dev, st) != hipSuccess ||
-            smf::launch_factors_green(g, spec->kappa[0], z_dev, 0, hp_dev, hn_dev, plan->f64, plan->f32, st) !=
+        if (smf::launch_green_tables(g, spec->n_kappa, spec->kappa, z_dev, hp_dev, hn_dev, st) != hipSuccess ||
+            smf::launch_factors_green(g, spec->kappa, z_dev, 0, hp_dev, hn_dev, plan->f64, plan->f32, st) !=
                 hipSuccess ||
-            (plan->asym && smf::launch_factors_green(g, spec->kappa[0], z_dev, 1, hp_dev, hn_dev, plan->f64 + nrec1,
+            (plan->asym && smf::launch_factors_green(g, spec->kappa, z_dev, 1, hp_dev, hn_dev, plan->f64 + nrec1,
                                                      plan->f32 ? plan->f32 + nrec1 : nullptr, st) != hipSuccess)) {
             rc = SMF_EHIP;
             goto fail;

@@ -682,23 +682,26 @@ __device__ void green_h01_far(const GreenConst& c, double u, double& h0, double&
 
 // Series side of the table: thread (ring i, mode m) fills H_m(+-z_i) for the sign that
 // makes the argument non-negative (both at z_i = 0).
+// Tables hold H_m for m = 0..m_hi (m_top at order 1, m_top + 1 at order 2), `w` values per ring.
 __global__ __launch_bounds__(64) void green_series_kernel(Geometry g, const double* __restrict__ zgrid, GreenConst c,
-                                                          double* __restrict__ hp, double* __restrict__ hn)
+                                                          int m_hi, int w, double* __restrict__ hp,
+                                                          double* __restrict__ hn)
 {
     const int m = blockIdx.x * 64 + threadIdx.x;
     const int i = blockIdx.y;
-    if (m > g.m_top) return;
+    if (m > m_hi) return;
     double z, sn;
     green_ring(g, zgrid, i, z, sn);
-    const size_t o = (size_t)i * g.m_rows + m;
+    const size_t o = (size_t)i * w + m;
     // t = (1 - x)/2 with 1 - x = sin^2 / (1 + x) for x >= 0
     if (z >= 0.0) hp[o] = green_series(m, c.kappa, sn * sn / (2.0 * (1.0 + z)));
     if (z <= 0.0) hn[o] = green_series(m, c.kappa, sn * sn / (2.0 * (1.0 - z)));
 }
 
-// Recurrence side: one thread per ring fills H_m(x) for x = -|z_i| < 0, m = 0..m_top.
+// Recurrence side: one thread per ring fills H_m(x) for x = -|z_i| < 0, m = 0..m_hi.
 __global__ __launch_bounds__(64) void green_recur_kernel(Geometry g, const double* __restrict__ zgrid, GreenConst c,
-                                                         double* __restrict__ hp, double* __restrict__ hn)
+                                                         int m_hi, int w, double* __restrict__ hp,
+                                                         double* __restrict__ hn)
 {
     const int i = blockIdx.x * 64 + threadIdx.x;
     if (i >= g.n_theta) return;
@@ -706,7 +709,7 @@ __global__ __launch_bounds__(64) void green_recur_kernel(Geometry g, const doubl
     green_ring(g, zgrid, i, z, sn);
     if (z == 0.0) return;
     const double x = -fabs(z);
-    double* __restrict__ h = (z > 0.0 ? hn : hp) + (size_t)i * g.m_rows;
+    double* __restrict__ h = (z > 0.0 ? hn : hp) + (size_t)i * w;
     const double u = sn * sn / (2.0 * (1.0 - x));       // (1 + x)/2
     double h0, h1;
     if (u * (c.kappa + 1.0) <= 0.5) {
@@ -716,10 +719,10 @@ __global__ __launch_bounds__(64) void green_recur_kernel(Geometry g, const doubl
         h1 = green_series(1, c.kappa, 1.0 - u);
     }
     h[0] = h0;
-    if (g.m_top >= 1) h[1] = h1;
+    if (m_hi >= 1) h[1] = h1;
     const double opx = 2.0 * u, omx = 1.0 - x;
     const double ratio = opx / omx, cross = -2.0 * x / opx;
-    for (int k = 0; k + 2 <= g.m_top; ++k) {
+    for (int k = 0; k + 2 <= m_hi; ++k) {
         const double dk = (double)k;
         const double q = (dk + 1.0) * (dk + 2.0) + c.kappa;
         const double h2 = (dk + 1.0) * (dk + 2.0) / q * ratio * fma(cross, h1, h0);
@@ -777,7 +780,7 @@ GreenConst green_const(double kappa)
 // One thread per (set j, mode m), sets as in factor_kernel (south: the southern walk's own
 // steps, stored mirrored; at order 1 the mirror leaves the record unchanged).
 __global__ __launch_bounds__(64) void green_factor_kernel(Geometry g, const double* __restrict__ zgrid, GreenConst c,
-                                                          int south, const double* __restrict__ hp,
+                                                          int south, int w, const double* __restrict__ hp,
                                                           const double* __restrict__ hn, double* __restrict__ f64,
                                                           float* __restrict__ f32)
 {
@@ -803,7 +806,7 @@ __global__ __launch_bounds__(64) void green_factor_kernel(Geometry g, const doub
     double za, sa, zb, sb;
     green_ring(g, zgrid, a, za, sa);
     green_ring(g, zgrid, b, zb, sb);
-    const size_t oa = (size_t)a * g.m_rows + m, ob = (size_t)b * g.m_rows + m;
+    const size_t oa = (size_t)a * w + m, ob = (size_t)b * w + m;
     const double kaa = green_j(c, rm, m, za, sa, za, sa, hn[oa], hp[oa]);
     const size_t base = ((size_t)j * g.m_rows + m) * factor_stride(1);
     double A, B;
@@ -819,6 +822,116 @@ __global__ __launch_bounds__(64) void green_factor_kernel(Geometry g, const doub
     f64[base] = A;
     f64[base + 1] = B;
     if (f32) { f32[base] = (float)A; f32[base + 1] = (float)B; }
+}
+
+// Order 2 (two distinct kappa, the basis (g, U g) of Sec. 3): with the partial fractions
+// C_l = b_0/(l(l+1) + kappa_0) + b_1/(l(l+1) + kappa_1), b_0 = 1/(kappa_1 - kappa_0) = -b_1
+// (eq. (C_ell_efficient)), eq. (Jmatrix_efficient) takes P^{m+p}(-z1) P^{m+q}(z2) for
+// p, q < 2 (z1 <= z2), and P^{m+1} / P^m adds the factor a (1 -+ z)/(1 +- z) ^(1/2) with
+// a = (m^2 + m + kappa)/(m + 1):
+//   J_pq = sum_i b_i R^i_m w^m / (4 |sin pi lambda_i|) (-1)^p (a_i r1)^p H^i_{m+p}(-z1)
+//          (a_i r2)^q H^i_{m+q}(z2),  r1 = sqrt((1+z1)/(1-z1)), r2 = sqrt((1-z2)/(1+z2)).
+// hn1[i][k] = H^i_{m+k}(-z1), hp2[i][k] = H^i_{m+k}(z2); J[p*2 + q].
+__device__ void green2_pair(const GreenConst* c, const double* rm, int m, double z1, double s1, double z2, double s2,
+                            const double (&hn1)[2][2], const double (&hp2)[2][2], double (&J)[4])
+{
+    double wm = 1.0, lp1, lm1, lp2, lm2;
+    green_logs(z1, s1, lp1, lm1);
+    green_logs(z2, s2, lp2, lm2);
+    if (z1 != z2 && m > 0) wm = exp(0.5 * (double)m * ((lp1 - lm1) + (lm2 - lp2)));
+    const double r1 = exp(0.5 * (lp1 - lm1)), r2 = exp(0.5 * (lm2 - lp2));
+    const double b0 = 1.0 / (c[1].kappa - c[0].kappa);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) J[k] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double sc = (i == 0 ? b0 : -b0) * rm[i] * wm * c[i].inv4s;
+        const double a = ((double)m * m + m + c[i].kappa) / (m + 1.0);
+        const double u0 = hn1[i][0], u1 = -a * r1 * hn1[i][1];
+        const double v0 = hp2[i][0], v1 = a * r2 * hp2[i][1];
+        J[0] = fma(sc * u0, v0, J[0]);
+        J[1] = fma(sc * u0, v1, J[1]);
+        J[2] = fma(sc * u1, v0, J[2]);
+        J[3] = fma(sc * u1, v1, J[3]);
+    }
+}
+
+// One thread per (set j, mode m) at order 2, sets and mirror as in factor_kernel.
+__global__ __launch_bounds__(64) void green2_factor_kernel(Geometry g, const double* __restrict__ zgrid, GreenConst c0,
+                                                           GreenConst c1, int south, int w,
+                                                           const double* __restrict__ hp,
+                                                           const double* __restrict__ hn, double* __restrict__ f64,
+                                                           float* __restrict__ f32)
+{
+    const int j = blockIdx.x * 64 + threadIdx.x;
+    const int m = blockIdx.y;
+    if (j >= g.n_sets) return;
+    const bool mirror = south && j >= (g.even ? 2 : 1);
+    int a, b;
+    if (mirror) {
+        a = g.s + j - 1; b = g.s + j;
+    } else if (j == 0) {
+        a = b = g.s;
+    } else if (g.even) {
+        if (j == 1) { a = g.s; b = g.s + 1; }
+        else { a = g.s - j + 2; b = g.s - j + 1; }
+    } else {
+        a = g.s - j + 1; b = g.s - j;
+    }
+    const GreenConst c[2] = {c0, c1};
+    double rm[2] = {1.0, 1.0};
+    for (int k = 1; k <= m; ++k) {
+        const double dk = (double)k;
+        rm[0] *= (dk * dk - dk + c0.kappa) / (dk * dk);
+        rm[1] *= (dk * dk - dk + c1.kappa) / (dk * dk);
+    }
+    double za, sa, zb, sb;
+    green_ring(g, zgrid, a, za, sa);
+    green_ring(g, zgrid, b, zb, sb);
+    // table i (kappa_i) starts at i * n_theta * w
+    const size_t tstride = (size_t)g.n_theta * w;
+    double hna[2][2], hpa[2][2], hnb[2][2], hpb[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            hna[i][k] = hn[i * tstride + (size_t)a * w + m + k];
+            hpa[i][k] = hp[i * tstride + (size_t)a * w + m + k];
+            hnb[i][k] = hn[i * tstride + (size_t)b * w + m + k];
+            hpb[i][k] = hp[i * tstride + (size_t)b * w + m + k];
+        }
+    double Ja[4], Jb[4], Jx[4];
+    green2_pair(c, rm, m, za, sa, za, sa, hna, hpa, Ja);
+    const double kaa[3] = {Ja[0], 0.5 * (Ja[1] + Ja[2]), Ja[3]};
+    double A[4] = {0, 0, 0, 0}, B[3];
+    if (j == 0) {
+        start_m2(kaa, B);
+    } else {
+        green2_pair(c, rm, m, zb, sb, zb, sb, hnb, hpb, Jb);
+        const double kbb[3] = {Jb[0], 0.5 * (Jb[1] + Jb[2]), Jb[3]};
+        double kba[4];
+        if (zb <= za) {                       // J(z_b, z_a) directly: E[x_b,p x_a,q]
+            green2_pair(c, rm, m, zb, sb, za, sa, hnb, hpa, Jx);
+            kba[0] = Jx[0]; kba[1] = Jx[1]; kba[2] = Jx[2]; kba[3] = Jx[3];
+        } else {                              // J(z_a, z_b) transposed
+            green2_pair(c, rm, m, za, sa, zb, sb, hna, hpb, Jx);
+            kba[0] = Jx[0]; kba[1] = Jx[2]; kba[2] = Jx[1]; kba[3] = Jx[3];
+        }
+        factors_m2(kaa, kbb, kba, A, B);
+    }
+    if (mirror) {   // D A D, D B D: the off-diagonal entries change sign
+        A[1] = -A[1];
+        A[2] = -A[2];
+        B[1] = -B[1];
+    }
+    const size_t base = ((size_t)j * g.m_rows + m) * factor_stride(2);
+    const double v[8] = {A[0], A[1], A[2], A[3], B[0], B[1], B[2], 0.0};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) f64[base + i] = v[i];
+    if (f32) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) f32[base + i] = (float)v[i];
+    }
 }
 
 }  // namespace
@@ -865,25 +978,39 @@ hipError_t launch_factors(const Geometry& g, const double* C_dev, const double* 
     return hipGetLastError();
 }
 
-hipError_t launch_green_tables(const Geometry& g, double kappa, const double* z_dev, double* hp, double* hn,
-                               hipStream_t st)
+hipError_t launch_green_tables(const Geometry& g, int n_kappa, const double* kappa, const double* z_dev, double* hp,
+                               double* hn, hipStream_t st)
 {
-    GreenConst c = green_const(kappa);
-    hipLaunchKernelGGL(green_series_kernel, dim3((g.m_top + 64) / 64, g.n_theta), dim3(64), 0, st, g, z_dev, c, hp,
-                       hn);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(green_recur_kernel, dim3((g.n_theta + 63) / 64), dim3(64), 0, st, g, z_dev, c, hp, hn);
-    return hipGetLastError();
+    const int m_hi = g.m_top + (g.order - 1), w = g.m_rows + 1;
+    const size_t tstride = (size_t)g.n_theta * w;
+    for (int i = 0; i < n_kappa; ++i) {
+        GreenConst c = green_const(kappa[i]);
+        hipLaunchKernelGGL(green_series_kernel, dim3((m_hi + 64) / 64, g.n_theta), dim3(64), 0, st, g, z_dev, c, m_hi,
+                           w, hp + i * tstride, hn + i * tstride);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(green_recur_kernel, dim3((g.n_theta + 63) / 64), dim3(64), 0, st, g, z_dev, c, m_hi, w,
+                           hp + i * tstride, hn + i * tstride);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
-hipError_t launch_factors_green(const Geometry& g, double kappa, const double* z_dev, int south, const double* hp,
-                                const double* hn, double* f64, float* f32, hipStream_t st)
+hipError_t launch_factors_green(const Geometry& g, const double* kappa, const double* z_dev, int south,
+                                const double* hp, const double* hn, double* f64, float* f32, hipStream_t st)
 {
-    if (g.order != 1) return hipErrorInvalidValue;
-    GreenConst c = green_const(kappa);
-    hipLaunchKernelGGL(green_factor_kernel, dim3((g.n_sets + 63) / 64, g.m_top + 1), dim3(64), 0, st, g, z_dev, c,
-                       south, hp, hn, f64, f32);
+    const int w = g.m_rows + 1;
+    const dim3 grid((g.n_sets + 63) / 64, g.m_top + 1);
+    if (g.order == 1) {
+        hipLaunchKernelGGL(green_factor_kernel, grid, dim3(64), 0, st, g, z_dev, green_const(kappa[0]), south, w, hp,
+                           hn, f64, f32);
+    } else if (g.order == 2) {
+        hipLaunchKernelGGL(green2_factor_kernel, grid, dim3(64), 0, st, g, z_dev, green_const(kappa[0]),
+                           green_const(kappa[1]), south, w, hp, hn, f64, f32);
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

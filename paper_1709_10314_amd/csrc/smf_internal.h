@@ -64,15 +64,16 @@ hipError_t launch_spectrum(const double* kappa_dev, int n_kappa, const double* c
 hipError_t launch_factors(const Geometry& g, const double* C_dev, const double* z_dev, int south, int ubasis,
                           double* f64, float* f32, hipStream_t st);
 hipError_t launch_twiddles(int n_phi, double* tw64, float* tw32, hipStream_t st);
-// Sec. 3 at order 1 (C_l = 1/(kappa + l(l+1)) for every l): the hypergeometric factors
-// H_m(z_i) into hp and H_m(-z_i) into hn ([n_theta][m_rows] each), then the factor records
-// from them.
-hipError_t launch_green_tables(const Geometry& g, double kappa, const double* z_dev, double* hp, double* hn,
-                               hipStream_t st);
-hipError_t launch_factors_green(const Geometry& g, double kappa, const double* z_dev, int south, const double* hp,
-                                const double* hn, double* f64, float* f32, hipStream_t st);
-// Largest n_theta * n_phi / 2 of a Green's-function plan (its two setup tables of that many
-// doubles each)
+// Sec. 3 at order 1 (C_l = 1/(kappa + l(l+1)) for every l) and order 2 (two distinct kappa,
+// basis (g, U g)): the hypergeometric factors H_m(z_i) into hp and H_m(-z_i) into hn, per kappa
+// a table [n_theta][m_rows + 1] (m up to m_top + order - 1), the tables of the kappa one after
+// the other; then the factor records from them.
+hipError_t launch_green_tables(const Geometry& g, int n_kappa, const double* kappa, const double* z_dev, double* hp,
+                               double* hn, hipStream_t st);
+hipError_t launch_factors_green(const Geometry& g, const double* kappa, const double* z_dev, int south,
+                                const double* hp, const double* hn, double* f64, float* f32, hipStream_t st);
+// Largest n_kappa * n_theta * (n_phi / 2 + 1) of a Green's-function plan (its two setup tables
+// of that many doubles each)
 constexpr long long kGreenMaxTable = 1LL << 27;
 // Phi per (fine ring block, m) for the affine scan, layout [block][m][M*M], m stride m_rows.
 hipError_t launch_phi(const Geometry& g, const double* f64, int blocks, double* phi64, float* phi32,

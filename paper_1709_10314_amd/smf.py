@@ -415,8 +415,9 @@ class Plan:
                  stream=None, z=None, basis="z", mirror=True, green=False):
         """basis: "z" (the state is the value and its z-derivatives) or "u" (order 2: (g, U g)
         of Sec. 3, SMF_UBASIS).  mirror=False stores the southern walk's own factor sets
-        (SMF_NO_MIRROR).  green=True (order 1, one kappa): the Green's-function setup of Sec. 3
-        for C_l = 1/(kappa + l(l+1)) without band limit (SMF_GREEN; ell_max is ignored)."""
+        (SMF_NO_MIRROR).  green=True (order 1 with one kappa, order 2 with two distinct ones): the
+        Green's-function setup of Sec. 3 for eq. (Cl) without band limit (SMF_GREEN; ell_max is
+        ignored; at order 2 the state is (g, U g))."""
         flags = {"fp32": SMF_FP32, "fp64": SMF_FP64}[precision] | {"z": 0, "u": SMF_UBASIS}[basis]
         if not mirror:
             flags |= SMF_NO_MIRROR

@@ -1,6 +1,7 @@
-"""GPU tests of the Green's-function setup of Sec. 3 at order 1 (SMF_GREEN): C_l =
+"""GPU tests of the Green's-function setup of Sec. 3 (SMF_GREEN): at order 1 C_l =
 1/(kappa + l(l+1)) for every l, J^m from eq. (Jmatrix_efficient) with P^m_lambda of complex
-(or, for kappa <= 1/4, real) degree.  The device factors against the oracle's Green's-function
+(or, for kappa <= 1/4, real) degree; at order 2 two distinct kappa through the partial
+fractions of eq. (C_ell_efficient), in the basis (g, U g).  The device factors against the oracle's Green's-function
 setup by their action on the chain's law, the fields against the oracle's chains and DFT on
 the same Philox normals (FP64 1e-10, FP32 1e-4 per field, with element-wise maxima), and the
 property the band-limited setup lacks: the device chain reproduces the closed-form J^m between
@@ -96,10 +97,88 @@ def test_green_chain_has_no_markov_defect(case):
 def test_green_rejects_what_it_does_not_cover():
     from paper_1709_10314_amd import smf
 
-    for kw in (dict(order=2, kappa=[64.0, 64.0]), dict(order=1, kappa=[64.0, 9.0]), dict(order=1, kappa=[-1.0])):
+    for kw in (dict(order=3, kappa=[64.0, 9.0, 4.0]), dict(order=1, kappa=[64.0, 9.0]), dict(order=1, kappa=[-1.0])):
         rc, _ = smf.smf_setup(kw["order"], 16, 32, 15, kappa=kw["kappa"], flags=smf.SMF_FP64 | smf.SMF_GREEN)
         assert rc == smf.SMF_EINVAL, kw
     rc, _ = smf.smf_setup(1, 16, 32, 15, c_ell=np.ones(16), flags=smf.SMF_FP64 | smf.SMF_GREEN)
     assert rc == smf.SMF_EINVAL
     rc, _ = smf.smf_setup(1, 16, 32, 15, kappa=[4.0], flags=smf.SMF_FP64 | smf.SMF_GREEN | smf.SMF_UBASIS)
     assert rc == smf.SMF_EINVAL
+
+
+# ---------------------------------------------------------------- order 2, two distinct kappa
+CASES2 = [(64, 128, [100.0, 900.0]), (256, 512, [64.0, 2500.0]), (33, 64, [0.2, 3.0])]
+
+
+def _plan2(n, nphi, kappas, precision):
+    from paper_1709_10314_amd import Plan
+
+    return Plan(2, n, nphi, 0, kappa=kappas, precision=precision, green=True)
+
+
+@pytest.mark.parametrize("case", CASES2, ids=lambda c: f"{c[0]}x{c[1]}-k{c[2][0]:g}-{c[2][1]:g}")
+def test_green2_factors_and_fields_match_oracle(case):
+    n, nphi, kappas = case
+    p = _plan2(n, nphi, kappas, "fp64")
+    Ag, Bg = p.factors()
+    T = p.sample(13, 2).double().cpu().numpy()
+    torch.cuda.synchronize()
+    p.close()
+    Ao, Bo = oracle.setup_green2(kappas, n, nphi)
+    dA, dS, amb = factor_errors(Ag, Bg, Ao, Bo, n)
+    # The factor bar is the conditioning of the problem, measured on the oracle alone: its own
+    # factors move this far when each kappa moves by one unit in the last place.  The partial
+    # fractions of eq. (C_ell_efficient) (weights 1/(kappa_2 - kappa_1)) and the Schur
+    # complement of Alg. 1 (conditional variances of the value a small power of the ring
+    # spacing below the marginal ones) both amplify FP64 rounding.
+    Ap, Bp = oracle.setup_green2([kappas[0] * (1 + 2.0 ** -52), kappas[1] * (1 - 2.0 ** -52)], n, nphi)
+    sA, sS, _ = factor_errors(Ap, Bp, Ao, Bo, n)
+    To, _ = oracle.sample(2, n, nphi, Ao, Bo, 13, 2)
+    e = max(rel_rms(T[f], To[f]) for f in range(2))
+    emax = max(max_rel_err(T[f], To[f]) for f in range(2))
+    log(f"green2 {n}x{nphi} kappa {kappas}: factors dA {dA:.2e} dS {dS:.2e} ({amb} steps next to a threshold), "
+        f"oracle's one-ulp sensitivity dA {sA:.2e} dS {sS:.2e}; fields rel RMS {e:.2e}, max {emax:.2e}")
+    assert dA <= 10 * sA + 1e-13 and dS <= 10 * sS + 1e-13
+    assert e <= 1e-10 and emax <= 1e-9
+    p32 = _plan2(n, nphi, kappas, "fp32")
+    T32 = p32.sample(13, 2).double().cpu().numpy()
+    torch.cuda.synchronize()
+    p32.close()
+    e32 = max(rel_rms(T32[f], To[f]) for f in range(2))
+    log(f"  fp32 fields rel RMS {e32:.2e}")
+    assert e32 <= 1e-4
+
+
+@pytest.mark.parametrize("case", CASES2[:2], ids=lambda c: f"{c[0]}x{c[1]}")
+def test_green2_chain_has_no_markov_defect(case):
+    """All four components of J^m between the start ring and rings far from it, from the
+    device's FP64 factors, against the closed form, to 1e-10 of the standard deviations."""
+    n, nphi, kappas = case
+    p = _plan2(n, nphi, kappas, "fp64")
+    A, B = p.factors()
+    p.close()
+    _, z = oracle.grid(n)
+    s = oracle.start_ring(n)
+    worst = 0.0
+    for m in (0, 1, 7, nphi // 8):
+        S = B[0, m] @ B[0, m].T
+        V, X = S.copy(), S.copy()
+        for j in range(2, A.shape[0]):
+            r = s - j + 1
+            V = A[j, m] @ V @ A[j, m].T + B[j, m] @ B[j, m].T
+            X = A[j, m] @ X
+            if (s - r) % 7 == 0:
+                J = oracle.jblock_green2(m, kappas, z[r], z[s])
+                sd = np.sqrt(np.outer(np.diag(V), np.diag(S)))
+                worst = max(worst, float(np.max(np.abs(X - J) / sd)))
+    log(f"green2 {n}x{nphi}: largest cross-covariance error {worst:.2e} of the sd products")
+    assert worst <= 1e-10
+
+
+def test_green2_rejects_repeated_or_missing_kappa():
+    from paper_1709_10314_amd import smf
+
+    for kw in (dict(order=2, kappa=[50.0, 50.0]), dict(order=2, kappa=[50.0]), dict(order=3, kappa=[1.0, 2.0, 3.0]),
+               dict(order=2, kappa=[50.0, 0.0])):
+        rc, _ = smf.smf_setup(kw["order"], 16, 32, 15, kappa=kw["kappa"], flags=smf.SMF_FP64 | smf.SMF_GREEN)
+        assert rc == smf.SMF_EINVAL, kw

@@ -5,7 +5,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["api.hip", "setup.hip", "sample.hip", "batch.hip", "rings.hip", "measure.hip"]
+SOURCES = ["api.hip", "setup.hip", "sample.hip", "batch.hip", "rings.hip", "rings_fft.hip", "measure.hip"]
 LIB = os.path.join(HERE, "libsmf.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -615,16 +615,66 @@ int smf_setup_rings(const smf_spectrum* spec, int n_theta, const double* z_host,
     int rc = setup_impl(spec, n_theta, z_host, n_phi, flags, st, true, out, rows);
     if (rc != SMF_OK) return rc;
     smf_plan* plan = *out;
-    // rings whose largest odd prime P (of n / 2) is at least SMF_RING_CHIRP_MIN and whose
-    // chirp-z length fits take the chirp-z pass in a launch of their own
+    // Transform class of each ring (h = n / 2):
+    //  - h a power of two L with 2^kRingFftMinLog2 <= L <= 2^kRingFftMaxLog2: radix-8 passes;
+    //  - Bluestein's convolution of length L >= 2h - 1 in the same range, where its estimated
+    //    work (SMF_RING_BLUE_COST L log2 L) is below that of the odd-prime passes, or where the
+    //    largest odd prime would take the chirp-z pass;
+    //  - else rings whose largest odd prime P is at least SMF_RING_CHIRP_MIN and whose chirp-z
+    //    length fits take the chirp-z pass in a launch of their own, the rest direct passes.
     std::vector<int> direct, chirp;
+    std::vector<int> blue[smf::kRingFftClasses], pow2[smf::kRingFftClasses];
     smf::RingSplit rs = {0, 0, 0, 0, 0};
     const int l_cap = fp64 ? smf::kRingChirpMaxL64 : smf::kRingChirpMaxL32;
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, plan->device) != hipSuccess) {
+        smf_destroy(plan);
+        *out = nullptr;
+        return SMF_EHIP;
+    }
+    auto fft_class_fits = [&](int log2l) {
+        return log2l >= smf::kRingFftMinLog2 && log2l <= smf::kRingFftMaxLog2 &&
+               smf::ring_fft_lds_bytes(log2l, plan->g.m_top, fp64) <= (size_t)lds_max;
+    };
+    // lane-operations of the odd-prime passes of the general kernel: 4 h p for the largest
+    // prime (paired inputs and outputs), 10 h p for each further one
+    auto odd_pass_work = [](int h) {
+        int r = h;
+        while ((r & 1) == 0) r >>= 1;
+        std::vector<int> ps;
+        for (int p = 3; r > 1;) {
+            if (p * p > r) p = r;
+            if (r % p) {
+                p += 2;
+                continue;
+            }
+            ps.push_back(p);
+            r /= p;
+        }
+        double w = 0;
+        for (size_t k = 0; k < ps.size(); ++k) w += (k + 1 == ps.size() ? 4.0 : 10.0) * h * ps[k];
+        return w;
+    };
     for (int i = 0; i < n_theta; ++i) {
-        const int P = smf::ring_largest_odd_prime(n_phi_ring[i] / 2);
+        const int h = n_phi_ring[i] / 2;
+        int lh = 0;
+        while ((1 << lh) < h) ++lh;
+        if ((1 << lh) == h && fft_class_fits(lh)) {
+            pow2[lh - smf::kRingFftMinLog2].push_back(i);
+            continue;
+        }
+        const int P = smf::ring_largest_odd_prime(h);
         int L = 1;
         while (L < 2 * P - 1) L <<= 1;
-        if (P >= SMF_RING_CHIRP_MIN && L <= l_cap) {
+        const bool chirped = P >= SMF_RING_CHIRP_MIN && L <= l_cap;
+        int lb = 0;
+        while ((1 << lb) < 2 * h - 1) ++lb;
+        if ((1 << lh) != h && lb >= SMF_RING_BLUE_MIN_LOG2 && fft_class_fits(lb) &&
+            (chirped || SMF_RING_BLUE_COST * (double)(1 << lb) * lb < odd_pass_work(h))) {
+            blue[lb - smf::kRingFftMinLog2].push_back(i);
+            continue;
+        }
+        if (chirped) {
             chirp.push_back(i);
             rs.n_max_chirp = std::max(rs.n_max_chirp, n_phi_ring[i]);
             rs.l_max = std::max(rs.l_max, L);
@@ -646,13 +696,38 @@ int smf_setup_rings(const smf_spectrum* spec, int n_theta, const double* z_host,
     std::stable_sort(chirp.begin(), chirp.end(), [&](int x, int y) { return cost(x, true) > cost(y, true); });
     rs.n_direct = (int)direct.size();
     rs.n_chirp = (int)chirp.size();
-    direct.insert(direct.end(), chirp.begin(), chirp.end());
+    // the launch order of the ring list, and the distinct Bluestein half-lengths of each L
+    std::vector<int> order;
+    std::vector<int> spec_h;          // by class, largest L first
+    std::vector<int64_t> spec_at;     // offset of each one's transform
+    int spec_n[smf::kRingFftClasses] = {0};
+    std::vector<int64_t> spec_off((size_t)n_theta, 0);
+    int64_t spec_total = 0;
+    for (int c = smf::kRingFftClasses - 1; c >= 0; --c) {
+        rs.n_blue[c] = (int)blue[c].size();
+        // rings of the same length next to each other, longest first
+        std::stable_sort(blue[c].begin(), blue[c].end(), [&](int x, int y) { return n_phi_ring[x] > n_phi_ring[y]; });
+        for (int i : blue[c]) {
+            const int h = n_phi_ring[i] / 2;
+            if (spec_n[c] == 0 || spec_h.back() != h) {
+                spec_h.push_back(h);
+                spec_at.push_back(spec_total);
+                spec_total += (int64_t)1 << (smf::kRingFftMinLog2 + c);
+                ++spec_n[c];
+            }
+            spec_off[i] = spec_at.back();
+            order.push_back(i);
+        }
+    }
+    for (int c = smf::kRingFftClasses - 1; c >= 0; --c) {
+        rs.n_pow2[c] = (int)pow2[c].size();
+        order.insert(order.end(), pow2[c].begin(), pow2[c].end());
+    }
+    order.insert(order.end(), direct.begin(), direct.end());
+    order.insert(order.end(), chirp.begin(), chirp.end());
     plan->ring_split = rs;
-    int lds_max = 0;
-    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, plan->device) != hipSuccess)
-        rc = SMF_EHIP;
-    else if (smf::ring_lds_bytes(rs.n_max_direct, plan->g.m_top, fp64) > (size_t)lds_max ||
-             smf::ring_lds_bytes(rs.n_max_chirp, plan->g.m_top, fp64, rs.l_max) > (size_t)lds_max)
+    if (smf::ring_lds_bytes(rs.n_max_direct, plan->g.m_top, fp64) > (size_t)lds_max ||
+        smf::ring_lds_bytes(rs.n_max_chirp, plan->g.m_top, fp64, rs.l_max) > (size_t)lds_max)
         rc = SMF_EINVAL;
     plan->n_ring_max = n_max;
     plan->ring_off = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n_theta + 1));
@@ -671,10 +746,55 @@ int smf_setup_rings(const smf_spectrum* spec, int n_theta, const double* z_host,
          hipMemcpyAsync(plan->phi0_dev, phi0, sizeof(double) * n_theta, hipMemcpyHostToDevice, st) != hipSuccess ||
          hipMemcpyAsync(plan->ring_off_dev, plan->ring_off, sizeof(int64_t) * ((size_t)n_theta + 1),
                         hipMemcpyHostToDevice, st) != hipSuccess ||
-         hipMemcpyAsync(plan->ring_list_dev, direct.data(), sizeof(int) * n_theta, hipMemcpyHostToDevice, st) !=
+         hipMemcpyAsync(plan->ring_list_dev, order.data(), sizeof(int) * n_theta, hipMemcpyHostToDevice, st) !=
              hipSuccess ||
          hipStreamSynchronize(st) != hipSuccess))
         rc = SMF_EHIP;
+    // the power-of-two transform tables and the Bluestein kernels' transforms
+    if (rc == SMF_OK && smf::ring_fft_count(rs) > 0) {
+        const size_t cx = fp64 ? 16 : 8;
+        int* hs_dev = nullptr;
+        int64_t* at_dev = nullptr;
+        if (dev_malloc((void**)&plan->ring_tw64, 16 * (size_t)smf::ring_tw_entries()) != hipSuccess ||
+            (!fp64 && dev_malloc((void**)&plan->ring_tw32, 8 * (size_t)smf::ring_tw_entries()) != hipSuccess) ||
+            dev_malloc((void**)&plan->ring_spec_off_dev, sizeof(int64_t) * n_theta) != hipSuccess ||
+            (spec_total > 0 && (dev_malloc(&plan->ring_spec_dev, cx * (size_t)spec_total) != hipSuccess ||
+                                dev_malloc((void**)&hs_dev, sizeof(int) * spec_h.size()) != hipSuccess ||
+                                dev_malloc((void**)&at_dev, sizeof(int64_t) * spec_at.size()) != hipSuccess)))
+            rc = SMF_ENOMEM;
+        if (rc == SMF_OK &&
+            (smf::launch_ring_tw(plan->ring_tw64, plan->ring_tw32, st) != hipSuccess ||
+             hipMemcpyAsync(plan->ring_spec_off_dev, spec_off.data(), sizeof(int64_t) * n_theta,
+                            hipMemcpyHostToDevice, st) != hipSuccess))
+            rc = SMF_EHIP;
+        if (rc == SMF_OK && spec_total > 0) {
+            if (hipMemcpyAsync(hs_dev, spec_h.data(), sizeof(int) * spec_h.size(), hipMemcpyHostToDevice, st) !=
+                    hipSuccess ||
+                hipMemcpyAsync(at_dev, spec_at.data(), sizeof(int64_t) * spec_at.size(), hipMemcpyHostToDevice,
+                               st) != hipSuccess)
+                rc = SMF_EHIP;
+            int first = 0;
+            for (int c = smf::kRingFftClasses - 1; c >= 0 && rc == SMF_OK; --c) {
+                if (smf::launch_ring_spectra(smf::kRingFftMinLog2 + c, spec_n[c], hs_dev + first, at_dev + first,
+                                             plan->ring_tw64, fp64, plan->ring_spec_dev, st) != hipSuccess)
+                    rc = SMF_EHIP;
+                first += spec_n[c];
+            }
+        }
+        if (hipStreamSynchronize(st) != hipSuccess && rc == SMF_OK) rc = SMF_EHIP;
+        if (hs_dev) (void)hipFree(hs_dev);
+        if (at_dev) (void)hipFree(at_dev);
+    }
+    // streams (default priority) and events over which a synthesis of several launches spreads
+    int units = rs.n_direct + rs.n_chirp > 0 ? 1 : 0;
+    for (int c = 0; c < smf::kRingFftClasses; ++c) units += (rs.n_blue[c] > 0) + (rs.n_pow2[c] > 0);
+    if (rc == SMF_OK && units > 1) {
+        if (hipEventCreateWithFlags(&plan->ring_fork, hipEventDisableTiming) != hipSuccess) rc = SMF_EHIP;
+        for (int j = 0; j < smf::kRingAuxStreams && rc == SMF_OK; ++j)
+            if (hipStreamCreateWithFlags(&plan->ring_aux[j], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&plan->ring_join[j], hipEventDisableTiming) != hipSuccess)
+                rc = SMF_EHIP;
+    }
     if (rc != SMF_OK) {
         smf_destroy(plan);
         *out = nullptr;
@@ -697,11 +817,61 @@ static int synthesize_rings(const smf_plan* plan, int count, const void* g_dev, 
     if (!g_dev || !out_dev) return SMF_EINVAL;
     DeviceGuard dg(plan->device);
     const Geometry& g = plan->g;
-    return smf::launch_ring_c2r(g.n_theta, g.m_top, g.n_phi / 2, plan->ring_off[g.n_theta], plan->ring_split,
-                                plan->flags == SMF_FP64, count, g_dev, plan->ring_list_dev, plan->n_ring_dev,
-                                plan->phi0_dev, plan->ring_off_dev, out_dev, ln, (hipStream_t)hip_stream) == hipSuccess
-               ? SMF_OK
-               : SMF_EHIP;
+    const smf::RingSplit& rs = plan->ring_split;
+    const bool fp64 = plan->flags == SMF_FP64;
+    const hipStream_t st = (hipStream_t)hip_stream;
+    const void* tw = fp64 ? (const void*)plan->ring_tw64 : (const void*)plan->ring_tw32;
+    // the launches: each class of rings_fft.hip (list order), then the general kernel's pair
+    struct Unit {
+        bool blue;
+        int log2l, rings, first;
+    };
+    std::vector<Unit> fft;
+    int first = 0;
+    for (int c = smf::kRingFftClasses - 1; c >= 0; --c) {
+        if (rs.n_blue[c]) fft.push_back({true, smf::kRingFftMinLog2 + c, rs.n_blue[c], first});
+        first += rs.n_blue[c];
+    }
+    for (int c = smf::kRingFftClasses - 1; c >= 0; --c) {
+        if (rs.n_pow2[c]) fft.push_back({false, smf::kRingFftMinLog2 + c, rs.n_pow2[c], first});
+        first += rs.n_pow2[c];
+    }
+    const bool general = rs.n_direct + rs.n_chirp > 0;
+    const bool fork = plan->ring_aux[0] != nullptr && fft.size() + (general ? 1 : 0) > 1;
+    // with several launches the general kernel's pair stays on the caller's stream and the
+    // classes go round robin to the plan's other streams, forked from and joined back to it by
+    // events; the lock keeps one call's fork, launches and join together
+    static std::mutex fork_mu;
+    std::unique_lock<std::mutex> lock(fork_mu, std::defer_lock);
+    if (fork) {
+        lock.lock();
+        if (hipEventRecord(plan->ring_fork, st) != hipSuccess) return SMF_EHIP;
+        for (int j = 0; j < smf::kRingAuxStreams; ++j)
+            if (hipStreamWaitEvent(plan->ring_aux[j], plan->ring_fork, 0) != hipSuccess) return SMF_EHIP;
+    }
+    int rc = SMF_OK;
+    for (size_t u = 0; u < fft.size() && rc == SMF_OK; ++u) {
+        const hipStream_t su = fork ? plan->ring_aux[u % smf::kRingAuxStreams] : st;
+        if (smf::launch_ring_fft_class(fft[u].blue, fft[u].log2l, fft[u].rings, g.n_theta, g.m_top, g.n_phi / 2,
+                                       plan->ring_off[g.n_theta], fp64, count, g_dev,
+                                       plan->ring_list_dev + fft[u].first, plan->n_ring_dev, plan->phi0_dev,
+                                       plan->ring_off_dev, tw, plan->ring_spec_dev, plan->ring_spec_off_dev, out_dev,
+                                       ln, su) != hipSuccess)
+            rc = SMF_EHIP;
+    }
+    if (rc == SMF_OK && general &&
+        smf::launch_ring_c2r(g.n_theta, g.m_top, g.n_phi / 2, plan->ring_off[g.n_theta], rs, fp64, count, g_dev,
+                             plan->ring_list_dev + first, plan->n_ring_dev, plan->phi0_dev, plan->ring_off_dev,
+                             out_dev, ln, st) != hipSuccess)
+        rc = SMF_EHIP;
+    if (fork) {
+        // the join, also after a failed launch, so that no stream is left forked
+        for (int j = 0; j < smf::kRingAuxStreams; ++j)
+            if (hipEventRecord(plan->ring_join[j], plan->ring_aux[j]) != hipSuccess ||
+                hipStreamWaitEvent(st, plan->ring_join[j], 0) != hipSuccess)
+                rc = SMF_EHIP;
+    }
+    return rc;
 }
 
 static int sample_rings(const smf_plan* plan, uint64_t seed, int count, void* g_work, void* out_dev,
@@ -804,6 +974,15 @@ int smf_destroy(smf_plan* plan)
     if (plan->phi0_dev) (void)hipFree(plan->phi0_dev);
     if (plan->ring_off_dev) (void)hipFree(plan->ring_off_dev);
     if (plan->ring_list_dev) (void)hipFree(plan->ring_list_dev);
+    if (plan->ring_tw64) (void)hipFree(plan->ring_tw64);
+    if (plan->ring_tw32) (void)hipFree(plan->ring_tw32);
+    if (plan->ring_spec_dev) (void)hipFree(plan->ring_spec_dev);
+    if (plan->ring_spec_off_dev) (void)hipFree(plan->ring_spec_off_dev);
+    for (int j = 0; j < smf::kRingAuxStreams; ++j) {
+        if (plan->ring_aux[j]) (void)hipStreamDestroy(plan->ring_aux[j]);
+        if (plan->ring_join[j]) (void)hipEventDestroy(plan->ring_join[j]);
+    }
+    if (plan->ring_fork) (void)hipEventDestroy(plan->ring_fork);
     free(plan->ring_off);
     free(plan);
     return SMF_OK;

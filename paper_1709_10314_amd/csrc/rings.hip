@@ -484,7 +484,7 @@ hipError_t launch_ring_c2r(int n_theta, int m_top, int g_row, int64_t total, con
                            int count, const void* g, const int* list, const int* n_ring, const double* phi0,
                            const int64_t* off, void* out, const LognormalMap* ln, hipStream_t st)
 {
-    if (count <= 0 || count > 65535 || n_theta <= 0 || rs.n_direct + rs.n_chirp != n_theta) return hipErrorInvalidValue;
+    if (count <= 0 || count > 65535 || n_theta <= 0 || rs.n_direct + rs.n_chirp > n_theta) return hipErrorInvalidValue;
     const RingArgs a = {n_theta, m_top, g_row, total, list};
     if (fp64)
         return launch_ring_pair<double>(a, rs, count, (const double*)g, n_ring, phi0, off, (double*)out, ln, st);

@@ -133,13 +133,49 @@ constexpr int kRingMaxCount = 65535;     // fields of one call (grid y)
 #ifndef SMF_RING_CHIRP_MIN
 #define SMF_RING_CHIRP_MIN 383
 #endif
+// Lane-operations per L log2 L of a Bluestein ring transform of length L (two transforms of
+// length L and the product with the kernel's transform), for the choice of its class
+// (measured on HEALPix nside 1024 x 8 fields: synthesis 0.476 ms at 6, 0.492 at 16, 0.516 at 24)
+#ifndef SMF_RING_BLUE_COST
+#define SMF_RING_BLUE_COST 6.0
+#endif
+// Smallest Bluestein length (log2)
+#ifndef SMF_RING_BLUE_MIN_LOG2
+#define SMF_RING_BLUE_MIN_LOG2 10
+#endif
 constexpr int kRingChirpMaxL32 = 4096;   // largest chirp-z length (LDS)
 constexpr int kRingChirpMaxL64 = 2048;
+// Rings whose half-length h is a power of two L, or whose whole length-h DFT goes through
+// Bluestein's convolution of power-of-two length L >= 2h - 1, with 2^kRingFftMinLog2 <= L <=
+// 2^kRingFftMaxLog2, take a launch per class and L (rings_fft.hip) ahead of the two above.
+constexpr int kRingFftMinLog2 = 10;
+constexpr int kRingFftMaxLog2 = 12;
+constexpr int kRingFftClasses = kRingFftMaxLog2 - kRingFftMinLog2 + 1;
 struct RingSplit {
     int n_direct, n_chirp;            // rings of each launch
     int n_max_direct, n_max_chirp;    // largest ring of each
     int l_max;                        // largest chirp-z length
+    int n_blue[kRingFftClasses];      // Bluestein rings by L = 2^(kRingFftMinLog2 + c)
+    int n_pow2[kRingFftClasses];      // rings with h = L
 };
+// Ring list order: Bluestein rings (largest L first), power-of-two rings (largest first),
+// then the n_direct and n_chirp rings of launch_ring_c2r.
+int ring_fft_count(const RingSplit& rs);
+int ring_tw_entries();                                     // complex entries of the tables
+size_t ring_fft_lds_bytes(int log2l, int m_top, bool fp64);
+hipError_t launch_ring_tw(double* tw64, float* tw32, hipStream_t st);
+// hs_dev[w]: half-lengths h whose Bluestein length is 2^log2l; the transform of each one's
+// kernel goes to out (plan type) at offs_dev[w] values
+hipError_t launch_ring_spectra(int log2l, int lengths, const int* hs_dev, const int64_t* offs_dev,
+                               const double* tw64, bool fp64, void* out, hipStream_t st);
+// One launch of the class (Bluestein or power-of-two) of length 2^log2l: `rings` rings from list.
+hipError_t launch_ring_fft_class(bool blue, int log2l, int rings, int n_theta, int m_top, int g_row, int64_t total,
+                                 bool fp64, int count, const void* g, const int* list, const int* n_ring,
+                                 const double* phi0, const int64_t* off, const void* tw, const void* spec,
+                                 const int64_t* spec_off, void* out, const LognormalMap* ln, hipStream_t st);
+// Streams besides the caller's that a ring plan's synthesis spreads its launches over (forked
+// from and joined back to the caller's stream by events)
+constexpr int kRingAuxStreams = 3;
 size_t ring_lds_bytes(int n_max, int m_top, bool fp64, int l_max = 0);
 int ring_largest_odd_prime(int h);    // 1 when h is a power of two
 hipError_t launch_ring_c2r(int n_theta, int m_top, int g_row, int64_t total, const RingSplit& rs, bool fp64,
@@ -176,6 +212,13 @@ struct smf_plan {
     int64_t* ring_off_dev;    // [n_theta + 1] start of each ring in a field
     int64_t* ring_off;        // host copy
     int n_ring_max;           // largest ring
-    int* ring_list_dev;       // [n_theta] rings by launch (direct, then chirp-z)
+    int* ring_list_dev;       // [n_theta] rings by launch (see RingSplit)
     smf::RingSplit ring_split;
+    double* ring_tw64;        // power-of-two transform tables (ring_tw_entries complex values)
+    float* ring_tw32;         // the same rounded to FP32 (FP32 plans)
+    void* ring_spec_dev;      // transforms of Bluestein's kernels, one per half-length, plan type
+    int64_t* ring_spec_off_dev;   // [n_theta] each ring's transform (in complex values)
+    hipStream_t ring_aux[smf::kRingAuxStreams];   // null when the synthesis is a single launch
+    hipEvent_t ring_fork;
+    hipEvent_t ring_join[smf::kRingAuxStreams];
 };

@@ -49,6 +49,9 @@ CASES = {
          dict(n_theta=33, n_phi=64, order=2, kappa=[40.0, 40.0], ell_max=32)]),
     "setup-rings": lambda smf: smf.smf_setup_rings(2, np.array([4, 8, 8, 4], dtype=np.int32),
                                                    np.zeros(4), 5, kappa=[30.0, 30.0], flags=smf.SMF_FP64),
+    # rings of the power-of-two and Bluestein transform classes (their tables and kernels' transforms)
+    "setup-rings-classes": lambda smf: smf.smf_setup_rings(1, np.array([1024, 2042, 2042, 1024], dtype=np.int32),
+                                                           np.zeros(4), 5, kappa=[30.0], flags=smf.SMF_FP32),
 }
 
 

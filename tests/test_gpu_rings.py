@@ -106,6 +106,37 @@ def test_largest_rings_and_all_modes(precision, n_max):
     plan.close()
 
 
+# Ring lengths of the power-of-two and Bluestein transform classes: n / 2 a power of two from
+# 512 to 4096, and n / 2 with a large odd prime (even and odd half-lengths, Bluestein lengths
+# 512 to 4096), next to lengths the general kernel keeps; ell_max = 3071 makes the modes
+# alias on the rings shorter than 3072 pixels.
+CLASS_RINGS = [1024, 2048, 4096, 8192, 2 * 257, 2 * 683, 2 * 1018, 2 * 1021, 2 * 1535, 2 * 2047, 2 * 1536, 2 * 750]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_power_of_two_and_bluestein_ring_classes(precision):
+    n_max = 8192 if precision == "fp32" else 4096
+    n_ring = np.array([n for n in CLASS_RINGS if n <= n_max], dtype=np.int32)
+    phi0 = np.random.default_rng(3).uniform(0, 2 * np.pi, len(n_ring))
+    phi0[0] = 0.0
+    phi0[1] = np.pi / n_ring[1]
+    plan = _ring_plan(n_ring, phi0, 3071, precision)
+    count = 2
+    gdev, g = _modes(plan, count, seed=29)
+    T = plan.synthesize_rings(gdev, count)
+    torch.cuda.synchronize()
+    To = oracle.dft_rings(g, n_ring, phi0)
+    _check(f"ring classes {precision}", T.double().cpu().numpy(), To, plan.offsets, TOL[precision])
+    # the lognormal map as these kernels store the pixels: exp(0.1 + 0.5 T) of the same seed's field
+    Tg = plan.sample_rings(4, count).double().cpu().numpy()
+    Tl = plan.sample_rings_lognormal(4, count, 0.1, 0.5).double().cpu().numpy()
+    torch.cuda.synchronize()
+    el = rel_rms(Tl, np.exp(0.1 + 0.5 * Tg))
+    log(f"ring classes {precision}: lognormal map rel RMS {el:.3e}")
+    assert el <= (1e-13 if precision == "fp64" else 1e-6)
+    plan.close()
+
+
 # (nside, order, kappa_i, ell_max, factors).  Order 1 at ell_max = 3 nside - 1 (modes alias
 # on every ring, the belt's n / 2 being 2 nside); order 2 on the plan's own factors keeps
 # m_top near n_theta / 2 (higher modes are evanescent at the polar rings, where pivots sit
@@ -398,8 +429,11 @@ def test_largest_healpix_plans_sampled_rings(precision, nside):
     T = plan.synthesize_rings(g, 1)
     torch.cuda.synchronize()
     n = len(z)
-    picks = [0, 1, 2, nside // 2 - 1, 1020, nside - 2, nside - 1, nside, 2 * nside - 1, 2 * nside, 3 * nside,
-             n - 1021, n - 2, n - 1]
+    # polar ring i holds 4 (i + 1) pixels: half-lengths 2 (i + 1) that are powers of two (i = 255,
+    # 511, 1023), that have a large odd prime (256: 257, 508: 509, 682: 683, 1020: 1021), or
+    # small ones only (767: 3 x 256)
+    picks = [0, 1, 2, nside // 2 - 1, 255, 256, 508, 511, 682, 767, 1020, 1023, nside - 2, nside - 1, nside,
+             2 * nside - 1, 2 * nside, 3 * nside, n - 1021, n - 257, n - 2, n - 1]
     picks = sorted({i for i in picks if 0 <= i < n})
     gs = g[0, picks].double().cpu().numpy()[:, : lmax + 1]
     gs = (gs[..., 0] + 1j * gs[..., 1])[None]

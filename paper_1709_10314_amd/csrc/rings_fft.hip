@@ -42,6 +42,19 @@ __device__ __forceinline__ Cx<T> ring_tw_n(const Cx<T>* Et, const Cx<T>* Ft, int
 template <typename T>
 __device__ __forceinline__ Cx<T> conj_c(Cx<T> a) { return {a.re, -a.im}; }
 
+// x mod n for 0 <= x < 2^22 and 0 < n < 2^13: the quotient from a float product is off by at
+// most one, which the remainder's range check corrects.
+__device__ __forceinline__ int mod_small(int x, int n, float inv_n)
+{
+    const int q = (int)((float)x * inv_n);
+    int r = x - q * n;
+    if (r < 0)
+        r += n;
+    else if (r >= n)
+        r -= n;
+    return r;
+}
+
 // ---- register-resident radix-16 form (L = 256 R3, R3 = 4, 8, 16; NT = L / 16 threads) ----
 // Thread t holds x_{t + NT r} (r < 16) in registers: pass 1 (radix 16, Ns = 1) takes them
 // straight from the split, pass 2 (radix 16, Ns = 16) goes through LDS, pass 3 (radix R3,
@@ -108,8 +121,10 @@ __device__ __forceinline__ void r16_pass3(const Cx<T>* buf, const Cx<T>* __restr
 // launch's list, blockIdx.y is the field.  BLUE: the Bluestein form (h <= L / 2); otherwise
 // h = L.  Thread t folds bins k = t + NT r with the phase e^{i k phi0} factored out:
 // B_k = e^{i k phi0} (U_k + conj X_k), U_k = sum_p g_{k+pn} E^p, X_k = sum_p g_{n-k+pn} E^{p+1},
-// E = e^{i n phi0}.  LDS: the buffer, e^{i NT r phi0} (r < 16) and E in FP64, B_h, and for the
-// Bluestein form e^{2 pi i b / n}, e^{2 pi i 64 a / n} in the type.
+// E = e^{i n phi0}, and e^{i k phi0} = e^{i (t mod 16) phi0} e^{i 16 (t / 16) phi0} e^{i NT r phi0},
+// three table values (FP64 sincos, rounded to the type once) multiplied in the type.  LDS: the
+// buffer, the phase tables (16 values each, then E and e^{i h phi0}), B_h, and for the Bluestein
+// form e^{2 pi i b / n}, e^{2 pi i 64 a / n} in the type.
 template <typename T, int LOG2L, bool BLUE>
 __global__ __launch_bounds__((1 << LOG2L) / 16) void ring_r16_kernel(RingFftArgs a, const T* __restrict__ g,
                                                                      const int* __restrict__ n_ring,
@@ -133,8 +148,9 @@ __global__ __launch_bounds__((1 << LOG2L) / 16) void ring_r16_kernel(RingFftArgs
     const int mt = a.m_top;
     const Cx<T>* tw = tw_all + ring_tw_base(LOG2L);
     Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem_raw);
-    Cx<double>* Sr = reinterpret_cast<Cx<double>*>(buf + lds_slots(L));
-    Cx<T>* Bh = reinterpret_cast<Cx<T>*>(Sr + 17);
+    Cx<T>* Ph = buf + lds_slots(L);   // [0, 16): e^{i b phi0}; [16, 32): e^{i 16 b phi0};
+                                      // [32, 48): e^{i NT b phi0}; 48: E; 49: e^{i h phi0}
+    Cx<T>* Bh = Ph + 50;
     Cx<T>* Et = Bh + 2;
     Cx<T>* Ft = Et + 64;
     const int na = n / 64 + 1;
@@ -157,26 +173,30 @@ __global__ __launch_bounds__((1 << LOG2L) / 16) void ring_r16_kernel(RingFftArgs
             xb[r] = (k < h && mk <= mt) ? gv[mk] : zero2;
         }
     }
-    const int ntab = 17 + (BLUE ? 64 + na : 0);
-    for (int e = t; e < ntab; e += NT) {
+    const bool phased = p0 != 0.0;   // uniform: rings starting at longitude 0 need no phases
+    const int ntab = (phased ? 50 : 0) + (BLUE ? 64 + na : 0);
+    for (int e0 = t; e0 < ntab; e0 += NT) {
         double sn, cs;
-        if (e < 17) {
-            sincos((double)(e < 16 ? NT * e : n) * p0, &sn, &cs);
-            Sr[e] = {cs, sn};
-        } else if (e < 17 + 64) {
-            sincospi(2.0 * (double)(e - 17) / (double)n, &sn, &cs);
-            Et[e - 17] = {(T)cs, (T)sn};
+        const int e = phased ? e0 : e0 + 50;
+        if (e < 50) {
+            const int a = e & 15, sel = e >> 4;
+            const double m = sel == 0 ? a : sel == 1 ? 16.0 * a : sel == 2 ? (double)NT * a : e == 48 ? n : h;
+            sincos(m * p0, &sn, &cs);
+            Ph[e] = {(T)cs, (T)sn};
+        } else if (e < 50 + 64) {
+            sincospi(2.0 * (double)(e - 50) / (double)n, &sn, &cs);
+            Et[e - 50] = {(T)cs, (T)sn};
         } else {
-            sincospi(128.0 * (double)(e - 81) / (double)n, &sn, &cs);
-            Ft[e - 81] = {(T)cs, (T)sn};
+            sincospi(128.0 * (double)(e - 114) / (double)n, &sn, &cs);
+            Ft[e - 114] = {(T)cs, (T)sn};
         }
     }
-    double bs, bc;
-    sincos((double)t * p0, &bs, &bc);   // e^{i t phi0}
     __syncthreads();
-    const Cx<T> En = {(T)Sr[16].re, (T)Sr[16].im};
-    const Cx<double> base = {bc, bs};
-    auto chirp = [&](int k) { return ring_tw_n(Et, Ft, (int)(((int64_t)k * k) % n)); };
+    const Cx<T> one = {T(1), T(0)};
+    const Cx<T> En = phased ? Ph[48] : one;
+    const Cx<T> base = phased ? cmul(Ph[t & 15], Ph[16 + (t >> 4)]) : one;   // e^{i t phi0}
+    const float inv_n = 1.0f / (float)n;
+    auto chirp = [&](int k) { return ring_tw_n(Et, Ft, mod_small(k * k, n, inv_n)); };
 
     // fold, one period of the modes at a time over all of this thread's bins (so that a
     // period's loads are in flight together): Y_k = U_k + conj X_k, then B_k = e^{i k phi0} Y_k,
@@ -217,16 +237,11 @@ __global__ __launch_bounds__((1 << LOG2L) / 16) void ring_r16_kernel(RingFftArgs
     for (int r = 0; r < RB; ++r) {
         const int k = t + NT * r;
         if (k < h) {
-            const Cx<double> ph = cmul(base, Sr[r]);
-            v[r] = cmul(Cx<T>{(T)ph.re, (T)ph.im}, v[r]);
+            if (phased) v[r] = cmul(cmul(base, Ph[32 + r]), v[r]);
             buf[lds_slot(k)] = v[r];
         }
     }
-    if (t == 0) {
-        double sn, cs;
-        sincos((double)h * p0, &sn, &cs);
-        Bh[0] = cmul(Cx<T>{(T)cs, (T)sn}, cadd(uh, conj_c(cmul(uh, En))));
-    }
+    if (t == 0) Bh[0] = cmul(phased ? Ph[49] : one, cadd(uh, conj_c(cmul(uh, En))));
     __syncthreads();
     // split: Z_k = (B_k + conj B_{h-k}) + i w^k (B_k - conj B_{h-k}), w = e^{2 pi i / n}
 #pragma unroll
@@ -340,7 +355,7 @@ size_t r16_kernel_lds(int log2l, bool fp64)
 {
     const size_t cx = fp64 ? 16 : 8;
     const int na = (1 << log2l) / 64 + 1;   // n <= L for the Bluestein form
-    return cx * ((size_t)lds_slots(1 << log2l) + 2 + 64 + (size_t)na) + 16 * 17;
+    return cx * ((size_t)lds_slots(1 << log2l) + 50 + 2 + 64 + (size_t)na);
 }
 
 template <typename T, int LOG2L, bool BLUE>

@@ -837,7 +837,7 @@ static int synthesize_rings(const smf_plan* plan, int count, const void* g_dev, 
         first += rs.n_pow2[c];
     }
     const bool general = rs.n_direct + rs.n_chirp > 0;
-    const bool fork = plan->ring_aux[0] != nullptr && fft.size() + (general ? 1 : 0) > 1;
+    const bool fork = SMF_RING_FORK && plan->ring_aux[0] != nullptr && fft.size() + (general ? 1 : 0) > 1;
     // with several launches the general kernel's pair stays on the caller's stream and the
     // classes go round robin to the plan's other streams, forked from and joined back to it by
     // events; the lock keeps one call's fork, launches and join together

@@ -23,6 +23,30 @@ struct RingArgs {
 
 constexpr int kRingThreads = 256;
 
+template <typename T>
+__device__ __forceinline__ Cx<T> conj_c(Cx<T> a) { return {a.re, -a.im}; }
+
+// q = x / d and r = x - q d for 0 <= x < 2^24, 0 < d, x / d < 2^22, from a float product with the
+// reciprocal (off by at most one, which the remainder's range check corrects).
+struct FastDiv {
+    int d;
+    float inv;
+};
+__device__ __forceinline__ FastDiv fast_div(int d) { return {d, 1.0f / (float)d}; }
+__device__ __forceinline__ int fdiv(int x, FastDiv f, int& r)
+{
+    int q = (int)((float)x * f.inv);
+    r = x - q * f.d;
+    if (r < 0) {
+        --q;
+        r += f.d;
+    } else if (r >= f.d) {
+        ++q;
+        r -= f.d;
+    }
+    return q;
+}
+
 // Re-anchoring interval of the twiddle recurrence of the direct passes.
 constexpr int kRingAnchor = 16;
 // Bins per thread whose first-period modes are loaded ahead of the table work.
@@ -128,9 +152,9 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
     const int mt = a.m_top;
     Cx<T>* buf0 = reinterpret_cast<Cx<T>*>(smem_raw);
     Cx<T>* buf1 = buf0 + (h + 1);
-    // small FP64 tables: E_b = e^{2 pi i b / n}, F_a = e^{2 pi i 64 a / n}, G_b = e^{i b phi0},
-    // H_a = e^{i 64 a phi0} (b < 64); a mode's phase is the product of one H and one G,
-    // rounded once; Et, Ft: E and F rounded to the type, whose products are the twiddles
+    // small tables from FP64 sincos, rounded to the type: Et_b = e^{2 pi i b / n},
+    // Ft_a = e^{2 pi i 64 a / n} (twiddles Ft Et), Gt_b = e^{i b phi0}, Ht_a = e^{i 64 a phi0}
+    // (b < 64; a mode's phase is Ht Gt); laid out in an FP64-sized region E, F, G, H
     Cx<double>* E = reinterpret_cast<Cx<double>*>(buf1 + (h + 1));
     const int na = n / 64 + 1;
     const int ma = mt / 64 + 1;
@@ -140,7 +164,10 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
     Cx<T>* Et = reinterpret_cast<Cx<T>*>(H + ma);
     Cx<T>* Ft = Et + 64;
     Cx<T>* part = Ft + na;   // partial sums of the fold, kRingThreads values
+    Cx<T>* Gt = reinterpret_cast<Cx<T>*>(G);
+    Cx<T>* Ht = Gt + 64;
     const double p0 = phi0[i];
+    const bool phased = p0 != 0.0;   // uniform: rings starting at longitude 0 need no phases
 
     // the modes of the first period of this thread's first kRingPre bins (m = k and m = n - k),
     // loaded before the tables are built so that their latency overlaps that work
@@ -160,7 +187,7 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
         }
     }
 
-    for (int k = tid; k < 128 + na + ma; k += kRingThreads) {
+    for (int k = tid; k < (phased ? 128 + na + ma : 64 + na); k += kRingThreads) {
         double s, c;
         if (k < 64)
             sincospi(2.0 * (double)k / (double)n, &s, &c);
@@ -170,51 +197,57 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
             sincos((double)(k - 64 - na) * p0, &s, &c);
         else
             sincos((double)(64 * (k - 128 - na)) * p0, &s, &c);
-        E[k] = {c, s};
-        if (k < 64 + na) Et[k] = {(T)c, (T)s};
+        if (k < 64 + na)
+            Et[k] = {(T)c, (T)s};
+        else
+            Gt[k - 64 - na] = {(T)c, (T)s};   // Gt then Ht
     }
     __syncthreads();
 
     // fold: B_k = sum_{m = k mod n} c_m + sum_{m = -k mod n, m >= 1} conj(c_m),  k <= h.
     // A ring with at most kRingThreads / 2 bins gives each bin `gs` threads, which sum every
     // gs-th period of its modes; the partial sums are added in a fixed order.
-    auto phase = [&](int m) {
-        const Cx<double> w = cmul(H[m >> 6], G[m & 63]);
-        return Cx<T>{(T)w.re, (T)w.im};
+    // c_m = g_m e^{i m phi0}
+    auto cph = [&](int m, V2 x) {
+        const Cx<T> v = {x.x, x.y};
+        return phased ? cmul(v, cmul(Ht[m >> 6], Gt[m & 63])) : v;
     };
+    const V2 zero2 = {T(0), T(0)};
     auto fold_bin = [&](int k, int g0) {
         Cx<T> acc = {T(0), T(0)};
-#pragma unroll 2
-        for (int m = k + g0 * n; m <= mt; m += gs * n)
-            acc = cadd(acc, cmul(Cx<T>{gr[2 * m], gr[2 * m + 1]}, phase(m)));
-#pragma unroll 2
-        for (int m = (k == 0 ? n : n - k) + g0 * n; m <= mt; m += gs * n) {
-            const Cx<T> cm = cmul(Cx<T>{gr[2 * m], gr[2 * m + 1]}, phase(m));
-            acc = cadd(acc, Cx<T>{cm.re, -cm.im});
-        }
+#pragma unroll 4
+        for (int m = k + g0 * n; m <= mt; m += gs * n) acc = cadd(acc, cph(m, gv[m]));
+#pragma unroll 4
+        for (int m = (k == 0 ? n : n - k) + g0 * n; m <= mt; m += gs * n) acc = cadd(acc, conj_c(cph(m, gv[m])));
         return acc;
     };
     if (gs == 1) {
-        // bins from the prefetched first period, then any further periods (modes above n)
+        // bins from the prefetched first period, then the further periods (modes above n), one
+        // period at a time over this thread's bins so that a period's loads are in flight together
+        Cx<T> acc[kRingPre];
 #pragma unroll
         for (int r = 0; r < kRingPre; ++r) {
             const int k = tid + r * kRingThreads;
-            if (k < nb) {
-                const int mn = k == 0 ? n : n - k;
-                Cx<T> acc = {T(0), T(0)};
-                if (k <= mt) acc = cmul(Cx<T>{pre_p[r].x, pre_p[r].y}, phase(k));
-                for (int m = k + n; m <= mt; m += n)
-                    acc = cadd(acc, cmul(Cx<T>{gr[2 * m], gr[2 * m + 1]}, phase(m)));
-                if (mn <= mt) {
-                    const Cx<T> cm = cmul(Cx<T>{pre_n[r].x, pre_n[r].y}, phase(mn));
-                    acc = cadd(acc, Cx<T>{cm.re, -cm.im});
-                }
-                for (int m = mn + n; m <= mt; m += n) {
-                    const Cx<T> cm = cmul(Cx<T>{gr[2 * m], gr[2 * m + 1]}, phase(m));
-                    acc = cadd(acc, Cx<T>{cm.re, -cm.im});
-                }
-                buf1[k] = acc;
+            const int mn = k == 0 ? n : n - k;
+            acc[r] = {T(0), T(0)};
+            if (k < nb && k <= mt) acc[r] = cph(k, pre_p[r]);
+            if (k < nb && mn <= mt) acc[r] = cadd(acc[r], conj_c(cph(mn, pre_n[r])));
+        }
+        for (int p = 1; p * n <= mt; ++p) {
+#pragma unroll
+            for (int r = 0; r < kRingPre; ++r) {
+                const int k = tid + r * kRingThreads;
+                const int m1 = k + p * n, m2 = (k == 0 ? n : n - k) + p * n;
+                const V2 x1 = (k < nb && m1 <= mt) ? gv[m1] : zero2;
+                const V2 x2 = (k < nb && m2 <= mt) ? gv[m2] : zero2;
+                if (k < nb && m1 <= mt) acc[r] = cadd(acc[r], cph(m1, x1));
+                if (k < nb && m2 <= mt) acc[r] = cadd(acc[r], conj_c(cph(m2, x2)));
             }
+        }
+#pragma unroll
+        for (int r = 0; r < kRingPre; ++r) {
+            const int k = tid + r * kRingThreads;
+            if (k < nb) buf1[k] = acc[r];
         }
         for (int k = tid + kRingPre * kRingThreads; k < nb; k += kRingThreads) buf1[k] = fold_bin(k, 0);
     } else {
@@ -305,18 +338,22 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
             }
         } else {
             // outputs q and P - q have conjugate twiddles too: one thread makes both
+            const FastDiv fh = fast_div(half), fp = fast_div(P);
             for (int idx = tid; idx < hp * half; idx += kRingThreads) {
-                const int b = idx / half;
-                const int q = idx - b * half;
+                int q;
+                const int b = fdiv(idx, fh, q);
                 const Cx<T> w1 = ring_tw(Et, Ft, q * step);
                 Cx<T> acc = src[b];
                 Cx<T> acc2 = acc;
                 Cx<T> W = w1;
                 for (int t = 1; 2 * t < P; ++t) {
-                    if (t % kRingAnchor == 0)
-                        W = ring_tw(Et, Ft, ((t * q) % P) * step);
-                    else if (t > 1)
+                    if (t % kRingAnchor == 0) {
+                        int tq;
+                        (void)fdiv(t * q, fp, tq);
+                        W = ring_tw(Et, Ft, tq * step);
+                    } else if (t > 1) {
                         W = cmul(W, w1);
+                    }
                     const Cx<T> x = src[b + t * hp], y = src[b + (P - t) * hp];
                     const Cx<T> sp = cadd(x, y), df = csub(x, y);
                     acc.re += sp.re * W.re - df.im * W.im;
@@ -348,18 +385,23 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
         const int NsR = Ns * p;
         const int step = n / NsR;
         const int hp = h / p;
+        const FastDiv fr = fast_div(NsR), fs = fast_div(Ns);
         for (int idx = tid; idx < h; idx += kRingThreads) {
-            const int b = idx / NsR;
-            const int u = idx - b * NsR;
-            const int j = b * Ns + u % Ns;
+            int u, us;
+            const int b = fdiv(idx, fr, u);
+            (void)fdiv(u, fs, us);
+            const int j = b * Ns + us;
             const Cx<T> w1 = ring_tw(Et, Ft, u * step);
             Cx<T> acc = src[j];
             Cx<T> W = w1;
             for (int t = 1; t < p; ++t) {
-                if (t % kRingAnchor == 0)
-                    W = ring_tw(Et, Ft, ((t * u) % NsR) * step);
-                else if (t > 1)
+                if (t % kRingAnchor == 0) {
+                    int tu;
+                    (void)fdiv(t * u, fr, tu);
+                    W = ring_tw(Et, Ft, tu * step);
+                } else if (t > 1) {
                     W = cmul(W, w1);
+                }
                 acc = cadd(acc, cmul(src[j + t * hp], W));
             }
             dst[idx] = acc;
@@ -374,8 +416,10 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
     while (h / Ns >= 4) {
         const int q = h >> 2;
         const int step = n / (4 * Ns);
+        const FastDiv fs = fast_div(Ns);
         for (int j = tid; j < q; j += kRingThreads) {
-            const int kq = j % Ns;
+            int kq;
+            const int jb = fdiv(j, fs, kq);
             // one table twiddle per butterfly; its square and cube by complex multiplies
             const Cx<T> w1 = ring_tw(Et, Ft, kq * step);
             const Cx<T> w2 = cmul(w1, w1);
@@ -385,7 +429,7 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
             v[2] = cmul(src[j + 2 * q], w2);
             v[3] = cmul(src[j + 3 * q], cmul(w1, w2));
             dft_inv<T, 4>(v);
-            const int base = (j / Ns) * 4 * Ns + kq;
+            const int base = jb * 4 * Ns + kq;
 #pragma unroll
             for (int t = 0; t < 4; ++t) dst[base + t * Ns] = v[t];
         }
@@ -398,11 +442,13 @@ __global__ __launch_bounds__(kRingThreads) void ring_c2r_kernel(RingArgs a, cons
     if (h / Ns == 2) {
         const int q = h >> 1;
         const int step = n / (2 * Ns);
+        const FastDiv fs = fast_div(Ns);
         for (int j = tid; j < q; j += kRingThreads) {
-            const int kq = j % Ns;
+            int kq;
+            const int jb = fdiv(j, fs, kq);
             Cx<T> v[2] = {src[j], cmul(src[j + q], ring_tw(Et, Ft, kq * step))};
             dft_inv<T, 2>(v);
-            const int base = (j / Ns) * 2 * Ns + kq;
+            const int base = jb * 2 * Ns + kq;
             dst[base] = v[0];
             dst[base + Ns] = v[1];
         }

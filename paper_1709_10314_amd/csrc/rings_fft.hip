@@ -125,8 +125,23 @@ __device__ __forceinline__ void r16_pass3(const Cx<T>* buf, const Cx<T>* __restr
 // three table values (FP64 sincos, rounded to the type once) multiplied in the type.  LDS: the
 // buffer, the phase tables (16 values each, then E and e^{i h phi0}), B_h, and for the Bluestein
 // form e^{2 pi i b / n}, e^{2 pi i 64 a / n} in the type.
+// Waves per SIMD the radix-16 ring kernels are compiled for (their register budget; 0: the
+// compiler's choice)
+#ifndef SMF_RING_R16_WAVES
+#define SMF_RING_R16_WAVES 0
+#endif
+// 1: the radix-16 ring kernels also load the modes n - k ahead of the tables (FP32)
+#ifndef SMF_RING_PRE_NEG
+#define SMF_RING_PRE_NEG 1
+#endif
+#if SMF_RING_R16_WAVES > 0
+#define SMF_R16_ATTR __attribute__((amdgpu_waves_per_eu(SMF_RING_R16_WAVES)))
+#else
+#define SMF_R16_ATTR
+#endif
+
 template <typename T, int LOG2L, bool BLUE>
-__global__ __launch_bounds__((1 << LOG2L) / 16) void ring_r16_kernel(RingFftArgs a, const T* __restrict__ g,
+__global__ __launch_bounds__((1 << LOG2L) / 16) SMF_R16_ATTR void ring_r16_kernel(RingFftArgs a, const T* __restrict__ g,
                                                                      const int* __restrict__ n_ring,
                                                                      const double* __restrict__ phi0,
                                                                      const int64_t* __restrict__ off,
@@ -163,14 +178,14 @@ __global__ __launch_bounds__((1 << LOG2L) / 16) void ring_r16_kernel(RingFftArgs
         return Cx<T>{x.x, x.y};
     };
 
-    V2 xa[PRE ? RB : 1], xb[PRE ? RB : 1];
+    V2 xa[PRE ? RB : 1], xb[PRE && SMF_RING_PRE_NEG ? RB : 1];
     if constexpr (PRE) {
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const int k = t + NT * r;
             const int mk = k == 0 ? n : n - k;
             xa[r] = (k < h && k <= mt) ? gv[k] : zero2;
-            xb[r] = (k < h && mk <= mt) ? gv[mk] : zero2;
+            if constexpr (SMF_RING_PRE_NEG) xb[r] = (k < h && mk <= mt) ? gv[mk] : zero2;
         }
     }
     const bool phased = p0 != 0.0;   // uniform: rings starting at longitude 0 need no phases
@@ -210,7 +225,10 @@ __global__ __launch_bounds__((1 << LOG2L) / 16) void ring_r16_kernel(RingFftArgs
         Cx<T> u, x;
         if constexpr (PRE) {
             u = {xa[r].x, xa[r].y};
-            x = {xb[r].x, xb[r].y};
+            if constexpr (SMF_RING_PRE_NEG)
+                x = {xb[r].x, xb[r].y};
+            else
+                x = (k < h && mk <= mt) ? mode(mk) : Cx<T>{T(0), T(0)};
         } else {
             u = (k < h && k <= mt) ? mode(k) : Cx<T>{T(0), T(0)};
             x = (k < h && mk <= mt) ? mode(mk) : Cx<T>{T(0), T(0)};

@@ -176,6 +176,9 @@ hipError_t launch_ring_fft_class(bool blue, int log2l, int rings, int n_theta, i
 // Streams besides the caller's that a ring plan's synthesis spreads its launches over (forked
 // from and joined back to the caller's stream by events)
 constexpr int kRingAuxStreams = 3;
+#ifndef SMF_RING_FORK
+#define SMF_RING_FORK 1
+#endif
 size_t ring_lds_bytes(int n_max, int m_top, bool fp64, int l_max = 0);
 int ring_largest_odd_prime(int h);    // 1 when h is a power of two
 hipError_t launch_ring_c2r(int n_theta, int m_top, int g_row, int64_t total, const RingSplit& rs, bool fp64,

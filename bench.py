@@ -35,7 +35,7 @@ def log(msg):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("rng.h", "device_path.h", "sample.hip", "rings.hip", "smf_internal.h"):
+    for f in ("rng.h", "device_path.h", "sample.hip", "rings.hip", "rings_fft.hip", "smf_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_1709_10314_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -17,12 +17,17 @@
 namespace smf {
 namespace {
 
+// Consecutive work items kept on one XCD (two rings of one length in eight fields)
+constexpr int kXcdChunk = 16;
+
 struct RingFftArgs {
     int n_theta;
     int m_top;
     int g_row;          // complex values per ring in the mode buffer
     int64_t total;      // pixels of one field
-    const int* list;    // rings of this launch (blockIdx.x indexes it)
+    const int* list;    // rings of this launch
+    int rings;          // entries of list
+    int count;          // fields
 };
 
 // First element of the twiddle table of length L = 2^LOG2L: e^{2 pi i t / (2L)}, t < 2L,
@@ -155,8 +160,17 @@ __global__ __launch_bounds__((1 << LOG2L) / 16) SMF_R16_ATTR void ring_r16_kerne
     constexpr int RB = BLUE ? 8 : 16;        // bins per thread (Bluestein: k < h <= L / 2)
     constexpr bool PRE = sizeof(T) == 4;     // first-period modes loaded ahead of the tables
     extern __shared__ unsigned char smem_raw[];
-    const int i = a.list[blockIdx.x];
-    const int f = blockIdx.y;
+    // work item w = (list position) * count + field.  Workgroup b runs on XCD b mod 8; the
+    // items are dealt to the XCDs in chunks of kXcdChunk consecutive items, chunk c to XCD c mod 8,
+    // so that the workgroups of one ring length (next to each other in the list, every field)
+    // share their XCD's L2 for the Bluestein kernel's transform while the XCDs get equal shares
+    // of the list.  Blocks past the last item return before any barrier.
+    const int n_items = a.rings * a.count;
+    const int slot = (int)(blockIdx.x >> 3);
+    const int w = ((slot / kXcdChunk) * 8 + (int)(blockIdx.x & 7)) * kXcdChunk + slot % kXcdChunk;
+    if (w >= n_items) return;
+    const int i = a.list[w / a.count];
+    const int f = w - (w / a.count) * a.count;
     const int n = n_ring[i];
     const int h = n >> 1;
     const int t = threadIdx.x;
@@ -388,7 +402,12 @@ hipError_t launch_fft_t(const RingFftArgs& a, int rings, int count, const T* g, 
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((ring_r16_kernel<T, LOG2L, BLUE>), dim3(rings, count), dim3((1 << LOG2L) / 16), lds, st, a, g,
+    RingFftArgs ab = a;
+    ab.rings = rings;
+    ab.count = count;
+    const int items = rings * count;
+    const int per_round = 8 * kXcdChunk;
+    hipLaunchKernelGGL((ring_r16_kernel<T, LOG2L, BLUE>), dim3(((items + per_round - 1) / per_round) * per_round), dim3((1 << LOG2L) / 16), lds, st, ab, g,
                        n_ring, phi0, off, (const Cx<T>*)tw, (const Cx<T>*)spec, spec_off, out, ep);
     return hipGetLastError();
 }
@@ -472,7 +491,7 @@ hipError_t launch_ring_fft_class(bool blue, int log2l, int rings, int n_theta, i
                                  const int64_t* spec_off, void* out, const LognormalMap* ln, hipStream_t st)
 {
     if (count <= 0 || count > 65535 || rings < 0) return hipErrorInvalidValue;
-    const RingFftArgs a = {n_theta, m_top, g_row, total, list};
+    const RingFftArgs a = {n_theta, m_top, g_row, total, list, rings, count};
     if (fp64) {
         const Epilogue<double> ep = {ln ? ln->mu : 0.0, ln ? ln->sigma : 0.0, ln ? 1 : 0};
         return blue ? launch_fft_l<double, true>(log2l, a, rings, count, (const double*)g, n_ring, phi0, off, tw, spec,

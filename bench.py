@@ -235,7 +235,7 @@ def healpix_leg(steps, warmup, nside=1024, order=2, kappa=50.0, count=8, seed=1)
             "fields": count, "value": pix / ms * 1e3, "unit": "pixels/s", "ms_per_step": ms,
             "synthesis_ms": ms_syn, "synthesis_alg_bytes": alg, "synthesis_alg_GBs": alg / (ms_syn * 1e-3) / 1e9,
             "synthesis_hbm_frac": alg / (ms_syn * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "synthesis_traffic": measured_traffic("ring_c2r_healpix1024") if nside == 1024 and count == 8 else None,
+            "synthesis_traffic": measured_traffic("ring_synthesis_healpix1024") if nside == 1024 and count == 8 else None,
             "setup_s": setup_s}
 
 

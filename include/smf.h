@@ -324,6 +324,13 @@ int smf_measure_fma(int workgroups, int iters, void* out_dev, void* hip_stream);
  * Errors: SMF_EINVAL (n < -1). */
 int smf_debug_fail_alloc(int n);
 
+/* Diagnostics on stderr, one line per event prefixed "[smf] ": level 0 none, 1 each plan's setup
+ * (geometry, layout and transform-class choices, sizes) and the reason for each argument a
+ * setup rejects, 2 also each sampling call's launch shape.  The level starts from the environment
+ * variable SMF_LOG (0 when unset) and this call replaces it for the process.  Returns the
+ * previous level; SMF_EINVAL for a negative level. */
+int smf_set_log_level(int level);
+
 /* Frees the plan and its device memory (synchronises the device first).  NULL is a
  * no-op. */
 int smf_destroy(smf_plan* plan);

@@ -1,5 +1,7 @@
 // C ABI of libsmf: plan creation (Alg. 1 on the GPU), sampling (Alg. 2), queries.
 #include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -38,6 +40,49 @@ struct BatchState {
     std::mutex call_mu;
 };
 }  // namespace smf
+
+// ---- diagnostics ----
+// Level from smf_set_log_level, else from the environment variable SMF_LOG (0 when unset): 1
+// prints each plan's setup (geometry, layout choices, sizes, time) and the reason for each
+// rejected argument of a setup; 2 also each sampling call's launch shape.  One line per event to
+// stderr, prefixed "[smf] ".
+static std::atomic<int> g_log_level{-1};
+
+static int log_level()
+{
+    int l = g_log_level.load(std::memory_order_relaxed);
+    if (l >= 0) return l;
+    const char* e = getenv("SMF_LOG");
+    int v = e ? atoi(e) : 0;
+    if (v < 0) v = 0;
+    int expected = -1;
+    g_log_level.compare_exchange_strong(expected, v);
+    return g_log_level.load(std::memory_order_relaxed);
+}
+
+__attribute__((format(printf, 2, 3))) static void log_line(int level, const char* fmt, ...)
+{
+    if (log_level() < level) return;
+    char buf[640] = "[smf] ";
+    const size_t p = strlen(buf);
+    va_list ap;
+    va_start(ap, fmt);
+    int n = vsnprintf(buf + p, sizeof(buf) - p - 1, fmt, ap);
+    va_end(ap);
+    if (n < 0) return;
+    size_t end = p + (size_t)n;
+    if (end > sizeof(buf) - 2) end = sizeof(buf) - 2;
+    buf[end] = '\n';
+    buf[end + 1] = '\0';
+    fputs(buf, stderr);   // one call per line, so that lines of concurrent calls do not interleave
+}
+
+// SMF_EINVAL with its reason logged at level 1
+static int reject(const char* where, const char* why)
+{
+    log_line(1, "%s: invalid argument: %s", where, why);
+    return SMF_EINVAL;
+}
 
 namespace {
 
@@ -152,30 +197,35 @@ bool grid_symmetric(const double* z, int n)
 int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int n_phi, int flags,
                hipStream_t st, bool scan, smf_plan** out, int rows = 0)
 {
-    if (!spec || !out) return SMF_EINVAL;
+    const char* W = "smf_setup";
+    if (!spec || !out) return reject(W, "spec or out is NULL");
     *out = nullptr;
-    if (spec->order < 1 || spec->order > 4) return SMF_EINVAL;
-    if (spec->ell_max < 0 || spec->ell_max > (1 << 20)) return SMF_EINVAL;
+    if (spec->order < 1 || spec->order > 4) return reject(W, "order must be 1, 2, 3 or 4");
+    if (spec->ell_max < 0 || spec->ell_max > (1 << 20)) return reject(W, "ell_max must be in [0, 2^20]");
     if (!spec->c_ell && (spec->n_kappa < 0 || spec->n_kappa > 64 || (spec->n_kappa > 0 && !spec->kappa)))
-        return SMF_EINVAL;
-    if (n_theta < 2 || n_theta > (1 << 16)) return SMF_EINVAL;
-    if (!is_pow2(n_phi) || n_phi < 4 || n_phi > 16384) return SMF_EINVAL;
+        return reject(W, "n_kappa must be in [0, 64] with kappa given, or c_ell given");
+    if (n_theta < 2 || n_theta > (1 << 16)) return reject(W, "n_theta must be in [2, 65536]");
+    if (!is_pow2(n_phi) || n_phi < 4 || n_phi > 16384) return reject(W, "n_phi must be a power of two in [4, 16384]");
     const int ubasis = (flags & SMF_UBASIS) ? 1 : 0;
     const int no_mirror = (flags & SMF_NO_MIRROR) ? 1 : 0;
     const int green = (flags & SMF_GREEN) ? 1 : 0;
     flags &= ~(SMF_UBASIS | SMF_NO_MIRROR | SMF_GREEN);
-    if (flags != SMF_FP64 && flags != SMF_FP32) return SMF_EINVAL;
-    if (ubasis && spec->order != 2) return SMF_EINVAL;
+    if (flags != SMF_FP64 && flags != SMF_FP32)
+        return reject(W, "flags must hold exactly one of SMF_FP64, SMF_FP32 (SMF_FUSED is not supported)");
+    if (ubasis && spec->order != 2) return reject(W, "SMF_UBASIS needs order 2");
     if (green) {
         // order 1 with one kappa, or order 2 with two distinct ones, all finite and positive
         if (spec->order > 2 || ubasis || spec->c_ell || spec->n_kappa != spec->order || !spec->kappa ||
             (long long)spec->order * n_theta * (n_phi / 2 + 1) > smf::kGreenMaxTable)
-            return SMF_EINVAL;
+            return reject(W, "SMF_GREEN needs order 1 or 2 with n_kappa = order, no c_ell, no SMF_UBASIS");
         for (int i = 0; i < spec->n_kappa; ++i)
-            if (!(spec->kappa[i] > 0.0) || !std::isfinite(spec->kappa[i])) return SMF_EINVAL;
-        if (spec->order == 2 && spec->kappa[0] == spec->kappa[1]) return SMF_EINVAL;
+            if (!(spec->kappa[i] > 0.0) || !std::isfinite(spec->kappa[i]))
+                return reject(W, "SMF_GREEN needs finite positive kappa");
+        if (spec->order == 2 && spec->kappa[0] == spec->kappa[1])
+            return reject(W, "SMF_GREEN at order 2 needs two distinct kappa");
     }
-    if (z_host && !grid_ok(z_host, n_theta)) return SMF_EINVAL;
+    if (z_host && !grid_ok(z_host, n_theta))
+        return reject(W, "z must be finite, strictly decreasing and inside (-1, 1)");
 
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SMF_EHIP;
@@ -302,6 +352,13 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
     if (hp_dev) (void)hipFree(hp_dev);
     if (hn_dev) (void)hipFree(hn_dev);
     *out = plan;
+    log_line(1, "setup: order %d, %d x %d rings x longitudes, ell_max %d (m_top %d), %s%s%s%s%s, %d factor sets x %d mode "
+             "rows (%.1f MB of factors), %s walk",
+             g.order, n_theta, n_phi, g.ell_max, g.m_top, flags == SMF_FP64 ? "FP64" : "FP32", ubasis ? ", U basis" : "",
+             green ? ", Green's functions" : "", z_host ? ", explicit grid" : "", plan->asym ? ", own southern sets" : "",
+             g.n_sets, g.m_rows,
+             (double)nrec1 * (plan->asym ? 2 : 1) * (8.0 + (flags == SMF_FP32 ? 4.0 : 0.0)) / 1e6,
+             plan->scan_fine > 1 ? "scan-capable" : "plain");
     return SMF_OK;
 
 fail:
@@ -309,6 +366,7 @@ fail:
     bufs.free_all();
     free(plan->zgrid);
     free(plan);
+    log_line(1, "smf_setup: failed: %s", smf_error_string(rc));
     return rc;
 }
 
@@ -392,6 +450,9 @@ static int sample_common(const smf_plan* plan, uint64_t seed, int count, void* o
     const int fp64 = plan->flags == SMF_FP64;
     const void* fac = fp64 ? (const void*)plan->f64 : (const void*)plan->f32;
     const CallShape cs = call_shape(plan, count);
+    log_line(2, "sample: %d field%s, %s, %d chain%s per lane%s", count, count == 1 ? "" : "s",
+             cs.blocks > 1 ? "affine scan over ring blocks" : "plain walk", cs.nch, cs.nch == 1 ? "" : "s",
+             fft ? ", then the transform" : "");
     if (cs.blocks > 1) {
         const void* phi = fp64 ? (const void*)plan->phi64 : (const void*)plan->phi32;
         if (smf::launch_scan(plan->g, fp64, fac, plan->south_off, phi, plan->phi_south_off, plan->scan_fine, cs.blocks,
@@ -594,16 +655,19 @@ int smf_plan_grid(const smf_plan* plan, double* z_host, int* symmetric)
 int smf_setup_rings(const smf_spectrum* spec, int n_theta, const double* z_host, const int* n_phi_ring,
                     const double* phi0, int flags, void* hip_stream, smf_plan** out)
 {
-    if (!spec || !out || !n_phi_ring || !phi0 || n_theta < 2 || n_theta > (1 << 16)) return SMF_EINVAL;
+    const char* W = "smf_setup_rings";
+    if (!spec || !out || !n_phi_ring || !phi0 || n_theta < 2 || n_theta > (1 << 16))
+        return reject(W, "NULL argument, or n_theta outside [2, 65536]");
     *out = nullptr;
-    if (spec->ell_max < 0 || spec->ell_max > smf::kRingMaxEll) return SMF_EINVAL;
+    if (spec->ell_max < 0 || spec->ell_max > smf::kRingMaxEll) return reject(W, "ell_max must be in [0, 8191]");
     const bool fp64 = (flags & ~(SMF_UBASIS | SMF_NO_MIRROR)) == SMF_FP64;
     const int n_cap = fp64 ? smf::kRingMaxPixels64 : smf::kRingMaxPixels32;
     int n_max = 0;
     std::vector<int64_t> off((size_t)n_theta + 1, 0);
     for (int i = 0; i < n_theta; ++i) {
         const int n = n_phi_ring[i];
-        if (n < 2 || n > n_cap || (n & 1) || !std::isfinite(phi0[i])) return SMF_EINVAL;
+        if (n < 2 || n > n_cap || (n & 1) || !std::isfinite(phi0[i]))
+            return reject(W, "each ring needs an even pixel count in [2, 8192] (FP32) or [2, 4096] (FP64) and a finite phi0");
         n_max = std::max(n_max, n);
         off[i + 1] = off[i] + n;
     }
@@ -798,6 +862,26 @@ int smf_setup_rings(const smf_spectrum* spec, int n_theta, const double* z_host,
     if (rc != SMF_OK) {
         smf_destroy(plan);
         *out = nullptr;
+        log_line(1, "smf_setup_rings: failed: %s", smf_error_string(rc));
+        return rc;
+    }
+    if (log_level() >= 1) {
+        char cls[256] = "";
+        size_t used = 0;
+        for (int c = smf::kRingFftClasses - 1; c >= 0; --c) {
+            if (rs.n_blue[c])
+                used += snprintf(cls + used, sizeof(cls) - used, " Bluestein L=%d: %d;", 1 << (smf::kRingFftMinLog2 + c),
+                                 rs.n_blue[c]);
+            if (rs.n_pow2[c] && used < sizeof(cls))
+                used += snprintf(cls + used, sizeof(cls) - used, " power of two L=%d: %d;",
+                                 1 << (smf::kRingFftMinLog2 + c), rs.n_pow2[c]);
+            if (used >= sizeof(cls)) break;
+        }
+        log_line(1, "setup_rings: %d rings, %lld pixels per field, largest %d, chains at n_phi %d; rings by transform "
+                 "class:%s general %d (chirp-z %d); %lld Bluestein kernel transforms (%.1f MB); %s",
+                 n_theta, (long long)off[n_theta], n_max, n_phi, cls, rs.n_direct + rs.n_chirp, rs.n_chirp,
+                 (long long)spec_h.size(), (double)spec_total * (fp64 ? 16 : 8) / 1e6,
+                 plan->ring_aux[0] ? "launches spread over 3 more streams" : "one stream");
     }
     return rc;
 }
@@ -849,6 +933,9 @@ static int synthesize_rings(const smf_plan* plan, int count, const void* g_dev, 
         for (int j = 0; j < smf::kRingAuxStreams; ++j)
             if (hipStreamWaitEvent(plan->ring_aux[j], plan->ring_fork, 0) != hipSuccess) return SMF_EHIP;
     }
+    log_line(2, "synthesize_rings: %d field%s, %d transform-class launch%s%s, general kernel %s", count,
+             count == 1 ? "" : "s", (int)fft.size(), fft.size() == 1 ? "" : "es", fork ? " on the plan's streams" : "",
+             general ? "on the caller's stream" : "not needed");
     int rc = SMF_OK;
     for (size_t u = 0; u < fft.size() && rc == SMF_OK; ++u) {
         const hipStream_t su = fork ? plan->ring_aux[u % smf::kRingAuxStreams] : st;
@@ -986,6 +1073,14 @@ int smf_destroy(smf_plan* plan)
     free(plan->ring_off);
     free(plan);
     return SMF_OK;
+}
+
+int smf_set_log_level(int level)
+{
+    if (level < 0) return SMF_EINVAL;
+    const int prev = log_level();
+    g_log_level.store(level);
+    return prev;
 }
 
 int smf_debug_fail_alloc(int n)

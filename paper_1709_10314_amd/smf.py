@@ -23,7 +23,7 @@ EXPORTS = ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", 
            "smf_destroy", "smf_error_string", "smf_setup_batch", "smf_batch_layout",
            "smf_sample_batch", "smf_sample_batch_packed", "smf_autotune_batch", "smf_setup_rings", "smf_ring_layout",
            "smf_synthesize_rings", "smf_sample_rings", "smf_sample_rings_lognormal", "smf_measure_normals",
-           "smf_measure_fma", "smf_debug_fail_alloc", "smf_sample_rings_noalloc")
+           "smf_measure_fma", "smf_debug_fail_alloc", "smf_sample_rings_noalloc", "smf_set_log_level")
 
 
 class smf_spectrum(ctypes.Structure):
@@ -89,12 +89,13 @@ def load():
     lib.smf_measure_fma.argtypes = [i, i, vp, vp]
     lib.smf_debug_fail_alloc.argtypes = [i]
     lib.smf_sample_rings_noalloc.argtypes = [vp, u64, i, vp, vp]
+    lib.smf_set_log_level.argtypes = [i]
     for name in ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks", "smf_get_ring_blocks",
                  "smf_plan_dims",
                  "smf_get_factors", "smf_set_factors", "smf_plan_grid", "smf_destroy", "smf_setup_batch", "smf_batch_layout",
                  "smf_sample_batch", "smf_sample_batch_packed", "smf_autotune_batch", "smf_setup_rings", "smf_ring_layout",
                  "smf_synthesize_rings", "smf_sample_rings", "smf_sample_rings_lognormal", "smf_measure_normals",
-                 "smf_measure_fma", "smf_debug_fail_alloc", "smf_sample_rings_noalloc"):
+                 "smf_measure_fma", "smf_debug_fail_alloc", "smf_sample_rings_noalloc", "smf_set_log_level"):
         getattr(lib, name).restype = i
     _lib = lib
     return lib
@@ -215,6 +216,12 @@ def smf_setup(order, n_theta, n_phi, ell_max, kappa=None, c_ell=None, flags=SMF_
 def smf_sample(plan, seed, count, out_ptr, stream=None):
     return load().smf_sample(plan, ctypes.c_uint64(int(seed)), int(count), ctypes.c_void_p(out_ptr),
                              _stream_handle(stream))
+
+
+def smf_set_log_level(level):
+    """Diagnostics level of the library (0 none, 1 setups and rejected arguments, 2 also each
+    sampling call's launch shape; lines on stderr).  Returns the previous level."""
+    return load().smf_set_log_level(int(level))
 
 
 def smf_sample_lognormal(plan, seed, count, mu, sigma, out_ptr, stream=None):

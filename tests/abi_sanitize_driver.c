@@ -27,6 +27,8 @@ int main(void)
     smf_spectrum ok = {2, 2, kappa, NULL, 16};
     smf_plan* plan = (smf_plan*)0x1;
 
+    expect(smf_set_log_level(-1), SMF_EINVAL, SMF_EINVAL, "log level -1");
+    if (smf_set_log_level(1) < 0) ++failures;   /* the rejections below are also explained on stderr */
     for (int code = -6; code <= 1; ++code)
         if (!smf_error_string(code) || !strlen(smf_error_string(code))) ++failures;
 

@@ -11,6 +11,8 @@
 // Folding the modes onto the ring's frequencies and the real-to-complex split are those of the
 // general ring kernel (rings.hip); here each thread folds the bins of its transform inputs, and
 // the split's mirror partners come through LDS.
+#include <algorithm>
+
 #include "device_path.h"
 #include "smf_internal.h"
 
@@ -402,14 +404,21 @@ hipError_t launch_fft_t(const RingFftArgs& a, int rings, int count, const T* g, 
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    RingFftArgs ab = a;
-    ab.rings = rings;
-    ab.count = count;
-    const int items = rings * count;
+    // fields in chunks whose work items (rings x fields) fit a 2^30-workgroup grid
     const int per_round = 8 * kXcdChunk;
-    hipLaunchKernelGGL((ring_r16_kernel<T, LOG2L, BLUE>), dim3(((items + per_round - 1) / per_round) * per_round), dim3((1 << LOG2L) / 16), lds, st, ab, g,
-                       n_ring, phi0, off, (const Cx<T>*)tw, (const Cx<T>*)spec, spec_off, out, ep);
-    return hipGetLastError();
+    const int chunk = (int)std::min<int64_t>(count, ((int64_t)1 << 30) / rings);
+    for (int f0 = 0; f0 < count; f0 += chunk) {
+        RingFftArgs ab = a;
+        ab.rings = rings;
+        ab.count = std::min(chunk, count - f0);
+        const int items = rings * ab.count;
+        hipLaunchKernelGGL((ring_r16_kernel<T, LOG2L, BLUE>), dim3(((items + per_round - 1) / per_round) * per_round),
+                           dim3((1 << LOG2L) / 16), lds, st, ab, g + (size_t)f0 * a.n_theta * a.g_row * 2, n_ring,
+                           phi0, off, (const Cx<T>*)tw, (const Cx<T>*)spec, spec_off, out + (size_t)f0 * a.total, ep);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <typename T, bool BLUE>

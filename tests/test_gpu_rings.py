@@ -298,11 +298,13 @@ def test_ring_plan_arguments():
 
 
 def test_sample_rings_graph_capture_replays():
-    """smf_sample_rings (chains, then both ring launches) captured in a HIP graph: every replay,
-    with eager work and synchronisations between replays, equals the eager call."""
+    """smf_sample_rings (chains, then the ring launches, forked over the plan's streams and joined
+    back) captured in a HIP graph: every replay, with eager work and synchronisations between
+    replays, equals the eager call."""
     z, n_ring, phi0 = _healpix(32)
     n_ring = n_ring.copy()
-    n_ring[3] = 2 * 509          # one ring takes the chirp-z launch
+    n_ring[3] = 2 * 509          # a Bluestein ring (L = 1024)
+    n_ring[5] = 2048             # a power-of-two ring: three launches, two of them on the plan's streams
     plan = _ring_plan(n_ring, phi0, 95, "fp32", order=2, kap=900.0, z=z)
     eager = plan.sample_rings(13, 2).clone()
     torch.cuda.synchronize()

@@ -158,8 +158,10 @@ def markov_defect(cfg, modes=(0, 64, 1024, 3000), span=16):
 
 
 def batch_leg(steps, warmup):
-    """The batched form on the 256-field mixed workload: one call samples every field
-    (chain launch + FFT launch) after the tile-shape autotuner has run."""
+    """The batched form on the 256-field mixed workload: one call samples every field after
+    the launch-shape autotuner has run (m-tiles per chain item; two launches, or one
+    persistent cooperative launch with a grid barrier between the chains and the rings); both
+    forms are also timed at the chosen tile shape."""
     import torch
 
     from paper_1709_10314_amd import BatchPlan, workloads
@@ -172,13 +174,19 @@ def batch_leg(steps, warmup):
     setup_s = time.perf_counter() - t0
     out = bp.empty()
     tiles = bp.autotune(1, out)
+    _, persistent = bp.shape()
     ms, _ = time_calls(lambda: bp.sample(1, out), steps, warmup)
+    forms = {}
+    for p in (False, True):
+        bp.set_shape(tiles, p)
+        forms["ms_persistent" if p else "ms_two_launches"] = time_calls(lambda: bp.sample(1, out), steps, warmup)[0]
+    bp.set_shape(tiles, persistent)
     pts = int(bp.offsets[-1])
     bp.close()
     del out
     torch.cuda.empty_cache()
     return {"value": pts / ms * 1e3, "unit": "grid points/s", "ms_per_step": ms, "fields": len(fields),
-            "points": pts, "tiles": tiles, "setup_s": setup_s,
+            "points": pts, "tiles": tiles, "persistent": persistent, **forms, "setup_s": setup_s,
             "workload": "256 fields: n_theta uniform on {128..2048}, n_phi = 2 n_theta, ln kappa ~ U(ln 2, ln 200), "
                         "order 1 or 2, FP32, seeds 1..256 (numpy PCG64(0))"}
 

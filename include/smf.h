@@ -15,7 +15,8 @@
  *    are asynchronous on that stream; setup synchronises its stream before returning.
  *  - The sampling calls only read a plan, so one plan may be used from several streams at
  *    once (each call needs its own output buffer); the calls that change a plan
- *    (smf_set_ring_blocks, smf_set_factors, smf_autotune_batch) must not overlap them.
+ *    (smf_set_ring_blocks, smf_set_factors, smf_autotune_batch, smf_batch_set_shape) must
+ *    not overlap them.
  *
  * Grid: n_theta iso-latitude rings at ring centres theta_i = pi (i + 1/2) / n_theta
  * (ring 0 nearest the north pole, z_i = cos theta_i) and n_phi equispaced longitudes
@@ -240,12 +241,23 @@ int smf_sample_batch(const smf_plan* plan, const uint64_t* seeds_host, void* con
  * Errors: SMF_EINVAL (NULL, not a batch plan), SMF_EHIP. */
 int smf_sample_batch_packed(const smf_plan* plan, uint64_t seed, void* out_dev, void* hip_stream);
 
-/* Autotuner of the chain-item tile shape: times smf_sample_batch_packed with 1, 2 and 4
- * m-tiles per chain item (2, 4 and 8 waves per workgroup; writing out_dev, seed as in
- * smf_sample_batch_packed), keeps the fastest in the plan and returns its m-tile count in
- * *tiles_out (may be NULL).  Synchronous; not to be called while the plan is in use.
+/* Autotuner of the launch shape: times smf_sample_batch_packed with 1, 2 and 4 m-tiles per
+ * chain item (2, 4 and 8 waves per workgroup), each in both forms of smf_batch_set_shape
+ * (writing out_dev, seed as in smf_sample_batch_packed), keeps the fastest in the plan and
+ * returns its m-tile count in *tiles_out (may be NULL; smf_batch_get_shape gives the form).
+ * Synchronous; not to be called while the plan is in use.
  * Errors: SMF_EINVAL, SMF_EHIP. */
 int smf_autotune_batch(smf_plan* plan, uint64_t seed, void* out_dev, void* hip_stream, int* tiles_out);
+
+/* The batch plan's launch shape: tiles m-tiles per chain item (1, 2 or 4) and the form, 0 for
+ * two launches (every chain item, then every ring), 1 for one cooperative launch of as many
+ * workgroups as the device holds at once, which run the chain items, meet at a grid barrier
+ * and run the ring items (the persistent form).  Results agree to FP32 rounding across shapes
+ * (the ring transforms of the persistent form run 128 * tiles threads per row, and are
+ * compiled separately for each count).
+ * smf_autotune_batch times all six shapes and keeps the fastest.  Errors: SMF_EINVAL. */
+int smf_batch_set_shape(smf_plan* plan, int tiles, int persistent);
+int smf_batch_get_shape(const smf_plan* plan, int* tiles, int* persistent);
 
 /* Rings with their own pixel counts (iso-latitude grids such as HEALPix, named in Sec. 1):
  * ring i (latitude z_host[i], or the ring centres if z_host is NULL, same rules as

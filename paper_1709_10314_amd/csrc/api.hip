@@ -29,6 +29,7 @@ struct BatchState {
     int n_fft = 0;
     size_t lds = 0;
     int tiles_idx = 1;                   // current tile shape: 2 m-tiles per item
+    int persistent = 0;                  // 1: one cooperative launch (launch_batch_persistent)
     // per-field keys and buffers of smf_sample_batch: kCallSlots tables of n entries in
     // device memory, staged through pinned host memory; slot k is reused only after the
     // event recorded behind the previous call that used it has completed
@@ -1222,7 +1223,7 @@ int smf_batch_layout(const smf_plan* plan, int64_t* offsets)
 }
 
 static int batch_launch(const smf_plan* plan, uint64_t seed, void* out_dev, hipStream_t st, int tiles_idx,
-                        const smf::BatchCall* call = nullptr)
+                        const smf::BatchCall* call = nullptr, int persistent = -1)
 {
     const smf::BatchState* b = plan->batch;
     smf::BatchArgs a;
@@ -1235,7 +1236,34 @@ static int batch_launch(const smf_plan* plan, uint64_t seed, void* out_dev, hipS
     a.tiles = 1 << tiles_idx;
     a.n_chain_items = b->n_chain[tiles_idx];
     a.n_fft_items = b->n_fft;
+    if (persistent < 0) persistent = b->persistent;
+    if (persistent) {
+        int grid = 0;
+        const hipError_t e = smf::launch_batch_persistent(a, b->lds, st, &grid);
+        log_line(2, "sample_batch: %d fields, one cooperative launch of %d workgroups of %d threads (%d chain items, "
+                 "%d ring items)", b->n, grid, 128 * a.tiles, a.n_chain_items, a.n_fft_items);
+        return e == hipSuccess ? SMF_OK : SMF_EHIP;
+    }
+    log_line(2, "sample_batch: %d fields, chain launch of %d workgroups of %d threads, ring launch of %d workgroups",
+             b->n, a.n_chain_items, 128 * a.tiles, a.n_fft_items);
     return smf::launch_batch(a, b->lds, st) == hipSuccess ? SMF_OK : SMF_EHIP;
+}
+
+int smf_batch_set_shape(smf_plan* plan, int tiles, int persistent)
+{
+    if (!plan || !plan->batch || (tiles != 1 && tiles != 2 && tiles != 4) || (persistent != 0 && persistent != 1))
+        return SMF_EINVAL;
+    plan->batch->tiles_idx = tiles == 1 ? 0 : tiles == 2 ? 1 : 2;
+    plan->batch->persistent = persistent;
+    return SMF_OK;
+}
+
+int smf_batch_get_shape(const smf_plan* plan, int* tiles, int* persistent)
+{
+    if (!plan || !plan->batch || !tiles || !persistent) return SMF_EINVAL;
+    *tiles = 1 << plan->batch->tiles_idx;
+    *persistent = plan->batch->persistent;
+    return SMF_OK;
 }
 
 int smf_sample_batch_packed(const smf_plan* plan, uint64_t seed, void* out_dev, void* hip_stream)
@@ -1283,26 +1311,36 @@ int smf_autotune_batch(smf_plan* plan, uint64_t seed, void* out_dev, void* hip_s
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return SMF_EHIP;
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return SMF_EHIP; }
-    int best_k = b->tiles_idx;
+    int best_k = b->tiles_idx, best_p = b->persistent;
     float best = 1e30f;
     int rc = SMF_OK;
-    for (int k = 0; k < 3 && rc == SMF_OK; ++k) {
-        float ms_min = 1e30f;
-        for (int rep = 0; rep < 3 && rc == SMF_OK; ++rep) {
-            float ms = 0.f;
-            if (hipEventRecord(e0, st) != hipSuccess) { rc = SMF_EHIP; break; }
-            rc = batch_launch(plan, seed, out_dev, st, k);
-            if (rc != SMF_OK) break;
-            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = SMF_EHIP; break; }
-            if (rep > 0) ms_min = std::min(ms_min, ms);   // the first run warms up
+    // every tile shape in both forms: two launches, or one cooperative launch
+    for (int p = 0; p < 2 && rc == SMF_OK; ++p) {
+        for (int k = 0; k < 3 && rc == SMF_OK; ++k) {
+            float ms_min = 1e30f;
+            for (int rep = 0; rep < 3 && rc == SMF_OK; ++rep) {
+                float ms = 0.f;
+                if (hipEventRecord(e0, st) != hipSuccess) { rc = SMF_EHIP; break; }
+                rc = batch_launch(plan, seed, out_dev, st, k, nullptr, p);
+                if (rc != SMF_OK) break;
+                if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = SMF_EHIP; break; }
+                if (rep > 0) ms_min = std::min(ms_min, ms);   // the first run warms up
+            }
+            log_line(1, "autotune_batch: %d m-tiles per item, %s: %.3f ms", 1 << k,
+                     p ? "one cooperative launch" : "two launches", ms_min);
+            if (rc == SMF_OK && ms_min < best) {
+                best = ms_min;
+                best_k = k;
+                best_p = p;
+            }
         }
-        if (rc == SMF_OK && ms_min < best) { best = ms_min; best_k = k; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != SMF_OK) return rc;
     b->tiles_idx = best_k;
+    b->persistent = best_p;
     if (tiles_out) *tiles_out = 1 << best_k;
     return SMF_OK;
 }

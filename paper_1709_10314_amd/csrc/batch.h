@@ -36,5 +36,9 @@ struct BatchArgs {
 };
 
 hipError_t launch_batch(const BatchArgs& a, size_t lds, hipStream_t st);
+// The same work in one cooperative launch with a grid barrier between the chain items and the
+// ring items (grid_out: the workgroups launched); hipErrorCooperativeLaunchTooLarge when the
+// device cannot hold a workgroup of the tile shape at once.
+hipError_t launch_batch_persistent(const BatchArgs& a, size_t lds, hipStream_t st, int* grid_out);
 
 }  // namespace smf

@@ -9,6 +9,10 @@
 // (hemisphere x m-tile).  Chain items are listed longest chain first so that the
 // in-order dispatch starts the long fields early.  The number of m-tiles per item is the
 // tile shape the autotuner picks.
+#include <hip/hip_cooperative_groups.h>
+
+#include <algorithm>
+
 #include "batch.h"
 #include "device_path.h"
 
@@ -41,14 +45,14 @@ __device__ void dispatch_fft(int log2h, float* row, const float* tw, int m_top, 
     }
 }
 
-// One workgroup per chain item; wave w -> hemisphere w & 1, m-tile tiles * sub + (w >> 1).
-__global__ __launch_bounds__(kMaxChainThreads) void batch_chain_kernel(BatchArgs a)
+// Chain item `item` by the calling wave w (hemisphere w & 1, m-tile tiles * sub + (w >> 1)).
+// No barriers: each wave returns on its own.
+__device__ __forceinline__ void chain_item(const BatchArgs& a, int item, int w)
 {
-    const uint32_t code = a.chain_items[blockIdx.x];
+    const uint32_t code = a.chain_items[item];
     const int fi = (int)(code >> 16);
     const int sub = (int)(code & 0xFFFF);
     const BatchField& F = a.fields[fi];
-    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int h = w & 1;
     const int lane = threadIdx.x & 63;
     const int m = (a.tiles * sub + (w >> 1)) * 32 + (lane >> 1), part = lane & 1;
@@ -81,6 +85,12 @@ __global__ __launch_bounds__(kMaxChainThreads) void batch_chain_kernel(BatchArgs
     }
 }
 
+// One workgroup per chain item.
+__global__ __launch_bounds__(kMaxChainThreads) void batch_chain_kernel(BatchArgs a)
+{
+    chain_item(a, blockIdx.x, __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)));
+}
+
 // One workgroup per ring of every field.
 __global__ __launch_bounds__(kFftThreads) void batch_fft_kernel(BatchArgs a)
 {
@@ -94,7 +104,81 @@ __global__ __launch_bounds__(kFftThreads) void batch_fft_kernel(BatchArgs a)
                  reinterpret_cast<Cx<float>*>(smem_raw));
 }
 
+// The persistent form: one cooperative launch of as many workgroups of NT = 128 * tiles threads
+// as the device holds at once.  Each workgroup runs the chain items blockIdx.x, blockIdx.x +
+// gridDim.x, ... (listed longest first, so the stride deals them out evenly), then every
+// workgroup meets at the grid barrier, after which all chain outputs are visible, and runs
+// the ring items the same way with all its threads.  The barrier is the runtime's cooperative
+// grid barrier, valid because the launch is cooperative and sized to co-residency.
+template <int NT>
+__device__ __forceinline__ void fft_item_nt(int log2h, float* row, const float* tw, int m_top, Cx<float>* buf)
+{
+    const Epilogue<float> ep = {0.0f, 0.0f, 0};
+    switch (log2h) {
+        case 1: c2r_row<float, 1, NT>(row, tw, m_top, buf, ep); break;
+        case 2: c2r_row<float, 2, NT>(row, tw, m_top, buf, ep); break;
+        case 3: c2r_row<float, 3, NT>(row, tw, m_top, buf, ep); break;
+        case 4: c2r_row<float, 4, NT>(row, tw, m_top, buf, ep); break;
+        case 5: c2r_row<float, 5, NT>(row, tw, m_top, buf, ep); break;
+        case 6: c2r_row<float, 6, NT>(row, tw, m_top, buf, ep); break;
+        case 7: c2r_row<float, 7, NT>(row, tw, m_top, buf, ep); break;
+        case 8: c2r_row<float, 8, NT>(row, tw, m_top, buf, ep); break;
+        case 9: c2r_row<float, 9, NT>(row, tw, m_top, buf, ep); break;
+        case 10: c2r_row<float, 10, NT>(row, tw, m_top, buf, ep); break;
+        case 11: c2r_row<float, 11, NT>(row, tw, m_top, buf, ep); break;
+        default: break;
+    }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void batch_persistent_kernel(BatchArgs a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (int it = blockIdx.x; it < a.n_chain_items; it += gridDim.x) chain_item(a, it, w);
+    cooperative_groups::this_grid().sync();
+    Cx<float>* buf = reinterpret_cast<Cx<float>*>(smem_raw);
+    for (int it = blockIdx.x; it < a.n_fft_items; it += gridDim.x) {
+        const uint32_t code = a.fft_items[it];
+        const int fi = (int)(code >> 16);
+        const int ring = (int)(code & 0xFFFF);
+        const BatchField& F = a.fields[fi];
+        float* base = a.call ? a.call[fi].out : a.out + F.out_off;
+        fft_item_nt<NT>(F.log2h, base + (size_t)ring * F.n_phi, F.tw, F.m_top, buf);
+        __syncthreads();   // the row's last LDS reads before the next row's writes
+    }
+}
+
+template <int NT>
+hipError_t launch_persistent_t(const BatchArgs& a, size_t lds, hipStream_t st, int* grid_out)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)batch_persistent_kernel<NT>, NT, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1 || cus < 1) return hipErrorCooperativeLaunchTooLarge;
+    const long items = std::max<long>(a.n_chain_items, a.n_fft_items);
+    const int grid = (int)std::min<long>((long)per_cu * cus, std::max<long>(items, 1));
+    if (grid_out) *grid_out = grid;
+    BatchArgs args = a;
+    void* params[] = {&args};
+    return hipLaunchCooperativeKernel((const void*)batch_persistent_kernel<NT>, dim3(grid), dim3(NT), params,
+                                      (unsigned)lds, st);
+}
+
 }  // namespace
+
+hipError_t launch_batch_persistent(const BatchArgs& a, size_t lds, hipStream_t st, int* grid_out)
+{
+    switch (a.tiles) {
+        case 1: return launch_persistent_t<128>(a, lds, st, grid_out);
+        case 2: return launch_persistent_t<256>(a, lds, st, grid_out);
+        case 4: return launch_persistent_t<512>(a, lds, st, grid_out);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_batch(const BatchArgs& a, size_t lds, hipStream_t st)
 {

@@ -23,7 +23,8 @@ EXPORTS = ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", 
            "smf_destroy", "smf_error_string", "smf_setup_batch", "smf_batch_layout",
            "smf_sample_batch", "smf_sample_batch_packed", "smf_autotune_batch", "smf_setup_rings", "smf_ring_layout",
            "smf_synthesize_rings", "smf_sample_rings", "smf_sample_rings_lognormal", "smf_measure_normals",
-           "smf_measure_fma", "smf_debug_fail_alloc", "smf_sample_rings_noalloc", "smf_set_log_level")
+           "smf_measure_fma", "smf_debug_fail_alloc", "smf_sample_rings_noalloc", "smf_set_log_level",
+           "smf_batch_set_shape", "smf_batch_get_shape")
 
 
 class smf_spectrum(ctypes.Structure):
@@ -90,12 +91,14 @@ def load():
     lib.smf_debug_fail_alloc.argtypes = [i]
     lib.smf_sample_rings_noalloc.argtypes = [vp, u64, i, vp, vp]
     lib.smf_set_log_level.argtypes = [i]
+    lib.smf_batch_set_shape.argtypes = [vp, i, i]
+    lib.smf_batch_get_shape.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i)]
     for name in ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks", "smf_get_ring_blocks",
                  "smf_plan_dims",
                  "smf_get_factors", "smf_set_factors", "smf_plan_grid", "smf_destroy", "smf_setup_batch", "smf_batch_layout",
                  "smf_sample_batch", "smf_sample_batch_packed", "smf_autotune_batch", "smf_setup_rings", "smf_ring_layout",
                  "smf_synthesize_rings", "smf_sample_rings", "smf_sample_rings_lognormal", "smf_measure_normals",
-                 "smf_measure_fma", "smf_debug_fail_alloc", "smf_sample_rings_noalloc", "smf_set_log_level"):
+                 "smf_measure_fma", "smf_debug_fail_alloc", "smf_sample_rings_noalloc", "smf_set_log_level", "smf_batch_set_shape", "smf_batch_get_shape"):
         getattr(lib, name).restype = i
     _lib = lib
     return lib
@@ -397,11 +400,27 @@ class BatchPlan:
         return out[self.offsets[i]:self.offsets[i + 1]].view(f["n_theta"], f["n_phi"])
 
     def autotune(self, seed, out, stream=None):
-        """Picks the chain-item tile shape (m-tiles per item); returns it."""
+        """Picks the launch shape (m-tiles per chain item, two launches or one persistent
+        cooperative launch); returns the m-tile count."""
         rc, tiles = smf_autotune_batch(self._h, seed, out.data_ptr(), stream)
         if rc != SMF_OK:
             raise SmfError(rc, "smf_autotune_batch")
         return tiles
+
+    def set_shape(self, tiles, persistent):
+        """tiles: m-tiles per chain item (1, 2, 4); persistent: one cooperative launch (True)
+        or two launches (False) (smf_batch_set_shape)."""
+        rc = load().smf_batch_set_shape(self._h, int(tiles), 1 if persistent else 0)
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_batch_set_shape")
+
+    def shape(self):
+        """(tiles, persistent) of the plan (smf_batch_get_shape)."""
+        t, p = ctypes.c_int(), ctypes.c_int()
+        rc = load().smf_batch_get_shape(self._h, ctypes.byref(t), ctypes.byref(p))
+        if rc != SMF_OK:
+            raise SmfError(rc, "smf_batch_get_shape")
+        return t.value, bool(p.value)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -73,6 +73,10 @@ def _load():
     lib.orc_jblock_zs.argtypes = [_i, _i, _i, _pd, _d, _d, _d, _d, _pd]
     lib.orc_ring_zs.argtypes = [_i, _i, _pd, _pd]
     lib.orc_setup.argtypes = [_i, _i, _pd, _i, _i, _i, _pd, _pd]
+    lib.orc_greenc_G.argtypes = [_i, _d, _d, _d, _d, _pd]
+    lib.orc_greenc_G.restype = None
+    lib.orc_jblock_green2c.argtypes = [_i, _pd, _d, _d, _d, _d, _pd]
+    lib.orc_jblock_green2c.restype = None
     lib.orc_setup.restype = _i
     lib.orc_setup_z.argtypes = [_i, _i, _pd, _i, _pd, _i, _i, _pd, _pd]
     lib.orc_setup_z.restype = _i
@@ -249,6 +253,42 @@ def setup_green2(kappas, n_theta, n_phi, sets=None, modes=None, z=None):
                                     md.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(md), _p(A), _p(B))
     if rc != 0:
         raise ValueError("orc_setup_modes_zb rejected its arguments")
+    return A, B
+
+
+def greenc_G(m, kappa, x):
+    """G_m(x) = 2F1(-lambda, lambda+1; 1+m; (1-x)/2) for complex kappa = -lambda(lambda+1)."""
+    x, s = _zs(x)
+    out = np.zeros(2)
+    _load().orc_greenc_G(int(m), float(np.real(kappa)), float(np.imag(kappa)), x, s, _p(out))
+    return complex(out[0], out[1])
+
+
+def jblock_green2c(m, alpha, beta, z1, z2):
+    """J^m(z1, z2) of order 2 in the basis (g, U g) from the Green's functions of the complex
+    pair kappa = alpha +- i beta (C_l = 1/((l(l+1) + alpha)^2 + beta^2)); a 2 x 2 array."""
+    z1, s1 = _zs(z1)
+    z2, s2 = _zs(z2)
+    k = np.array([alpha, beta], dtype=np.float64)
+    J = np.zeros(4)
+    _load().orc_jblock_green2c(int(m), _p(k), z1, s1, z2, s2, _p(J))
+    return J.reshape(2, 2)
+
+
+def setup_green2c(alpha, beta, n_theta, n_phi, sets=None, modes=None, z=None):
+    """Alg. 1 at order 2 in the basis (g, U g) on the Green's-function cross covariances of the
+    pair alpha +- i beta (no band limit; modes m <= n_phi/2 - 1, or the listed ones)."""
+    mt = n_phi // 2 - 1
+    md = np.arange(mt + 1, dtype=np.int32) if modes is None else np.ascontiguousarray(modes, dtype=np.int32)
+    ns = n_sets(n_theta) if sets is None else min(sets, n_sets(n_theta))
+    A = np.zeros((ns, len(md), 2, 2))
+    B = np.zeros((ns, len(md), 2, 2))
+    kap = np.array([alpha, beta], dtype=np.float64)
+    zg = _zgrid(z, n_theta)
+    rc = _load().orc_setup_modes_zb(2, 4, 0, _p(kap), n_theta, None if zg is None else _p(zg), ns,
+                                    md.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(md), _p(A), _p(B))
+    if rc != 0:
+        raise ValueError("oracle setup_green2c failed")
     return A, B
 
 

@@ -549,6 +549,152 @@ void orc_jblock_green2(int m, const double* kap, double z1, double s1, double z2
     }
 }
 
+/* ------------------------------------------------------------------------- */
+/* Sec. 3 with a complex-conjugate pair kappa_{1,2} = alpha +- i beta (beta > 0), the form of */
+/* the Sec. 5 spectrum C_l = 1/((l(l+1))^2 + 10) = 1/((l(l+1) + i sqrt10)(l(l+1) - i sqrt10)).  */
+/* Every step of the real case holds with complex arithmetic: lambda = -1/2 + sqrt(1/4 -       */
+/* kappa) (either root: G_m and sin(pi lambda) are symmetric under lambda -> -1 - lambda),     */
+/* the series and continuation of G_m with complex terms, and Gamma(1+lambda) Gamma(-lambda)   */
+/* = -pi / sin(pi lambda), so that                                                           */
+/*   J^m_kappa(z1, z2) = (Pi_m / m!^2) w^m G_m(-z1) G_m(z2) / (-4 sin pi lambda),  z1 <= z2.    */
+/* For the real cases -sin(pi lambda) = |sin(pi lambda)|, the form above.  The partial fractions */
+/* have b_1 = 1/(kappa_2 - kappa_1) = i / (2 beta) = -b_2, and the kappa_2 term is the complex  */
+/* conjugate of the kappa_1 term, so the order-2 block in the basis (g, U g) is                 */
+/*   J_pq = 2 Re[ b_1 (Pi_m / m!^2) w^m / (-4 sin pi lambda_1) (-1)^p (a_1 r1)^p              */
+/*                G_{m+p}(-z1) (a_1 r2)^q G_{m+q}(z2) ],  a_1 = (m^2 + m + kappa_1) / (m + 1).   */
+/* ------------------------------------------------------------------------- */
+static double complex greenc_lambda(double complex kappa) { return -0.5 + csqrt(0.25 - kappa); }
+
+static double complex greenc_G_series(int m, double complex kappa, double t)
+{
+    double complex sum = 1.0, term = 1.0;
+    for (int n = 0; n < 200000; ++n) {
+        const double complex ratio = ((double)n * n + n + kappa) / ((n + 1.0) * (n + 1.0 + m)) * t;
+        term *= ratio;
+        sum += term;
+        if (cabs(ratio) < 1.0 && cabs(term) < 1e-18 * cabs(sum)) break;
+    }
+    return sum;
+}
+
+/* the continuation about t = 1 (as green_G01_far), g = 1/(Gamma(a) Gamma(b)) = -sin(pi lambda)/pi */
+static void greenc_G01_far(double complex kappa, double u, double complex* G0, double complex* G1)
+{
+    const double complex lam = greenc_lambda(kappa);
+    const double complex g = -csin(M_PI * lam) / M_PI;
+    const double L = log(u);
+    const double euler = 0.57721566490153286061;
+    double complex c = 1.0, d = 1.0, s0 = 0.0, s1 = 0.0;
+    double uk = 1.0, psi_k1 = -euler;
+    for (int k = 0; k < 100000; ++k) {
+        const double psi_k2 = psi_k1 + 1.0 / (k + 1.0);
+        const double complex pp0 = cdigamma(-lam + k) + cdigamma(lam + 1.0 + k);
+        const double complex pp1 = cdigamma(-lam + k + 1.0) + cdigamma(lam + 2.0 + k);
+        const double complex t0 = c * uk * (L - 2.0 * psi_k1 + pp0);
+        const double complex t1 = d * uk * (L - psi_k1 - psi_k2 + pp1);
+        s0 += t0;
+        s1 += t1;
+        const double dk = k;
+        const double complex rc = (dk * dk + dk + kappa) / ((dk + 1.0) * (dk + 1.0));
+        c *= rc;
+        d *= ((dk + 1.0) * (dk + 1.0) + (dk + 1.0) + kappa) / ((dk + 1.0) * (dk + 2.0));
+        uk *= u;
+        psi_k1 = psi_k2;
+        if (k > 4 && cabs(t0) < 1e-18 * cabs(s0) && cabs(t1) < 1e-18 * cabs(s1) && cabs(rc) * u < 0.9) break;
+    }
+    *G0 = -g * s0;
+    *G1 = g / kappa + g * u * s1;
+}
+
+/* G_0 .. G_{m_top} at x (s = sin theta), as green_G_all with |kappa| in the switch rule */
+static void greenc_G_all(int m_top, double complex kappa, double x, double s, double complex* G)
+{
+    if (x >= 0.0) {
+        const double t = s * s / (2.0 * (1.0 + x));
+        for (int m = 0; m <= m_top; ++m) G[m] = greenc_G_series(m, kappa, t);
+        return;
+    }
+    const double u = s * s / (2.0 * (1.0 - x));
+    double complex g0, g1;
+    if (u * (cabs(kappa) + 1.0) <= 0.5) {
+        greenc_G01_far(kappa, u, &g0, &g1);
+    } else {
+        g0 = greenc_G_series(0, kappa, 1.0 - u);
+        g1 = greenc_G_series(1, kappa, 1.0 - u);
+    }
+    G[0] = g0;
+    if (m_top >= 1) G[1] = g1;
+    const double opx = 2.0 * u, omx = 1.0 - x;
+    for (int k = 0; k + 2 <= m_top; ++k) {
+        const double complex q = (k + 1.0) * (k + 1.0) + (k + 1.0) + kappa;
+        G[k + 2] = (k + 1.0) * (k + 2.0) / q * (opx / omx) * (G[k] - 2.0 * x / opx * G[k + 1]);
+    }
+}
+
+/* G_m and G_{m+1} at x: the series alone for x >= 0, else the recurrence from G_0, G_1 */
+static void greenc_G_pair(int m, double complex kappa, double x, double s, double complex* out)
+{
+    if (x >= 0.0) {
+        const double t = s * s / (2.0 * (1.0 + x));
+        out[0] = greenc_G_series(m, kappa, t);
+        out[1] = greenc_G_series(m + 1, kappa, t);
+        return;
+    }
+    double complex* G = (double complex*)malloc(sizeof(double complex) * (m + 2));
+    greenc_G_all(m + 1, kappa, x, s, G);
+    out[0] = G[m];
+    out[1] = G[m + 1];
+    free(G);
+}
+
+/* G_m at x for complex kappa = kre + i kim: out[0] = Re, out[1] = Im. */
+void orc_greenc_G(int m, double kre, double kim, double x, double s, double* out)
+{
+    double complex* G = (double complex*)malloc(sizeof(double complex) * (m + 1));
+    greenc_G_all(m, kre + I * kim, x, s, G);
+    out[0] = creal(G[m]);
+    out[1] = cimag(G[m]);
+    free(G);
+}
+
+/* J^m(z1, z2) of order 2 for the pair alpha +- i beta in the basis (g, U g); kap = {alpha, beta}. */
+void orc_jblock_green2c(int m, const double* kap, double z1, double s1, double z2, double s2, double* J)
+{
+    const int swap = z1 > z2;
+    if (swap) {
+        double t = z1; z1 = z2; z2 = t;
+        t = s1; s1 = s2; s2 = t;
+    }
+    const double complex kappa = kap[0] + I * kap[1];
+    double complex gn[2], gp[2];
+    greenc_G_pair(m, kappa, -z1, s1, gn);
+    greenc_G_pair(m, kappa, z2, s2, gp);
+    /* (Pi_m / m!^2) w^m / (-4 sin pi lambda), w as in green_J_scale */
+    double complex ratio = 1.0;
+    for (int k = 1; k <= m; ++k) ratio *= ((double)k * k - k + kappa) / ((double)k * k);
+    double wm = 1.0;
+    const double l1p = z1 >= 0.0 ? log1p(z1) : log(s1 * s1 / (1.0 - z1));
+    const double l1m = z1 >= 0.0 ? log(s1 * s1 / (1.0 + z1)) : log1p(-z1);
+    const double l2p = z2 >= 0.0 ? log1p(z2) : log(s2 * s2 / (1.0 - z2));
+    const double l2m = z2 >= 0.0 ? log(s2 * s2 / (1.0 + z2)) : log1p(-z2);
+    if (z1 != z2 && m > 0) wm = exp(0.5 * m * (l1p + l2m - l1m - l2p));
+    const double complex lam = greenc_lambda(kappa);
+    const double complex b1 = I / (2.0 * kap[1]);
+    const double complex sc = b1 * ratio * wm / (-4.0 * csin(M_PI * lam));
+    const double r1 = exp(0.5 * (l1p - l1m)), r2 = exp(0.5 * (l2m - l2p));
+    const double complex a = ((double)m * m + m + kappa) / (m + 1.0);
+    const double complex u[2] = {gn[0], -a * r1 * gn[1]};
+    const double complex v[2] = {gp[0], a * r2 * gp[1]};
+    double K[4];
+    for (int p = 0; p < 2; ++p)
+        for (int q = 0; q < 2; ++q) K[p * 2 + q] = 2.0 * creal(sc * u[p] * v[q]);
+    if (swap) {
+        J[0] = K[0]; J[1] = K[2]; J[2] = K[1]; J[3] = K[3];
+    } else {
+        for (int i = 0; i < 4; ++i) J[i] = K[i];
+    }
+}
+
 /* The same with z1 = cos(theta1), z2 = cos(theta2). */
 void orc_jblock(int order, int m, int ell_max, const double* C, double theta1, double theta2,
                 double* J)
@@ -716,7 +862,7 @@ static int grid_ok(const double* zgrid, int n_theta, int symmetric)
 /* basis 0: value and z-derivatives; 1: (g, U g) of Sec. 3 (order 2); 2: the Green's   */
 /* function of Sec. 3 at order 1, C then holding the single kappa (no band limit);     */
 /* 3: the Green's functions at order 2 in the basis (g, U g), C holding two distinct   */
-/* kappa.                                                                              */
+/* kappa; 4: the same for the complex-conjugate pair C[0] +- i C[1] (C[1] > 0).        */
 static void jblock_basis(int order, int basis, int m, int ell_max, const double* C, double z1, double s1, double z2,
                          double s2, double* J)
 {
@@ -724,6 +870,8 @@ static void jblock_basis(int order, int basis, int m, int ell_max, const double*
         orc_jblock_green(m, C[0], z1, s1, z2, s2, J);
     else if (basis == 3)
         orc_jblock_green2(m, C, z1, s1, z2, s2, J);
+    else if (basis == 4)
+        orc_jblock_green2c(m, C, z1, s1, z2, s2, J);
     else if (basis == 1)
         orc_jblock_zs_u(m, ell_max, C, z1, s1, z2, s2, J);
     else
@@ -830,7 +978,8 @@ int orc_setup_modes_zb(int order, int basis, int ell_max, const double* C, int n
 {
     if (order < 1 || order > ORC_MAXM || n_theta < 2 || ell_max < 0) return -1;
     if (basis != 0 && !(basis == 1 && order == 2) && !(basis == 2 && order == 1 && C[0] > 0.0) &&
-        !(basis == 3 && order == 2 && C[0] > 0.0 && C[1] > 0.0 && C[0] != C[1]))
+        !(basis == 3 && order == 2 && C[0] > 0.0 && C[1] > 0.0 && C[0] != C[1]) &&
+        !(basis == 4 && order == 2 && C[1] > 0.0 && isfinite(C[0]) && isfinite(C[1])))
         return -1;
     if (zgrid && !grid_ok(zgrid, n_theta, 1)) return -1;
     int total = orc_n_sets(n_theta);

@@ -1,6 +1,8 @@
-"""Pins of the oracle's Green's-function setup (Sec. 3, order 1): C_l = 1/(kappa + l(l+1))
+"""Pins of the oracle's Green's-function setup (Sec. 3): at order 1 C_l = 1/(kappa + l(l+1))
 for every l, kappa = -lambda(lambda+1), J^m from eq. (Jmatrix_efficient) with P^m_lambda of
-eq. (Legendre_hypergeometric) and no sum over l.  Each check compares with something other
+eq. (Legendre_hypergeometric) and no sum over l; at order 2 the partial fractions of eq.
+(C_ell_efficient) over two distinct real kappa or a complex-conjugate pair (the Sec. 5
+spectrum's kappa = +- i sqrt 10) in the basis (g, U g).  Each check compares with something other
 than the oracle's own formula: mpmath's Gauss hypergeometric function and Ferrers function
 of complex degree, scipy's hypergeometric function for real degree (0 < kappa <= 1/4), the
 value at z = 1, the Wronskian of DLMF 14.2.3 as the paper quotes it, the associated Legendre
@@ -201,4 +203,79 @@ def test_order2_green_chain_is_exactly_markov(orc, kappas, n):
                 sd = np.sqrt(np.outer(np.diag(V), np.diag(S)))
                 assert np.max(np.abs(X - J) / sd) < 1e-10, (m, r)
                 Jrr = orc.jblock_green2(m, kappas, z[r], z[r])
+                assert np.max(np.abs(V - Jrr) / np.sqrt(np.outer(np.diag(V), np.diag(V)))) < 1e-10, (m, r)
+
+
+# ---------------------------------------------------------------- order 2, complex-conjugate kappa
+# The Sec. 5 spectrum C_l = 1/((l(l+1))^2 + 10): kappa = +- i sqrt(10).
+BETA = np.sqrt(10.0)
+
+
+def test_complex_kappa_G_matches_mpmath(orc):
+    """G_m of complex degree for complex kappa = i sqrt(10) against mpmath's hyp2f1, on both
+    sides of the equator and next to the south pole (the continuation about t = 1)."""
+    mpmath = pytest.importorskip("mpmath")
+    kappa = 1j * BETA
+    lam = -0.5 + np.sqrt(0.25 - kappa + 0j)
+    worst = 0.0
+    for m in (0, 1, 5, 30, 120):
+        for x in (0.9, 0.3, -0.2, -0.7, -0.97, -0.9995):
+            g = orc.greenc_G(m, kappa, x)
+            ref = complex(mpmath.hyp2f1(-lam, lam + 1, 1 + m, (1 - x) / 2))
+            worst = max(worst, abs(g - ref) / abs(ref))
+    assert worst < 1e-13, worst
+
+
+def test_complex_kappa_G_reduces_to_the_real_case(orc):
+    """With a real kappa the complex-kappa path gives the real path's G_m (both degrees of the
+    real case: complex lambda for kappa > 1/4, real lambda below)."""
+    for kappa in (0.2, 40.0):
+        for m in (0, 3, 17):
+            for x in (0.5, -0.4, -0.99):
+                assert orc.greenc_G(m, kappa, x) == pytest.approx(orc.green_G(m, kappa, x), rel=1e-13)
+
+
+def test_conjugate_pair_green_matches_u_basis_sums(orc):
+    """Order 2 for kappa = +- i sqrt(10) (the partial fractions with b_1 = i / (2 sqrt 10) = -b_2,
+    whose two terms are complex conjugates) against the brute-force U-basis Legendre sums of
+    the same spectrum (C_l from the complex factors) as ell_max grows: off the diagonal to 1e-6
+    of the standard deviations at ell_max = 16000, the U U entry on it at the 1/ell_max rate."""
+    for m in (0, 2, 11):
+        for z1, z2 in ((0.2, 0.35), (-0.3, 0.1), (0.6, 0.1), (0.45, 0.45)):
+            Jg = orc.jblock_green2c(m, 0.0, BETA, z1, z2)
+            sd = np.sqrt(np.outer(np.diag(orc.jblock_green2c(m, 0.0, BETA, z1, z1)),
+                                  np.diag(orc.jblock_green2c(m, 0.0, BETA, z2, z2))))
+            worst = []
+            for lmax in (2000, 8000, 16000):
+                C = orc.spectrum_complex([1j * BETA, -1j * BETA], lmax)
+                worst.append(float((np.abs(orc.jblock_u(m, lmax, C, z1, z2) - Jg) / sd).max()))
+            assert worst[2] < worst[1] < worst[0], (m, z1, z2, worst)
+            if z1 != z2:
+                assert worst[2] < 1e-6, (m, z1, z2, worst)
+            else:
+                assert worst[2] < 1e-3 and 16000 * worst[2] == pytest.approx(8000 * worst[1], rel=0.15), worst
+
+
+@pytest.mark.parametrize("n", [64, 33])
+def test_conjugate_pair_chain_is_exactly_markov(orc, n):
+    """The order-2 chain on the conjugate-pair factors reproduces the closed-form J^m (all four
+    components) between the start ring and rings far from it, to 1e-10 of the standard
+    deviations."""
+    nphi = 2 * n if n % 2 == 0 else 2 * (n + 1)
+    A, B = orc.setup_green2c(0.0, BETA, n, nphi)
+    _, z = orc.grid(n)
+    s = orc.start_ring(n)
+    even = n % 2 == 0
+    for m in (0, 1, 5, n // 2):
+        S = B[0, m] @ B[0, m].T
+        V, X = S.copy(), S.copy()
+        for j in range(2 if even else 1, A.shape[0]):
+            r = s - j + 1 if even else s - j
+            V = A[j, m] @ V @ A[j, m].T + B[j, m] @ B[j, m].T
+            X = A[j, m] @ X
+            if (s - r) % 5 == 0:
+                J = orc.jblock_green2c(m, 0.0, BETA, z[r], z[s])
+                sd = np.sqrt(np.outer(np.diag(V), np.diag(S)))
+                assert np.max(np.abs(X - J) / sd) < 1e-10, (m, r)
+                Jrr = orc.jblock_green2c(m, 0.0, BETA, z[r], z[r])
                 assert np.max(np.abs(V - Jrr) / np.sqrt(np.outer(np.diag(V), np.diag(V)))) < 1e-10, (m, r)

@@ -77,6 +77,12 @@ enum {
                             exactly Markov.  At order 2 the state is (g, U_m g), the basis of
                             SMF_UBASIS.  Needs order * n_theta * (n_phi / 2 + 1) <= 2^27 (two setup
                             tables of that many doubles). */
+    SMF_KAPPA_PAIR = 64, /* with SMF_GREEN at order 2: kappa = {alpha, beta} names the complex-
+                            conjugate pair kappa = alpha +- i beta (beta > 0), the spectrum
+                            C_l = 1/((l(l+1) + alpha)^2 + beta^2) (the Sec. 5 example is alpha = 0,
+                            beta = sqrt(10)); the two terms of the partial fractions are complex
+                            conjugates and the Green's functions have complex degree and complex
+                            kappa.  SMF_EINVAL without SMF_GREEN at order 2. */
     SMF_UBASIS = 16      /* order 2 only, or'ed with one of the above: the chain state is
                             (g, U_m g) with the operator U_m of Sec. 3 (eq. (Jmatrix_more_efficient):
                             U_m maps P^m to P^{m+1}, so the setup sums L_{l,m+1} instead of
@@ -93,7 +99,7 @@ enum {
  *   spec      host; copied, not retained.
  *   n_theta   >= 2 rings.     n_phi  power of two in [4, 16384].
  *   flags     exactly one of SMF_FP64, SMF_FP32, optionally or'ed with SMF_NO_MIRROR,
- *             SMF_UBASIS (order 2) or SMF_GREEN (orders 1 and 2).
+ *             SMF_UBASIS (order 2) or SMF_GREEN (orders 1 and 2; with SMF_KAPPA_PAIR at order 2).
  *   out       receives the new plan (host pointer to a pointer).
  * Orders 3 and 4 take the second and third z-derivatives of L_lm from the associated
  * Legendre equation; their records hold A row-major and B's lower triangle (16 and 32

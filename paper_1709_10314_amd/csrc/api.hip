@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "batch.h"
+#include "green_pair.h"
 #include "smf_internal.h"
 
 using smf::Geometry;
@@ -210,20 +211,28 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
     const int ubasis = (flags & SMF_UBASIS) ? 1 : 0;
     const int no_mirror = (flags & SMF_NO_MIRROR) ? 1 : 0;
     const int green = (flags & SMF_GREEN) ? 1 : 0;
-    flags &= ~(SMF_UBASIS | SMF_NO_MIRROR | SMF_GREEN);
+    const int pair = (flags & SMF_KAPPA_PAIR) ? 1 : 0;
+    flags &= ~(SMF_UBASIS | SMF_NO_MIRROR | SMF_GREEN | SMF_KAPPA_PAIR);
     if (flags != SMF_FP64 && flags != SMF_FP32)
         return reject(W, "flags must hold exactly one of SMF_FP64, SMF_FP32 (SMF_FUSED is not supported)");
     if (ubasis && spec->order != 2) return reject(W, "SMF_UBASIS needs order 2");
+    if (pair && (!green || spec->order != 2)) return reject(W, "SMF_KAPPA_PAIR needs SMF_GREEN at order 2");
     if (green) {
-        // order 1 with one kappa, or order 2 with two distinct ones, all finite and positive
+        // order 1 with one kappa, or order 2 with two distinct ones, all finite and positive, or
+        // the pair alpha +- i beta given as (alpha, beta), beta > 0
         if (spec->order > 2 || ubasis || spec->c_ell || spec->n_kappa != spec->order || !spec->kappa ||
             (long long)spec->order * n_theta * (n_phi / 2 + 1) > smf::kGreenMaxTable)
             return reject(W, "SMF_GREEN needs order 1 or 2 with n_kappa = order, no c_ell, no SMF_UBASIS");
-        for (int i = 0; i < spec->n_kappa; ++i)
-            if (!(spec->kappa[i] > 0.0) || !std::isfinite(spec->kappa[i]))
-                return reject(W, "SMF_GREEN needs finite positive kappa");
-        if (spec->order == 2 && spec->kappa[0] == spec->kappa[1])
-            return reject(W, "SMF_GREEN at order 2 needs two distinct kappa");
+        if (pair) {
+            if (!std::isfinite(spec->kappa[0]) || !std::isfinite(spec->kappa[1]) || !(spec->kappa[1] > 0.0))
+                return reject(W, "SMF_KAPPA_PAIR needs a finite alpha and a finite beta > 0");
+        } else {
+            for (int i = 0; i < spec->n_kappa; ++i)
+                if (!(spec->kappa[i] > 0.0) || !std::isfinite(spec->kappa[i]))
+                    return reject(W, "SMF_GREEN needs finite positive kappa");
+            if (spec->order == 2 && spec->kappa[0] == spec->kappa[1])
+                return reject(W, "SMF_GREEN at order 2 needs two distinct kappa");
+        }
     }
     if (z_host && !grid_ok(z_host, n_theta))
         return reject(W, "z must be finite, strictly decreasing and inside (-1, 1)");
@@ -261,6 +270,9 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
     double* hn_dev = nullptr;
     int* bad_dev = nullptr;
     int bad = 0;
+    // the spectrum as given, or for the pair alpha +- i beta 1/((l(l+1) + alpha)^2 + beta^2) on the host
+    const double* c_host = spec->c_ell;
+    double* c_pair = nullptr;
     // the northern table, and for a grid with no symmetry the southern walk's own table after it
     const size_t nrec1 = (size_t)g.n_sets * g.m_rows * smf::factor_stride(g.order);
     const size_t nrec = nrec1 * (plan->asym ? 2 : 1);
@@ -268,9 +280,18 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
 
     if ((rc = bufs.alloc(&plan->C, (size_t)g.ell_max + 1))) goto fail;
     if ((rc = bufs.alloc(&bad_dev, 1))) goto fail;
-    if (spec->c_ell) {
+    if (pair) {
+        c_pair = (double*)malloc(sizeof(double) * ((size_t)g.ell_max + 1));
+        if (!c_pair) { rc = SMF_ENOMEM; goto fail; }
+        for (int l = 0; l <= g.ell_max; ++l) {
+            const double t = (double)l * (l + 1.0) + spec->kappa[0];
+            c_pair[l] = 1.0 / (t * t + spec->kappa[1] * spec->kappa[1]);
+        }
+        c_host = c_pair;
+    }
+    if (c_host) {
         if ((rc = bufs.alloc(&cexp_dev, (size_t)g.ell_max + 1))) goto fail;
-        e = hipMemcpyAsync(cexp_dev, spec->c_ell, sizeof(double) * (g.ell_max + 1),
+        e = hipMemcpyAsync(cexp_dev, c_host, sizeof(double) * (g.ell_max + 1),
                            hipMemcpyHostToDevice, st);
     } else if (spec->n_kappa > 0) {
         if ((rc = bufs.alloc(&kappa_dev, (size_t)spec->n_kappa))) goto fail;
@@ -279,10 +300,12 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
     }
     if (e != hipSuccess) { rc = SMF_EHIP; goto fail; }
     if (hipMemsetAsync(bad_dev, 0, sizeof(int), st) != hipSuccess) { rc = SMF_EHIP; goto fail; }
-    if (smf::launch_spectrum(kappa_dev, spec->c_ell ? 0 : spec->n_kappa, cexp_dev, g.ell_max,
+    if (smf::launch_spectrum(kappa_dev, c_host ? 0 : spec->n_kappa, cexp_dev, g.ell_max,
                              plan->C, bad_dev, st) != hipSuccess) { rc = SMF_EHIP; goto fail; }
     if (hipMemcpyAsync(&bad, bad_dev, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) { rc = SMF_EHIP; goto fail; }
+    free(c_pair);
+    c_pair = nullptr;
     if (bad) { rc = SMF_ENUMERIC; goto fail; }
 
     if ((rc = bufs.alloc(&plan->f64, nrec))) goto fail;
@@ -299,7 +322,20 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
         }
     }
     plan->south_off = plan->asym ? nrec1 : 0;
-    if (green) {
+    if (green && pair) {
+        // kappa_1's complex tables: 2 doubles per entry
+        const size_t nt = (size_t)2 * n_theta * (g.m_rows + 1);
+        if ((rc = bufs.alloc(&hp_dev, nt))) goto fail;
+        if ((rc = bufs.alloc(&hn_dev, nt))) goto fail;
+        if (smf::launch_green_pair(g, spec->kappa[0], spec->kappa[1], z_dev, 0, hp_dev, hn_dev, plan->f64, plan->f32,
+                                   st) != hipSuccess ||
+            (plan->asym && smf::launch_green_pair(g, spec->kappa[0], spec->kappa[1], z_dev, 1, hp_dev, hn_dev,
+                                                  plan->f64 + nrec1, plan->f32 ? plan->f32 + nrec1 : nullptr, st) !=
+                               hipSuccess)) {
+            rc = SMF_EHIP;
+            goto fail;
+        }
+    } else if (green) {
         const size_t nt = (size_t)spec->n_kappa * n_theta * (g.m_rows + 1);
         if ((rc = bufs.alloc(&hp_dev, nt))) goto fail;
         if ((rc = bufs.alloc(&hn_dev, nt))) goto fail;
@@ -356,7 +392,7 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
     log_line(1, "setup: order %d, %d x %d rings x longitudes, ell_max %d (m_top %d), %s%s%s%s%s, %d factor sets x %d mode "
              "rows (%.1f MB of factors), %s walk",
              g.order, n_theta, n_phi, g.ell_max, g.m_top, flags == SMF_FP64 ? "FP64" : "FP32", ubasis ? ", U basis" : "",
-             green ? ", Green's functions" : "", z_host ? ", explicit grid" : "", plan->asym ? ", own southern sets" : "",
+             green ? (pair ? ", Green's functions of a conjugate kappa pair" : ", Green's functions") : "", z_host ? ", explicit grid" : "", plan->asym ? ", own southern sets" : "",
              g.n_sets, g.m_rows,
              (double)nrec1 * (plan->asym ? 2 : 1) * (8.0 + (flags == SMF_FP32 ? 4.0 : 0.0)) / 1e6,
              plan->scan_fine > 1 ? "scan-capable" : "plain");
@@ -365,6 +401,7 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
 fail:
     (void)hipStreamSynchronize(st);
     bufs.free_all();
+    free(c_pair);
     free(plan->zgrid);
     free(plan);
     log_line(1, "smf_setup: failed: %s", smf_error_string(rc));

@@ -1,6 +1,7 @@
 // FP64 setup on the GPU: spectrum, cross-covariance blocks by Legendre sums, and the
 // transition / innovation / start factors of every (mode, ring step)
 // (Creasey & Lang, Alg. 1; Lemma 2.1; eqs. (trans_matrix), (innov_matrix), (state_initial)).
+#include "green_pair.h"
 #include "smf_internal.h"
 
 namespace smf {
@@ -934,6 +935,270 @@ __global__ __launch_bounds__(64) void green2_factor_kernel(Geometry g, const dou
     }
 }
 
+// ---- Sec. 3 for a complex-conjugate pair kappa = alpha +- i beta (order 2, basis (g, U g)) ----
+// The order-1 formulas hold with complex arithmetic: lambda = -1/2 + sqrt(1/4 - kappa),
+// G_m by its series (x >= 0) or by the continuation about t = 1 and the m-recurrence (x < 0),
+// J^m_kappa = (Pi_m / m!^2) w^m G_m(-z1) G_m(z2) / (-4 sin pi lambda).  The kappa_2 term of the
+// partial fractions is the complex conjugate of the kappa_1 term, b_1 = i / (2 beta), so
+// J_pq = 2 Re[b_1 (...)_1]: only kappa_1's tables are built.
+struct Zd {
+    double re, im;
+};
+__device__ __host__ inline Zd zadd(Zd a, Zd b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __host__ inline Zd zsub(Zd a, Zd b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __host__ inline Zd zmul(Zd a, Zd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __host__ inline Zd zscale(Zd a, double s) { return {a.re * s, a.im * s}; }
+__device__ __host__ inline Zd zdiv(Zd a, Zd b)
+{
+    const double d = b.re * b.re + b.im * b.im;
+    return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+__device__ __host__ inline double zabs(Zd a) { return hypot(a.re, a.im); }
+
+struct GreenConstC {
+    Zd kappa;
+    Zd lam;      // -1/2 + sqrt(1/4 - kappa)
+    Zd g;        // -sin(pi lambda) / pi = 1 / (Gamma(-lambda) Gamma(lambda + 1))
+    Zd sc;       // 1 / (-4 sin pi lambda)
+    double beta;
+};
+
+GreenConstC greenc_const(double alpha, double beta)
+{
+    GreenConstC c;
+    c.kappa = {alpha, beta};
+    // principal square root of 1/4 - kappa
+    const double xr = 0.25 - alpha, xi = -beta;
+    const double r = hypot(xr, xi);
+    double sr = sqrt(0.5 * (r + xr)), si = sqrt(0.5 * (r - xr));
+    if (xi < 0.0) si = -si;
+    c.lam = {-0.5 + sr, si};
+    // sin(pi (a + i b)) = sin(pi a) cosh(pi b) + i cos(pi a) sinh(pi b)
+    const Zd sn = {sin(M_PI * c.lam.re) * cosh(M_PI * c.lam.im), cos(M_PI * c.lam.re) * sinh(M_PI * c.lam.im)};
+    c.g = zscale(sn, -1.0 / M_PI);
+    c.sc = zdiv({1.0, 0.0}, zscale(sn, -4.0));
+    c.beta = beta;
+    return c;
+}
+
+__device__ Zd greenc_series(int m, Zd kappa, double t)
+{
+    Zd acc = {1.0, 0.0}, term = {1.0, 0.0};
+    for (int n = 0; n < 1000000; ++n) {
+        const double dn = (double)n;
+        const double den = t / ((dn + 1.0) * (dn + 1.0 + (double)m));
+        const Zd r = {(dn * dn + dn + kappa.re) * den, kappa.im * den};
+        term = zmul(term, r);
+        acc = zadd(acc, term);
+        if (zabs(r) < 1.0 && zabs(term) < 1e-18 * zabs(acc)) break;
+    }
+    return acc;
+}
+
+// digamma at z (not a pole): shifted up to Re z >= 20 by psi(z) = psi(z + 1) - 1/z, then the
+// asymptotic series log z - 1/(2z) - 1/(12 z^2) + 1/(120 z^4) - 1/(252 z^6) + 1/(240 z^8) - 1/(132 z^10)
+__device__ Zd zdigamma(Zd z)
+{
+    Zd shift = {0.0, 0.0};
+    while (z.re < 20.0) {
+        shift = zadd(shift, zdiv({1.0, 0.0}, z));
+        z.re += 1.0;
+    }
+    const Zd w = zdiv({1.0, 0.0}, z);
+    const Zd w2 = zmul(w, w), w4 = zmul(w2, w2), w6 = zmul(w4, w2), w8 = zmul(w4, w4), w10 = zmul(w8, w2);
+    Zd v = {log(zabs(z)), atan2(z.im, z.re)};
+    v = zsub(v, zscale(w, 0.5));
+    v = zsub(v, zscale(w2, 1.0 / 12.0));
+    v = zadd(v, zscale(w4, 1.0 / 120.0));
+    v = zsub(v, zscale(w6, 1.0 / 252.0));
+    v = zadd(v, zscale(w8, 1.0 / 240.0));
+    v = zsub(v, zscale(w10, 1.0 / 132.0));
+    return zsub(v, shift);
+}
+
+// H_0 and H_1 at t = 1 - u from the continuation about t = 1 (as green_h01_far, complex)
+__device__ void greenc_h01_far(const GreenConstC& c, double u, Zd& h0, Zd& h1)
+{
+    const double lu = log(u);
+    const Zd mlam = {-c.lam.re, -c.lam.im}, lam1 = {c.lam.re + 1.0, c.lam.im};
+    Zd ck = {1.0, 0.0}, dk = {1.0, 0.0}, s0 = {0.0, 0.0}, s1 = {0.0, 0.0};
+    double uk = 1.0, psi1 = -0.57721566490153286061;    // psi(1)
+    for (int k = 0; k < 100000; ++k) {
+        const double dkk = (double)k;
+        const double psi2 = psi1 + 1.0 / (dkk + 1.0);
+        const Zd pp0 = zadd(zdigamma({mlam.re + dkk, mlam.im}), zdigamma({lam1.re + dkk, lam1.im}));
+        const Zd pp1 = zadd(zdigamma({mlam.re + dkk + 1.0, mlam.im}), zdigamma({lam1.re + dkk + 1.0, lam1.im}));
+        const Zd e0 = zscale(zmul(ck, {lu - 2.0 * psi1 + pp0.re, pp0.im}), uk);
+        const Zd e1 = zscale(zmul(dk, {lu - psi1 - psi2 + pp1.re, pp1.im}), uk);
+        s0 = zadd(s0, e0);
+        s1 = zadd(s1, e1);
+        const Zd rc = zscale({dkk * dkk + dkk + c.kappa.re, c.kappa.im}, 1.0 / ((dkk + 1.0) * (dkk + 1.0)));
+        ck = zmul(ck, rc);
+        dk = zmul(dk, zscale({(dkk + 1.0) * (dkk + 2.0) + c.kappa.re, c.kappa.im}, 1.0 / ((dkk + 1.0) * (dkk + 2.0))));
+        uk *= u;
+        psi1 = psi2;
+        if (k > 4 && zabs(rc) * u < 0.9 && zabs(e0) < 1e-18 * zabs(s0) && zabs(e1) < 1e-18 * zabs(s1)) break;
+    }
+    h0 = zscale(zmul(c.g, s0), -1.0);
+    h1 = zadd(zdiv(c.g, c.kappa), zscale(zmul(c.g, s1), u));
+}
+
+// The tables of kappa_1, complex values interleaved (re, im): as green_series_kernel and
+// green_recur_kernel.
+__global__ __launch_bounds__(64) void greenc_series_kernel(Geometry g, const double* __restrict__ zgrid, GreenConstC c,
+                                                           int m_hi, int w, double* __restrict__ hp,
+                                                           double* __restrict__ hn)
+{
+    const int m = blockIdx.x * 64 + threadIdx.x;
+    const int i = blockIdx.y;
+    if (m > m_hi) return;
+    double z, sn;
+    green_ring(g, zgrid, i, z, sn);
+    const size_t o = 2 * ((size_t)i * w + m);
+    if (z >= 0.0) {
+        const Zd v = greenc_series(m, c.kappa, sn * sn / (2.0 * (1.0 + z)));
+        hp[o] = v.re;
+        hp[o + 1] = v.im;
+    }
+    if (z <= 0.0) {
+        const Zd v = greenc_series(m, c.kappa, sn * sn / (2.0 * (1.0 - z)));
+        hn[o] = v.re;
+        hn[o + 1] = v.im;
+    }
+}
+
+__global__ __launch_bounds__(64) void greenc_recur_kernel(Geometry g, const double* __restrict__ zgrid, GreenConstC c,
+                                                          int m_hi, int w, double* __restrict__ hp,
+                                                          double* __restrict__ hn)
+{
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i >= g.n_theta) return;
+    double z, sn;
+    green_ring(g, zgrid, i, z, sn);
+    if (z == 0.0) return;
+    const double x = -fabs(z);
+    double* __restrict__ h = (z > 0.0 ? hn : hp) + 2 * (size_t)i * w;
+    const double u = sn * sn / (2.0 * (1.0 - x));
+    Zd h0, h1;
+    if (u * (zabs(c.kappa) + 1.0) <= 0.5) {
+        greenc_h01_far(c, u, h0, h1);
+    } else {
+        h0 = greenc_series(0, c.kappa, 1.0 - u);
+        h1 = greenc_series(1, c.kappa, 1.0 - u);
+    }
+    h[0] = h0.re;
+    h[1] = h0.im;
+    if (m_hi >= 1) {
+        h[2] = h1.re;
+        h[3] = h1.im;
+    }
+    const double opx = 2.0 * u, omx = 1.0 - x;
+    const double ratio = opx / omx, cross = -2.0 * x / opx;
+    for (int k = 0; k + 2 <= m_hi; ++k) {
+        const double dk = (double)k;
+        const Zd q = {(dk + 1.0) * (dk + 2.0) + c.kappa.re, c.kappa.im};
+        const Zd f = zdiv({(dk + 1.0) * (dk + 2.0) * ratio, 0.0}, q);
+        const Zd h2 = zmul(f, zadd(h0, zscale(h1, cross)));
+        h[2 * (k + 2)] = h2.re;
+        h[2 * (k + 2) + 1] = h2.im;
+        h0 = h1;
+        h1 = h2;
+    }
+}
+
+// J_pq between rings 1 (lower value) and 2 from kappa_1's tables: hn1[k] = G_{m+k}(-z1),
+// hp2[k] = G_{m+k}(z2), rm = Pi_m / m!^2 of kappa_1
+__device__ void greenc2_pair(const GreenConstC& c, Zd rm, int m, double z1, double s1, double z2, double s2,
+                             const Zd (&hn1)[2], const Zd (&hp2)[2], double (&J)[4])
+{
+    double wm = 1.0, lp1, lm1, lp2, lm2;
+    green_logs(z1, s1, lp1, lm1);
+    green_logs(z2, s2, lp2, lm2);
+    if (z1 != z2 && m > 0) wm = exp(0.5 * (double)m * ((lp1 - lm1) + (lm2 - lp2)));
+    const double r1 = exp(0.5 * (lp1 - lm1)), r2 = exp(0.5 * (lm2 - lp2));
+    // 2 b_1 = i / beta
+    const Zd sc = zmul({0.0, 1.0 / c.beta}, zscale(zmul(rm, c.sc), wm));
+    const Zd a = zscale({(double)m * m + m + c.kappa.re, c.kappa.im}, 1.0 / (m + 1.0));
+    const Zd u[2] = {hn1[0], zscale(zmul(a, hn1[1]), -r1)};
+    const Zd v[2] = {hp2[0], zscale(zmul(a, hp2[1]), r2)};
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) J[p * 2 + q] = zmul(sc, zmul(u[p], v[q])).re;
+}
+
+// One thread per (set j, mode m) for the conjugate pair, sets and mirror as in factor_kernel.
+__global__ __launch_bounds__(64) void greenc2_factor_kernel(Geometry g, const double* __restrict__ zgrid, GreenConstC c,
+                                                            int south, int w, const double* __restrict__ hp,
+                                                            const double* __restrict__ hn, double* __restrict__ f64,
+                                                            float* __restrict__ f32)
+{
+    const int j = blockIdx.x * 64 + threadIdx.x;
+    const int m = blockIdx.y;
+    if (j >= g.n_sets) return;
+    const bool mirror = south && j >= (g.even ? 2 : 1);
+    int a, b;
+    if (mirror) {
+        a = g.s + j - 1; b = g.s + j;
+    } else if (j == 0) {
+        a = b = g.s;
+    } else if (g.even) {
+        if (j == 1) { a = g.s; b = g.s + 1; }
+        else { a = g.s - j + 2; b = g.s - j + 1; }
+    } else {
+        a = g.s - j + 1; b = g.s - j;
+    }
+    Zd rm = {1.0, 0.0};
+    for (int k = 1; k <= m; ++k) {
+        const double dk = (double)k;
+        rm = zmul(rm, zscale({dk * dk - dk + c.kappa.re, c.kappa.im}, 1.0 / (dk * dk)));
+    }
+    double za, sa, zb, sb;
+    green_ring(g, zgrid, a, za, sa);
+    green_ring(g, zgrid, b, zb, sb);
+    Zd hna[2], hpa[2], hnb[2], hpb[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const size_t oa = 2 * ((size_t)a * w + m + k), ob = 2 * ((size_t)b * w + m + k);
+        hna[k] = {hn[oa], hn[oa + 1]};
+        hpa[k] = {hp[oa], hp[oa + 1]};
+        hnb[k] = {hn[ob], hn[ob + 1]};
+        hpb[k] = {hp[ob], hp[ob + 1]};
+    }
+    double Ja[4], Jb[4], Jx[4];
+    greenc2_pair(c, rm, m, za, sa, za, sa, hna, hpa, Ja);
+    const double kaa[3] = {Ja[0], 0.5 * (Ja[1] + Ja[2]), Ja[3]};
+    double A[4] = {0, 0, 0, 0}, B[3];
+    if (j == 0) {
+        start_m2(kaa, B);
+    } else {
+        greenc2_pair(c, rm, m, zb, sb, zb, sb, hnb, hpb, Jb);
+        const double kbb[3] = {Jb[0], 0.5 * (Jb[1] + Jb[2]), Jb[3]};
+        double kba[4];
+        if (zb <= za) {
+            greenc2_pair(c, rm, m, zb, sb, za, sa, hnb, hpa, Jx);
+            kba[0] = Jx[0]; kba[1] = Jx[1]; kba[2] = Jx[2]; kba[3] = Jx[3];
+        } else {
+            greenc2_pair(c, rm, m, za, sa, zb, sb, hna, hpb, Jx);
+            kba[0] = Jx[0]; kba[1] = Jx[2]; kba[2] = Jx[1]; kba[3] = Jx[3];
+        }
+        factors_m2(kaa, kbb, kba, A, B);
+    }
+    if (mirror) {
+        A[1] = -A[1];
+        A[2] = -A[2];
+        B[1] = -B[1];
+    }
+    const size_t base = ((size_t)j * g.m_rows + m) * factor_stride(2);
+    const double v[8] = {A[0], A[1], A[2], A[3], B[0], B[1], B[2], 0.0};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) f64[base + i] = v[i];
+    if (f32) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) f32[base + i] = (float)v[i];
+    }
+}
+
 }  // namespace
 
 hipError_t launch_phi(const Geometry& g, const double* f64, int blocks, double* phi64, float* phi32,
@@ -1018,6 +1283,25 @@ hipError_t launch_twiddles(int n_phi, double* tw64, float* tw32, hipStream_t st)
 {
     hipLaunchKernelGGL(twiddle_kernel, dim3((n_phi + 255) / 256), dim3(256), 0, st, n_phi, tw64,
                        tw32);
+    return hipGetLastError();
+}
+
+hipError_t launch_green_pair(const Geometry& g, double alpha, double beta, const double* z_dev, int south,
+                              double* hp, double* hn, double* f64, float* f32, hipStream_t st)
+{
+    if (g.order != 2 || !(beta > 0.0)) return hipErrorInvalidValue;
+    const GreenConstC c = greenc_const(alpha, beta);
+    const int m_hi = g.m_top + 1, w = g.m_rows + 1;
+    hipLaunchKernelGGL(greenc_series_kernel, dim3((m_hi + 64) / 64, g.n_theta), dim3(64), 0, st, g, z_dev, c, m_hi, w,
+                       hp, hn);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(greenc_recur_kernel, dim3((g.n_theta + 63) / 64), dim3(64), 0, st, g, z_dev, c, m_hi, w, hp,
+                       hn);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 grid((g.n_sets + 63) / 64, g.m_top + 1);
+    hipLaunchKernelGGL(greenc2_factor_kernel, grid, dim3(64), 0, st, g, z_dev, c, south, w, hp, hn, f64, f32);
     return hipGetLastError();
 }
 

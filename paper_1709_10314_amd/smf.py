@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsmf.so")
 
 SMF_OK, SMF_EINVAL, SMF_ENOMEM, SMF_EHIP, SMF_ENUMERIC = 0, -1, -2, -3, -4
-SMF_FP64, SMF_FP32, SMF_NO_MIRROR, SMF_FUSED, SMF_UBASIS, SMF_GREEN = 1, 2, 4, 8, 16, 32
+SMF_FP64, SMF_FP32, SMF_NO_MIRROR, SMF_FUSED, SMF_UBASIS, SMF_GREEN, SMF_KAPPA_PAIR = 1, 2, 4, 8, 16, 32, 64
 
 # every symbol include/smf.h declares
 EXPORTS = ("smf_setup", "smf_setup_grid", "smf_sample", "smf_sample_lognormal", "smf_sample_modes", "smf_transform", "smf_set_ring_blocks",
@@ -438,17 +438,20 @@ class Plan:
     """A setup plan (Alg. 1 factors on the GPU) with sampling methods (Alg. 2)."""
 
     def __init__(self, order, n_theta, n_phi, ell_max, kappa=None, c_ell=None, precision="fp32",
-                 stream=None, z=None, basis="z", mirror=True, green=False):
+                 stream=None, z=None, basis="z", mirror=True, green=False, kappa_pair=False):
         """basis: "z" (the state is the value and its z-derivatives) or "u" (order 2: (g, U g)
         of Sec. 3, SMF_UBASIS).  mirror=False stores the southern walk's own factor sets
         (SMF_NO_MIRROR).  green=True (order 1 with one kappa, order 2 with two distinct ones): the
         Green's-function setup of Sec. 3 for eq. (Cl) without band limit (SMF_GREEN; ell_max is
-        ignored; at order 2 the state is (g, U g))."""
+        ignored; at order 2 the state is (g, U g)).  kappa_pair=True with green at order 2:
+        kappa = (alpha, beta) names the pair alpha +- i beta (SMF_KAPPA_PAIR)."""
         flags = {"fp32": SMF_FP32, "fp64": SMF_FP64}[precision] | {"z": 0, "u": SMF_UBASIS}[basis]
         if not mirror:
             flags |= SMF_NO_MIRROR
         if green:
             flags |= SMF_GREEN
+        if kappa_pair:
+            flags |= SMF_KAPPA_PAIR
         rc, h = smf_setup(order, n_theta, n_phi, ell_max, kappa=kappa, c_ell=c_ell, flags=flags,
                           stream=stream, z=z)
         if rc != SMF_OK:

@@ -52,6 +52,16 @@ int main(void)
     expect(smf_setup(&one, 8, 32, SMF_FP64 | SMF_UBASIS, NULL, &plan), SMF_EINVAL, SMF_EINVAL, "U basis order 1");
     smf_spectrum same = {2, 2, (const double[]){4.0, 4.0}, NULL, 16};
     expect(smf_setup(&same, 8, 32, SMF_FP64 | SMF_GREEN, NULL, &plan), SMF_EINVAL, SMF_EINVAL, "Green repeated kappa");
+    smf_spectrum pair0 = {2, 2, (const double[]){0.0, 0.0}, NULL, 0};
+    expect(smf_setup(&pair0, 8, 32, SMF_FP64 | SMF_GREEN | SMF_KAPPA_PAIR, NULL, &plan), SMF_EINVAL, SMF_EINVAL,
+           "pair beta 0");
+    smf_spectrum pair1 = {2, 2, (const double[]){0.0, 3.0}, NULL, 0};
+    expect(smf_setup(&pair1, 8, 32, SMF_FP64 | SMF_KAPPA_PAIR, NULL, &plan), SMF_EINVAL, SMF_EINVAL,
+           "pair without Green");
+    plan = NULL;
+    expect(smf_setup(&pair1, 8, 32, SMF_FP64 | SMF_GREEN | SMF_KAPPA_PAIR, NULL, &plan), SMF_EHIP, SMF_OK,
+           "pair valid");
+    if (plan) smf_destroy(plan);
     smf_spectrum explicit_c = {1, 0, NULL, c_ell, 16};
     expect(smf_setup(&explicit_c, 8, 32, SMF_FP32, NULL, &plan), SMF_EHIP, SMF_OK, "setup explicit C_l");
     expect(smf_setup(&ok, 8, 32, SMF_FP64, NULL, &plan), SMF_EHIP, SMF_OK, "setup valid");

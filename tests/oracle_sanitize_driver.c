@@ -17,6 +17,8 @@ void orc_legendre(int m, int ell_max, double theta, double* L, double* dL);
 void orc_jblock(int order, int m, int ell_max, const double* C, double theta1, double theta2, double* J);
 void orc_jblock_green(int m, double kappa, double z1, double s1, double z2, double s2, double* J);
 void orc_jblock_green2(int m, const double* kap, double z1, double s1, double z2, double s2, double* J);
+void orc_jblock_green2c(int m, const double* kap, double z1, double s1, double z2, double s2, double* J);
+void orc_greenc_G(int m, double kre, double kim, double x, double s, double* out);
 double orc_green_G(int m, double kappa, double x, double s);
 double orc_green_P(int m, double kappa, double x, double s);
 int orc_setup_modes_zb(int order, int basis, int ell_max, const double* C, int n_theta, const double* zgrid,
@@ -108,6 +110,8 @@ int main(void)
     const double kg1[1] = {40.0}, kg2[2] = {16.0, 400.0};
     setup_and_sample(1, 2, 0, kg1, 8, n_phi, NULL, 0, "Green order 1");
     setup_and_sample(2, 3, 0, kg2, 7, n_phi, NULL, 0, "Green order 2");
+    const double kpair[2] = {0.0, sqrt(10.0)};
+    setup_and_sample(2, 4, 0, kpair, 8, n_phi, NULL, 0, "Green order 2, conjugate pair");
     /* the paper's complex pair kappa = +-i sqrt(10) */
     const double kre[2] = {0.0, 0.0}, kim[2] = {sqrt(10.0), -sqrt(10.0)};
     check(orc_spectrum_complex(2, kre, kim, ell_max, C) == 0, "complex spectrum");
@@ -119,6 +123,10 @@ int main(void)
     orc_jblock(3, 2, ell_max, C, 0.4, 1.1, J);
     orc_jblock_green(5, 40.0, -0.3, sqrt(1 - 0.09), 0.6, 0.8, J);
     orc_jblock_green2(5, kg2, -0.3, sqrt(1 - 0.09), 0.6, 0.8, J);
+    orc_jblock_green2c(5, kpair, -0.3, sqrt(1 - 0.09), 0.6, 0.8, J);
+    double gc[2];
+    orc_greenc_G(7, 2.0, 5.0, -0.95, sqrt(1 - 0.95 * 0.95), gc);
+    check(isfinite(gc[0]) && isfinite(gc[1]), "Green G, complex degree");
     check(isfinite(orc_green_G(7, 0.2, -0.95, sqrt(1 - 0.95 * 0.95))), "Green G, real degree");
     check(isfinite(orc_green_P(7, 40.0, 0.5, sqrt(0.75))), "Green P");
     const uint32_t ctr[4] = {1u, 2u, 3u, 4u}, key[2] = {5u, 6u};

@@ -182,3 +182,85 @@ def test_green2_rejects_repeated_or_missing_kappa():
                dict(order=2, kappa=[50.0, 0.0])):
         rc, _ = smf.smf_setup(kw["order"], 16, 32, 15, kappa=kw["kappa"], flags=smf.SMF_FP64 | smf.SMF_GREEN)
         assert rc == smf.SMF_EINVAL, kw
+
+
+# ---------------------------------------------------------------- order 2, complex-conjugate kappa pair
+# (alpha, beta): kappa = alpha +- i beta; (0, sqrt 10) is the Sec. 5 spectrum 1/((l(l+1))^2 + 10)
+CASES2C = [(64, 128, (0.0, float(np.sqrt(10.0)))), (256, 512, (0.0, float(np.sqrt(10.0)))), (33, 64, (2.0, 5.0)),
+           (128, 256, (-3.0, 1.5))]
+
+
+def _plan2c(n, nphi, ab, precision):
+    from paper_1709_10314_amd import Plan
+
+    return Plan(2, n, nphi, 0, kappa=list(ab), precision=precision, green=True, kappa_pair=True)
+
+
+@pytest.mark.parametrize("case", CASES2C, ids=lambda c: f"{c[0]}x{c[1]}-a{c[2][0]:g}-b{c[2][1]:.3g}")
+def test_green_pair_factors_and_fields_match_oracle(case):
+    """The GPU setup for the conjugate pair against the oracle's: factors by their action on the
+    chain's law within ten times the oracle's own movement when alpha and beta move by one unit
+    in the last place (of beta's size), FP64 fields to 1e-10 relative RMS (1e-9 element-wise),
+    FP32 fields to 1e-4."""
+    n, nphi, (alpha, beta) = case
+    p = _plan2c(n, nphi, (alpha, beta), "fp64")
+    Ag, Bg = p.factors()
+    T = p.sample(17, 2).double().cpu().numpy()
+    torch.cuda.synchronize()
+    p.close()
+    Ao, Bo = oracle.setup_green2c(alpha, beta, n, nphi)
+    dA, dS, amb = factor_errors(Ag, Bg, Ao, Bo, n)
+    ulp = 2.0 ** -52 * max(abs(alpha), beta)
+    Ap, Bp = oracle.setup_green2c(alpha + ulp, beta - ulp, n, nphi)
+    sA, sS, _ = factor_errors(Ap, Bp, Ao, Bo, n)
+    To, _ = oracle.sample(2, n, nphi, Ao, Bo, 17, 2)
+    e = max(rel_rms(T[f], To[f]) for f in range(2))
+    emax = max(max_rel_err(T[f], To[f]) for f in range(2))
+    log(f"green pair {n}x{nphi} alpha {alpha} beta {beta:.4g}: factors dA {dA:.2e} dS {dS:.2e} ({amb} near a "
+        f"threshold), oracle's one-ulp sensitivity dA {sA:.2e} dS {sS:.2e}; fields rel RMS {e:.2e}, max {emax:.2e}")
+    assert dA <= 10 * sA + 1e-13 and dS <= 10 * sS + 1e-13
+    assert e <= 1e-10 and emax <= 1e-9
+    p32 = _plan2c(n, nphi, (alpha, beta), "fp32")
+    T32 = p32.sample(17, 2).double().cpu().numpy()
+    torch.cuda.synchronize()
+    p32.close()
+    e32 = max(rel_rms(T32[f], To[f]) for f in range(2))
+    log(f"  fp32 fields rel RMS {e32:.2e}")
+    assert e32 <= 1e-4
+
+
+@pytest.mark.parametrize("case", CASES2C[:2], ids=lambda c: f"{c[0]}x{c[1]}")
+def test_green_pair_chain_has_no_markov_defect(case):
+    """All four components of J^m between the start ring and rings far from it, from the device's
+    FP64 factors for the Sec. 5 spectrum, against the closed form, to 1e-10 of the standard
+    deviations: the band-limit defect the Legendre-sum setup leaves for this spectrum is gone."""
+    n, nphi, (alpha, beta) = case
+    p = _plan2c(n, nphi, (alpha, beta), "fp64")
+    A, B = p.factors()
+    p.close()
+    _, z = oracle.grid(n)
+    s = oracle.start_ring(n)
+    worst = 0.0
+    for m in (0, 1, 7, nphi // 8):
+        S = B[0, m] @ B[0, m].T
+        V, X = S.copy(), S.copy()
+        for j in range(2, A.shape[0]):
+            r = s - j + 1
+            V = A[j, m] @ V @ A[j, m].T + B[j, m] @ B[j, m].T
+            X = A[j, m] @ X
+            if (s - r) % 7 == 0:
+                J = oracle.jblock_green2c(m, alpha, beta, z[r], z[s])
+                sd = np.sqrt(np.outer(np.diag(V), np.diag(S)))
+                worst = max(worst, float(np.max(np.abs(X - J) / sd)))
+    log(f"green pair {n}x{nphi}: largest cross-covariance error {worst:.2e} of the sd products")
+    assert worst <= 1e-10
+
+
+def test_green_pair_rejects_what_it_does_not_cover():
+    from paper_1709_10314_amd import smf
+
+    F = smf.SMF_FP64 | smf.SMF_GREEN | smf.SMF_KAPPA_PAIR
+    for order, kap, flags in ((2, [0.0, 0.0], F), (2, [0.0, -1.0], F), (1, [3.0], F), (2, [float("nan"), 1.0], F),
+                              (2, [0.0, 3.0], smf.SMF_FP64 | smf.SMF_KAPPA_PAIR)):
+        rc, _ = smf.smf_setup(order, 16, 32, 15, kappa=kap, flags=flags)
+        assert rc == smf.SMF_EINVAL, (order, kap, flags)

@@ -226,6 +226,21 @@ def test_complex_kappa_G_matches_mpmath(orc):
     assert worst < 1e-13, worst
 
 
+def test_complex_kappa_with_real_part_G_matches_mpmath(orc):
+    """G_m for kappa = alpha + i beta with alpha != 0 (the pairs 2 +- 5i and -3 +- 1.5i, the
+    second with Re kappa < 0) against mpmath's hyp2f1, on both sides of the equator."""
+    mpmath = pytest.importorskip("mpmath")
+    worst = 0.0
+    for kappa in (2.0 + 5.0j, -3.0 + 1.5j, -3.0 - 1.5j):
+        lam = -0.5 + np.sqrt(0.25 - kappa + 0j)
+        for m in (0, 1, 6, 40):
+            for x in (0.8, 0.1, -0.5, -0.95, -0.999):
+                g = orc.greenc_G(m, kappa, x)
+                ref = complex(mpmath.hyp2f1(-lam, lam + 1, 1 + m, (1 - x) / 2))
+                worst = max(worst, abs(g - ref) / abs(ref))
+    assert worst < 1e-12, worst
+
+
 def test_complex_kappa_G_reduces_to_the_real_case(orc):
     """With a real kappa the complex-kappa path gives the real path's G_m (both degrees of the
     real case: complex lambda for kappa > 1/4, real lambda below)."""
@@ -254,6 +269,22 @@ def test_conjugate_pair_green_matches_u_basis_sums(orc):
                 assert worst[2] < 1e-6, (m, z1, z2, worst)
             else:
                 assert worst[2] < 1e-3 and 16000 * worst[2] == pytest.approx(8000 * worst[1], rel=0.15), worst
+
+
+@pytest.mark.parametrize("alpha,beta", [(2.0, 5.0), (-3.0, 1.5)])
+def test_conjugate_pair_with_real_part_matches_u_basis_sums(orc, alpha, beta):
+    """The same check for pairs alpha +- i beta with alpha != 0, C_l = 1/((l(l+1) + alpha)^2 +
+    beta^2), off the diagonal: the sums approach the closed form as ell_max grows."""
+    for m in (0, 3):
+        for z1, z2 in ((-0.3, 0.1), (0.6, 0.1)):
+            Jg = orc.jblock_green2c(m, alpha, beta, z1, z2)
+            sd = np.sqrt(np.outer(np.diag(orc.jblock_green2c(m, alpha, beta, z1, z1)),
+                                  np.diag(orc.jblock_green2c(m, alpha, beta, z2, z2))))
+            worst = []
+            for lmax in (2000, 8000):
+                C = orc.spectrum_complex([alpha + 1j * beta, alpha - 1j * beta], lmax)
+                worst.append(float((np.abs(orc.jblock_u(m, lmax, C, z1, z2) - Jg) / sd).max()))
+            assert worst[1] < worst[0] and worst[1] < 1e-6, (m, z1, z2, worst)
 
 
 @pytest.mark.parametrize("n", [64, 33])

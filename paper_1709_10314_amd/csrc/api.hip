@@ -814,7 +814,7 @@ int smf_setup_rings(const smf_spectrum* spec, int n_theta, const double* z_host,
             if (spec_n[c] == 0 || spec_h.back() != h) {
                 spec_h.push_back(h);
                 spec_at.push_back(spec_total);
-                spec_total += (int64_t)1 << (smf::kRingFftMinLog2 + c);
+                spec_total += (int64_t)2 << (smf::kRingFftMinLog2 + c);   // S, c and D
                 ++spec_n[c];
             }
             spec_off[i] = spec_at.back();
@@ -916,7 +916,7 @@ int smf_setup_rings(const smf_spectrum* spec, int n_theta, const double* z_host,
             if (used >= sizeof(cls)) break;
         }
         log_line(1, "setup_rings: %d rings, %lld pixels per field, largest %d, chains at n_phi %d; rings by transform "
-                 "class:%s general %d (chirp-z %d); %lld Bluestein kernel transforms (%.1f MB); %s",
+                 "class:%s general %d (chirp-z %d); %lld Bluestein half-lengths (tables %.1f MB); %s",
                  n_theta, (long long)off[n_theta], n_max, n_phi, cls, rs.n_direct + rs.n_chirp, rs.n_chirp,
                  (long long)spec_h.size(), (double)spec_total * (fp64 ? 16 : 8) / 1e6,
                  plan->ring_aux[0] ? "launches spread over 3 more streams" : "one stream");
@@ -961,8 +961,11 @@ static int synthesize_rings(const smf_plan* plan, int count, const void* g_dev, 
     const bool general = rs.n_direct + rs.n_chirp > 0;
     const bool fork = SMF_RING_FORK && plan->ring_aux[0] != nullptr && fft.size() + (general ? 1 : 0) > 1;
     // with several launches the general kernel's pair stays on the caller's stream and the
-    // classes go round robin to the plan's other streams, forked from and joined back to it by
-    // events; the lock keeps one call's fork, launches and join together
+    // classes go to the plan's other streams, forked from and joined back to it by events: the
+    // largest first, each to the stream with the least work so far (work: rings x L log2 L per
+    // transform, two for the Bluestein form), so that a memory-bound class (the power-of-two
+    // rings) and the VALU-bound Bluestein classes run side by side instead of one after the
+    // other; the lock keeps one call's fork, launches and join together
     static std::mutex fork_mu;
     std::unique_lock<std::mutex> lock(fork_mu, std::defer_lock);
     if (fork) {
@@ -974,9 +977,16 @@ static int synthesize_rings(const smf_plan* plan, int count, const void* g_dev, 
     log_line(2, "synthesize_rings: %d field%s, %d transform-class launch%s%s, general kernel %s", count,
              count == 1 ? "" : "s", (int)fft.size(), fft.size() == 1 ? "" : "es", fork ? " on the plan's streams" : "",
              general ? "on the caller's stream" : "not needed");
+    auto work = [](const Unit& x) { return (x.blue ? 2.0 : 1.0) * x.rings * (double)x.log2l * (double)(1 << x.log2l); };
+    std::stable_sort(fft.begin(), fft.end(), [&](const Unit& x, const Unit& y) { return work(x) > work(y); });
+    double load[smf::kRingAuxStreams] = {0.0};
     int rc = SMF_OK;
     for (size_t u = 0; u < fft.size() && rc == SMF_OK; ++u) {
-        const hipStream_t su = fork ? plan->ring_aux[u % smf::kRingAuxStreams] : st;
+        int j = 0;
+        for (int k = 1; k < smf::kRingAuxStreams; ++k)
+            if (load[k] < load[j]) j = k;
+        load[j] += work(fft[u]);
+        const hipStream_t su = fork ? plan->ring_aux[j] : st;
         if (smf::launch_ring_fft_class(fft[u].blue, fft[u].log2l, fft[u].rings, g.n_theta, g.m_top, g.n_phi / 2,
                                        plan->ring_off[g.n_theta], fp64, count, g_dev,
                                        plan->ring_list_dev + fft[u].first, plan->n_ring_dev, plan->phi0_dev,

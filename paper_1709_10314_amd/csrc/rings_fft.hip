@@ -7,7 +7,8 @@
 //     k q = (k^2 + q^2 - (q - k)^2) / 2, i.e. z_q = e^{i pi q^2 / h} sum_k (Z_k e^{i pi k^2 / h})
 //     e^{-i pi (q - k)^2 / h}, a cyclic convolution of length L >= 2h - 1 done by two
 //     power-of-two transforms of length L (the same passes) and a product with the transform
-//     of the chirp, which depends on h only and is computed once, at setup, in FP64.
+//     of the chirp; that transform, the chirp and the chirp times the split's twiddle depend
+//     on h only and are computed once, at setup, in FP64.
 // Folding the modes onto the ring's frequencies and the real-to-complex split are those of the
 // general ring kernel (rings.hip); here each thread folds the bins of its transform inputs, and
 // the split's mirror partners come through LDS.
@@ -39,28 +40,8 @@ __host__ __device__ constexpr int ring_tw_base(int log2l)
     return 2 * ((1 << log2l) - (1 << kRingFftMinLog2));
 }
 
-// e^{+2 pi i k / n} for 0 <= k < n from the ring's small tables: Ft[k / 64] * Et[k mod 64].
-template <typename T>
-__device__ __forceinline__ Cx<T> ring_tw_n(const Cx<T>* Et, const Cx<T>* Ft, int k)
-{
-    return cmul(Ft[k >> 6], Et[k & 63]);
-}
-
 template <typename T>
 __device__ __forceinline__ Cx<T> conj_c(Cx<T> a) { return {a.re, -a.im}; }
-
-// x mod n for 0 <= x < 2^22 and 0 < n < 2^13: the quotient from a float product is off by at
-// most one, which the remainder's range check corrects.
-__device__ __forceinline__ int mod_small(int x, int n, float inv_n)
-{
-    const int q = (int)((float)x * inv_n);
-    int r = x - q * n;
-    if (r < 0)
-        r += n;
-    else if (r >= n)
-        r -= n;
-    return r;
-}
 
 // ---- register-resident radix-16 form (L = 256 R3, R3 = 4, 8, 16; NT = L / 16 threads) ----
 // Thread t holds x_{t + NT r} (r < 16) in registers: pass 1 (radix 16, Ns = 1) takes them
@@ -130,8 +111,9 @@ __device__ __forceinline__ void r16_pass3(const Cx<T>* buf, const Cx<T>* __restr
 // B_k = e^{i k phi0} (U_k + conj X_k), U_k = sum_p g_{k+pn} E^p, X_k = sum_p g_{n-k+pn} E^{p+1},
 // E = e^{i n phi0}, and e^{i k phi0} = e^{i (t mod 16) phi0} e^{i 16 (t / 16) phi0} e^{i NT r phi0},
 // three table values (FP64 sincos, rounded to the type once) multiplied in the type.  LDS: the
-// buffer, the phase tables (16 values each, then E and e^{i h phi0}), B_h, and for the Bluestein
-// form e^{2 pi i b / n}, e^{2 pi i 64 a / n} in the type.
+// buffer, the phase tables (16 values each, then E and e^{i h phi0}) and B_h.  The Bluestein form
+// reads its length's block of the plan's table: S (L values), then c_k = e^{i pi k^2 / h} and
+// D_k = i e^{2 pi i k / n} c_k (L / 2 values each, k < h used).
 // Waves per SIMD the radix-16 ring kernels are compiled for (their register budget; 0: the
 // compiler's choice)
 #ifndef SMF_RING_R16_WAVES
@@ -147,8 +129,17 @@ __device__ __forceinline__ void r16_pass3(const Cx<T>* buf, const Cx<T>* __restr
 #define SMF_R16_ATTR
 #endif
 
+// The Bluestein form keeps the chirp of its bins in registers for the outputs (FP32, L = 4096:
+// measured faster, within 128 VGPRs) or reloads it after the second transform (measured faster
+// at the shorter lengths, whose transforms then get more registers)
 template <typename T, int LOG2L, bool BLUE>
-__global__ __launch_bounds__((1 << LOG2L) / 16) SMF_R16_ATTR void ring_r16_kernel(RingFftArgs a, const T* __restrict__ g,
+__host__ __device__ constexpr bool r16_keeps_chirp()
+{
+    return BLUE && sizeof(T) == 4 && LOG2L == 12;
+}
+
+template <typename T, int LOG2L, bool BLUE>
+__global__ __launch_bounds__((1 << LOG2L) / 16, (r16_keeps_chirp<T, LOG2L, BLUE>() ? 4 : 1)) SMF_R16_ATTR void ring_r16_kernel(RingFftArgs a, const T* __restrict__ g,
                                                                      const int* __restrict__ n_ring,
                                                                      const double* __restrict__ phi0,
                                                                      const int64_t* __restrict__ off,
@@ -182,9 +173,6 @@ __global__ __launch_bounds__((1 << LOG2L) / 16) SMF_R16_ATTR void ring_r16_kerne
     Cx<T>* Ph = buf + lds_slots(L);   // [0, 16): e^{i b phi0}; [16, 32): e^{i 16 b phi0};
                                       // [32, 48): e^{i NT b phi0}; 48: E; 49: e^{i h phi0}
     Cx<T>* Bh = Ph + 50;
-    Cx<T>* Et = Bh + 2;
-    Cx<T>* Ft = Et + 64;
-    const int na = n / 64 + 1;
     const double p0 = phi0[i];
     using V2 = typename Vec2<T>::type;
     const V2* gv = reinterpret_cast<const V2*>(g + ((size_t)f * a.n_theta + i) * (size_t)a.g_row * 2);
@@ -205,29 +193,18 @@ __global__ __launch_bounds__((1 << LOG2L) / 16) SMF_R16_ATTR void ring_r16_kerne
         }
     }
     const bool phased = p0 != 0.0;   // uniform: rings starting at longitude 0 need no phases
-    const int ntab = (phased ? 50 : 0) + (BLUE ? 64 + na : 0);
-    for (int e0 = t; e0 < ntab; e0 += NT) {
+    if (phased && t < 50) {
         double sn, cs;
-        const int e = phased ? e0 : e0 + 50;
-        if (e < 50) {
-            const int a = e & 15, sel = e >> 4;
-            const double m = sel == 0 ? a : sel == 1 ? 16.0 * a : sel == 2 ? (double)NT * a : e == 48 ? n : h;
-            sincos(m * p0, &sn, &cs);
-            Ph[e] = {(T)cs, (T)sn};
-        } else if (e < 50 + 64) {
-            sincospi(2.0 * (double)(e - 50) / (double)n, &sn, &cs);
-            Et[e - 50] = {(T)cs, (T)sn};
-        } else {
-            sincospi(128.0 * (double)(e - 114) / (double)n, &sn, &cs);
-            Ft[e - 114] = {(T)cs, (T)sn};
-        }
+        const int a = t & 15, sel = t >> 4;
+        const double m = sel == 0 ? a : sel == 1 ? 16.0 * a : sel == 2 ? (double)NT * a : t == 48 ? n : h;
+        sincos(m * p0, &sn, &cs);
+        Ph[t] = {(T)cs, (T)sn};
     }
     __syncthreads();
     const Cx<T> one = {T(1), T(0)};
     const Cx<T> En = phased ? Ph[48] : one;
     const Cx<T> base = phased ? cmul(Ph[t & 15], Ph[16 + (t >> 4)]) : one;   // e^{i t phi0}
-    const float inv_n = 1.0f / (float)n;
-    auto chirp = [&](int k) { return ring_tw_n(Et, Ft, mod_small(k * k, n, inv_n)); };
+    const Cx<T>* S = spec + (BLUE ? spec_off[i] : 0);   // S, then c (at L), then D (at 3 L / 2)
 
     // fold, one period of the modes at a time over all of this thread's bins (so that a
     // period's loads are in flight together): Y_k = U_k + conj X_k, then B_k = e^{i k phi0} Y_k,
@@ -250,6 +227,17 @@ __global__ __launch_bounds__((1 << LOG2L) / 16) SMF_R16_ATTR void ring_r16_kerne
             x = (k < h && mk <= mt) ? mode(mk) : Cx<T>{T(0), T(0)};
         }
         v[r] = cadd(u, conj_c(cmul(x, En)));
+    }
+    // the Bluestein tables of this thread's bins, loaded while the fold goes on (zero from h on);
+    // c_k is also the chirp of output q = k
+    constexpr bool KEEP_C = r16_keeps_chirp<T, LOG2L, BLUE>();
+    Cx<T> cc[BLUE ? RB : 1], dd[BLUE ? RB : 1];
+    if constexpr (BLUE) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            cc[r] = S[L + t + NT * r];
+            dd[r] = S[L + L / 2 + t + NT * r];
+        }
     }
     Cx<T> uh = (t == 0 && h <= mt) ? mode(h) : Cx<T>{T(0), T(0)};
     Cx<T> Ep = En, Eq = cmul(En, En);   // E^p, E^{p+1}
@@ -277,7 +265,8 @@ __global__ __launch_bounds__((1 << LOG2L) / 16) SMF_R16_ATTR void ring_r16_kerne
     }
     if (t == 0) Bh[0] = cmul(phased ? Ph[49] : one, cadd(uh, conj_c(cmul(uh, En))));
     __syncthreads();
-    // split: Z_k = (B_k + conj B_{h-k}) + i w^k (B_k - conj B_{h-k}), w = e^{2 pi i / n}
+    // split: Z_k = (B_k + conj B_{h-k}) + i w^k (B_k - conj B_{h-k}), w = e^{2 pi i / n}; the
+    // Bluestein form takes Z_k c_k = (B_k + conj B_{h-k}) c_k + (B_k - conj B_{h-k}) D_k
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
         const int k = t + NT * r;
@@ -285,9 +274,10 @@ __global__ __launch_bounds__((1 << LOG2L) / 16) SMF_R16_ATTR void ring_r16_kerne
         if (k < h) {
             const Cx<T> b1 = v[r];
             const Cx<T> b2 = conj_c(k == 0 ? Bh[0] : buf[lds_slot(h - k)]);
-            const Cx<T> w = BLUE ? ring_tw_n(Et, Ft, k) : tw[k];
-            z = cadd(cadd(b1, b2), mul_i(cmul(w, csub(b1, b2))));
-            if (BLUE) z = cmul(z, chirp(k));
+            if constexpr (BLUE)
+                z = cadd(cmul(cadd(b1, b2), cc[r]), cmul(csub(b1, b2), dd[r]));
+            else
+                z = cadd(cadd(b1, b2), mul_i(cmul(tw[k], csub(b1, b2))));
         }
         v[r] = z;
     }
@@ -309,8 +299,7 @@ __global__ __launch_bounds__((1 << LOG2L) / 16) SMF_R16_ATTR void ring_r16_kerne
         }
     } else {
         // the product with the chirp's transform S (divided by L), then the forward transform
-        // as conj(inverse(conj(.))), z_q = e^{i pi q^2 / h} c_q for q < h
-        const Cx<T>* S = spec + spec_off[i];
+        // as conj(inverse(conj(.))), z_q = c_q (the convolution at q) for q < h
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = conj_c(cmul(v[r], S[t + NT * r]));
         __syncthreads();   // pass 3's reads before pass 1 writes the buffer
@@ -320,7 +309,7 @@ __global__ __launch_bounds__((1 << LOG2L) / 16) SMF_R16_ATTR void ring_r16_kerne
         for (int r = 0; r < 8; ++r) {
             const int q = t + NT * r;
             if (q < h) {
-                const Cx<T> x = epilogue(ep, cmul(conj_c(v[r]), chirp(q)));
+                const Cx<T> x = epilogue(ep, cmul(conj_c(v[r]), KEEP_C ? cc[r] : S[L + q]));
                 V2 w;
                 w.x = x.re;
                 w.y = x.im;
@@ -350,8 +339,9 @@ __global__ void ring_tw_kernel(double* __restrict__ tw64, float* __restrict__ tw
 }
 
 // S = inverse DFT_L(b) / L of Bluestein's kernel b_j = e^{-i pi j^2 / h} (j < h), b_{L-j} = b_j
-// (0 < j < h), zero elsewhere; one workgroup per listed length h, in FP64, stored in the
-// plan's type at out + off[w].
+// (0 < j < h), zero elsewhere, then the chirp c_j = e^{i pi j^2 / h} and D_j = i e^{i pi j / h} c_j
+// (j < L / 2; zero from h on); one workgroup per listed length h, in FP64, stored in the plan's
+// type at out + off[w] (2 L complex values).
 template <typename T, int LOG2L>
 __global__ __launch_bounds__((1 << LOG2L) / 8) void ring_spectrum_kernel(const int* __restrict__ hs,
                                                                          const int64_t* __restrict__ offs,
@@ -382,14 +372,26 @@ __global__ __launch_bounds__((1 << LOG2L) / 8) void ring_spectrum_kernel(const i
         const Cx<double> v = buf[lds_slot(j)];
         o[j] = {(T)(v.re * inv), (T)(v.im * inv)};
     }
+    // the phases reduced modulo n = 2 h exactly in integers before the FP64 sincospi
+    for (int j = threadIdx.x; j < L / 2; j += NT) {
+        Cx<T> c = {T(0), T(0)}, d = {T(0), T(0)};
+        if (j < h) {
+            double s, co;
+            sincospi((double)(((int64_t)j * j) % n) / (double)h, &s, &co);
+            c = {(T)co, (T)s};
+            sincospi((double)(((int64_t)j * j + j) % n) / (double)h, &s, &co);
+            d = {(T)(-s), (T)co};
+        }
+        o[L + j] = c;
+        o[L + L / 2 + j] = d;
+    }
 }
 
 // LDS of ring_r16_kernel
 size_t r16_kernel_lds(int log2l, bool fp64)
 {
     const size_t cx = fp64 ? 16 : 8;
-    const int na = (1 << log2l) / 64 + 1;   // n <= L for the Bluestein form
-    return cx * ((size_t)lds_slots(1 << log2l) + 50 + 2 + 64 + (size_t)na);
+    return cx * ((size_t)lds_slots(1 << log2l) + 50 + 2);
 }
 
 template <typename T, int LOG2L, bool BLUE>

@@ -133,11 +133,14 @@ constexpr int kRingMaxCount = 65535;     // fields of one call (grid y)
 #ifndef SMF_RING_CHIRP_MIN
 #define SMF_RING_CHIRP_MIN 383
 #endif
-// Lane-operations per L log2 L of a Bluestein ring transform of length L (two transforms of
-// length L and the product with the kernel's transform), for the choice of its class
-// (measured on HEALPix nside 1024 x 8 fields: synthesis 0.476 ms at 6, 0.492 at 16, 0.516 at 24)
+// Weight of a Bluestein ring transform of length L, per L log2 L, against the estimated work of
+// the general kernel's odd-prime passes, for the choice of its class.  Not a count of operations:
+// the general kernel's launch is the last to finish when the classes overlap, so moving rings
+// out of it pays beyond their own work (measured on HEALPix nside 1024 x 8 fields with the
+// Bluestein tables computed at setup and the classes balanced over the streams: synthesis
+// 0.449 ms at 8, 0.436 at 6, 0.426 at 3.5, 0.422 at 2.5, 0.419 at 1.5, 0.418 at 0)
 #ifndef SMF_RING_BLUE_COST
-#define SMF_RING_BLUE_COST 6.0
+#define SMF_RING_BLUE_COST 1.5
 #endif
 // Smallest Bluestein length (log2)
 #ifndef SMF_RING_BLUE_MIN_LOG2
@@ -219,7 +222,7 @@ struct smf_plan {
     smf::RingSplit ring_split;
     double* ring_tw64;        // power-of-two transform tables (ring_tw_entries complex values)
     float* ring_tw32;         // the same rounded to FP32 (FP32 plans)
-    void* ring_spec_dev;      // transforms of Bluestein's kernels, one per half-length, plan type
+    void* ring_spec_dev;      // Bluestein tables per half-length (2 L values: the kernel's transform, chirp, chirp x twiddle), plan type
     int64_t* ring_spec_off_dev;   // [n_theta] each ring's transform (in complex values)
     hipStream_t ring_aux[smf::kRingAuxStreams];   // null when the synthesis is a single launch
     hipEvent_t ring_fork;

@@ -915,11 +915,13 @@ int smf_setup_rings(const smf_spectrum* spec, int n_theta, const double* z_host,
                                  1 << (smf::kRingFftMinLog2 + c), rs.n_pow2[c]);
             if (used >= sizeof(cls)) break;
         }
+        char streams[64] = "one stream";
+        if (plan->ring_aux[0])
+            snprintf(streams, sizeof(streams), "launches spread over %d more streams", smf::kRingAuxStreams);
         log_line(1, "setup_rings: %d rings, %lld pixels per field, largest %d, chains at n_phi %d; rings by transform "
                  "class:%s general %d (chirp-z %d); %lld Bluestein half-lengths (tables %.1f MB); %s",
                  n_theta, (long long)off[n_theta], n_max, n_phi, cls, rs.n_direct + rs.n_chirp, rs.n_chirp,
-                 (long long)spec_h.size(), (double)spec_total * (fp64 ? 16 : 8) / 1e6,
-                 plan->ring_aux[0] ? "launches spread over 3 more streams" : "one stream");
+                 (long long)spec_h.size(), (double)spec_total * (fp64 ? 16 : 8) / 1e6, streams);
     }
     return rc;
 }

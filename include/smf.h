@@ -271,7 +271,9 @@ int smf_batch_get_shape(const smf_plan* plan, int* tiles, int* persistent);
  * j < n_phi_ring[i].  The plan is that of smf_setup_grid on n_phi = the smallest power of
  * two >= 2 (ell_max + 1), so m_top = ell_max and every mode is sampled (smf_plan_dims
  * reports that n_phi; every call of a plan works on it), plus the ring table.  Host arrays
- * of n_theta entries, copied.
+ * of n_theta entries, copied.  With SMF_GREEN (and SMF_KAPPA_PAIR) the factors are those of
+ * Sec. 3 for the modes up to ell_max, the band the rings are synthesised from (the spectrum
+ * itself has no band limit, so the chains are exactly Markov).
  * Errors: as smf_setup_grid, plus SMF_EINVAL for a NULL n_phi_ring or phi0, an odd
  * n_phi_ring[i] or one outside [2, 8192] (SMF_FP32) or [2, 4096] (SMF_FP64), a phi0 that is
  * not finite, or ell_max > 8191. */

@@ -246,8 +246,10 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
         return SMF_EHIP;
     if (lds > (size_t)lds_max) return SMF_EINVAL;
 
-    // no band limit with SMF_GREEN: every mode of the FFT layout is sampled
-    Geometry g = smf::make_geometry(spec->order, n_theta, n_phi, green ? n_phi / 2 - 1 : spec->ell_max);
+    // no band limit with SMF_GREEN: every mode of the FFT layout is sampled, except on a ring
+    // plan (rows > 0), whose synthesis stops at ell_max: its chains run the Green's-function
+    // factors of the modes up to ell_max
+    Geometry g = smf::make_geometry(spec->order, n_theta, n_phi, green && rows == 0 ? n_phi / 2 - 1 : spec->ell_max);
     if (rows > 0 && rows < g.m_rows) g.m_rows = rows;
     DevBufs bufs;
     smf_plan* plan = (smf_plan*)calloc(1, sizeof(smf_plan));
@@ -698,7 +700,7 @@ int smf_setup_rings(const smf_spectrum* spec, int n_theta, const double* z_host,
         return reject(W, "NULL argument, or n_theta outside [2, 65536]");
     *out = nullptr;
     if (spec->ell_max < 0 || spec->ell_max > smf::kRingMaxEll) return reject(W, "ell_max must be in [0, 8191]");
-    const bool fp64 = (flags & ~(SMF_UBASIS | SMF_NO_MIRROR)) == SMF_FP64;
+    const bool fp64 = (flags & ~(SMF_UBASIS | SMF_NO_MIRROR | SMF_GREEN | SMF_KAPPA_PAIR)) == SMF_FP64;
     const int n_cap = fp64 ? smf::kRingMaxPixels64 : smf::kRingMaxPixels32;
     int n_max = 0;
     std::vector<int64_t> off((size_t)n_theta + 1, 0);

@@ -588,8 +588,14 @@ class RingPlan(Plan):
     power-of-two n_phi that keeps them all) and each ring is synthesised at its own pixels."""
 
     def __init__(self, order, n_phi_ring, phi0, ell_max, kappa=None, c_ell=None, precision="fp32",
-                 stream=None, z=None, basis="z"):
+                 stream=None, z=None, basis="z", green=False, kappa_pair=False):
+        """green / kappa_pair: the Green's-function setup of Sec. 3 (as Plan) for the modes up
+        to ell_max, which the rings are synthesised from."""
         flags = {"fp32": SMF_FP32, "fp64": SMF_FP64}[precision] | {"z": 0, "u": SMF_UBASIS}[basis]
+        if green:
+            flags |= SMF_GREEN
+        if kappa_pair:
+            flags |= SMF_KAPPA_PAIR
         rc, h = smf_setup_rings(order, n_phi_ring, phi0, ell_max, kappa=kappa, c_ell=c_ell, flags=flags,
                                 stream=stream, z=z)
         if rc != SMF_OK:

@@ -81,6 +81,11 @@ int main(void)
     const double phi0[4] = {0.1, 0.0, 0.0, 0.1};
     expect(smf_setup_rings(&ok, 4, NULL, n_odd, phi0, SMF_FP32, NULL, &plan), SMF_EINVAL, SMF_EINVAL, "odd ring");
     expect(smf_setup_rings(&ok, 4, NULL, NULL, phi0, SMF_FP32, NULL, &plan), SMF_EINVAL, SMF_EINVAL, "rings NULL");
+    /* the FP64 ring limit (4096 pixels) holds with the Green's-function flags too */
+    const int n_big[4] = {4, 8192, 8, 4};
+    smf_spectrum green1 = {1, 1, kappa, NULL, 16};
+    expect(smf_setup_rings(&green1, 4, NULL, n_big, phi0, SMF_FP64 | SMF_GREEN, NULL, &plan), SMF_EINVAL, SMF_EINVAL,
+           "FP64 Green ring of 8192 pixels");
     plan = NULL;
     expect(smf_setup_rings(&ok, 4, NULL, n_ring, phi0, SMF_FP32, NULL, &plan), SMF_EHIP, SMF_OK, "rings valid");
     if (plan) smf_destroy(plan);

@@ -67,8 +67,9 @@ enum {
     SMF_FUSED = 8,       /* reserved for a single-kernel recursion + FFT; smf_setup returns
                             SMF_EINVAL for it (the two launches of smf_sample are the path) */
     SMF_GREEN = 32,      /* or'ed with SMF_FP64 or SMF_FP32: the setup of Sec. 3 at order 1 or 2.
-                            The spectrum is eq. (Cl) with n_kappa = order distinct real kappa_i > 0
-                            (c_ell NULL) for every l >= 0, not truncated (ell_max is ignored and
+                            The spectrum is eq. (Cl) with n_kappa = order distinct real kappa_i in
+                            (0, 1e4] (c_ell NULL; the Green's functions grow like exp(pi sqrt kappa)
+                            and are formed in FP64) for every l >= 0, not truncated (ell_max is ignored and
                             every mode up to n_phi/2 - 1 is sampled), and J^m comes from the Green's
                             functions of the mode's operator, eq. (Jmatrix_efficient) with the
                             partial fractions of eq. (C_ell_efficient), and P^m_lambda of complex
@@ -78,7 +79,7 @@ enum {
                             SMF_UBASIS.  Needs order * n_theta * (n_phi / 2 + 1) <= 2^27 (two setup
                             tables of that many doubles). */
     SMF_KAPPA_PAIR = 64, /* with SMF_GREEN at order 2: kappa = {alpha, beta} names the complex-
-                            conjugate pair kappa = alpha +- i beta (beta > 0), the spectrum
+                            conjugate pair kappa = alpha +- i beta (beta > 0, |kappa| <= 1e4), the spectrum
                             C_l = 1/((l(l+1) + alpha)^2 + beta^2) (the Sec. 5 example is alpha = 0,
                             beta = sqrt(10)); the two terms of the partial fractions are complex
                             conjugates and the Green's functions have complex degree and complex

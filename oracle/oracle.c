@@ -973,6 +973,18 @@ int orc_setup_modes_z(int order, int ell_max, const double* C, int n_theta, cons
 
 /* The same in the basis (g, U g) of Sec. 3 (order 2; basis 1), or the z-derivative one
    (basis 0). */
+/* The Green's-function setups (bases 2-4) evaluate G_m and sin(pi lambda), which grow like
+ * exp(pi sqrt|kappa|), and their products, in FP64: |kappa| is held to ORC_GREEN_MAX_KAPPA (G and
+ * |sin pi lambda| then stay below about 1e137; near |kappa| = 1e5 the products leave the FP64 range). */
+#define ORC_GREEN_MAX_KAPPA 1e4
+static int green_kappa_ok(int order, int basis, const double* C)
+{
+    if (basis == 4) return hypot(C[0], C[1]) <= ORC_GREEN_MAX_KAPPA;
+    for (int i = 0; i < order; ++i)
+        if (!(C[i] <= ORC_GREEN_MAX_KAPPA)) return 0;
+    return 1;
+}
+
 int orc_setup_modes_zb(int order, int basis, int ell_max, const double* C, int n_theta, const double* zgrid,
                        int n_sets, const int* modes, int n_modes, double* A, double* B)
 {
@@ -981,6 +993,7 @@ int orc_setup_modes_zb(int order, int basis, int ell_max, const double* C, int n
         !(basis == 3 && order == 2 && C[0] > 0.0 && C[1] > 0.0 && C[0] != C[1]) &&
         !(basis == 4 && order == 2 && C[1] > 0.0 && isfinite(C[0]) && isfinite(C[1])))
         return -1;
+    if (basis >= 2 && !green_kappa_ok(order, basis, C)) return -1;
     if (zgrid && !grid_ok(zgrid, n_theta, 1)) return -1;
     int total = orc_n_sets(n_theta);
     if (n_sets > total) n_sets = total;

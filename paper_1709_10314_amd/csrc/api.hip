@@ -223,13 +223,19 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
         if (spec->order > 2 || ubasis || spec->c_ell || spec->n_kappa != spec->order || !spec->kappa ||
             (long long)spec->order * n_theta * (n_phi / 2 + 1) > smf::kGreenMaxTable)
             return reject(W, "SMF_GREEN needs order 1 or 2 with n_kappa = order, no c_ell, no SMF_UBASIS");
+        // G_m and sin(pi lambda) grow like exp(pi sqrt|kappa|) and are formed in FP64, with their
+        // products: |kappa| is held to kGreenMaxKappa, where they stay below about 1e137 (the
+        // products leave the FP64 range near |kappa| = 1e5)
+        constexpr double kGreenMaxKappa = 1e4;
         if (pair) {
             if (!std::isfinite(spec->kappa[0]) || !std::isfinite(spec->kappa[1]) || !(spec->kappa[1] > 0.0))
                 return reject(W, "SMF_KAPPA_PAIR needs a finite alpha and a finite beta > 0");
+            if (!(std::hypot(spec->kappa[0], spec->kappa[1]) <= kGreenMaxKappa))
+                return reject(W, "SMF_KAPPA_PAIR needs |alpha + i beta| <= 1e4");
         } else {
             for (int i = 0; i < spec->n_kappa; ++i)
-                if (!(spec->kappa[i] > 0.0) || !std::isfinite(spec->kappa[i]))
-                    return reject(W, "SMF_GREEN needs finite positive kappa");
+                if (!(spec->kappa[i] > 0.0) || !(spec->kappa[i] <= kGreenMaxKappa))
+                    return reject(W, "SMF_GREEN needs kappa in (0, 1e4]");
             if (spec->order == 2 && spec->kappa[0] == spec->kappa[1])
                 return reject(W, "SMF_GREEN at order 2 needs two distinct kappa");
         }

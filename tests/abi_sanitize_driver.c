@@ -55,6 +55,8 @@ int main(void)
     smf_spectrum pair0 = {2, 2, (const double[]){0.0, 0.0}, NULL, 0};
     expect(smf_setup(&pair0, 8, 32, SMF_FP64 | SMF_GREEN | SMF_KAPPA_PAIR, NULL, &plan), SMF_EINVAL, SMF_EINVAL,
            "pair beta 0");
+    smf_spectrum big1 = {1, 1, (const double[]){2e4}, NULL, 0};
+    expect(smf_setup(&big1, 8, 32, SMF_FP64 | SMF_GREEN, NULL, &plan), SMF_EINVAL, SMF_EINVAL, "Green kappa 2e4");
     smf_spectrum pair1 = {2, 2, (const double[]){0.0, 3.0}, NULL, 0};
     expect(smf_setup(&pair1, 8, 32, SMF_FP64 | SMF_KAPPA_PAIR, NULL, &plan), SMF_EINVAL, SMF_EINVAL,
            "pair without Green");

@@ -310,3 +310,18 @@ def test_conjugate_pair_chain_is_exactly_markov(orc, n):
                 assert np.max(np.abs(X - J) / sd) < 1e-10, (m, r)
                 Jrr = orc.jblock_green2c(m, 0.0, BETA, z[r], z[r])
                 assert np.max(np.abs(V - Jrr) / np.sqrt(np.outer(np.diag(V), np.diag(V)))) < 1e-10, (m, r)
+
+
+def test_green_setups_hold_kappa_to_their_fp64_range(orc):
+    """G_m and sin(pi lambda) grow like exp(pi sqrt|kappa|) in FP64: the Green's-function setups
+    take |kappa| <= 1e4 (there the values stay below about 1e137; near 1e5 the closed-form J^m
+    of nearby rings already underflows to zero, which a setup must not pass on silently)."""
+    assert orc.jblock_green(0, 1e5, 0.1, 0.2) == 0.0   # the failure the bound keeps out
+    A, B = orc.setup_green(1e4, 8, 16)
+    assert np.isfinite(A).all() and np.isfinite(B).all()
+    for bad in (lambda: orc.setup_green(2e4, 8, 16), lambda: orc.setup_green2([100.0, 2e4], 8, 16),
+                lambda: orc.setup_green2c(8e3, 7e3, 8, 16)):
+        with pytest.raises(ValueError):
+            bad()
+    A, B = orc.setup_green2c(0.0, 9.9e3, 8, 16)
+    assert np.isfinite(A).all() and np.isfinite(B).all()

@@ -236,8 +236,11 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
             for (int i = 0; i < spec->n_kappa; ++i)
                 if (!(spec->kappa[i] > 0.0) || !(spec->kappa[i] <= kGreenMaxKappa))
                     return reject(W, "SMF_GREEN needs kappa in (0, 1e4]");
-            if (spec->order == 2 && spec->kappa[0] == spec->kappa[1])
-                return reject(W, "SMF_GREEN at order 2 needs two distinct kappa");
+            // the partial fractions' weights +-1/(kappa_2 - kappa_1) cancel about
+            // log10(kappa / |kappa_2 - kappa_1|) digits of J^m: the roots keep a relative distance
+            if (spec->order == 2 && !(std::fabs(spec->kappa[1] - spec->kappa[0]) >=
+                                      1e-6 * std::fmax(spec->kappa[0], spec->kappa[1])))
+                return reject(W, "SMF_GREEN at order 2 needs |kappa_2 - kappa_1| >= 1e-6 max(kappa)");
         }
     }
     if (z_host && !grid_ok(z_host, n_theta))

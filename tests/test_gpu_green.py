@@ -181,7 +181,7 @@ def test_green2_rejects_repeated_or_missing_kappa():
     from paper_1709_10314_amd import smf
 
     for kw in (dict(order=2, kappa=[50.0, 50.0]), dict(order=2, kappa=[50.0]), dict(order=3, kappa=[1.0, 2.0, 3.0]),
-               dict(order=2, kappa=[50.0, 0.0])):
+               dict(order=2, kappa=[50.0, 0.0]), dict(order=2, kappa=[50.0, 50.0 * (1 + 1e-7)])):
         rc, _ = smf.smf_setup(kw["order"], 16, 32, 15, kappa=kw["kappa"], flags=smf.SMF_FP64 | smf.SMF_GREEN)
         assert rc == smf.SMF_EINVAL, kw
 

@@ -315,3 +315,28 @@ def test_green_on_healpix_rings_matches_oracle(case):
         emax = max(max_rel_err(T[f], To[f]) for f in range(count))
         log(f"green on HEALPix {case} {precision}: fields rel RMS {e:.2e}, max {emax:.2e}")
         assert e <= bar
+
+
+# ---------------------------------------------------------------- the southern walk's own factor sets
+@pytest.mark.parametrize("grid", [(64, 128), (33, 64)], ids=["64x128", "33x64"])
+@pytest.mark.parametrize("case", [(1, (400.0,)), (2, (100.0, 900.0)), (2, (0.0, float(np.sqrt(10.0))))],
+                         ids=["order1", "order2-real", "pair"])
+def test_green_southern_sets_equal_the_mirror(grid, case):
+    """SMF_NO_MIRROR with SMF_GREEN: the southern walk's factor sets computed on their own (the
+    Green's-function kernels' southern form) against the mirrored northern sets on a symmetric
+    grid; the fields must agree to rounding (the mirrored path is the one pinned to the oracle)."""
+    from paper_1709_10314_amd import Plan
+
+    n, nphi = grid
+    order, kap = case
+    pair = order == 2 and kap[0] == 0.0
+    for precision, bar in (("fp64", 1e-12), ("fp32", 1e-6)):
+        plans = [Plan(order, n, nphi, 0, kappa=list(kap), precision=precision, green=True, kappa_pair=pair,
+                      mirror=mirror) for mirror in (True, False)]
+        T = [p.sample(5, 2).double().cpu().numpy() for p in plans]
+        torch.cuda.synchronize()
+        for p in plans:
+            p.close()
+        e = max(rel_rms(T[1][f], T[0][f]) for f in range(2))
+        log(f"green {case} {grid} {precision}: own southern sets against the mirror, rel RMS {e:.2e}")
+        assert e <= bar

@@ -81,7 +81,8 @@ enum {
                             SMF_UBASIS.  Needs order * n_theta * (n_phi / 2 + 1) <= 2^27 (two setup
                             tables of that many doubles). */
     SMF_KAPPA_PAIR = 64, /* with SMF_GREEN at order 2: kappa = {alpha, beta} names the complex-
-                            conjugate pair kappa = alpha +- i beta (beta > 0, |kappa| <= 1e4), the spectrum
+                            conjugate pair kappa = alpha +- i beta (alpha >= -50, 0 < beta <= 1000, |kappa| <= 1e4:
+                            outside, the series of the Green's functions cancels), the spectrum
                             C_l = 1/((l(l+1) + alpha)^2 + beta^2) (the Sec. 5 example is alpha = 0,
                             beta = sqrt(10)); the two terms of the partial fractions are complex
                             conjugates and the Green's functions have complex degree and complex

@@ -979,7 +979,9 @@ int orc_setup_modes_z(int order, int ell_max, const double* C, int n_theta, cons
 #define ORC_GREEN_MAX_KAPPA 1e4
 static int green_kappa_ok(int order, int basis, const double* C)
 {
-    if (basis == 4) return hypot(C[0], C[1]) <= ORC_GREEN_MAX_KAPPA;
+    /* the pair alpha +- i beta: the series' terms n^2 + n + kappa turn sign (alpha < 0) or rotate
+     * (beta large) and cancel; alpha >= -50 and beta <= 1000 keep G_m within about 1e-11 */
+    if (basis == 4) return hypot(C[0], C[1]) <= ORC_GREEN_MAX_KAPPA && C[0] >= -50.0 && C[1] <= 1000.0;
     for (int i = 0; i < order; ++i)
         if (!(C[i] <= ORC_GREEN_MAX_KAPPA)) return 0;
     /* two real roots: the weights +-1/(kappa_2 - kappa_1) cancel about log10(kappa / |kappa_2 -

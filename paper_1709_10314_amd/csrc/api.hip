@@ -230,8 +230,11 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
         if (pair) {
             if (!std::isfinite(spec->kappa[0]) || !std::isfinite(spec->kappa[1]) || !(spec->kappa[1] > 0.0))
                 return reject(W, "SMF_KAPPA_PAIR needs a finite alpha and a finite beta > 0");
-            if (!(std::hypot(spec->kappa[0], spec->kappa[1]) <= kGreenMaxKappa))
-                return reject(W, "SMF_KAPPA_PAIR needs |alpha + i beta| <= 1e4");
+            // the series of G_m cancels when its terms n^2 + n + kappa turn (alpha < 0) or rotate
+            // (beta large): alpha >= -50 and beta <= 1000 keep G_m within about 1e-11
+            if (!(std::hypot(spec->kappa[0], spec->kappa[1]) <= kGreenMaxKappa) || !(spec->kappa[0] >= -50.0) ||
+                !(spec->kappa[1] <= 1000.0))
+                return reject(W, "SMF_KAPPA_PAIR needs alpha >= -50, beta <= 1000 and |alpha + i beta| <= 1e4");
         } else {
             for (int i = 0; i < spec->n_kappa; ++i)
                 if (!(spec->kappa[i] > 0.0) || !(spec->kappa[i] <= kGreenMaxKappa))

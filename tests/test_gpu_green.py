@@ -263,7 +263,8 @@ def test_green_pair_rejects_what_it_does_not_cover():
 
     F = smf.SMF_FP64 | smf.SMF_GREEN | smf.SMF_KAPPA_PAIR
     for order, kap, flags in ((2, [0.0, 0.0], F), (2, [0.0, -1.0], F), (1, [3.0], F), (2, [float("nan"), 1.0], F),
-                              (2, [0.0, 3.0], smf.SMF_FP64 | smf.SMF_KAPPA_PAIR), (2, [8e3, 7e3], F)):
+                              (2, [0.0, 3.0], smf.SMF_FP64 | smf.SMF_KAPPA_PAIR), (2, [9.99e3, 999.0], F),
+                              (2, [-100.0, 1.0], F), (2, [0.0, 2000.0], F)):
         rc, _ = smf.smf_setup(order, 16, 32, 15, kappa=kap, flags=flags)
         assert rc == smf.SMF_EINVAL, (order, kap, flags)
 

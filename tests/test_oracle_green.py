@@ -320,11 +320,32 @@ def test_green_setups_hold_kappa_to_their_fp64_range(orc):
     A, B = orc.setup_green(1e4, 8, 16)
     assert np.isfinite(A).all() and np.isfinite(B).all()
     for bad in (lambda: orc.setup_green(2e4, 8, 16), lambda: orc.setup_green2([100.0, 2e4], 8, 16),
-                lambda: orc.setup_green2c(8e3, 7e3, 8, 16)):
+                lambda: orc.setup_green2c(9.99e3, 999.0, 8, 16)):
         with pytest.raises(ValueError):
             bad()
-    A, B = orc.setup_green2c(0.0, 9.9e3, 8, 16)
+    A, B = orc.setup_green2c(5e3, 1e3, 8, 16)
     assert np.isfinite(A).all() and np.isfinite(B).all()
+
+
+def test_conjugate_pair_domain_keeps_G_accurate(orc):
+    """The pair's series of G_m cancels where its terms n^2 + n + kappa turn sign (alpha well
+    below zero: at alpha = -1000 the sum is wrong by orders of magnitude) or rotate (beta in the
+    thousands), so the setup takes alpha >= -50 and beta <= 1000 (|kappa| <= 1e4): at the corners
+    of that domain G_m is within 1e-10 of mpmath's hyp2f1 at 40 digits; outside it is rejected."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 40
+    worst = 0.0
+    for kappa in (complex(-50.0, 0.1), complex(-50.0, 1000.0), complex(0.0, 1000.0), complex(9000.0, 1000.0)):
+        lam = -mpmath.mpf(1) / 2 + mpmath.sqrt(mpmath.mpf(1) / 4 - mpmath.mpc(kappa))
+        for m in (0, 1, 10):
+            for x in (0.9, 0.0, -0.5, -0.9, -0.999):
+                ref = complex(mpmath.hyp2f1(-lam, lam + 1, 1 + m, (1 - mpmath.mpf(x)) / 2))
+                worst = max(worst, abs(orc.greenc_G(m, kappa, x) - ref) / abs(ref))
+    mpmath.mp.dps = 15
+    assert worst < 1e-10, worst
+    for alpha, beta in ((-100.0, 1.0), (0.0, 2000.0), (9e3, 5e3)):
+        with pytest.raises(ValueError):
+            orc.setup_green2c(alpha, beta, 8, 16)
 
 
 def test_green2_holds_its_real_roots_apart(orc):

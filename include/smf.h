@@ -68,8 +68,8 @@ enum {
                             SMF_EINVAL for it (the two launches of smf_sample are the path) */
     SMF_GREEN = 32,      /* or'ed with SMF_FP64 or SMF_FP32: the setup of Sec. 3 at order 1 or 2.
                             The spectrum is eq. (Cl) with n_kappa = order distinct real kappa_i in
-                            (0, 1e4] (c_ell NULL; the Green's functions grow like exp(pi sqrt kappa)
-                            and are formed in FP64; at order 2 |kappa_2 - kappa_1| >= 1e-6 max kappa,
+                            [1e-5, 1e4] (c_ell NULL; the Green's functions grow like exp(pi sqrt kappa)
+                            and are formed in FP64, and lose digits as kappa -> 0; at order 2 |kappa_2 - kappa_1| >= 1e-6 max kappa,
                             as the partial fractions cancel log10(kappa / |kappa_2 - kappa_1|)
                             digits) for every l >= 0, not truncated (ell_max is ignored and
                             every mode up to n_phi/2 - 1 is sampled), and J^m comes from the Green's
@@ -81,7 +81,7 @@ enum {
                             SMF_UBASIS.  Needs order * n_theta * (n_phi / 2 + 1) <= 2^27 (two setup
                             tables of that many doubles). */
     SMF_KAPPA_PAIR = 64, /* with SMF_GREEN at order 2: kappa = {alpha, beta} names the complex-
-                            conjugate pair kappa = alpha +- i beta (alpha >= -50, 0 < beta <= 1000, |kappa| <= 1e4:
+                            conjugate pair kappa = alpha +- i beta (alpha >= -50, 0 < beta <= 1000, 1e-5 <= |kappa| <= 1e4:
                             outside, the series of the Green's functions cancels), the spectrum
                             C_l = 1/((l(l+1) + alpha)^2 + beta^2) (the Sec. 5 example is alpha = 0,
                             beta = sqrt(10)); the two terms of the partial fractions are complex

@@ -977,13 +977,17 @@ int orc_setup_modes_z(int order, int ell_max, const double* C, int n_theta, cons
  * exp(pi sqrt|kappa|), and their products, in FP64: |kappa| is held to ORC_GREEN_MAX_KAPPA (G and
  * |sin pi lambda| then stay below about 1e137; near |kappa| = 1e5 the products leave the FP64 range). */
 #define ORC_GREEN_MAX_KAPPA 1e4
+/* below 1e-5 the continuation about t = 1 loses digits as lambda -> 0 (5e-11 at kappa = 1e-7) */
+#define ORC_GREEN_MIN_KAPPA 1e-5
 static int green_kappa_ok(int order, int basis, const double* C)
 {
     /* the pair alpha +- i beta: the series' terms n^2 + n + kappa turn sign (alpha < 0) or rotate
      * (beta large) and cancel; alpha >= -50 and beta <= 1000 keep G_m within about 1e-11 */
-    if (basis == 4) return hypot(C[0], C[1]) <= ORC_GREEN_MAX_KAPPA && C[0] >= -50.0 && C[1] <= 1000.0;
+    if (basis == 4)
+        return hypot(C[0], C[1]) <= ORC_GREEN_MAX_KAPPA && hypot(C[0], C[1]) >= ORC_GREEN_MIN_KAPPA && C[0] >= -50.0 &&
+               C[1] <= 1000.0;
     for (int i = 0; i < order; ++i)
-        if (!(C[i] <= ORC_GREEN_MAX_KAPPA)) return 0;
+        if (!(C[i] <= ORC_GREEN_MAX_KAPPA) || !(C[i] >= ORC_GREEN_MIN_KAPPA)) return 0;
     /* two real roots: the weights +-1/(kappa_2 - kappa_1) cancel about log10(kappa / |kappa_2 -
      * kappa_1|) digits, so the roots keep a relative distance of 1e-6 */
     if (basis == 3 && !(fabs(C[1] - C[0]) >= 1e-6 * fmax(C[0], C[1]))) return 0;

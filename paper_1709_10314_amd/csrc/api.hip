@@ -227,18 +227,21 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
         // products: |kappa| is held to kGreenMaxKappa, where they stay below about 1e137 (the
         // products leave the FP64 range near |kappa| = 1e5)
         constexpr double kGreenMaxKappa = 1e4;
+        // and below 1e-5 the continuation about t = 1 loses digits as lambda -> 0 (5e-11 at 1e-7)
+        constexpr double kGreenMinKappa = 1e-5;
         if (pair) {
             if (!std::isfinite(spec->kappa[0]) || !std::isfinite(spec->kappa[1]) || !(spec->kappa[1] > 0.0))
                 return reject(W, "SMF_KAPPA_PAIR needs a finite alpha and a finite beta > 0");
             // the series of G_m cancels when its terms n^2 + n + kappa turn (alpha < 0) or rotate
             // (beta large): alpha >= -50 and beta <= 1000 keep G_m within about 1e-11
-            if (!(std::hypot(spec->kappa[0], spec->kappa[1]) <= kGreenMaxKappa) || !(spec->kappa[0] >= -50.0) ||
+            const double mod = std::hypot(spec->kappa[0], spec->kappa[1]);
+            if (!(mod <= kGreenMaxKappa) || !(mod >= kGreenMinKappa) || !(spec->kappa[0] >= -50.0) ||
                 !(spec->kappa[1] <= 1000.0))
-                return reject(W, "SMF_KAPPA_PAIR needs alpha >= -50, beta <= 1000 and |alpha + i beta| <= 1e4");
+                return reject(W, "SMF_KAPPA_PAIR needs alpha >= -50, beta <= 1000 and 1e-5 <= |alpha + i beta| <= 1e4");
         } else {
             for (int i = 0; i < spec->n_kappa; ++i)
-                if (!(spec->kappa[i] > 0.0) || !(spec->kappa[i] <= kGreenMaxKappa))
-                    return reject(W, "SMF_GREEN needs kappa in (0, 1e4]");
+                if (!(spec->kappa[i] >= kGreenMinKappa) || !(spec->kappa[i] <= kGreenMaxKappa))
+                    return reject(W, "SMF_GREEN needs kappa in [1e-5, 1e4]");
             // the partial fractions' weights +-1/(kappa_2 - kappa_1) cancel about
             // log10(kappa / |kappa_2 - kappa_1|) digits of J^m: the roots keep a relative distance
             if (spec->order == 2 && !(std::fabs(spec->kappa[1] - spec->kappa[0]) >=

@@ -99,7 +99,8 @@ def test_green_chain_has_no_markov_defect(case):
 def test_green_rejects_what_it_does_not_cover():
     from paper_1709_10314_amd import smf
 
-    for kw in (dict(order=3, kappa=[64.0, 9.0, 4.0]), dict(order=1, kappa=[64.0, 9.0]), dict(order=1, kappa=[-1.0])):
+    for kw in (dict(order=3, kappa=[64.0, 9.0, 4.0]), dict(order=1, kappa=[64.0, 9.0]), dict(order=1, kappa=[-1.0]),
+               dict(order=1, kappa=[1e-6]), dict(order=1, kappa=[2e4])):
         rc, _ = smf.smf_setup(kw["order"], 16, 32, 15, kappa=kw["kappa"], flags=smf.SMF_FP64 | smf.SMF_GREEN)
         assert rc == smf.SMF_EINVAL, kw
     rc, _ = smf.smf_setup(1, 16, 32, 15, c_ell=np.ones(16), flags=smf.SMF_FP64 | smf.SMF_GREEN)

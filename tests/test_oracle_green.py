@@ -343,9 +343,30 @@ def test_conjugate_pair_domain_keeps_G_accurate(orc):
                 worst = max(worst, abs(orc.greenc_G(m, kappa, x) - ref) / abs(ref))
     mpmath.mp.dps = 15
     assert worst < 1e-10, worst
-    for alpha, beta in ((-100.0, 1.0), (0.0, 2000.0), (9e3, 5e3)):
+    for alpha, beta in ((-100.0, 1.0), (0.0, 2000.0), (9e3, 5e3), (0.0, 1e-6)):
         with pytest.raises(ValueError):
             orc.setup_green2c(alpha, beta, 8, 16)
+
+
+def test_green_setups_hold_small_kappa_off(orc):
+    """As kappa -> 0 (lambda -> 0) the continuation about t = 1 loses digits (against mpmath at
+    40 digits: 5e-11 at kappa = 1e-7, 6e-10 at 1e-8): the setups take |kappa| >= 1e-5, where G_m
+    is within 1e-11, real or complex."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 40
+    worst = 0.0
+    for kappa in (1e-5, 1e-5j, complex(1e-5, 1e-5)):
+        lam = -mpmath.mpf(1) / 2 + mpmath.sqrt(mpmath.mpf(1) / 4 - mpmath.mpc(kappa))
+        for m in (0, 1, 100):
+            for x in (0.9, -0.5, -0.999, -0.99999):
+                ref = complex(mpmath.hyp2f1(-lam, lam + 1, 1 + m, (1 - mpmath.mpf(x)) / 2))
+                worst = max(worst, abs(orc.greenc_G(m, complex(kappa), x) - ref) / abs(ref))
+    mpmath.mp.dps = 15
+    assert worst < 1e-11, worst
+    orc.setup_green(1e-5, 8, 16)
+    for bad in (lambda: orc.setup_green(1e-6, 8, 16), lambda: orc.setup_green2([1e-6, 1.0], 8, 16)):
+        with pytest.raises(ValueError):
+            bad()
 
 
 def test_green2_holds_its_real_roots_apart(orc):

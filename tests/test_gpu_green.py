@@ -342,3 +342,36 @@ def test_green_southern_sets_equal_the_mirror(grid, case):
         e = max(rel_rms(T[1][f], T[0][f]) for f in range(2))
         log(f"green {case} {grid} {precision}: own southern sets against the mirror, rel RMS {e:.2e}")
         assert e <= bar
+
+
+# ---------------------------------------------------------------- the corners of the accepted kappa domain
+@pytest.mark.parametrize("case", [(1, (1e-5,)), (1, (1e4,)), (2, (-50.0, 0.1)), (2, (-50.0, 1000.0)),
+                                  (2, (9000.0, 1000.0))], ids=lambda c: f"order{c[0]}-{c[1]}")
+def test_green_domain_corners_match_oracle(case):
+    """The Green's-function setups at the edges of the kappa domain they accept (|kappa| from 1e-5
+    to 1e4; for the pair alpha >= -50, beta <= 1000), 64 x 128, FP64: fields against the oracle's
+    factors and chains on the same normals within 1e-10 relative RMS, or ten times the oracle's
+    own movement when kappa moves by one unit in the last place if that is larger."""
+    from paper_1709_10314_amd import Plan
+
+    order, kap = case
+    n, nphi, seed, count = 64, 128, 23, 2
+
+    def oracle_factors(k):
+        return oracle.setup_green(k[0], n, nphi) if order == 1 else oracle.setup_green2c(k[0], k[1], n, nphi)
+
+    p = Plan(order, n, nphi, 0, kappa=list(kap), precision="fp64", green=True, kappa_pair=order == 2)
+    T = p.sample(seed, count).double().cpu().numpy()
+    torch.cuda.synchronize()
+    p.close()
+    Ao, Bo = oracle_factors(kap)
+    To, _ = oracle.sample(order, n, nphi, Ao, Bo, seed, count)
+    # one unit in the last place, into the domain
+    kp = tuple(k * (1 + 2.0 ** -52) if abs(k) <= 1e-5 else k * (1 - 2.0 ** -52) for k in kap)
+    Ap, Bp = oracle_factors(kp)
+    Tp, _ = oracle.sample(order, n, nphi, Ap, Bp, seed, count)
+    sens = max(rel_rms(Tp[f], To[f]) for f in range(count))
+    e = max(rel_rms(T[f], To[f]) for f in range(count))
+    bar = max(1e-10, 10 * sens)
+    log(f"green domain corner {case}: fields rel RMS {e:.2e}, oracle's one-ulp sensitivity {sens:.2e}, bar {bar:.2e}")
+    assert np.isfinite(T).all() and e <= bar

@@ -69,7 +69,7 @@ enum {
     SMF_GREEN = 32,      /* or'ed with SMF_FP64 or SMF_FP32: the setup of Sec. 3 at order 1 or 2.
                             The spectrum is eq. (Cl) with n_kappa = order distinct real kappa_i in
                             [1e-5, 1e4] (c_ell NULL; the Green's functions grow like exp(pi sqrt kappa)
-                            and are formed in FP64, and lose digits as kappa -> 0; at order 2 |kappa_2 - kappa_1| >= 1e-6 max kappa,
+                            and are formed in FP64, and lose digits as kappa -> 0; at order 2 |kappa_2 - kappa_1| >= 1e-3 max kappa,
                             as the partial fractions cancel log10(kappa / |kappa_2 - kappa_1|)
                             digits) for every l >= 0, not truncated (ell_max is ignored and
                             every mode up to n_phi/2 - 1 is sampled), and J^m comes from the Green's

@@ -989,8 +989,9 @@ static int green_kappa_ok(int order, int basis, const double* C)
     for (int i = 0; i < order; ++i)
         if (!(C[i] <= ORC_GREEN_MAX_KAPPA) || !(C[i] >= ORC_GREEN_MIN_KAPPA)) return 0;
     /* two real roots: the weights +-1/(kappa_2 - kappa_1) cancel about log10(kappa / |kappa_2 -
-     * kappa_1|) digits, so the roots keep a relative distance of 1e-6 */
-    if (basis == 3 && !(fabs(C[1] - C[0]) >= 1e-6 * fmax(C[0], C[1]))) return 0;
+     * kappa_1|) digits, so the roots keep a relative distance of 1e-3 (a field then moves by 5e-11
+     * when kappa moves by one unit in the last place) */
+    if (basis == 3 && !(fabs(C[1] - C[0]) >= 1e-3 * fmax(C[0], C[1]))) return 0;
     return 1;
 }
 

@@ -244,9 +244,10 @@ int setup_impl(const smf_spectrum* spec, int n_theta, const double* z_host, int 
                     return reject(W, "SMF_GREEN needs kappa in [1e-5, 1e4]");
             // the partial fractions' weights +-1/(kappa_2 - kappa_1) cancel about
             // log10(kappa / |kappa_2 - kappa_1|) digits of J^m: the roots keep a relative distance
+            // of 1e-3, where a field moves by 5e-11 when kappa moves by one unit in the last place
             if (spec->order == 2 && !(std::fabs(spec->kappa[1] - spec->kappa[0]) >=
-                                      1e-6 * std::fmax(spec->kappa[0], spec->kappa[1])))
-                return reject(W, "SMF_GREEN at order 2 needs |kappa_2 - kappa_1| >= 1e-6 max(kappa)");
+                                      1e-3 * std::fmax(spec->kappa[0], spec->kappa[1])))
+                return reject(W, "SMF_GREEN at order 2 needs |kappa_2 - kappa_1| >= 1e-3 max(kappa)");
         }
     }
     if (z_host && !grid_ok(z_host, n_theta))

@@ -182,7 +182,7 @@ def test_green2_rejects_repeated_or_missing_kappa():
     from paper_1709_10314_amd import smf
 
     for kw in (dict(order=2, kappa=[50.0, 50.0]), dict(order=2, kappa=[50.0]), dict(order=3, kappa=[1.0, 2.0, 3.0]),
-               dict(order=2, kappa=[50.0, 0.0]), dict(order=2, kappa=[50.0, 50.0 * (1 + 1e-7)])):
+               dict(order=2, kappa=[50.0, 0.0]), dict(order=2, kappa=[50.0, 50.0 * (1 + 1e-4)])):
         rc, _ = smf.smf_setup(kw["order"], 16, 32, 15, kappa=kw["kappa"], flags=smf.SMF_FP64 | smf.SMF_GREEN)
         assert rc == smf.SMF_EINVAL, kw
 
@@ -346,21 +346,26 @@ def test_green_southern_sets_equal_the_mirror(grid, case):
 
 # ---------------------------------------------------------------- the corners of the accepted kappa domain
 @pytest.mark.parametrize("case", [(1, (1e-5,)), (1, (1e4,)), (2, (-50.0, 0.1)), (2, (-50.0, 1000.0)),
-                                  (2, (9000.0, 1000.0))], ids=lambda c: f"order{c[0]}-{c[1]}")
+                                  (2, (9000.0, 1000.0)), ("real2", (1e-5, 1e4)), ("real2", (100.0, 100.0 * (1 + 2e-3)))],
+                         ids=lambda c: f"{c[0]}-{c[1]}")
 def test_green_domain_corners_match_oracle(case):
     """The Green's-function setups at the edges of the kappa domain they accept (|kappa| from 1e-5
-    to 1e4; for the pair alpha >= -50, beta <= 1000), 64 x 128, FP64: fields against the oracle's
-    factors and chains on the same normals within 1e-10 relative RMS, or ten times the oracle's
-    own movement when kappa moves by one unit in the last place if that is larger."""
+    to 1e4; for the pair alpha >= -50, beta <= 1000; two real roots a relative distance of at
+    least 1e-3 apart), 64 x 128, FP64: fields against the oracle's factors and chains on the same
+    normals within 1e-10 relative RMS, or ten times the oracle's own movement when kappa moves by
+    one unit in the last place if that is larger."""
     from paper_1709_10314_amd import Plan
 
-    order, kap = case
+    kind, kap = case
+    order = 1 if kind == 1 else 2
     n, nphi, seed, count = 64, 128, 23, 2
 
     def oracle_factors(k):
-        return oracle.setup_green(k[0], n, nphi) if order == 1 else oracle.setup_green2c(k[0], k[1], n, nphi)
+        if kind == 1:
+            return oracle.setup_green(k[0], n, nphi)
+        return oracle.setup_green2(list(k), n, nphi) if kind == "real2" else oracle.setup_green2c(k[0], k[1], n, nphi)
 
-    p = Plan(order, n, nphi, 0, kappa=list(kap), precision="fp64", green=True, kappa_pair=order == 2)
+    p = Plan(order, n, nphi, 0, kappa=list(kap), precision="fp64", green=True, kappa_pair=kind == 2)
     T = p.sample(seed, count).double().cpu().numpy()
     torch.cuda.synchronize()
     p.close()
@@ -369,7 +374,7 @@ def test_green_domain_corners_match_oracle(case):
     # one unit in the last place, into the domain
     kp = tuple(k * (1 + 2.0 ** -52) if abs(k) <= 1e-5 else k * (1 - 2.0 ** -52) for k in kap)
     Ap, Bp = oracle_factors(kp)
-    Tp, _ = oracle.sample(order, n, nphi, Ap, Bp, seed, count)
+    Tp, _ = oracle.sample(order, n, nphi, Ap, Bp, seed, count)   # (for two real roots both move inward)
     sens = max(rel_rms(Tp[f], To[f]) for f in range(count))
     e = max(rel_rms(T[f], To[f]) for f in range(count))
     bar = max(1e-10, 10 * sens)

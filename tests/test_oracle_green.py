@@ -372,12 +372,14 @@ def test_green_setups_hold_small_kappa_off(orc):
 def test_green2_holds_its_real_roots_apart(orc):
     """Two real roots lose about log10(kappa / |kappa_2 - kappa_1|) digits to the partial
     fractions (against the U-basis Legendre sums at ell_max = 16000: 3e-7 of the standard
-    deviations, the sums' own truncation, at a relative distance of 1e-8, 3.6e-3 at 1e-12):
-    the setup takes a relative distance of at least 1e-6; a conjugate pair has no such loss
-    (its second term is the conjugate of the first, not subtracted from it)."""
-    orc.setup_green2([100.0, 100.0 * (1 + 2e-6)], 8, 16)
+    deviations, the sums' own truncation, at a relative distance of 1e-8, 3.6e-3 at 1e-12; a
+    64 x 128 field moves by 5e-11 when kappa moves by one unit in the last place at 1e-3, by
+    1e-9 at 1e-4): the setup takes a relative distance of at least 1e-3, which keeps FP64 fields
+    reproducible to 1e-10; a conjugate pair has no such loss (its second term is the conjugate of
+    the first, not subtracted from it)."""
+    orc.setup_green2([100.0, 100.0 * (1 + 2e-3)], 8, 16)
     with pytest.raises(ValueError):
-        orc.setup_green2([100.0, 100.0 * (1 + 1e-7)], 8, 16)
+        orc.setup_green2([100.0, 100.0 * (1 + 1e-4)], 8, 16)
     k = [100.0, 100.0 + 1e-10]
     Jg = orc.jblock_green2(3, k, 0.2, 0.35)
     Ju = orc.jblock_u(3, 16000, orc.spectrum(k, 16000), 0.2, 0.35)

@@ -380,3 +380,39 @@ def test_green_domain_corners_match_oracle(case):
     bar = max(1e-10, 10 * sens)
     log(f"green domain corner {case}: fields rel RMS {e:.2e}, oracle's one-ulp sensitivity {sens:.2e}, bar {bar:.2e}")
     assert np.isfinite(T).all() and e <= bar
+
+
+@pytest.mark.parametrize("case", [(1, (400.0,)), (2, (0.0, float(np.sqrt(10.0))))], ids=["order1", "pair"])
+def test_green_on_an_explicit_grid_matches_oracle(case):
+    """SMF_GREEN on an explicit grid (smf_setup_grid): 48 Gauss-Legendre latitudes, 128 longitudes,
+    every mode up to n_phi / 2 - 1; FP64 fields against the oracle's factors on the same latitudes
+    within 1e-10 relative RMS (or ten times the oracle's own movement when the northern latitudes
+    move by a relative 2.2e-16, if larger), FP32 within 1e-4."""
+    from paper_1709_10314_amd import Plan
+
+    order, kap = case
+    n, nphi, seed, count = 48, 128, 31, 2
+    z = np.sort(np.polynomial.legendre.leggauss(n)[0])[::-1].copy()
+    z[n // 2:] = -z[: n // 2][::-1]   # symmetric to the bit
+
+    def factors(zz):
+        if order == 1:
+            return oracle.setup_green(kap[0], n, nphi, z=zz)
+        return oracle.setup_green2c(kap[0], kap[1], n, nphi, z=zz)
+
+    A, B = factors(z)
+    To, _ = oracle.sample(order, n, nphi, A, B, seed, count)
+    zp = z.copy()
+    zp[: n // 2] *= 1 + 2.2e-16 * np.random.default_rng(0).standard_normal(n // 2)
+    zp[n // 2:] = -zp[: n // 2][::-1]
+    Ap, Bp = factors(zp)
+    Tp, _ = oracle.sample(order, n, nphi, Ap, Bp, seed, count)
+    sens = max(rel_rms(Tp[f], To[f]) for f in range(count))
+    for precision, bar in (("fp64", max(1e-10, 10 * sens)), ("fp32", 1e-4)):
+        p = Plan(order, n, nphi, 0, kappa=list(kap), precision=precision, z=z, green=True, kappa_pair=order == 2)
+        T = p.sample(seed, count).double().cpu().numpy()
+        torch.cuda.synchronize()
+        p.close()
+        e = max(rel_rms(T[f], To[f]) for f in range(count))
+        log(f"green on Gauss-Legendre latitudes {case} {precision}: fields rel RMS {e:.2e} (oracle's sensitivity {sens:.2e})")
+        assert e <= bar
